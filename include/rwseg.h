@@ -1,0 +1,174 @@
+/*
+ * rwseg.h -- C ABI of the MI355X (gfx950) brick-local random-walker library.
+ *
+ * Method: Drees, Eilers & Jiang, "Hierarchical Random Walker Segmentation for
+ * Large Volumetric Biomedical Images", arXiv 2103.09564.
+ *
+ * Everything below takes plain pointers and sizes.  "dev" marks a device
+ * (HBM) pointer, "host" a host pointer.  The caller owns every buffer it
+ * passes and keeps it alive until the work queued on `stream` has finished;
+ * the library never frees a caller buffer.  Library objects (rw_ctx,
+ * rw_pyramid, rw_result) are opaque and freed only by their *_free/_destroy
+ * call.  `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ * all device work is queued on it, asynchronously, unless a call says
+ * otherwise.  Device stats and outputs are valid after a stream sync.
+ *
+ * Errors: every int-returning call returns RW_OK (0) or a negative RW_E_*
+ * code; rw_last_error(ctx) gives a message.  Arguments are validated on the
+ * host before anything is queued.  Per-brick numerical outcomes (iteration
+ * cap, non-finite data, no Dirichlet voxel) are reported in rw_brick_stats and
+ * never fail a call.  One rw_ctx per host thread.
+ *
+ * Box layout: a box of nx*ny*nz voxels is stored contiguously from its
+ * element offset `offset`; voxel (i,j,k) sits at offset + i + nx*(j + ny*k).
+ * With nrhs right-hand sides the per-voxel values are interleaved:
+ * element (offset + v)*nrhs + c.
+ */
+#ifndef RWSEG_H
+#define RWSEG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RW_VERSION 100
+
+enum rw_error {
+    RW_OK = 0,
+    RW_E_INVAL = -1,        /* bad argument (message says which) */
+    RW_E_HIP = -2,          /* a HIP runtime call failed */
+    RW_E_NOMEM = -3,        /* device allocation failed */
+    RW_E_UNSUPPORTED = -4   /* valid request this build does not implement */
+};
+
+enum rw_precision {
+    RW_PREC_FP64 = 0,          /* plain FP64 PCG: vectors, weights, reductions in FP64 */
+    RW_PREC_MIXED = 1,         /* FP32 stencil/vectors, FP64 dot products, FP64 true-residual
+                                  check, and at most refine_max FP32 correction solves when the
+                                  true residual misses tol */
+    RW_PREC_MIXED_REFINE = 2   /* as MIXED, then FP64 iterative refinement of an FP64 copy of x
+                                  until the FP64 true relative residual <= refine_tol */
+};
+
+enum rw_status {
+    RW_ST_CONVERGED = 0,     /* ||r|| <= tol ||b|| */
+    RW_ST_MAX_ITER = 1,      /* hit max_iter before tol */
+    RW_ST_REFINED = 2,       /* FP32 solve missed tol in FP64; refinement brought it within */
+    RW_ST_STALLED = 3,       /* refinement steps exhausted without meeting the target */
+    RW_ST_NONFINITE = 4,     /* NaN/Inf met (input g or breakdown); x left as the last finite iterate */
+    RW_ST_NO_DIRICHLET = 5   /* box has no seeded voxel: problem has no unique solution, x untouched */
+};
+
+/* One box (solve domain).  nx, ny, nz >= 1. */
+typedef struct rw_brick {
+    int32_t nx, ny, nz;
+    int32_t reserved;        /* must be 0 */
+    int64_t offset;          /* first voxel, in voxels, into g / mask / x */
+} rw_brick;
+
+/* Per-box result, written to device memory. */
+typedef struct rw_brick_stats {
+    int32_t iters;           /* PCG iterations of the main solve (max over rhs) */
+    int32_t status;          /* rw_status (worst over rhs) */
+    int32_t refine_steps;    /* FP64-residual correction solves run */
+    int32_t refine_iters;    /* PCG iterations summed over those correction solves */
+    double rel_resid;        /* final recursive ||r||/||b|| of the main solve (max over rhs) */
+    double true_rel_resid;   /* FP64 ||b - L_UU x_U|| / ||b|| of the returned x (max over rhs);
+                                0 if ||b|| = 0 */
+} rw_brick_stats;
+
+/* Parameters of the box solve (Section III-B; solver as in Section V). */
+typedef struct rw_solve_params {
+    double beta;             /* w = exp(-beta (g_p - g_q)^2) + eps, beta >= 0 */
+    double eps;              /* eps >= 0 */
+    double tol;              /* stop when ||r||_2 <= tol ||b||_2, b = -L_UM x_M; tol >= 0 */
+    int32_t max_iter;        /* PCG iteration cap (the paper uses 5000) */
+    int32_t precision;       /* rw_precision */
+    int32_t nrhs;            /* 1..3 right-hand sides sharing g and the seed mask */
+    int32_t refine_max;      /* max correction solves (MIXED: usually 1, MIXED_REFINE: e.g. 4) */
+    double refine_tol;       /* MIXED_REFINE target FP64 true relative residual */
+    double inner_tol;        /* relative tolerance of each FP32 correction solve */
+} rw_solve_params;
+
+/* Fill *p with the defaults: beta 128, eps 1e-6, tol 1e-6, max_iter 5000,
+ * MIXED, nrhs 1, refine_max 1, refine_tol 1e-13, inner_tol 1e-4. */
+void rw_solve_params_default(rw_solve_params* p);
+
+typedef struct rw_ctx rw_ctx;
+
+int rw_version(void);
+
+/* Create a context on HIP device `hip_device`.  The context owns a device
+ * workspace that grows on demand and is freed by rw_ctx_destroy. */
+int rw_ctx_create(int hip_device, rw_ctx** out);
+void rw_ctx_destroy(rw_ctx* ctx);
+
+/* Message of the last error on this context ("" if none).  The pointer is
+ * valid until the next call on ctx.  ctx may be NULL (then: the last error
+ * of rw_ctx_create on this thread). */
+const char* rw_last_error(const rw_ctx* ctx);
+
+/*
+ * Batched brick-local random-walker solve (Section III-B, eq. rw(n, l, beta)
+ * of Section IV-A applied to each box independently, as Section IV-D3 allows).
+ *
+ * For every box: weights w = exp(-beta (g_p - g_q)^2) + eps on all
+ * 6-neighbour pairs inside the box, Laplacian L = D - W, and the Dirichlet
+ * problem L_UU x_U = -L_UM x_M on the unseeded set U (mask == 0) with the
+ * seeded values x_M (mask != 0) taken from x.  Solved by Jacobi-preconditioned
+ * CG (Section V) starting from the values x holds on U.
+ *
+ *   bricks   host, n_bricks descriptors; boxes may not overlap
+ *   n_voxels dev buffers below hold n_voxels voxels (every box must fit)
+ *   g        dev float [n_voxels]          intensities (any range; beta applies as given)
+ *   mask     dev uint8 [n_voxels]          nonzero = seeded (Dirichlet)
+ *   x        dev float [n_voxels*nrhs]     in: x_M on seeded voxels, initial guess elsewhere;
+ *                                          out: solution (seeded voxels unchanged)
+ *   x64      dev double [n_voxels*nrhs] or NULL: if given, also receives the solution in FP64
+ *            (MIXED_REFINE: the refined FP64 solution; its seeded entries are x_M)
+ *   stats    dev rw_brick_stats [n_bricks] or NULL
+ *
+ * Returns RW_E_INVAL on bad descriptors/params; numerical outcomes go to stats.
+ */
+int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks,
+                    const rw_brick* bricks, int64_t n_voxels, const float* g,
+                    const uint8_t* mask, float* x, double* x64, rw_brick_stats* stats,
+                    void* stream);
+
+/*
+ * Host-only check of the arguments rw_solve_bricks would validate (params,
+ * descriptors, buffer extents, overlap).  Needs no GPU and queues nothing.
+ * Returns RW_OK or RW_E_INVAL; the message is in rw_last_error(NULL).
+ */
+int rw_validate_solve(const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                      int64_t n_voxels);
+
+/*
+ * Adjoint of rw_solve_bricks for gradients of a loss l(x) (derived from the
+ * Dirichlet problem of Section III-B).  For each box solves
+ * L_UU lambda = dl/dx_U (lambda = 0 on seeded voxels) with the same FP32 PCG
+ * (params->tol, params->max_iter; nrhs must be 1), then, per edge e = (p,q),
+ * dl/dw_e = -(lambda_p - lambda_q)(x_p - x_q) and
+ *   dl_dg[p] += dl/dw_e * dw_e/dg_p,  dw/dg_p = -2 beta (g_p - g_q)(w - eps) = -dw/dg_q,
+ *   dl_dbeta += dl/dw_e * (-(g_p - g_q)^2 (w - eps)).
+ *
+ *   x        dev float [n_voxels]   the converged forward solution
+ *   dl_dx    dev float [n_voxels]   loss gradient (ignored on seeded voxels)
+ *   dl_dg    dev float [n_voxels]   out: gradient w.r.t. g (every voxel, seeded included)
+ *   dl_dbeta dev double [1]         out: gradient w.r.t. beta (FP64, summed over all boxes)
+ *   lambda   dev float [n_voxels] or NULL: out, the adjoint solution
+ *   stats    dev rw_brick_stats [n_bricks] or NULL: adjoint solve stats
+ */
+int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks,
+                            const rw_brick* bricks, int64_t n_voxels, const float* g,
+                            const uint8_t* mask, const float* x, const float* dl_dx,
+                            float* dl_dg, double* dl_dbeta, float* lambda,
+                            rw_brick_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RWSEG_H */

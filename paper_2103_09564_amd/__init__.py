@@ -1,0 +1,11 @@
+"""MI355X-native brick-local random-walker segmentation (arXiv 2103.09564).
+
+The compute path is librwseg.so (hand-written gfx950 HIP kernels behind the C
+ABI in include/rwseg.h); ``binding`` marshals torch tensors into it.
+"""
+
+from .binding import (  # noqa: F401
+    Context, RWError, SolveParams, BRICK_DTYPE, STATS_DTYPE, STATUS_NAMES,
+    PREC_FP64, PREC_MIXED, PREC_MIXED_REFINE,
+    bricks_array, context, solve_bricks, solve_bricks_adjoint, solve_params, stats_to_numpy, validate_solve, version,
+)

@@ -1,0 +1,192 @@
+"""ctypes binding of librwseg (the C ABI in include/rwseg.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Torch supplies device memory (``tensor.data_ptr()``) and the stream
+(``torch.cuda.current_stream().cuda_stream``); no torch op runs on the data
+inside these calls.  Importing this module fails loudly if librwseg.so has not
+been built; there is no fallback implementation.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librwseg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as e; e.build()' "
+        "or python -m paper_2103_09564_amd._build)")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+RW_OK, RW_E_INVAL, RW_E_HIP, RW_E_NOMEM, RW_E_UNSUPPORTED = 0, -1, -2, -3, -4
+PREC_FP64, PREC_MIXED, PREC_MIXED_REFINE = 0, 1, 2
+ST_CONVERGED, ST_MAX_ITER, ST_REFINED, ST_STALLED, ST_NONFINITE, ST_NO_DIRICHLET = range(6)
+STATUS_NAMES = ["CONVERGED", "MAX_ITER", "REFINED", "STALLED", "NONFINITE", "NO_DIRICHLET"]
+
+BRICK_DTYPE = np.dtype([("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"), ("reserved", "<i4"), ("offset", "<i8")])
+STATS_DTYPE = np.dtype([("iters", "<i4"), ("status", "<i4"), ("refine_steps", "<i4"), ("refine_iters", "<i4"),
+                        ("rel_resid", "<f8"), ("true_rel_resid", "<f8")])
+assert BRICK_DTYPE.itemsize == 24 and STATS_DTYPE.itemsize == 32
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32), ("nrhs", ctypes.c_int32),
+                ("refine_max", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("inner_tol", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+lib.rw_version.restype = ctypes.c_int
+lib.rw_solve_params_default.argtypes = [ctypes.POINTER(SolveParams)]
+lib.rw_solve_params_default.restype = None
+lib.rw_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(_vp)]
+lib.rw_ctx_create.restype = ctypes.c_int
+lib.rw_ctx_destroy.argtypes = [_vp]
+lib.rw_ctx_destroy.restype = None
+lib.rw_last_error.argtypes = [_vp]
+lib.rw_last_error.restype = ctypes.c_char_p
+lib.rw_solve_bricks.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
+lib.rw_solve_bricks.restype = ctypes.c_int
+lib.rw_solve_bricks_adjoint.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp,
+                                        _vp, _vp, _vp, _vp, _vp]
+lib.rw_solve_bricks_adjoint.restype = ctypes.c_int
+lib.rw_validate_solve.argtypes = [ctypes.POINTER(SolveParams), _i64, _vp, _i64]
+lib.rw_validate_solve.restype = ctypes.c_int
+
+
+class RWError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"librwseg error {code}: {msg}")
+        self.code = code
+
+
+def version():
+    return lib.rw_version()
+
+
+def validate_solve(params, bricks, n_voxels):
+    """Host-only argument check (no GPU).  Returns (code, message)."""
+    bricks = np.ascontiguousarray(bricks, dtype=BRICK_DTYPE)
+    rc = lib.rw_validate_solve(ctypes.byref(params), len(bricks), bricks.ctypes.data_as(_vp), int(n_voxels))
+    return rc, lib.rw_last_error(None).decode()
+
+
+def solve_params(**kw):
+    """rw_solve_params with the library defaults, overridden by ``kw``."""
+    p = SolveParams()
+    lib.rw_solve_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown solve parameter {k!r}")
+        setattr(p, k, v)
+    return p
+
+
+def bricks_array(shapes, offsets):
+    """Host rw_brick array from (n,3) shapes (nx, ny, nz) and (n,) offsets."""
+    shapes = np.asarray(shapes).reshape(-1, 3)
+    b = np.zeros(len(shapes), dtype=BRICK_DTYPE)
+    b["nx"], b["ny"], b["nz"] = shapes[:, 0], shapes[:, 1], shapes[:, 2]
+    b["offset"] = np.asarray(offsets, dtype=np.int64)
+    return b
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """An rw_ctx on one HIP device (owns the library's workspace)."""
+
+    def __init__(self, device=0):
+        h = _vp()
+        rc = lib.rw_ctx_create(int(device), ctypes.byref(h))
+        if rc != RW_OK:
+            raise RWError(rc, lib.rw_last_error(None).decode())
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib.rw_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != RW_OK:
+            raise RWError(rc, lib.rw_last_error(self.handle).decode())
+
+    def rw_solve_bricks(self, params, bricks, g, mask, x, x64=None, stats=None, stream=None):
+        """Queue rw_solve_bricks.  g, mask, x (and x64, stats) are device tensors;
+        bricks a host BRICK_DTYPE array; stats a uint8 tensor of n*32 bytes."""
+        bricks = np.ascontiguousarray(bricks, dtype=BRICK_DTYPE)
+        n_vox = g.numel()
+        self._check(lib.rw_solve_bricks(self.handle, ctypes.byref(params), len(bricks),
+                                        bricks.ctypes.data_as(_vp), n_vox, _ptr(g), _ptr(mask), _ptr(x),
+                                        _ptr(x64), _ptr(stats), _stream(stream)))
+
+    def rw_solve_bricks_adjoint(self, params, bricks, g, mask, x, dl_dx, dl_dg, dl_dbeta, lam=None,
+                                stats=None, stream=None):
+        bricks = np.ascontiguousarray(bricks, dtype=BRICK_DTYPE)
+        self._check(lib.rw_solve_bricks_adjoint(self.handle, ctypes.byref(params), len(bricks),
+                                                bricks.ctypes.data_as(_vp), g.numel(), _ptr(g), _ptr(mask),
+                                                _ptr(x), _ptr(dl_dx), _ptr(dl_dg), _ptr(dl_dbeta), _ptr(lam),
+                                                _ptr(stats), _stream(stream)))
+
+
+def stats_to_numpy(stats_tensor):
+    """Parse a device/host uint8 stats tensor into a STATS_DTYPE array."""
+    raw = stats_tensor.detach().cpu().numpy().view(np.uint8).reshape(-1)
+    return raw.view(STATS_DTYPE)
+
+
+_default_ctx = {}
+
+
+def context(device=0):
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def solve_bricks(g, mask, x, shapes, offsets, x64=None, stream=None, ctx=None, **params):
+    """Solve all boxes; x is updated in place.  Returns the stats tensor
+    (device, uint8 [n, 32]; parse with ``stats_to_numpy``)."""
+    import torch
+    ctx = ctx or context(g.device.index or 0)
+    b = bricks_array(shapes, offsets)
+    st = torch.empty((len(b), STATS_DTYPE.itemsize), dtype=torch.uint8, device=g.device)
+    ctx.rw_solve_bricks(solve_params(**params), b, g, mask, x, x64=x64, stats=st, stream=stream)
+    return st
+
+
+def solve_bricks_adjoint(g, mask, x, dl_dx, shapes, offsets, lam=None, stream=None, ctx=None, **params):
+    """Adjoint gradients: returns (dl_dg tensor, dl_dbeta 1-element float64 tensor, stats)."""
+    import torch
+    ctx = ctx or context(g.device.index or 0)
+    b = bricks_array(shapes, offsets)
+    dl_dg = torch.empty_like(g)
+    dl_dbeta = torch.empty(1, dtype=torch.float64, device=g.device)
+    st = torch.empty((len(b), STATS_DTYPE.itemsize), dtype=torch.uint8, device=g.device)
+    ctx.rw_solve_bricks_adjoint(solve_params(**params), b, g, mask, x, dl_dx, dl_dg, dl_dbeta, lam=lam,
+                                stats=st, stream=stream)
+    return dl_dg, dl_dbeta, st

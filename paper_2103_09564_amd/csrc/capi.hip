@@ -1,0 +1,307 @@
+// C ABI of librwseg: contexts, argument validation, workspace, launches.
+// No C++ exception crosses the ABI; every entry point returns an rw_error.
+
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+struct rw_ctx {
+    int device = 0;
+    std::string err;
+    void* ws = nullptr;          // vector workspace
+    size_t ws_bytes = 0;
+    void* bricks = nullptr;      // device BrickDev list
+    size_t bricks_bytes = 0;
+    void* aux = nullptr;         // small per-box buffers (adjoint partials)
+    size_t aux_bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(rw_ctx* ctx, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(rw_ctx* ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_create_err = buf;
+    return code;
+}
+
+int hip_fail(rw_ctx* ctx, hipError_t e, const char* what) {
+    return fail(ctx, e == hipErrorOutOfMemory ? RW_E_NOMEM : RW_E_HIP, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+// Grow a device buffer to at least `bytes` (contents are not kept).
+hipError_t grow(rw_ctx* ctx, void** buf, size_t* have, size_t bytes, hipStream_t s) {
+    if (*have >= bytes) return hipSuccess;
+    if (*buf) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        e = hipFree(*buf);
+        if (e != hipSuccess) return e;
+        *buf = nullptr;
+        *have = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    hipError_t e = hipMalloc(buf, want);
+    if (e != hipSuccess) {
+        *buf = nullptr;
+        return e;
+    }
+    *have = want;
+    return hipSuccess;
+}
+
+struct DevGuard {
+    int prev = -1;
+    explicit DevGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DevGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int check_params(rw_ctx* ctx, const rw_solve_params* p) {
+    if (!p) return fail(ctx, RW_E_INVAL, "params is NULL");
+    if (!std::isfinite(p->beta) || p->beta < 0) return fail(ctx, RW_E_INVAL, "beta must be finite and >= 0");
+    if (!std::isfinite(p->eps) || p->eps < 0) return fail(ctx, RW_E_INVAL, "eps must be finite and >= 0");
+    if (!std::isfinite(p->tol) || p->tol < 0) return fail(ctx, RW_E_INVAL, "tol must be finite and >= 0");
+    if (p->max_iter < 0) return fail(ctx, RW_E_INVAL, "max_iter must be >= 0");
+    if (p->precision < RW_PREC_FP64 || p->precision > RW_PREC_MIXED_REFINE)
+        return fail(ctx, RW_E_INVAL, "unknown precision %d", p->precision);
+    if (p->nrhs < 1 || p->nrhs > 3) return fail(ctx, RW_E_INVAL, "nrhs must be 1, 2 or 3 (got %d)", p->nrhs);
+    if (p->refine_max < 0 || p->refine_max > 64) return fail(ctx, RW_E_INVAL, "refine_max must be in [0, 64]");
+    if (!std::isfinite(p->refine_tol) || p->refine_tol < 0) return fail(ctx, RW_E_INVAL, "refine_tol must be >= 0");
+    if (!std::isfinite(p->inner_tol) || p->inner_tol < 0) return fail(ctx, RW_E_INVAL, "inner_tol must be >= 0");
+    return RW_OK;
+}
+
+// Validate host descriptors and build the launch list (largest box first).
+int build_list(rw_ctx* ctx, int64_t n, const rw_brick* bricks, int64_t n_voxels,
+               std::vector<rwk::BrickDev>* out) {
+    if (n < 0) return fail(ctx, RW_E_INVAL, "n_bricks < 0");
+    if (n > 0 && !bricks) return fail(ctx, RW_E_INVAL, "bricks is NULL");
+    if (n > (int64_t)0x7fffffff) return fail(ctx, RW_E_INVAL, "too many bricks (max 2^31-1)");
+    if (n_voxels < 0) return fail(ctx, RW_E_INVAL, "n_voxels < 0");
+    std::vector<std::pair<int64_t, int64_t>> spans;
+    spans.reserve((size_t)n);
+    out->resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        const rw_brick& b = bricks[i];
+        if (b.nx < 1 || b.ny < 1 || b.nz < 1)
+            return fail(ctx, RW_E_INVAL, "brick %lld: dims %d x %d x %d must be >= 1", (long long)i, b.nx, b.ny, b.nz);
+        if (b.reserved != 0) return fail(ctx, RW_E_INVAL, "brick %lld: reserved field must be 0", (long long)i);
+        const int64_t nxy = (int64_t)b.nx * b.ny;
+        if (nxy > (int64_t)0x7fffffff) return fail(ctx, RW_E_INVAL, "brick %lld: nx*ny too large", (long long)i);
+        const int64_t vox = nxy * b.nz;
+        if (b.offset < 0 || vox > n_voxels || b.offset > n_voxels - vox)
+            return fail(ctx, RW_E_INVAL, "brick %lld: [%lld, %lld) outside the %lld-voxel buffers", (long long)i,
+                        (long long)b.offset, (long long)(b.offset + vox), (long long)n_voxels);
+        (*out)[(size_t)i] = rwk::BrickDev{b.nx, b.ny, b.nz, (int32_t)i, b.offset};
+        spans.emplace_back(b.offset, b.offset + vox);
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second) return fail(ctx, RW_E_INVAL, "bricks overlap in the voxel buffers");
+    std::stable_sort(out->begin(), out->end(), [](const rwk::BrickDev& a, const rwk::BrickDev& b) {
+        return (int64_t)a.nx * a.ny * a.nz > (int64_t)b.nx * b.ny * b.nz;
+    });
+    return RW_OK;
+}
+
+int upload_list(rw_ctx* ctx, const std::vector<rwk::BrickDev>& list, hipStream_t s) {
+    size_t bytes = std::max<size_t>(list.size() * sizeof(rwk::BrickDev), 64);
+    hipError_t e = grow(ctx, &ctx->bricks, &ctx->bricks_bytes, bytes, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "allocating brick list");
+    if (!list.empty()) {
+        e = hipMemcpyAsync(ctx->bricks, list.data(), list.size() * sizeof(rwk::BrickDev), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "uploading brick list");
+    }
+    return RW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rw_solve_params_default(rw_solve_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->beta = 128.0;
+    p->eps = 1e-6;
+    p->tol = 1e-6;
+    p->max_iter = 5000;
+    p->precision = RW_PREC_MIXED;
+    p->nrhs = 1;
+    p->refine_max = 1;
+    p->refine_tol = 1e-13;
+    p->inner_tol = 1e-4;
+}
+
+int rw_version(void) { return RW_VERSION; }
+
+int rw_ctx_create(int hip_device, rw_ctx** out) {
+    if (!out) return fail(nullptr, RW_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return fail(nullptr, RW_E_HIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (hip_device < 0 || hip_device >= n)
+        return fail(nullptr, RW_E_INVAL, "device %d out of range (have %d)", hip_device, n);
+    rw_ctx* c = new (std::nothrow) rw_ctx();
+    if (!c) return fail(nullptr, RW_E_NOMEM, "host allocation failed");
+    c->device = hip_device;
+    *out = c;
+    return RW_OK;
+}
+
+void rw_ctx_destroy(rw_ctx* ctx) {
+    if (!ctx) return;
+    DevGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->bricks) (void)hipFree(ctx->bricks);
+    if (ctx->aux) (void)hipFree(ctx->aux);
+    delete ctx;
+}
+
+const char* rw_last_error(const rw_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+int rw_validate_solve(const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                      int64_t n_voxels) {
+    g_create_err.clear();
+    int rc = check_params(nullptr, params);
+    if (rc) return rc;
+    std::vector<rwk::BrickDev> list;
+    return build_list(nullptr, n_bricks, bricks, n_voxels, &list);
+}
+
+int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                    int64_t n_voxels, const float* g, const uint8_t* mask, float* x, double* x64,
+                    rw_brick_stats* stats, void* stream) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    std::vector<rwk::BrickDev> list;
+    rc = build_list(ctx, n_bricks, bricks, n_voxels, &list);
+    if (rc) return rc;
+    if (n_bricks == 0) return RW_OK;
+    if (!g || !mask || !x) return fail(ctx, RW_E_INVAL, "g, mask and x must be non-NULL");
+    const rw_solve_params& p = *params;
+    const int R = p.nrhs;
+    const bool fp64 = p.precision == RW_PREC_FP64;
+    const bool need_x64 = fp64 || p.precision == RW_PREC_MIXED_REFINE;
+    hipStream_t s = (hipStream_t)stream;
+    DevGuard dg(ctx->device);
+
+    const size_t nv = (size_t)n_voxels * (size_t)R;
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    // r, z, p0, p1, then FP32 correction buffer, then FP64 solution buffer if the caller gave none
+    size_t bytes = 4 * nv * es;
+    const size_t off_dcorr = bytes;
+    if (!fp64) bytes += nv * sizeof(float);
+    const size_t off_x64 = (bytes + 255) & ~size_t(255);
+    if (need_x64 && !x64) bytes = off_x64 + nv * sizeof(double);
+    hipError_t e = grow(ctx, &ctx->ws, &ctx->ws_bytes, std::max<size_t>(bytes, 256), s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "allocating solver workspace");
+    rc = upload_list(ctx, list, s);
+    if (rc) return rc;
+
+    char* w = (char*)ctx->ws;
+    rwk::SolveArgs a{};
+    a.bricks = (const rwk::BrickDev*)ctx->bricks;
+    a.g = g;
+    a.mask = mask;
+    a.x = x;
+    a.r = w;
+    a.z = w + nv * es;
+    a.p0 = w + 2 * nv * es;
+    a.p1 = w + 3 * nv * es;
+    a.dcorr = fp64 ? nullptr : (float*)(w + off_dcorr);
+    double* x64buf = x64 ? x64 : (need_x64 ? (double*)(w + off_x64) : nullptr);
+    a.x64 = x64buf;
+    a.xt = x64buf;
+    a.want_x64 = x64 ? 1 : 0;
+    a.stats = stats;
+    a.beta = p.beta;
+    a.eps = p.eps;
+    a.tol = p.tol;
+    a.refine_tol = p.refine_tol;
+    a.inner_tol = p.inner_tol;
+    a.max_iter = p.max_iter;
+    a.precision = p.precision;
+    a.refine_max = p.refine_max;
+    e = rwk::launch_solve(a, n_bricks, R, fp64, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "launching solve kernel");
+    return RW_OK;
+}
+
+int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks,
+                            const rw_brick* bricks, int64_t n_voxels, const float* g, const uint8_t* mask,
+                            const float* x, const float* dl_dx, float* dl_dg, double* dl_dbeta,
+                            float* lambda, rw_brick_stats* stats, void* stream) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    if (params->nrhs != 1) return fail(ctx, RW_E_UNSUPPORTED, "adjoint supports nrhs = 1 only");
+    std::vector<rwk::BrickDev> list;
+    rc = build_list(ctx, n_bricks, bricks, n_voxels, &list);
+    if (rc) return rc;
+    if (!dl_dbeta) return fail(ctx, RW_E_INVAL, "dl_dbeta must be non-NULL");
+    if (n_bricks > 0 && (!g || !mask || !x || !dl_dx || !dl_dg))
+        return fail(ctx, RW_E_INVAL, "g, mask, x, dl_dx and dl_dg must be non-NULL");
+    hipStream_t s = (hipStream_t)stream;
+    DevGuard dg(ctx->device);
+    const size_t nv = (size_t)n_voxels;
+    size_t bytes = 4 * nv * sizeof(float);
+    const size_t off_lam = bytes;
+    if (!lambda) bytes += nv * sizeof(float);
+    hipError_t e = grow(ctx, &ctx->ws, &ctx->ws_bytes, std::max<size_t>(bytes, 256), s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint workspace");
+    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, std::max<size_t>((size_t)n_bricks * sizeof(double), 256), s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint partials");
+    rc = upload_list(ctx, list, s);
+    if (rc) return rc;
+    char* w = (char*)ctx->ws;
+    rwk::AdjointArgs a{};
+    a.bricks = (const rwk::BrickDev*)ctx->bricks;
+    a.g = g;
+    a.mask = mask;
+    a.x = x;
+    a.dl_dx = dl_dx;
+    a.dl_dg = dl_dg;
+    a.r = (float*)w;
+    a.z = (float*)(w + nv * 4);
+    a.p0 = (float*)(w + 2 * nv * 4);
+    a.p1 = (float*)(w + 3 * nv * 4);
+    a.lambda = lambda ? lambda : (float*)(w + off_lam);
+    a.beta_part = (double*)ctx->aux;
+    a.stats = stats;
+    a.beta = params->beta;
+    a.eps = params->eps;
+    a.tol = params->tol;
+    a.max_iter = params->max_iter;
+    e = rwk::launch_adjoint(a, n_bricks, dl_dbeta, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "launching adjoint kernels");
+    return RW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+"""GPU parity of the batched box solve against the FP64 oracle, through the C ABI.
+
+Tolerances: max |x_gpu - x_oracle| <= 1e-4 for the FP32 (mixed) path at
+relative residual 1e-6, <= 1e-9 for the FP64-refined path and for the plain
+FP64 path at relative residual 1e-12.  The oracle reference is the unique
+solution of the box's Dirichlet problem (oracle.rw.solve_box; Jacobi-PCG to
+1e-14, pinned against sparse/dense factorisations on the CPU).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import rw as orw
+
+pytestmark = pytest.mark.gpu
+
+BETA, EPS = 128.0, 1e-6
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2103_09564_amd as rwg
+    assert torch.cuda.is_available()
+    return torch, rwg, torch.device("cuda:0")
+
+
+def _ref(box, beta=BETA, eps=EPS):
+    g, m, x = box
+    return orw.solve_box(g, m, x, beta, eps, method="pcg", tol=1e-14).ravel()
+
+
+def _run(env, d, x64=False, **params):
+    torch, rwg, dev = env
+    g = torch.from_numpy(d["g"]).to(dev)
+    m = torch.from_numpy(d["mask"]).to(dev)
+    x = torch.from_numpy(d["x"]).to(dev)
+    xd = torch.zeros(x.numel(), dtype=torch.float64, device=dev) if x64 else None
+    st = rwg.solve_bricks(g, m, x, d["shapes"], d["offsets"], x64=xd, **params)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), (xd.cpu().numpy() if x64 else None), rwg.stats_to_numpy(st)
+
+
+def _mixed_set(seed=5):
+    rng = np.random.default_rng(seed)
+    boxes = list(synth.stress_boxes(n=10, seed=seed)["boxes"])
+    for s in [(1, 1, 40), (3, 4, 5), (7, 1, 9), (33, 2, 3), (2, 31, 2), (40, 40, 40)]:
+        boxes.append(synth.random_box(rng, s, dirichlet_frac=0.03))
+    return boxes
+
+
+@pytest.fixture(scope="module")
+def mixed_set():
+    boxes = _mixed_set()
+    return boxes, synth.from_boxes(boxes), [_ref(b) for b in boxes]
+
+
+def test_mixed_matches_oracle(env, mixed_set):
+    boxes, d, refs = mixed_set
+    x, _, st = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    for i, ref in enumerate(refs):
+        o, n = int(d["offsets"][i]), ref.size
+        err = np.max(np.abs(x[o:o + n] - ref))
+        assert err <= 1e-4, (i, d["shapes"][i], err, st[i])
+        # boxes of the stress recipe meet tol in FP64 (possibly after refinement);
+        # the extra random boxes include a weak-link chain (cond ~1e7) where an
+        # FP32-stored x cannot reach tol relative to its tiny ||b||: STALLED is
+        # the honest outcome there and the error bound above still holds.
+        allowed = (0, 2) if i < 10 else (0, 2, 3)
+        assert st["status"][i] in allowed, (i, st[i])
+        if st["status"][i] in (0, 2):
+            assert st["true_rel_resid"][i] <= 1e-6 * 1.0001
+
+
+def test_refined_matches_oracle_1e9(env, mixed_set):
+    boxes, d, refs = mixed_set
+    x, x64, st = _run(env, d, x64=True, beta=BETA, eps=EPS, tol=1e-6, precision=2,
+                      refine_max=6, refine_tol=1e-13, inner_tol=1e-4)
+    for i, ref in enumerate(refs):
+        o, n = int(d["offsets"][i]), ref.size
+        err = np.max(np.abs(x64[o:o + n] - ref))
+        assert err <= 1e-9, (i, d["shapes"][i], err, st[i])
+        assert np.max(np.abs(x[o:o + n] - ref)) <= 1e-6
+
+
+def test_fp64_matches_oracle(env, mixed_set):
+    boxes, d, refs = mixed_set
+    _, x64, st = _run(env, d, x64=True, beta=BETA, eps=EPS, tol=1e-12, precision=0)
+    for i, ref in enumerate(refs):
+        o, n = int(d["offsets"][i]), ref.size
+        err = np.max(np.abs(x64[o:o + n] - ref))
+        assert err <= 1e-9, (i, d["shapes"][i], err, st[i])
+        assert st["status"][i] == 0
+
+
+def test_seeded_voxels_unchanged(env, mixed_set):
+    boxes, d, refs = mixed_set
+    x, _, _ = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    s = d["mask"] != 0
+    assert np.array_equal(x[s], d["x"][s])
+
+
+def test_edge_cases(env):
+    rng = np.random.default_rng(9)
+    # 0: no seed at all; 1: every voxel seeded; 2: zero Dirichlet data; 3: chain closed form;
+    # 4: single unknown voxel
+    g0, _, _ = synth.random_box(rng, (4, 5, 6))
+    x0 = rng.random(g0.shape).astype(np.float32)
+    nodir = (g0, np.zeros(g0.shape, np.uint8), x0)
+    g1 = rng.random((3, 3, 3)).astype(np.float32)
+    alls = (g1, np.ones(g1.shape, np.uint8), rng.random(g1.shape).astype(np.float32))
+    g2, m2, _ = synth.random_box(rng, (6, 6, 6), dirichlet_frac=0.1)
+    zero = (g2, m2, np.where(m2 != 0, 0.0, rng.random(g2.shape)).astype(np.float32))
+    n = 25
+    gl = rng.random(n).astype(np.float32)
+    mc = np.zeros(n, np.uint8)
+    mc[0] = mc[-1] = 1
+    xc = np.zeros(n, np.float32)
+    xc[-1] = 1.0
+    chain = (gl.reshape(n, 1, 1), mc.reshape(n, 1, 1), xc.reshape(n, 1, 1))
+    one = (np.array([[[0.1, 0.5, 0.9]]], np.float32), np.array([[[1, 0, 1]]], np.uint8),
+           np.array([[[0.0, 0.3, 1.0]]], np.float32))
+    boxes = [nodir, alls, zero, chain, one]
+    d = synth.from_boxes(boxes)
+    x, _, st = _run(env, d, beta=20.0, eps=1e-3, tol=1e-7, precision=1)
+    off = d["offsets"]
+    assert st["status"][0] == 5 and np.array_equal(x[off[0]:off[0] + g0.size], x0.ravel())
+    assert st["status"][1] == 0 and st["iters"][1] == 0
+    assert np.array_equal(x[off[1]:off[1] + 27], alls[2].ravel())
+    assert st["status"][2] == 0 and np.all(x[off[2]:off[2] + 216][m2.ravel() == 0] == 0.0)
+    w = np.exp(-20.0 * np.diff(gl.astype(np.float64)) ** 2) + 1e-3
+    R = 1.0 / w
+    expect = np.concatenate([[0.0], np.cumsum(R)]) / R.sum()
+    assert np.max(np.abs(x[off[3]:off[3] + n] - expect)) < 1e-5
+    w01 = np.exp(-20.0 * 0.16) + 1e-3
+    w12 = np.exp(-20.0 * 0.16) + 1e-3
+    assert abs(x[off[4] + 1] - (w01 * 0.0 + w12 * 1.0) / (w01 + w12)) < 1e-6
+
+
+def test_iteration_cap_and_nonfinite(env):
+    rng = np.random.default_rng(10)
+    a = synth.random_box(rng, (12, 12, 12), dirichlet_frac=0.02)
+    gb = a[0].copy()
+    gb[3, 4, 5] = np.nan
+    bad = (gb, a[1], a[2])
+    d = synth.from_boxes([a, bad])
+    x, _, st = _run(env, d, beta=BETA, eps=EPS, tol=1e-12, max_iter=1, precision=1, refine_max=0)
+    assert st["status"][0] == 1 and st["iters"][0] == 1
+    d2 = synth.from_boxes([bad])
+    _, _, st2 = _run(env, d2, beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    assert st2["status"][0] == 4
+
+
+def test_multi_rhs_equals_separate(env):
+    rng = np.random.default_rng(12)
+    boxes = [synth.random_box(rng, s, dirichlet_frac=0.05) for s in [(9, 8, 7), (16, 5, 3), (20, 20, 20)]]
+    d = synth.from_boxes(boxes)
+    R = 3
+    xs = [np.where(d["mask"] != 0, rng.random(d["x"].size), 0.0).astype(np.float32) for _ in range(R)]
+    inter = np.stack(xs, axis=1).ravel()
+    d3 = dict(d, x=inter)
+    x3, _, st3 = _run(env, d3, beta=BETA, eps=EPS, tol=1e-7, precision=1, nrhs=3)
+    x3 = x3.reshape(-1, R)
+    for k in range(R):
+        dk = dict(d, x=xs[k])
+        xk, _, _ = _run(env, dk, beta=BETA, eps=EPS, tol=1e-7, precision=1)
+        assert np.max(np.abs(x3[:, k] - xk)) < 1e-5
+        for i, (g, m, _) in enumerate(boxes):
+            o = int(d["offsets"][i])
+            ref = orw.solve_box(g, m, xs[k][o:o + g.size].reshape(g.shape), BETA, EPS, method="pcg", tol=1e-14)
+            assert np.max(np.abs(x3[o:o + g.size, k] - ref.ravel())) <= 1e-4
+
+
+def test_deterministic_and_order_independent(env, mixed_set):
+    boxes, d, _ = mixed_set
+    xa, _, sa = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    xb, _, sb = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    assert np.array_equal(xa, xb) and np.array_equal(sa, sb)
+    rev = synth.from_boxes(boxes[::-1])
+    xr, _, sr = _run(env, rev, beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    n = len(boxes)
+    for i in range(n):
+        j = n - 1 - i
+        oi, oj, sz = int(d["offsets"][i]), int(rev["offsets"][j]), boxes[i][0].size
+        assert np.array_equal(xa[oi:oi + sz], xr[oj:oj + sz])
+        assert sa["iters"][i] == sr["iters"][j]
+
+
+def test_plain_sphere_single_domain(env):
+    g, m, x0, inside = synth.plain_sphere()
+    d = synth.from_boxes([(g, m, x0)])
+    ref = orw.solve_box(g, m, x0, BETA, EPS, method="pcg", tol=1e-13).ravel()
+    x, _, st = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    assert np.max(np.abs(x - ref)) <= 1e-4, st
+    _, x64, st64 = _run(env, d, x64=True, beta=BETA, eps=EPS, tol=1e-6, precision=0)
+    assert np.max(np.abs(x64 - ref)) <= 1e-4, st64
+    # the sphere is segmented (sanity, not parity)
+    assert ((x.reshape(g.shape) > 0.5) == inside).mean() > 0.99
+
+
+def test_full_size_stress_sampled(env):
+    """All 8192 mixed-shape boxes in one launch (the benchmark configuration);
+    sampled boxes against the oracle, every box against its own residual."""
+    d = synth.stress_boxes(n=8192, seed=3)
+    x, _, st = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    assert np.all(np.isin(st["status"], (0, 2))), np.unique(st["status"], return_counts=True)
+    assert np.all(st["true_rel_resid"] <= 1e-6 * 1.0001)
+    rng = np.random.default_rng(0)
+    for i in rng.choice(len(d["boxes"]), 12, replace=False):
+        ref = _ref(d["boxes"][i])
+        o = int(d["offsets"][i])
+        assert np.max(np.abs(x[o:o + ref.size] - ref)) <= 1e-4, (i, st[i])
