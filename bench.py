@@ -1,0 +1,209 @@
+"""Benchmark: batched brick-local random-walker PCG on one MI355X.
+
+Workload (the batching + precision stress configuration): 8192 boxes with
+shapes drawn uniformly from {32^3, 32x32x17, 32x9x32, 5x32x32, 16^3},
+Gaussian-smoothed noise intensities scaled to [0, 1] per box, random Dirichlet
+faces and 1 % interior seeds (recipe in ``synth.stress_boxes``), beta 128,
+eps 1e-6, per-box relative residual tolerance 1e-6.  All inputs are resident
+in HBM before the timed region.
+
+A step is one ``rw_solve_bricks`` call over all 8192 boxes (x reset to its
+initial values first, inside the step).  The headline value is
+voxel-iterations per second of the mixed-precision path (FP32 stencil and
+vectors, FP64 reductions, FP64 true-residual check with refinement where it
+misses tol): sum over boxes of (box voxels x PCG iterations executed, main +
+correction solves) / seconds per step.  The plain-FP64 path runs on the same
+workload for the mixed-vs-FP64 comparison.
+
+Prints ONE JSON line.  --gpus N with N > 1 exits: this build targets one GPU.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
+BYTES_PER_VOXEL_ITER = 28      # read x, r, p, g; write x, r, p (FP32, one rhs)
+BETA, EPS, TOL = 128.0, 1e-6, 1e-6
+N_BOXES, SEED = 8192, 3
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("pcg.hip", "capi.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2103_09564_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_ms_unused=None):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "k_solve_stress8192_counters.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("bench-traffic:"):
+            rec = json.loads(line.split(":", 1)[1])
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def _oracle_worker(args):
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import rw as orw
+    g, m, x, deadline = args
+    if time.time() > deadline:
+        return None
+    with threadpool_limits(1):
+        A, b, U, M = orw.dirichlet_system(g, m, x, BETA, EPS)
+        xu, it, _ = orw.pcg(A, b, x0=np.asarray(x, np.float64).ravel()[U], tol=TOL)
+    out = np.asarray(x, np.float64).ravel().copy()
+    out[U] = xu
+    return g.size * it, out
+
+
+def cpu_baseline(boxes, seconds=15.0):
+    """The FP64 oracle (sparse Laplacian + Jacobi-PCG at the same tol) on a
+    time-bounded sample of the same boxes, one box per process."""
+    import multiprocessing as mp
+    workers = min(os.cpu_count() or 1, 16)
+    n = min(len(boxes), 4096)
+    t0 = time.time()
+    deadline = t0 + seconds
+    vi, done, sols = 0, 0, {}
+    with mp.get_context("fork").Pool(workers) as pool:
+        for i, r in enumerate(pool.imap(_oracle_worker, [(b[0], b[1], b[2], deadline) for b in boxes[:n]],
+                                        chunksize=1)):
+            if r is None:
+                continue
+            vi += r[0]
+            done += 1
+            sols[i] = r[1]
+    el = time.time() - t0
+    return {"value": vi / el, "unit": "voxel-iters/s", "cores": workers, "kind": "oracle",
+            "sample": f"first {done} of the {len(boxes)} boxes within a {seconds:.0f} s budget "
+                      f"({el:.1f} s wall, FP64 scipy CSR + numpy Jacobi-PCG, tol {TOL:g}, "
+                      f"one single-threaded process per core)"}, sols
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (boxes are independent; multi-GPU sharding "
+              "is a design note, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2103_09564_amd as rwg
+
+    dev = torch.device("cuda:0")
+    d = synth.stress_boxes(n=N_BOXES, seed=SEED)
+    shapes, offsets = d["shapes"], d["offsets"]
+    sizes = shapes.prod(axis=1).astype(np.int64)
+    g = torch.from_numpy(d["g"]).to(dev)
+    m = torch.from_numpy(d["mask"]).to(dev)
+    x0 = torch.from_numpy(d["x"]).to(dev)
+    x = x0.clone()
+    ctx = rwg.Context(0)
+    bricks = rwg.bricks_array(shapes, offsets)
+    st = torch.empty((N_BOXES, 32), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def run(prec, steps, warmup):
+        p = rwg.solve_params(beta=BETA, eps=EPS, tol=TOL, precision=prec, refine_max=1, inner_tol=1e-4)
+        for _ in range(warmup):
+            x.copy_(x0)
+            ctx.rw_solve_bricks(p, bricks, g, m, x, stats=st, stream=stream)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.perf_counter()
+        for e0, e1 in evs:
+            x.copy_(x0)
+            e0.record(stream)
+            ctx.rw_solve_bricks(p, bricks, g, m, x, stats=st, stream=stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        kern = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs])) / 1e3
+        s = rwg.stats_to_numpy(st)
+        iters = s["iters"].astype(np.int64) + s["refine_iters"].astype(np.int64)
+        vox_it = int(np.sum(sizes * iters))
+        return dict(wall=wall, kern=kern, vox_it=vox_it, stats=s, x=x.cpu().numpy())
+
+    mixed = run(rwg.PREC_MIXED, args.steps, args.warmup)
+    fp64 = None if args.no_fp64 else run(rwg.PREC_FP64, max(1, args.steps // 2), 1)
+
+    value = mixed["vox_it"] / mixed["wall"]
+    achieved = BYTES_PER_VOXEL_ITER * mixed["vox_it"] / mixed["kern"] / 1e9
+    traffic = traffic_from_profile()
+    s = mixed["stats"]
+    out = {
+        "metric": "brick-PCG voxel-iters/s, %HBM peak; mixed vs plain FP64 at 1e-4 err",
+        "value": value,
+        "unit": "voxel-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["wall"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "stress boxes: 8192 boxes, shapes U{32^3,32x32x17,32x9x32,5x32x32,16^3}, "
+                               "beta 128, eps 1e-6, tol 1e-6, mixed FP32/FP64",
+                   "n_boxes": N_BOXES, "voxels": int(sizes.sum()), "unknowns": int((d["mask"] == 0).sum()),
+                   "tol": TOL, "precision": "mixed (FP32 vectors, FP64 reductions + FP64 true-residual check)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic},
+        "solve": {"kernel_ms": mixed["kern"] * 1e3, "voxel_iters": mixed["vox_it"],
+                  "mean_iters": float(s["iters"].mean()), "max_iters": int(s["iters"].max()),
+                  "refined_boxes": int((s["refine_steps"] > 0).sum()),
+                  "status_counts": {rwg.STATUS_NAMES[k]: int((s["status"] == k).sum()) for k in np.unique(s["status"])},
+                  "max_true_rel_resid": float(s["true_rel_resid"].max()),
+                  "algorithmic_bytes_per_voxel_iter": BYTES_PER_VOXEL_ITER,
+                  "source_hash": source_hash()},
+    }
+    if fp64 is not None:
+        f = fp64["stats"]
+        out["fp64_plain"] = {"value": fp64["vox_it"] / fp64["wall"], "ms_per_step": fp64["wall"] * 1e3,
+                             "mean_iters": float(f["iters"].mean()),
+                             "max_true_rel_resid": float(f["true_rel_resid"].max())}
+        out["speedup_mixed_vs_fp64"] = fp64["wall"] / mixed["wall"]
+    if not args.no_cpu_baseline:
+        cb, sols = cpu_baseline(d["boxes"])
+        out["cpu_baseline"] = cb
+        err = {"mixed": 0.0}
+        if fp64 is not None:
+            err["fp64"] = 0.0
+        for i, ref in sols.items():
+            o, n = int(offsets[i]), int(sizes[i])
+            err["mixed"] = max(err["mixed"], float(np.max(np.abs(mixed["x"][o:o + n] - ref))))
+            if fp64 is not None:
+                err["fp64"] = max(err["fp64"], float(np.max(np.abs(fp64["x"][o:o + n] - ref))))
+        out["max_abs_diff_vs_oracle"] = dict(err, boxes=len(sols),
+                                             note="oracle at the same tol 1e-6; both sides carry solver error")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
