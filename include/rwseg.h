@@ -47,15 +47,16 @@ enum rw_precision {
     RW_PREC_FP64 = 0,          /* plain FP64 PCG: vectors, weights, reductions in FP64 */
     RW_PREC_MIXED = 1,         /* FP32 stencil/vectors, FP64 dot products, FP64 true-residual
                                   check, and at most refine_max FP32 correction solves when the
-                                  true residual misses tol */
+                                  true residual exceeds stall_ratio * tol */
     RW_PREC_MIXED_REFINE = 2   /* as MIXED, then FP64 iterative refinement of an FP64 copy of x
                                   until the FP64 true relative residual <= refine_tol */
 };
 
 enum rw_status {
-    RW_ST_CONVERGED = 0,     /* ||r|| <= tol ||b|| */
+    RW_ST_CONVERGED = 0,     /* recursive ||r|| <= tol ||b|| (and, MIXED, FP64 true residual
+                                <= stall_ratio * tol) */
     RW_ST_MAX_ITER = 1,      /* hit max_iter before tol */
-    RW_ST_REFINED = 2,       /* FP32 solve missed tol in FP64; refinement brought it within */
+    RW_ST_REFINED = 2,       /* FP32 solve stalled in FP64; refinement brought it within target */
     RW_ST_STALLED = 3,       /* refinement steps exhausted without meeting the target */
     RW_ST_NONFINITE = 4,     /* NaN/Inf met (input g or breakdown); x left as the last finite iterate */
     RW_ST_NO_DIRICHLET = 5   /* box has no seeded voxel: problem has no unique solution, x untouched */
@@ -90,10 +91,12 @@ typedef struct rw_solve_params {
     int32_t refine_max;      /* max correction solves (MIXED: usually 1, MIXED_REFINE: e.g. 4) */
     double refine_tol;       /* MIXED_REFINE target FP64 true relative residual */
     double inner_tol;        /* relative tolerance of each FP32 correction solve */
+    double stall_ratio;      /* MIXED: a box counts as stalled, and gets a correction solve, when
+                                its FP64 true relative residual exceeds stall_ratio * tol (>= 1) */
 } rw_solve_params;
 
 /* Fill *p with the defaults: beta 128, eps 1e-6, tol 1e-6, max_iter 5000,
- * MIXED, nrhs 1, refine_max 1, refine_tol 1e-13, inner_tol 1e-4. */
+ * MIXED, nrhs 1, refine_max 1, refine_tol 1e-13, inner_tol 1e-4, stall_ratio 10. */
 void rw_solve_params_default(rw_solve_params* p);
 
 typedef struct rw_ctx rw_ctx;

@@ -36,7 +36,8 @@ assert BRICK_DTYPE.itemsize == 24 and STATS_DTYPE.itemsize == 32
 class SolveParams(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32), ("nrhs", ctypes.c_int32),
-                ("refine_max", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("inner_tol", ctypes.c_double)]
+                ("refine_max", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
+                ("stall_ratio", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p

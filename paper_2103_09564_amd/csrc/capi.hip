@@ -15,6 +15,7 @@
 
 struct rw_ctx {
     int device = 0;
+    size_t lds_limit = 0;        // LDS bytes one workgroup may allocate
     std::string err;
     void* ws = nullptr;          // vector workspace
     size_t ws_bytes = 0;
@@ -89,6 +90,7 @@ int check_params(rw_ctx* ctx, const rw_solve_params* p) {
     if (p->refine_max < 0 || p->refine_max > 64) return fail(ctx, RW_E_INVAL, "refine_max must be in [0, 64]");
     if (!std::isfinite(p->refine_tol) || p->refine_tol < 0) return fail(ctx, RW_E_INVAL, "refine_tol must be >= 0");
     if (!std::isfinite(p->inner_tol) || p->inner_tol < 0) return fail(ctx, RW_E_INVAL, "inner_tol must be >= 0");
+    if (!std::isfinite(p->stall_ratio) || p->stall_ratio < 1) return fail(ctx, RW_E_INVAL, "stall_ratio must be >= 1");
     return RW_OK;
 }
 
@@ -125,6 +127,26 @@ int build_list(rw_ctx* ctx, int64_t n, const rw_brick* bricks, int64_t n_voxels,
     return RW_OK;
 }
 
+// Choose the PCG kernel split for this batch and move the boxes that are too
+// wide for the LDS plane march to the front of the (largest-first) list.
+rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, int nrhs, bool fp64) {
+    rwk::PlanePlan pp{0, 2, (int64_t)list->size()};
+    int widest = 0;
+    for (const auto& b : *list)
+        if (b.nx * b.ny <= rwk::plane_max(4)) widest = std::max(widest, b.nx * b.ny);
+    int cols = rwk::plane_cols(widest);
+    if (rwk::plane_lds_bytes(nrhs, fp64, cols) > ctx->lds_limit) cols = 2;
+    if (rwk::plane_lds_bytes(nrhs, fp64, cols) > ctx->lds_limit) return pp;
+    const int lim = rwk::plane_max(cols);
+    std::stable_partition(list->begin(), list->end(), [lim](const rwk::BrickDev& b) { return b.nx * b.ny > lim; });
+    int64_t n_big = 0;
+    for (const auto& b : *list) n_big += b.nx * b.ny > lim ? 1 : 0;
+    pp.use = 1;
+    pp.cols = cols;
+    pp.n_big = n_big;
+    return pp;
+}
+
 int upload_list(rw_ctx* ctx, const std::vector<rwk::BrickDev>& list, hipStream_t s) {
     size_t bytes = std::max<size_t>(list.size() * sizeof(rwk::BrickDev), 64);
     hipError_t e = grow(ctx, &ctx->bricks, &ctx->bricks_bytes, bytes, s);
@@ -152,6 +174,7 @@ void rw_solve_params_default(rw_solve_params* p) {
     p->refine_max = 1;
     p->refine_tol = 1e-13;
     p->inner_tol = 1e-4;
+    p->stall_ratio = 10.0;
 }
 
 int rw_version(void) { return RW_VERSION; }
@@ -167,6 +190,9 @@ int rw_ctx_create(int hip_device, rw_ctx** out) {
     rw_ctx* c = new (std::nothrow) rw_ctx();
     if (!c) return fail(nullptr, RW_E_NOMEM, "host allocation failed");
     c->device = hip_device;
+    int lds = 0;
+    e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device);
+    c->lds_limit = e == hipSuccess && lds > 0 ? (size_t)lds : 64 * 1024;
     *out = c;
     return RW_OK;
 }
@@ -221,6 +247,9 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
     if (need_x64 && !x64) bytes = off_x64 + nv * sizeof(double);
     hipError_t e = grow(ctx, &ctx->ws, &ctx->ws_bytes, std::max<size_t>(bytes, 256), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating solver workspace");
+    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, std::max<size_t>((size_t)n_bricks * sizeof(rwk::BoxState), 256), s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "allocating per-box state");
+    const rwk::PlanePlan pp = plan_planes(ctx, &list, R, fp64);
     rc = upload_list(ctx, list, s);
     if (rc) return rc;
 
@@ -240,6 +269,7 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
     a.xt = x64buf;
     a.want_x64 = x64 ? 1 : 0;
     a.stats = stats;
+    a.state = (rwk::BoxState*)ctx->aux;
     a.beta = p.beta;
     a.eps = p.eps;
     a.tol = p.tol;
@@ -248,7 +278,8 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
     a.max_iter = p.max_iter;
     a.precision = p.precision;
     a.refine_max = p.refine_max;
-    e = rwk::launch_solve(a, n_bricks, R, fp64, s);
+    a.stall_ratio = p.stall_ratio;
+    e = rwk::launch_solve(a, n_bricks, R, fp64, pp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching solve kernel");
     return RW_OK;
 }
@@ -276,8 +307,10 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     if (!lambda) bytes += nv * sizeof(float);
     hipError_t e = grow(ctx, &ctx->ws, &ctx->ws_bytes, std::max<size_t>(bytes, 256), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint workspace");
-    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, std::max<size_t>((size_t)n_bricks * sizeof(double), 256), s);
+    const size_t state_bytes = ((size_t)n_bricks * sizeof(rwk::BoxState) + 255) & ~size_t(255);
+    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, state_bytes + std::max<size_t>((size_t)n_bricks * sizeof(double), 256), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint partials");
+    const rwk::PlanePlan pp = plan_planes(ctx, &list, 1, false);
     rc = upload_list(ctx, list, s);
     if (rc) return rc;
     char* w = (char*)ctx->ws;
@@ -293,13 +326,28 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     a.p0 = (float*)(w + 2 * nv * 4);
     a.p1 = (float*)(w + 3 * nv * 4);
     a.lambda = lambda ? lambda : (float*)(w + off_lam);
-    a.beta_part = (double*)ctx->aux;
+    a.beta_part = (double*)((char*)ctx->aux + state_bytes);
     a.stats = stats;
     a.beta = params->beta;
     a.eps = params->eps;
     a.tol = params->tol;
     a.max_iter = params->max_iter;
-    e = rwk::launch_adjoint(a, n_bricks, dl_dbeta, s);
+    rwk::SolveArgs sa{};
+    sa.bricks = a.bricks;
+    sa.g = g;
+    sa.mask = mask;
+    sa.r = a.r;
+    sa.z = a.z;
+    sa.p0 = a.p0;
+    sa.p1 = a.p1;
+    sa.state = (rwk::BoxState*)ctx->aux;
+    sa.beta = a.beta;
+    sa.eps = a.eps;
+    sa.tol = a.tol;
+    sa.inner_tol = a.tol;
+    sa.max_iter = a.max_iter;
+    sa.precision = RW_PREC_MIXED;
+    e = rwk::launch_adjoint(a, sa, n_bricks, dl_dbeta, pp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching adjoint kernels");
     return RW_OK;
 }

@@ -16,6 +16,16 @@ struct BrickDev {
     int64_t off;
 };
 
+// Per-box scalars carried between the phases of one solve (launch order).
+struct BoxState {
+    double rz[3], rr[3], bb[3];   // r.z, ||r||^2, ||b||^2 per rhs
+    double nU, nM;                // unknown / seeded voxel counts
+    double rel, true_rel;         // recursive and FP64 true relative residual
+    int32_t iters, status, refine_steps, refine_iters;
+    int32_t active;               // next k_pcg runs on this machine
+    int32_t pending;              // a correction was solved and is to be applied
+};
+
 struct SolveArgs {
     const BrickDev* bricks;
     const float* g;
@@ -29,7 +39,8 @@ struct SolveArgs {
     void* xt;              // FP64 path: solution accumulator (double); unused otherwise
     float* dcorr;          // FP32 correction accumulator
     rw_brick_stats* stats;
-    double beta, eps, tol, refine_tol, inner_tol;
+    BoxState* state;       // [n_bricks], workspace
+    double beta, eps, tol, refine_tol, inner_tol, stall_ratio;
     int32_t max_iter, precision, refine_max, want_x64;
 };
 
@@ -51,8 +62,24 @@ struct AdjointArgs {
     int32_t max_iter;
 };
 
+// How the PCG kernel is split: boxes [0, n_big) of the launch list use the
+// global-memory march, [n_big, n) the LDS plane march with `cols` columns per
+// thread (planes up to plane_max(cols) voxels).  use = 0: all global.
+struct PlanePlan {
+    int use;
+    int cols;
+    int64_t n_big;
+};
+
+size_t plane_lds_bytes(int nrhs, bool fp64, int cols);
+int plane_cols(int max_plane);
+int plane_max(int cols);
+
 // Launchers (pcg.hip).  Return a hipError_t.
-hipError_t launch_solve(const SolveArgs& a, int64_t n_bricks, int nrhs, bool fp64, hipStream_t s);
-hipError_t launch_adjoint(const AdjointArgs& a, int64_t n_bricks, double* dl_dbeta, hipStream_t s);
+hipError_t launch_solve(const SolveArgs& a, int64_t n_bricks, int nrhs, bool fp64, const PlanePlan& pp,
+                        hipStream_t s);
+// The adjoint reuses the solve kernels: `sa` carries the PCG view (r, z, p, state) of the workspace.
+hipError_t launch_adjoint(const AdjointArgs& a, const SolveArgs& sa, int64_t n_bricks, double* dl_dbeta,
+                          const PlanePlan& pp, hipStream_t s);
 
 }  // namespace rwk

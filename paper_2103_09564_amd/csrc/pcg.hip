@@ -33,7 +33,7 @@
 
 namespace rwk {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 
 template <typename T>
@@ -84,6 +84,8 @@ template <typename T, int N>
 struct Val {
     T a[N];
 };
+template <typename T>
+struct Val<T, 0> {};
 
 // Sum N doubles over the workgroup; every thread receives the same bits.
 template <int N>
@@ -166,6 +168,129 @@ __device__ __forceinline__ void march(const Box& b, const float* __restrict__ g,
     }
 }
 
+// Plane march with in-plane exchange through LDS (boxes whose z-plane has at
+// most C*kThreads voxels).  Thread t owns the columns t + q*kThreads, q < C,
+// and walks them along z.  Per plane k: the operand (N values, e.g. p) and g
+// of plane k+1 go to one of three rotating LDS plane buffers, one barrier,
+// then every voxel of plane k reads its 4 in-plane neighbours from LDS and its
+// 2 z-neighbours from registers.  Global loads run two planes ahead of the
+// compute (operand, g, mask and NX private extras such as x and r), so each
+// wave keeps several loads in flight while it computes.  Only unknown voxels
+// are visited: visit_u(v, d, acc, self, extras).
+template <typename T, int N, int NX, int C, typename Load, typename LoadX, typename VisitU>
+__device__ __forceinline__ void plane_march(const Box& b, const float* __restrict__ g,
+                                            const uint8_t* __restrict__ m, const Weight<T>& W,
+                                            T* __restrict__ lds, Load load, LoadX loadx, VisitU visit_u) {
+    const int nxy = b.nxy;
+    const int sb = (N + 1) * nxy;
+    int col[C];
+    unsigned fl[C];  // 1 valid, 2 x-, 4 x+, 8 y-, 16 y+
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        const int c = threadIdx.x + q * kThreads;
+        col[q] = c;
+        fl[q] = 0;
+        if (c < nxy) {
+            const int j = c / b.nx, i = c - j * b.nx;
+            fl[q] = 1u | (i > 0 ? 2u : 0u) | (i + 1 < b.nx ? 4u : 0u) | (j > 0 ? 8u : 0u) |
+                    (j + 1 < b.ny ? 16u : 0u);
+        }
+    }
+    Val<T, N> sm[C], s0[C], su[C], sn[C];
+    Val<T, NX> x0[C], xu[C], xn[C];
+    T g0[C], gu[C], gn[C], wzm[C];
+    unsigned m0[C], mu[C], mn[C];
+    const int64_t off = b.off;
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) sm[q].a[a] = s0[q].a[a] = su[q].a[a] = sn[q].a[a] = T(0);
+        g0[q] = gu[q] = gn[q] = wzm[q] = T(0);
+        m0[q] = mu[q] = mn[q] = 1u;
+        if (fl[q]) {
+            const int64_t v = off + col[q];
+            s0[q] = load(v);
+            g0[q] = (T)g[v];
+            m0[q] = m[v];
+            x0[q] = loadx(v);
+            if (b.nz > 1) {
+                su[q] = load(v + nxy);
+                gu[q] = (T)g[v + nxy];
+                mu[q] = m[v + nxy];
+                xu[q] = loadx(v + nxy);
+            }
+#pragma unroll
+            for (int a = 0; a < N; ++a) lds[a * nxy + col[q]] = s0[q].a[a];
+            lds[N * nxy + col[q]] = g0[q];
+        }
+    }
+    for (int k = 0; k < b.nz; ++k) {
+        const int64_t base = off + (int64_t)k * nxy;
+        const bool h1 = k + 1 < b.nz, h2 = k + 2 < b.nz;
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+#pragma unroll
+            for (int a = 0; a < N; ++a) sn[q].a[a] = T(0);
+            gn[q] = T(0);
+            mn[q] = 1u;
+            if (fl[q] && h2) {
+                const int64_t u = base + 2 * nxy + col[q];
+                sn[q] = load(u);
+                gn[q] = (T)g[u];
+                mn[q] = m[u];
+                xn[q] = loadx(u);
+            }
+        }
+        if (h1) {
+            T* Lw = lds + ((k + 1) % 3) * sb;
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                if (fl[q]) {
+#pragma unroll
+                    for (int a = 0; a < N; ++a) Lw[a * nxy + col[q]] = su[q].a[a];
+                    Lw[N * nxy + col[q]] = gu[q];
+                }
+            }
+        }
+        __syncthreads();
+        const T* L = lds + (k % 3) * sb;
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            if (!fl[q]) continue;
+            const T wzp = h1 ? W(g0[q], gu[q]) : T(0);
+            if (m0[q] == 0) {
+                T d = wzm[q] + wzp;
+                Val<T, N> acc;
+#pragma unroll
+                for (int a = 0; a < N; ++a) acc.a[a] = wzm[q] * sm[q].a[a] + wzp * su[q].a[a];
+                const T gc = g0[q];
+                auto nb = [&](int cc) {
+                    const T w = W(gc, L[N * nxy + cc]);
+                    d += w;
+#pragma unroll
+                    for (int a = 0; a < N; ++a) acc.a[a] += w * L[a * nxy + cc];
+                };
+                if (fl[q] & 2u) nb(col[q] - 1);
+                if (fl[q] & 4u) nb(col[q] + 1);
+                if (fl[q] & 8u) nb(col[q] - b.nx);
+                if (fl[q] & 16u) nb(col[q] + b.nx);
+                visit_u(base + col[q], d, acc, s0[q], x0[q]);
+            }
+            wzm[q] = wzp;
+            sm[q] = s0[q];
+            s0[q] = su[q];
+            su[q] = sn[q];
+            g0[q] = gu[q];
+            gu[q] = gn[q];
+            m0[q] = mu[q];
+            mu[q] = mn[q];
+            x0[q] = xu[q];
+            xu[q] = xn[q];
+        }
+    }
+    __syncthreads();
+}
+
 // Plain loop over the voxels of a box (pointwise sweeps).
 template <typename F>
 __device__ __forceinline__ void each_voxel(const Box& b, F f) {
@@ -207,6 +332,7 @@ __device__ void init_implicit(const Box& b, const float* __restrict__ g, const u
             V.r[v * R + k] = rv;
             V.z[v * R + k] = zv;
             V.p[0][v * R + k] = T(0);
+            V.p[1][v * R + k] = T(0);
             rz[k] += (double)rv * (double)zv;
             rr[k] += (double)rv * (double)rv;
             bb[k] += (double)acc.a[R + k] * (double)acc.a[R + k];
@@ -219,6 +345,7 @@ __device__ void init_implicit(const Box& b, const float* __restrict__ g, const u
             V.r[v * R + k] = T(0);
             V.z[v * R + k] = T(0);
             V.p[0][v * R + k] = T(0);
+            V.p[1][v * R + k] = T(0);
         }
         nM += 1.0;
     };
@@ -245,6 +372,7 @@ __device__ void init_explicit(const Box& b, const float* __restrict__ g, const u
             const T zv = rv * id;
             V.z[v * R + k] = zv;
             V.p[0][v * R + k] = T(0);
+            V.p[1][v * R + k] = T(0);
             tgt[v * R + k] = XT(0);
             rz[k] += (double)rv * (double)zv;
             rr[k] += (double)rv * (double)rv;
@@ -256,6 +384,7 @@ __device__ void init_explicit(const Box& b, const float* __restrict__ g, const u
             V.r[v * R + k] = T(0);
             V.z[v * R + k] = T(0);
             V.p[0][v * R + k] = T(0);
+            V.p[1][v * R + k] = T(0);
             tgt[v * R + k] = XT(0);
         }
     };
@@ -295,16 +424,29 @@ __device__ void true_residual(const Box& b, const float* __restrict__ g, const u
 }
 
 // Sweep A: p_new = z + beta p_old, sigma = p_new . L_UU p_new.
-template <typename T, int R>
+template <typename T, int R, int C>
 __device__ void sweep_pq(const Box& b, const float* __restrict__ g, const uint8_t* __restrict__ m,
                          const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
-                         const T (&bk)[R], const Weight<T>& W, double (&sig)[R]) {
+                         const T (&bk)[R], const Weight<T>& W, double (&sig)[R], T* lds, bool plane) {
     auto load = [&](int64_t u) {
         Val<T, R> o;
 #pragma unroll
         for (int k = 0; k < R; ++k) o.a[k] = z[u * R + k] + bk[k] * pold[u * R + k];
         return o;
     };
+    if (plane) {
+        auto nox = [&](int64_t) { return Val<T, 0>{}; };
+        auto vp = [&](int64_t v, T d, const Val<T, R>& acc, const Val<T, R>& self, const Val<T, 0>&) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const T q = d * self.a[k] - acc.a[k];
+                sig[k] += (double)self.a[k] * (double)q;
+                pnew[v * R + k] = self.a[k];
+            }
+        };
+        plane_march<T, R, 0, C>(b, g, m, W, lds, load, nox, vp);
+        return;
+    }
     auto vu = [&](int64_t v, T d, const Val<T, R>& acc, const Val<T, R>& self) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -321,16 +463,44 @@ __device__ void sweep_pq(const Box& b, const float* __restrict__ g, const uint8_
 }
 
 // Sweep B: q = L_UU p, x += alpha p, r -= alpha q, z = r/d, rho' and ||r||^2.
-template <typename T, int R, typename XT>
+template <typename T, int R, int C, typename XT>
 __device__ void sweep_update(const Box& b, const float* __restrict__ g, const uint8_t* __restrict__ m,
                              const T* __restrict__ p, Vecs<T, R> V, XT* __restrict__ xt,
-                             const T (&al)[R], const Weight<T>& W, double (&rz)[R], double (&rr)[R]) {
+                             const T (&al)[R], const Weight<T>& W, double (&rz)[R], double (&rr)[R],
+                             T* lds, bool plane) {
     auto load = [&](int64_t u) {
         Val<T, R> o;
 #pragma unroll
         for (int k = 0; k < R; ++k) o.a[k] = p[u * R + k];
         return o;
     };
+    if (plane) {
+        auto lx = [&](int64_t u) {
+            Val<T, 2 * R> o;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                o.a[k] = (T)xt[u * R + k];
+                o.a[R + k] = V.r[u * R + k];
+            }
+            return o;
+        };
+        auto vp = [&](int64_t v, T d, const Val<T, R>& acc, const Val<T, R>& self, const Val<T, 2 * R>& ex) {
+            const T id = recip(d);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const T q = d * self.a[k] - acc.a[k];
+                xt[v * R + k] = (XT)(ex.a[k] + al[k] * self.a[k]);
+                const T rv = ex.a[R + k] - al[k] * q;
+                const T zv = rv * id;
+                V.r[v * R + k] = rv;
+                V.z[v * R + k] = zv;
+                rz[k] += (double)rv * (double)zv;
+                rr[k] += (double)rv * (double)rv;
+            }
+        };
+        plane_march<T, R, 2 * R, C>(b, g, m, W, lds, load, lx, vp);
+        return;
+    }
     auto vu = [&](int64_t v, T d, const Val<T, R>& acc, const Val<T, R>& self) {
         const T id = recip(d);
 #pragma unroll
@@ -352,19 +522,23 @@ __device__ void sweep_update(const Box& b, const float* __restrict__ g, const ui
 __device__ __forceinline__ bool finite(double v) { return isfinite(v); }
 
 // Jacobi-PCG from an initialised state (r, z, p[0] = 0).  Returns iterations;
-// sets *nonfinite on breakdown.  done[k] marks rhs that met tol.
-template <typename T, int R, typename XT>
-__device__ int pcg_loop(const Box& b, const float* __restrict__ g, const uint8_t* __restrict__ m,
-                        Vecs<T, R> V, XT* __restrict__ xt, const Weight<T>& W, double (&rz)[R],
-                        double (&rr)[R], const double (&bb)[R], double tol, int max_iter,
-                        bool* nonfinite, bool* hit_cap, double* red) {
+// flags breakdown / the iteration cap.  done[k] marks rhs that met tol.
+struct LoopEnd {
+    int iters;
+    int flags;  // 1: non-finite / breakdown, 2: iteration cap
+};
+
+template <typename T, int R, int C, bool kPlane, typename XT>
+__device__ LoopEnd pcg_loop(const Box& b, const float* __restrict__ g, const uint8_t* __restrict__ m,
+                            Vecs<T, R> V, XT* __restrict__ xt, const Weight<T>& W, double (&rz)[R],
+                            double (&rr)[R], const double (&bb)[R], double tol, int max_iter, double* red,
+                            T* lds) {
     double betac[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) betac[k] = 0.0;
     const double tol2 = tol * tol;
     int it = 0;
-    *nonfinite = false;
-    *hit_cap = false;
+    int flags = 0;
     for (;;) {
         bool done[R];
         bool all = true;
@@ -375,18 +549,19 @@ __device__ int pcg_loop(const Box& b, const float* __restrict__ g, const uint8_t
         }
         if (all) break;
         if (it >= max_iter) {
-            *hit_cap = true;
+            flags = 2;
             break;
         }
-        T* pold = V.p[it & 1];
-        T* pnew = V.p[(it + 1) & 1];
+        // select, not index: a dynamically indexed pointer pair would live in scratch
+        T* pold = (it & 1) ? V.p[1] : V.p[0];
+        T* pnew = (it & 1) ? V.p[0] : V.p[1];
         T bk[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) bk[k] = done[k] ? T(0) : (T)betac[k];
         double sig[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) sig[k] = 0.0;
-        sweep_pq<T, R>(b, g, m, V.z, pold, pnew, bk, W, sig);
+        sweep_pq<T, R, C>(b, g, m, V.z, pold, pnew, bk, W, sig, lds, kPlane);
         block_sum<R>(sig, red);
         T al[R];
         bool bad = false;
@@ -397,13 +572,13 @@ __device__ int pcg_loop(const Box& b, const float* __restrict__ g, const uint8_t
             al[k] = bad ? T(0) : (T)a;
         }
         if (bad) {
-            *nonfinite = true;
+            flags = 1;
             break;
         }
         double rzn[R], rrn[R], acc[2 * R];
 #pragma unroll
         for (int k = 0; k < R; ++k) rzn[k] = rrn[k] = 0.0;
-        sweep_update<T, R, XT>(b, g, m, pnew, V, xt, al, W, rzn, rrn);
+        sweep_update<T, R, C, XT>(b, g, m, pnew, V, xt, al, W, rzn, rrn, lds, kPlane);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             acc[k] = rzn[k];
@@ -420,266 +595,339 @@ __device__ int pcg_loop(const Box& b, const float* __restrict__ g, const uint8_t
         }
         ++it;
         if (bad) {
-            *nonfinite = true;
+            flags = 1;
             break;
         }
     }
-    return it;
+    return LoopEnd{it, flags};
 }
 
-template <typename T, int R>
-__global__ __launch_bounds__(kThreads) void k_solve(SolveArgs a) {
-    __shared__ double red[kWaves * 4 * 3];
-    const BrickDev bd = a.bricks[blockIdx.x];
-    const Box b{bd.off, bd.nx, bd.ny, bd.nz, bd.nx * bd.ny};
-    const Weight<T> W = make_weight<T>(a.beta, a.eps);
-    Vecs<T, R> V{(T*)a.r, (T*)a.z, {(T*)a.p0, (T*)a.p1}};
-    constexpr bool kF64 = sizeof(T) == 8;
+// ---------------------------------------------------------------------------
+// Kernels.  A solve is a short sequence of launches over the same box list
+// (one workgroup per box, launch order = largest box first); per-box scalars
+// travel between them in BoxState.  Splitting the phases keeps the register
+// budget of the hot PCG kernel to what its two sweeps need.
+// ---------------------------------------------------------------------------
 
+template <typename T, int R>
+__device__ __forceinline__ Vecs<T, R> vecs(const SolveArgs& a) {
+    return Vecs<T, R>{(T*)a.r, (T*)a.z, {(T*)a.p0, (T*)a.p1}};
+}
+
+__device__ __forceinline__ Box box_of(const BrickDev& bd) {
+    return Box{bd.off, bd.nx, bd.ny, bd.nz, bd.nx * bd.ny};
+}
+
+// Phase 1: Dirichlet init, per-box decision (no seed / no unknown / zero rhs).
+template <typename T, int R>
+__global__ __launch_bounds__(kThreads) void k_init(SolveArgs a) {
+    __shared__ double red[kWaves * 12];
+    const BrickDev bd = a.bricks[blockIdx.x];
+    const Box b = box_of(bd);
+    const Weight<T> W = make_weight<T>(a.beta, a.eps);
+    Vecs<T, R> V = vecs<T, R>(a);
     double rz[R], rr[R], bb[R], nU = 0.0, nM = 0.0;
 #pragma unroll
     for (int k = 0; k < R; ++k) rz[k] = rr[k] = bb[k] = 0.0;
     init_implicit<T, R>(b, a.g, a.mask, a.x, V, W, rz, rr, bb, nU, nM);
-    {
-        double s[3 * R + 2];
+    double s[3 * R + 2];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            s[k] = rz[k];
-            s[R + k] = rr[k];
-            s[2 * R + k] = bb[k];
-        }
-        s[3 * R] = nU;
-        s[3 * R + 1] = nM;
-        block_sum<3 * R + 2>(s, red);
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            rz[k] = s[k];
-            rr[k] = s[R + k];
-            bb[k] = s[2 * R + k];
-        }
-        nU = s[3 * R];
-        nM = s[3 * R + 1];
+    for (int k = 0; k < R; ++k) {
+        s[k] = rz[k];
+        s[R + k] = rr[k];
+        s[2 * R + k] = bb[k];
     }
-
-    rw_brick_stats st{};
-    st.status = RW_ST_CONVERGED;
-    T* xt;
-    if constexpr (kF64) {
-        xt = (T*)a.xt;
+    s[3 * R] = nU;
+    s[3 * R + 1] = nM;
+    block_sum<3 * R + 2>(s, red);
+    T* xt = sizeof(T) == 8 ? (T*)a.xt : (T*)a.x;
+    if (sizeof(T) == 8) {
         each_voxel(b, [&](int64_t v) {
 #pragma unroll
             for (int k = 0; k < R; ++k) xt[v * R + k] = (T)a.x[v * R + k];
         });
-    } else {
-        xt = (T*)a.x;
     }
-    bool bzero = true;
+    nU = s[3 * R];
+    nM = s[3 * R + 1];
+    bool allzero = true, anyzero = false;
 #pragma unroll
-    for (int k = 0; k < R; ++k) bzero = bzero && (bb[k] == 0.0);
-
-    if (nM == 0.0) {
-        st.status = RW_ST_NO_DIRICHLET;
-    } else if (nU > 0.0) {
-        bool nonfinite = false, cap = false;
-        // ||b|| = 0 for an rhs: its solution is x_U = 0 (no iterations)
-        bool anyzero = false;
-#pragma unroll
-        for (int k = 0; k < R; ++k) anyzero = anyzero || (bb[k] == 0.0);
-        if (anyzero) {
-            const double* bbp = bb;
-            each_voxel(b, [&](int64_t v) {
-                if (a.mask[v] == 0) {
-#pragma unroll
-                    for (int k = 0; k < R; ++k)
-                        if (bbp[k] == 0.0) {
-                            xt[v * R + k] = T(0);
-                            V.r[v * R + k] = T(0);
-                            V.z[v * R + k] = T(0);
-                        }
-                }
-            });
-#pragma unroll
-            for (int k = 0; k < R; ++k)
-                if (bb[k] == 0.0) rr[k] = rz[k] = 0.0;
-            __syncthreads();
-        }
-        if (!bzero) {
-            st.iters = pcg_loop<T, R, T>(b, a.g, a.mask, V, xt, W, rz, rr, bb, a.tol, a.max_iter,
-                                         &nonfinite, &cap, red);
-        }
-        double rel = 0.0;
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-            if (bb[k] > 0.0) rel = fmax(rel, sqrt(rr[k] / bb[k]));
-        st.rel_resid = rel;
-        if (nonfinite) st.status = RW_ST_NONFINITE;
-        else if (cap) st.status = RW_ST_MAX_ITER;
+    for (int k = 0; k < R; ++k) {
+        allzero = allzero && s[2 * R + k] == 0.0;
+        anyzero = anyzero || s[2 * R + k] == 0.0;
     }
-    __syncthreads();
-
-    // FP64 true residual of the result; mixed path: refinement.
-    if (nM > 0.0 && nU > 0.0 && st.status != RW_ST_NONFINITE) {
-        if constexpr (kF64) {
-            double r2[R], b2[R], q[2 * R];
-#pragma unroll
-            for (int k = 0; k < R; ++k) r2[k] = b2[k] = 0.0;
-            true_residual<R, T, float>(b, a.g, a.mask, xt, (float*)nullptr, a.beta, a.eps, r2, b2);
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                q[k] = r2[k];
-                q[R + k] = b2[k];
-            }
-            block_sum<2 * R>(q, red);
-            double tr = 0.0;
-#pragma unroll
-            for (int k = 0; k < R; ++k)
-                if (q[R + k] > 0.0) tr = fmax(tr, sqrt(q[k] / q[R + k]));
-            st.true_rel_resid = tr;
-        } else {
-            const bool refine64 = a.precision == RW_PREC_MIXED_REFINE;
-            const double target = refine64 ? a.refine_tol : a.tol;
-            double* x64 = a.x64;
-            if (refine64) {
-                each_voxel(b, [&](int64_t v) {
-#pragma unroll
-                    for (int k = 0; k < R; ++k) x64[v * R + k] = (double)a.x[v * R + k];
-                });
-                __syncthreads();
-            }
-            int steps = 0, riters = 0;
-            double tr = 0.0;
-            for (;;) {
-                double r2[R], b2[R], q[2 * R];
-#pragma unroll
-                for (int k = 0; k < R; ++k) r2[k] = b2[k] = 0.0;
-                if (refine64)
-                    true_residual<R, double, T>(b, a.g, a.mask, x64, V.r, a.beta, a.eps, r2, b2);
-                else
-                    true_residual<R, float, T>(b, a.g, a.mask, a.x, V.r, a.beta, a.eps, r2, b2);
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    q[k] = r2[k];
-                    q[R + k] = b2[k];
-                }
-                block_sum<2 * R>(q, red);
-                tr = 0.0;
-                bool ok = true;
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    if (q[R + k] > 0.0) tr = fmax(tr, sqrt(q[k] / q[R + k]));
-                    if (q[k] > target * target * q[R + k]) ok = false;
-                }
-                if (ok || steps >= a.refine_max) break;
-                // correction solve L_UU d = r64 in FP32, from d = 0
-                double crz[R], crr[R], cbb[R], e[2 * R];
-#pragma unroll
-                for (int k = 0; k < R; ++k) crz[k] = crr[k] = 0.0;
-                init_explicit<T, R, float>(b, a.g, a.mask, V, a.dcorr, W, crz, crr);
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    e[k] = crz[k];
-                    e[R + k] = crr[k];
-                }
-                block_sum<2 * R>(e, red);
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    crz[k] = e[k];
-                    crr[k] = cbb[k] = e[R + k];
-                }
-                bool nf = false, cap = false;
-                riters += pcg_loop<T, R, float>(b, a.g, a.mask, V, a.dcorr, W, crz, crr, cbb,
-                                                a.inner_tol, a.max_iter, &nf, &cap, red);
-                __syncthreads();
-                if (nf) break;
-                if (refine64) {
-                    each_voxel(b, [&](int64_t v) {
-                        if (a.mask[v] == 0) {
-#pragma unroll
-                            for (int k = 0; k < R; ++k) x64[v * R + k] += (double)a.dcorr[v * R + k];
-                        }
-                    });
-                } else {
-                    each_voxel(b, [&](int64_t v) {
-                        if (a.mask[v] == 0) {
-#pragma unroll
-                            for (int k = 0; k < R; ++k) a.x[v * R + k] += a.dcorr[v * R + k];
-                        }
-                    });
-                }
-                __syncthreads();
-                ++steps;
-            }
-            st.true_rel_resid = tr;
-            st.refine_steps = steps;
-            st.refine_iters = riters;
-            if (steps > 0 && st.status == RW_ST_CONVERGED) {
-                bool ok = tr <= target;
-                st.status = ok ? RW_ST_REFINED : RW_ST_STALLED;
-            }
-            if (refine64) {
-                each_voxel(b, [&](int64_t v) {
-                    if (a.mask[v] == 0) {
-#pragma unroll
-                        for (int k = 0; k < R; ++k) a.x[v * R + k] = (float)x64[v * R + k];
-                    }
-                });
-            }
-        }
-    }
-    // outputs
-    if constexpr (kF64) {
+    if (nM > 0.0 && nU > 0.0 && anyzero) {
+        // ||b|| = 0 for an rhs: its solution is x_U = 0, no iterations
+        __syncthreads();
         each_voxel(b, [&](int64_t v) {
+            if (a.mask[v] == 0) {
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const double xv = (double)xt[v * R + k];
-                if (a.mask[v] == 0) a.x[v * R + k] = (float)xv;
-                if (a.want_x64) a.x64[v * R + k] = xv;
+                for (int k = 0; k < R; ++k)
+                    if (s[2 * R + k] == 0.0) {
+                        xt[v * R + k] = T(0);
+                        V.r[v * R + k] = T(0);
+                        V.z[v * R + k] = T(0);
+                    }
             }
         });
-    } else if (a.want_x64 && a.precision != RW_PREC_MIXED_REFINE) {
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (s[2 * R + k] == 0.0) s[k] = s[R + k] = 0.0;
+    }
+    if (threadIdx.x == 0) {
+        BoxState& st = a.state[blockIdx.x];
+        for (int k = 0; k < 3; ++k) st.rz[k] = st.rr[k] = st.bb[k] = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            st.rz[k] = s[k];
+            st.rr[k] = s[R + k];
+            st.bb[k] = s[2 * R + k];
+        }
+        st.nU = nU;
+        st.nM = nM;
+        st.rel = 0.0;
+        st.true_rel = 0.0;
+        st.iters = st.refine_steps = st.refine_iters = 0;
+        st.status = nM == 0.0 ? RW_ST_NO_DIRICHLET : RW_ST_CONVERGED;
+        st.active = (nM > 0.0 && nU > 0.0 && !allzero) ? 1 : 0;
+        st.pending = 0;
+    }
+}
+
+// Phase 2: the PCG loop on every active box.  corr = 0: main solve into xt
+// (x, or the FP64 accumulator on the FP64 path); corr = 1: FP32 correction
+// solve into dcorr from the state init_explicit left (tolerance inner_tol).
+template <typename T, int R, int C, bool kPlane, typename XT>
+__global__ __launch_bounds__(kThreads) void k_pcg(SolveArgs a, XT* xt, int corr, int base) {
+    __shared__ double red[kWaves * 12];
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    const int ib = base + blockIdx.x;
+    BoxState& st = a.state[ib];
+    if (!st.active) return;
+    const BrickDev bd = a.bricks[ib];
+    const Box b = box_of(bd);
+    const Weight<T> W = make_weight<T>(a.beta, a.eps);
+    Vecs<T, R> V = vecs<T, R>(a);
+    double rz[R], rr[R], bb[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        rz[k] = st.rz[k];
+        rr[k] = st.rr[k];
+        bb[k] = st.bb[k];
+    }
+    const LoopEnd e = pcg_loop<T, R, C, kPlane, XT>(b, a.g, a.mask, V, xt, W, rz, rr, bb,
+                                                    corr ? a.inner_tol : a.tol, a.max_iter, red,
+                                                    reinterpret_cast<T*>(dyn_lds));
+    if (threadIdx.x == 0) {
+        if (corr) {
+            st.refine_iters += e.iters;
+        } else {
+            st.iters = e.iters;
+            double rel = 0.0;
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                if (bb[k] > 0.0) rel = fmax(rel, sqrt(rr[k] / bb[k]));
+            st.rel = rel;
+            if (e.flags & 2) st.status = RW_ST_MAX_ITER;
+        }
+        if (e.flags & 1) st.status = RW_ST_NONFINITE;
+        st.pending = corr && !(e.flags & 1) ? 1 : 0;
+    }
+}
+
+// Phase 3: FP64 true residual of the current solution (x, or x64 when
+// refine64), relative to ||b||.  With may_refine, a box whose residual misses
+// its target (stall_ratio*tol for MIXED, refine_tol for MIXED_REFINE) gets the
+// correction system L_UU d = r64 initialised (r <- r64, z, p, d = 0) and is
+// marked active for the next k_pcg(corr = 1).
+template <int R, bool kRefine64>
+__global__ __launch_bounds__(kThreads) void k_check(SolveArgs a, int may_refine) {
+    __shared__ double red[kWaves * 12];
+    BoxState& st = a.state[blockIdx.x];
+    const bool solved = st.nM > 0.0 && st.nU > 0.0 && st.status != RW_ST_NONFINITE;
+    if (!solved) {
+        if (threadIdx.x == 0) st.active = 0;
+        return;
+    }
+    const BrickDev bd = a.bricks[blockIdx.x];
+    const Box b = box_of(bd);
+    Vecs<float, R> V = vecs<float, R>(a);
+    double r2[R], b2[R], q[2 * R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) r2[k] = b2[k] = 0.0;
+    if (kRefine64)
+        true_residual<R, double, float>(b, a.g, a.mask, a.x64, V.r, a.beta, a.eps, r2, b2);
+    else
+        true_residual<R, float, float>(b, a.g, a.mask, a.x, V.r, a.beta, a.eps, r2, b2);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        q[k] = r2[k];
+        q[R + k] = b2[k];
+    }
+    block_sum<2 * R>(q, red);
+    const double target = kRefine64 ? a.refine_tol : a.tol * a.stall_ratio;
+    double tr = 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if (q[R + k] > 0.0) tr = fmax(tr, sqrt(q[k] / q[R + k]));
+        if (q[k] > target * target * q[R + k]) ok = false;
+    }
+    const bool refine = may_refine && !ok && st.refine_steps < a.refine_max;
+    if (refine) {
+        const Weight<float> W = make_weight<float>(a.beta, a.eps);
+        double crz[R], crr[R], e[2 * R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) crz[k] = crr[k] = 0.0;
+        __syncthreads();
+        init_explicit<float, R, float>(b, a.g, a.mask, V, a.dcorr, W, crz, crr);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            e[k] = crz[k];
+            e[R + k] = crr[k];
+        }
+        block_sum<2 * R>(e, red);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                st.rz[k] = e[k];
+                st.rr[k] = st.bb[k] = e[R + k];
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        st.true_rel = tr;
+        st.active = refine ? 1 : 0;
+        if (!may_refine && st.refine_steps > 0 && st.status == RW_ST_CONVERGED)
+            st.status = ok ? RW_ST_REFINED : RW_ST_STALLED;
+    }
+}
+
+// Phase 4: add the correction d to x (MIXED) or to x64 (MIXED_REFINE).
+template <int R, bool kRefine64>
+__global__ __launch_bounds__(kThreads) void k_apply(SolveArgs a) {
+    BoxState& st = a.state[blockIdx.x];
+    if (!st.pending) return;
+    const Box b = box_of(a.bricks[blockIdx.x]);
+    each_voxel(b, [&](int64_t v) {
+        if (a.mask[v] == 0) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                if (kRefine64) a.x64[v * R + k] += (double)a.dcorr[v * R + k];
+                else a.x[v * R + k] += a.dcorr[v * R + k];
+            }
+        }
+    });
+    if (threadIdx.x == 0) {
+        st.refine_steps += 1;
+        st.pending = 0;
+    }
+}
+
+// Copy x into the FP64 accumulator (MIXED_REFINE start) or back (end).
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_copy64(SolveArgs a, int to64) {
+    const Box b = box_of(a.bricks[blockIdx.x]);
+    each_voxel(b, [&](int64_t v) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (to64) a.x64[v * R + k] = (double)a.x[v * R + k];
+            else if (a.mask[v] == 0) a.x[v * R + k] = (float)a.x64[v * R + k];
+        }
+    });
+}
+
+// FP64 path end: true residual of the FP64 solution (stats), x <- (float)x64.
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_finish64(SolveArgs a) {
+    __shared__ double red[kWaves * 12];
+    BoxState& st = a.state[blockIdx.x];
+    const Box b = box_of(a.bricks[blockIdx.x]);
+    const double* xt = (const double*)a.xt;
+    if (st.nM > 0.0 && st.nU > 0.0 && st.status != RW_ST_NONFINITE) {
+        double r2[R], b2[R], q[2 * R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) r2[k] = b2[k] = 0.0;
+        true_residual<R, double, float>(b, a.g, a.mask, xt, (float*)nullptr, a.beta, a.eps, r2, b2);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            q[k] = r2[k];
+            q[R + k] = b2[k];
+        }
+        block_sum<2 * R>(q, red);
+        double tr = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (q[R + k] > 0.0) tr = fmax(tr, sqrt(q[k] / q[R + k]));
+        if (threadIdx.x == 0) st.true_rel = tr;
+    }
+    each_voxel(b, [&](int64_t v) {
+        if (a.mask[v] == 0) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) a.x[v * R + k] = (float)xt[v * R + k];
+        }
+    });
+}
+
+// Last phase: stats in caller order, optional FP64 copy of the result.
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_stats(SolveArgs a, int copy64) {
+    const BrickDev bd = a.bricks[blockIdx.x];
+    if (copy64) {
+        const Box b = box_of(bd);
         each_voxel(b, [&](int64_t v) {
 #pragma unroll
             for (int k = 0; k < R; ++k) a.x64[v * R + k] = (double)a.x[v * R + k];
         });
     }
-    if (threadIdx.x == 0 && a.stats) a.stats[bd.slot] = st;
+    if (threadIdx.x == 0 && a.stats) {
+        const BoxState& st = a.state[blockIdx.x];
+        rw_brick_stats o{};
+        o.iters = st.iters;
+        o.status = st.status;
+        o.refine_steps = st.refine_steps;
+        o.refine_iters = st.refine_iters;
+        o.rel_resid = st.rel;
+        o.true_rel_resid = st.true_rel;
+        a.stats[bd.slot] = o;
+    }
 }
 
-// Adjoint: L_UU lambda = dl/dx_U (FP32 PCG), then the edge gradient in
-// gather form (every voxel sums over its own edges; no atomics).
-__global__ __launch_bounds__(kThreads) void k_adjoint(AdjointArgs a) {
-    __shared__ double red[kWaves * 4 * 3];
-    const BrickDev bd = a.bricks[blockIdx.x];
-    const Box b{bd.off, bd.nx, bd.ny, bd.nz, bd.nx * bd.ny};
+// Adjoint phases: rhs dl/dx on U -> explicit init; PCG into lambda; gradient.
+__global__ __launch_bounds__(kThreads) void k_adj_init(AdjointArgs a, SolveArgs sa) {
+    __shared__ double red[kWaves * 12];
+    const Box b = box_of(a.bricks[blockIdx.x]);
     const Weight<float> W = make_weight<float>(a.beta, a.eps);
     Vecs<float, 1> V{a.r, a.z, {a.p0, a.p1}};
-    // rhs into r (U only), count seeds
     double cnt[1] = {0.0};
     each_voxel(b, [&](int64_t v) {
         const bool u = a.mask[v] == 0;
         a.r[v] = u ? a.dl_dx[v] : 0.0f;
         if (!u) cnt[0] += 1.0;
     });
-    block_sum<1>(cnt, red);
-    rw_brick_stats st{};
+    block_sum<1>(cnt, red);   // barrier: r complete before init_explicit reads it
     double rz[1] = {0.0}, rr[1] = {0.0};
     init_explicit<float, 1, float>(b, a.g, a.mask, V, a.lambda, W, rz, rr);
     double e[2] = {rz[0], rr[0]};
     block_sum<2>(e, red);
-    rz[0] = e[0];
-    rr[0] = e[1];
-    double bb[1] = {rr[0]};
-    if (cnt[0] == 0.0) {
-        st.status = RW_ST_NO_DIRICHLET;
-    } else if (bb[0] > 0.0) {
-        bool nf = false, cap = false;
-        st.iters = pcg_loop<float, 1, float>(b, a.g, a.mask, V, a.lambda, W, rz, rr, bb, a.tol,
-                                             a.max_iter, &nf, &cap, red);
-        st.rel_resid = sqrt(rr[0] / bb[0]);
-        st.status = nf ? RW_ST_NONFINITE : (cap ? RW_ST_MAX_ITER : RW_ST_CONVERGED);
+    if (threadIdx.x == 0) {
+        BoxState& st = sa.state[blockIdx.x];
+        st.rz[0] = e[0];
+        st.rr[0] = st.bb[0] = e[1];
+        st.nM = cnt[0];
+        st.nU = (double)b.nxy * b.nz - cnt[0];
+        st.iters = st.refine_steps = st.refine_iters = 0;
+        st.rel = st.true_rel = 0.0;
+        st.status = cnt[0] == 0.0 ? RW_ST_NO_DIRICHLET : RW_ST_CONVERGED;
+        st.active = (cnt[0] > 0.0 && e[1] > 0.0) ? 1 : 0;
+        st.pending = 0;
     }
-    __syncthreads();
-    // gradient sweep
+}
+
+__global__ __launch_bounds__(kThreads) void k_adj_grad(AdjointArgs a, SolveArgs sa) {
+    __shared__ double red[kWaves * 12];
+    const BrickDev bd = a.bricks[blockIdx.x];
+    const Box b = box_of(bd);
+    const Weight<float> W = make_weight<float>(a.beta, a.eps);
     const float beta = (float)a.beta, eps = (float)a.eps;
     double db[1] = {0.0};
     for (int c = threadIdx.x; c < b.nxy; c += kThreads) {
@@ -707,7 +955,14 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjointArgs a) {
     block_sum<1>(db, red);
     if (threadIdx.x == 0) {
         a.beta_part[blockIdx.x] = db[0];
-        if (a.stats) a.stats[bd.slot] = st;
+        const BoxState& st = sa.state[blockIdx.x];
+        if (a.stats) {
+            rw_brick_stats o{};
+            o.iters = st.iters;
+            o.status = st.status;
+            o.rel_resid = st.bb[0] > 0.0 ? sqrt(st.rr[0] / st.bb[0]) : 0.0;
+            a.stats[bd.slot] = o;
+        }
     }
 }
 
@@ -715,35 +970,114 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjointArgs a) {
 __global__ __launch_bounds__(kThreads) void k_sum_partials(const double* part, int64_t n, double* out) {
     __shared__ double red[kWaves];
     double s[1] = {0.0};
-    // fixed assignment of partials to threads, fixed tree: deterministic
     for (int64_t i = threadIdx.x; i < n; i += kThreads) s[0] += part[i];
     block_sum<1>(s, red);
     if (threadIdx.x == 0) *out = s[0];
 }
 
-hipError_t launch_solve(const SolveArgs& a, int64_t n, int nrhs, bool fp64, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    dim3 grid((unsigned)n), block(kThreads);
-    if (fp64) {
-        switch (nrhs) {
-            case 1: hipLaunchKernelGGL((k_solve<double, 1>), grid, block, 0, s, a); break;
-            case 2: hipLaunchKernelGGL((k_solve<double, 2>), grid, block, 0, s, a); break;
-            case 3: hipLaunchKernelGGL((k_solve<double, 3>), grid, block, 0, s, a); break;
-            default: return hipErrorInvalidValue;
-        }
-    } else {
-        switch (nrhs) {
-            case 1: hipLaunchKernelGGL((k_solve<float, 1>), grid, block, 0, s, a); break;
-            case 2: hipLaunchKernelGGL((k_solve<float, 2>), grid, block, 0, s, a); break;
-            case 3: hipLaunchKernelGGL((k_solve<float, 3>), grid, block, 0, s, a); break;
-            default: return hipErrorInvalidValue;
-        }
+// In k_pcg the adjoint keeps rr in st.rr; its final relative residual is read
+// back by k_adj_grad from the same state.
+
+// ---------------------------------------------------------------------------
+// Launch sequences.
+// ---------------------------------------------------------------------------
+
+#define RW_TRY(...)                           \
+    do {                                      \
+        hipError_t e_ = (__VA_ARGS__);        \
+        if (e_ != hipSuccess) return e_;      \
+    } while (0)
+
+// The box list is ordered so that boxes whose z-plane exceeds the LDS plane
+// march (nx*ny > C*kThreads) come first: [0, n_big) run the global-memory
+// march, [n_big, n) the LDS plane march, each kernel compiled for one path.
+template <typename T, int R, int C, typename XT>
+static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big, XT* xt, int corr, size_t lds,
+                                   hipStream_t s) {
+    if (n_big > 0)
+        hipLaunchKernelGGL((k_pcg<T, R, C, false, XT>), dim3((unsigned)n_big), dim3(kThreads), 0, s, a, xt, corr, 0);
+    if (n > n_big) {
+        auto k = k_pcg<T, R, C, true, XT>;
+        if (lds > 48 * 1024)
+            RW_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k, dim3((unsigned)(n - n_big)), dim3(kThreads), lds, s, a, xt, corr, (int)n_big);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const AdjointArgs& a, int64_t n, double* dl_dbeta, hipStream_t s) {
-    if (n > 0) hipLaunchKernelGGL(k_adjoint, dim3((unsigned)n), dim3(kThreads), 0, s, a);
+template <typename T, int R, typename XT>
+static hipError_t launch_pcg_c(const SolveArgs& a, int64_t n, XT* xt, int corr, const PlanePlan& pp, hipStream_t s) {
+    const size_t lds = pp.use ? (size_t)3 * (R + 1) * pp.cols * kThreads * sizeof(T) : 0;
+    const int64_t n_big = pp.use ? pp.n_big : n;
+    return pp.cols == 2 ? launch_pcg_plane<T, R, 2, XT>(a, n, n_big, xt, corr, lds, s)
+                        : launch_pcg_plane<T, R, 4, XT>(a, n, n_big, xt, corr, lds, s);
+}
+
+template <int R>
+static hipError_t launch_mixed(const SolveArgs& a, int64_t n, const PlanePlan& pp, hipStream_t s) {
+    const dim3 grid((unsigned)n), blk(kThreads);
+    hipLaunchKernelGGL((k_init<float, R>), grid, blk, 0, s, a);
+    RW_TRY(launch_pcg_c<float, R, float>(a, n, a.x, 0, pp, s));
+    const bool r64 = a.precision == RW_PREC_MIXED_REFINE;
+    if (r64) hipLaunchKernelGGL((k_copy64<R>), grid, blk, 0, s, a, 1);
+    for (int step = 0; step < a.refine_max; ++step) {
+        if (r64) hipLaunchKernelGGL((k_check<R, true>), grid, blk, 0, s, a, 1);
+        else hipLaunchKernelGGL((k_check<R, false>), grid, blk, 0, s, a, 1);
+        RW_TRY(launch_pcg_c<float, R, float>(a, n, a.dcorr, 1, pp, s));
+        if (r64) hipLaunchKernelGGL((k_apply<R, true>), grid, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_apply<R, false>), grid, blk, 0, s, a);
+    }
+    if (r64) hipLaunchKernelGGL((k_check<R, true>), grid, blk, 0, s, a, 0);
+    else hipLaunchKernelGGL((k_check<R, false>), grid, blk, 0, s, a, 0);
+    if (r64) hipLaunchKernelGGL((k_copy64<R>), grid, blk, 0, s, a, 0);
+    hipLaunchKernelGGL((k_stats<R>), grid, blk, 0, s, a, (a.want_x64 && !r64) ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <int R>
+static hipError_t launch_fp64(const SolveArgs& a, int64_t n, const PlanePlan& pp, hipStream_t s) {
+    const dim3 grid((unsigned)n), blk(kThreads);
+    hipLaunchKernelGGL((k_init<double, R>), grid, blk, 0, s, a);
+    RW_TRY(launch_pcg_c<double, R, double>(a, n, (double*)a.xt, 0, pp, s));
+    hipLaunchKernelGGL((k_finish64<R>), grid, blk, 0, s, a);
+    hipLaunchKernelGGL((k_stats<R>), grid, blk, 0, s, a, 0);
+    return hipGetLastError();
+}
+
+size_t plane_lds_bytes(int nrhs, bool fp64, int cols) {
+    return (size_t)3 * (nrhs + 1) * cols * kThreads * (fp64 ? 8 : 4);
+}
+
+int plane_cols(int max_plane) { return max_plane <= 2 * kThreads ? 2 : 4; }
+
+int plane_max(int cols) { return cols * kThreads; }
+
+hipError_t launch_solve(const SolveArgs& a, int64_t n, int nrhs, bool fp64, const PlanePlan& pp, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (fp64) {
+        switch (nrhs) {
+            case 1: return launch_fp64<1>(a, n, pp, s);
+            case 2: return launch_fp64<2>(a, n, pp, s);
+            case 3: return launch_fp64<3>(a, n, pp, s);
+        }
+    } else {
+        switch (nrhs) {
+            case 1: return launch_mixed<1>(a, n, pp, s);
+            case 2: return launch_mixed<2>(a, n, pp, s);
+            case 3: return launch_mixed<3>(a, n, pp, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint(const AdjointArgs& a, const SolveArgs& sa, int64_t n, double* dl_dbeta, const PlanePlan& pp,
+                          hipStream_t s) {
+    if (n > 0) {
+        const dim3 grid((unsigned)n), blk(kThreads);
+        hipLaunchKernelGGL(k_adj_init, grid, blk, 0, s, a, sa);
+        RW_TRY(launch_pcg_c<float, 1, float>(sa, n, a.lambda, 0, pp, s));
+        hipLaunchKernelGGL(k_adj_grad, grid, blk, 0, s, a, sa);
+    }
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, s, a.beta_part, n, dl_dbeta);
     return hipGetLastError();
 }
