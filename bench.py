@@ -103,6 +103,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--schedule", type=int, default=0, help="CG schedule: 0 library choice, 1 two-sweep, 2 one-sweep")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (boxes are independent; multi-GPU sharding "
@@ -128,7 +129,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     def run(prec, steps, warmup):
-        p = rwg.solve_params(beta=BETA, eps=EPS, tol=TOL, precision=prec, refine_max=1, inner_tol=1e-4)
+        p = rwg.solve_params(beta=BETA, eps=EPS, tol=TOL, precision=prec, refine_max=1, inner_tol=1e-4,
+                             schedule=args.schedule)
         for _ in range(warmup):
             x.copy_(x0)
             ctx.rw_solve_bricks(p, bricks, g, m, x, stats=st, stream=stream)

@@ -93,6 +93,10 @@ typedef struct rw_solve_params {
     double inner_tol;        /* relative tolerance of each FP32 correction solve */
     double stall_ratio;      /* MIXED: a box counts as stalled, and gets a correction solve, when
                                 its FP64 true relative residual exceeds stall_ratio * tol (>= 1) */
+    int32_t schedule;        /* CG iteration schedule: 0 library choice, 1 two sweeps and two
+                                reductions per iteration (Hestenes-Stiefel), 2 one sweep and one
+                                reduction (Chronopoulos-Gear; weights computed once per iteration) */
+    int32_t reserved;        /* must be 0 */
 } rw_solve_params;
 
 /* Fill *p with the defaults: beta 128, eps 1e-6, tol 1e-6, max_iter 5000,

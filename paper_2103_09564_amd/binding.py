@@ -37,7 +37,7 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32), ("nrhs", ctypes.c_int32),
                 ("refine_max", ctypes.c_int32), ("refine_tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
-                ("stall_ratio", ctypes.c_double)]
+                ("stall_ratio", ctypes.c_double), ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p

@@ -91,6 +91,7 @@ int check_params(rw_ctx* ctx, const rw_solve_params* p) {
     if (!std::isfinite(p->refine_tol) || p->refine_tol < 0) return fail(ctx, RW_E_INVAL, "refine_tol must be >= 0");
     if (!std::isfinite(p->inner_tol) || p->inner_tol < 0) return fail(ctx, RW_E_INVAL, "inner_tol must be >= 0");
     if (!std::isfinite(p->stall_ratio) || p->stall_ratio < 1) return fail(ctx, RW_E_INVAL, "stall_ratio must be >= 1");
+    if (p->schedule < 0 || p->schedule > 2) return fail(ctx, RW_E_INVAL, "schedule must be 0, 1 or 2");
     return RW_OK;
 }
 
@@ -279,6 +280,7 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
     a.precision = p.precision;
     a.refine_max = p.refine_max;
     a.stall_ratio = p.stall_ratio;
+    a.schedule = p.schedule == 0 ? 1 : p.schedule;
     e = rwk::launch_solve(a, n_bricks, R, fp64, pp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching solve kernel");
     return RW_OK;
@@ -347,6 +349,7 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     sa.inner_tol = a.tol;
     sa.max_iter = a.max_iter;
     sa.precision = RW_PREC_MIXED;
+    sa.schedule = params->schedule == 0 ? 1 : params->schedule;
     e = rwk::launch_adjoint(a, sa, n_bricks, dl_dbeta, pp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching adjoint kernels");
     return RW_OK;

@@ -42,6 +42,7 @@ struct SolveArgs {
     BoxState* state;       // [n_bricks], workspace
     double beta, eps, tol, refine_tol, inner_tol, stall_ratio;
     int32_t max_iter, precision, refine_max, want_x64;
+    int32_t schedule;      // 1: two-sweep Jacobi-PCG, 2: single-reduction (Chronopoulos-Gear)
 };
 
 struct AdjointArgs {

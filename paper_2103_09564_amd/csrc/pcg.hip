@@ -87,6 +87,15 @@ struct Val {
 template <typename T>
 struct Val<T, 0> {};
 
+// Workgroup barrier that orders LDS only.  The march loops keep global loads
+// for later chunks in flight across their per-step barriers; __syncthreads()
+// would wait for those (its release fence covers global memory too).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Sum N doubles over the workgroup; every thread receives the same bits.
 template <int N>
 __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
@@ -168,124 +177,165 @@ __device__ __forceinline__ void march(const Box& b, const float* __restrict__ g,
     }
 }
 
-// Plane march with in-plane exchange through LDS (boxes whose z-plane has at
-// most C*kThreads voxels).  Thread t owns the columns t + q*kThreads, q < C,
-// and walks them along z.  Per plane k: the operand (N values, e.g. p) and g
-// of plane k+1 go to one of three rotating LDS plane buffers, one barrier,
-// then every voxel of plane k reads its 4 in-plane neighbours from LDS and its
-// 2 z-neighbours from registers.  Global loads run two planes ahead of the
-// compute (operand, g, mask and NX private extras such as x and r), so each
-// wave keeps several loads in flight while it computes.  Only unknown voxels
-// are visited: visit_u(v, d, acc, self, extras).
-template <typename T, int N, int NX, int C, typename Load, typename LoadX, typename VisitU>
-__device__ __forceinline__ void plane_march(const Box& b, const float* __restrict__ g,
-                                            const uint8_t* __restrict__ m, const Weight<T>& W,
-                                            T* __restrict__ lds, Load load, LoadX loadx, VisitU visit_u) {
-    const int nxy = b.nxy;
-    const int sb = (N + 1) * nxy;
-    int col[C];
-    unsigned fl[C];  // 1 valid, 2 x-, 4 x+, 8 y-, 16 y+
+// Register-ring depth of the window march (3: loads two chunks ahead, 4: three).
+#ifndef RW_WINDOW_RING
+#define RW_WINDOW_RING 3
+#endif
+constexpr int kRing = RW_WINDOW_RING;
+
+// Window march: the box is walked as a flat array in chunks of CH = C*kThreads
+// consecutive voxels (thread t handles voxels t + q*kThreads of each chunk, so
+// every load is coalesced and every thread is busy whatever the box shape).
+// A ring of four LDS chunk buffers holds chunks c-1, c, c+1 while chunk c is
+// computed, so all six stencil neighbours (+-1, +-nx, +-nx*ny; requires
+// nx*ny <= CH) are read from LDS.  Global loads of raw operand values, g, the
+// seed mask and NX private extras (e.g. x and r) run three chunks ahead in a
+// four-deep register ring that is rotated by unrolling, not by copying.
+// prep(raw) turns the raw loads into the N operand values written to LDS.
+// Only unknown voxels are visited: visit_u(v, d, acc, self, extras).
+template <typename T, int RN, int NX>
+struct Slot {
+    Val<T, RN> raw;
+    Val<T, NX> ex;
+    T g;
+    unsigned m;
+};
+
+template <typename T, int N, int RN, int NX, int C, typename LoadRaw, typename Prep, typename LoadX,
+          typename VisitU>
+__device__ __forceinline__ void window_march(const Box& b, const float* __restrict__ g,
+                                             const uint8_t* __restrict__ m, const Weight<T>& W,
+                                             T* __restrict__ lds, LoadRaw loadraw, Prep prep, LoadX loadx,
+                                             VisitU visit_u) {
+    // box-relative 32-bit indices on uniform base pointers (scalar base + vector offset loads)
+    const float* __restrict__ gb = g + b.off;
+    const uint8_t* __restrict__ mb = m + b.off;
+    constexpr int CH = C * kThreads;
+    constexpr int LOG = __builtin_ctz(CH);
+    static_assert((1 << LOG) == CH, "chunk must be a power of two");
+    constexpr int BS = (N + 1) * CH;
+    const int nv = b.nxy * b.nz;
+    const int NC = (nv + CH - 1) / CH;
+    const int dk = CH / b.nxy, rem = CH - dk * b.nxy, dj = rem / b.nx, di = rem - dj * b.nx;
+    int vi[C], ii[C], jj[C], kk[C];
 #pragma unroll
     for (int q = 0; q < C; ++q) {
-        const int c = threadIdx.x + q * kThreads;
-        col[q] = c;
-        fl[q] = 0;
-        if (c < nxy) {
-            const int j = c / b.nx, i = c - j * b.nx;
-            fl[q] = 1u | (i > 0 ? 2u : 0u) | (i + 1 < b.nx ? 4u : 0u) | (j > 0 ? 8u : 0u) |
-                    (j + 1 < b.ny ? 16u : 0u);
-        }
+        const int v = q * kThreads + threadIdx.x;
+        vi[q] = v;
+        kk[q] = v / b.nxy;
+        const int r = v - kk[q] * b.nxy;
+        jj[q] = r / b.nx;
+        ii[q] = r - jj[q] * b.nx;
     }
-    Val<T, N> sm[C], s0[C], su[C], sn[C];
-    Val<T, NX> x0[C], xu[C], xn[C];
-    T g0[C], gu[C], gn[C], wzm[C];
-    unsigned m0[C], mu[C], mn[C];
-    const int64_t off = b.off;
-#pragma unroll
-    for (int q = 0; q < C; ++q) {
-#pragma unroll
-        for (int a = 0; a < N; ++a) sm[q].a[a] = s0[q].a[a] = su[q].a[a] = sn[q].a[a] = T(0);
-        g0[q] = gu[q] = gn[q] = wzm[q] = T(0);
-        m0[q] = mu[q] = mn[q] = 1u;
-        if (fl[q]) {
-            const int64_t v = off + col[q];
-            s0[q] = load(v);
-            g0[q] = (T)g[v];
-            m0[q] = m[v];
-            x0[q] = loadx(v);
-            if (b.nz > 1) {
-                su[q] = load(v + nxy);
-                gu[q] = (T)g[v + nxy];
-                mu[q] = m[v + nxy];
-                xu[q] = loadx(v + nxy);
-            }
-#pragma unroll
-            for (int a = 0; a < N; ++a) lds[a * nxy + col[q]] = s0[q].a[a];
-            lds[N * nxy + col[q]] = g0[q];
-        }
-    }
-    for (int k = 0; k < b.nz; ++k) {
-        const int64_t base = off + (int64_t)k * nxy;
-        const bool h1 = k + 1 < b.nz, h2 = k + 2 < b.nz;
+    using S = Slot<T, RN, NX>;
+    S r0[C], r1[C], r2[C], r3[C];
+    (void)r3;
+    auto load_chunk = [&](int c, S (&Sl)[C]) {
 #pragma unroll
         for (int q = 0; q < C; ++q) {
-#pragma unroll
-            for (int a = 0; a < N; ++a) sn[q].a[a] = T(0);
-            gn[q] = T(0);
-            mn[q] = 1u;
-            if (fl[q] && h2) {
-                const int64_t u = base + 2 * nxy + col[q];
-                sn[q] = load(u);
-                gn[q] = (T)g[u];
-                mn[q] = m[u];
-                xn[q] = loadx(u);
+            const int v = c * CH + q * kThreads + threadIdx.x;
+            if (v < nv) {
+                Sl[q].raw = loadraw(v);
+                Sl[q].ex = loadx(v);
+                Sl[q].g = (T)gb[v];
+                Sl[q].m = mb[v];
             }
         }
-        if (h1) {
-            T* Lw = lds + ((k + 1) % 3) * sb;
+    };
+    auto write_chunk = [&](int c, const S (&Sl)[C]) {
+        T* L = lds + (c & 3) * BS;
 #pragma unroll
-            for (int q = 0; q < C; ++q) {
-                if (fl[q]) {
+        for (int q = 0; q < C; ++q) {
+            const int v = c * CH + q * kThreads + threadIdx.x;
+            if (v < nv) {
+                const Val<T, N> op = prep(Sl[q].raw);
+                const int o = q * kThreads + threadIdx.x;
 #pragma unroll
-                    for (int a = 0; a < N; ++a) Lw[a * nxy + col[q]] = su[q].a[a];
-                    Lw[N * nxy + col[q]] = gu[q];
+                for (int a = 0; a < N; ++a) L[a * CH + o] = op.a[a];
+                L[N * CH + o] = Sl[q].g;
+            }
+        }
+    };
+    auto compute_chunk = [&](const S (&Sl)[C]) {
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int v = vi[q];
+            if (v < nv && Sl[q].m == 0) {
+                const T* self = lds + ((v >> LOG) & 3) * BS + (v & (CH - 1));
+                const T gc = Sl[q].g;
+                T d = T(0);
+                Val<T, N> acc, sv;
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    acc.a[a] = T(0);
+                    sv.a[a] = self[a * CH];
                 }
-            }
-        }
-        __syncthreads();
-        const T* L = lds + (k % 3) * sb;
-#pragma unroll
-        for (int q = 0; q < C; ++q) {
-            if (!fl[q]) continue;
-            const T wzp = h1 ? W(g0[q], gu[q]) : T(0);
-            if (m0[q] == 0) {
-                T d = wzm[q] + wzp;
-                Val<T, N> acc;
-#pragma unroll
-                for (int a = 0; a < N; ++a) acc.a[a] = wzm[q] * sm[q].a[a] + wzp * su[q].a[a];
-                const T gc = g0[q];
-                auto nb = [&](int cc) {
-                    const T w = W(gc, L[N * nxy + cc]);
+                auto nb = [&](int u) {
+                    const T* p = lds + ((u >> LOG) & 3) * BS + (u & (CH - 1));
+                    const T w = W(gc, p[N * CH]);
                     d += w;
 #pragma unroll
-                    for (int a = 0; a < N; ++a) acc.a[a] += w * L[a * nxy + cc];
+                    for (int a = 0; a < N; ++a) acc.a[a] += w * p[a * CH];
                 };
-                if (fl[q] & 2u) nb(col[q] - 1);
-                if (fl[q] & 4u) nb(col[q] + 1);
-                if (fl[q] & 8u) nb(col[q] - b.nx);
-                if (fl[q] & 16u) nb(col[q] + b.nx);
-                visit_u(base + col[q], d, acc, s0[q], x0[q]);
+                if (ii[q] > 0) nb(v - 1);
+                if (ii[q] + 1 < b.nx) nb(v + 1);
+                if (jj[q] > 0) nb(v - b.nx);
+                if (jj[q] + 1 < b.ny) nb(v + b.nx);
+                if (kk[q] > 0) nb(v - b.nxy);
+                if (kk[q] + 1 < b.nz) nb(v + b.nxy);
+                visit_u(v, d, acc, sv, Sl[q].ex);
             }
-            wzm[q] = wzp;
-            sm[q] = s0[q];
-            s0[q] = su[q];
-            su[q] = sn[q];
-            g0[q] = gu[q];
-            gu[q] = gn[q];
-            m0[q] = mu[q];
-            mu[q] = mn[q];
-            x0[q] = xu[q];
-            xu[q] = xn[q];
+            vi[q] = v + CH;
+            ii[q] += di;
+            jj[q] += dj;
+            kk[q] += dk;
+            if (ii[q] >= b.nx) {
+                ii[q] -= b.nx;
+                jj[q] += 1;
+            }
+            if (jj[q] >= b.ny) {
+                jj[q] -= b.ny;
+                kk[q] += 1;
+            }
+        }
+    };
+    if constexpr (kRing == 4) {
+        auto step = [&](int c, S (&s0)[C], S (&s1)[C], S (&s3)[C]) {
+            if (c + 3 < NC) load_chunk(c + 3, s3);
+            if (c + 1 < NC) write_chunk(c + 1, s1);
+            lds_barrier();
+            compute_chunk(s0);
+        };
+        load_chunk(0, r0);
+        if (NC > 1) load_chunk(1, r1);
+        if (NC > 2) load_chunk(2, r2);
+        write_chunk(0, r0);
+        for (int c = 0; c < NC; c += 4) {
+            step(c, r0, r1, r3);
+            if (c + 1 >= NC) break;
+            step(c + 1, r1, r2, r0);
+            if (c + 2 >= NC) break;
+            step(c + 2, r2, r3, r1);
+            if (c + 3 >= NC) break;
+            step(c + 3, r3, r0, r2);
+        }
+    } else {
+        // three-deep register ring: loads run two chunks ahead
+        auto step = [&](int c, S (&s0)[C], S (&s1)[C], S (&s2)[C]) {
+            if (c + 2 < NC) load_chunk(c + 2, s2);
+            if (c + 1 < NC) write_chunk(c + 1, s1);
+            lds_barrier();
+            compute_chunk(s0);
+        };
+        load_chunk(0, r0);
+        if (NC > 1) load_chunk(1, r1);
+        write_chunk(0, r0);
+        for (int c = 0; c < NC; c += 3) {
+            step(c, r0, r1, r2);
+            if (c + 1 >= NC) break;
+            step(c + 1, r1, r2, r0);
+            if (c + 2 >= NC) break;
+            step(c + 2, r2, r0, r1);
         }
     }
     __syncthreads();
@@ -435,16 +485,34 @@ __device__ void sweep_pq(const Box& b, const float* __restrict__ g, const uint8_
         return o;
     };
     if (plane) {
-        auto nox = [&](int64_t) { return Val<T, 0>{}; };
-        auto vp = [&](int64_t v, T d, const Val<T, R>& acc, const Val<T, R>& self, const Val<T, 0>&) {
+        const T* __restrict__ zb = z + b.off * R;
+        const T* __restrict__ pb = pold + b.off * R;
+        T* __restrict__ nb_ = pnew + b.off * R;
+        auto raw = [&](int u) {
+            Val<T, 2 * R> o;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                o.a[k] = zb[u * R + k];
+                o.a[R + k] = pb[u * R + k];
+            }
+            return o;
+        };
+        auto prep = [&](const Val<T, 2 * R>& o) {
+            Val<T, R> p;
+#pragma unroll
+            for (int k = 0; k < R; ++k) p.a[k] = o.a[k] + bk[k] * o.a[R + k];
+            return p;
+        };
+        auto nox = [&](int) { return Val<T, 0>{}; };
+        auto vp = [&](int v, T d, const Val<T, R>& acc, const Val<T, R>& self, const Val<T, 0>&) {
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const T q = d * self.a[k] - acc.a[k];
                 sig[k] += (double)self.a[k] * (double)q;
-                pnew[v * R + k] = self.a[k];
+                nb_[v * R + k] = self.a[k];
             }
         };
-        plane_march<T, R, 0, C>(b, g, m, W, lds, load, nox, vp);
+        window_march<T, R, 2 * R, 0, C>(b, g, m, W, lds, raw, prep, nox, vp);
         return;
     }
     auto vu = [&](int64_t v, T d, const Val<T, R>& acc, const Val<T, R>& self) {
@@ -475,30 +543,41 @@ __device__ void sweep_update(const Box& b, const float* __restrict__ g, const ui
         return o;
     };
     if (plane) {
-        auto lx = [&](int64_t u) {
+        const T* __restrict__ pbb = p + b.off * R;
+        T* __restrict__ rb = V.r + b.off * R;
+        T* __restrict__ zb = V.z + b.off * R;
+        XT* __restrict__ xb = xt + b.off * R;
+        auto ld = [&](int u) {
+            Val<T, R> o;
+#pragma unroll
+            for (int k = 0; k < R; ++k) o.a[k] = pbb[u * R + k];
+            return o;
+        };
+        auto lx = [&](int u) {
             Val<T, 2 * R> o;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                o.a[k] = (T)xt[u * R + k];
-                o.a[R + k] = V.r[u * R + k];
+                o.a[k] = (T)xb[u * R + k];
+                o.a[R + k] = rb[u * R + k];
             }
             return o;
         };
-        auto vp = [&](int64_t v, T d, const Val<T, R>& acc, const Val<T, R>& self, const Val<T, 2 * R>& ex) {
+        auto vp = [&](int v, T d, const Val<T, R>& acc, const Val<T, R>& self, const Val<T, 2 * R>& ex) {
             const T id = recip(d);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const T q = d * self.a[k] - acc.a[k];
-                xt[v * R + k] = (XT)(ex.a[k] + al[k] * self.a[k]);
+                xb[v * R + k] = (XT)(ex.a[k] + al[k] * self.a[k]);
                 const T rv = ex.a[R + k] - al[k] * q;
                 const T zv = rv * id;
-                V.r[v * R + k] = rv;
-                V.z[v * R + k] = zv;
+                rb[v * R + k] = rv;
+                zb[v * R + k] = zv;
                 rz[k] += (double)rv * (double)zv;
                 rr[k] += (double)rv * (double)rv;
             }
         };
-        plane_march<T, R, 2 * R, C>(b, g, m, W, lds, load, lx, vp);
+        auto prep = [&](const Val<T, R>& o) { return o; };
+        window_march<T, R, R, 2 * R, C>(b, g, m, W, lds, ld, prep, lx, vp);
         return;
     }
     auto vu = [&](int64_t v, T d, const Val<T, R>& acc, const Val<T, R>& self) {
@@ -603,6 +682,322 @@ __device__ LoopEnd pcg_loop(const Box& b, const float* __restrict__ g, const uin
 }
 
 // ---------------------------------------------------------------------------
+// Single-reduction CG (Chronopoulos-Gear) for the window path.
+//
+// Mathematically the Jacobi-PCG above, reordered so that one stencil sweep
+// and one workgroup reduction make an iteration: with z = r/d, w = L_UU z and
+// the recurrence s = L_UU p,
+//   beta_i  = gamma_i / gamma_{i-1},  alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})
+//   p = z + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+//   z = r/d,  w = L_UU z,  gamma = r.z,  delta = w.z,  ||r||^2      (one reduction)
+// so the edge weights (and d) are computed once per iteration instead of
+// twice.  Storage: V.r = r, V.z = w, V.p[0] = p, V.p[1] = s.
+// ---------------------------------------------------------------------------
+
+template <typename T, int R>
+struct CgRaw {
+    T x[R], r[R], p[R], s[R], w[R];
+    T g;
+    unsigned m;
+};
+
+template <typename T>
+struct CgCarry {
+    T w[6];
+    T d;
+    unsigned mk;  // bit 0: unknown voxel; bits 1..6: neighbour -x,+x,-y,+y,-z,+z present
+};
+
+// One CG-CG iteration over the box.  Pipeline per step c (chunks of CH
+// voxels, thread t owning voxels t + q*kThreads of each chunk):
+//   (a) global loads of chunk c+4 into a four-deep register ring,
+//   (b) g of chunk c+3 into the LDS g-ring,
+//   (c) stage 1, chunk c+1: the six weights and d (g of chunks c..c+2 from
+//       LDS), the pointwise updates of p, s, x, r and z = r/d; z goes to the
+//       LDS z-ring, weights and d stay in registers,
+//   (d) barrier,
+//   (e) stage 2, chunk c: w = d z - sum_nb w_nb z_nb from the z-ring; delta.
+// Rings of four chunks make every LDS write land in a slot no thread can
+// still be reading (one barrier per step).
+template <typename T, int R, int C, typename XT>
+__device__ void cgcg_sweep(const Box& b, const float* __restrict__ g, const uint8_t* __restrict__ m,
+                           Vecs<T, R> V, XT* __restrict__ xt, const T (&al)[R], const T (&be)[R],
+                           const Weight<T>& W, T* __restrict__ lds, double (&gam)[R], double (&del)[R],
+                           double (&rr)[R]) {
+    constexpr int CH = C * kThreads;
+    constexpr int RING = 4 * CH;
+    constexpr int RM = RING - 1;
+    T* __restrict__ Gr = lds;
+    T* __restrict__ Zr = lds + RING;
+    const int nv = b.nxy * b.nz;
+    const int NC = (nv + CH - 1) / CH;
+    const int nx = b.nx, ny = b.ny, nz = b.nz, nxy = b.nxy;
+    const float* __restrict__ gb = g + b.off;
+    const uint8_t* __restrict__ mb = m + b.off;
+    XT* __restrict__ xb = xt + b.off * R;
+    T* __restrict__ rb = V.r + b.off * R;
+    T* __restrict__ pb = V.p[0] + b.off * R;
+    T* __restrict__ sb = V.p[1] + b.off * R;
+    T* __restrict__ wb = V.z + b.off * R;
+    const int dk = CH / nxy, rem = CH - dk * nxy, dj = rem / nx, di = rem - dj * nx;
+    int ii[C], jj[C], kk[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        const int v = q * kThreads + threadIdx.x;
+        kk[q] = v / nxy;
+        const int r0 = v - kk[q] * nxy;
+        jj[q] = r0 / nx;
+        ii[q] = r0 - jj[q] * nx;
+    }
+    using Raw = CgRaw<T, R>;
+    using Car = CgCarry<T>;
+    Raw q0[C], q1[C], q2[C], q3[C];
+    Car k0[C], k1[C];
+
+    auto load = [&](int c, Raw (&S)[C]) {
+        if (c >= NC) return;
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const unsigned v = (unsigned)(c * CH + q * kThreads) + threadIdx.x;
+            if (v < (unsigned)nv) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    S[q].x[k] = (T)xb[v * R + k];
+                    S[q].r[k] = rb[v * R + k];
+                    S[q].p[k] = pb[v * R + k];
+                    S[q].s[k] = sb[v * R + k];
+                    S[q].w[k] = wb[v * R + k];
+                }
+                S[q].g = (T)gb[v];
+                S[q].m = mb[v];
+            }
+        }
+    };
+    auto write_g = [&](int c, const Raw (&S)[C]) {
+        if (c >= NC) return;
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const unsigned v = (unsigned)(c * CH + q * kThreads) + threadIdx.x;
+            if (v < (unsigned)nv) Gr[v & RM] = S[q].g;
+        }
+    };
+    auto stage1 = [&](int c, const Raw (&S)[C], Car (&K)[C]) {
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const unsigned v = (unsigned)(c * CH + q * kThreads) + threadIdx.x;
+            K[q].mk = 0u;
+            if (c < NC && v < (unsigned)nv) {
+                const int vm = (int)(v & RM);
+                if (S[q].m == 0) {
+                    const T gc = S[q].g;
+                    const bool f0 = ii[q] > 0, f1 = ii[q] + 1 < nx, f2 = jj[q] > 0, f3 = jj[q] + 1 < ny,
+                               f4 = kk[q] > 0, f5 = kk[q] + 1 < nz;
+                    const T w0 = f0 ? W(gc, Gr[(vm - 1) & RM]) : T(0);
+                    const T w1 = f1 ? W(gc, Gr[(vm + 1) & RM]) : T(0);
+                    const T w2 = f2 ? W(gc, Gr[(vm - nx) & RM]) : T(0);
+                    const T w3 = f3 ? W(gc, Gr[(vm + nx) & RM]) : T(0);
+                    const T w4 = f4 ? W(gc, Gr[(vm - nxy) & RM]) : T(0);
+                    const T w5 = f5 ? W(gc, Gr[(vm + nxy) & RM]) : T(0);
+                    const T d = ((w0 + w1) + (w2 + w3)) + (w4 + w5);
+                    const T id = recip(d);
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const T zi = S[q].r[k] * id;
+                        const T pn = zi + be[k] * S[q].p[k];
+                        const T sn = S[q].w[k] + be[k] * S[q].s[k];
+                        const T rn = S[q].r[k] - al[k] * sn;
+                        const T zn = rn * id;
+                        pb[v * R + k] = pn;
+                        sb[v * R + k] = sn;
+                        xb[v * R + k] = (XT)(S[q].x[k] + al[k] * pn);
+                        rb[v * R + k] = rn;
+                        Zr[k * RING + vm] = zn;
+                        gam[k] += (double)rn * (double)zn;
+                        rr[k] += (double)rn * (double)rn;
+                    }
+                    K[q].w[0] = w0;
+                    K[q].w[1] = w1;
+                    K[q].w[2] = w2;
+                    K[q].w[3] = w3;
+                    K[q].w[4] = w4;
+                    K[q].w[5] = w5;
+                    K[q].d = d;
+                    K[q].mk = 1u | (f0 ? 2u : 0u) | (f1 ? 4u : 0u) | (f2 ? 8u : 0u) | (f3 ? 16u : 0u) |
+                              (f4 ? 32u : 0u) | (f5 ? 64u : 0u);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) Zr[k * RING + vm] = T(0);
+                }
+            }
+            ii[q] += di;
+            jj[q] += dj;
+            kk[q] += dk;
+            if (ii[q] >= nx) {
+                ii[q] -= nx;
+                jj[q] += 1;
+            }
+            if (jj[q] >= ny) {
+                jj[q] -= ny;
+                kk[q] += 1;
+            }
+        }
+    };
+    auto stage2 = [&](int c, const Car (&K)[C]) {
+        if (c < 0) return;
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const unsigned mk = K[q].mk;
+            if (mk & 1u) {
+                const unsigned v = (unsigned)(c * CH + q * kThreads) + threadIdx.x;
+                const int vm = (int)(v & RM);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const T* Z = Zr + k * RING;
+                    T acc = T(0);
+                    if (mk & 2u) acc += K[q].w[0] * Z[(vm - 1) & RM];
+                    if (mk & 4u) acc += K[q].w[1] * Z[(vm + 1) & RM];
+                    if (mk & 8u) acc += K[q].w[2] * Z[(vm - nx) & RM];
+                    if (mk & 16u) acc += K[q].w[3] * Z[(vm + nx) & RM];
+                    if (mk & 32u) acc += K[q].w[4] * Z[(vm - nxy) & RM];
+                    if (mk & 64u) acc += K[q].w[5] * Z[(vm + nxy) & RM];
+                    const T zc = Z[vm];
+                    const T wn = K[q].d * zc - acc;
+                    wb[v * R + k] = wn;
+                    del[k] += (double)wn * (double)zc;
+                }
+            }
+        }
+    };
+    // step c: load c+4, g of c+3, stage 1 on c+1, barrier, stage 2 on c
+    auto step = [&](int c, Raw (&S1)[C], Raw (&S3)[C], Raw (&S4)[C], Car (&Kin)[C], Car (&Kout)[C]) {
+        load(c + 4, S4);
+        write_g(c + 3, S3);
+        stage1(c + 1, S1, Kout);
+        lds_barrier();
+        stage2(c, Kin);
+    };
+    load(0, q0);
+    load(1, q1);
+    load(2, q2);
+    write_g(0, q0);
+    write_g(1, q1);
+    lds_barrier();
+    // steps c = -1 .. NC-1; raw ring slot of chunk j is j mod 4, carry slot j mod 2
+    for (int c = -1; c < NC; c += 4) {
+        step(c, q0, q2, q3, k1, k0);
+        if (c + 1 >= NC) break;
+        step(c + 1, q1, q3, q0, k0, k1);
+        if (c + 2 >= NC) break;
+        step(c + 2, q2, q0, q1, k1, k0);
+        if (c + 3 >= NC) break;
+        step(c + 3, q3, q1, q2, k0, k1);
+    }
+    __syncthreads();
+}
+
+// w0 = L_UU z0 in place over z (V.z), delta0 = z.w0.  Every voxel's z is
+// loaded three chunks before its w is written, so the in-place update is safe.
+template <typename T, int R, int C>
+__device__ void cgcg_init_w(const Box& b, const float* __restrict__ g, const uint8_t* __restrict__ m, Vecs<T, R> V,
+                            const Weight<T>& W, T* lds, double (&del)[R]) {
+    T* __restrict__ zb = V.z + b.off * R;
+    auto raw = [&](int u) {
+        Val<T, R> o;
+#pragma unroll
+        for (int k = 0; k < R; ++k) o.a[k] = zb[u * R + k];
+        return o;
+    };
+    auto prep = [&](const Val<T, R>& o) { return o; };
+    auto nox = [&](int) { return Val<T, 0>{}; };
+    auto vp = [&](int v, T d, const Val<T, R>& acc, const Val<T, R>& self, const Val<T, 0>&) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const T w = d * self.a[k] - acc.a[k];
+            del[k] += (double)self.a[k] * (double)w;
+            zb[v * R + k] = w;
+        }
+    };
+    window_march<T, R, R, 0, C>(b, g, m, W, lds, raw, prep, nox, vp);
+}
+
+template <typename T, int R, int C, typename XT>
+__device__ LoopEnd cgcg_loop(const Box& b, const float* __restrict__ g, const uint8_t* __restrict__ m,
+                             Vecs<T, R> V, XT* __restrict__ xt, const Weight<T>& W, double (&gam)[R],
+                             double (&rr)[R], const double (&bb)[R], double tol, int max_iter, double* red,
+                             T* lds) {
+    const double tol2 = tol * tol;
+    int it = 0, flags = 0;
+    bool done[R];
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        done[k] = rr[k] <= tol2 * bb[k];
+        all = all && done[k];
+    }
+    if (all) return LoopEnd{0, 0};
+    if (max_iter <= 0) return LoopEnd{0, 2};
+    double del[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) del[k] = 0.0;
+    cgcg_init_w<T, R, C>(b, g, m, V, W, lds, del);
+    block_sum<R>(del, red);
+    double alpha[R], beta[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        alpha[k] = done[k] ? 0.0 : gam[k] / del[k];
+        beta[k] = 0.0;
+        if (!done[k] && !(del[k] > 0.0 && finite(alpha[k]))) flags = 1;
+    }
+    if (flags) return LoopEnd{0, flags};
+    for (;;) {
+        T al[R], be[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            al[k] = done[k] ? T(0) : (T)alpha[k];
+            be[k] = done[k] ? T(0) : (T)beta[k];
+        }
+        double acc[3 * R], gn[R], dn[R], rn[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) gn[k] = dn[k] = rn[k] = 0.0;
+        cgcg_sweep<T, R, C, XT>(b, g, m, V, xt, al, be, W, lds, gn, dn, rn);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            acc[k] = gn[k];
+            acc[R + k] = dn[k];
+            acc[2 * R + k] = rn[k];
+        }
+        block_sum<3 * R>(acc, red);
+        ++it;
+        bool alld = true;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (done[k]) continue;
+            const double g1 = acc[k], d1 = acc[R + k], r1 = acc[2 * R + k];
+            const double b1 = g1 / gam[k];
+            const double den = d1 - b1 * g1 / alpha[k];
+            rr[k] = r1;
+            gam[k] = g1;
+            if (!finite(r1) || !finite(g1)) flags = 1;
+            done[k] = r1 <= tol2 * bb[k];
+            if (!done[k]) {
+                if (!(den > 0.0)) flags = 1;
+                beta[k] = b1;
+                alpha[k] = g1 / den;
+                if (!finite(alpha[k])) flags = 1;
+            }
+            alld = alld && done[k];
+        }
+        if (flags) break;
+        if (alld) break;
+        if (it >= max_iter) {
+            flags = 2;
+            break;
+        }
+    }
+    return LoopEnd{it, flags};
+}
+
+// ---------------------------------------------------------------------------
 // Kernels.  A solve is a short sequence of launches over the same box list
 // (one workgroup per box, launch order = largest box first); per-box scalars
 // travel between them in BoxState.  Splitting the phases keeps the register
@@ -696,7 +1091,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SolveArgs a) {
 // Phase 2: the PCG loop on every active box.  corr = 0: main solve into xt
 // (x, or the FP64 accumulator on the FP64 path); corr = 1: FP32 correction
 // solve into dcorr from the state init_explicit left (tolerance inner_tol).
-template <typename T, int R, int C, bool kPlane, typename XT>
+template <typename T, int R, int C, bool kPlane, int kSched, typename XT>
 __global__ __launch_bounds__(kThreads) void k_pcg(SolveArgs a, XT* xt, int corr, int base) {
     __shared__ double red[kWaves * 12];
     extern __shared__ __align__(16) unsigned char dyn_lds[];
@@ -714,9 +1109,17 @@ __global__ __launch_bounds__(kThreads) void k_pcg(SolveArgs a, XT* xt, int corr,
         rr[k] = st.rr[k];
         bb[k] = st.bb[k];
     }
-    const LoopEnd e = pcg_loop<T, R, C, kPlane, XT>(b, a.g, a.mask, V, xt, W, rz, rr, bb,
-                                                    corr ? a.inner_tol : a.tol, a.max_iter, red,
-                                                    reinterpret_cast<T*>(dyn_lds));
+    const double tol = corr ? a.inner_tol : a.tol;
+    LoopEnd e;
+    if constexpr (kPlane && kSched == 2)
+        e = cgcg_loop<T, R, C, XT>(b, a.g, a.mask, V, xt, W, rz, rr, bb, tol, a.max_iter, red,
+                                   reinterpret_cast<T*>(dyn_lds));
+    else if constexpr (kPlane)
+        e = pcg_loop<T, R, C, true, XT>(b, a.g, a.mask, V, xt, W, rz, rr, bb, tol, a.max_iter, red,
+                                        reinterpret_cast<T*>(dyn_lds));
+    else
+        e = pcg_loop<T, R, C, false, XT>(b, a.g, a.mask, V, xt, W, rz, rr, bb, tol, a.max_iter, red,
+                                         reinterpret_cast<T*>(dyn_lds));
     if (threadIdx.x == 0) {
         if (corr) {
             st.refine_iters += e.iters;
@@ -995,9 +1398,9 @@ template <typename T, int R, int C, typename XT>
 static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big, XT* xt, int corr, size_t lds,
                                    hipStream_t s) {
     if (n_big > 0)
-        hipLaunchKernelGGL((k_pcg<T, R, C, false, XT>), dim3((unsigned)n_big), dim3(kThreads), 0, s, a, xt, corr, 0);
+        hipLaunchKernelGGL((k_pcg<T, R, C, false, 1, XT>), dim3((unsigned)n_big), dim3(kThreads), 0, s, a, xt, corr, 0);
     if (n > n_big) {
-        auto k = k_pcg<T, R, C, true, XT>;
+        auto k = a.schedule == 2 ? k_pcg<T, R, C, true, 2, XT> : k_pcg<T, R, C, true, 1, XT>;
         if (lds > 48 * 1024)
             RW_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(k, dim3((unsigned)(n - n_big)), dim3(kThreads), lds, s, a, xt, corr, (int)n_big);
@@ -1007,7 +1410,7 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
 
 template <typename T, int R, typename XT>
 static hipError_t launch_pcg_c(const SolveArgs& a, int64_t n, XT* xt, int corr, const PlanePlan& pp, hipStream_t s) {
-    const size_t lds = pp.use ? (size_t)3 * (R + 1) * pp.cols * kThreads * sizeof(T) : 0;
+    const size_t lds = pp.use ? plane_lds_bytes(R, sizeof(T) == 8, pp.cols) : 0;
     const int64_t n_big = pp.use ? pp.n_big : n;
     return pp.cols == 2 ? launch_pcg_plane<T, R, 2, XT>(a, n, n_big, xt, corr, lds, s)
                         : launch_pcg_plane<T, R, 4, XT>(a, n, n_big, xt, corr, lds, s);
@@ -1045,10 +1448,11 @@ static hipError_t launch_fp64(const SolveArgs& a, int64_t n, const PlanePlan& pp
 }
 
 size_t plane_lds_bytes(int nrhs, bool fp64, int cols) {
-    return (size_t)3 * (nrhs + 1) * cols * kThreads * (fp64 ? 8 : 4);
+    return (size_t)4 * (nrhs + 1) * cols * kThreads * (fp64 ? 8 : 4);
 }
 
 int plane_cols(int max_plane) { return max_plane <= 2 * kThreads ? 2 : 4; }
+// LDS of the window march: four chunk buffers of (nrhs operands + g).
 
 int plane_max(int cols) { return cols * kThreads; }
 
