@@ -174,6 +174,119 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
                             float* dl_dg, double* dl_dbeta, float* lambda,
                             rw_brick_stats* stats, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Hierarchical random walker over the LOD pyramid (Sections III-A and IV).
+ * ------------------------------------------------------------------------ */
+
+enum rw_dtype { RW_U16 = 0, RW_F32 = 1 };
+
+typedef struct rw_pyramid rw_pyramid;
+typedef struct rw_result rw_result;
+
+#define RW_MAX_LEVELS 16
+
+/*
+ * Build the LOD pyramid (Section III-A) on the device: level 0 is the volume
+ * normalised to [0,1] (uint16: global min-max; float: clipped), level l+1 is
+ * the 2x2x2 mean of level l (partial blocks at odd edges average the voxels
+ * they have; dims halve rounding up).  `vol` dev [nz][ny][nx] (x fastest);
+ * dims = {nx, ny, nz}; 1 <= levels <= RW_MAX_LEVELS.  The pyramid owns its
+ * device memory.  Work is queued on `stream`; the call returns after it is
+ * queued.  Errors: RW_E_INVAL (dims, dtype, levels), RW_E_NOMEM.
+ */
+int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels,
+                     rw_pyramid** out, void* stream);
+void rw_pyramid_free(rw_pyramid* p);
+/* Level accessor: dims = {nx, ny, nz} of the level, *data = dev float [nz][ny][nx]. */
+int rw_pyramid_level(const rw_pyramid* p, int level, int64_t dims[3], const float** data);
+
+/* A label (Section IV-A): a point in full-resolution voxel units (voxel k
+ * covers [k, k+1)) with a class.  Binary segmentation: label 1 foreground,
+ * 0 background.  K classes: label in [0, K). */
+typedef struct rw_seed {
+    double x, y, z;
+    int32_t label;
+    int32_t reserved;        /* must be 0 */
+} rw_seed;
+
+/* Parameters of the hierarchical run.  Paper defaults: brick 32 (Section
+ * IV-A), expand 1.25 (IV-B), t_hom 0.3, t_bin 0.01 (IV-D1), t_inc 0.01 (IV-E). */
+typedef struct rw_params {
+    double beta, eps;        /* edge weights exp(-beta dg^2) + eps */
+    double tol;              /* per-box PCG relative residual */
+    double expand;           /* e: box side floor(e * brick) */
+    double t_hom, t_bin, t_inc;
+    int32_t brick;           /* s >= 2 */
+    int32_t max_iter;
+    int32_t precision;       /* rw_precision of the box solves */
+    int32_t n_classes;       /* K in [2, 4]; K - 1 right-hand sides are solved */
+    int32_t prune_hom, prune_dt;  /* enable the hom / dt tests (dt only for K = 2) */
+    int32_t refine_max;
+    int32_t reserved;        /* must be 0 */
+} rw_params;
+
+void rw_params_default(rw_params* p);
+
+/* Per-run counters (host struct). */
+typedef struct rw_run_stats {
+    int32_t levels;
+    int32_t reserved;
+    int64_t bricks[RW_MAX_LEVELS];      /* bricks of each level */
+    int64_t computed[RW_MAX_LEVELS];    /* bricks reached (solved or reused) */
+    int64_t solved[RW_MAX_LEVELS];      /* boxes solved in this run */
+    int64_t prunable[RW_MAX_LEVELS];    /* reached bricks whose children were pruned */
+    int64_t voxel_iters[RW_MAX_LEVELS]; /* sum over solved boxes of box voxels x PCG iterations */
+    int64_t box_voxels[RW_MAX_LEVELS];  /* sum of solved box voxels */
+    int32_t max_iters[RW_MAX_LEVELS];
+    int32_t not_converged[RW_MAX_LEVELS];  /* solved boxes with status MAX_ITER / STALLED / NONFINITE */
+} rw_run_stats;
+
+/*
+ * Hierarchical segmentation, eqs. (1)-(3) with pruning (Section IV-D1) and,
+ * when `prev` is given, incremental reuse (Section IV-E):
+ *  - coarsest level: one domain, user seeds only (eq. 1);
+ *  - every finer brick whose parent brick was reached and is not prunable:
+ *    box = brick expanded by floor(e*s) - s voxels (low side half, rounded
+ *    down), clipped to the volume; the outer voxel layer on faces inside the
+ *    volume is seeded with the trilinear sample (cell centres, clamped) of the
+ *    parent level map; user seeds (rasterised to floor(q / 2^level),
+ *    conflicting voxels left unseeded) override; the rest starts from that
+ *    sample (Section IV-D2); the solution's s^3 core is kept;
+ *  - prunable = (hom or dt) and not cfl (a conflict voxel in the box);
+ *  - regions not reached keep the upsampled parent map (ancestor fallback);
+ *  - incremental: a reached brick is solved again only if a new label lands
+ *    in its box, it was not reached in `prev`, or the parent level map moved by
+ *    >= t_inc over the parent voxels its box samples; otherwise its previous
+ *    core values and prunable flag are reused.
+ * `seeds` is a host array.  The run is queued on `stream` but the call
+ * synchronises with it once per level (it reads back brick flags and
+ * solver statistics to plan the next level).  *out owns its device memory.
+ */
+int rw_segment(rw_ctx* ctx, const rw_pyramid* pyr, const rw_seed* seeds, int64_t n_seeds,
+               const rw_params* params, const rw_result* prev, rw_result** out, void* stream);
+void rw_result_free(rw_result* r);
+int rw_result_stats(const rw_result* r, rw_run_stats* out);
+/* Level map: dims = {nx, ny, nz}, nrhs = K - 1, *map = dev float [voxel][nrhs]
+ * (probabilities of classes 1..K-1; class 0 is the complement). */
+int rw_result_level(const rw_result* r, int level, int64_t dims[3], int* nrhs, const float** map);
+/* Brick flags of a level: nb = bricks per axis {x, y, z}, *flags = dev uint8
+ * [nbz][nby][nbx]; bit 0 reached, bit 1 prunable, bit 2 seed conflict in the
+ * box, bit 3 solved in this run. */
+int rw_result_flags(const rw_result* r, int level, int64_t nb[3], const uint8_t** flags);
+/* Copies of the data behind the accessors above into caller device buffers,
+ * queued on `stream`: a level map (float [voxel][K-1]), a level's brick flags
+ * (uint8 [bricks]), a pyramid level (float [voxel]). */
+int rw_result_copy_level(rw_ctx* ctx, const rw_result* r, int level, float* dst, void* stream);
+int rw_result_copy_flags(rw_ctx* ctx, const rw_result* r, int level, uint8_t* dst, void* stream);
+int rw_pyramid_copy_level(rw_ctx* ctx, const rw_pyramid* p, int level, float* dst, void* stream);
+/*
+ * Dense output of a level: prob (dev float [voxels] or NULL) receives the
+ * probability of class `cls` (0 = complement); labels (dev uint8 [voxels] or
+ * NULL) the argmax class, lowest index on ties (Section III-B).
+ */
+int rw_result_materialize(rw_ctx* ctx, const rw_result* r, int level, int cls, float* prob,
+                          uint8_t* labels, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

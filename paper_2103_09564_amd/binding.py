@@ -191,3 +191,193 @@ def solve_bricks_adjoint(g, mask, x, dl_dx, shapes, offsets, lam=None, stream=No
     ctx.rw_solve_bricks_adjoint(solve_params(**params), b, g, mask, x, dl_dx, dl_dg, dl_dbeta, lam=lam,
                                 stats=st, stream=stream)
     return dl_dg, dl_dbeta, st
+
+
+# ---------------------------------------------------------------------------
+# Hierarchical segmentation (pyramid, rw_segment, results)
+# ---------------------------------------------------------------------------
+
+RW_U16, RW_F32 = 0, 1
+MAX_LEVELS = 16
+F_REACHED, F_PRUNABLE, F_CFL, F_SOLVED = 1, 2, 4, 8
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("tol", ctypes.c_double),
+                ("expand", ctypes.c_double), ("t_hom", ctypes.c_double), ("t_bin", ctypes.c_double),
+                ("t_inc", ctypes.c_double), ("brick", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("n_classes", ctypes.c_int32), ("prune_hom", ctypes.c_int32),
+                ("prune_dt", ctypes.c_int32), ("refine_max", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Seed(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_double), ("y", ctypes.c_double), ("z", ctypes.c_double),
+                ("label", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_L = ctypes.c_int64 * MAX_LEVELS
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("reserved", ctypes.c_int32), ("bricks", _L), ("computed", _L),
+                ("solved", _L), ("prunable", _L), ("voxel_iters", _L), ("box_voxels", _L),
+                ("max_iters", ctypes.c_int32 * MAX_LEVELS), ("not_converged", ctypes.c_int32 * MAX_LEVELS)]
+
+    def as_dict(self):
+        n = self.levels
+        return {k: [int(v) for v in getattr(self, k)[:n]] for k, _ in self._fields_[2:]}
+
+
+_dims3 = ctypes.c_int64 * 3
+lib.rw_params_default.argtypes = [ctypes.POINTER(Params)]
+lib.rw_params_default.restype = None
+lib.rw_pyramid_build.argtypes = [_vp, _vp, ctypes.c_int, _dims3, ctypes.c_int, ctypes.POINTER(_vp), _vp]
+lib.rw_pyramid_build.restype = ctypes.c_int
+lib.rw_pyramid_free.argtypes = [_vp]
+lib.rw_pyramid_free.restype = None
+lib.rw_pyramid_level.argtypes = [_vp, ctypes.c_int, _dims3, ctypes.POINTER(_vp)]
+lib.rw_pyramid_level.restype = ctypes.c_int
+lib.rw_segment.argtypes = [_vp, _vp, _vp, _i64, ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp), _vp]
+lib.rw_segment.restype = ctypes.c_int
+lib.rw_result_free.argtypes = [_vp]
+lib.rw_result_free.restype = None
+lib.rw_result_stats.argtypes = [_vp, ctypes.POINTER(RunStats)]
+lib.rw_result_stats.restype = ctypes.c_int
+lib.rw_result_level.argtypes = [_vp, ctypes.c_int, _dims3, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_vp)]
+lib.rw_result_level.restype = ctypes.c_int
+lib.rw_result_flags.argtypes = [_vp, ctypes.c_int, _dims3, ctypes.POINTER(_vp)]
+lib.rw_result_flags.restype = ctypes.c_int
+lib.rw_result_materialize.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+lib.rw_result_materialize.restype = ctypes.c_int
+for _f in ("rw_result_copy_level", "rw_result_copy_flags", "rw_pyramid_copy_level"):
+    getattr(lib, _f).argtypes = [_vp, _vp, ctypes.c_int, _vp, _vp]
+    getattr(lib, _f).restype = ctypes.c_int
+
+
+def params(**kw):
+    """rw_params with the library defaults, overridden by ``kw``."""
+    p = Params()
+    lib.rw_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k!r}")
+        setattr(p, k, v)
+    return p
+
+
+def seeds_array(seeds):
+    """ctypes rw_seed array from an (n, 4) array of (x, y, z, label)."""
+    s = np.asarray(seeds, dtype=np.float64).reshape(-1, 4)
+    arr = (Seed * max(len(s), 1))()
+    for i, (x, y, z, lab) in enumerate(s):
+        arr[i] = Seed(float(x), float(y), float(z), int(lab), 0)
+    return arr, len(s)
+
+
+class Pyramid:
+    def __init__(self, ctx, volume, levels, stream=None):
+        import torch
+        self.ctx = ctx
+        dt = {torch.uint16: RW_U16, torch.float32: RW_F32}.get(volume.dtype)
+        if dt is None:
+            raise TypeError("volume must be uint16 or float32")
+        nz, ny, nx = volume.shape
+        h = _vp()
+        ctx._check(lib.rw_pyramid_build(ctx.handle, _ptr(volume), dt, _dims3(nx, ny, nz), int(levels),
+                                        ctypes.byref(h), _stream(stream)))
+        self.handle = h
+        self.levels = levels
+        self.device = volume.device
+
+    def level(self, l, stream=None):
+        """Copy of pyramid level l as a (nz, ny, nx) float32 device tensor."""
+        import torch
+        d = _dims3()
+        rc = lib.rw_pyramid_level(self.handle, int(l), d, None)
+        if rc != RW_OK:
+            raise RWError(rc, lib.rw_last_error(None).decode())
+        nx, ny, nz = d
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.device)
+        self.ctx._check(lib.rw_pyramid_copy_level(self.ctx.handle, self.handle, int(l), _ptr(out), _stream(stream)))
+        return out
+
+    def close(self):
+        if self.handle:
+            lib.rw_pyramid_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Result:
+    def __init__(self, ctx, handle, device):
+        self.ctx, self.handle, self.device = ctx, handle, device
+
+    def stats(self):
+        st = RunStats()
+        rc = lib.rw_result_stats(self.handle, ctypes.byref(st))
+        if rc != RW_OK:
+            raise RWError(rc, lib.rw_last_error(None).decode())
+        return st.as_dict()
+
+    def level_map(self, l, stream=None):
+        """Copy of level map l as a (nz, ny, nx, K-1) float32 device tensor."""
+        import torch
+        d = _dims3()
+        r = ctypes.c_int()
+        rc = lib.rw_result_level(self.handle, int(l), d, ctypes.byref(r), None)
+        if rc != RW_OK:
+            raise RWError(rc, lib.rw_last_error(None).decode())
+        nx, ny, nz = d
+        out = torch.empty((nz, ny, nx, r.value), dtype=torch.float32, device=self.device)
+        self.ctx._check(lib.rw_result_copy_level(self.ctx.handle, self.handle, int(l), _ptr(out), _stream(stream)))
+        return out
+
+    def flags(self, l, stream=None):
+        """Copy of level l's brick flags as a (nbz, nby, nbx) uint8 device tensor."""
+        import torch
+        d = _dims3()
+        rc = lib.rw_result_flags(self.handle, int(l), d, None)
+        if rc != RW_OK:
+            raise RWError(rc, lib.rw_last_error(None).decode())
+        nx, ny, nz = d
+        out = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.device)
+        self.ctx._check(lib.rw_result_copy_flags(self.ctx.handle, self.handle, int(l), _ptr(out), _stream(stream)))
+        return out
+
+    def materialize(self, level=0, cls=1, prob=True, labels=False, stream=None):
+        import torch
+        d = _dims3()
+        r = ctypes.c_int()
+        lib.rw_result_level(self.handle, int(level), d, ctypes.byref(r), None)
+        nx, ny, nz = d
+        pr = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.device) if prob else None
+        lb = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.device) if labels else None
+        self.ctx._check(lib.rw_result_materialize(self.ctx.handle, self.handle, int(level), int(cls), _ptr(pr),
+                                                  _ptr(lb), _stream(stream)))
+        return pr, lb
+
+    def close(self):
+        if self.handle:
+            lib.rw_result_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def segment(pyramid, seeds, prev=None, stream=None, ctx=None, **kw):
+    """Hierarchical segmentation of a Pyramid with (n, 4) seeds (x, y, z, label)."""
+    ctx = ctx or pyramid.ctx
+    arr, n = seeds_array(seeds)
+    h = _vp()
+    ctx._check(lib.rw_segment(ctx.handle, pyramid.handle, arr, n, ctypes.byref(params(**kw)),
+                              prev.handle if prev is not None else None, ctypes.byref(h), _stream(stream)))
+    return Result(ctx, h, pyramid.device)

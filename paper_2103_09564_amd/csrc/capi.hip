@@ -13,24 +13,13 @@
 #include <string>
 #include <vector>
 
-struct rw_ctx {
-    int device = 0;
-    size_t lds_limit = 0;        // LDS bytes one workgroup may allocate
-    std::string err;
-    void* ws = nullptr;          // vector workspace
-    size_t ws_bytes = 0;
-    void* bricks = nullptr;      // device BrickDev list
-    size_t bricks_bytes = 0;
-    void* aux = nullptr;         // small per-box buffers (adjoint partials)
-    size_t aux_bytes = 0;
-};
-
 namespace {
 
 thread_local std::string g_create_err;
 
-int fail(rw_ctx* ctx, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
-int fail(rw_ctx* ctx, int code, const char* fmt, ...) {
+}  // namespace
+
+int rwk::fail(rw_ctx* ctx, int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -41,13 +30,13 @@ int fail(rw_ctx* ctx, int code, const char* fmt, ...) {
     return code;
 }
 
-int hip_fail(rw_ctx* ctx, hipError_t e, const char* what) {
+int rwk::hip_fail(rw_ctx* ctx, hipError_t e, const char* what) {
     return fail(ctx, e == hipErrorOutOfMemory ? RW_E_NOMEM : RW_E_HIP, "%s: %s", what,
                 hipGetErrorString(e));
 }
 
 // Grow a device buffer to at least `bytes` (contents are not kept).
-hipError_t grow(rw_ctx* ctx, void** buf, size_t* have, size_t bytes, hipStream_t s) {
+hipError_t rwk::grow(rw_ctx* ctx, void** buf, size_t* have, size_t bytes, hipStream_t s) {
     if (*have >= bytes) return hipSuccess;
     if (*buf) {
         hipError_t e = hipStreamSynchronize(s);
@@ -67,16 +56,12 @@ hipError_t grow(rw_ctx* ctx, void** buf, size_t* have, size_t bytes, hipStream_t
     return hipSuccess;
 }
 
-struct DevGuard {
-    int prev = -1;
-    explicit DevGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DevGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
+namespace {
+
+using rwk::DevGuard;
+using rwk::fail;
+using rwk::grow;
+using rwk::hip_fail;
 
 int check_params(rw_ctx* ctx, const rw_solve_params* p) {
     if (!p) return fail(ctx, RW_E_INVAL, "params is NULL");
@@ -205,6 +190,8 @@ void rw_ctx_destroy(rw_ctx* ctx) {
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->bricks) (void)hipFree(ctx->bricks);
     if (ctx->aux) (void)hipFree(ctx->aux);
+    if (ctx->hws) (void)hipFree(ctx->hws);
+    if (ctx->hgeo) (void)hipFree(ctx->hgeo);
     delete ctx;
 }
 

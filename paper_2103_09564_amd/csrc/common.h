@@ -7,7 +7,42 @@
 
 #include "rwseg.h"
 
+// Library context (opaque to callers).
+struct rw_ctx {
+    int device = 0;
+    size_t lds_limit = 0;        // LDS bytes one workgroup may allocate
+    std::string err;
+    void* ws = nullptr;          // solver vector workspace
+    size_t ws_bytes = 0;
+    void* bricks = nullptr;      // device BrickDev list
+    size_t bricks_bytes = 0;
+    void* aux = nullptr;         // per-box state / partials
+    size_t aux_bytes = 0;
+    void* hws = nullptr;         // hierarchy: packed boxes (g, mask, x)
+    size_t hws_bytes = 0;
+    void* hgeo = nullptr;        // hierarchy: box geometry, seed entries, per-box scalars
+    size_t hgeo_bytes = 0;
+};
+
 namespace rwk {
+
+// Error helpers (capi.hip): record the message on ctx (or the thread's
+// create-error slot when ctx is NULL) and return `code`.
+int fail(rw_ctx* ctx, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int hip_fail(rw_ctx* ctx, hipError_t e, const char* what);
+// Grow a device buffer to at least `bytes` (contents are not kept; syncs `s` first).
+hipError_t grow(rw_ctx* ctx, void** buf, size_t* have, size_t bytes, hipStream_t s);
+
+struct DevGuard {
+    int prev = -1;
+    explicit DevGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DevGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
 
 // Device-side box descriptor, in launch order (largest boxes first); `slot`
 // is the caller's brick index (where its stats go).

@@ -1,0 +1,1010 @@
+// Hierarchical random walker over the LOD pyramid (arXiv 2103.09564,
+// Sections III-A and IV): pyramid build, the level loop with border seeds from
+// the parent level, pruning, multi-class and incremental reuse.
+//
+// Device data of a run: one dense map per level, float [voxel][K-1]
+// (classes 1..K-1; class 0 is the complement), and one flag byte per brick.
+// Boxes of a level are packed into a workspace (g, seed mask, x), solved by the
+// batched box solver (rw_solve_bricks), and their cores scattered back into
+// the level map.  The host plans each level from the parent level's brick
+// flags (one small read-back per level) and handles the few labels.
+
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <set>
+#include <tuple>
+#include <vector>
+
+struct rw_pyramid {
+    int device = 0;
+    int levels = 0;
+    int64_t dims[RW_MAX_LEVELS][3] = {};   // x, y, z
+    float* data[RW_MAX_LEVELS] = {};
+};
+
+namespace rwk {
+struct LevelRes {
+    int64_t dims[3] = {0, 0, 0};   // x, y, z
+    int64_t nb[3] = {0, 0, 0};
+    float* map = nullptr;
+    uint8_t* flags = nullptr;
+};
+}  // namespace rwk
+
+struct rw_result {
+    int device = 0;
+    rw_params params{};
+    int levels = 0;
+    int R = 1;
+    rwk::LevelRes lv[RW_MAX_LEVELS];
+    std::vector<rw_seed> seeds;
+    rw_run_stats stats{};
+};
+
+namespace rwk {
+
+constexpr int kHThreads = 256;
+enum : uint8_t { F_REACHED = 1, F_PRUNABLE = 2, F_CFL = 4, F_SOLVED = 8 };
+
+// Geometry of one packed box of a level (level voxel coordinates).
+struct BoxGeo {
+    int32_t x0, y0, z0;        // box origin
+    int32_t nx, ny, nz;        // box dims
+    int32_t cx0, cy0, cz0;     // core origin
+    int32_t cnx, cny, cnz;     // core dims
+    int32_t faces;             // Dirichlet layer from the parent: bit 0 x-lo, 1 x-hi, 2 y-lo, 3 y-hi, 4 z-lo, 5 z-hi
+    int32_t brick;             // brick linear index at the level
+    int64_t off;               // packed offset (voxels)
+};
+
+struct SeedEntry {
+    int64_t v;                 // packed voxel index
+    int32_t label;
+    int32_t pad;
+};
+
+// ---- pyramid ---------------------------------------------------------------
+
+__global__ void k_minmax_u16(const uint16_t* __restrict__ v, int64_t n, unsigned* mm) {
+    unsigned lo = 0xffffu, hi = 0u;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned a = v[i];
+        lo = a < lo ? a : lo;
+        hi = a > hi ? a : hi;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned l2 = __shfl_xor(lo, o, 64), h2 = __shfl_xor(hi, o, 64);
+        lo = l2 < lo ? l2 : lo;
+        hi = h2 > hi ? h2 : hi;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&mm[0], lo);
+        atomicMax(&mm[1], hi);
+    }
+}
+
+__global__ void k_normalize_u16(const uint16_t* __restrict__ v, int64_t n, const unsigned* mm, float* __restrict__ g) {
+    const float lo = (float)mm[0], range = (float)mm[1] - (float)mm[0];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        g[i] = range > 0.0f ? ((float)v[i] - lo) / range : 0.0f;
+}
+
+__global__ void k_clip_f32(const float* __restrict__ v, int64_t n, float* __restrict__ g) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        g[i] = fminf(fmaxf(v[i], 0.0f), 1.0f);
+}
+
+// Parent voxel = mean of the child voxels its 2x2x2 block holds.
+__global__ void k_downsample(const float* __restrict__ c, int64_t cx, int64_t cy, int64_t cz, float* __restrict__ p,
+                             int64_t px, int64_t py, int64_t pz) {
+    const int64_t n = px * py * pz;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x = i % px, y = (i / px) % py, z = i / (px * py);
+        float s = 0.0f;
+        int cnt = 0;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    const int64_t X = 2 * x + dx, Y = 2 * y + dy, Z = 2 * z + dz;
+                    if (X < cx && Y < cy && Z < cz) {
+                        s += c[X + cx * (Y + cy * Z)];
+                        ++cnt;
+                    }
+                }
+        p[i] = s / (float)cnt;
+    }
+}
+
+// ---- level maps ------------------------------------------------------------
+
+// Trilinear taps at cell centres: child index X -> parent coordinate
+// (X + 1/2)/2 - 1/2, clamped to [0, n-1].
+__device__ __forceinline__ void taps(int64_t X, int64_t n, int64_t& i0, int64_t& i1, float& t) {
+    float P = ((float)X + 0.5f) * 0.5f - 0.5f;
+    P = fminf(fmaxf(P, 0.0f), (float)(n - 1));
+    int64_t a = (int64_t)floorf(P);
+    a = a > n - 2 ? n - 2 : a;
+    a = a < 0 ? 0 : a;
+    i0 = a;
+    i1 = a + 1 < n ? a + 1 : n - 1;
+    t = P - (float)a;
+}
+
+template <int R>
+__global__ void k_upsample(const float* __restrict__ pm, int64_t px, int64_t py, int64_t pz, float* __restrict__ cm,
+                           int64_t cx, int64_t cy, int64_t cz) {
+    const int64_t n = cx * cy * cz;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t X = i % cx, Y = (i / cx) % cy, Z = i / (cx * cy);
+        int64_t x0, x1, y0, y1, z0, z1;
+        float tx, ty, tz;
+        taps(X, px, x0, x1, tx);
+        taps(Y, py, y0, y1, ty);
+        taps(Z, pz, z0, z1, tz);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            auto P = [&](int64_t a, int64_t b, int64_t c) { return pm[(a + px * (b + py * c)) * R + k]; };
+            const float c00 = (1.0f - tx) * P(x0, y0, z0) + tx * P(x1, y0, z0);
+            const float c10 = (1.0f - tx) * P(x0, y1, z0) + tx * P(x1, y1, z0);
+            const float c01 = (1.0f - tx) * P(x0, y0, z1) + tx * P(x1, y0, z1);
+            const float c11 = (1.0f - tx) * P(x0, y1, z1) + tx * P(x1, y1, z1);
+            const float c0 = (1.0f - ty) * c00 + ty * c10;
+            const float c1 = (1.0f - ty) * c01 + ty * c11;
+            cm[i * R + k] = (1.0f - tz) * c0 + tz * c1;
+        }
+    }
+}
+
+// Trilinear sample of a parent level map at child voxel (X, Y, Z), class c.
+template <int R>
+__device__ __forceinline__ float sample_parent(const float* __restrict__ pm, int64_t px, int64_t py, int64_t pz,
+                                               int64_t X, int64_t Y, int64_t Z, int c) {
+    int64_t x0, x1, y0, y1, z0, z1;
+    float tx, ty, tz;
+    taps(X, px, x0, x1, tx);
+    taps(Y, py, y0, y1, ty);
+    taps(Z, pz, z0, z1, tz);
+    auto P = [&](int64_t a, int64_t b, int64_t cc) { return pm[(a + px * (b + py * cc)) * R + c]; };
+    const float c00 = (1.0f - tx) * P(x0, y0, z0) + tx * P(x1, y0, z0);
+    const float c10 = (1.0f - tx) * P(x0, y1, z0) + tx * P(x1, y1, z0);
+    const float c01 = (1.0f - tx) * P(x0, y0, z1) + tx * P(x1, y0, z1);
+    const float c11 = (1.0f - tx) * P(x0, y1, z1) + tx * P(x1, y1, z1);
+    const float c0 = (1.0f - ty) * c00 + ty * c10;
+    const float c1 = (1.0f - ty) * c01 + ty * c11;
+    return (1.0f - tz) * c0 + tz * c1;
+}
+
+// One workgroup per box: gather g, set the Dirichlet layer on border faces,
+// x = trilinear sample of the parent level map (border values and warm
+// start), or 0 on the coarsest level (pm == nullptr).  The parent map is read
+// directly, so cores already written into this level's map never leak into
+// another box's border.
+template <int R>
+__global__ void k_setup(const BoxGeo* __restrict__ geo, const float* __restrict__ glev, int64_t Dx, int64_t Dy,
+                        const float* __restrict__ pm, int64_t px, int64_t py, int64_t pz, float* __restrict__ gb,
+                        uint8_t* __restrict__ mb, float* __restrict__ xb) {
+    const BoxGeo b = geo[blockIdx.x];
+    const int64_t n = (int64_t)b.nx * b.ny * b.nz;
+    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
+        const int i = (int)(t % b.nx), j = (int)((t / b.nx) % b.ny), k = (int)(t / ((int64_t)b.nx * b.ny));
+        const int64_t X = b.x0 + i, Y = b.y0 + j, Z = b.z0 + k;
+        const int64_t L = X + Dx * (Y + Dy * Z);
+        const int64_t v = b.off + t;
+        gb[v] = glev[L];
+        const bool border = ((b.faces & 1) && i == 0) || ((b.faces & 2) && i == b.nx - 1) ||
+                            ((b.faces & 4) && j == 0) || ((b.faces & 8) && j == b.ny - 1) ||
+                            ((b.faces & 16) && k == 0) || ((b.faces & 32) && k == b.nz - 1);
+        mb[v] = border ? 1 : 0;
+#pragma unroll
+        for (int c = 0; c < R; ++c) xb[v * R + c] = pm ? sample_parent<R>(pm, px, py, pz, X, Y, Z, c) : 0.0f;
+    }
+}
+
+// User seeds override: x = [label == class] for classes 1..K-1.
+template <int R>
+__global__ void k_seeds(const SeedEntry* __restrict__ e, int64_t n, uint8_t* __restrict__ mb, float* __restrict__ xb) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const SeedEntry s = e[i];
+    mb[s.v] = 1;
+#pragma unroll
+    for (int c = 0; c < R; ++c) xb[s.v * R + c] = s.label == c + 1 ? 1.0f : 0.0f;
+}
+
+// Keep the box solution's core (eq. 3, contraction).
+template <int R>
+__global__ void k_contract(const BoxGeo* __restrict__ geo, const float* __restrict__ xb, int64_t Dx, int64_t Dy,
+                           float* __restrict__ lmap) {
+    const BoxGeo b = geo[blockIdx.x];
+    const int64_t n = (int64_t)b.cnx * b.cny * b.cnz;
+    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
+        const int i = (int)(t % b.cnx), j = (int)((t / b.cnx) % b.cny), k = (int)(t / ((int64_t)b.cnx * b.cny));
+        const int X = b.cx0 + i, Y = b.cy0 + j, Z = b.cz0 + k;
+        const int64_t L = X + Dx * (Y + Dy * (int64_t)Z);
+        const int64_t v = b.off + (X - b.x0) + (int64_t)b.nx * ((Y - b.y0) + (int64_t)b.ny * (Z - b.z0));
+#pragma unroll
+        for (int c = 0; c < R; ++c) lmap[L * R + c] = xb[v * R + c];
+    }
+}
+
+// Reuse a previous result's core (incremental update).
+template <int R>
+__global__ void k_copy_core(const BoxGeo* __restrict__ geo, const float* __restrict__ src, int64_t Dx, int64_t Dy,
+                            float* __restrict__ dst) {
+    const BoxGeo b = geo[blockIdx.x];
+    const int64_t n = (int64_t)b.cnx * b.cny * b.cnz;
+    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
+        const int i = (int)(t % b.cnx), j = (int)((t / b.cnx) % b.cny), k = (int)(t / ((int64_t)b.cnx * b.cny));
+        const int64_t L = (b.cx0 + i) + Dx * ((b.cy0 + j) + Dy * (int64_t)(b.cz0 + k));
+#pragma unroll
+        for (int c = 0; c < R; ++c) dst[L * R + c] = src[L * R + c];
+    }
+}
+
+// Block-wide float min / max.
+__device__ __forceinline__ void block_minmax(float& lo, float& hi, float* red) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, o, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, o, 64));
+    }
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[2 * w] = lo;
+        red[2 * w + 1] = hi;
+    }
+    __syncthreads();
+    lo = red[0];
+    hi = red[1];
+    for (int i = 1; i < nw; ++i) {
+        lo = fminf(lo, red[2 * i]);
+        hi = fmaxf(hi, red[2 * i + 1]);
+    }
+    __syncthreads();
+}
+
+// Pruning tests on a brick core of the level map (Section IV-D1):
+// hom = max - min < t_hom (every class, the complement included, when K > 2),
+// dt = min - 0.5 > t_bin or 0.5 - max > t_bin (K = 2 only);
+// prunable = (hom or dt) and not cfl.  One workgroup per brick.
+template <int R>
+__global__ void k_prune(const BoxGeo* __restrict__ geo, const float* __restrict__ lmap, int64_t Dx, int64_t Dy,
+                        float t_hom, float t_bin, int use_hom, int use_dt, uint8_t* __restrict__ flags) {
+    __shared__ float red[2 * 16];
+    const BoxGeo b = geo[blockIdx.x];
+    const int64_t n = (int64_t)b.cnx * b.cny * b.cnz;
+    float lo[R + 1], hi[R + 1];
+#pragma unroll
+    for (int c = 0; c <= R; ++c) {
+        lo[c] = INFINITY;
+        hi[c] = -INFINITY;
+    }
+    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
+        const int i = (int)(t % b.cnx), j = (int)((t / b.cnx) % b.cny), k = (int)(t / ((int64_t)b.cnx * b.cny));
+        const int64_t L = (b.cx0 + i) + Dx * ((b.cy0 + j) + Dy * (int64_t)(b.cz0 + k));
+        float sum = 0.0f;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const float v = lmap[L * R + c];
+            sum += v;
+            lo[c] = fminf(lo[c], v);
+            hi[c] = fmaxf(hi[c], v);
+        }
+        lo[R] = fminf(lo[R], 1.0f - sum);
+        hi[R] = fmaxf(hi[R], 1.0f - sum);
+    }
+    bool hom = true;
+#pragma unroll
+    for (int c = 0; c <= R; ++c) {
+        block_minmax(lo[c], hi[c], red);
+        if (c < R || R > 1) hom = hom && (hi[c] - lo[c] < t_hom);
+    }
+    const bool dt = R == 1 && ((lo[0] - 0.5f > t_bin) || (0.5f - hi[0] > t_bin));
+    if (threadIdx.x == 0) {
+        uint8_t f = flags[b.brick];
+        const bool prunable = ((use_hom && hom) || (use_dt && dt)) && !(f & F_CFL);
+        flags[b.brick] = prunable ? (uint8_t)(f | F_PRUNABLE) : (uint8_t)(f & ~F_PRUNABLE);
+    }
+}
+
+// Incremental: max |new - old| of the parent level map over the parent voxels
+// a box samples, [(lo-1)/2, hi/2] per axis, clamped.  One workgroup per box.
+template <int R>
+__global__ void k_parent_change(const BoxGeo* __restrict__ geo, const float* __restrict__ pn, const float* __restrict__ po,
+                                int64_t Px, int64_t Py, int64_t Pz, float* __restrict__ out) {
+    __shared__ float red[2 * 16];
+    const BoxGeo b = geo[blockIdx.x];
+    auto lo_of = [](int a) { return a - 1 >= 0 ? (a - 1) / 2 : 0; };
+    const int64_t ax = lo_of(b.x0), ay = lo_of(b.y0), az = lo_of(b.z0);
+    const int64_t bx = std::min<int64_t>((b.x0 + b.nx) / 2, Px - 1), by = std::min<int64_t>((b.y0 + b.ny) / 2, Py - 1),
+                  bz = std::min<int64_t>((b.z0 + b.nz) / 2, Pz - 1);
+    const int64_t sx = bx - ax + 1, sy = by - ay + 1, sz = bz - az + 1;
+    float m = 0.0f, dummy = 0.0f;
+    for (int64_t t = threadIdx.x; t < sx * sy * sz; t += blockDim.x) {
+        const int64_t X = ax + t % sx, Y = ay + (t / sx) % sy, Z = az + t / (sx * sy);
+        const int64_t L = X + Px * (Y + Py * Z);
+#pragma unroll
+        for (int c = 0; c < R; ++c) m = fmaxf(m, fabsf(pn[L * R + c] - po[L * R + c]));
+    }
+    float lo = -m;
+    block_minmax(lo, dummy, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = -lo;
+}
+
+template <int R>
+__global__ void k_materialize(const float* __restrict__ lmap, int64_t n, int cls, float* __restrict__ prob,
+                              uint8_t* __restrict__ labels) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float v[R + 1];
+        float sum = 0.0f;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            v[c + 1] = lmap[i * R + c];
+            sum += v[c + 1];
+        }
+        v[0] = 1.0f - sum;
+        if (prob) prob[i] = v[cls];
+        if (labels) {
+            int best = 0;
+#pragma unroll
+            for (int c = 1; c <= R; ++c)
+                if (v[c] > v[best]) best = c;
+            labels[i] = (uint8_t)best;
+        }
+    }
+}
+
+static unsigned grid_for(int64_t n, int threads) {
+    const int64_t g = (n + threads - 1) / threads;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+// ---- host planning ------------------------------------------------------------
+
+struct LevelGeo {
+    int64_t D[3];    // x, y, z
+    int64_t nb[3];
+};
+
+// Brick b (bx, by, bz) -> box geometry (core and expanded box, clipped).
+static BoxGeo brick_box(const LevelGeo& L, int s, double e, int64_t bx, int64_t by, int64_t bz) {
+    const int se = (int)std::floor(e * s);
+    const int lo_pad = (se - s) / 2, hi_pad = se - s - lo_pad;
+    BoxGeo g{};
+    const int64_t bi[3] = {bx, by, bz};
+    int32_t c0[3], c1[3], b0[3], b1[3];
+    for (int a = 0; a < 3; ++a) {
+        c0[a] = (int32_t)(bi[a] * s);
+        c1[a] = (int32_t)std::min<int64_t>((bi[a] + 1) * s, L.D[a]);
+        b0[a] = std::max(c0[a] - lo_pad, 0);
+        b1[a] = (int32_t)std::min<int64_t>(c1[a] + hi_pad, L.D[a]);
+    }
+    g.x0 = b0[0]; g.y0 = b0[1]; g.z0 = b0[2];
+    g.nx = b1[0] - b0[0]; g.ny = b1[1] - b0[1]; g.nz = b1[2] - b0[2];
+    g.cx0 = c0[0]; g.cy0 = c0[1]; g.cz0 = c0[2];
+    g.cnx = c1[0] - c0[0]; g.cny = c1[1] - c0[1]; g.cnz = c1[2] - c0[2];
+    g.faces = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (b0[a] > 0) g.faces |= 1 << (2 * a);
+        if (b1[a] < L.D[a]) g.faces |= 2 << (2 * a);
+    }
+    g.brick = (int32_t)(bx + L.nb[0] * (by + L.nb[1] * bz));
+    return g;
+}
+
+static bool in_box(const BoxGeo& g, int64_t X, int64_t Y, int64_t Z) {
+    return X >= g.x0 && X < g.x0 + g.nx && Y >= g.y0 && Y < g.y0 + g.ny && Z >= g.z0 && Z < g.z0 + g.nz;
+}
+
+// Level-l label grid, sparse: voxel linear index -> class, or -2 (conflict).
+static std::map<int64_t, int> rasterize(const std::vector<rw_seed>& seeds, int level, const LevelGeo& L) {
+    std::map<int64_t, int> lab;
+    const double f = std::ldexp(1.0, level);
+    for (const rw_seed& s : seeds) {
+        const int64_t X = (int64_t)std::floor(s.x / f), Y = (int64_t)std::floor(s.y / f),
+                      Z = (int64_t)std::floor(s.z / f);
+        if (X < 0 || Y < 0 || Z < 0 || X >= L.D[0] || Y >= L.D[1] || Z >= L.D[2]) continue;
+        const int64_t v = X + L.D[0] * (Y + L.D[1] * Z);
+        auto it = lab.find(v);
+        if (it == lab.end()) lab[v] = s.label;
+        else if (it->second >= 0 && it->second != s.label) it->second = -2;
+    }
+    return lab;
+}
+
+// Bricks whose (expanded, clipped) box contains voxel (X, Y, Z).
+template <typename F>
+static void bricks_containing(const LevelGeo& L, int s, double e, int64_t X, int64_t Y, int64_t Z, F f) {
+    const int se = (int)std::floor(e * s);
+    const int pad = std::max((se - s) / 2, se - s - (se - s) / 2);
+    const int64_t P[3] = {X, Y, Z};
+    int64_t lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = std::max<int64_t>(0, (P[a] - pad) / s - 1);
+        hi[a] = std::min<int64_t>(L.nb[a] - 1, (P[a] + pad) / s + 1);
+    }
+    for (int64_t bz = lo[2]; bz <= hi[2]; ++bz)
+        for (int64_t by = lo[1]; by <= hi[1]; ++by)
+            for (int64_t bx = lo[0]; bx <= hi[0]; ++bx) {
+                const BoxGeo g = brick_box(L, s, e, bx, by, bz);
+                if (in_box(g, X, Y, Z)) f(g.brick);
+            }
+}
+
+struct Planner {
+    rw_ctx* ctx;
+    hipStream_t s;
+    int R;
+    const rw_params* p;
+
+    int ensure(void** buf, size_t* have, size_t bytes) {
+        hipError_t e = grow(ctx, buf, have, std::max<size_t>(bytes, 256), s);
+        return e == hipSuccess ? RW_OK : hip_fail(ctx, e, "allocating hierarchy workspace");
+    }
+};
+
+template <typename T>
+static int upload(rw_ctx* ctx, void* dst, const std::vector<T>& v, hipStream_t s) {
+    if (v.empty()) return RW_OK;
+    hipError_t e = hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    return e == hipSuccess ? RW_OK : hip_fail(ctx, e, "uploading hierarchy plan");
+}
+
+#define H_TRY(x)                     \
+    do {                             \
+        int rc_ = (x);               \
+        if (rc_ != RW_OK) return rc_; \
+    } while (0)
+#define H_HIP(x, what)                                   \
+    do {                                                 \
+        hipError_t e_ = (x);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+template <int R>
+static void launch_setup(const BoxGeo* geo, int64_t n, const float* glev, int64_t Dx, int64_t Dy, const float* pm,
+                         const int64_t* PD, float* gb, uint8_t* mb, float* xb, hipStream_t s) {
+    hipLaunchKernelGGL(k_setup<R>, dim3((unsigned)n), dim3(kHThreads), 0, s, geo, glev, Dx, Dy, pm, PD ? PD[0] : 0,
+                       PD ? PD[1] : 0, PD ? PD[2] : 0, gb, mb, xb);
+}
+
+// Solve the listed boxes of a level and scatter their cores into lmap.
+// `geos` are the boxes (host); `entries` the seed overrides per packed voxel.
+template <int R>
+static int solve_boxes(rw_ctx* ctx, hipStream_t s, const rw_params& P, const LevelGeo& L, const float* glev,
+                       float* lmap, const float* pmap, const int64_t* PD, std::vector<BoxGeo>& geos,
+                       const std::map<int64_t, int>& lab, rw_run_stats* st, int level) {
+    const int top = pmap == nullptr;
+    const int64_t maxv_batch = (int64_t)1 << 28;   // voxels per batch
+    size_t i0 = 0;
+    while (i0 < geos.size()) {
+        // batch [i0, i1)
+        int64_t nv = 0;
+        size_t i1 = i0;
+        while (i1 < geos.size()) {
+            const int64_t v = (int64_t)geos[i1].nx * geos[i1].ny * geos[i1].nz;
+            if (i1 > i0 && nv + v > maxv_batch) break;
+            geos[i1].off = nv;
+            nv += v;
+            ++i1;
+        }
+        const int64_t nb = (int64_t)(i1 - i0);
+        // seed entries of this batch
+        std::vector<SeedEntry> ent;
+        std::map<int32_t, size_t> brick_to_box;
+        for (size_t i = i0; i < i1; ++i) brick_to_box[geos[i].brick] = i;
+        for (const auto& kv : lab) {
+            if (kv.second < 0) continue;
+            const int64_t v = kv.first;
+            const int64_t X = v % L.D[0], Y = (v / L.D[0]) % L.D[1], Z = v / (L.D[0] * L.D[1]);
+            auto add = [&](int32_t brick) {
+                auto it = brick_to_box.find(brick);
+                if (it == brick_to_box.end()) return;
+                const BoxGeo& g = geos[it->second];
+                const int64_t pv = g.off + (X - g.x0) + (int64_t)g.nx * ((Y - g.y0) + (int64_t)g.ny * (Z - g.z0));
+                ent.push_back(SeedEntry{pv, kv.second, 0});
+            };
+            if (top) add(geos[i0].brick);
+            else bricks_containing(L, P.brick, P.expand, X, Y, Z, add);
+        }
+        // workspace: g f32, x f32 * R, mask u8 | geo, seed entries, stats
+        const size_t bx = ((size_t)nv * R * 4 + 255) & ~size_t(255);
+        const size_t bg = ((size_t)nv * 4 + 255) & ~size_t(255);
+        const size_t bm = ((size_t)nv + 255) & ~size_t(255);
+        H_HIP(grow(ctx, &ctx->hws, &ctx->hws_bytes, bx + bg + bm, s), "allocating packed boxes");
+        char* w = (char*)ctx->hws;
+        float* xb = (float*)w;
+        float* gb = (float*)(w + bx);
+        uint8_t* mb = (uint8_t*)(w + bx + bg);
+        const size_t gg = ((size_t)nb * sizeof(BoxGeo) + 255) & ~size_t(255);
+        const size_t ge = ((ent.size() + 1) * sizeof(SeedEntry) + 255) & ~size_t(255);
+        const size_t gs = (size_t)nb * sizeof(rw_brick_stats);
+        H_HIP(grow(ctx, &ctx->hgeo, &ctx->hgeo_bytes, gg + ge + gs, s), "allocating box geometry");
+        BoxGeo* dgeo = (BoxGeo*)ctx->hgeo;
+        SeedEntry* dent = (SeedEntry*)((char*)ctx->hgeo + gg);
+        rw_brick_stats* dst = (rw_brick_stats*)((char*)ctx->hgeo + gg + ge);
+        std::vector<BoxGeo> part(geos.begin() + i0, geos.begin() + i1);
+        H_TRY(upload(ctx, dgeo, part, s));
+        H_TRY(upload(ctx, dent, ent, s));
+        launch_setup<R>(dgeo, nb, glev, L.D[0], L.D[1], pmap, PD, gb, mb, xb, s);
+        if (!ent.empty())
+            hipLaunchKernelGGL(k_seeds<R>, dim3(grid_for((int64_t)ent.size(), kHThreads)), dim3(kHThreads), 0, s, dent,
+                               (int64_t)ent.size(), mb, xb);
+        H_HIP(hipGetLastError(), "launching box setup");
+        // batched box solve
+        std::vector<rw_brick> br((size_t)nb);
+        for (int64_t i = 0; i < nb; ++i)
+            br[(size_t)i] = rw_brick{part[(size_t)i].nx, part[(size_t)i].ny, part[(size_t)i].nz, 0, part[(size_t)i].off};
+        rw_solve_params sp;
+        rw_solve_params_default(&sp);
+        sp.beta = P.beta;
+        sp.eps = P.eps;
+        sp.tol = P.tol;
+        sp.max_iter = P.max_iter;
+        sp.precision = P.precision;
+        sp.nrhs = R;
+        sp.refine_max = P.refine_max;
+        H_TRY(rw_solve_bricks(ctx, &sp, nb, br.data(), nv, gb, mb, xb, nullptr, dst, s));
+        hipLaunchKernelGGL(k_contract<R>, dim3((unsigned)nb), dim3(kHThreads), 0, s, dgeo, xb, L.D[0], L.D[1], lmap);
+        H_HIP(hipGetLastError(), "launching contraction");
+        // stats (the workspaces are reused by the next batch: sync)
+        std::vector<rw_brick_stats> hs((size_t)nb);
+        H_HIP(hipMemcpyAsync(hs.data(), dst, (size_t)nb * sizeof(rw_brick_stats), hipMemcpyDeviceToHost, s),
+              "reading solver stats");
+        H_HIP(hipStreamSynchronize(s), "synchronising level");
+        for (int64_t i = 0; i < nb; ++i) {
+            const rw_brick_stats& q = hs[(size_t)i];
+            const int64_t v = (int64_t)part[(size_t)i].nx * part[(size_t)i].ny * part[(size_t)i].nz;
+            st->voxel_iters[level] += v * (int64_t)(q.iters + q.refine_iters);
+            st->box_voxels[level] += v;
+            st->max_iters[level] = std::max(st->max_iters[level], q.iters);
+            if (q.status == RW_ST_MAX_ITER || q.status == RW_ST_STALLED || q.status == RW_ST_NONFINITE)
+                st->not_converged[level] += 1;
+        }
+        st->solved[level] += nb;
+        i0 = i1;
+    }
+    return RW_OK;
+}
+
+template <int R>
+static int run_prune(rw_ctx* ctx, hipStream_t s, const rw_params& P, const LevelGeo& L, const float* lmap,
+                     const std::vector<BoxGeo>& geos, uint8_t* dflags) {
+    if (geos.empty()) return RW_OK;
+    const size_t gg = geos.size() * sizeof(BoxGeo);
+    H_HIP(grow(ctx, &ctx->hgeo, &ctx->hgeo_bytes, gg, s), "allocating box geometry");
+    H_TRY(upload(ctx, ctx->hgeo, geos, s));
+    hipLaunchKernelGGL(k_prune<R>, dim3((unsigned)geos.size()), dim3(kHThreads), 0, s, (const BoxGeo*)ctx->hgeo, lmap,
+                       L.D[0], L.D[1], (float)P.t_hom, (float)P.t_bin, P.prune_hom, P.prune_dt, dflags);
+    H_HIP(hipGetLastError(), "launching prune test");
+    H_HIP(hipStreamSynchronize(s), "synchronising prune");
+    return RW_OK;
+}
+
+template <int R>
+static int segment_impl(rw_ctx* ctx, const rw_pyramid* pyr, const std::vector<rw_seed>& seeds, const rw_params& P,
+                        const rw_result* prev, rw_result* res, hipStream_t s) {
+    const int Lv = pyr->levels, top = Lv - 1;
+    rw_run_stats& st = res->stats;
+    st.levels = Lv;
+    std::vector<rw_seed> newseeds;
+    if (prev) {
+        auto key = [](const rw_seed& a) { return std::make_tuple(a.x, a.y, a.z, a.label); };
+        std::set<std::tuple<double, double, double, int>> old;
+        for (const rw_seed& q : prev->seeds) old.insert(key(q));
+        for (const rw_seed& q : seeds)
+            if (!old.count(key(q))) newseeds.push_back(q);
+    }
+    std::vector<LevelGeo> LG((size_t)Lv);
+    for (int l = 0; l < Lv; ++l) {
+        for (int a = 0; a < 3; ++a) {
+            LG[(size_t)l].D[a] = pyr->dims[l][a];
+            LG[(size_t)l].nb[a] = (pyr->dims[l][a] + P.brick - 1) / P.brick;
+        }
+        rwk::LevelRes& lr = res->lv[l];
+        for (int a = 0; a < 3; ++a) {
+            lr.dims[a] = LG[(size_t)l].D[a];
+            lr.nb[a] = LG[(size_t)l].nb[a];
+        }
+        const int64_t nvox = lr.dims[0] * lr.dims[1] * lr.dims[2];
+        const int64_t nbr = lr.nb[0] * lr.nb[1] * lr.nb[2];
+        st.bricks[l] = nbr;
+        H_HIP(hipMalloc((void**)&lr.map, (size_t)nvox * R * sizeof(float)), "allocating level map");
+        H_HIP(hipMalloc((void**)&lr.flags, (size_t)nbr), "allocating brick flags");
+        H_HIP(hipMemsetAsync(lr.flags, 0, (size_t)nbr, s), "clearing brick flags");
+    }
+    auto all_bricks = [&](int l) {
+        std::vector<BoxGeo> v;
+        const LevelGeo& L = LG[(size_t)l];
+        for (int64_t bz = 0; bz < L.nb[2]; ++bz)
+            for (int64_t by = 0; by < L.nb[1]; ++by)
+                for (int64_t bx = 0; bx < L.nb[0]; ++bx) v.push_back(brick_box(L, P.brick, P.expand, bx, by, bz));
+        return v;
+    };
+    auto cfl_bricks = [&](int l, const std::map<int64_t, int>& lab, std::vector<uint8_t>& hflags) {
+        const LevelGeo& L = LG[(size_t)l];
+        for (const auto& kv : lab) {
+            if (kv.second != -2) continue;
+            const int64_t v = kv.first;
+            const int64_t X = v % L.D[0], Y = (v / L.D[0]) % L.D[1], Z = v / (L.D[0] * L.D[1]);
+            bricks_containing(L, P.brick, P.expand, X, Y, Z, [&](int32_t b) { hflags[(size_t)b] |= F_CFL; });
+        }
+    };
+
+    // ---- coarsest level: one domain, user seeds only (eq. 1)
+    {
+        const LevelGeo& L = LG[(size_t)top];
+        rwk::LevelRes& lr = res->lv[top];
+        const int64_t nbr = L.nb[0] * L.nb[1] * L.nb[2];
+        auto lab = rasterize(seeds, top, L);
+        std::vector<uint8_t> hflags((size_t)nbr, F_REACHED);
+        cfl_bricks(top, lab, hflags);
+        const bool reuse = prev && newseeds.empty();
+        if (reuse) {
+            H_HIP(hipMemcpyAsync(lr.map, prev->lv[top].map, (size_t)(L.D[0] * L.D[1] * L.D[2]) * R * sizeof(float),
+                                 hipMemcpyDeviceToDevice, s),
+                  "copying previous coarsest level");
+        } else {
+            for (auto& f : hflags) f |= F_SOLVED;
+            BoxGeo g{};
+            g.nx = (int32_t)L.D[0];
+            g.ny = (int32_t)L.D[1];
+            g.nz = (int32_t)L.D[2];
+            g.cnx = g.nx;
+            g.cny = g.ny;
+            g.cnz = g.nz;
+            g.brick = 0;
+            std::vector<BoxGeo> one{g};
+            H_TRY(solve_boxes<R>(ctx, s, P, L, pyr->data[top], lr.map, nullptr, nullptr, one, lab, &st, top));
+        }
+        H_HIP(hipMemcpyAsync(lr.flags, hflags.data(), (size_t)nbr, hipMemcpyHostToDevice, s), "uploading flags");
+        H_TRY(run_prune<R>(ctx, s, P, L, lr.map, all_bricks(top), lr.flags));
+        st.computed[top] = nbr;
+    }
+
+    // ---- finer levels (eqs. 2-3)
+    for (int l = top - 1; l >= 0; --l) {
+        const LevelGeo& L = LG[(size_t)l];
+        const LevelGeo& PL = LG[(size_t)l + 1];
+        rwk::LevelRes& lr = res->lv[l];
+        const rwk::LevelRes& pr = res->lv[l + 1];
+        const int64_t nvox = L.D[0] * L.D[1] * L.D[2];
+        const int64_t nbr = L.nb[0] * L.nb[1] * L.nb[2];
+        hipLaunchKernelGGL(k_upsample<R>, dim3(grid_for(nvox, kHThreads)), dim3(kHThreads), 0, s, pr.map, PL.D[0],
+                           PL.D[1], PL.D[2], lr.map, L.D[0], L.D[1], L.D[2]);
+        H_HIP(hipGetLastError(), "launching upsample");
+        std::vector<uint8_t> pflags((size_t)(PL.nb[0] * PL.nb[1] * PL.nb[2]));
+        H_HIP(hipMemcpyAsync(pflags.data(), pr.flags, pflags.size(), hipMemcpyDeviceToHost, s), "reading parent flags");
+        std::vector<uint8_t> prevflags;
+        if (prev) {
+            prevflags.resize((size_t)nbr);
+            H_HIP(hipMemcpyAsync(prevflags.data(), prev->lv[l].flags, (size_t)nbr, hipMemcpyDeviceToHost, s),
+                  "reading previous flags");
+        }
+        H_HIP(hipStreamSynchronize(s), "synchronising level");
+        auto lab = rasterize(seeds, l, L);
+        std::vector<uint8_t> hflags((size_t)nbr, 0);
+        cfl_bricks(l, lab, hflags);
+        std::vector<BoxGeo> reached;
+        for (int64_t bz = 0; bz < L.nb[2]; ++bz)
+            for (int64_t by = 0; by < L.nb[1]; ++by)
+                for (int64_t bx = 0; bx < L.nb[0]; ++bx) {
+                    const int64_t pb = bx / 2 + PL.nb[0] * (by / 2 + PL.nb[1] * (bz / 2));
+                    const uint8_t f = pflags[(size_t)pb];
+                    if ((f & F_REACHED) && !(f & F_PRUNABLE)) reached.push_back(brick_box(L, P.brick, P.expand, bx, by, bz));
+                }
+        std::vector<BoxGeo> solve, reuse;
+        if (!prev) {
+            solve = reached;
+        } else {
+            std::vector<uint8_t> newin((size_t)nbr, 0);
+            auto nl = rasterize(newseeds, l, L);
+            for (const auto& kv : nl) {
+                const int64_t v = kv.first;
+                const int64_t X = v % L.D[0], Y = (v / L.D[0]) % L.D[1], Z = v / (L.D[0] * L.D[1]);
+                bricks_containing(L, P.brick, P.expand, X, Y, Z, [&](int32_t b) { newin[(size_t)b] = 1; });
+            }
+            std::vector<BoxGeo> cand;
+            for (const BoxGeo& g : reached) {
+                if ((prevflags[(size_t)g.brick] & F_REACHED) && !newin[(size_t)g.brick]) cand.push_back(g);
+                else solve.push_back(g);
+            }
+            if (!cand.empty()) {
+                const size_t gg = (cand.size() * sizeof(BoxGeo) + 255) & ~size_t(255);
+                H_HIP(grow(ctx, &ctx->hgeo, &ctx->hgeo_bytes, gg + cand.size() * sizeof(float), s),
+                      "allocating box geometry");
+                H_TRY(upload(ctx, ctx->hgeo, cand, s));
+                float* dch = (float*)((char*)ctx->hgeo + gg);
+                hipLaunchKernelGGL(k_parent_change<R>, dim3((unsigned)cand.size()), dim3(kHThreads), 0, s,
+                                   (const BoxGeo*)ctx->hgeo, pr.map, prev->lv[l + 1].map, PL.D[0], PL.D[1], PL.D[2], dch);
+                H_HIP(hipGetLastError(), "launching change test");
+                std::vector<float> ch(cand.size());
+                H_HIP(hipMemcpyAsync(ch.data(), dch, ch.size() * sizeof(float), hipMemcpyDeviceToHost, s),
+                      "reading change test");
+                H_HIP(hipStreamSynchronize(s), "synchronising change test");
+                for (size_t i = 0; i < cand.size(); ++i) {
+                    if ((double)ch[i] >= P.t_inc) solve.push_back(cand[i]);
+                    else reuse.push_back(cand[i]);
+                }
+            }
+        }
+        for (const BoxGeo& g : reached) hflags[(size_t)g.brick] |= F_REACHED;
+        for (const BoxGeo& g : solve) hflags[(size_t)g.brick] |= F_SOLVED;
+        for (const BoxGeo& g : reuse) hflags[(size_t)g.brick] |= (uint8_t)(prevflags[(size_t)g.brick] & F_PRUNABLE);
+        H_HIP(hipMemcpyAsync(lr.flags, hflags.data(), (size_t)nbr, hipMemcpyHostToDevice, s), "uploading flags");
+        H_HIP(hipStreamSynchronize(s), "synchronising flags");   // hflags is host memory of this scope
+        if (!reuse.empty()) {
+            H_HIP(grow(ctx, &ctx->hgeo, &ctx->hgeo_bytes, reuse.size() * sizeof(BoxGeo), s), "allocating box geometry");
+            H_TRY(upload(ctx, ctx->hgeo, reuse, s));
+            hipLaunchKernelGGL(k_copy_core<R>, dim3((unsigned)reuse.size()), dim3(kHThreads), 0, s,
+                               (const BoxGeo*)ctx->hgeo, prev->lv[l].map, L.D[0], L.D[1], lr.map);
+            H_HIP(hipGetLastError(), "launching reuse copy");
+            H_HIP(hipStreamSynchronize(s), "synchronising reuse copy");
+        }
+        if (!solve.empty()) {
+            // largest boxes first is done by the solver; keep brick order here
+            H_TRY(solve_boxes<R>(ctx, s, P, L, pyr->data[l], lr.map, pr.map, PL.D, solve, lab, &st, l));
+            H_TRY(run_prune<R>(ctx, s, P, L, lr.map, solve, lr.flags));
+        }
+        st.computed[l] = (int64_t)reached.size();
+    }
+    // prunable counts
+    for (int l = 0; l < Lv; ++l) {
+        std::vector<uint8_t> f((size_t)(res->lv[l].nb[0] * res->lv[l].nb[1] * res->lv[l].nb[2]));
+        H_HIP(hipMemcpyAsync(f.data(), res->lv[l].flags, f.size(), hipMemcpyDeviceToHost, s), "reading flags");
+        H_HIP(hipStreamSynchronize(s), "synchronising");
+        for (uint8_t v : f) st.prunable[l] += (v & F_REACHED) && (v & F_PRUNABLE) ? 1 : 0;
+    }
+    return RW_OK;
+}
+
+}  // namespace rwk
+
+using namespace rwk;
+
+static void free_result_mem(rw_result* r) {
+    for (int l = 0; l < RW_MAX_LEVELS; ++l) {
+        if (r->lv[l].map) (void)hipFree(r->lv[l].map);
+        if (r->lv[l].flags) (void)hipFree(r->lv[l].flags);
+        r->lv[l].map = nullptr;
+        r->lv[l].flags = nullptr;
+    }
+}
+
+extern "C" {
+
+void rw_params_default(rw_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->beta = 128.0;
+    p->eps = 1e-6;
+    p->tol = 1e-5;
+    p->expand = 1.25;
+    p->t_hom = 0.3;
+    p->t_bin = 0.01;
+    p->t_inc = 0.01;
+    p->brick = 32;
+    p->max_iter = 5000;
+    p->precision = RW_PREC_MIXED;
+    p->n_classes = 2;
+    p->prune_hom = 1;
+    p->prune_dt = 1;
+    p->refine_max = 1;
+}
+
+int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels, rw_pyramid** out,
+                     void* stream) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!out) return fail(ctx, RW_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!vol || !dims) return fail(ctx, RW_E_INVAL, "vol and dims must be non-NULL");
+    if (dtype != RW_U16 && dtype != RW_F32) return fail(ctx, RW_E_INVAL, "dtype must be RW_U16 or RW_F32");
+    if (levels < 1 || levels > RW_MAX_LEVELS) return fail(ctx, RW_E_INVAL, "levels must be in [1, %d]", RW_MAX_LEVELS);
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1 || dims[a] > (1 << 20)) return fail(ctx, RW_E_INVAL, "dims must be in [1, 2^20]");
+    hipStream_t s = (hipStream_t)stream;
+    DevGuard dg(ctx->device);
+    rw_pyramid* p = new (std::nothrow) rw_pyramid();
+    if (!p) return fail(ctx, RW_E_NOMEM, "host allocation failed");
+    p->device = ctx->device;
+    p->levels = levels;
+    for (int l = 0; l < levels; ++l)
+        for (int a = 0; a < 3; ++a) p->dims[l][a] = l == 0 ? dims[a] : (p->dims[l - 1][a] + 1) / 2;
+    for (int l = 0; l < levels; ++l) {
+        const int64_t n = p->dims[l][0] * p->dims[l][1] * p->dims[l][2];
+        hipError_t e = hipMalloc((void**)&p->data[l], (size_t)n * sizeof(float));
+        if (e != hipSuccess) {
+            rw_pyramid_free(p);
+            return hip_fail(ctx, e, "allocating pyramid level");
+        }
+    }
+    const int64_t n0 = dims[0] * dims[1] * dims[2];
+    const int T = 256;
+    if (dtype == RW_U16) {
+        unsigned init[2] = {0xffffu, 0u};
+        unsigned* mm = nullptr;
+        hipError_t e = hipMalloc((void**)&mm, sizeof(init));
+        if (e == hipSuccess) e = hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_minmax_u16, dim3(grid_for(n0, T)), dim3(T), 0, s, (const uint16_t*)vol, n0, mm);
+            hipLaunchKernelGGL(k_normalize_u16, dim3(grid_for(n0, T)), dim3(T), 0, s, (const uint16_t*)vol, n0, mm,
+                               p->data[0]);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (mm) (void)hipFree(mm);
+        if (e != hipSuccess) {
+            rw_pyramid_free(p);
+            return hip_fail(ctx, e, "normalising volume");
+        }
+    } else {
+        hipLaunchKernelGGL(k_clip_f32, dim3(grid_for(n0, T)), dim3(T), 0, s, (const float*)vol, n0, p->data[0]);
+    }
+    for (int l = 1; l < levels; ++l) {
+        const int64_t n = p->dims[l][0] * p->dims[l][1] * p->dims[l][2];
+        hipLaunchKernelGGL(k_downsample, dim3(grid_for(n, T)), dim3(T), 0, s, p->data[l - 1], p->dims[l - 1][0],
+                           p->dims[l - 1][1], p->dims[l - 1][2], p->data[l], p->dims[l][0], p->dims[l][1], p->dims[l][2]);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        rw_pyramid_free(p);
+        return hip_fail(ctx, e, "building pyramid");
+    }
+    *out = p;
+    return RW_OK;
+}
+
+void rw_pyramid_free(rw_pyramid* p) {
+    if (!p) return;
+    DevGuard dg(p->device);
+    (void)hipDeviceSynchronize();
+    for (int l = 0; l < RW_MAX_LEVELS; ++l)
+        if (p->data[l]) (void)hipFree(p->data[l]);
+    delete p;
+}
+
+int rw_pyramid_level(const rw_pyramid* p, int level, int64_t dims[3], const float** data) {
+    if (!p || level < 0 || level >= p->levels) return fail(nullptr, RW_E_INVAL, "bad pyramid or level");
+    if (dims)
+        for (int a = 0; a < 3; ++a) dims[a] = p->dims[level][a];
+    if (data) *data = p->data[level];
+    return RW_OK;
+}
+
+int rw_segment(rw_ctx* ctx, const rw_pyramid* pyr, const rw_seed* seeds, int64_t n_seeds, const rw_params* params,
+               const rw_result* prev, rw_result** out, void* stream) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!out) return fail(ctx, RW_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!pyr || !params) return fail(ctx, RW_E_INVAL, "pyramid and params must be non-NULL");
+    if (n_seeds < 0 || (n_seeds > 0 && !seeds)) return fail(ctx, RW_E_INVAL, "bad seed array");
+    const rw_params& P = *params;
+    if (P.n_classes < 2 || P.n_classes > 4) return fail(ctx, RW_E_INVAL, "n_classes must be in [2, 4]");
+    if (P.brick < 2 || P.brick > 1024) return fail(ctx, RW_E_INVAL, "brick must be in [2, 1024]");
+    if (!(P.expand >= 1.0) || P.expand > 4.0) return fail(ctx, RW_E_INVAL, "expand must be in [1, 4]");
+    if (!(P.t_hom >= 0) || !(P.t_bin >= 0) || !(P.t_inc >= 0)) return fail(ctx, RW_E_INVAL, "thresholds must be >= 0");
+    if (P.reserved != 0) return fail(ctx, RW_E_INVAL, "reserved must be 0");
+    for (int64_t i = 0; i < n_seeds; ++i) {
+        const rw_seed& q = seeds[i];
+        if (!std::isfinite(q.x) || !std::isfinite(q.y) || !std::isfinite(q.z))
+            return fail(ctx, RW_E_INVAL, "seed %lld has a non-finite coordinate", (long long)i);
+        if (q.label < 0 || q.label >= P.n_classes)
+            return fail(ctx, RW_E_INVAL, "seed %lld: label %d outside [0, %d)", (long long)i, q.label, P.n_classes);
+    }
+    if (prev) {
+        if (prev->levels != pyr->levels || prev->R != P.n_classes - 1 || prev->params.brick != P.brick ||
+            prev->params.expand != P.expand)
+            return fail(ctx, RW_E_INVAL, "prev was computed with a different pyramid or brick layout");
+        for (int l = 0; l < pyr->levels; ++l)
+            for (int a = 0; a < 3; ++a)
+                if (prev->lv[l].dims[a] != pyr->dims[l][a]) return fail(ctx, RW_E_INVAL, "prev dims differ");
+    }
+    rw_result* r = new (std::nothrow) rw_result();
+    if (!r) return fail(ctx, RW_E_NOMEM, "host allocation failed");
+    r->device = ctx->device;
+    r->params = P;
+    r->levels = pyr->levels;
+    r->R = P.n_classes - 1;
+    r->seeds.assign(seeds, seeds + n_seeds);
+    hipStream_t s = (hipStream_t)stream;
+    DevGuard dg(ctx->device);
+    int rc = RW_OK;
+    switch (r->R) {
+        case 1: rc = segment_impl<1>(ctx, pyr, r->seeds, P, prev, r, s); break;
+        case 2: rc = segment_impl<2>(ctx, pyr, r->seeds, P, prev, r, s); break;
+        case 3: rc = segment_impl<3>(ctx, pyr, r->seeds, P, prev, r, s); break;
+    }
+    if (rc != RW_OK) {
+        (void)hipStreamSynchronize(s);
+        free_result_mem(r);
+        delete r;
+        return rc;
+    }
+    *out = r;
+    return RW_OK;
+}
+
+void rw_result_free(rw_result* r) {
+    if (!r) return;
+    DevGuard dg(r->device);
+    (void)hipDeviceSynchronize();
+    free_result_mem(r);
+    delete r;
+}
+
+int rw_result_stats(const rw_result* r, rw_run_stats* out) {
+    if (!r || !out) return fail(nullptr, RW_E_INVAL, "result and out must be non-NULL");
+    *out = r->stats;
+    return RW_OK;
+}
+
+int rw_result_level(const rw_result* r, int level, int64_t dims[3], int* nrhs, const float** map) {
+    if (!r || level < 0 || level >= r->levels) return fail(nullptr, RW_E_INVAL, "bad result or level");
+    if (dims)
+        for (int a = 0; a < 3; ++a) dims[a] = r->lv[level].dims[a];
+    if (nrhs) *nrhs = r->R;
+    if (map) *map = r->lv[level].map;
+    return RW_OK;
+}
+
+int rw_result_flags(const rw_result* r, int level, int64_t nb[3], const uint8_t** flags) {
+    if (!r || level < 0 || level >= r->levels) return fail(nullptr, RW_E_INVAL, "bad result or level");
+    if (nb)
+        for (int a = 0; a < 3; ++a) nb[a] = r->lv[level].nb[a];
+    if (flags) *flags = r->lv[level].flags;
+    return RW_OK;
+}
+
+static int copy_out(rw_ctx* ctx, void* dst, const void* src, size_t bytes, void* stream, int device) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!dst) return fail(ctx, RW_E_INVAL, "dst is NULL");
+    DevGuard dg(device);
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? RW_OK : hip_fail(ctx, e, "copying out");
+}
+
+int rw_result_copy_level(rw_ctx* ctx, const rw_result* r, int level, float* dst, void* stream) {
+    if (!r || level < 0 || level >= r->levels) return fail(ctx, RW_E_INVAL, "bad result or level");
+    const int64_t n = r->lv[level].dims[0] * r->lv[level].dims[1] * r->lv[level].dims[2];
+    return copy_out(ctx, dst, r->lv[level].map, (size_t)n * r->R * sizeof(float), stream, r->device);
+}
+
+int rw_result_copy_flags(rw_ctx* ctx, const rw_result* r, int level, uint8_t* dst, void* stream) {
+    if (!r || level < 0 || level >= r->levels) return fail(ctx, RW_E_INVAL, "bad result or level");
+    const int64_t n = r->lv[level].nb[0] * r->lv[level].nb[1] * r->lv[level].nb[2];
+    return copy_out(ctx, dst, r->lv[level].flags, (size_t)n, stream, r->device);
+}
+
+int rw_pyramid_copy_level(rw_ctx* ctx, const rw_pyramid* p, int level, float* dst, void* stream) {
+    if (!p || level < 0 || level >= p->levels) return fail(ctx, RW_E_INVAL, "bad pyramid or level");
+    const int64_t n = p->dims[level][0] * p->dims[level][1] * p->dims[level][2];
+    return copy_out(ctx, dst, p->data[level], (size_t)n * sizeof(float), stream, p->device);
+}
+
+int rw_result_materialize(rw_ctx* ctx, const rw_result* r, int level, int cls, float* prob, uint8_t* labels,
+                          void* stream) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!r || level < 0 || level >= r->levels) return fail(ctx, RW_E_INVAL, "bad result or level");
+    if (cls < 0 || cls > r->R) return fail(ctx, RW_E_INVAL, "class %d outside [0, %d]", cls, r->R);
+    const int64_t n = r->lv[level].dims[0] * r->lv[level].dims[1] * r->lv[level].dims[2];
+    hipStream_t s = (hipStream_t)stream;
+    DevGuard dg(ctx->device);
+    const int T = 256;
+    switch (r->R) {
+        case 1: hipLaunchKernelGGL(k_materialize<1>, dim3(grid_for(n, T)), dim3(T), 0, s, r->lv[level].map, n, cls, prob, labels); break;
+        case 2: hipLaunchKernelGGL(k_materialize<2>, dim3(grid_for(n, T)), dim3(T), 0, s, r->lv[level].map, n, cls, prob, labels); break;
+        case 3: hipLaunchKernelGGL(k_materialize<3>, dim3(grid_for(n, T)), dim3(T), 0, s, r->lv[level].map, n, cls, prob, labels); break;
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RW_OK : hip_fail(ctx, e, "launching materialize");
+}
+
+}  // extern "C"
