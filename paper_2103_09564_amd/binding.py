@@ -381,3 +381,50 @@ def segment(pyramid, seeds, prev=None, stream=None, ctx=None, **kw):
     ctx._check(lib.rw_segment(ctx.handle, pyramid.handle, arr, n, ctypes.byref(params(**kw)),
                               prev.handle if prev is not None else None, ctypes.byref(h), _stream(stream)))
     return Result(ctx, h, pyramid.device)
+
+
+# ---------------------------------------------------------------------------
+# Differentiation: autograd wrapper around the batched solve and its adjoint
+# ---------------------------------------------------------------------------
+
+def _make_rwsolve():
+    import torch
+
+    class RWSolve(torch.autograd.Function):
+        """x = rw(g, beta) for a batch of boxes, differentiable in g and beta.
+
+        forward(g, beta, mask, x_dirichlet, shapes, offsets, eps, tol, precision):
+        solves every box (x_dirichlet supplies the seeded values and the start);
+        backward runs the library's adjoint (L_UU lambda = dl/dx_U and the
+        edge-weight chain rule) and returns dl/dg (per voxel) and dl/dbeta.
+        The Dirichlet values get no gradient.
+        """
+
+        @staticmethod
+        def forward(fctx, g, beta, mask, x_dirichlet, shapes, offsets, eps=1e-6, tol=1e-8,
+                    precision=PREC_MIXED_REFINE, adjoint_tol=1e-8):
+            b = float(beta.detach().cpu()) if torch.is_tensor(beta) else float(beta)
+            x = x_dirichlet.detach().clone()
+            st = solve_bricks(g.detach(), mask, x, shapes, offsets, beta=b, eps=eps, tol=tol, precision=precision,
+                              refine_max=4, refine_tol=tol)
+            fctx.save_for_backward(g.detach(), x)
+            fctx.meta = (mask, shapes, offsets, b, eps, adjoint_tol, torch.is_tensor(beta))
+            fctx.solve_stats = st
+            return x
+
+        @staticmethod
+        def backward(fctx, grad_x):
+            g, x = fctx.saved_tensors
+            mask, shapes, offsets, b, eps, atol, beta_is_tensor = fctx.meta
+            dl_dg, dl_dbeta, _ = solve_bricks_adjoint(g, mask, x, grad_x.contiguous().float(), shapes, offsets,
+                                                      beta=b, eps=eps, tol=atol)
+            gb = dl_dbeta.reshape(()).to(torch.float32) if beta_is_tensor else None
+            return dl_dg, gb, None, None, None, None, None, None, None, None
+
+    return RWSolve
+
+
+try:
+    RWSolve = _make_rwsolve()
+except ImportError:   # torch is only needed for the autograd wrapper
+    RWSolve = None
