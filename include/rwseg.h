@@ -145,6 +145,21 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
                     void* stream);
 
 /*
+ * Phase timing of rw_solve_bricks (tracing).  With timing enabled the next
+ * solves record HIP events on their stream around each phase; rw_last_timing
+ * waits for those events and returns the phase durations of the last solve
+ * in milliseconds.  pcg_ms is the main PCG kernel alone (the hot loop).
+ */
+typedef struct rw_timing {
+    float init_ms;           /* Dirichlet init (r = -(L x)_U, z, p) */
+    float pcg_ms;            /* main PCG kernel(s) */
+    float finish_ms;         /* FP64 true residual, refinement, stats */
+    float total_ms;
+} rw_timing;
+int rw_set_timing(rw_ctx* ctx, int enable);
+int rw_last_timing(rw_ctx* ctx, rw_timing* out);
+
+/*
  * Host-only check of the arguments rw_solve_bricks would validate (params,
  * descriptors, buffer extents, overlap).  Needs no GPU and queues nothing.
  * Returns RW_OK or RW_E_INVAL; the message is in rw_last_error(NULL).

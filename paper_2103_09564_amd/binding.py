@@ -60,6 +60,17 @@ lib.rw_validate_solve.argtypes = [ctypes.POINTER(SolveParams), _i64, _vp, _i64]
 lib.rw_validate_solve.restype = ctypes.c_int
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("init_ms", ctypes.c_float), ("pcg_ms", ctypes.c_float), ("finish_ms", ctypes.c_float),
+                ("total_ms", ctypes.c_float)]
+
+
+lib.rw_set_timing.argtypes = [_vp, ctypes.c_int]
+lib.rw_set_timing.restype = ctypes.c_int
+lib.rw_last_timing.argtypes = [_vp, ctypes.POINTER(Timing)]
+lib.rw_last_timing.restype = ctypes.c_int
+
+
 class RWError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"librwseg error {code}: {msg}")
@@ -144,6 +155,15 @@ class Context:
         self._check(lib.rw_solve_bricks(self.handle, ctypes.byref(params), len(bricks),
                                         bricks.ctypes.data_as(_vp), n_vox, _ptr(g), _ptr(mask), _ptr(x),
                                         _ptr(x64), _ptr(stats), _stream(stream)))
+
+    def set_timing(self, enable=True):
+        self._check(lib.rw_set_timing(self.handle, 1 if enable else 0))
+
+    def last_timing(self):
+        """Phase durations (ms) of the last timed solve; waits for its events."""
+        t = Timing()
+        self._check(lib.rw_last_timing(self.handle, ctypes.byref(t)))
+        return {"init_ms": t.init_ms, "pcg_ms": t.pcg_ms, "finish_ms": t.finish_ms, "total_ms": t.total_ms}
 
     def rw_solve_bricks_adjoint(self, params, bricks, g, mask, x, dl_dx, dl_dg, dl_dbeta, lam=None,
                                 stats=None, stream=None):

@@ -192,10 +192,34 @@ void rw_ctx_destroy(rw_ctx* ctx) {
     if (ctx->aux) (void)hipFree(ctx->aux);
     if (ctx->hws) (void)hipFree(ctx->hws);
     if (ctx->hgeo) (void)hipFree(ctx->hgeo);
+    for (int i = 0; i < 4; ++i)
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     delete ctx;
 }
 
 const char* rw_last_error(const rw_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+int rw_set_timing(rw_ctx* ctx, int enable) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->timing = enable ? 1 : 0;
+    ctx->ev_valid = 0;
+    return RW_OK;
+}
+
+int rw_last_timing(rw_ctx* ctx, rw_timing* out) {
+    if (!ctx || !out) return fail(ctx, RW_E_INVAL, "ctx and out must be non-NULL");
+    if (!ctx->ev_valid) return fail(ctx, RW_E_INVAL, "no timed solve recorded (enable with rw_set_timing)");
+    DevGuard dg(ctx->device);
+    hipError_t e = hipEventSynchronize(ctx->ev[3]);
+    float t[3] = {0, 0, 0};
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventElapsedTime(&t[i], ctx->ev[i], ctx->ev[i + 1]);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reading timing events");
+    out->init_ms = t[0];
+    out->pcg_ms = t[1];
+    out->finish_ms = t[2];
+    out->total_ms = t[0] + t[1] + t[2];
+    return RW_OK;
+}
 
 int rw_validate_solve(const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
                       int64_t n_voxels) {
@@ -268,8 +292,24 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
     a.refine_max = p.refine_max;
     a.stall_ratio = p.stall_ratio;
     a.schedule = p.schedule == 0 ? 1 : p.schedule;
-    e = rwk::launch_solve(a, n_bricks, R, fp64, pp, s);
+    hipEvent_t* ev = nullptr;
+    if (ctx->timing) {
+        for (int i = 0; i < 4; ++i)
+            if (!ctx->ev[i]) {
+                e = hipEventCreate(&ctx->ev[i]);
+                if (e != hipSuccess) return hip_fail(ctx, e, "creating timing events");
+            }
+        e = hipEventRecord(ctx->ev[0], s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "recording timing event");
+        ev = &ctx->ev[1];
+    }
+    e = rwk::launch_solve(a, n_bricks, R, fp64, pp, s, ev);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching solve kernel");
+    if (ctx->timing) {
+        e = hipEventRecord(ctx->ev[3], s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "recording timing event");
+        ctx->ev_valid = 1;
+    }
     return RW_OK;
 }
 

@@ -22,6 +22,9 @@ struct rw_ctx {
     size_t hws_bytes = 0;
     void* hgeo = nullptr;        // hierarchy: box geometry, seed entries, per-box scalars
     size_t hgeo_bytes = 0;
+    int timing = 0;              // record phase events in rw_solve_bricks
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // start, after init, after pcg, end
+    int ev_valid = 0;
 };
 
 namespace rwk {
@@ -112,8 +115,9 @@ int plane_cols(int max_plane);
 int plane_max(int cols);
 
 // Launchers (pcg.hip).  Return a hipError_t.
+// ev: optional events {after init, after main PCG} recorded on s (may be null).
 hipError_t launch_solve(const SolveArgs& a, int64_t n_bricks, int nrhs, bool fp64, const PlanePlan& pp,
-                        hipStream_t s);
+                        hipStream_t s, hipEvent_t* ev = nullptr);
 // The adjoint reuses the solve kernels: `sa` carries the PCG view (r, z, p, state) of the workspace.
 hipError_t launch_adjoint(const AdjointArgs& a, const SolveArgs& sa, int64_t n_bricks, double* dl_dbeta,
                           const PlanePlan& pp, hipStream_t s);

@@ -1417,10 +1417,12 @@ static hipError_t launch_pcg_c(const SolveArgs& a, int64_t n, XT* xt, int corr, 
 }
 
 template <int R>
-static hipError_t launch_mixed(const SolveArgs& a, int64_t n, const PlanePlan& pp, hipStream_t s) {
+static hipError_t launch_mixed(const SolveArgs& a, int64_t n, const PlanePlan& pp, hipStream_t s, hipEvent_t* ev) {
     const dim3 grid((unsigned)n), blk(kThreads);
     hipLaunchKernelGGL((k_init<float, R>), grid, blk, 0, s, a);
+    if (ev) RW_TRY(hipEventRecord(ev[0], s));
     RW_TRY(launch_pcg_c<float, R, float>(a, n, a.x, 0, pp, s));
+    if (ev) RW_TRY(hipEventRecord(ev[1], s));
     const bool r64 = a.precision == RW_PREC_MIXED_REFINE;
     if (r64) hipLaunchKernelGGL((k_copy64<R>), grid, blk, 0, s, a, 1);
     for (int step = 0; step < a.refine_max; ++step) {
@@ -1438,10 +1440,12 @@ static hipError_t launch_mixed(const SolveArgs& a, int64_t n, const PlanePlan& p
 }
 
 template <int R>
-static hipError_t launch_fp64(const SolveArgs& a, int64_t n, const PlanePlan& pp, hipStream_t s) {
+static hipError_t launch_fp64(const SolveArgs& a, int64_t n, const PlanePlan& pp, hipStream_t s, hipEvent_t* ev) {
     const dim3 grid((unsigned)n), blk(kThreads);
     hipLaunchKernelGGL((k_init<double, R>), grid, blk, 0, s, a);
+    if (ev) RW_TRY(hipEventRecord(ev[0], s));
     RW_TRY(launch_pcg_c<double, R, double>(a, n, (double*)a.xt, 0, pp, s));
+    if (ev) RW_TRY(hipEventRecord(ev[1], s));
     hipLaunchKernelGGL((k_finish64<R>), grid, blk, 0, s, a);
     hipLaunchKernelGGL((k_stats<R>), grid, blk, 0, s, a, 0);
     return hipGetLastError();
@@ -1456,19 +1460,20 @@ int plane_cols(int max_plane) { return max_plane <= 2 * kThreads ? 2 : 4; }
 
 int plane_max(int cols) { return cols * kThreads; }
 
-hipError_t launch_solve(const SolveArgs& a, int64_t n, int nrhs, bool fp64, const PlanePlan& pp, hipStream_t s) {
+hipError_t launch_solve(const SolveArgs& a, int64_t n, int nrhs, bool fp64, const PlanePlan& pp, hipStream_t s,
+                        hipEvent_t* ev) {
     if (n == 0) return hipSuccess;
     if (fp64) {
         switch (nrhs) {
-            case 1: return launch_fp64<1>(a, n, pp, s);
-            case 2: return launch_fp64<2>(a, n, pp, s);
-            case 3: return launch_fp64<3>(a, n, pp, s);
+            case 1: return launch_fp64<1>(a, n, pp, s, ev);
+            case 2: return launch_fp64<2>(a, n, pp, s, ev);
+            case 3: return launch_fp64<3>(a, n, pp, s, ev);
         }
     } else {
         switch (nrhs) {
-            case 1: return launch_mixed<1>(a, n, pp, s);
-            case 2: return launch_mixed<2>(a, n, pp, s);
-            case 3: return launch_mixed<3>(a, n, pp, s);
+            case 1: return launch_mixed<1>(a, n, pp, s, ev);
+            case 2: return launch_mixed<2>(a, n, pp, s, ev);
+            case 3: return launch_mixed<3>(a, n, pp, s, ev);
         }
     }
     return hipErrorInvalidValue;
