@@ -115,21 +115,48 @@ int build_list(rw_ctx* ctx, int64_t n, const rw_brick* bricks, int64_t n_voxels,
 
 // Choose the PCG kernel split for this batch and move the boxes that are too
 // wide for the LDS plane march to the front of the (largest-first) list.
+// The few largest boxes (single domains) go to the multi-workgroup solver in
+// front of the list.
 rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, int nrhs, bool fp64) {
-    rwk::PlanePlan pp{0, 2, (int64_t)list->size()};
+    rwk::PlanePlan pp{0, 2, (int64_t)list->size(), 0, nullptr};
     int widest = 0;
     for (const auto& b : *list)
         if (b.nx * b.ny <= rwk::plane_max(4)) widest = std::max(widest, b.nx * b.ny);
     int cols = rwk::plane_cols(widest);
     if (rwk::plane_lds_bytes(nrhs, fp64, cols) > ctx->lds_limit) cols = 2;
-    if (rwk::plane_lds_bytes(nrhs, fp64, cols) > ctx->lds_limit) return pp;
-    const int lim = rwk::plane_max(cols);
-    std::stable_partition(list->begin(), list->end(), [lim](const rwk::BrickDev& b) { return b.nx * b.ny > lim; });
+    const bool use = rwk::plane_lds_bytes(nrhs, fp64, cols) <= ctx->lds_limit;
+    const int lim = use ? rwk::plane_max(cols) : 0;
+    // group 0: domain solver, 1: global march, 2: plane march (list is largest-first)
+    std::vector<uint8_t> grp(list->size());
+    int n_dom = 0;
+    for (size_t i = 0; i < list->size(); ++i) {
+        const rwk::BrickDev& b = (*list)[i];
+        const int64_t nxy = (int64_t)b.nx * b.ny, vox = nxy * b.nz;
+        const bool wide = nxy > lim;
+        // (the domain kernels index voxels with 32-bit integers)
+        const bool dom = vox < (int64_t(1) << 31) && (vox >= rwk::kDomBigVox || (wide && vox >= rwk::kDomMinVox));
+        if (dom && n_dom < rwk::kDomMaxBoxes) {
+            grp[i] = 0;
+            ++n_dom;
+        } else {
+            grp[i] = wide ? 1 : 2;
+        }
+    }
+    std::vector<size_t> idx(list->size());
+    std::iota(idx.begin(), idx.end(), size_t(0));
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return grp[a] < grp[b]; });
+    std::vector<rwk::BrickDev> sorted(list->size());
     int64_t n_big = 0;
-    for (const auto& b : *list) n_big += b.nx * b.ny > lim ? 1 : 0;
-    pp.use = 1;
+    for (size_t i = 0; i < idx.size(); ++i) {
+        sorted[i] = (*list)[idx[i]];
+        n_big += grp[idx[i]] < 2 ? 1 : 0;
+    }
+    list->swap(sorted);
+    pp.use = use ? 1 : 0;
     pp.cols = cols;
     pp.n_big = n_big;
+    pp.n_dom = n_dom;
+    pp.host = list->data();
     return pp;
 }
 
@@ -259,7 +286,8 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
     if (need_x64 && !x64) bytes = off_x64 + nv * sizeof(double);
     hipError_t e = grow(ctx, &ctx->ws, &ctx->ws_bytes, std::max<size_t>(bytes, 256), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating solver workspace");
-    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, std::max<size_t>((size_t)n_bricks * sizeof(rwk::BoxState), 256), s);
+    const size_t state_bytes = ((size_t)n_bricks * sizeof(rwk::BoxState) + 255) & ~size_t(255);
+    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, state_bytes + rwk::domain_scratch_bytes(), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating per-box state");
     const rwk::PlanePlan pp = plan_planes(ctx, &list, R, fp64);
     rc = upload_list(ctx, list, s);
@@ -292,6 +320,7 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
     a.refine_max = p.refine_max;
     a.stall_ratio = p.stall_ratio;
     a.schedule = p.schedule == 0 ? 1 : p.schedule;
+    rwk::domain_bind(a, (char*)ctx->aux + state_bytes);
     hipEvent_t* ev = nullptr;
     if (ctx->timing) {
         for (int i = 0; i < 4; ++i)
@@ -337,7 +366,8 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     hipError_t e = grow(ctx, &ctx->ws, &ctx->ws_bytes, std::max<size_t>(bytes, 256), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint workspace");
     const size_t state_bytes = ((size_t)n_bricks * sizeof(rwk::BoxState) + 255) & ~size_t(255);
-    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, state_bytes + std::max<size_t>((size_t)n_bricks * sizeof(double), 256), s);
+    const size_t part_bytes = ((size_t)n_bricks * sizeof(double) + 255) & ~size_t(255);
+    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, state_bytes + part_bytes + rwk::domain_scratch_bytes(), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint partials");
     const rwk::PlanePlan pp = plan_planes(ctx, &list, 1, false);
     rc = upload_list(ctx, list, s);
@@ -377,6 +407,7 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     sa.max_iter = a.max_iter;
     sa.precision = RW_PREC_MIXED;
     sa.schedule = params->schedule == 0 ? 1 : params->schedule;
+    rwk::domain_bind(sa, (char*)ctx->aux + state_bytes + part_bytes);
     e = rwk::launch_adjoint(a, sa, n_bricks, dl_dbeta, pp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching adjoint kernels");
     return RW_OK;

@@ -81,6 +81,9 @@ struct SolveArgs {
     double beta, eps, tol, refine_tol, inner_tol, stall_ratio;
     int32_t max_iter, precision, refine_max, want_x64;
     int32_t schedule;      // 1: two-sweep Jacobi-PCG, 2: single-reduction (Chronopoulos-Gear)
+    void* dom;             // multi-workgroup domain solver: scalar state (two slots)
+    double* dom_partA;     // per-workgroup partials of p.Ap
+    double* dom_partB;     // per-workgroup partials of r.z and ||r||^2
 };
 
 struct AdjointArgs {
@@ -101,16 +104,34 @@ struct AdjointArgs {
     int32_t max_iter;
 };
 
-// How the PCG kernel is split: boxes [0, n_big) of the launch list use the
-// global-memory march, [n_big, n) the LDS plane march with `cols` columns per
-// thread (planes up to plane_max(cols) voxels).  use = 0: all global.
+// How the PCG kernel is split: boxes [0, n_dom) of the launch list run the
+// multi-workgroup domain solver one after another (host copies in `host`),
+// [n_dom, n_big) the global-memory march, [n_big, n) the LDS plane march with
+// `cols` columns per thread (planes up to plane_max(cols) voxels).  use = 0:
+// no plane march (n_big = n).
 struct PlanePlan {
     int use;
     int cols;
     int64_t n_big;
+    int64_t n_dom;
+    const BrickDev* host;
 };
 
 size_t plane_lds_bytes(int nrhs, bool fp64, int cols);
+
+// Multi-workgroup domain solver (domain.hip).  A box goes there when it has at
+// least kDomMinVox voxels and a plane too wide for the LDS march, or at least
+// kDomBigVox voxels; at most kDomMaxBoxes boxes per call (the largest).
+constexpr int64_t kDomMinVox = int64_t(1) << 16;
+constexpr int64_t kDomBigVox = int64_t(1) << 20;
+constexpr int kDomMaxBoxes = 16;
+size_t domain_scratch_bytes();
+void domain_bind(SolveArgs& a, void* scratch);
+// PCG on box ib (launch order; bd = its host descriptor) from the state k_init
+// or k_check left, into xt (corr = 0: main solve, 1: correction solve).
+// Synchronises s every few iterations to test for convergence.
+template <typename T, int R, typename XT>
+hipError_t domain_pcg(const SolveArgs& a, int ib, const BrickDev& bd, XT* xt, int corr, hipStream_t s);
 int plane_cols(int max_plane);
 int plane_max(int cols);
 

@@ -1391,14 +1391,17 @@ __global__ __launch_bounds__(kThreads) void k_sum_partials(const double* part, i
         if (e_ != hipSuccess) return e_;      \
     } while (0)
 
-// The box list is ordered so that boxes whose z-plane exceeds the LDS plane
-// march (nx*ny > C*kThreads) come first: [0, n_big) run the global-memory
-// march, [n_big, n) the LDS plane march, each kernel compiled for one path.
+// The box list is ordered so that the large single domains come first (the
+// multi-workgroup solver), then boxes whose z-plane exceeds the LDS plane
+// march (nx*ny > C*kThreads, global-memory march), then the rest (LDS plane
+// march), each kernel compiled for one path.
 template <typename T, int R, int C, typename XT>
 static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big, XT* xt, int corr, size_t lds,
-                                   hipStream_t s) {
-    if (n_big > 0)
-        hipLaunchKernelGGL((k_pcg<T, R, C, false, 1, XT>), dim3((unsigned)n_big), dim3(kThreads), 0, s, a, xt, corr, 0);
+                                   const PlanePlan& pp, hipStream_t s) {
+    for (int64_t i = 0; i < pp.n_dom; ++i) RW_TRY((domain_pcg<T, R, XT>(a, (int)i, pp.host[i], xt, corr, s)));
+    if (n_big > pp.n_dom)
+        hipLaunchKernelGGL((k_pcg<T, R, C, false, 1, XT>), dim3((unsigned)(n_big - pp.n_dom)), dim3(kThreads), 0, s,
+                           a, xt, corr, (int)pp.n_dom);
     if (n > n_big) {
         auto k = a.schedule == 2 ? k_pcg<T, R, C, true, 2, XT> : k_pcg<T, R, C, true, 1, XT>;
         if (lds > 48 * 1024)
@@ -1412,8 +1415,8 @@ template <typename T, int R, typename XT>
 static hipError_t launch_pcg_c(const SolveArgs& a, int64_t n, XT* xt, int corr, const PlanePlan& pp, hipStream_t s) {
     const size_t lds = pp.use ? plane_lds_bytes(R, sizeof(T) == 8, pp.cols) : 0;
     const int64_t n_big = pp.use ? pp.n_big : n;
-    return pp.cols == 2 ? launch_pcg_plane<T, R, 2, XT>(a, n, n_big, xt, corr, lds, s)
-                        : launch_pcg_plane<T, R, 4, XT>(a, n, n_big, xt, corr, lds, s);
+    return pp.cols == 2 ? launch_pcg_plane<T, R, 2, XT>(a, n, n_big, xt, corr, lds, pp, s)
+                        : launch_pcg_plane<T, R, 4, XT>(a, n, n_big, xt, corr, lds, pp, s);
 }
 
 template <int R>

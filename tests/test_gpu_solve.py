@@ -216,3 +216,52 @@ def test_full_size_stress_sampled(env):
         ref = _ref(d["boxes"][i])
         o = int(d["offsets"][i])
         assert np.max(np.abs(x[o:o + ref.size] - ref)) <= 1e-4, (i, st[i])
+
+
+def test_domain_solver_boxes(env):
+    """Large single boxes (wide planes of >= 2^16 voxels, or >= 2^20 voxels)
+    take the multi-workgroup solver, at most 16 per call; the rest of such a
+    call runs the per-box kernels.  Every path against the oracle."""
+    rng = np.random.default_rng(21)
+    wide = synth.random_box(rng, (48, 48, 40), dirichlet_frac=0.02)
+    tall = synth.random_box(rng, (32, 32, 1024), dirichlet_frac=0.05)
+    d = synth.from_boxes([wide, tall])
+    refs = [_ref(b) for b in (wide, tall)]
+    x, _, st = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    _, x64, st64 = _run(env, d, x64=True, beta=BETA, eps=EPS, tol=1e-6, precision=2,
+                        refine_max=6, refine_tol=1e-13, inner_tol=1e-4)
+    _, f64, stf = _run(env, d, x64=True, beta=BETA, eps=EPS, tol=1e-12, precision=0)
+    for i, ref in enumerate(refs):
+        o, n = int(d["offsets"][i]), ref.size
+        assert st["status"][i] in (0, 2) and np.max(np.abs(x[o:o + n] - ref)) <= 1e-4, st[i]
+        assert st64["status"][i] == 2 and np.max(np.abs(x64[o:o + n] - ref)) <= 1e-9, st64[i]
+        assert stf["status"][i] == 0 and np.max(np.abs(f64[o:o + n] - ref)) <= 1e-9, stf[i]
+        assert st["iters"][i] > 0 and stf["true_rel_resid"][i] <= 1e-12 * 1.01
+
+
+def test_domain_solver_multi_rhs_and_cap(env):
+    # 17 wide boxes of 2^16+ voxels: 16 go to the domain solver, one to the
+    # global-memory march; nrhs = 2 and 3 against per-rhs oracle solves
+    rng = np.random.default_rng(22)
+    boxes = [synth.random_box(rng, (46, 46, 31), dirichlet_frac=0.03) for _ in range(17)]
+    d = synth.from_boxes(boxes)
+    for R in (2, 3):
+        xs = [np.where(d["mask"] != 0, rng.random(d["x"].size), 0.0).astype(np.float32) for _ in range(R)]
+        dR = dict(d, x=np.stack(xs, axis=1).ravel())
+        xR, _, st = _run(env, dR, beta=BETA, eps=EPS, tol=1e-7, precision=1, nrhs=R)
+        xR = xR.reshape(-1, R)
+        assert np.all(np.isin(st["status"], (0, 2))), st
+        for i in (0, 7, 15, 16):
+            g, m, _ = boxes[i]
+            o = int(d["offsets"][i])
+            for k in range(R):
+                ref = orw.solve_box(g, m, xs[k][o:o + g.size].reshape(g.shape), BETA, EPS, method="pcg",
+                                    tol=1e-14)
+                assert np.max(np.abs(xR[o:o + g.size, k] - ref.ravel())) <= 1e-4, (R, i, k)
+    # same boxes solved one call per box agree with the batched call
+    x1, _, _ = _run(env, d, beta=BETA, eps=EPS, tol=1e-7, precision=1)
+    for i in (3, 16):
+        di = synth.from_boxes([boxes[i]])
+        xi, _, _ = _run(env, di, beta=BETA, eps=EPS, tol=1e-7, precision=1)
+        o = int(d["offsets"][i])
+        assert np.max(np.abs(x1[o:o + boxes[i][0].size] - xi)) <= 1e-5
