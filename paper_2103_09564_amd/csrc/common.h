@@ -81,9 +81,8 @@ struct SolveArgs {
     double beta, eps, tol, refine_tol, inner_tol, stall_ratio;
     int32_t max_iter, precision, refine_max, want_x64;
     int32_t schedule;      // 1: two-sweep Jacobi-PCG, 2: single-reduction (Chronopoulos-Gear)
-    void* dom;             // multi-workgroup domain solver: scalar state (two slots)
-    double* dom_partA;     // per-workgroup partials of p.Ap
-    double* dom_partB;     // per-workgroup partials of r.z and ||r||^2
+    void* dom;             // multi-workgroup domain solver: scalar state and ticket
+    double* dom_part;      // its per-workgroup partial sums
 };
 
 struct AdjointArgs {
@@ -127,11 +126,22 @@ constexpr int64_t kDomBigVox = int64_t(1) << 20;
 constexpr int kDomMaxBoxes = 16;
 size_t domain_scratch_bytes();
 void domain_bind(SolveArgs& a, void* scratch);
-// PCG on box ib (launch order; bd = its host descriptor) from the state k_init
-// or k_check left, into xt (corr = 0: main solve, 1: correction solve).
-// Synchronises s every few iterations to test for convergence.
+// The phases of the per-box solve for box ib of the launch list (bd: its host
+// descriptor), each over many workgroups.  domain_pcg runs PCG from the state
+// the init or check left, into xt (corr = 0: main solve, 1: correction
+// solve); it synchronises s every few iterations to test for convergence.
+template <typename T, int R>
+hipError_t domain_init(const SolveArgs& a, int ib, const BrickDev& bd, hipStream_t s);
 template <typename T, int R, typename XT>
 hipError_t domain_pcg(const SolveArgs& a, int ib, const BrickDev& bd, XT* xt, int corr, hipStream_t s);
+template <int R, bool kRefine64>
+hipError_t domain_check(const SolveArgs& a, int ib, const BrickDev& bd, int may_refine, hipStream_t s);
+template <int R, bool kRefine64>
+hipError_t domain_apply(const SolveArgs& a, int ib, const BrickDev& bd, hipStream_t s);
+template <int R>
+hipError_t domain_copy64(const SolveArgs& a, int ib, const BrickDev& bd, int to64, hipStream_t s);
+template <int R>
+hipError_t domain_finish64(const SolveArgs& a, int ib, const BrickDev& bd, hipStream_t s);
 int plane_cols(int max_plane);
 int plane_max(int cols);
 

@@ -1,15 +1,22 @@
-// Multi-workgroup Jacobi-PCG for one large box (a single domain such as the
-// coarsest pyramid level or a plain volume solve): the same iteration as the
-// per-box kernels (Section III-B system, Section V solver), spread over up to
-// kDomMaxWG workgroups.  Each CG iteration is two launches:
-//   A(it): gamma/beta from the partial sums of B(it-1), convergence test;
-//          p_new = z + beta p_old, sigma = p_new . L_UU p_new (per-WG partials)
-//   B(it): alpha = gamma / sigma; x += alpha p, r -= alpha L_UU p, z = r/d,
-//          per-WG partials of r.z and ||r||^2
-// Every workgroup sums the partials in workgroup order, so all of them get the
-// same scalars bit for bit and the result is deterministic.  Workgroup 0 keeps
-// the scalars in a two-slot state (slot it & 1); the host polls the done flag
-// every few iterations.
+// Multi-workgroup solve of one large box (a single domain such as the
+// coarsest pyramid level or a plain volume solve): every phase of the per-box
+// solve (Dirichlet init, Jacobi-PCG, FP64 true residual, correction set-up and
+// apply; Section III-B system, Section V solver) spread over up to kDomMaxWG
+// workgroups of kDomThreads threads (grid-stride over the box's voxels).
+//
+// Each voxel's stencil is evaluated branch-free: out-of-box neighbours are
+// replaced by the voxel itself with weight 0, so all loads of a voxel are in
+// flight together.  Workgroup sums go to a partials array; the last workgroup
+// to finish (ticket counter) adds them in workgroup order and writes the
+// scalars, so every result is deterministic.
+//
+// One CG iteration is two launches:
+//   A(n): p_new = z + beta_n p_old, partial sigma = p_new . L_UU p_new;
+//         last workgroup: alpha_n = rho_n / sigma (breakdown test)
+//   B(n): x += alpha p, r -= alpha L_UU p, z = r / d, partial r.z, ||r||^2;
+//         last workgroup: convergence test, beta_{n+1}, state n+1
+// The scalar state of iteration n lives in slot n & 1; the host reads the
+// done flag every few iterations and stops launching.
 
 #include "common.h"
 
@@ -18,124 +25,373 @@
 namespace rwk {
 
 constexpr int kDomThreads = 256;
-constexpr int kDomMaxWG = 1024;
+constexpr int kDomWaves = kDomThreads / 64;
+constexpr int kDomMaxWG = 2048;
+constexpr int kDomPart = 12;  // doubles per workgroup partial record
 
 struct DomState {
-    double rz[3], rr[3], beta[3];
+    double rz[3], rr[3], beta[3], alpha[3];
     int32_t done[3];
-    int32_t all_done, iters, flags, pad;
+    int32_t all_done, iters, flags;
 };
 
-template <typename T>
-__device__ __forceinline__ T dom_weight(T a, T b, double beta, double eps);
-template <>
-__device__ __forceinline__ float dom_weight<float>(float a, float b, double beta, double eps) {
-    const float d = a - b;
-    return __builtin_amdgcn_exp2f((float)(-beta * 1.4426950408889634) * d * d) + (float)eps;
-}
-template <>
-__device__ __forceinline__ double dom_weight<double>(double a, double b, double beta, double eps) {
-    const double d = a - b;
-    return exp(-beta * d * d) + eps;
+struct DomCtl {
+    DomState s[2];
+    uint32_t ticket;
+    int32_t pad[3];
+};
+
+// Scratch layout: DomCtl (padded to 512 B), partials [kDomMaxWG][kDomPart].
+size_t domain_scratch_bytes() { return 512 + (size_t)kDomMaxWG * kDomPart * sizeof(double); }
+
+void domain_bind(SolveArgs& a, void* scratch) {
+    static_assert(sizeof(DomCtl) <= 512, "DomCtl exceeds its scratch");
+    char* c = (char*)scratch;
+    a.dom = c;
+    a.dom_part = (double*)(c + 512);
 }
 
-// Workgroup sum of N doubles, identical on every thread.
+namespace {
+
+template <typename T>
+struct DWeight;
+template <>
+struct DWeight<float> {
+    float c, eps;  // c = -beta * log2(e)
+    __device__ DWeight(double beta, double e) : c((float)(-beta * 1.4426950408889634)), eps((float)e) {}
+    __device__ __forceinline__ float operator()(float a, float b) const {
+        const float d = a - b;
+        return __builtin_amdgcn_exp2f(c * d * d) + eps;
+    }
+};
+template <>
+struct DWeight<double> {
+    double nb, eps;
+    __device__ DWeight(double beta, double e) : nb(-beta), eps(e) {}
+    __device__ __forceinline__ double operator()(double a, double b) const {
+        const double d = a - b;
+        return exp(nb * d * d) + eps;
+    }
+};
+
+__device__ __forceinline__ float drecip(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double drecip(double d) { return 1.0 / d; }
+
+// The six neighbours of flat box voxel v; absent ones point at v itself.
+struct Nb {
+    int u[6];
+    bool h[6];
+};
+
+__device__ __forceinline__ Nb neighbours(int v, int nx, int ny, int nz) {
+    const int nxy = nx * ny;
+    const int k = v / nxy, r0 = v - k * nxy, j = r0 / nx, i = r0 - j * nx;
+    Nb n;
+    n.h[0] = i > 0;
+    n.h[1] = i + 1 < nx;
+    n.h[2] = j > 0;
+    n.h[3] = j + 1 < ny;
+    n.h[4] = k > 0;
+    n.h[5] = k + 1 < nz;
+    n.u[0] = n.h[0] ? v - 1 : v;
+    n.u[1] = n.h[1] ? v + 1 : v;
+    n.u[2] = n.h[2] ? v - nx : v;
+    n.u[3] = n.h[3] ? v + nx : v;
+    n.u[4] = n.h[4] ? v - nxy : v;
+    n.u[5] = n.h[5] ? v + nxy : v;
+    return n;
+}
+
+// Edge weights of voxel v to its neighbours (0 where absent); returns the diagonal.
+template <typename T>
+__device__ __forceinline__ T stencil_weights(const float* __restrict__ g, int v, const Nb& n, const DWeight<T>& W,
+                                             T (&w)[6]) {
+    const T gc = (T)g[v];
+    T gn[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) gn[q] = (T)g[n.u[q]];
+    T d = T(0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        w[q] = n.h[q] ? W(gc, gn[q]) : T(0);
+        d += w[q];
+    }
+    return d;
+}
+
 template <int N>
-__device__ __forceinline__ void dom_block_sum(double (&v)[N], double* red) {
+__device__ __forceinline__ void wg_sum(double (&v)[N], double* red) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         double s = v[k];
+#pragma unroll
         for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
         v[k] = s;
     }
-    if (lane == 0)
+    if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < N; ++k) red[w * N + k] = v[k];
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         double s = 0.0;
-        for (int i = 0; i < kDomThreads / 64; ++i) s += red[i * N + k];
+#pragma unroll
+        for (int i = 0; i < kDomWaves; ++i) s += red[i * N + k];
         v[k] = s;
     }
     __syncthreads();
 }
 
-// Sum of per-workgroup partials part[w * N + k], w < G, in order.
+// Store this workgroup's sums, take a ticket; in the last workgroup to arrive
+// return true with the sums over all workgroups (fixed order) in v.
 template <int N>
-__device__ __forceinline__ void dom_sum_partials(const double* part, int G, double (&out)[N], double* red) {
+__device__ __forceinline__ bool last_wg_sum(double (&v)[N], DomCtl* ctl, double* part, double* red) {
+    __shared__ int last;
+    wg_sum<N>(v, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) part[blockIdx.x * kDomPart + k] = v[k];
+        __threadfence();
+        const uint32_t t = atomicAdd(&ctl->ticket, 1u);
+        last = t == gridDim.x - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double s[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) s[k] = 0.0;
+    // thread t adds workgroups t, t + 256, ... in order; then the fixed tree of wg_sum
+    for (int w = threadIdx.x; w < (int)gridDim.x; w += kDomThreads) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) s[k] += __builtin_nontemporal_load(&part[w * kDomPart + k]);
+    }
+    wg_sum<N>(s, red);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = s[k];
+    if (threadIdx.x == 0) ctl->ticket = 0u;
+    return true;
+}
+
+// Ticket without sums: true in the last workgroup to arrive.
+__device__ __forceinline__ bool last_wg(DomCtl* ctl) {
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t t = atomicAdd(&ctl->ticket, 1u);
+        last = t == gridDim.x - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    if (threadIdx.x == 0) ctl->ticket = 0u;
+    return true;
+}
+
+__device__ __forceinline__ bool fin(double v) { return isfinite(v); }
+
+#define RW_DOM_LOOP(v, nv) for (int v = blockIdx.x * kDomThreads + threadIdx.x; v < (nv); v += gridDim.x * kDomThreads)
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Dirichlet init (the multi-workgroup form of the per-box init): r = -(L x)_U,
+// z = r/d, p = 0, sums r.z, ||r||^2, ||b||^2, |U|, |M|; the FP64 path copies x
+// into its FP64 solution buffer.
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__global__ __launch_bounds__(kDomThreads) void k_dinit(SolveArgs a, int ib) {
+    __shared__ double red[kDomWaves * kDomPart];
+    const BrickDev b = a.bricks[ib];
+    const int nv = b.nx * b.ny * b.nz;
+    double s[3 * R + 2];
+#pragma unroll
+    for (int k = 0; k < 3 * R + 2; ++k) s[k] = 0.0;
+    const DWeight<T> W(a.beta, a.eps);
+    const float* g = a.g + b.off;
+    const uint8_t* m = a.mask + b.off;
+    const float* x = a.x + b.off * R;
+    T* r = (T*)a.r + b.off * R;
+    T* z = (T*)a.z + b.off * R;
+    T* p0 = (T*)a.p0 + b.off * R;
+    T* p1 = (T*)a.p1 + b.off * R;
+    RW_DOM_LOOP(v, nv) {
+        if (sizeof(T) == 8) {
+            double* xt = (double*)a.xt + b.off * R;
+#pragma unroll
+            for (int k = 0; k < R; ++k) xt[v * R + k] = (double)x[v * R + k];
+        }
+        if (m[v] == 0) {
+            const Nb n = neighbours(v, b.nx, b.ny, b.nz);
+            T w[6];
+            bool sm[6];
+            T xn[6][R], xv[R];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                sm[q] = m[n.u[q]] != 0;
+#pragma unroll
+                for (int k = 0; k < R; ++k) xn[q][k] = (T)x[n.u[q] * R + k];
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) xv[k] = (T)x[v * R + k];
+            const T d = stencil_weights<T>(g, v, n, W, w);
+            const T id = drecip(d);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                T acc = T(0), accm = T(0);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    acc += w[q] * xn[q][k];
+                    accm += w[q] * (sm[q] ? xn[q][k] : T(0));
+                }
+                const T rv = acc - d * xv[k];
+                const T zv = rv * id;
+                r[v * R + k] = rv;
+                z[v * R + k] = zv;
+                p0[v * R + k] = T(0);
+                p1[v * R + k] = T(0);
+                s[k] += (double)rv * (double)zv;
+                s[R + k] += (double)rv * (double)rv;
+                s[2 * R + k] += (double)accm * (double)accm;
+            }
+            s[3 * R] += 1.0;
+        } else {
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                r[v * R + k] = T(0);
+                z[v * R + k] = T(0);
+                p0[v * R + k] = T(0);
+                p1[v * R + k] = T(0);
+            }
+            s[3 * R + 1] += 1.0;
+        }
+    }
+    DomCtl* ctl = (DomCtl*)a.dom;
+    if (!last_wg_sum<3 * R + 2>(s, ctl, a.dom_part, red)) return;
+    if (threadIdx.x == 0) {
+        BoxState& st = a.state[ib];
+        const double nU = s[3 * R], nM = s[3 * R + 1];
+        bool allzero = true;
+        for (int k = 0; k < 3; ++k) st.rz[k] = st.rr[k] = st.bb[k] = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const bool zero = s[2 * R + k] == 0.0;
+            allzero = allzero && zero;
+            // ||b|| = 0 for an rhs: its solution is x_U = 0 (k_dzero), no iterations
+            st.rz[k] = zero ? 0.0 : s[k];
+            st.rr[k] = zero ? 0.0 : s[R + k];
+            st.bb[k] = s[2 * R + k];
+        }
+        st.nU = nU;
+        st.nM = nM;
+        st.rel = 0.0;
+        st.true_rel = 0.0;
+        st.iters = st.refine_steps = st.refine_iters = 0;
+        st.status = nM == 0.0 ? RW_ST_NO_DIRICHLET : RW_ST_CONVERGED;
+        st.active = (nM > 0.0 && nU > 0.0 && !allzero) ? 1 : 0;
+        st.pending = 0;
+    }
+}
+
+// Right-hand sides with ||b|| = 0: x_U = r = z = 0 for them.
+template <typename T, int R>
+__global__ __launch_bounds__(kDomThreads) void k_dzero(SolveArgs a, int ib) {
+    const BoxState& st = a.state[ib];
+    if (!(st.nM > 0.0 && st.nU > 0.0)) return;
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < R; ++k) any = any || st.bb[k] == 0.0;
+    if (!any) return;
+    const BrickDev b = a.bricks[ib];
+    const int nv = b.nx * b.ny * b.nz;
+    T* xt = (sizeof(T) == 8 ? (T*)a.xt : (T*)a.x) + b.off * R;
+    T* r = (T*)a.r + b.off * R;
+    T* z = (T*)a.z + b.off * R;
+    RW_DOM_LOOP(v, nv) {
+        if (a.mask[b.off + v] != 0) continue;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (st.bb[k] == 0.0) {
+                xt[v * R + k] = T(0);
+                r[v * R + k] = T(0);
+                z[v * R + k] = T(0);
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi-PCG
+// ---------------------------------------------------------------------------
+
+// Ticket counter to 0 (device memory is not cleared when allocated).
+__global__ void k_dreset(SolveArgs a) {
+    if (threadIdx.x == 0) ((DomCtl*)a.dom)->ticket = 0u;
+}
+
+// The PCG kernels spread a box over at most kDomPcgWG workgroups, kVpt voxels
+// per thread and pass.  Each launch starts by adding the previous launch's
+// per-workgroup partials in workgroup order (every workgroup gets the same
+// scalars; kernel boundaries make the partials visible); workgroup 0 records
+// the scalar state.
+constexpr int kDomPcgWG = 1024;
+constexpr int kVpt = 2;
+
+// Sum of per-workgroup partials part[w * stride + k], w < G, k < N, in order.
+template <int N>
+__device__ __forceinline__ void sum_partials(const double* part, int stride, int G, double (&out)[N], double* red) {
     double v[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) v[k] = 0.0;
-    for (int w = threadIdx.x; w < G; w += kDomThreads)
+    for (int w = threadIdx.x; w < G; w += kDomThreads) {
 #pragma unroll
-        for (int k = 0; k < N; ++k) v[k] += part[w * N + k];
-    dom_block_sum<N>(v, red);
+        for (int k = 0; k < N; ++k) v[k] += part[w * stride + k];
+    }
+    wg_sum<N>(v, red);
 #pragma unroll
     for (int k = 0; k < N; ++k) out[k] = v[k];
 }
 
-// Stencil of voxel v (box-relative) on an operand given by op(u): returns d and acc.
-template <typename T, int N, typename Op>
-__device__ __forceinline__ void dom_stencil(const BrickDev& b, const float* __restrict__ g, int v, double beta,
-                                            double eps, Op op, T& d, T (&acc)[N]) {
-    const int nx = b.nx, nxy = b.nx * b.ny;
-    const int k = v / nxy, r0 = v - k * nxy, j = r0 / nx, i = r0 - j * nx;
-    const T gc = (T)g[v];
-    d = T(0);
-#pragma unroll
-    for (int a = 0; a < N; ++a) acc[a] = T(0);
-    auto nb = [&](int u) {
-        const T w = dom_weight<T>(gc, (T)g[u], beta, eps);
-        d += w;
-        T o[N];
-        op(u, o);
-#pragma unroll
-        for (int a = 0; a < N; ++a) acc[a] += w * o[a];
-    };
-    if (i > 0) nb(v - 1);
-    if (i + 1 < nx) nb(v + 1);
-    if (j > 0) nb(v - nx);
-    if (j + 1 < b.ny) nb(v + nx);
-    if (k > 0) nb(v - nxy);
-    if (k + 1 < b.nz) nb(v + nxy);
-}
+// Slot layout of the PCG partials: A (sigma) [G][3], B (r.z, ||r||^2) [G][6].
+__device__ __forceinline__ double* part_a(const SolveArgs& a) { return a.dom_part; }
+__device__ __forceinline__ double* part_b(const SolveArgs& a) { return a.dom_part + kDomPcgWG * 3; }
 
-__device__ __forceinline__ bool dom_finite(double v) { return isfinite(v); }
-__device__ __forceinline__ float dom_recip(float d) { return __builtin_amdgcn_rcpf(d); }
-__device__ __forceinline__ double dom_recip(double d) { return 1.0 / d; }
-
-// Start: state slot 1 (read by A(0)) from the box's BoxState.
+// State for A(0) (slot 1, and slot 0) from the box state (init or check).
 template <int R>
-__global__ void k_dom_start(const BoxState* st, DomState* ds) {
+__global__ void k_dstart(SolveArgs a, int ib) {
     if (threadIdx.x != 0) return;
+    const BoxState& st = a.state[ib];
+    DomCtl* ctl = (DomCtl*)a.dom;
     DomState s{};
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        s.rz[k] = st->rz[k];
-        s.rr[k] = st->rr[k];
+        s.rz[k] = st.rz[k];
+        s.rr[k] = st.rr[k];
     }
-    s.all_done = st->active ? 0 : 1;
-    ds[1] = s;
-    ds[0] = s;
+    s.all_done = st.active ? 0 : 1;
+    ctl->s[0] = s;
+    ctl->s[1] = s;
+    ctl->ticket = 0u;
 }
 
+// A(it): scalars of iteration it from B(it-1)'s partials (A(0): from the
+// start state), convergence test; then p_new = z + beta p_old and the
+// partials of sigma = p_new . L_UU p_new.
 template <typename T, int R>
-__global__ __launch_bounds__(kDomThreads) void k_dom_A(SolveArgs a, int ib, int it, double tol, int max_iter,
-                                                       const T* __restrict__ z, const T* __restrict__ pold,
-                                                       T* __restrict__ pnew) {
-    __shared__ double red[(kDomThreads / 64) * 2 * 3];
-    DomState* ds = (DomState*)a.dom;
-    const DomState* prev = ds + ((it + 1) & 1);
-    DomState* out = ds + (it & 1);
+__global__ __launch_bounds__(kDomThreads) void k_dA(SolveArgs a, int ib, int it, double tol, int max_iter,
+                                                    const T* __restrict__ z, const T* __restrict__ pold,
+                                                    T* __restrict__ pnew) {
+    __shared__ double red[kDomWaves * kDomPart];
+    DomCtl* ctl = (DomCtl*)a.dom;
+    const volatile DomState* prev = &ctl->s[(it + 1) & 1];
+    DomState* out = &ctl->s[it & 1];
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (prev->all_done) {
-        if (lead) *out = *prev;
+        if (lead) *out = *(const DomState*)prev;
         return;
     }
-    const BrickDev b = a.bricks[ib];
-    const int G = gridDim.x;
     double rz[R], rr[R];
     if (it == 0) {
 #pragma unroll
@@ -145,154 +401,203 @@ __global__ __launch_bounds__(kDomThreads) void k_dom_A(SolveArgs a, int ib, int 
         }
     } else {
         double s2[2 * R];
-        dom_sum_partials<2 * R>(a.dom_partB, G, s2, red);
+        sum_partials<2 * R>(part_b(a), 6, gridDim.x, s2, red);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             rz[k] = s2[k];
             rr[k] = s2[R + k];
         }
     }
+    const double* bb = a.state[ib].bb;
     bool all = true;
     int flags = prev->flags;
-    double be64[R];
+    T be[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const bool was = it > 0 && prev->done[k];
-        const bool dn = was || rr[k] <= tol * tol * a.state[ib].bb[k];
-        const double prz = prev->rz[k];
-        be64[k] = (it == 0 || dn) ? 0.0 : rz[k] / prz;
-        if (!dom_finite(rz[k]) || !dom_finite(rr[k])) flags |= 1;
+        const double prz = prev->rz[k], prr = prev->rr[k];
+        if (!was && (!fin(rz[k]) || !fin(rr[k]))) flags |= 1;
         if (was) {
             rz[k] = prz;
-            rr[k] = prev->rr[k];
+            rr[k] = prr;
         }
+        const bool dn = was || rr[k] <= tol * tol * bb[k];
+        const double bk = (it == 0 || dn) ? 0.0 : rz[k] / prz;
+        be[k] = (T)bk;
         all = all && dn;
         if (lead) {
             out->done[k] = dn ? 1 : 0;
-            out->beta[k] = be64[k];
-        }
-    }
-    if (!all && it >= max_iter) flags |= 2;
-    const int fin = (all || flags) ? 1 : 0;
-    if (lead) {
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
+            out->beta[k] = bk;
             out->rz[k] = rz[k];
             out->rr[k] = rr[k];
         }
-        out->all_done = fin;
+    }
+    if (!all && it >= max_iter) flags |= 2;
+    const int fin_ = (all || flags) ? 1 : 0;
+    if (lead) {
+        out->all_done = fin_;
         out->iters = it;
         out->flags = flags;
     }
-    if (fin) return;
+    if (fin_) return;
+    const BrickDev b = a.bricks[ib];
+    const int nv = b.nx * b.ny * b.nz;
+    const DWeight<T> W(a.beta, a.eps);
     const T* zb = z + b.off * R;
     const T* pb = pold + b.off * R;
-    T* nbp = pnew + b.off * R;
     const float* gb = a.g + b.off;
     const uint8_t* mb = a.mask + b.off;
-    const int nv = b.nx * b.ny * b.nz;
-    T be[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) be[k] = (T)be64[k];
+    T* nb = pnew + b.off * R;
     double sig[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) sig[k] = 0.0;
-    for (int v = blockIdx.x * kDomThreads + threadIdx.x; v < nv; v += G * kDomThreads) {
-        if (mb[v] != 0) continue;
-        T d, acc[R];
-        dom_stencil<T, R>(b, gb, v, a.beta, a.eps,
-                          [&](int u, T (&o)[R]) {
+    const int stride = gridDim.x * kDomThreads;
+    for (int v0 = blockIdx.x * kDomThreads + threadIdx.x; v0 < nv; v0 += kVpt * stride) {
+        // all loads of the kVpt voxels first (clamped in-box indices), then compute
+        int vv[kVpt];
+        bool use[kVpt];
+        Nb n[kVpt];
+        T pn[kVpt][6][R], pv[kVpt][R], w[kVpt][6], d[kVpt];
 #pragma unroll
-                              for (int k = 0; k < R; ++k) o[k] = zb[u * R + k] + be[k] * pb[u * R + k];
-                          },
-                          d, acc);
+        for (int j = 0; j < kVpt; ++j) {
+            const int v = v0 + j * stride;
+            vv[j] = v < nv ? v : nv - 1;
+            use[j] = v < nv && mb[vv[j]] == 0;
+            n[j] = neighbours(vv[j], b.nx, b.ny, b.nz);
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const T pv = zb[v * R + k] + be[k] * pb[v * R + k];
-            const T q = d * pv - acc[k];
-            sig[k] += (double)pv * (double)q;
-            nbp[v * R + k] = pv;
+            for (int q = 0; q < 6; ++q)
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    pn[j][q][k] = zb[n[j].u[q] * R + k] + be[k] * pb[n[j].u[q] * R + k];
+#pragma unroll
+            for (int k = 0; k < R; ++k) pv[j][k] = zb[vv[j] * R + k] + be[k] * pb[vv[j] * R + k];
+            d[j] = stencil_weights<T>(gb, vv[j], n[j], W, w[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kVpt; ++j) {
+            if (!use[j]) continue;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                T acc = T(0);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) acc += w[j][q] * pn[j][q][k];
+                const T qv = d[j] * pv[j][k] - acc;
+                sig[k] += (double)pv[j][k] * (double)qv;
+                nb[vv[j] * R + k] = pv[j][k];
+            }
         }
     }
-    dom_block_sum<R>(sig, red);
-    if (threadIdx.x == 0)
+    wg_sum<R>(sig, red);
+    if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < R; ++k) a.dom_partA[blockIdx.x * R + k] = sig[k];
+        for (int k = 0; k < R; ++k) part_a(a)[blockIdx.x * 3 + k] = sig[k];
+    }
 }
 
+// B(it): alpha from A(it)'s partials (breakdown test); x += alpha p,
+// r -= alpha L_UU p, z = r / d and the partials of r.z, ||r||^2.
 template <typename T, int R, typename XT>
-__global__ __launch_bounds__(kDomThreads) void k_dom_B(SolveArgs a, int ib, int it, XT* __restrict__ xt,
-                                                       const T* __restrict__ p, T* __restrict__ r, T* __restrict__ z) {
-    __shared__ double red[(kDomThreads / 64) * 2 * 3];
-    DomState* ds = (DomState*)a.dom;
-    DomState cur = ds[it & 1];
-    if (cur.all_done) return;
-    const BrickDev b = a.bricks[ib];
-    const int G = gridDim.x;
+__global__ __launch_bounds__(kDomThreads) void k_dB(SolveArgs a, int ib, int it, XT* xt, const T* __restrict__ p) {
+    __shared__ double red[kDomWaves * kDomPart];
+    DomCtl* ctl = (DomCtl*)a.dom;
+    const volatile DomState* cur = &ctl->s[it & 1];
+    if (cur->all_done) return;
     double sig[R];
-    dom_sum_partials<R>(a.dom_partA, G, sig, red);
+    sum_partials<R>(part_a(a), 3, gridDim.x, sig, red);
     T al[R];
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        const double alpha = cur.done[k] ? 0.0 : cur.rz[k] / sig[k];
-        if (!cur.done[k] && (!(sig[k] > 0.0) || !dom_finite(alpha))) bad = true;
-        al[k] = bad ? T(0) : (T)alpha;
+        const bool dn = cur->done[k];
+        const double alpha = dn ? 0.0 : cur->rz[k] / sig[k];
+        if (!dn && (!(sig[k] > 0.0) || !fin(alpha))) bad = true;
+        al[k] = (T)alpha;
     }
     if (bad) {
-        // breakdown: record and stop (x keeps the last finite iterate)
+        // breakdown: stop with the current iterate
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            cur.flags |= 1;
-            cur.all_done = 1;
-            ds[it & 1] = cur;
-            ds[(it + 1) & 1] = cur;
+            DomState s = *(const DomState*)cur;
+            s.flags |= 1;
+            s.all_done = 1;
+            ctl->s[it & 1] = s;
+            ctl->s[(it + 1) & 1] = s;
         }
         return;
     }
+    const BrickDev b = a.bricks[ib];
+    const int nv = b.nx * b.ny * b.nz;
+    const DWeight<T> W(a.beta, a.eps);
     const T* pb = p + b.off * R;
-    T* rb = r + b.off * R;
-    T* zb = z + b.off * R;
+    T* rb = (T*)a.r + b.off * R;
+    T* zb = (T*)a.z + b.off * R;
     XT* xb = xt + b.off * R;
     const float* gb = a.g + b.off;
     const uint8_t* mb = a.mask + b.off;
-    const int nv = b.nx * b.ny * b.nz;
-    double s2[2 * R];
+    double arz[R], arr[R];
 #pragma unroll
-    for (int k = 0; k < 2 * R; ++k) s2[k] = 0.0;
-    for (int v = blockIdx.x * kDomThreads + threadIdx.x; v < nv; v += G * kDomThreads) {
-        if (mb[v] != 0) continue;
-        T d, acc[R];
-        dom_stencil<T, R>(b, gb, v, a.beta, a.eps,
-                          [&](int u, T (&o)[R]) {
+    for (int k = 0; k < R; ++k) arz[k] = arr[k] = 0.0;
+    const int stride = gridDim.x * kDomThreads;
+    for (int v0 = blockIdx.x * kDomThreads + threadIdx.x; v0 < nv; v0 += kVpt * stride) {
+        int vv[kVpt];
+        bool use[kVpt];
+        Nb n[kVpt];
+        T pn[kVpt][6][R], pv[kVpt][R], rv0[kVpt][R], xv0[kVpt][R], w[kVpt][6], d[kVpt];
 #pragma unroll
-                              for (int k = 0; k < R; ++k) o[k] = pb[u * R + k];
-                          },
-                          d, acc);
-        const T id = dom_recip(d);
+        for (int j = 0; j < kVpt; ++j) {
+            const int v = v0 + j * stride;
+            vv[j] = v < nv ? v : nv - 1;
+            use[j] = v < nv && mb[vv[j]] == 0;
+            n[j] = neighbours(vv[j], b.nx, b.ny, b.nz);
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const T pv = pb[v * R + k];
-            const T q = d * pv - acc[k];
-            xb[v * R + k] = (XT)((T)xb[v * R + k] + al[k] * pv);
-            const T rv = rb[v * R + k] - al[k] * q;
-            const T zv = rv * id;
-            rb[v * R + k] = rv;
-            zb[v * R + k] = zv;
-            s2[k] += (double)rv * (double)zv;
-            s2[R + k] += (double)rv * (double)rv;
+            for (int q = 0; q < 6; ++q)
+#pragma unroll
+                for (int k = 0; k < R; ++k) pn[j][q][k] = pb[n[j].u[q] * R + k];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                pv[j][k] = pb[vv[j] * R + k];
+                rv0[j][k] = rb[vv[j] * R + k];
+                xv0[j][k] = (T)xb[vv[j] * R + k];
+            }
+            d[j] = stencil_weights<T>(gb, vv[j], n[j], W, w[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kVpt; ++j) {
+            if (!use[j]) continue;
+            const T id = drecip(d[j]);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                T acc = T(0);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) acc += w[j][q] * pn[j][q][k];
+                const T qv = d[j] * pv[j][k] - acc;
+                const T rv = rv0[j][k] - al[k] * qv;
+                const T zv = rv * id;
+                xb[vv[j] * R + k] = (XT)(xv0[j][k] + al[k] * pv[j][k]);
+                rb[vv[j] * R + k] = rv;
+                zb[vv[j] * R + k] = zv;
+                arz[k] += (double)rv * (double)zv;
+                arr[k] += (double)rv * (double)rv;
+            }
         }
     }
-    dom_block_sum<2 * R>(s2, red);
-    if (threadIdx.x == 0)
+    double s2[2 * R];
 #pragma unroll
-        for (int k = 0; k < 2 * R; ++k) a.dom_partB[blockIdx.x * 2 * R + k] = s2[k];
+    for (int k = 0; k < R; ++k) {
+        s2[k] = arz[k];
+        s2[R + k] = arr[k];
+    }
+    wg_sum<2 * R>(s2, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 2 * R; ++k) part_b(a)[blockIdx.x * 6 + k] = s2[k];
+    }
 }
 
-// End: final scalars back into the box's BoxState (stats and the next phases).
+// Final scalars into the box state (as the per-box PCG kernel leaves it).
 template <int R>
-__global__ void k_dom_end(SolveArgs a, int ib, int slot, int corr) {
+__global__ void k_dend(SolveArgs a, int ib, int slot, int corr) {
     if (threadIdx.x != 0) return;
-    const DomState s = ((DomState*)a.dom)[slot];
+    const DomState s = ((DomCtl*)a.dom)->s[slot];
     BoxState& st = a.state[ib];
     if (!st.active) return;
 #pragma unroll
@@ -315,59 +620,283 @@ __global__ void k_dom_end(SolveArgs a, int ib, int slot, int corr) {
     st.pending = corr && !(s.flags & 1) ? 1 : 0;
 }
 
-// Scratch layout: two DomState slots (256 B), partials A [kDomMaxWG][3],
-// partials B [kDomMaxWG][6].
-size_t domain_scratch_bytes() { return 256 + (size_t)kDomMaxWG * 9 * sizeof(double); }
-
-void domain_bind(SolveArgs& a, void* scratch) {
-    static_assert(2 * sizeof(DomState) <= 256, "DomState slots exceed their scratch");
-    char* c = (char*)scratch;
-    a.dom = c;
-    a.dom_partA = (double*)(c + 256);
-    a.dom_partB = a.dom_partA + kDomMaxWG * 3;
+// ---------------------------------------------------------------------------
+// FP64 true residual r64 = b - L_UU x with FP64 weights, of xs (float x or
+// double x64).  kMode 0 (check): r <- (float)r64; the last workgroup takes
+// the refinement decision.  kMode 1 (FP64 finish): x <- (float)x64 on U; the
+// last workgroup stores the true relative residual.
+// ---------------------------------------------------------------------------
+template <int R, typename XS, int kMode>
+__global__ __launch_bounds__(kDomThreads) void k_dresid(SolveArgs a, int ib, const XS* __restrict__ xs,
+                                                        int may_refine, int refine64) {
+    __shared__ double red[kDomWaves * kDomPart];
+    const BoxState& st0 = a.state[ib];
+    const bool solved = st0.nM > 0.0 && st0.nU > 0.0 && st0.status != RW_ST_NONFINITE;
+    const BrickDev b = a.bricks[ib];
+    const int nv = b.nx * b.ny * b.nz;
+    const uint8_t* m = a.mask + b.off;
+    const XS* x = xs + b.off * R;
+    if (kMode == 1) {
+        RW_DOM_LOOP(v, nv) {
+            if (m[v] != 0) continue;
+#pragma unroll
+            for (int k = 0; k < R; ++k) a.x[(b.off + v) * R + k] = (float)x[v * R + k];
+        }
+    }
+    if (!solved) {
+        if (kMode == 0 && blockIdx.x == 0 && threadIdx.x == 0) a.state[ib].active = 0;
+        return;
+    }
+    double q[2 * R];
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) q[k] = 0.0;
+    const DWeight<double> W(a.beta, a.eps);
+    RW_DOM_LOOP(v, nv) {
+        if (m[v] != 0) continue;
+        const Nb n = neighbours(v, b.nx, b.ny, b.nz);
+        bool sm[6];
+        double xn[6][R], xv[R];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            sm[j] = m[n.u[j]] != 0;
+#pragma unroll
+            for (int k = 0; k < R; ++k) xn[j][k] = (double)x[n.u[j] * R + k];
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) xv[k] = (double)x[v * R + k];
+        double w[6];
+        const double d = stencil_weights<double>(a.g + b.off, v, n, W, w);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            double acc = 0.0, accm = 0.0;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                acc += w[j] * xn[j][k];
+                accm += w[j] * (sm[j] ? xn[j][k] : 0.0);
+            }
+            const double rv = acc - d * xv[k];
+            q[k] += rv * rv;
+            q[R + k] += accm * accm;
+            if (kMode == 0) ((float*)a.r)[(b.off + v) * R + k] = (float)rv;
+        }
+    }
+    if (!last_wg_sum<2 * R>(q, (DomCtl*)a.dom, a.dom_part, red)) return;
+    if (threadIdx.x != 0) return;
+    BoxState& st = a.state[ib];
+    double tr = 0.0;
+    bool ok = true;
+    const double target = refine64 ? a.refine_tol : a.tol * a.stall_ratio;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if (q[R + k] > 0.0) tr = fmax(tr, sqrt(q[k] / q[R + k]));
+        if (q[k] > target * target * q[R + k]) ok = false;
+    }
+    st.true_rel = tr;
+    if (kMode == 0) {
+        const bool refine = may_refine && !ok && st.refine_steps < a.refine_max;
+        st.active = refine ? 1 : 0;
+        if (!may_refine && st.refine_steps > 0 && st.status == RW_ST_CONVERGED)
+            st.status = ok ? RW_ST_REFINED : RW_ST_STALLED;
+    }
 }
 
-// One box, launch index ib, host copy of its descriptor bd.
+// Correction system L_UU d = r64 (r holds r64 in FP32): z = r/d, p = 0, d = 0;
+// seeded voxels all 0; ||b||^2 = ||r||^2.  Only when the check set `active`.
+template <int R>
+__global__ __launch_bounds__(kDomThreads) void k_dexplicit(SolveArgs a, int ib) {
+    __shared__ double red[kDomWaves * kDomPart];
+    if (!a.state[ib].active) return;
+    const BrickDev b = a.bricks[ib];
+    const int nv = b.nx * b.ny * b.nz;
+    double e[2 * R];
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) e[k] = 0.0;
+    const DWeight<float> W(a.beta, a.eps);
+    float* r = (float*)a.r + b.off * R;
+    float* z = (float*)a.z + b.off * R;
+    float* p0 = (float*)a.p0 + b.off * R;
+    float* p1 = (float*)a.p1 + b.off * R;
+    float* dc = a.dcorr + b.off * R;
+    RW_DOM_LOOP(v, nv) {
+        if (a.mask[b.off + v] == 0) {
+            const Nb n = neighbours(v, b.nx, b.ny, b.nz);
+            float w[6];
+            const float id = drecip(stencil_weights<float>(a.g + b.off, v, n, W, w));
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const float rv = r[v * R + k];
+                const float zv = rv * id;
+                z[v * R + k] = zv;
+                p0[v * R + k] = 0.0f;
+                p1[v * R + k] = 0.0f;
+                dc[v * R + k] = 0.0f;
+                e[k] += (double)rv * (double)zv;
+                e[R + k] += (double)rv * (double)rv;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                r[v * R + k] = 0.0f;
+                z[v * R + k] = 0.0f;
+                p0[v * R + k] = 0.0f;
+                p1[v * R + k] = 0.0f;
+                dc[v * R + k] = 0.0f;
+            }
+        }
+    }
+    if (!last_wg_sum<2 * R>(e, (DomCtl*)a.dom, a.dom_part, red)) return;
+    if (threadIdx.x == 0) {
+        BoxState& st = a.state[ib];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            st.rz[k] = e[k];
+            st.rr[k] = st.bb[k] = e[R + k];
+        }
+    }
+}
+
+// x (MIXED) or x64 (MIXED_REFINE) += d on U when a correction is pending.
+template <int R, bool kRefine64>
+__global__ __launch_bounds__(kDomThreads) void k_dapply(SolveArgs a, int ib) {
+    if (!a.state[ib].pending) return;
+    const BrickDev b = a.bricks[ib];
+    const int nv = b.nx * b.ny * b.nz;
+    RW_DOM_LOOP(v, nv) {
+        if (a.mask[b.off + v] != 0) continue;
+        const int64_t o = (b.off + v) * R;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (kRefine64) a.x64[o + k] += (double)a.dcorr[o + k];
+            else a.x[o + k] += a.dcorr[o + k];
+        }
+    }
+    if (!last_wg((DomCtl*)a.dom)) return;
+    if (threadIdx.x == 0) {
+        BoxState& st = a.state[ib];
+        st.refine_steps += 1;
+        st.pending = 0;
+    }
+}
+
+// to64: x64 = x on every voxel; else x = (float)x64 on U.
+template <int R>
+__global__ __launch_bounds__(kDomThreads) void k_dcopy64(SolveArgs a, int ib, int to64) {
+    const BrickDev b = a.bricks[ib];
+    const int nv = b.nx * b.ny * b.nz;
+    RW_DOM_LOOP(v, nv) {
+        const int64_t o = (b.off + v) * R;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (to64) a.x64[o + k] = (double)a.x[o + k];
+            else if (a.mask[b.off + v] == 0) a.x[o + k] = (float)a.x64[o + k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+static unsigned dom_grid(const BrickDev& bd) {
+    const int64_t nv = (int64_t)bd.nx * bd.ny * bd.nz;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kDomMaxWG, (nv + kDomThreads - 1) / kDomThreads));
+}
+
+template <typename T, int R>
+hipError_t domain_init(const SolveArgs& a, int ib, const BrickDev& bd, hipStream_t s) {
+    const unsigned G = dom_grid(bd);
+    hipLaunchKernelGGL(k_dreset, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_dinit<T, R>), dim3(G), dim3(kDomThreads), 0, s, a, ib);
+    hipLaunchKernelGGL((k_dzero<T, R>), dim3(G), dim3(kDomThreads), 0, s, a, ib);
+    return hipGetLastError();
+}
+
 template <typename T, int R, typename XT>
 hipError_t domain_pcg(const SolveArgs& a, int ib, const BrickDev& bd, XT* xt, int corr, hipStream_t s) {
     const int64_t nv = (int64_t)bd.nx * bd.ny * bd.nz;
-    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(kDomMaxWG, (nv + 2 * kDomThreads - 1) / (2 * kDomThreads)));
+    const unsigned G = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>(kDomPcgWG, (nv + kVpt * kDomThreads - 1) / (kVpt * kDomThreads)));
     const double tol = corr ? a.inner_tol : a.tol;
-    T* r = (T*)a.r;
     T* z = (T*)a.z;
     T* p0 = (T*)a.p0;
     T* p1 = (T*)a.p1;
-    hipLaunchKernelGGL(k_dom_start<R>, dim3(1), dim3(64), 0, s, a.state + ib, (DomState*)a.dom);
-    DomState* dsp = (DomState*)a.dom;
+    DomCtl* ctl = (DomCtl*)a.dom;
+    hipLaunchKernelGGL(k_dstart<R>, dim3(1), dim3(64), 0, s, a, ib);
+    auto finished = [&](int slot, bool* out) -> hipError_t {
+        int32_t f = 0;
+        hipError_t e = hipMemcpyAsync(&f, &ctl->s[slot].all_done, sizeof(f), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        *out = f != 0;
+        return e;
+    };
     const int poll = 16;
     int it = 0;
-    for (; it <= a.max_iter; ++it) {
+    for (;; ++it) {
         T* pold = (it & 1) ? p1 : p0;
         T* pnew = (it & 1) ? p0 : p1;
-        hipLaunchKernelGGL((k_dom_A<T, R>), dim3(G), dim3(kDomThreads), 0, s, a, ib, it, tol, a.max_iter, z, pold,
+        hipLaunchKernelGGL((k_dA<T, R>), dim3(G), dim3(kDomThreads), 0, s, a, ib, it, tol, a.max_iter, z, pold,
                            pnew);
-        hipLaunchKernelGGL((k_dom_B<T, R, XT>), dim3(G), dim3(kDomThreads), 0, s, a, ib, it, xt, pnew, r, z);
+        if (it >= a.max_iter) break;  // A(max_iter) records the final state
+        hipLaunchKernelGGL((k_dB<T, R, XT>), dim3(G), dim3(kDomThreads), 0, s, a, ib, it, xt, (const T*)pnew);
         if (it == 0 || (it + 1) % poll == 0) {
-            int32_t done = 0;
-            hipError_t e = hipMemcpyAsync(&done, &dsp[it & 1].all_done, sizeof(done), hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            bool done = false;
+            hipError_t e = finished(it & 1, &done);
             if (e != hipSuccess) return e;
             if (done) break;
         }
     }
-    if (it > a.max_iter) it = a.max_iter;
-    // the state slot of the last A launch holds the final scalars
-    hipLaunchKernelGGL(k_dom_end<R>, dim3(1), dim3(64), 0, s, a, ib, it & 1, corr);
+    // slot it & 1 holds the final scalars (written by A(it), or carried there)
+    hipLaunchKernelGGL(k_dend<R>, dim3(1), dim3(64), 0, s, a, ib, it & 1, corr);
     return hipGetLastError();
 }
 
-#define RW_DOM_INST(T, R, XT) \
-    template hipError_t domain_pcg<T, R, XT>(const SolveArgs&, int, const BrickDev&, XT*, int, hipStream_t);
-RW_DOM_INST(float, 1, float)
-RW_DOM_INST(float, 2, float)
-RW_DOM_INST(float, 3, float)
-RW_DOM_INST(double, 1, double)
-RW_DOM_INST(double, 2, double)
-RW_DOM_INST(double, 3, double)
+template <int R, bool kRefine64>
+hipError_t domain_check(const SolveArgs& a, int ib, const BrickDev& bd, int may_refine, hipStream_t s) {
+    const unsigned G = dom_grid(bd);
+    if (kRefine64)
+        hipLaunchKernelGGL((k_dresid<R, double, 0>), dim3(G), dim3(kDomThreads), 0, s, a, ib,
+                           (const double*)a.x64, may_refine, 1);
+    else
+        hipLaunchKernelGGL((k_dresid<R, float, 0>), dim3(G), dim3(kDomThreads), 0, s, a, ib, (const float*)a.x,
+                           may_refine, 0);
+    if (may_refine) hipLaunchKernelGGL((k_dexplicit<R>), dim3(G), dim3(kDomThreads), 0, s, a, ib);
+    return hipGetLastError();
+}
+
+template <int R, bool kRefine64>
+hipError_t domain_apply(const SolveArgs& a, int ib, const BrickDev& bd, hipStream_t s) {
+    hipLaunchKernelGGL((k_dapply<R, kRefine64>), dim3(dom_grid(bd)), dim3(kDomThreads), 0, s, a, ib);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t domain_copy64(const SolveArgs& a, int ib, const BrickDev& bd, int to64, hipStream_t s) {
+    hipLaunchKernelGGL((k_dcopy64<R>), dim3(dom_grid(bd)), dim3(kDomThreads), 0, s, a, ib, to64);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t domain_finish64(const SolveArgs& a, int ib, const BrickDev& bd, hipStream_t s) {
+    hipLaunchKernelGGL((k_dresid<R, double, 1>), dim3(dom_grid(bd)), dim3(kDomThreads), 0, s, a, ib,
+                       (const double*)a.xt, 0, 0);
+    return hipGetLastError();
+}
+
+#define RW_DOM_INST_R(R)                                                                                    \
+    template hipError_t domain_init<float, R>(const SolveArgs&, int, const BrickDev&, hipStream_t);         \
+    template hipError_t domain_init<double, R>(const SolveArgs&, int, const BrickDev&, hipStream_t);        \
+    template hipError_t domain_pcg<float, R, float>(const SolveArgs&, int, const BrickDev&, float*, int,    \
+                                                    hipStream_t);                                           \
+    template hipError_t domain_pcg<double, R, double>(const SolveArgs&, int, const BrickDev&, double*, int, \
+                                                      hipStream_t);                                         \
+    template hipError_t domain_check<R, false>(const SolveArgs&, int, const BrickDev&, int, hipStream_t);   \
+    template hipError_t domain_check<R, true>(const SolveArgs&, int, const BrickDev&, int, hipStream_t);    \
+    template hipError_t domain_apply<R, false>(const SolveArgs&, int, const BrickDev&, hipStream_t);        \
+    template hipError_t domain_apply<R, true>(const SolveArgs&, int, const BrickDev&, hipStream_t);         \
+    template hipError_t domain_copy64<R>(const SolveArgs&, int, const BrickDev&, int, hipStream_t);         \
+    template hipError_t domain_finish64<R>(const SolveArgs&, int, const BrickDev&, hipStream_t);
+RW_DOM_INST_R(1)
+RW_DOM_INST_R(2)
+RW_DOM_INST_R(3)
 
 }  // namespace rwk

@@ -1015,9 +1015,10 @@ __device__ __forceinline__ Box box_of(const BrickDev& bd) {
 
 // Phase 1: Dirichlet init, per-box decision (no seed / no unknown / zero rhs).
 template <typename T, int R>
-__global__ __launch_bounds__(kThreads) void k_init(SolveArgs a) {
+__global__ __launch_bounds__(kThreads) void k_init(SolveArgs a, int base) {
+    const int ib = base + blockIdx.x;
     __shared__ double red[kWaves * 12];
-    const BrickDev bd = a.bricks[blockIdx.x];
+    const BrickDev bd = a.bricks[ib];
     const Box b = box_of(bd);
     const Weight<T> W = make_weight<T>(a.beta, a.eps);
     Vecs<T, R> V = vecs<T, R>(a);
@@ -1069,7 +1070,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SolveArgs a) {
             if (s[2 * R + k] == 0.0) s[k] = s[R + k] = 0.0;
     }
     if (threadIdx.x == 0) {
-        BoxState& st = a.state[blockIdx.x];
+        BoxState& st = a.state[ib];
         for (int k = 0; k < 3; ++k) st.rz[k] = st.rr[k] = st.bb[k] = 0.0;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -1143,15 +1144,16 @@ __global__ __launch_bounds__(kThreads) void k_pcg(SolveArgs a, XT* xt, int corr,
 // correction system L_UU d = r64 initialised (r <- r64, z, p, d = 0) and is
 // marked active for the next k_pcg(corr = 1).
 template <int R, bool kRefine64>
-__global__ __launch_bounds__(kThreads) void k_check(SolveArgs a, int may_refine) {
+__global__ __launch_bounds__(kThreads) void k_check(SolveArgs a, int may_refine, int base) {
+    const int ib = base + blockIdx.x;
     __shared__ double red[kWaves * 12];
-    BoxState& st = a.state[blockIdx.x];
+    BoxState& st = a.state[ib];
     const bool solved = st.nM > 0.0 && st.nU > 0.0 && st.status != RW_ST_NONFINITE;
     if (!solved) {
         if (threadIdx.x == 0) st.active = 0;
         return;
     }
-    const BrickDev bd = a.bricks[blockIdx.x];
+    const BrickDev bd = a.bricks[ib];
     const Box b = box_of(bd);
     Vecs<float, R> V = vecs<float, R>(a);
     double r2[R], b2[R], q[2 * R];
@@ -1207,10 +1209,11 @@ __global__ __launch_bounds__(kThreads) void k_check(SolveArgs a, int may_refine)
 
 // Phase 4: add the correction d to x (MIXED) or to x64 (MIXED_REFINE).
 template <int R, bool kRefine64>
-__global__ __launch_bounds__(kThreads) void k_apply(SolveArgs a) {
-    BoxState& st = a.state[blockIdx.x];
+__global__ __launch_bounds__(kThreads) void k_apply(SolveArgs a, int base) {
+    const int ib = base + blockIdx.x;
+    BoxState& st = a.state[ib];
     if (!st.pending) return;
-    const Box b = box_of(a.bricks[blockIdx.x]);
+    const Box b = box_of(a.bricks[ib]);
     each_voxel(b, [&](int64_t v) {
         if (a.mask[v] == 0) {
 #pragma unroll
@@ -1228,8 +1231,9 @@ __global__ __launch_bounds__(kThreads) void k_apply(SolveArgs a) {
 
 // Copy x into the FP64 accumulator (MIXED_REFINE start) or back (end).
 template <int R>
-__global__ __launch_bounds__(kThreads) void k_copy64(SolveArgs a, int to64) {
-    const Box b = box_of(a.bricks[blockIdx.x]);
+__global__ __launch_bounds__(kThreads) void k_copy64(SolveArgs a, int to64, int base) {
+    const int ib = base + blockIdx.x;
+    const Box b = box_of(a.bricks[ib]);
     each_voxel(b, [&](int64_t v) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -1241,10 +1245,11 @@ __global__ __launch_bounds__(kThreads) void k_copy64(SolveArgs a, int to64) {
 
 // FP64 path end: true residual of the FP64 solution (stats), x <- (float)x64.
 template <int R>
-__global__ __launch_bounds__(kThreads) void k_finish64(SolveArgs a) {
+__global__ __launch_bounds__(kThreads) void k_finish64(SolveArgs a, int base) {
+    const int ib = base + blockIdx.x;
     __shared__ double red[kWaves * 12];
-    BoxState& st = a.state[blockIdx.x];
-    const Box b = box_of(a.bricks[blockIdx.x]);
+    BoxState& st = a.state[ib];
+    const Box b = box_of(a.bricks[ib]);
     const double* xt = (const double*)a.xt;
     if (st.nM > 0.0 && st.nU > 0.0 && st.status != RW_ST_NONFINITE) {
         double r2[R], b2[R], q[2 * R];
@@ -1273,9 +1278,9 @@ __global__ __launch_bounds__(kThreads) void k_finish64(SolveArgs a) {
 
 // Last phase: stats in caller order, optional FP64 copy of the result.
 template <int R>
-__global__ __launch_bounds__(kThreads) void k_stats(SolveArgs a, int copy64) {
+__global__ __launch_bounds__(kThreads) void k_stats(SolveArgs a, int copy64, int copy_from) {
     const BrickDev bd = a.bricks[blockIdx.x];
-    if (copy64) {
+    if (copy64 && (int)blockIdx.x >= copy_from) {
         const Box b = box_of(bd);
         each_voxel(b, [&](int64_t v) {
 #pragma unroll
@@ -1419,38 +1424,68 @@ static hipError_t launch_pcg_c(const SolveArgs& a, int64_t n, XT* xt, int corr, 
                         : launch_pcg_plane<T, R, 4, XT>(a, n, n_big, xt, corr, lds, pp, s);
 }
 
+// Per-box phase kernels cover boxes [nd, n) with one workgroup each; the
+// domain boxes [0, nd) run the multi-workgroup phases one after another.
 template <int R>
 static hipError_t launch_mixed(const SolveArgs& a, int64_t n, const PlanePlan& pp, hipStream_t s, hipEvent_t* ev) {
-    const dim3 grid((unsigned)n), blk(kThreads);
-    hipLaunchKernelGGL((k_init<float, R>), grid, blk, 0, s, a);
+    const int nd = (int)pp.n_dom;
+    const dim3 grid((unsigned)(n - nd)), blk(kThreads);
+    const bool rest = n > nd;
+    const bool r64 = a.precision == RW_PREC_MIXED_REFINE;
+    if (rest) hipLaunchKernelGGL((k_init<float, R>), grid, blk, 0, s, a, nd);
+    for (int i = 0; i < nd; ++i) RW_TRY((domain_init<float, R>(a, i, pp.host[i], s)));
     if (ev) RW_TRY(hipEventRecord(ev[0], s));
     RW_TRY(launch_pcg_c<float, R, float>(a, n, a.x, 0, pp, s));
     if (ev) RW_TRY(hipEventRecord(ev[1], s));
-    const bool r64 = a.precision == RW_PREC_MIXED_REFINE;
-    if (r64) hipLaunchKernelGGL((k_copy64<R>), grid, blk, 0, s, a, 1);
-    for (int step = 0; step < a.refine_max; ++step) {
-        if (r64) hipLaunchKernelGGL((k_check<R, true>), grid, blk, 0, s, a, 1);
-        else hipLaunchKernelGGL((k_check<R, false>), grid, blk, 0, s, a, 1);
-        RW_TRY(launch_pcg_c<float, R, float>(a, n, a.dcorr, 1, pp, s));
-        if (r64) hipLaunchKernelGGL((k_apply<R, true>), grid, blk, 0, s, a);
-        else hipLaunchKernelGGL((k_apply<R, false>), grid, blk, 0, s, a);
+    if (r64) {
+        if (rest) hipLaunchKernelGGL((k_copy64<R>), grid, blk, 0, s, a, 1, nd);
+        for (int i = 0; i < nd; ++i) RW_TRY(domain_copy64<R>(a, i, pp.host[i], 1, s));
     }
-    if (r64) hipLaunchKernelGGL((k_check<R, true>), grid, blk, 0, s, a, 0);
-    else hipLaunchKernelGGL((k_check<R, false>), grid, blk, 0, s, a, 0);
-    if (r64) hipLaunchKernelGGL((k_copy64<R>), grid, blk, 0, s, a, 0);
-    hipLaunchKernelGGL((k_stats<R>), grid, blk, 0, s, a, (a.want_x64 && !r64) ? 1 : 0);
+    auto check = [&](int may_refine) -> hipError_t {
+        if (rest) {
+            if (r64) hipLaunchKernelGGL((k_check<R, true>), grid, blk, 0, s, a, may_refine, nd);
+            else hipLaunchKernelGGL((k_check<R, false>), grid, blk, 0, s, a, may_refine, nd);
+        }
+        for (int i = 0; i < nd; ++i)
+            RW_TRY(r64 ? domain_check<R, true>(a, i, pp.host[i], may_refine, s)
+                       : domain_check<R, false>(a, i, pp.host[i], may_refine, s));
+        return hipGetLastError();
+    };
+    for (int step = 0; step < a.refine_max; ++step) {
+        RW_TRY(check(1));
+        RW_TRY(launch_pcg_c<float, R, float>(a, n, a.dcorr, 1, pp, s));
+        if (rest) {
+            if (r64) hipLaunchKernelGGL((k_apply<R, true>), grid, blk, 0, s, a, nd);
+            else hipLaunchKernelGGL((k_apply<R, false>), grid, blk, 0, s, a, nd);
+        }
+        for (int i = 0; i < nd; ++i)
+            RW_TRY(r64 ? domain_apply<R, true>(a, i, pp.host[i], s) : domain_apply<R, false>(a, i, pp.host[i], s));
+    }
+    RW_TRY(check(0));
+    if (r64) {
+        if (rest) hipLaunchKernelGGL((k_copy64<R>), grid, blk, 0, s, a, 0, nd);
+        for (int i = 0; i < nd; ++i) RW_TRY(domain_copy64<R>(a, i, pp.host[i], 0, s));
+    }
+    const int copy = (a.want_x64 && !r64) ? 1 : 0;
+    if (copy)
+        for (int i = 0; i < nd; ++i) RW_TRY(domain_copy64<R>(a, i, pp.host[i], 1, s));
+    hipLaunchKernelGGL((k_stats<R>), dim3((unsigned)n), blk, 0, s, a, copy, nd);
     return hipGetLastError();
 }
 
 template <int R>
 static hipError_t launch_fp64(const SolveArgs& a, int64_t n, const PlanePlan& pp, hipStream_t s, hipEvent_t* ev) {
-    const dim3 grid((unsigned)n), blk(kThreads);
-    hipLaunchKernelGGL((k_init<double, R>), grid, blk, 0, s, a);
+    const int nd = (int)pp.n_dom;
+    const dim3 grid((unsigned)(n - nd)), blk(kThreads);
+    const bool rest = n > nd;
+    if (rest) hipLaunchKernelGGL((k_init<double, R>), grid, blk, 0, s, a, nd);
+    for (int i = 0; i < nd; ++i) RW_TRY((domain_init<double, R>(a, i, pp.host[i], s)));
     if (ev) RW_TRY(hipEventRecord(ev[0], s));
     RW_TRY(launch_pcg_c<double, R, double>(a, n, (double*)a.xt, 0, pp, s));
     if (ev) RW_TRY(hipEventRecord(ev[1], s));
-    hipLaunchKernelGGL((k_finish64<R>), grid, blk, 0, s, a);
-    hipLaunchKernelGGL((k_stats<R>), grid, blk, 0, s, a, 0);
+    if (rest) hipLaunchKernelGGL((k_finish64<R>), grid, blk, 0, s, a, nd);
+    for (int i = 0; i < nd; ++i) RW_TRY(domain_finish64<R>(a, i, pp.host[i], s));
+    hipLaunchKernelGGL((k_stats<R>), dim3((unsigned)n), blk, 0, s, a, 0, nd);
     return hipGetLastError();
 }
 
