@@ -45,7 +45,7 @@ def source_hash():
 def traffic_from_profile(kernel_ms_unused=None):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "k_solve_stress8192_counters.md")
+    path = os.path.join(ROOT, "profiles", "k_solve_stress8192.md")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -96,6 +96,156 @@ def cpu_baseline(boxes, seconds=15.0):
                       f"one single-threaded process per core)"}, sols
 
 
+# ---------------------------------------------------------------------------
+# Further workloads (reported beside the headline, not part of it)
+# ---------------------------------------------------------------------------
+
+def _best_ms(torch, fn, reps):
+    best = float("inf")
+    out = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        best = min(best, (time.perf_counter() - t0) * 1e3)
+    return best, out
+
+
+def oracle_plain_solve(g, m, x):
+    """cpu_baseline leg: exact reference of one box (FP64 oracle, tol 1e-13)."""
+    from oracle import rw as orw
+    t0 = time.time()
+    ref = orw.solve_box(g, m, x, BETA, EPS, method="pcg", tol=1e-13).ravel()
+    return ref, time.time() - t0
+
+
+def bench_plain_sphere(torch, rwg, dev, cpu_leg):
+    """64^3 sphere, one domain: FP64 to relative residual 1e-6 (the stated
+    configuration) beside the mixed and mixed+refine paths."""
+    import numpy as np
+    import synth
+    g, m, x0, inside = synth.plain_sphere()
+    d = synth.from_boxes([(g, m, x0)])
+    gd, md = torch.from_numpy(d["g"]).to(dev), torch.from_numpy(d["mask"]).to(dev)
+    xd0 = torch.from_numpy(d["x"]).to(dev)
+    x64 = torch.zeros(xd0.numel(), dtype=torch.float64, device=dev)
+    ref, ref_s = oracle_plain_solve(g, m, x0) if cpu_leg else (None, None)
+    runs = {"fp64_tol1e-6": dict(precision=0, tol=1e-6),
+            "mixed_tol1e-6": dict(precision=1, tol=1e-6),
+            "mixed_refine_tol1e-6": dict(precision=2, tol=1e-6, refine_max=4, refine_tol=1e-12)}
+    out = {"workload": "plain sphere 64^3 float32 (radius 20, 0.7 on 0.3, noise 0.05), fg 5^3 centre block, "
+                       "bg all faces, beta 128, eps 1e-6, one domain",
+           "unknowns": int((m == 0).sum())}
+    for name, kw in runs.items():
+        xd = xd0.clone()
+
+        def step():
+            xd.copy_(xd0)
+            return rwg.solve_bricks(gd, md, xd, d["shapes"], d["offsets"], x64=x64 if kw["precision"] != 1 else None,
+                                    beta=BETA, eps=EPS, **kw)
+        ms, st = _best_ms(torch, step, 3)
+        s = rwg.stats_to_numpy(st)[0]
+        sol = (x64.cpu().numpy() if kw["precision"] != 1 else xd.cpu().numpy().astype(np.float64))
+        r = {"ms": ms, "iters": int(s["iters"]), "refine_iters": int(s["refine_iters"]),
+             "status": rwg.STATUS_NAMES[int(s["status"])], "true_rel_resid": float(s["true_rel_resid"]),
+             "voxel_iters_per_s": float(g.size * (int(s["iters"]) + int(s["refine_iters"])) / (ms / 1e3)),
+             "dice_vs_sphere": float(2 * ((sol.reshape(g.shape) > 0.5) & inside).sum()
+                                     / ((sol > 0.5).sum() + inside.sum()))}
+        if ref is not None:
+            r["max_abs_err_vs_oracle"] = float(np.max(np.abs(sol - ref)))
+        out[name] = r
+    if ref is not None:
+        out["oracle_exact_s"] = ref_s
+    return out
+
+
+def bench_tubes(torch, rwg, ctx, n=512, n_tubes=40, levels=4):
+    """Hierarchical pipeline on the random-tube volume (uint16, 4 levels,
+    32^3 bricks expanded to 40^3, dt pruning at t_bin 0.49, mixed, tol 1e-5)."""
+    import numpy as np
+    import synth
+    t0 = time.time()
+    v, seeds, tube = synth.tube_volume(n=n, n_tubes=n_tubes, n_fg=20, n_bg=200, seed=2)
+    gen_s = time.time() - t0
+    vd = torch.from_numpy(v).to("cuda:0")
+    kw = dict(brick=32, expand=1.25, beta=BETA, eps=EPS, tol=1e-5, precision=1, n_classes=2, prune_hom=0,
+              prune_dt=1, t_bin=0.49)
+    pyr_ms, pyr = _best_ms(torch, lambda: rwg.Pyramid(ctx, vd, levels), 3)
+    seg_ms, res = _best_ms(torch, lambda: rwg.segment(pyr, seeds, **kw), 3)
+    st = res.stats()
+    _, lab = res.materialize(0, 1, prob=False, labels=True)
+    lb = lab.cpu().numpy().astype(bool)
+    gt = (tube > 0) & (tube <= 20)
+    vi = int(sum(st["voxel_iters"]))
+    return {"workload": f"tubes {n}^3 uint16, {n_tubes} tubes, 20 fg + 200 bg seeds, {levels} levels, s=32, e=1.25, "
+                        "beta 128, dt pruning t_bin 0.49, mixed tol 1e-5",
+            "pyramid_ms": pyr_ms, "segment_ms": seg_ms,
+            "end_to_end_voxels_per_s": float(v.size / (seg_ms / 1e3)),
+            "voxel_iters": vi, "voxel_iters_per_s": float(vi / (seg_ms / 1e3)),
+            "per_level": {k: st[k] for k in ("bricks", "computed", "solved", "prunable", "max_iters", "not_converged")},
+            "dice_vs_seeded_tubes": float(2 * (lb & gt).sum() / (lb.sum() + gt.sum())),
+            "generate_s": gen_s}
+
+
+def bench_blobs_adjoint(torch, rwg, dev, n=512):
+    """Forward (mixed + FP64 refinement) and adjoint on 512 two-blob 32^3
+    boxes, beta 64; loss = mean BCE over unseeded voxels."""
+    import synth
+    d = synth.blob_boxes(n=n, seed=4)
+    g = torch.from_numpy(d["g"]).to(dev)
+    m = torch.from_numpy(d["mask"]).to(dev)
+    x0 = torch.from_numpy(d["x"]).to(dev)
+    y = torch.from_numpy(d["gt"]).to(dev).float()
+    u = (m == 0).float()
+    x = x0.clone()
+    kw = dict(beta=64.0, eps=EPS, tol=1e-6)
+
+    def fwd():
+        x.copy_(x0)
+        return rwg.solve_bricks(g, m, x, d["shapes"], d["offsets"], precision=1, **kw)
+    f_ms, st = _best_ms(torch, fwd, 3)
+    xc = x.clamp(1e-6, 1 - 1e-6)
+    dl_dx = ((xc - y) / (xc * (1 - xc)) * u / u.sum()).contiguous()
+    b_ms, (dl_dg, dl_db, sta) = _best_ms(
+        torch, lambda: rwg.solve_bricks_adjoint(g, m, x, dl_dx, d["shapes"], d["offsets"], **kw), 3)
+    s, sa = rwg.stats_to_numpy(st), rwg.stats_to_numpy(sta)
+    vox = 32 ** 3
+    return {"workload": f"{n} two-blob boxes 32^3, beta 64, forward mixed tol 1e-6 + adjoint tol 1e-6",
+            "forward_ms": f_ms, "adjoint_ms": b_ms,
+            "forward_voxel_iters_per_s": float(vox * (s["iters"] + s["refine_iters"]).sum() / (f_ms / 1e3)),
+            "adjoint_voxel_iters_per_s": float(vox * sa["iters"].sum() / (b_ms / 1e3)),
+            "dl_dbeta": float(dl_db.item()), "dl_dg_norm": float(dl_dg.norm().item())}
+
+
+def bench_shells(torch, rwg, ctx, dims=(256, 256, 128), levels=3):
+    """Four-class nested-shell volume (3 right-hand sides per box, hom
+    pruning t_hom 0.3, mixed tol 1e-5), then a 2000-voxel class-2 stroke
+    solved incrementally."""
+    import numpy as np
+    import synth
+    t0 = time.time()
+    v, labels, seeds, geo = synth.shell_volume(dims=dims, seed=5)
+    stroke = synth.stroke(labels, geo, cls=2, length=2000, seed=6)
+    gen_s = time.time() - t0
+    vd = torch.from_numpy(v).to("cuda:0")
+    kw = dict(brick=32, expand=1.25, beta=BETA, eps=EPS, tol=1e-5, precision=1, n_classes=4, prune_hom=1,
+              prune_dt=0, t_hom=0.3)
+    pyr_ms, pyr = _best_ms(torch, lambda: rwg.Pyramid(ctx, vd, levels), 2)
+    full_ms, res = _best_ms(torch, lambda: rwg.segment(pyr, seeds, **kw), 2)
+    more = np.concatenate([seeds, stroke])
+    inc_ms, rinc = _best_ms(torch, lambda: rwg.segment(pyr, more, prev=res, **kw), 2)
+    st, si = res.stats(), rinc.stats()
+    _, lab = rinc.materialize(0, 0, prob=False, labels=True)
+    acc = float((lab.cpu().numpy() == labels).mean())
+    return {"workload": f"nested shells {dims[0]}x{dims[1]}x{dims[2]} uint16, 4 classes (3 rhs), {levels} levels, "
+                        "s=32, e=1.25, hom pruning t_hom 0.3, mixed tol 1e-5; then a 2000-voxel stroke (class 2)",
+            "pyramid_ms": pyr_ms, "full_ms": full_ms, "incremental_ms": inc_ms,
+            "full_voxel_iters_per_s": float(sum(st["voxel_iters"]) / (full_ms / 1e3)),
+            "full_solved": st["solved"], "incremental_solved": si["solved"], "bricks": st["bricks"],
+            "label_accuracy_vs_truth": acc, "generate_s": gen_s}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +254,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--schedule", type=int, default=0, help="CG schedule: 0 library choice, 1 two-sweep, 2 one-sweep")
+    ap.add_argument("--no-extras", action="store_true", help="skip the further workloads (sphere, tubes, blobs, shells)")
+    ap.add_argument("--shells-dims", default="256,256,128", help="nested-shell volume dims nx,ny,nz")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (boxes are independent; multi-GPU sharding "
@@ -211,6 +363,20 @@ def main():
                 err["fp64"] = max(err["fp64"], float(np.max(np.abs(fp64["x"][o:o + n] - ref))))
         out["max_abs_diff_vs_oracle"] = dict(err, boxes=len(sols),
                                              note="oracle at the same tol 1e-6; both sides carry solver error")
+    if not args.no_extras:
+        extras = {}
+        shell_dims = tuple(int(t) for t in args.shells_dims.split(","))
+        jobs = (("plain_sphere_64", lambda: bench_plain_sphere(torch, rwg, dev, not args.no_cpu_baseline)),
+                ("tubes_512_hierarchy", lambda: bench_tubes(torch, rwg, ctx)),
+                ("blobs_512x32_adjoint", lambda: bench_blobs_adjoint(torch, rwg, dev)),
+                ("shells_hierarchy_incremental", lambda: bench_shells(torch, rwg, ctx, dims=shell_dims)))
+        for name, job in jobs:
+            print(f"bench.py: {name}", file=sys.stderr, flush=True)
+            try:
+                extras[name] = job()
+            except Exception as e:  # a failing side workload must not hide the headline line
+                extras[name] = {"error": f"{type(e).__name__}: {e}"}
+        out["workloads"] = extras
     print(json.dumps(out), flush=True)
 
 

@@ -176,3 +176,244 @@ def random_box(rng, shape, dirichlet_frac=0.05, smooth=1.0):
         mask.flat[rng.integers(0, mask.size)] = 1
     x = np.where(mask != 0, rng.random((nz, ny, nx)), 0.0)
     return g.astype(np.float32), mask, x.astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Hierarchical pipeline volumes
+# ---------------------------------------------------------------------------
+
+def _catmull_rom(ctrl, step=1.0):
+    """Points along the uniform Catmull-Rom spline through all control points
+    (end points reflected), spaced <= step voxels.  A union of balls of radius
+    r >= 2 about points 1 voxel apart is within 0.07 voxel of the swept tube."""
+    P = np.asarray(ctrl, np.float64)
+    P = np.concatenate([2 * P[:1] - P[1:2], P, 2 * P[-1:] - P[-2:-1]])
+    out = []
+    for i in range(1, len(P) - 2):
+        p0, p1, p2, p3 = P[i - 1], P[i], P[i + 1], P[i + 2]
+        # oversample by the control polygon length so spacing stays below step
+        n = int(np.ceil((np.linalg.norm(p1 - p0) + np.linalg.norm(p2 - p1) + np.linalg.norm(p3 - p2)) / step)) + 2
+        t = np.linspace(0.0, 1.0, n, endpoint=(i == len(P) - 3))[:, None]
+        t2, t3 = t * t, t * t * t
+        out.append(0.5 * ((2 * p1) + (-p0 + p2) * t + (2 * p0 - 5 * p1 + 4 * p2 - p3) * t2
+                          + (-p0 + 3 * p1 - 3 * p2 + p3) * t3))
+    return np.concatenate(out)
+
+
+def _tube_voxels(shape, pts, r):
+    """Flat indices (array [z, y, x], voxel centres at integer indices) of the
+    voxels within distance r of any of the points (x, y, z); an index may
+    repeat."""
+    nz, ny, nx = shape
+    R = int(np.ceil(r)) + 1
+    o = np.arange(-R, R + 1)
+    off = np.stack(np.meshgrid(o, o, o, indexing="ij"), -1).reshape(-1, 3)  # (dx, dy, dz)
+    off = off[np.sum((off - 0.5) ** 2, axis=1) <= (r + 1.8) ** 2]           # cannot reach r otherwise
+    off = off.astype(np.int32)
+    p32 = pts.astype(np.float32)
+    base = np.floor(p32).astype(np.int32)
+    frac = p32 - base                                                       # point within its base voxel
+    found = []
+    for c in range(0, len(pts), 512):
+        d = off[None, :, :].astype(np.float32) - frac[c:c + 512, None, :]
+        hit = np.einsum("ijk,ijk->ij", d, d) <= r * r
+        b = (base[c:c + 512, None, :] + off[None, :, :])[hit]
+        ok = (b[:, 0] >= 0) & (b[:, 0] < nx) & (b[:, 1] >= 0) & (b[:, 1] < ny) & (b[:, 2] >= 0) & (b[:, 2] < nz)
+        b = b[ok].astype(np.int64)
+        found.append((b[:, 2] * ny + b[:, 1]) * nx + b[:, 0])
+    return np.concatenate(found) if found else np.zeros(0, np.int64)
+
+
+def _smooth_field(rng, n, sigma, coarse=4):
+    """Gaussian-smoothed white noise rescaled to [-1, 1].  For a wide kernel
+    the noise is drawn at 1/coarse resolution, smoothed with sigma/coarse and
+    trilinearly resampled (the smoothed field is band-limited far below the
+    coarse grid's Nyquist rate)."""
+    import torch
+    m = max(4, n // coarse)
+    a = ndimage.gaussian_filter(rng.standard_normal((m, m, m)), sigma / coarse, mode="wrap")
+    t = torch.from_numpy(a.astype(np.float32))[None, None]
+    t = torch.nn.functional.interpolate(t, size=(n, n, n), mode="trilinear", align_corners=False)[0, 0]
+    f = t.numpy()
+    lo, hi = float(f.min()), float(f.max())
+    return (2.0 * (f - lo) / (hi - lo) - 1.0).astype(np.float32)
+
+
+def tube_volume(n=512, n_tubes=40, n_fg=20, n_bg=200, seed=2):
+    """uint16 volume of random tubes on a textured background, with seeds.
+
+    Tubes: Catmull-Rom centrelines through 5 control points U[32, n-32]^3
+    (scaled for small n), radius U[2, 8], intensity U[2700, 3300] per tube.
+    Background 800 + 200 s(p), s a Gaussian-smoothed (sigma n/32) white-noise
+    field in [-1, 1]; then iid N(0, 150^2), clip to [0, 65535], round.
+    Seeds (x, y, z, label) in voxel units where voxel k covers [k, k+1):
+    n_fg foreground points (label 1), one on each of the first n_fg tube
+    centrelines; n_bg background points (label 0) uniform in the volume,
+    redrawn when closer than radius + 4 to a centreline.
+
+    Returns (vol [z, y, x] uint16, seeds float64 [k, 4], tube index map uint8
+    [z, y, x]: 0 background, t + 1 inside tube t, later tubes on top)."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    lo, hi = 32.0 * n / 512.0, n - 32.0 * n / 512.0
+    tube = np.zeros((n, n, n), dtype=np.uint8)
+    vol = 800.0 + 200.0 * _smooth_field(rng, n, sigma=16.0 * n / 512.0)
+    curves, radii = [], []
+    for t in range(n_tubes):
+        ctrl = rng.uniform(lo, hi, (5, 3))
+        r = rng.uniform(2.0, 8.0)
+        inten = rng.uniform(2700.0, 3300.0)
+        pts = _catmull_rom(ctrl)
+        idx = _tube_voxels(tube.shape, pts, r)
+        vol.reshape(-1)[idx] = inten
+        tube.reshape(-1)[idx] = t + 1
+        curves.append(pts)
+        radii.append(r)
+    vol += rng.standard_normal((n, n, n), dtype=np.float32) * 150.0
+    vol = np.rint(np.clip(vol, 0.0, 65535.0)).astype(np.uint16)
+    seeds = []
+    for t in range(min(n_fg, n_tubes)):
+        p = curves[t][rng.integers(0, len(curves[t]))]
+        seeds.append([p[0] + 0.5, p[1] + 0.5, p[2] + 0.5, 1])
+    trees = [cKDTree(c) for c in curves]
+    while len(seeds) < min(n_fg, n_tubes) + n_bg:
+        q = rng.uniform(0.0, n, 3)
+        if all(tr.query(q - 0.5)[0] > r + 4.0 for tr, r in zip(trees, radii)):
+            seeds.append([q[0], q[1], q[2], 0])
+    return vol, np.array(seeds, dtype=np.float64), tube
+
+
+def _rotation(rng):
+    """Uniform random 3-D rotation (QR of a Gaussian matrix, sign-fixed)."""
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def _lattice_noise(rng, dims, wavelength):
+    """Trilinear interpolation of iid N(0, 1) values on a lattice of the given
+    spacing (voxels), sampled at the voxel centres of dims = (nx, ny, nz);
+    returns [z, y, x] float32."""
+    import torch
+    nx, ny, nz = dims
+    cells = [int(np.ceil(d / wavelength)) + 2 for d in (nz, ny, nx)]
+    lat = torch.from_numpy(rng.standard_normal(cells).astype(np.float32))
+    # voxel i sits at lattice coordinate (i + 0.5) / wavelength
+    axes = [(torch.arange(d, dtype=torch.float32) + 0.5) / float(wavelength) for d in (nz, ny, nx)]
+    out = torch.zeros((nz, ny, nx))
+    i0 = [a.floor().long() for a in axes]
+    f = [a - a.floor() for a in axes]
+    for dz in (0, 1):
+        wz = (f[0] if dz else 1 - f[0])[:, None, None]
+        for dy in (0, 1):
+            wy = (f[1] if dy else 1 - f[1])[None, :, None]
+            for dx in (0, 1):
+                wx = (f[2] if dx else 1 - f[2])[None, None, :]
+                out += wz * wy * wx * lat[(i0[0] + dz)[:, None, None], (i0[1] + dy)[None, :, None],
+                                          (i0[2] + dx)[None, None, :]]
+    return out.numpy()
+
+
+def shell_volume(dims=(256, 256, 128), seed=5, n_per_class=50, margin=None, fbm_std=100.0):
+    """uint16 volume of 4 classes: background (mean 500) and three nested
+    ellipsoids E1 > E2 > E3 (common centre jittered by +-5 % of dims, common
+    random rotation; semi-axes a1 = U[.35, .45] dims, a2 = a1 U[.6, .75],
+    a3 = a2 U[.5, .7] per axis); class 1 = E1 \\ E2 (1500), 2 = E2 \\ E3 (2500),
+    3 = E3 (3500).  Plus iid N(0, 250^2) and a 6-octave fBm of trilinear
+    lattice noise (base wavelength 512 voxels, amplitude halved per octave,
+    total std fbm_std); clip, round.
+
+    Seeds: n_per_class points per class, each at least `margin` voxels from
+    the class's region boundaries (ellipsoid-radius bound; default 8 voxels
+    at a 1024-voxel short side, scaled with it, at least 2).  Returns
+    (vol [z, y, x] uint16, labels [z, y, x] uint8, seeds float64 [k, 4],
+    geometry dict for stroke drawing)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    D = np.array([nx, ny, nz], np.float64)
+    if margin is None:
+        margin = max(2.0, 8.0 * min(dims) / 1024.0)
+    c = D / 2.0 + rng.uniform(-0.05, 0.05, 3) * D
+    Q = _rotation(rng)
+    a1 = rng.uniform(0.35, 0.45, 3) * D
+    a2 = a1 * rng.uniform(0.6, 0.75, 3)
+    a3 = a2 * rng.uniform(0.5, 0.7, 3)
+    axes = [a1, a2, a3]
+    labels = np.zeros((nz, ny, nx), np.uint8)
+    xs = np.arange(nx, dtype=np.float64)
+    ys = np.arange(ny, dtype=np.float64)
+    for z in range(nz):
+        # voxel centres at integer indices; ellipsoid frame coordinates u = Q^T (p - c)
+        P = np.stack(np.broadcast_arrays(xs[None, :], ys[:, None], np.float64(z)), -1) - c
+        u = P @ Q
+        for k, a in enumerate(axes):
+            inside = np.sum((u / a) ** 2, axis=-1) <= 1.0
+            labels[z][inside] = k + 1
+    means = np.array([500.0, 1500.0, 2500.0, 3500.0], np.float32)
+    vol = means[labels]
+    fbm = np.zeros((nz, ny, nx), np.float32)
+    amp, var = 1.0, 0.0
+    for o in range(6):
+        fbm += amp * _lattice_noise(rng, dims, 512.0 / 2 ** o)
+        var += amp * amp
+        amp *= 0.5
+    vol += fbm * np.float32(fbm_std / np.sqrt(var))   # lattice noise variance < 1: std <= fbm_std
+    vol += rng.standard_normal((nz, ny, nx), dtype=np.float32) * 250.0
+    vol = np.rint(np.clip(vol, 0.0, 65535.0)).astype(np.uint16)
+
+    def rho(p):  # ellipsoid radii of points p (x, y, z) in index space, per ellipsoid
+        u = (np.atleast_2d(p) - c) @ Q
+        return [np.sqrt(np.sum((u / a) ** 2, axis=-1)) for a in axes]
+
+    def clearance(p):  # lower bound of the distance to every ellipsoid surface
+        return np.min([np.abs(r - 1.0) * a.min() for r, a in zip(rho(p), axes)], axis=0)
+
+    seeds = []
+    for cls in range(4):
+        got, tries = 0, 0
+        while got < n_per_class:
+            tries += 1
+            if tries > 1000:
+                raise RuntimeError(f"class {cls}: too few voxels {margin} away from the boundaries")
+            p = rng.uniform(0.0, 1.0, (4096, 3)) * (D - 1)
+            q = np.rint(p).astype(np.int64)
+            ok = (labels[q[:, 2], q[:, 1], q[:, 0]] == cls) & (clearance(q.astype(np.float64)) >= margin)
+            for v in q[ok][: n_per_class - got]:
+                seeds.append([v[0] + 0.5, v[1] + 0.5, v[2] + 0.5, cls])
+                got += 1
+    geo = dict(centre=c, rotation=Q, axes=axes, clearance=clearance, margin=margin)
+    return vol, labels, np.array(seeds, np.float64), geo
+
+
+def stroke(labels, geo, cls=2, length=2000, seed=6):
+    """Self-avoiding 6-neighbour walk of `length` voxels inside class `cls`,
+    every voxel at least geo["margin"] from the region boundaries (a walk that
+    gets stuck starts again elsewhere).  Returns seeds (x, y, z, cls) at the
+    voxel centres."""
+    rng = np.random.default_rng(seed)
+    margin = geo["margin"]
+    nz, ny, nx = labels.shape
+    steps = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]])
+
+    def ok(v):
+        return (0 <= v[0] < nx and 0 <= v[1] < ny and 0 <= v[2] < nz and labels[v[2], v[1], v[0]] == cls
+                and geo["clearance"](v.astype(np.float64))[0] >= margin)
+
+    for _ in range(100000):
+        start = np.array([rng.integers(0, nx), rng.integers(0, ny), rng.integers(0, nz)])
+        if not ok(start):
+            continue
+        path, seen = [start], {tuple(start)}
+        while len(path) < length:
+            cand = [path[-1] + s for s in steps[rng.permutation(6)]]
+            nxt = next((v for v in cand if tuple(v) not in seen and ok(v)), None)
+            if nxt is None:
+                break
+            path.append(nxt)
+            seen.add(tuple(nxt))
+        if len(path) == length:
+            p = np.array(path, np.float64) + 0.5
+            return np.concatenate([p, np.full((length, 1), float(cls))], axis=1)
+    raise RuntimeError("no self-avoiding walk of the requested length found")
