@@ -93,9 +93,15 @@ typedef struct rw_solve_params {
     double inner_tol;        /* relative tolerance of each FP32 correction solve */
     double stall_ratio;      /* MIXED: a box counts as stalled, and gets a correction solve, when
                                 its FP64 true relative residual exceeds stall_ratio * tol (>= 1) */
-    int32_t schedule;        /* CG iteration schedule: 0 library choice, 1 two sweeps and two
-                                reductions per iteration (Hestenes-Stiefel), 2 one sweep and one
-                                reduction (Chronopoulos-Gear; weights computed once per iteration) */
+    int32_t schedule;        /* CG iteration schedule: 0 library choice (MIXED with nrhs 1: boxes
+                                that fit one CU's LDS run entirely in LDS and registers, the
+                                others stream as in 1), 1 streaming, two sweeps and two
+                                reductions per iteration (Hestenes-Stiefel), 2 streaming, one
+                                sweep and one reduction (Chronopoulos-Gear; weights computed once
+                                per iteration), 3 as 0 with the streaming boxes as in 2.  Every
+                                schedule is the same Jacobi-PCG iteration in exact arithmetic;
+                                results differ by rounding (the one-sweep recurrence is the less
+                                stable one on very ill-conditioned boxes). */
     int32_t reserved;        /* must be 0 */
 } rw_solve_params;
 
@@ -148,16 +154,37 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
  * Phase timing of rw_solve_bricks (tracing).  With timing enabled the next
  * solves record HIP events on their stream around each phase; rw_last_timing
  * waits for those events and returns the phase durations of the last solve
- * in milliseconds.  pcg_ms is the main PCG kernel alone (the hot loop).
+ * in milliseconds.  pcg_ms is the main PCG phase alone (the hot loop).  In
+ * that phase the boxes that stream from HBM and the boxes that run resident
+ * in LDS (see rw_solve_plan) are solved by concurrent kernels; stream_ms and
+ * resident_ms are the durations of the two groups (0 for an empty group).
  */
 typedef struct rw_timing {
     float init_ms;           /* Dirichlet init (r = -(L x)_U, z, p) */
-    float pcg_ms;            /* main PCG kernel(s) */
+    float pcg_ms;            /* main PCG phase */
     float finish_ms;         /* FP64 true residual, refinement, stats */
     float total_ms;
+    float stream_ms;         /* main PCG: streaming kernels (RW_PATH_STREAM*) */
+    float resident_ms;       /* main PCG: LDS-resident kernels (RW_PATH_RESIDENT) */
 } rw_timing;
 int rw_set_timing(rw_ctx* ctx, int enable);
 int rw_last_timing(rw_ctx* ctx, rw_timing* out);
+
+/* Kernel path of a box in rw_solve_bricks. */
+enum rw_path {
+    RW_PATH_STREAM = 0,          /* one workgroup per box, vectors streamed from HBM, LDS window march */
+    RW_PATH_STREAM_GLOBAL = 1,   /* the same without the LDS window (planes wider than it holds) */
+    RW_PATH_RESIDENT = 2,        /* one workgroup per box, g and p in LDS, x and r in registers */
+    RW_PATH_DOMAIN = 3           /* large single box: many workgroups, host-driven iteration */
+};
+
+/*
+ * Host-only: the kernel path rw_solve_bricks would take for each brick with
+ * these params on ctx's device (caller order) into path[n_bricks] (host).
+ * Validates like rw_solve_bricks; queues nothing.
+ */
+int rw_solve_plan(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                  int64_t n_voxels, int32_t* path);
 
 /*
  * Host-only check of the arguments rw_solve_bricks would validate (params,

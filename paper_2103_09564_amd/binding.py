@@ -62,13 +62,17 @@ lib.rw_validate_solve.restype = ctypes.c_int
 
 class Timing(ctypes.Structure):
     _fields_ = [("init_ms", ctypes.c_float), ("pcg_ms", ctypes.c_float), ("finish_ms", ctypes.c_float),
-                ("total_ms", ctypes.c_float)]
+                ("total_ms", ctypes.c_float), ("stream_ms", ctypes.c_float), ("resident_ms", ctypes.c_float)]
 
 
 lib.rw_set_timing.argtypes = [_vp, ctypes.c_int]
 lib.rw_set_timing.restype = ctypes.c_int
 lib.rw_last_timing.argtypes = [_vp, ctypes.POINTER(Timing)]
 lib.rw_last_timing.restype = ctypes.c_int
+lib.rw_solve_plan.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp]
+lib.rw_solve_plan.restype = ctypes.c_int
+
+PATH_STREAM, PATH_STREAM_GLOBAL, PATH_RESIDENT, PATH_DOMAIN = 0, 1, 2, 3
 
 
 class RWError(RuntimeError):
@@ -163,7 +167,15 @@ class Context:
         """Phase durations (ms) of the last timed solve; waits for its events."""
         t = Timing()
         self._check(lib.rw_last_timing(self.handle, ctypes.byref(t)))
-        return {"init_ms": t.init_ms, "pcg_ms": t.pcg_ms, "finish_ms": t.finish_ms, "total_ms": t.total_ms}
+        return {k: getattr(t, k) for k, _ in Timing._fields_}
+
+    def solve_plan(self, params, bricks, n_voxels):
+        """Kernel path (PATH_*) of each brick, as an int32 numpy array."""
+        bricks = np.ascontiguousarray(bricks, dtype=BRICK_DTYPE)
+        out = np.zeros(len(bricks), dtype=np.int32)
+        self._check(lib.rw_solve_plan(self.handle, ctypes.byref(params), len(bricks), bricks.ctypes.data_as(_vp),
+                                      int(n_voxels), out.ctypes.data_as(_vp)))
+        return out
 
     def rw_solve_bricks_adjoint(self, params, bricks, g, mask, x, dl_dx, dl_dg, dl_dbeta, lam=None,
                                 stats=None, stream=None):

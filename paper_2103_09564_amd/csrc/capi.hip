@@ -76,9 +76,13 @@ int check_params(rw_ctx* ctx, const rw_solve_params* p) {
     if (!std::isfinite(p->refine_tol) || p->refine_tol < 0) return fail(ctx, RW_E_INVAL, "refine_tol must be >= 0");
     if (!std::isfinite(p->inner_tol) || p->inner_tol < 0) return fail(ctx, RW_E_INVAL, "inner_tol must be >= 0");
     if (!std::isfinite(p->stall_ratio) || p->stall_ratio < 1) return fail(ctx, RW_E_INVAL, "stall_ratio must be >= 1");
-    if (p->schedule < 0 || p->schedule > 2) return fail(ctx, RW_E_INVAL, "schedule must be 0, 1 or 2");
+    if (p->schedule < 0 || p->schedule > 3) return fail(ctx, RW_E_INVAL, "schedule must be 0, 1, 2 or 3");
     return RW_OK;
 }
+
+// Schedule of the streaming kernels for a requested schedule (0 and 1: two
+// sweeps, 2 and 3: one sweep; 0 and 3 also use the LDS-resident kernel).
+int stream_schedule(int requested) { return requested == 2 || requested == 3 ? 2 : 1; }
 
 // Validate host descriptors and build the launch list (largest box first).
 int build_list(rw_ctx* ctx, int64_t n, const rw_brick* bricks, int64_t n_voxels,
@@ -116,9 +120,16 @@ int build_list(rw_ctx* ctx, int64_t n, const rw_brick* bricks, int64_t n_voxels,
 // Choose the PCG kernel split for this batch and move the boxes that are too
 // wide for the LDS plane march to the front of the (largest-first) list.
 // The few largest boxes (single domains) go to the multi-workgroup solver in
-// front of the list.
-rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, int nrhs, bool fp64) {
-    rwk::PlanePlan pp{0, 2, (int64_t)list->size(), 0, nullptr};
+// front of the list; boxes that fit in one CU's LDS (one rhs, FP32, streaming
+// schedule not forced) go to the resident kernel at the end.
+rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, int nrhs, bool fp64,
+                           int schedule) {
+    const int64_t n = (int64_t)list->size();
+    rwk::PlanePlan pp{};
+    pp.cols = 2;
+    pp.n_big = pp.n_res_l = pp.n_res_s = n;
+    const bool res_ok = nrhs == 1 && !fp64 && (schedule == 0 || schedule == 3);
+    const int64_t res_small = rwk::kResSmallVox;
     int widest = 0;
     for (const auto& b : *list)
         if (b.nx * b.ny <= rwk::plane_max(4)) widest = std::max(widest, b.nx * b.ny);
@@ -126,7 +137,8 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     if (rwk::plane_lds_bytes(nrhs, fp64, cols) > ctx->lds_limit) cols = 2;
     const bool use = rwk::plane_lds_bytes(nrhs, fp64, cols) <= ctx->lds_limit;
     const int lim = use ? rwk::plane_max(cols) : 0;
-    // group 0: domain solver, 1: global march, 2: plane march (list is largest-first)
+    // group 0: domain solver, 1: global march, 2: plane march, 3: resident,
+    // 4: resident small boxes; the list is largest-first
     std::vector<uint8_t> grp(list->size());
     int n_dom = 0;
     for (size_t i = 0; i < list->size(); ++i) {
@@ -138,6 +150,8 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
         if (dom && n_dom < rwk::kDomMaxBoxes) {
             grp[i] = 0;
             ++n_dom;
+        } else if (res_ok && rwk::resident_fits(b, ctx->lds_limit)) {
+            grp[i] = vox <= res_small ? 4 : 3;
         } else {
             grp[i] = wide ? 1 : 2;
         }
@@ -146,18 +160,47 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     std::iota(idx.begin(), idx.end(), size_t(0));
     std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return grp[a] < grp[b]; });
     std::vector<rwk::BrickDev> sorted(list->size());
-    int64_t n_big = 0;
+    int64_t cnt[5] = {0, 0, 0, 0, 0};
     for (size_t i = 0; i < idx.size(); ++i) {
         sorted[i] = (*list)[idx[i]];
-        n_big += grp[idx[i]] < 2 ? 1 : 0;
+        cnt[grp[idx[i]]] += 1;
     }
     list->swap(sorted);
     pp.use = use ? 1 : 0;
     pp.cols = cols;
-    pp.n_big = n_big;
     pp.n_dom = n_dom;
+    pp.n_big = cnt[0] + cnt[1];
+    pp.n_res_l = pp.n_big + cnt[2];
+    pp.n_res_s = pp.n_res_l + cnt[3];
+    auto vox = [&](int64_t i) { const auto& b = (*list)[(size_t)i]; return (int64_t)b.nx * b.ny * b.nz; };
+    pp.max_res_l = cnt[3] ? vox(pp.n_res_l) : 0;
+    pp.max_res_s = cnt[4] ? vox(pp.n_res_s) : 0;
+    for (int64_t i = pp.n_res_l; i < n; ++i) {
+        const auto& b = (*list)[(size_t)i];
+        int64_t& pl = i < pp.n_res_s ? pp.plane_res_l : pp.plane_res_s;
+        pl = std::max<int64_t>(pl, (int64_t)b.nx * b.ny);
+    }
     pp.host = list->data();
     return pp;
+}
+
+// Side streams and events for concurrent kernel groups (created once).
+int attach_side_streams(rw_ctx* ctx, rwk::PlanePlan* pp) {
+    if (!ctx->side[0]) {
+        for (int i = 0; i < 2; ++i) {
+            hipError_t e = hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join[i], hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(ctx, e, "creating side streams");
+        }
+        hipError_t e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(ctx, e, "creating side-stream events");
+    }
+    pp->side[0] = ctx->side[0];
+    pp->side[1] = ctx->side[1];
+    pp->fork = ctx->fork;
+    pp->join[0] = ctx->join[0];
+    pp->join[1] = ctx->join[1];
+    return RW_OK;
 }
 
 int upload_list(rw_ctx* ctx, const std::vector<rwk::BrickDev>& list, hipStream_t s) {
@@ -219,8 +262,15 @@ void rw_ctx_destroy(rw_ctx* ctx) {
     if (ctx->aux) (void)hipFree(ctx->aux);
     if (ctx->hws) (void)hipFree(ctx->hws);
     if (ctx->hgeo) (void)hipFree(ctx->hgeo);
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+        if (ctx->gev[i]) (void)hipEventDestroy(ctx->gev[i]);
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
+        if (ctx->join[i]) (void)hipEventDestroy(ctx->join[i]);
+    }
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     delete ctx;
 }
 
@@ -245,6 +295,12 @@ int rw_last_timing(rw_ctx* ctx, rw_timing* out) {
     out->pcg_ms = t[1];
     out->finish_ms = t[2];
     out->total_ms = t[0] + t[1] + t[2];
+    out->stream_ms = out->resident_ms = 0.0f;
+    for (int gidx = 0; gidx < 2 && e == hipSuccess; ++gidx)
+        if (ctx->gev_used & (1 << gidx))
+            e = hipEventElapsedTime(gidx ? &out->resident_ms : &out->stream_ms, ctx->gev[2 * gidx],
+                                    ctx->gev[2 * gidx + 1]);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reading timing events");
     return RW_OK;
 }
 
@@ -255,6 +311,28 @@ int rw_validate_solve(const rw_solve_params* params, int64_t n_bricks, const rw_
     if (rc) return rc;
     std::vector<rwk::BrickDev> list;
     return build_list(nullptr, n_bricks, bricks, n_voxels, &list);
+}
+
+int rw_solve_plan(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                  int64_t n_voxels, int32_t* path) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    std::vector<rwk::BrickDev> list;
+    rc = build_list(ctx, n_bricks, bricks, n_voxels, &list);
+    if (rc) return rc;
+    if (n_bricks > 0 && !path) return fail(ctx, RW_E_INVAL, "path is NULL");
+    const rwk::PlanePlan pp =
+        plan_planes(ctx, &list, params->nrhs, params->precision == RW_PREC_FP64, params->schedule);
+    for (int64_t i = 0; i < n_bricks; ++i) {
+        const int32_t slot = list[(size_t)i].slot;
+        path[slot] = i < pp.n_dom ? RW_PATH_DOMAIN
+                     : i < pp.n_big ? RW_PATH_STREAM_GLOBAL
+                     : i < pp.n_res_l ? RW_PATH_STREAM
+                                      : RW_PATH_RESIDENT;
+    }
+    return RW_OK;
 }
 
 int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
@@ -289,7 +367,9 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
     const size_t state_bytes = ((size_t)n_bricks * sizeof(rwk::BoxState) + 255) & ~size_t(255);
     e = grow(ctx, &ctx->aux, &ctx->aux_bytes, state_bytes + rwk::domain_scratch_bytes(), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating per-box state");
-    const rwk::PlanePlan pp = plan_planes(ctx, &list, R, fp64);
+    rwk::PlanePlan pp = plan_planes(ctx, &list, R, fp64, p.schedule);
+    rc = attach_side_streams(ctx, &pp);
+    if (rc) return rc;
     rc = upload_list(ctx, list, s);
     if (rc) return rc;
 
@@ -319,7 +399,7 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
     a.precision = p.precision;
     a.refine_max = p.refine_max;
     a.stall_ratio = p.stall_ratio;
-    a.schedule = p.schedule == 0 ? 1 : p.schedule;
+    a.schedule = stream_schedule(p.schedule);
     rwk::domain_bind(a, (char*)ctx->aux + state_bytes);
     hipEvent_t* ev = nullptr;
     if (ctx->timing) {
@@ -328,9 +408,16 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
                 e = hipEventCreate(&ctx->ev[i]);
                 if (e != hipSuccess) return hip_fail(ctx, e, "creating timing events");
             }
+        for (int i = 0; i < 4; ++i)
+            if (!ctx->gev[i]) {
+                e = hipEventCreate(&ctx->gev[i]);
+                if (e != hipSuccess) return hip_fail(ctx, e, "creating timing events");
+            }
         e = hipEventRecord(ctx->ev[0], s);
         if (e != hipSuccess) return hip_fail(ctx, e, "recording timing event");
         ev = &ctx->ev[1];
+        pp.gev = ctx->gev;
+        ctx->gev_used = (pp.n_res_l > pp.n_dom ? 1 : 0) | (pp.n_res_l < n_bricks ? 2 : 0);
     }
     e = rwk::launch_solve(a, n_bricks, R, fp64, pp, s, ev);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching solve kernel");
@@ -369,7 +456,9 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     const size_t part_bytes = ((size_t)n_bricks * sizeof(double) + 255) & ~size_t(255);
     e = grow(ctx, &ctx->aux, &ctx->aux_bytes, state_bytes + part_bytes + rwk::domain_scratch_bytes(), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint partials");
-    const rwk::PlanePlan pp = plan_planes(ctx, &list, 1, false);
+    rwk::PlanePlan pp = plan_planes(ctx, &list, 1, false, params->schedule);
+    rc = attach_side_streams(ctx, &pp);
+    if (rc) return rc;
     rc = upload_list(ctx, list, s);
     if (rc) return rc;
     char* w = (char*)ctx->ws;
@@ -406,7 +495,7 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     sa.inner_tol = a.tol;
     sa.max_iter = a.max_iter;
     sa.precision = RW_PREC_MIXED;
-    sa.schedule = params->schedule == 0 ? 1 : params->schedule;
+    sa.schedule = stream_schedule(params->schedule);
     rwk::domain_bind(sa, (char*)ctx->aux + state_bytes + part_bytes);
     e = rwk::launch_adjoint(a, sa, n_bricks, dl_dbeta, pp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching adjoint kernels");

@@ -25,6 +25,15 @@ struct rw_ctx {
     int timing = 0;              // record phase events in rw_solve_bricks
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // start, after init, after pcg, end
     int ev_valid = 0;
+    // two side streams (default priority) that run the streaming and the
+    // LDS-resident PCG kernels of one call concurrently, and their events
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[2] = {nullptr, nullptr};
+    // timing of the two kernel groups of the main PCG phase: streaming
+    // start/end, resident start/end; gev_used bit 0 / bit 1 when recorded
+    hipEvent_t gev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int gev_used = 0;
 };
 
 namespace rwk {
@@ -80,7 +89,7 @@ struct SolveArgs {
     BoxState* state;       // [n_bricks], workspace
     double beta, eps, tol, refine_tol, inner_tol, stall_ratio;
     int32_t max_iter, precision, refine_max, want_x64;
-    int32_t schedule;      // 1: two-sweep Jacobi-PCG, 2: single-reduction (Chronopoulos-Gear)
+    int32_t schedule;      // streaming kernels: 1 two-sweep Jacobi-PCG, 2 single-reduction (Chronopoulos-Gear)
     void* dom;             // multi-workgroup domain solver: scalar state and ticket
     double* dom_part;      // its per-workgroup partial sums
 };
@@ -114,7 +123,29 @@ struct PlanePlan {
     int64_t n_big;
     int64_t n_dom;
     const BrickDev* host;
+    // LDS-resident PCG (one rhs, FP32): [n_res_l, n_res_s) the larger boxes,
+    // [n_res_s, n) the small ones (launched apart so that their LDS size lets
+    // several workgroups share a CU); max_res_*: the largest box of each group
+    // (voxels).  Without resident boxes both are n.
+    int64_t n_res_l, n_res_s;
+    int64_t max_res_l, max_res_s;
+    int64_t plane_res_l, plane_res_s;  // widest nx*ny of each group
+    // when set, the streaming and resident groups run on these two streams
+    // (forked from and joined back into the caller's stream)
+    hipStream_t side[2];
+    hipEvent_t fork, join[2];
+    // main-solve group timing events (start/end streaming, start/end
+    // resident) or null
+    hipEvent_t* gev;
 };
+
+// LDS-resident PCG (resident.hip).
+constexpr int kResThreads = 512;
+constexpr int kResMaxVpt = 34;    // voxels per thread: boxes up to 17408 voxels (32 x 32 x 17)
+constexpr int kResSmallVox = 5120;  // the small group: at most 10 voxels per thread
+bool resident_fits(const BrickDev& b, size_t lds_limit);
+hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_voxels, int64_t max_plane,
+                           float* xt, int corr, hipStream_t s);
 
 size_t plane_lds_bytes(int nrhs, bool fp64, int cols);
 

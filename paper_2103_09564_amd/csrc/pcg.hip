@@ -31,6 +31,9 @@
 
 #include <math.h>
 
+#include <algorithm>
+#include <type_traits>
+
 namespace rwk {
 
 constexpr int kThreads = 512;
@@ -1404,14 +1407,43 @@ template <typename T, int R, int C, typename XT>
 static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big, XT* xt, int corr, size_t lds,
                                    const PlanePlan& pp, hipStream_t s) {
     for (int64_t i = 0; i < pp.n_dom; ++i) RW_TRY((domain_pcg<T, R, XT>(a, (int)i, pp.host[i], xt, corr, s)));
+    const int64_t n_stream_end = std::min<int64_t>(n, pp.n_res_l);
+    const bool res = std::is_same<T, float>::value && std::is_same<XT, float>::value && R == 1 && n > pp.n_res_l;
+    // streaming and resident groups concurrently when both are present
+    const bool fork = res && n_stream_end > pp.n_dom && pp.side[0] != nullptr;
+    hipStream_t s_str = s, s_res = s;
+    if (fork) {
+        RW_TRY(hipEventRecord(pp.fork, s));
+        RW_TRY(hipStreamWaitEvent(pp.side[0], pp.fork, 0));
+        RW_TRY(hipStreamWaitEvent(pp.side[1], pp.fork, 0));
+        s_str = pp.side[0];
+        s_res = pp.side[1];
+    }
+    hipEvent_t* tev = corr == 0 ? pp.gev : nullptr;
+    const bool any_str = n_stream_end > pp.n_dom;
+    if (tev && any_str) RW_TRY(hipEventRecord(tev[0], s_str));
     if (n_big > pp.n_dom)
-        hipLaunchKernelGGL((k_pcg<T, R, C, false, 1, XT>), dim3((unsigned)(n_big - pp.n_dom)), dim3(kThreads), 0, s,
-                           a, xt, corr, (int)pp.n_dom);
-    if (n > n_big) {
+        hipLaunchKernelGGL((k_pcg<T, R, C, false, 1, XT>), dim3((unsigned)(n_big - pp.n_dom)), dim3(kThreads), 0,
+                           s_str, a, xt, corr, (int)pp.n_dom);
+    if (n_stream_end > n_big) {
         auto k = a.schedule == 2 ? k_pcg<T, R, C, true, 2, XT> : k_pcg<T, R, C, true, 1, XT>;
         if (lds > 48 * 1024)
             RW_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(k, dim3((unsigned)(n - n_big)), dim3(kThreads), lds, s, a, xt, corr, (int)n_big);
+        hipLaunchKernelGGL(k, dim3((unsigned)(n_stream_end - n_big)), dim3(kThreads), lds, s_str, a, xt, corr,
+                           (int)n_big);
+    }
+    if (tev && any_str) RW_TRY(hipEventRecord(tev[1], s_str));
+    if constexpr (std::is_same<T, float>::value && std::is_same<XT, float>::value && R == 1) {
+        if (tev && res) RW_TRY(hipEventRecord(tev[2], s_res));
+        RW_TRY(launch_resident(a, pp.n_res_l, pp.n_res_s, pp.max_res_l, pp.plane_res_l, xt, corr, s_res));
+        RW_TRY(launch_resident(a, pp.n_res_s, n, pp.max_res_s, pp.plane_res_s, xt, corr, s_res));
+        if (tev && res) RW_TRY(hipEventRecord(tev[3], s_res));
+    }
+    if (fork) {
+        RW_TRY(hipEventRecord(pp.join[0], s_str));
+        RW_TRY(hipEventRecord(pp.join[1], s_res));
+        RW_TRY(hipStreamWaitEvent(s, pp.join[0], 0));
+        RW_TRY(hipStreamWaitEvent(s, pp.join[1], 0));
     }
     return hipGetLastError();
 }

@@ -265,3 +265,27 @@ def test_domain_solver_multi_rhs_and_cap(env):
         xi, _, _ = _run(env, di, beta=BETA, eps=EPS, tol=1e-7, precision=1)
         o = int(d["offsets"][i])
         assert np.max(np.abs(x1[o:o + boxes[i][0].size] - xi)) <= 1e-5
+
+
+def test_resident_kernel_matches_oracle_and_streaming(env):
+    """Boxes that fit one CU run an on-chip PCG (schedule 0): g and p in LDS
+    (two workgroup shapes), or p in LDS for boxes up to 32^3; schedule 1
+    forces the streaming kernels.  Both against the oracle, on ragged sizes
+    of every variant."""
+    rng = np.random.default_rng(31)
+    shapes = [(7, 13, 11), (31, 17, 33), (20, 20, 12), (3, 3, 3), (1, 1, 5), (32, 9, 32), (5, 32, 32),
+              (16, 16, 16), (32, 32, 17), (9, 1, 40), (32, 32, 32), (30, 31, 33), (26, 29, 27)]
+    boxes = [synth.random_box(rng, s, dirichlet_frac=0.03) for s in shapes]
+    d = synth.from_boxes(boxes)
+    refs = [_ref(b) for b in boxes]
+    xr, _, sr = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1, schedule=0)
+    xs, _, ss = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1, schedule=1)
+    _, x64, s64 = _run(env, d, x64=True, beta=BETA, eps=EPS, tol=1e-6, precision=2, refine_max=6,
+                       refine_tol=1e-13, inner_tol=1e-4, schedule=0)
+    for i, ref in enumerate(refs):
+        o, n = int(d["offsets"][i]), ref.size
+        assert np.max(np.abs(xr[o:o + n] - ref)) <= 1e-4, (shapes[i], sr[i])
+        assert np.max(np.abs(xr[o:o + n] - xs[o:o + n])) <= 2e-5, (shapes[i], sr[i], ss[i])
+        assert np.max(np.abs(x64[o:o + n] - ref)) <= 1e-9, (shapes[i], s64[i])
+        assert abs(int(sr["iters"][i]) - int(ss["iters"][i])) <= max(3, ss["iters"][i] // 20), (sr[i], ss[i])
+    assert np.all(np.isin(sr["status"], (0, 2))) and np.all(s64["status"] == 2) | np.all(np.isin(s64["status"], (0, 2)))
