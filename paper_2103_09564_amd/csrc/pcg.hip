@@ -180,6 +180,19 @@ __device__ __forceinline__ void march(const Box& b, const float* __restrict__ g,
     }
 }
 
+// 1 or 0 in T from integer bit operations (a select here can turn into a
+// branch around the multiplied exponential).
+template <typename T>
+__device__ __forceinline__ T unit_or_zero(bool h);
+template <>
+__device__ __forceinline__ float unit_or_zero<float>(bool h) {
+    return __uint_as_float((0u - (unsigned)h) & 0x3f800000u);
+}
+template <>
+__device__ __forceinline__ double unit_or_zero<double>(bool h) {
+    return __longlong_as_double((0ll - (long long)h) & 0x3ff0000000000000ll);
+}
+
 // Register-ring depth of the window march (3: loads two chunks ahead, 4: three).
 #ifndef RW_WINDOW_RING
 #define RW_WINDOW_RING 3
@@ -273,19 +286,23 @@ __device__ __forceinline__ void window_march(const Box& b, const float* __restri
                     acc.a[a] = T(0);
                     sv.a[a] = self[a * CH];
                 }
-                auto nb = [&](int u) {
+                // Every neighbour slot is read (the ring wraps, so u outside
+                // the box still lands in the LDS ring, which holds finite
+                // values) and its weight is multiplied by 0 or 1: branches
+                // around the exponentials would serialise the LDS reads.
+                auto nb = [&](int u, bool h) {
                     const T* p = lds + ((u >> LOG) & 3) * BS + (u & (CH - 1));
-                    const T w = W(gc, p[N * CH]);
+                    const T w = W(gc, p[N * CH]) * unit_or_zero<T>(h);
                     d += w;
 #pragma unroll
                     for (int a = 0; a < N; ++a) acc.a[a] += w * p[a * CH];
                 };
-                if (ii[q] > 0) nb(v - 1);
-                if (ii[q] + 1 < b.nx) nb(v + 1);
-                if (jj[q] > 0) nb(v - b.nx);
-                if (jj[q] + 1 < b.ny) nb(v + b.nx);
-                if (kk[q] > 0) nb(v - b.nxy);
-                if (kk[q] + 1 < b.nz) nb(v + b.nxy);
+                nb(v - 1, ii[q] > 0);
+                nb(v + 1, ii[q] + 1 < b.nx);
+                nb(v - b.nx, jj[q] > 0);
+                nb(v + b.nx, jj[q] + 1 < b.ny);
+                nb(v - b.nxy, kk[q] > 0);
+                nb(v + b.nxy, kk[q] + 1 < b.nz);
                 visit_u(v, d, acc, sv, Sl[q].ex);
             }
             vi[q] = v + CH;
@@ -1096,7 +1113,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SolveArgs a, int base) {
 // (x, or the FP64 accumulator on the FP64 path); corr = 1: FP32 correction
 // solve into dcorr from the state init_explicit left (tolerance inner_tol).
 template <typename T, int R, int C, bool kPlane, int kSched, typename XT>
-__global__ __launch_bounds__(kThreads) void k_pcg(SolveArgs a, XT* xt, int corr, int base) {
+__device__ __forceinline__ void pcg_box(SolveArgs a, XT* xt, int corr, int base) {
     __shared__ double red[kWaves * 12];
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     const int ib = base + blockIdx.x;
@@ -1114,6 +1131,13 @@ __global__ __launch_bounds__(kThreads) void k_pcg(SolveArgs a, XT* xt, int corr,
         bb[k] = st.bb[k];
     }
     const double tol = corr ? a.inner_tol : a.tol;
+    if constexpr (kPlane) {
+        // the window march reads ring slots of chunks outside the box (with
+        // weight 0): start from a ring of finite values
+        T* L = reinterpret_cast<T*>(dyn_lds);
+        for (int i = threadIdx.x; i < 4 * (R + 1) * C * kThreads; i += kThreads) L[i] = T(0);
+        __syncthreads();
+    }
     LoopEnd e;
     if constexpr (kPlane && kSched == 2)
         e = cgcg_loop<T, R, C, XT>(b, a.g, a.mask, V, xt, W, rz, rr, bb, tol, a.max_iter, red,
@@ -1139,6 +1163,19 @@ __global__ __launch_bounds__(kThreads) void k_pcg(SolveArgs a, XT* xt, int corr,
         if (e.flags & 1) st.status = RW_ST_NONFINITE;
         st.pending = corr && !(e.flags & 1) ? 1 : 0;
     }
+}
+
+template <typename T, int R, int C, bool kPlane, int kSched, typename XT>
+__global__ __launch_bounds__(kThreads) void k_pcg(SolveArgs a, XT* xt, int corr, int base) {
+    pcg_box<T, R, C, kPlane, kSched, XT>(a, xt, corr, base);
+}
+
+// The window-march kernel of the common case (FP32, one rhs, two-sweep
+// schedule, planes up to 1024 voxels) held to 128 VGPRs so that two
+// 512-thread workgroups share a CU.
+template <int C>
+__global__ __launch_bounds__(kThreads, 4) void k_pcg_w1(SolveArgs a, float* xt, int corr, int base) {
+    pcg_box<float, 1, C, true, 1, float>(a, xt, corr, base);
 }
 
 // Phase 3: FP64 true residual of the current solution (x, or x64 when
@@ -1427,6 +1464,8 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
                            s_str, a, xt, corr, (int)pp.n_dom);
     if (n_stream_end > n_big) {
         auto k = a.schedule == 2 ? k_pcg<T, R, C, true, 2, XT> : k_pcg<T, R, C, true, 1, XT>;
+        if constexpr (std::is_same<T, float>::value && std::is_same<XT, float>::value && R == 1 && C == 2)
+            if (a.schedule != 2) k = k_pcg_w1<C>;
         if (lds > 48 * 1024)
             RW_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(k, dim3((unsigned)(n_stream_end - n_big)), dim3(kThreads), lds, s_str, a, xt, corr,
