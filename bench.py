@@ -32,6 +32,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 BYTES_PER_VOXEL_ITER = 28      # read x, r, p, g; write x, r, p (FP32, one rhs)
 BETA, EPS, TOL = 128.0, 1e-6, 1e-6
 N_BOXES, SEED = 8192, 3
+EXTRAS = ("plain_sphere_64", "tubes_512_hierarchy", "blobs_512x32_adjoint", "shells_hierarchy_incremental")
 
 
 def source_hash():
@@ -45,7 +46,7 @@ def source_hash():
 def traffic_from_profile(kernel_ms_unused=None):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "k_solve_stress8192.md")
+    path = os.path.join(ROOT, "profiles", "k_pcg_w1_stress8192.md")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -256,6 +257,8 @@ def main():
     ap.add_argument("--schedule", type=int, default=0, help="CG schedule: 0 library choice, 1 two-sweep, 2 one-sweep")
     ap.add_argument("--no-extras", action="store_true", help="skip the further workloads (sphere, tubes, blobs, shells)")
     ap.add_argument("--shells-dims", default="256,256,128", help="nested-shell volume dims nx,ny,nz")
+    ap.add_argument("--only", choices=EXTRAS, default=None,
+                    help="run one further workload alone and print its JSON (for profiling; no headline line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (boxes are independent; multi-GPU sharding "
@@ -268,6 +271,20 @@ def main():
     import paper_2103_09564_amd as rwg
 
     dev = torch.device("cuda:0")
+    shell_dims = tuple(int(t) for t in args.shells_dims.split(","))
+
+    def extra(name, ctx):
+        if name == "plain_sphere_64":
+            return bench_plain_sphere(torch, rwg, dev, not args.no_cpu_baseline)
+        if name == "tubes_512_hierarchy":
+            return bench_tubes(torch, rwg, ctx)
+        if name == "blobs_512x32_adjoint":
+            return bench_blobs_adjoint(torch, rwg, dev)
+        return bench_shells(torch, rwg, ctx, dims=shell_dims)
+
+    if args.only:
+        print(json.dumps({args.only: extra(args.only, rwg.Context(0))}), flush=True)
+        return
     d = synth.stress_boxes(n=N_BOXES, seed=SEED)
     shapes, offsets = d["shapes"], d["offsets"]
     sizes = shapes.prod(axis=1).astype(np.int64)
@@ -382,15 +399,10 @@ def main():
                                              note="oracle at the same tol 1e-6; both sides carry solver error")
     if not args.no_extras:
         extras = {}
-        shell_dims = tuple(int(t) for t in args.shells_dims.split(","))
-        jobs = (("plain_sphere_64", lambda: bench_plain_sphere(torch, rwg, dev, not args.no_cpu_baseline)),
-                ("tubes_512_hierarchy", lambda: bench_tubes(torch, rwg, ctx)),
-                ("blobs_512x32_adjoint", lambda: bench_blobs_adjoint(torch, rwg, dev)),
-                ("shells_hierarchy_incremental", lambda: bench_shells(torch, rwg, ctx, dims=shell_dims)))
-        for name, job in jobs:
+        for name in EXTRAS:
             print(f"bench.py: {name}", file=sys.stderr, flush=True)
             try:
-                extras[name] = job()
+                extras[name] = extra(name, ctx)
             except Exception as e:  # a failing side workload must not hide the headline line
                 extras[name] = {"error": f"{type(e).__name__}: {e}"}
         out["workloads"] = extras

@@ -113,7 +113,13 @@ def bricks_array(shapes, offsets):
 
 
 def _ptr(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+    """Device pointer of a tensor; the library reads dense buffers, so views
+    with gaps are rejected rather than read wrongly."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("librwseg takes contiguous tensors (call .contiguous() first)")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _stream(stream):

@@ -70,19 +70,48 @@ struct SeedEntry {
 
 // ---- pyramid ---------------------------------------------------------------
 
-__global__ void k_minmax_u16(const uint16_t* __restrict__ v, int64_t n, unsigned* mm) {
+// Global min and max of a uint16 volume: grid-stride, 8 voxels per 16-byte
+// load (when the volume is 16-byte aligned), then wave and workgroup
+// reductions and one atomic pair per workgroup (a launch has at most
+// kMinMaxBlocks workgroups, so the atomics stay few).
+constexpr int kMinMaxBlocks = 2048;
+
+__global__ __launch_bounds__(256) void k_minmax_u16(const uint16_t* __restrict__ v, int64_t n, int aligned16,
+                                                    unsigned* mm) {
+    __shared__ unsigned red[2][4];
     unsigned lo = 0xffffu, hi = 0u;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n8 = aligned16 ? n / 8 : 0;
+    const uint4* v8 = reinterpret_cast<const uint4*>(v);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n8; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 q = v8[i];
+        const unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const unsigned a = w[k] & 0xffffu, b = w[k] >> 16;
+            lo = min(lo, min(a, b));
+            hi = max(hi, max(a, b));
+        }
+    }
+    for (int64_t i = n8 * 8 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
         const unsigned a = v[i];
-        lo = a < lo ? a : lo;
-        hi = a > hi ? a : hi;
+        lo = min(lo, a);
+        hi = max(hi, a);
     }
     for (int o = 32; o >= 1; o >>= 1) {
-        const unsigned l2 = __shfl_xor(lo, o, 64), h2 = __shfl_xor(hi, o, 64);
-        lo = l2 < lo ? l2 : lo;
-        hi = h2 > hi ? h2 : hi;
+        lo = min(lo, (unsigned)__shfl_xor(lo, o, 64));
+        hi = max(hi, (unsigned)__shfl_xor(hi, o, 64));
     }
     if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = lo;
+        red[1][threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)blockDim.x / 64; ++w) {
+            lo = min(lo, red[0][w]);
+            hi = max(hi, red[1][w]);
+        }
         atomicMin(&mm[0], lo);
         atomicMax(&mm[1], hi);
     }
@@ -831,7 +860,9 @@ int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims
         hipError_t e = hipMalloc((void**)&mm, sizeof(init));
         if (e == hipSuccess) e = hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_minmax_u16, dim3(grid_for(n0, T)), dim3(T), 0, s, (const uint16_t*)vol, n0, mm);
+            const unsigned gmm = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kMinMaxBlocks, (n0 / 8 + 255) / 256));
+            const int al16 = ((uintptr_t)vol & 15u) == 0 ? 1 : 0;
+            hipLaunchKernelGGL(k_minmax_u16, dim3(gmm), dim3(256), 0, s, (const uint16_t*)vol, n0, al16, mm);
             hipLaunchKernelGGL(k_normalize_u16, dim3(grid_for(n0, T)), dim3(T), 0, s, (const uint16_t*)vol, n0, mm,
                                p->data[0]);
             e = hipGetLastError();

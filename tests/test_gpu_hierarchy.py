@@ -92,6 +92,11 @@ def test_pyramid_u16_and_f32(env):
         got = pyr.level(l).cpu().numpy()
         assert got.shape == ref[l].shape
         assert np.max(np.abs(got - ref[l])) < 2e-6
+    # a volume that starts 2 bytes past an aligned address (scalar loads in the min-max)
+    flat = torch.from_numpy(np.concatenate([[7], v.ravel()]).astype(np.uint16)).cuda()
+    pyr = rwg.Pyramid(ctx, flat[1:].view(v.shape), 2)
+    for l in range(2):
+        assert np.max(np.abs(pyr.level(l).cpu().numpy() - ref[l])) < 2e-6
     f = (rng.random((16, 12, 20)) * 1.4 - 0.2).astype(np.float32)
     pyr = rwg.Pyramid(ctx, torch.from_numpy(f).cuda(), 2)
     ref = H.pyramid(f, 2)
