@@ -117,3 +117,36 @@ def test_rwsolve_autograd_and_finite_differences(env, blobs):
         num += (ag[v] - fd) ** 2
         den += fd ** 2
     assert np.sqrt(num / den) <= 1e-3, np.sqrt(num / den)
+
+
+def test_adjoint_on_resident_and_ragged_boxes(env):
+    """Adjoint gradients on boxes small enough for the LDS-resident PCG and on
+    ragged shapes, with a fixed random dl/dx, against the oracle."""
+    torch, rwg = env
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(41)
+    shapes = [(16, 16, 16), (32, 9, 32), (5, 32, 32), (13, 7, 19), (33, 31, 30)]
+    boxes = [synth.random_box(rng, s, dirichlet_frac=0.04) for s in shapes]
+    d = synth.from_boxes(boxes)
+    g = torch.from_numpy(d["g"]).to(dev)
+    m = torch.from_numpy(d["mask"]).to(dev)
+    x = torch.from_numpy(d["x"]).to(dev)
+    beta = 96.0
+    rwg.solve_bricks(g, m, x, d["shapes"], d["offsets"], beta=beta, eps=EPS, tol=1e-7, precision=2,
+                     refine_max=4, refine_tol=1e-10)
+    dl_dx_np = rng.standard_normal(d["x"].size).astype(np.float32)
+    dl_dx = torch.from_numpy(dl_dx_np).to(dev)
+    dl_dg, dl_db, st = rwg.solve_bricks_adjoint(g, m, x, dl_dx, d["shapes"], d["offsets"], beta=beta, eps=EPS,
+                                                tol=1e-7)
+    torch.cuda.synchronize()
+    dg = dl_dg.cpu().numpy()
+    tot = 0.0
+    for i, (gb, mb, xb) in enumerate(boxes):
+        o = int(d["offsets"][i])
+        xo = orw.solve_box(gb, mb, xb, beta, EPS, method="pcg", tol=1e-14)
+        og, odb, _ = oadj.adjoint_gradients(gb, mb, xo, dl_dx_np[o:o + gb.size].reshape(gb.shape), beta, EPS)
+        tot += odb
+        rel = np.linalg.norm(dg[o:o + gb.size] - og.ravel()) / np.linalg.norm(og)
+        assert rel <= 1e-3, (shapes[i], rel)
+    assert abs(float(dl_db.cpu()[0]) - tot) <= 1e-3 * abs(tot)
+    assert np.all(rwg.stats_to_numpy(st)["status"] == 0)

@@ -212,3 +212,61 @@ def test_segment_argument_errors(env):
         rwg.segment(pyr, [[1, 1, 1, 1]], n_classes=9)
     with pytest.raises(rwg.RWError):
         rwg.segment(pyr, [[1, 1, 1, 1]], brick=1)
+
+
+def test_conflicting_labels_match_oracle(env):
+    """Two labels on one voxel leave it unseeded and mark every brick whose box
+    holds it cfl (never prunable); flags and maps against the oracle."""
+    n, levels = 64, 3
+    vol = _sphere_volume(n, "f32", seed=11)
+    seeds = _seeds(n, np.random.default_rng(12))
+    c = (n - 1) / 2
+    extra = [[c + 0.3, 0.8 * c + 0.3, 1.1 * c, 0], [c + 0.3, 0.8 * c + 0.3, 1.1 * c, 1],   # inside the sphere
+             [5.5, 60.2, 9.0, 1], [5.5, 60.2, 9.0, 0]]                                  # far outside it
+    seeds = np.concatenate([seeds, np.array(extra, dtype=np.float64)])
+    kw = dict(brick=8, beta=64.0, t_bin=0.01, t_hom=0.3)
+    p = _oracle_params(levels=levels, **kw)
+    ores = H.segment(vol, seeds, p)
+    assert any(np.any(cf) for cf in ores.cfl)
+    _, res, gmaps, gflags = _gpu_run(env, vol, seeds, levels, precision=0, tol=1e-12, **kw)
+    _compare(ores.maps, ores, gmaps, gflags, 1e-6, exact_flags=True)
+    for l in range(levels):
+        reached = ores.computed[l]
+        assert np.array_equal(((gflags[l] & 4) != 0) & reached, ores.cfl[l] & reached), f"level {l}: cfl differs"
+        assert not np.any(((gflags[l] & 4) != 0) & ((gflags[l] & 2) != 0)), "a cfl brick was marked prunable"
+
+
+def test_tube_volume_full_size_properties(env):
+    """The 512^3 tube pipeline (4 levels, s = 32, e = 1.25, dt pruning at
+    t_bin 0.49, mixed tol 1e-5) at full size, where the oracle is too slow:
+    properties that hold at any size.  Maps lie in [0, 1] (maximum
+    principle); every label voxel of a reached brick keeps its value; a brick
+    is reached exactly when its parent is reached and not prunable; every
+    solve converged."""
+    import synth
+    torch, rwg, ctx = env
+    vol, seeds, _ = synth.tube_volume(n=512, n_tubes=40, n_fg=20, n_bg=200, seed=2)
+    levels = 4
+    pyr, res, maps, flags = _gpu_run(env, vol, seeds, levels, brick=32, expand=1.25, beta=128.0, eps=1e-6,
+                                     tol=1e-5, precision=1, n_classes=2, prune_hom=0, prune_dt=1, t_bin=0.49)
+    st = res.stats()
+    assert st["not_converged"] == [0] * levels
+    for l in range(levels):
+        assert maps[l].min() >= -1e-6 and maps[l].max() <= 1 + 1e-6, l
+    assert np.all((flags[levels - 1] & 1) != 0)
+    for l in range(levels - 1):
+        par = flags[l + 1]
+        open_par = ((par & 1) != 0) & ((par & 2) == 0)
+        nz, ny, nx = flags[l].shape
+        expect = open_par[np.arange(nz)[:, None, None] // 2, np.arange(ny)[None, :, None] // 2,
+                          np.arange(nx)[None, None, :] // 2]
+        assert np.array_equal((flags[l] & 1) != 0, expect), f"level {l}: reached bricks"
+    # labels at level 0 (voxel floor(q)); a voxel carrying both labels is unseeded
+    vox = np.floor(seeds[:, :3]).astype(np.int64)
+    keys = {}
+    for (x, y, z), lab in zip(vox, seeds[:, 3].astype(int)):
+        keys.setdefault((x, y, z), set()).add(lab)
+    m0 = maps[0][..., 0]
+    for (x, y, z), labs in keys.items():
+        if len(labs) == 1 and (flags[0][z // 32, y // 32, x // 32] & 1):
+            assert m0[z, y, x] == float(next(iter(labs))), (x, y, z, labs, m0[z, y, x])
