@@ -180,6 +180,11 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
         int64_t& pl = i < pp.n_res_s ? pp.plane_res_l : pp.plane_res_s;
         pl = std::max<int64_t>(pl, (int64_t)b.nx * b.ny);
     }
+    pp.plane_aligned = 1;
+    for (int64_t i = pp.n_big; i < pp.n_res_l; ++i) {
+        const auto& b = (*list)[(size_t)i];
+        if ((int64_t)rwk::plane_max(cols) % ((int64_t)b.nx * b.ny) != 0) pp.plane_aligned = 0;
+    }
     pp.host = list->data();
     return pp;
 }

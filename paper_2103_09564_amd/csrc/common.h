@@ -120,6 +120,7 @@ struct AdjointArgs {
 struct PlanePlan {
     int use;
     int cols;
+    int plane_aligned;  // every window-march box has CH % (nx*ny) == 0 (CH = cols * 512)
     int64_t n_big;
     int64_t n_dom;
     const BrickDev* host;

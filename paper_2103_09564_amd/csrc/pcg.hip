@@ -217,7 +217,10 @@ struct Slot {
     unsigned m;
 };
 
-template <typename T, int N, int RN, int NX, int C, typename LoadRaw, typename Prep, typename LoadX,
+// kAligned: the chunk holds a whole number of z-planes (CH % (nx*ny) == 0),
+// so each thread keeps its (i, j) from chunk to chunk and advances k by
+// CH / (nx*ny): the x and y neighbour tests are computed once.
+template <typename T, int N, int RN, int NX, int C, bool kAligned, typename LoadRaw, typename Prep, typename LoadX,
           typename VisitU>
 __device__ __forceinline__ void window_march(const Box& b, const float* __restrict__ g,
                                              const uint8_t* __restrict__ m, const Weight<T>& W,
@@ -234,6 +237,7 @@ __device__ __forceinline__ void window_march(const Box& b, const float* __restri
     const int NC = (nv + CH - 1) / CH;
     const int dk = CH / b.nxy, rem = CH - dk * b.nxy, dj = rem / b.nx, di = rem - dj * b.nx;
     int vi[C], ii[C], jj[C], kk[C];
+    unsigned xy[C];  // kAligned: bits 0..3 = neighbour -x, +x, -y, +y inside the box
 #pragma unroll
     for (int q = 0; q < C; ++q) {
         const int v = q * kThreads + threadIdx.x;
@@ -242,6 +246,8 @@ __device__ __forceinline__ void window_march(const Box& b, const float* __restri
         const int r = v - kk[q] * b.nxy;
         jj[q] = r / b.nx;
         ii[q] = r - jj[q] * b.nx;
+        xy[q] = (ii[q] > 0 ? 1u : 0u) | (ii[q] + 1 < b.nx ? 2u : 0u) | (jj[q] > 0 ? 4u : 0u) |
+                (jj[q] + 1 < b.ny ? 8u : 0u);
     }
     using S = Slot<T, RN, NX>;
     S r0[C], r1[C], r2[C], r3[C];
@@ -297,25 +303,34 @@ __device__ __forceinline__ void window_march(const Box& b, const float* __restri
 #pragma unroll
                     for (int a = 0; a < N; ++a) acc.a[a] += w * p[a * CH];
                 };
-                nb(v - 1, ii[q] > 0);
-                nb(v + 1, ii[q] + 1 < b.nx);
-                nb(v - b.nx, jj[q] > 0);
-                nb(v + b.nx, jj[q] + 1 < b.ny);
+                if constexpr (kAligned) {
+                    nb(v - 1, xy[q] & 1u);
+                    nb(v + 1, xy[q] & 2u);
+                    nb(v - b.nx, xy[q] & 4u);
+                    nb(v + b.nx, xy[q] & 8u);
+                } else {
+                    nb(v - 1, ii[q] > 0);
+                    nb(v + 1, ii[q] + 1 < b.nx);
+                    nb(v - b.nx, jj[q] > 0);
+                    nb(v + b.nx, jj[q] + 1 < b.ny);
+                }
                 nb(v - b.nxy, kk[q] > 0);
                 nb(v + b.nxy, kk[q] + 1 < b.nz);
                 visit_u(v, d, acc, sv, Sl[q].ex);
             }
             vi[q] = v + CH;
-            ii[q] += di;
-            jj[q] += dj;
             kk[q] += dk;
-            if (ii[q] >= b.nx) {
-                ii[q] -= b.nx;
-                jj[q] += 1;
-            }
-            if (jj[q] >= b.ny) {
-                jj[q] -= b.ny;
-                kk[q] += 1;
+            if constexpr (!kAligned) {
+                ii[q] += di;
+                jj[q] += dj;
+                if (ii[q] >= b.nx) {
+                    ii[q] -= b.nx;
+                    jj[q] += 1;
+                }
+                if (jj[q] >= b.ny) {
+                    jj[q] -= b.ny;
+                    kk[q] += 1;
+                }
             }
         }
     };
@@ -494,7 +509,7 @@ __device__ void true_residual(const Box& b, const float* __restrict__ g, const u
 }
 
 // Sweep A: p_new = z + beta p_old, sigma = p_new . L_UU p_new.
-template <typename T, int R, int C>
+template <typename T, int R, int C, bool kAligned>
 __device__ void sweep_pq(const Box& b, const float* __restrict__ g, const uint8_t* __restrict__ m,
                          const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
                          const T (&bk)[R], const Weight<T>& W, double (&sig)[R], T* lds, bool plane) {
@@ -532,7 +547,7 @@ __device__ void sweep_pq(const Box& b, const float* __restrict__ g, const uint8_
                 nb_[v * R + k] = self.a[k];
             }
         };
-        window_march<T, R, 2 * R, 0, C>(b, g, m, W, lds, raw, prep, nox, vp);
+        window_march<T, R, 2 * R, 0, C, kAligned>(b, g, m, W, lds, raw, prep, nox, vp);
         return;
     }
     auto vu = [&](int64_t v, T d, const Val<T, R>& acc, const Val<T, R>& self) {
@@ -551,7 +566,7 @@ __device__ void sweep_pq(const Box& b, const float* __restrict__ g, const uint8_
 }
 
 // Sweep B: q = L_UU p, x += alpha p, r -= alpha q, z = r/d, rho' and ||r||^2.
-template <typename T, int R, int C, typename XT>
+template <typename T, int R, int C, bool kAligned, typename XT>
 __device__ void sweep_update(const Box& b, const float* __restrict__ g, const uint8_t* __restrict__ m,
                              const T* __restrict__ p, Vecs<T, R> V, XT* __restrict__ xt,
                              const T (&al)[R], const Weight<T>& W, double (&rz)[R], double (&rr)[R],
@@ -597,7 +612,7 @@ __device__ void sweep_update(const Box& b, const float* __restrict__ g, const ui
             }
         };
         auto prep = [&](const Val<T, R>& o) { return o; };
-        window_march<T, R, R, 2 * R, C>(b, g, m, W, lds, ld, prep, lx, vp);
+        window_march<T, R, R, 2 * R, C, kAligned>(b, g, m, W, lds, ld, prep, lx, vp);
         return;
     }
     auto vu = [&](int64_t v, T d, const Val<T, R>& acc, const Val<T, R>& self) {
@@ -627,7 +642,7 @@ struct LoopEnd {
     int flags;  // 1: non-finite / breakdown, 2: iteration cap
 };
 
-template <typename T, int R, int C, bool kPlane, typename XT>
+template <typename T, int R, int C, bool kPlane, bool kAligned, typename XT>
 __device__ LoopEnd pcg_loop(const Box& b, const float* __restrict__ g, const uint8_t* __restrict__ m,
                             Vecs<T, R> V, XT* __restrict__ xt, const Weight<T>& W, double (&rz)[R],
                             double (&rr)[R], const double (&bb)[R], double tol, int max_iter, double* red,
@@ -660,7 +675,7 @@ __device__ LoopEnd pcg_loop(const Box& b, const float* __restrict__ g, const uin
         double sig[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) sig[k] = 0.0;
-        sweep_pq<T, R, C>(b, g, m, V.z, pold, pnew, bk, W, sig, lds, kPlane);
+        sweep_pq<T, R, C, kAligned>(b, g, m, V.z, pold, pnew, bk, W, sig, lds, kPlane);
         block_sum<R>(sig, red);
         T al[R];
         bool bad = false;
@@ -677,7 +692,7 @@ __device__ LoopEnd pcg_loop(const Box& b, const float* __restrict__ g, const uin
         double rzn[R], rrn[R], acc[2 * R];
 #pragma unroll
         for (int k = 0; k < R; ++k) rzn[k] = rrn[k] = 0.0;
-        sweep_update<T, R, C, XT>(b, g, m, pnew, V, xt, al, W, rzn, rrn, lds, kPlane);
+        sweep_update<T, R, C, kAligned, XT>(b, g, m, pnew, V, xt, al, W, rzn, rrn, lds, kPlane);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             acc[k] = rzn[k];
@@ -937,7 +952,7 @@ __device__ void cgcg_init_w(const Box& b, const float* __restrict__ g, const uin
             zb[v * R + k] = w;
         }
     };
-    window_march<T, R, R, 0, C>(b, g, m, W, lds, raw, prep, nox, vp);
+    window_march<T, R, R, 0, C, false>(b, g, m, W, lds, raw, prep, nox, vp);
 }
 
 template <typename T, int R, int C, typename XT>
@@ -1112,7 +1127,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SolveArgs a, int base) {
 // Phase 2: the PCG loop on every active box.  corr = 0: main solve into xt
 // (x, or the FP64 accumulator on the FP64 path); corr = 1: FP32 correction
 // solve into dcorr from the state init_explicit left (tolerance inner_tol).
-template <typename T, int R, int C, bool kPlane, int kSched, typename XT>
+template <typename T, int R, int C, bool kPlane, int kSched, typename XT, bool kAligned = false>
 __device__ __forceinline__ void pcg_box(SolveArgs a, XT* xt, int corr, int base) {
     __shared__ double red[kWaves * 12];
     extern __shared__ __align__(16) unsigned char dyn_lds[];
@@ -1143,10 +1158,10 @@ __device__ __forceinline__ void pcg_box(SolveArgs a, XT* xt, int corr, int base)
         e = cgcg_loop<T, R, C, XT>(b, a.g, a.mask, V, xt, W, rz, rr, bb, tol, a.max_iter, red,
                                    reinterpret_cast<T*>(dyn_lds));
     else if constexpr (kPlane)
-        e = pcg_loop<T, R, C, true, XT>(b, a.g, a.mask, V, xt, W, rz, rr, bb, tol, a.max_iter, red,
+        e = pcg_loop<T, R, C, true, kAligned, XT>(b, a.g, a.mask, V, xt, W, rz, rr, bb, tol, a.max_iter, red,
                                         reinterpret_cast<T*>(dyn_lds));
     else
-        e = pcg_loop<T, R, C, false, XT>(b, a.g, a.mask, V, xt, W, rz, rr, bb, tol, a.max_iter, red,
+        e = pcg_loop<T, R, C, false, false, XT>(b, a.g, a.mask, V, xt, W, rz, rr, bb, tol, a.max_iter, red,
                                          reinterpret_cast<T*>(dyn_lds));
     if (threadIdx.x == 0) {
         if (corr) {
@@ -1173,9 +1188,9 @@ __global__ __launch_bounds__(kThreads) void k_pcg(SolveArgs a, XT* xt, int corr,
 // The window-march kernel of the common case (FP32, one rhs, two-sweep
 // schedule, planes up to 1024 voxels) held to 128 VGPRs so that two
 // 512-thread workgroups share a CU.
-template <int C>
+template <int C, bool kAligned>
 __global__ __launch_bounds__(kThreads, 4) void k_pcg_w1(SolveArgs a, float* xt, int corr, int base) {
-    pcg_box<float, 1, C, true, 1, float>(a, xt, corr, base);
+    pcg_box<float, 1, C, true, 1, float, kAligned>(a, xt, corr, base);
 }
 
 // Phase 3: FP64 true residual of the current solution (x, or x64 when
@@ -1465,7 +1480,7 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
     if (n_stream_end > n_big) {
         auto k = a.schedule == 2 ? k_pcg<T, R, C, true, 2, XT> : k_pcg<T, R, C, true, 1, XT>;
         if constexpr (std::is_same<T, float>::value && std::is_same<XT, float>::value && R == 1 && C == 2)
-            if (a.schedule != 2) k = k_pcg_w1<C>;
+            if (a.schedule != 2) k = pp.plane_aligned ? k_pcg_w1<C, true> : k_pcg_w1<C, false>;
         if (lds > 48 * 1024)
             RW_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(k, dim3((unsigned)(n_stream_end - n_big)), dim3(kThreads), lds, s_str, a, xt, corr,
