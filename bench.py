@@ -73,6 +73,22 @@ def _oracle_worker(args):
     return g.size * it, out
 
 
+def _oracle_exact(args):
+    from threadpoolctl import threadpool_limits
+    from oracle import rw as orw
+    g, m, x = args
+    with threadpool_limits(1):
+        return orw.solve_box(g, m, x, BETA, EPS, method="pcg", tol=1e-13).ravel()
+
+
+def oracle_exact_sample(boxes, idx):
+    """cpu_baseline leg: the exact solutions (oracle PCG to 1e-13) of the
+    sampled boxes, for the error of each GPU path against the true answer."""
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(os.cpu_count() or 1, 16)) as pool:
+        return dict(zip(idx, pool.map(_oracle_exact, [boxes[i] for i in idx], chunksize=1)))
+
+
 def cpu_baseline(boxes, seconds=15.0):
     """The FP64 oracle (sparse Laplacian + Jacobi-PCG at the same tol) on a
     time-bounded sample of the same boxes, one box per process."""
@@ -158,6 +174,14 @@ def bench_plain_sphere(torch, rwg, dev, cpu_leg):
         out[name] = r
     if ref is not None:
         out["oracle_exact_s"] = ref_s
+        # cpu_baseline leg: the oracle at the configuration's own tolerance (FP64, 1e-6)
+        from oracle import rw as orw
+        t0 = time.time()
+        A, b_, U, M = orw.dirichlet_system(g, m, x0, BETA, EPS)
+        _, it, _ = orw.pcg(A, b_, tol=1e-6)
+        el = time.time() - t0
+        out["cpu_oracle_tol1e-6"] = {"s": el, "iters": int(it), "voxel_iters_per_s": g.size * it / el,
+                                     "cores": 1}
     return out
 
 
@@ -189,7 +213,7 @@ def bench_tubes(torch, rwg, ctx, n=512, n_tubes=40, levels=4):
             "generate_s": gen_s}
 
 
-def bench_blobs_adjoint(torch, rwg, dev, n=512):
+def bench_blobs_adjoint(torch, rwg, dev, n=512, cpu_leg=False):
     """Forward (mixed + FP64 refinement) and adjoint on 512 two-blob 32^3
     boxes, beta 64; loss = mean BCE over unseeded voxels."""
     import synth
@@ -212,7 +236,24 @@ def bench_blobs_adjoint(torch, rwg, dev, n=512):
         torch, lambda: rwg.solve_bricks_adjoint(g, m, x, dl_dx, d["shapes"], d["offsets"], **kw), 3)
     s, sa = rwg.stats_to_numpy(st), rwg.stats_to_numpy(sta)
     vox = 32 ** 3
+    cpu = None
+    if cpu_leg:
+        # cpu_baseline leg: oracle forward (PCG, tol 1e-6) and adjoint (sparse direct) on 2 boxes
+        from oracle import adjoint as oadj
+        from oracle import rw as orw
+        yh = d["gt"]
+        t0 = time.time()
+        for i in range(2):
+            gb, mb, xb = d["boxes"][i]
+            o = int(d["offsets"][i])
+            xo = orw.solve_box(gb, mb, xb, 64.0, EPS, method="pcg", tol=1e-6)
+            _, grad = oadj.bce_loss(xo, yh[o:o + gb.size].reshape(gb.shape), mb)
+            oadj.adjoint_gradients(gb, mb, xo, grad, 64.0, EPS)
+        el = time.time() - t0
+        cpu = {"s_per_box": el / 2, "extrapolated_s_for_all": el / 2 * n, "cores": 1,
+               "sample": "2 boxes, one process; the total is extrapolated"}
     return {"workload": f"{n} two-blob boxes 32^3, beta 64, forward mixed tol 1e-6 + adjoint tol 1e-6",
+            "cpu_oracle": cpu,
             "forward_ms": f_ms, "adjoint_ms": b_ms,
             "forward_voxel_iters_per_s": float(vox * (s["iters"] + s["refine_iters"]).sum() / (f_ms / 1e3)),
             "adjoint_voxel_iters_per_s": float(vox * sa["iters"].sum() / (b_ms / 1e3)),
@@ -279,7 +320,7 @@ def main():
         if name == "tubes_512_hierarchy":
             return bench_tubes(torch, rwg, ctx)
         if name == "blobs_512x32_adjoint":
-            return bench_blobs_adjoint(torch, rwg, dev)
+            return bench_blobs_adjoint(torch, rwg, dev, cpu_leg=not args.no_cpu_baseline)
         return bench_shells(torch, rwg, ctx, dims=shell_dims)
 
     if args.only:
@@ -395,6 +436,19 @@ def main():
             err["mixed"] = max(err["mixed"], float(np.max(np.abs(mixed["x"][o:o + n] - ref))))
             if fp64 is not None:
                 err["fp64"] = max(err["fp64"], float(np.max(np.abs(fp64["x"][o:o + n] - ref))))
+        # against the exact solution (every 64th box): the "at 1e-4 error" of the metric
+        idx = list(range(0, len(d["boxes"]), 64))
+        exact = oracle_exact_sample(d["boxes"], idx)
+        ex = {"mixed": 0.0}
+        if fp64 is not None:
+            ex["fp64"] = 0.0
+        for i, ref in exact.items():
+            o, n = int(offsets[i]), int(sizes[i])
+            ex["mixed"] = max(ex["mixed"], float(np.max(np.abs(mixed["x"][o:o + n] - ref))))
+            if fp64 is not None:
+                ex["fp64"] = max(ex["fp64"], float(np.max(np.abs(fp64["x"][o:o + n] - ref))))
+        out["max_abs_err_vs_exact"] = dict(ex, boxes=len(exact),
+                                           note="oracle PCG to 1e-13 on every 64th box; both GPU paths at tol 1e-6")
         out["max_abs_diff_vs_oracle"] = dict(err, boxes=len(sols),
                                              note="oracle at the same tol 1e-6; both sides carry solver error")
     if not args.no_extras:
