@@ -127,7 +127,7 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     const int64_t n = (int64_t)list->size();
     rwk::PlanePlan pp{};
     pp.cols = 2;
-    pp.n_big = pp.n_res_l = pp.n_res_s = n;
+    pp.n_big = pp.n_res = n;
     const bool res_ok = nrhs == 1 && !fp64 && (schedule == 0 || schedule == 3);
     const int64_t res_small = rwk::kResSmallVox;
     int widest = 0;
@@ -137,8 +137,9 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     if (rwk::plane_lds_bytes(nrhs, fp64, cols) > ctx->lds_limit) cols = 2;
     const bool use = rwk::plane_lds_bytes(nrhs, fp64, cols) <= ctx->lds_limit;
     const int lim = use ? rwk::plane_max(cols) : 0;
-    // group 0: domain solver, 1: global march, 2: plane march, 3: resident,
-    // 4: resident small boxes; the list is largest-first
+    // group 0: domain solver, 1: global march, 2: plane march, 3: resident
+    // (g, p), 4: resident (weights), 5: resident (weights) small boxes; the
+    // list is largest-first
     std::vector<uint8_t> grp(list->size());
     int n_dom = 0;
     for (size_t i = 0; i < list->size(); ++i) {
@@ -150,8 +151,10 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
         if (dom && n_dom < rwk::kDomMaxBoxes) {
             grp[i] = 0;
             ++n_dom;
+        } else if (res_ok && rwk::resident_w_fits(b, ctx->lds_limit)) {
+            grp[i] = vox <= res_small ? 5 : 4;
         } else if (res_ok && rwk::resident_fits(b, ctx->lds_limit)) {
-            grp[i] = vox <= res_small ? 4 : 3;
+            grp[i] = 3;
         } else {
             grp[i] = wide ? 1 : 2;
         }
@@ -160,7 +163,7 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     std::iota(idx.begin(), idx.end(), size_t(0));
     std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return grp[a] < grp[b]; });
     std::vector<rwk::BrickDev> sorted(list->size());
-    int64_t cnt[5] = {0, 0, 0, 0, 0};
+    int64_t cnt[6] = {0, 0, 0, 0, 0, 0};
     for (size_t i = 0; i < idx.size(); ++i) {
         sorted[i] = (*list)[idx[i]];
         cnt[grp[idx[i]]] += 1;
@@ -170,18 +173,26 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     pp.cols = cols;
     pp.n_dom = n_dom;
     pp.n_big = cnt[0] + cnt[1];
-    pp.n_res_l = pp.n_big + cnt[2];
-    pp.n_res_s = pp.n_res_l + cnt[3];
-    auto vox = [&](int64_t i) { const auto& b = (*list)[(size_t)i]; return (int64_t)b.nx * b.ny * b.nz; };
-    pp.max_res_l = cnt[3] ? vox(pp.n_res_l) : 0;
-    pp.max_res_s = cnt[4] ? vox(pp.n_res_s) : 0;
-    for (int64_t i = pp.n_res_l; i < n; ++i) {
-        const auto& b = (*list)[(size_t)i];
-        int64_t& pl = i < pp.n_res_s ? pp.plane_res_l : pp.plane_res_s;
-        pl = std::max<int64_t>(pl, (int64_t)b.nx * b.ny);
+    pp.n_res = pp.n_big + cnt[2];
+    pp.n_rl = 0;
+    int64_t b0 = pp.n_res;
+    for (int gi = 3; gi <= 5; ++gi) {
+        if (cnt[gi] == 0) continue;
+        rwk::PlanePlan::ResLaunch& L = pp.rl[pp.n_rl++];
+        L.b0 = b0;
+        L.b1 = b0 + cnt[gi];
+        L.kind = gi == 3 ? 0 : 1;
+        L.max_voxels = 0;
+        L.max_plane = 0;
+        for (int64_t i = L.b0; i < L.b1; ++i) {
+            const auto& b = (*list)[(size_t)i];
+            L.max_voxels = std::max<int64_t>(L.max_voxels, (int64_t)b.nx * b.ny * b.nz);
+            L.max_plane = std::max<int64_t>(L.max_plane, (int64_t)b.nx * b.ny);
+        }
+        b0 = L.b1;
     }
     pp.plane_aligned = 1;
-    for (int64_t i = pp.n_big; i < pp.n_res_l; ++i) {
+    for (int64_t i = pp.n_big; i < pp.n_res; ++i) {
         const auto& b = (*list)[(size_t)i];
         if ((int64_t)rwk::plane_max(cols) % ((int64_t)b.nx * b.ny) != 0) pp.plane_aligned = 0;
     }
@@ -334,7 +345,7 @@ int rw_solve_plan(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, 
         const int32_t slot = list[(size_t)i].slot;
         path[slot] = i < pp.n_dom ? RW_PATH_DOMAIN
                      : i < pp.n_big ? RW_PATH_STREAM_GLOBAL
-                     : i < pp.n_res_l ? RW_PATH_STREAM
+                     : i < pp.n_res ? RW_PATH_STREAM
                                       : RW_PATH_RESIDENT;
     }
     return RW_OK;
@@ -422,7 +433,7 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
         if (e != hipSuccess) return hip_fail(ctx, e, "recording timing event");
         ev = &ctx->ev[1];
         pp.gev = ctx->gev;
-        ctx->gev_used = (pp.n_res_l > pp.n_dom ? 1 : 0) | (pp.n_res_l < n_bricks ? 2 : 0);
+        ctx->gev_used = (pp.n_res > pp.n_dom ? 1 : 0) | (pp.n_res < n_bricks ? 2 : 0);
     }
     e = rwk::launch_solve(a, n_bricks, R, fp64, pp, s, ev);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching solve kernel");

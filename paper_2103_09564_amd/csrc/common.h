@@ -124,13 +124,19 @@ struct PlanePlan {
     int64_t n_big;
     int64_t n_dom;
     const BrickDev* host;
-    // LDS-resident PCG (one rhs, FP32): [n_res_l, n_res_s) the larger boxes,
-    // [n_res_s, n) the small ones (launched apart so that their LDS size lets
-    // several workgroups share a CU); max_res_*: the largest box of each group
-    // (voxels).  Without resident boxes both are n.
-    int64_t n_res_l, n_res_s;
-    int64_t max_res_l, max_res_s;
-    int64_t plane_res_l, plane_res_s;  // widest nx*ny of each group
+    // LDS-resident PCG (one rhs, FP32): boxes [n_res, n), in up to three
+    // launches (largest box first within each): (g, p) in LDS, then
+    // precomputed weights and p in LDS for larger and for small boxes
+    // (launched apart so that their LDS size lets several workgroups share
+    // a CU).  Without resident boxes n_res = n.
+    int64_t n_res;
+    int n_rl;
+    struct ResLaunch {
+        int64_t b0, b1;       // launch-list range
+        int64_t max_voxels;   // largest box of the range
+        int64_t max_plane;    // widest nx*ny of the range
+        int kind;             // 0: (g, p) kernel, 1: weights kernel
+    } rl[3];
     // when set, the streaming and resident groups run on these two streams
     // (forked from and joined back into the caller's stream)
     hipStream_t side[2];
@@ -143,10 +149,12 @@ struct PlanePlan {
 // LDS-resident PCG (resident.hip).
 constexpr int kResThreads = 512;
 constexpr int kResMaxVpt = 34;    // voxels per thread: boxes up to 17408 voxels (32 x 32 x 17)
-constexpr int kResSmallVox = 5120;  // the small group: at most 10 voxels per thread
-bool resident_fits(const BrickDev& b, size_t lds_limit);
+constexpr int kResMaxVptW = 20;   // weights kernel: boxes up to 10240 voxels
+constexpr int kResSmallVox = 5120;  // the small weights group: at most 10 voxels per thread
+bool resident_fits(const BrickDev& b, size_t lds_limit);      // (g, p) kernel
+bool resident_w_fits(const BrickDev& b, size_t lds_limit);    // weights kernel
 hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_voxels, int64_t max_plane,
-                           float* xt, int corr, hipStream_t s);
+                           int kind, float* xt, int corr, hipStream_t s);
 
 size_t plane_lds_bytes(int nrhs, bool fp64, int cols);
 

@@ -1459,8 +1459,8 @@ template <typename T, int R, int C, typename XT>
 static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big, XT* xt, int corr, size_t lds,
                                    const PlanePlan& pp, hipStream_t s) {
     for (int64_t i = 0; i < pp.n_dom; ++i) RW_TRY((domain_pcg<T, R, XT>(a, (int)i, pp.host[i], xt, corr, s)));
-    const int64_t n_stream_end = std::min<int64_t>(n, pp.n_res_l);
-    const bool res = std::is_same<T, float>::value && std::is_same<XT, float>::value && R == 1 && n > pp.n_res_l;
+    const int64_t n_stream_end = std::min<int64_t>(n, pp.n_res);
+    const bool res = std::is_same<T, float>::value && std::is_same<XT, float>::value && R == 1 && n > pp.n_res;
     // streaming and resident groups concurrently when both are present
     const bool fork = res && n_stream_end > pp.n_dom && pp.side[0] != nullptr;
     hipStream_t s_str = s, s_res = s;
@@ -1489,8 +1489,9 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
     if (tev && any_str) RW_TRY(hipEventRecord(tev[1], s_str));
     if constexpr (std::is_same<T, float>::value && std::is_same<XT, float>::value && R == 1) {
         if (tev && res) RW_TRY(hipEventRecord(tev[2], s_res));
-        RW_TRY(launch_resident(a, pp.n_res_l, pp.n_res_s, pp.max_res_l, pp.plane_res_l, xt, corr, s_res));
-        RW_TRY(launch_resident(a, pp.n_res_s, n, pp.max_res_s, pp.plane_res_s, xt, corr, s_res));
+        for (int i = 0; i < pp.n_rl; ++i)
+            RW_TRY(launch_resident(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_voxels, pp.rl[i].max_plane,
+                                   pp.rl[i].kind, xt, corr, s_res));
         if (tev && res) RW_TRY(hipEventRecord(tev[3], s_res));
     }
     if (fork) {

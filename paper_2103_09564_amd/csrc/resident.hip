@@ -83,9 +83,9 @@ __device__ __forceinline__ void nb_offsets(int nx, int nxy, int (&o)[6]) {
 // One workgroup of NT threads per box; VPT = most voxels a thread owns.
 // xt: x (main solve) or the correction accumulator (corr = 1).
 //
-// LDS holds (g, p) pairs for the box with nx*ny zero pairs before and after
-// it, so every neighbour address v + offset is inside the array (pairs that
-// are not in-box neighbours get weight 0).  One 8-byte LDS read per
+// LDS holds (g, p) pairs for the box with nx*ny zero pairs before it and
+// nx*ny + 1 after it, so every neighbour address v + offset is inside the
+// array (pairs that are not in-box neighbours get weight 0).  One 8-byte LDS read per
 // neighbour fetches both g and p.
 template <int NT, int VPT>
 __global__ __launch_bounds__(NT) void k_pcg_res(SolveArgs a, float* xt, int corr, int base) {
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(NT) void k_pcg_res(SolveArgs a, float* xt, int corr
     int off[6];
     nb_offsets(nx, nxy, off);
 
-    for (int v = (int)threadIdx.x - nxy; v < nv + nxy; v += NT) gp[v] = make_float2(v >= 0 && v < nv ? g[v] : 0.0f, 0.0f);
+    for (int v = (int)threadIdx.x - nxy; v <= nv + nxy; v += NT) gp[v] = make_float2(v >= 0 && v < nv ? g[v] : 0.0f, 0.0f);
     // Per-voxel arrays are only ever updated with selects, never under a
     // branch: a conditional update of one element makes the compiler carry
     // the whole array through the branch (and copy it).  Voxel slots past the
@@ -245,9 +245,164 @@ __global__ __launch_bounds__(NT) void k_pcg_res(SolveArgs a, float* xt, int corr
     }
 }
 
-// Dynamic LDS of a launch: (g, p) pairs for the largest box plus its two
-// nx*ny pads (a plane is at most the whole box).
-size_t resident_lds_bytes(int64_t voxels, int64_t plane) { return (size_t)(voxels + 2 * plane) * sizeof(float2); }
+// Variant for smaller boxes: LDS holds (p, w+x, w+y, w+z) per voxel, the
+// weights of the edges to the +x, +y and +z neighbours (0 where that
+// neighbour is not in the box), computed once per solve; the pads (as in the
+// (g, p) kernel) are all 0.
+// A voxel's other three weights are its -x, -y, -z neighbours' forward
+// weights, so the stencil is six multiply-adds with no exponential and no
+// mask.  16 bytes of LDS per voxel instead of 8.
+template <int NT, int VPT>
+__global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int corr, int base) {
+    extern __shared__ __align__(16) float4 wp_lds[];
+    __shared__ double red[(NT / 64) * 2];
+    constexpr int NC = (VPT + 31) / 32;  // unknown-voxel bits
+    const int ib = base + blockIdx.x;
+    BoxState& st = a.state[ib];
+    if (!st.active) return;
+    const BrickDev bd = a.bricks[ib];
+    const int nx = bd.nx, ny = bd.ny, nz = bd.nz, nxy = nx * ny, nv = nxy * nz;
+    float4* wp = wp_lds + nxy;
+    const float* g = a.g + bd.off;
+    const uint8_t* m = a.mask + bd.off;
+    float* xb = xt + bd.off;
+    const float* rb = (const float*)a.r + bd.off;
+    const ResWeight W{(float)(-a.beta * 1.4426950408889634), (float)a.eps};
+
+    // forward weights from g (global loads of the voxel and its +x, +y, +z neighbours)
+    for (int v = (int)threadIdx.x - nxy; v <= nv + nxy; v += NT) {
+        float4 e = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (v >= 0 && v < nv) {
+            const int kz = v / nxy, rem = v - kz * nxy, j = rem / nx, i = rem - j * nx;
+            const float gc = g[v];
+            if (i + 1 < nx) e.y = W(gc, g[v + 1]);
+            if (j + 1 < ny) e.z = W(gc, g[v + nx]);
+            if (kz + 1 < nz) e.w = W(gc, g[v + nxy]);
+        }
+        wp[v] = e;
+    }
+    float x[VPT], r[VPT], id[VPT], d[VPT], q[VPT];
+    unsigned unk[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) unk[c] = 0u;
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v0 = threadIdx.x + k * NT;
+        const int v = v0 < nv ? v0 : nv - 1;
+        const bool u = v0 < nv && m[v] == 0;
+        const float xv = xb[v], rv = rb[v];
+        x[k] = u ? xv : 0.0f;
+        r[k] = u ? rv : 0.0f;
+        unk[k >> 5] |= (u ? 1u : 0u) << (k & 31);
+    }
+    auto isu = [&](int k) { return (unk[k >> 5] >> (k & 31)) & 1u; };
+    auto slot = [&](int tb, int k) { const int v0 = tb + k * NT; return v0 < nv ? v0 : nv; };
+    int off_x = 1, off_y = nx, off_z = nxy;
+    __syncthreads();
+    // d = the six weights of the voxel (its own forward ones and its
+    // neighbours' forward ones toward it); static
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v = slot(threadIdx.x, k);
+        const float4 self = wp[v];
+        const float dd = self.y + self.z + self.w + wp[v - off_x].y + wp[v - off_y].z + wp[v - off_z].w;
+        d[k] = isu(k) ? dd : 0.0f;
+        id[k] = isu(k) ? __builtin_amdgcn_rcpf(dd) : 0.0f;
+    }
+
+    double rz = st.rz[0], rr = st.rr[0];
+    const double bb = st.bb[0];
+    const double tol = corr ? a.inner_tol : a.tol;
+    const double tol2 = tol * tol;
+    double betac = 0.0;
+    int it = 0, flags = 0;
+    for (;;) {
+        if (rr <= tol2 * bb) break;
+        if (it >= a.max_iter) {
+            flags = 2;
+            break;
+        }
+        // opaque copies: per-voxel addresses stay inside the loop
+        int tb = threadIdx.x;
+        asm volatile("" : "+v"(tb));
+        asm volatile("" : "+v"(off_y));
+        asm volatile("" : "+v"(off_z));
+        const float be = it == 0 ? 0.0f : (float)betac;
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            const int v = slot(tb, k);
+            const float pn = r[k] * id[k] + be * wp[v].x;
+            wp[v].x = isu(k) ? pn : 0.0f;
+        }
+        __syncthreads();
+        double sig = 0.0;
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            const int v = slot(tb, k);
+            const float4 self = wp[v];
+            const float2 mx = *reinterpret_cast<const float2*>(&wp[v - off_x]);  // p, w+x of v - 1
+            const float4 my = wp[v - off_y];
+            const float4 mz = wp[v - off_z];
+            const float acc = self.y * wp[v + off_x].x + self.z * wp[v + off_y].x + self.w * wp[v + off_z].x +
+                              mx.y * mx.x + my.z * my.x + mz.w * mz.x;
+            q[k] = isu(k) ? d[k] * self.x - acc : 0.0f;
+            sig += (double)self.x * (double)q[k];
+        }
+        double s1[1] = {sig};
+        res_block_sum<NT, 1>(s1, red);
+        sig = s1[0];
+        const double alpha = rz / sig;
+        if (!res_finite(alpha) || !(sig > 0.0)) {
+            flags = 1;
+            break;
+        }
+        const float al = (float)alpha;
+        double acc2[2] = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            const int v = slot(tb, k);
+            // p, q, r and 1/d are 0 on seeded and unused slots, so these stay 0
+            x[k] += al * wp[v].x;
+            r[k] -= al * q[k];
+            const float z = r[k] * id[k];
+            acc2[0] += (double)r[k] * (double)z;
+            acc2[1] += (double)r[k] * (double)r[k];
+        }
+        res_block_sum<NT, 2>(acc2, red);
+        ++it;
+        if (!res_finite(acc2[0]) || !res_finite(acc2[1])) {
+            flags = 1;
+            break;
+        }
+        betac = acc2[0] / rz;
+        rz = acc2[0];
+        rr = acc2[1];
+    }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v = threadIdx.x + k * NT;
+        if (isu(k)) xb[v] = x[k];
+    }
+    if (threadIdx.x == 0) {
+        st.rz[0] = rz;
+        st.rr[0] = rr;
+        if (corr) {
+            st.refine_iters += it;
+        } else {
+            st.iters = it;
+            st.rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            if (flags & 2) st.status = RW_ST_MAX_ITER;
+        }
+        if (flags & 1) st.status = RW_ST_NONFINITE;
+        st.pending = corr && !(flags & 1) ? 1 : 0;
+    }
+}
+
+// Dynamic LDS of a launch, in elements: the largest box, nx*ny pad elements
+// before it and nx*ny + 1 after it (the unused voxel slots of a thread map
+// to the element just past the box, whose +z neighbour is the last one).
+int64_t resident_lds_elems(int64_t voxels, int64_t plane) { return voxels + 2 * plane + 1; }
+size_t resident_lds_bytes(int64_t voxels, int64_t plane) { return (size_t)resident_lds_elems(voxels, plane) * sizeof(float2); }
 
 bool resident_fits(const BrickDev& b, size_t lds_limit) {
     const int64_t nxy = (int64_t)b.nx * b.ny, nv = nxy * b.nz;
@@ -255,11 +410,19 @@ bool resident_fits(const BrickDev& b, size_t lds_limit) {
     return nv <= (int64_t)kResMaxVpt * kResThreads && resident_lds_bytes(nv, nxy) + 1024 <= lds_limit;
 }
 
-// Boxes [b0, b1) of the launch list, all resident-eligible, largest first.
+bool resident_w_fits(const BrickDev& b, size_t lds_limit) {
+    const int64_t nxy = (int64_t)b.nx * b.ny, nv = nxy * b.nz;
+    return nv <= (int64_t)kResMaxVptW * kResThreads &&
+           (size_t)resident_lds_elems(nv, nxy) * sizeof(float4) + 1024 <= lds_limit;
+}
+
+// Boxes [b0, b1) of the launch list, all eligible for the kernel `kind`
+// (0: g and p in LDS, 1: weights and p in LDS), largest first.
 hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_voxels, int64_t max_plane,
-                           float* xt, int corr, hipStream_t s) {
+                           int kind, float* xt, int corr, hipStream_t s) {
     if (b1 <= b0) return hipSuccess;
-    const size_t lds = resident_lds_bytes(max_voxels, max_plane);
+    const size_t lds = kind == 1 ? (size_t)resident_lds_elems(max_voxels, max_plane) * sizeof(float4)
+                                 : resident_lds_bytes(max_voxels, max_plane);
     const dim3 grid((unsigned)(b1 - b0));
     auto go = [&](auto kern) -> hipError_t {
         if (lds > 48 * 1024) {
@@ -270,6 +433,11 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
         return hipGetLastError();
     };
     const int64_t vpt = (max_voxels + kResThreads - 1) / kResThreads;
+    if (kind == 1) {
+        if (vpt <= 10) return go(k_pcg_resw<kResThreads, 10>);
+        if (vpt <= kResMaxVptW) return go(k_pcg_resw<kResThreads, kResMaxVptW>);
+        return hipErrorInvalidValue;
+    }
     if (vpt <= 4) return go(k_pcg_res<kResThreads, 4>);
     if (vpt <= 10) return go(k_pcg_res<kResThreads, 10>);
     if (vpt <= 20) return go(k_pcg_res<kResThreads, 20>);
