@@ -98,7 +98,9 @@ typedef struct rw_solve_params {
                                 others stream as in 1), 1 streaming, two sweeps and two
                                 reductions per iteration (Hestenes-Stiefel), 2 streaming, one
                                 sweep and one reduction (Chronopoulos-Gear; weights computed once
-                                per iteration), 3 as 0 with the streaming boxes as in 2.  Every
+                                per iteration), 3 as 0 with the streaming boxes as in 2, 4 as 0
+                                with every box that fits it on the streamed-weights resident
+                                kernel (RW_PATH_RESIDENT_STREAMED).  Every
                                 schedule is the same Jacobi-PCG iteration in exact arithmetic;
                                 results differ by rounding (the one-sweep recurrence is the less
                                 stable one on very ill-conditioned boxes). */
@@ -155,17 +157,18 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
  * solves record HIP events on their stream around each phase; rw_last_timing
  * waits for those events and returns the phase durations of the last solve
  * in milliseconds.  pcg_ms is the main PCG phase alone (the hot loop).  In
- * that phase the boxes that stream from HBM and the boxes that run resident
- * in LDS (see rw_solve_plan) are solved by concurrent kernels; stream_ms and
- * resident_ms are the durations of the two groups (0 for an empty group).
+ * that phase two groups of kernels run concurrently on two streams (see
+ * rw_solve_plan): the streaming boxes followed by the streamed-weights
+ * resident boxes, and the boxes resident in LDS; stream_ms and resident_ms
+ * are the durations of the two groups (0 for an empty group).
  */
 typedef struct rw_timing {
     float init_ms;           /* Dirichlet init (r = -(L x)_U, z, p) */
     float pcg_ms;            /* main PCG phase */
     float finish_ms;         /* FP64 true residual, refinement, stats */
     float total_ms;
-    float stream_ms;         /* main PCG: streaming kernels (RW_PATH_STREAM*) */
-    float resident_ms;       /* main PCG: LDS-resident kernels (RW_PATH_RESIDENT) */
+    float stream_ms;         /* main PCG: RW_PATH_STREAM* then RW_PATH_RESIDENT_STREAMED boxes */
+    float resident_ms;       /* main PCG: RW_PATH_RESIDENT boxes */
 } rw_timing;
 int rw_set_timing(rw_ctx* ctx, int enable);
 int rw_last_timing(rw_ctx* ctx, rw_timing* out);
@@ -174,8 +177,12 @@ int rw_last_timing(rw_ctx* ctx, rw_timing* out);
 enum rw_path {
     RW_PATH_STREAM = 0,          /* one workgroup per box, vectors streamed from HBM, LDS window march */
     RW_PATH_STREAM_GLOBAL = 1,   /* the same without the LDS window (planes wider than it holds) */
-    RW_PATH_RESIDENT = 2,        /* one workgroup per box, g and p in LDS, x and r in registers */
-    RW_PATH_DOMAIN = 3           /* large single box: many workgroups, host-driven iteration */
+    RW_PATH_RESIDENT = 2,        /* one workgroup per box, g and p (or p and the edge weights) in
+                                    LDS, x and r in registers */
+    RW_PATH_DOMAIN = 3,          /* large single box: many workgroups, host-driven iteration */
+    RW_PATH_RESIDENT_STREAMED = 4 /* one workgroup per box, p in LDS, r in registers; the edge
+                                    weights and 1/d are computed once into a per-box buffer and
+                                    re-read from cache each iteration (boxes up to 32768 voxels) */
 };
 
 /*

@@ -72,7 +72,7 @@ lib.rw_last_timing.restype = ctypes.c_int
 lib.rw_solve_plan.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp]
 lib.rw_solve_plan.restype = ctypes.c_int
 
-PATH_STREAM, PATH_STREAM_GLOBAL, PATH_RESIDENT, PATH_DOMAIN = 0, 1, 2, 3
+PATH_STREAM, PATH_STREAM_GLOBAL, PATH_RESIDENT, PATH_DOMAIN, PATH_RESIDENT_STREAMED = 0, 1, 2, 3, 4
 
 
 class RWError(RuntimeError):

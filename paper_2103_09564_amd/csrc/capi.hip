@@ -76,12 +76,12 @@ int check_params(rw_ctx* ctx, const rw_solve_params* p) {
     if (!std::isfinite(p->refine_tol) || p->refine_tol < 0) return fail(ctx, RW_E_INVAL, "refine_tol must be >= 0");
     if (!std::isfinite(p->inner_tol) || p->inner_tol < 0) return fail(ctx, RW_E_INVAL, "inner_tol must be >= 0");
     if (!std::isfinite(p->stall_ratio) || p->stall_ratio < 1) return fail(ctx, RW_E_INVAL, "stall_ratio must be >= 1");
-    if (p->schedule < 0 || p->schedule > 3) return fail(ctx, RW_E_INVAL, "schedule must be 0, 1, 2 or 3");
+    if (p->schedule < 0 || p->schedule > 4) return fail(ctx, RW_E_INVAL, "schedule must be 0, 1, 2, 3 or 4");
     return RW_OK;
 }
 
-// Schedule of the streaming kernels for a requested schedule (0 and 1: two
-// sweeps, 2 and 3: one sweep; 0 and 3 also use the LDS-resident kernel).
+// Schedule of the streaming kernels for a requested schedule (0, 1 and 4:
+// two sweeps, 2 and 3: one sweep; 0, 3 and 4 also use the resident kernels).
 int stream_schedule(int requested) { return requested == 2 || requested == 3 ? 2 : 1; }
 
 // Validate host descriptors and build the launch list (largest box first).
@@ -128,7 +128,8 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     rwk::PlanePlan pp{};
     pp.cols = 2;
     pp.n_big = pp.n_res = n;
-    const bool res_ok = nrhs == 1 && !fp64 && (schedule == 0 || schedule == 3);
+    const bool res_ok = nrhs == 1 && !fp64 && (schedule == 0 || schedule == 3 || schedule == 4);
+    const bool prefer_g = schedule == 4;
     const int64_t res_small = rwk::kResSmallVox;
     int widest = 0;
     for (const auto& b : *list)
@@ -138,8 +139,8 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     const bool use = rwk::plane_lds_bytes(nrhs, fp64, cols) <= ctx->lds_limit;
     const int lim = use ? rwk::plane_max(cols) : 0;
     // group 0: domain solver, 1: global march, 2: plane march, 3: resident
-    // (g, p), 4: resident (weights), 5: resident (weights) small boxes; the
-    // list is largest-first
+    // (p in LDS, weights streamed), 4: resident (g, p), 5: resident
+    // (weights), 6: resident (weights) small boxes; the list is largest-first
     std::vector<uint8_t> grp(list->size());
     int n_dom = 0;
     for (size_t i = 0; i < list->size(); ++i) {
@@ -151,9 +152,13 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
         if (dom && n_dom < rwk::kDomMaxBoxes) {
             grp[i] = 0;
             ++n_dom;
+        } else if (res_ok && prefer_g && rwk::resident_g_fits(b, ctx->lds_limit)) {
+            grp[i] = 3;
         } else if (res_ok && rwk::resident_w_fits(b, ctx->lds_limit)) {
-            grp[i] = vox <= res_small ? 5 : 4;
+            grp[i] = vox <= res_small ? 6 : 5;
         } else if (res_ok && rwk::resident_fits(b, ctx->lds_limit)) {
+            grp[i] = 4;
+        } else if (res_ok && rwk::resident_g_fits(b, ctx->lds_limit)) {
             grp[i] = 3;
         } else {
             grp[i] = wide ? 1 : 2;
@@ -163,7 +168,7 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     std::iota(idx.begin(), idx.end(), size_t(0));
     std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return grp[a] < grp[b]; });
     std::vector<rwk::BrickDev> sorted(list->size());
-    int64_t cnt[6] = {0, 0, 0, 0, 0, 0};
+    int64_t cnt[7] = {0, 0, 0, 0, 0, 0, 0};
     for (size_t i = 0; i < idx.size(); ++i) {
         sorted[i] = (*list)[idx[i]];
         cnt[grp[idx[i]]] += 1;
@@ -176,18 +181,27 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     pp.n_res = pp.n_big + cnt[2];
     pp.n_rl = 0;
     int64_t b0 = pp.n_res;
-    for (int gi = 3; gi <= 5; ++gi) {
+    pp.wts_elems = 0;
+    for (int gi = 3; gi <= 6; ++gi) {
         if (cnt[gi] == 0) continue;
         rwk::PlanePlan::ResLaunch& L = pp.rl[pp.n_rl++];
         L.b0 = b0;
         L.b1 = b0 + cnt[gi];
-        L.kind = gi == 3 ? 0 : 1;
+        L.kind = gi == 3 ? 2 : gi == 4 ? 0 : 1;
         L.max_voxels = 0;
         L.max_plane = 0;
         for (int64_t i = L.b0; i < L.b1; ++i) {
             const auto& b = (*list)[(size_t)i];
             L.max_voxels = std::max<int64_t>(L.max_voxels, (int64_t)b.nx * b.ny * b.nz);
             L.max_plane = std::max<int64_t>(L.max_plane, (int64_t)b.nx * b.ny);
+        }
+        if (L.kind == 2) {
+            const int64_t span = rwk::resident_g_span(L.max_voxels);
+            for (int64_t i = L.b0; i < L.b1; ++i) {
+                auto& b = (*list)[(size_t)i];
+                b.woff = pp.wts_elems;
+                pp.wts_elems += rwk::resident_g_elems(b, span);
+            }
         }
         b0 = L.b1;
     }
@@ -216,6 +230,16 @@ int attach_side_streams(rw_ctx* ctx, rwk::PlanePlan* pp) {
     pp->fork = ctx->fork;
     pp->join[0] = ctx->join[0];
     pp->join[1] = ctx->join[1];
+    return RW_OK;
+}
+
+// Weight segments of the streamed-weights resident boxes (none: null).
+int bind_weights(rw_ctx* ctx, const rwk::PlanePlan& pp, rwk::SolveArgs* a, hipStream_t s) {
+    a->wts = nullptr;
+    if (pp.wts_elems == 0) return RW_OK;
+    hipError_t e = grow(ctx, &ctx->wts, &ctx->wts_bytes, (size_t)pp.wts_elems * sizeof(float), s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "allocating weight segments");
+    a->wts = (float*)ctx->wts;
     return RW_OK;
 }
 
@@ -278,6 +302,7 @@ void rw_ctx_destroy(rw_ctx* ctx) {
     if (ctx->aux) (void)hipFree(ctx->aux);
     if (ctx->hws) (void)hipFree(ctx->hws);
     if (ctx->hgeo) (void)hipFree(ctx->hgeo);
+    if (ctx->wts) (void)hipFree(ctx->wts);
     for (int i = 0; i < 4; ++i) {
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
         if (ctx->gev[i]) (void)hipEventDestroy(ctx->gev[i]);
@@ -347,6 +372,8 @@ int rw_solve_plan(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, 
                      : i < pp.n_big ? RW_PATH_STREAM_GLOBAL
                      : i < pp.n_res ? RW_PATH_STREAM
                                       : RW_PATH_RESIDENT;
+        for (int k = 0; k < pp.n_rl; ++k)
+            if (pp.rl[k].kind == 2 && i >= pp.rl[k].b0 && i < pp.rl[k].b1) path[slot] = RW_PATH_RESIDENT_STREAMED;
     }
     return RW_OK;
 }
@@ -417,6 +444,8 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
     a.stall_ratio = p.stall_ratio;
     a.schedule = stream_schedule(p.schedule);
     rwk::domain_bind(a, (char*)ctx->aux + state_bytes);
+    rc = bind_weights(ctx, pp, &a, s);
+    if (rc) return rc;
     hipEvent_t* ev = nullptr;
     if (ctx->timing) {
         for (int i = 0; i < 4; ++i)
@@ -433,7 +462,12 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
         if (e != hipSuccess) return hip_fail(ctx, e, "recording timing event");
         ev = &ctx->ev[1];
         pp.gev = ctx->gev;
-        ctx->gev_used = (pp.n_res > pp.n_dom ? 1 : 0) | (pp.n_res < n_bricks ? 2 : 0);
+        // bit 0: streaming kernels or streamed-weights resident launches
+        // (one stream), bit 1: the other resident launches
+        bool any_g = false, any_lds = false;
+        for (int i = 0; i < pp.n_rl; ++i) (pp.rl[i].kind == 2 ? any_g : any_lds) = true;
+        const bool res_path = R == 1 && !fp64;
+        ctx->gev_used = (pp.n_res > pp.n_dom || (res_path && any_g) ? 1 : 0) | (res_path && any_lds ? 2 : 0);
     }
     e = rwk::launch_solve(a, n_bricks, R, fp64, pp, s, ev);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching solve kernel");
@@ -513,6 +547,8 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     sa.precision = RW_PREC_MIXED;
     sa.schedule = stream_schedule(params->schedule);
     rwk::domain_bind(sa, (char*)ctx->aux + state_bytes + part_bytes);
+    rc = bind_weights(ctx, pp, &sa, s);
+    if (rc) return rc;
     e = rwk::launch_adjoint(a, sa, n_bricks, dl_dbeta, pp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching adjoint kernels");
     return RW_OK;

@@ -22,6 +22,8 @@ struct rw_ctx {
     size_t hws_bytes = 0;
     void* hgeo = nullptr;        // hierarchy: box geometry, seed entries, per-box scalars
     size_t hgeo_bytes = 0;
+    void* wts = nullptr;         // weight segments of the streamed-weights resident kernel
+    size_t wts_bytes = 0;
     int timing = 0;              // record phase events in rw_solve_bricks
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // start, after init, after pcg, end
     int ev_valid = 0;
@@ -61,6 +63,7 @@ struct DevGuard {
 struct BrickDev {
     int32_t nx, ny, nz, slot;
     int64_t off;
+    int64_t woff;  // streamed-weights resident kernel: start of the box's weight segment
 };
 
 // Per-box scalars carried between the phases of one solve (launch order).
@@ -92,6 +95,7 @@ struct SolveArgs {
     int32_t schedule;      // streaming kernels: 1 two-sweep Jacobi-PCG, 2 single-reduction (Chronopoulos-Gear)
     void* dom;             // multi-workgroup domain solver: scalar state and ticket
     double* dom_part;      // its per-workgroup partial sums
+    float* wts;            // streamed-weights resident kernel: per-box weight segments
 };
 
 struct AdjointArgs {
@@ -135,8 +139,9 @@ struct PlanePlan {
         int64_t b0, b1;       // launch-list range
         int64_t max_voxels;   // largest box of the range
         int64_t max_plane;    // widest nx*ny of the range
-        int kind;             // 0: (g, p) kernel, 1: weights kernel
-    } rl[3];
+        int kind;             // 0: (g, p) kernel, 1: weights kernel, 2: streamed-weights kernel
+    } rl[4];
+    int64_t wts_elems;        // floats of weight segments the kind-2 boxes need (BrickDev::woff)
     // when set, the streaming and resident groups run on these two streams
     // (forked from and joined back into the caller's stream)
     hipStream_t side[2];
@@ -151,8 +156,14 @@ constexpr int kResThreads = 512;
 constexpr int kResMaxVpt = 34;    // voxels per thread: boxes up to 17408 voxels (32 x 32 x 17)
 constexpr int kResMaxVptW = 20;   // weights kernel: boxes up to 10240 voxels
 constexpr int kResSmallVox = 5120;  // the small weights group: at most 10 voxels per thread
+constexpr int kResThreadsG = 512;   // streamed-weights kernel
+constexpr int kResVptG0 = 34;       // its launches for boxes up to 17408 voxels (32 x 32 x 17)
+constexpr int kResMaxVptG = 64;     // and up to 32768 voxels (32^3)
 bool resident_fits(const BrickDev& b, size_t lds_limit);      // (g, p) kernel
 bool resident_w_fits(const BrickDev& b, size_t lds_limit);    // weights kernel
+bool resident_g_fits(const BrickDev& b, size_t lds_limit);    // streamed-weights kernel
+int64_t resident_g_span(int64_t max_voxels);                  // its voxel slots per workgroup
+int64_t resident_g_elems(const BrickDev& b, int64_t span);    // a box's weight segment, in floats
 hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_voxels, int64_t max_plane,
                            int kind, float* xt, int corr, hipStream_t s);
 

@@ -1460,9 +1460,15 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
                                    const PlanePlan& pp, hipStream_t s) {
     for (int64_t i = 0; i < pp.n_dom; ++i) RW_TRY((domain_pcg<T, R, XT>(a, (int)i, pp.host[i], xt, corr, s)));
     const int64_t n_stream_end = std::min<int64_t>(n, pp.n_res);
-    const bool res = std::is_same<T, float>::value && std::is_same<XT, float>::value && R == 1 && n > pp.n_res;
-    // streaming and resident groups concurrently when both are present
-    const bool fork = res && n_stream_end > pp.n_dom && pp.side[0] != nullptr;
+    constexpr bool kRes = std::is_same<T, float>::value && std::is_same<XT, float>::value && R == 1;
+    // streamed-weights resident launches share the streaming kernel's stream;
+    // the other resident launches run on a second stream, concurrently
+    bool any_g = false, any_lds = false;
+    if (kRes && n > pp.n_res)
+        for (int i = 0; i < pp.n_rl; ++i) (pp.rl[i].kind == 2 ? any_g : any_lds) = true;
+    const bool any_str = n_stream_end > pp.n_dom;
+    const bool on_a = any_str || any_g;
+    const bool fork = on_a && any_lds && pp.side[0] != nullptr;
     hipStream_t s_str = s, s_res = s;
     if (fork) {
         RW_TRY(hipEventRecord(pp.fork, s));
@@ -1472,27 +1478,33 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
         s_res = pp.side[1];
     }
     hipEvent_t* tev = corr == 0 ? pp.gev : nullptr;
-    const bool any_str = n_stream_end > pp.n_dom;
-    if (tev && any_str) RW_TRY(hipEventRecord(tev[0], s_str));
+    if (tev && on_a) RW_TRY(hipEventRecord(tev[0], s_str));
     if (n_big > pp.n_dom)
         hipLaunchKernelGGL((k_pcg<T, R, C, false, 1, XT>), dim3((unsigned)(n_big - pp.n_dom)), dim3(kThreads), 0,
                            s_str, a, xt, corr, (int)pp.n_dom);
     if (n_stream_end > n_big) {
         auto k = a.schedule == 2 ? k_pcg<T, R, C, true, 2, XT> : k_pcg<T, R, C, true, 1, XT>;
-        if constexpr (std::is_same<T, float>::value && std::is_same<XT, float>::value && R == 1 && C == 2)
+        if constexpr (kRes && C == 2)
             if (a.schedule != 2) k = pp.plane_aligned ? k_pcg_w1<C, true> : k_pcg_w1<C, false>;
         if (lds > 48 * 1024)
             RW_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(k, dim3((unsigned)(n_stream_end - n_big)), dim3(kThreads), lds, s_str, a, xt, corr,
                            (int)n_big);
     }
-    if (tev && any_str) RW_TRY(hipEventRecord(tev[1], s_str));
-    if constexpr (std::is_same<T, float>::value && std::is_same<XT, float>::value && R == 1) {
-        if (tev && res) RW_TRY(hipEventRecord(tev[2], s_res));
+    if constexpr (kRes) {
         for (int i = 0; i < pp.n_rl; ++i)
-            RW_TRY(launch_resident(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_voxels, pp.rl[i].max_plane,
-                                   pp.rl[i].kind, xt, corr, s_res));
-        if (tev && res) RW_TRY(hipEventRecord(tev[3], s_res));
+            if (pp.rl[i].kind == 2)
+                RW_TRY(launch_resident(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_voxels, pp.rl[i].max_plane, 2, xt,
+                                       corr, s_str));
+    }
+    if (tev && on_a) RW_TRY(hipEventRecord(tev[1], s_str));
+    if constexpr (kRes) {
+        if (tev && any_lds) RW_TRY(hipEventRecord(tev[2], s_res));
+        for (int i = 0; i < pp.n_rl; ++i)
+            if (pp.rl[i].kind != 2)
+                RW_TRY(launch_resident(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_voxels, pp.rl[i].max_plane,
+                                       pp.rl[i].kind, xt, corr, s_res));
+        if (tev && any_lds) RW_TRY(hipEventRecord(tev[3], s_res));
     }
     if (fork) {
         RW_TRY(hipEventRecord(pp.join[0], s_str));

@@ -27,6 +27,7 @@ namespace {
 // Per-voxel code: bits 0..5 neighbour -x,+x,-y,+y,-z,+z inside the box, bit 6 unknown.
 constexpr unsigned kUnknown = 64u;
 
+
 template <int NT, int N>
 __device__ __forceinline__ void res_block_sum(double (&v)[N], double* red) {
     constexpr int W = NT / 64;
@@ -398,6 +399,299 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
     }
 }
 
+// Variant for boxes whose search direction alone fits in one CU's LDS (up
+// to 32768 voxels, e.g. 32^3): LDS holds p only (4 B per voxel, pads as
+// above).  The forward weights w+x, w+y, w+z and 1/d are computed once per
+// launch into the box's segment of a global buffer and read back in every
+// iteration; a box's segment stays in the last-level cache while its
+// workgroup iterates, so an iteration reads about 16 B per voxel from there
+// and computes no exponential.  r and q (q holds z between iterations) stay
+// in registers, and x too unless XG (then x is updated in place in global
+// memory, 8 B per voxel and iteration, to leave registers for the loads).
+//
+// Segment of a box (floats): arrays WX, WY, WZ, ID (and X when XG) of
+// stride T = nx*ny + NT*VPT, each nx*ny zeros, the box, then zeros up to
+// NT*VPT.  Thread t owns the slots t + k*NT, k < VPT, of which those >= nv
+// are unused: they read LDS pads and segment zeros (p = 0, 1/d = 0) and
+// write only their own X element, so no address is clamped.  1/d = 0 also
+// marks seeded voxels, whose r is kept at 0.
+//
+// The loads of each phase are issued G voxels ahead of their use (a
+// two-group register ring, pinned with scheduling barriers), so a wave has
+// about 6G loads in flight instead of waiting on each voxel's weights.
+// Segment accesses are buffer instructions on one resource for the
+// segment: a per-voxel byte offset in a VGPR and the array (and neighbour)
+// offset in an SGPR, so no 64-bit address is formed or kept per voxel.
+// The resource's size bounds every access to the segment.
+struct SegBuf {
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ __forceinline__ float ld(unsigned vo, int so) const {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)vo, so, 0));
+    }
+    __device__ __forceinline__ void st(unsigned vo, int so, float v) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rsrc, (int)vo, so, 0);
+    }
+};
+
+// Workgroup barrier that orders LDS only (global loads stay in flight).
+__device__ __forceinline__ void res_lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int NT, int N>
+__device__ __forceinline__ void res_block_sum_lds(double (&v)[N], double* red) {
+    constexpr int W = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double s = v[k];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+        v[k] = s;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) red[w * N + k] = v[k];
+    }
+    res_lds_barrier();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) s += red[i * N + k];
+        v[k] = s;
+    }
+    res_lds_barrier();
+}
+
+template <int NT, int VPT, bool XG, int G>
+__global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int corr, int base) {
+    extern __shared__ __align__(16) float p_lds[];
+    __shared__ double red[(NT / 64) * 2];
+    constexpr int NG = (VPT + G - 1) / G;
+    constexpr int XR = XG ? 1 : VPT;  // register copy of x
+    const int ib = base + blockIdx.x;
+    BoxState& st = a.state[ib];
+    if (!st.active) return;
+    const BrickDev bd = a.bricks[ib];
+    const int nx = bd.nx, ny = bd.ny, nz = bd.nz, nxy = nx * ny, nv = nxy * nz;
+    constexpr int span = NT * VPT;
+    const int T = nxy + span;  // stride of the segment arrays
+    float* P = p_lds + nxy;
+    const float* g = a.g + bd.off;
+    const uint8_t* m = a.mask + bd.off;
+    float* const xb = xt + bd.off;
+    const float* rb = (const float*)a.r + bd.off;
+    float* const seg = a.wts + bd.woff;
+    float* const WX = seg + nxy;
+    float* const WY = WX + T;
+    float* const WZ = WY + T;
+    float* const ID = WZ + T;
+    float* const X = ID + T;  // XG only
+    const ResWeight W{(float)(-a.beta * 1.4426950408889634), (float)a.eps};
+
+    // weights (0 toward neighbours outside the box) and 1/d (0 on seeded
+    // voxels); pads and unused slots are 0
+    for (int v = (int)threadIdx.x - nxy; v < span; v += NT) {
+        float wx = 0.0f, wy = 0.0f, wz = 0.0f, id = 0.0f, xv = 0.0f;
+        if (v >= 0 && v < nv) {
+            const int kz = v / nxy, rem = v - kz * nxy, j = rem / nx, i = rem - j * nx;
+            const float gc = g[v];
+            if (i + 1 < nx) wx = W(gc, g[v + 1]);
+            if (j + 1 < ny) wy = W(gc, g[v + nx]);
+            if (kz + 1 < nz) wz = W(gc, g[v + nxy]);
+            float d = wx + wy + wz;
+            if (i > 0) d += W(g[v - 1], gc);
+            if (j > 0) d += W(g[v - nx], gc);
+            if (kz > 0) d += W(g[v - nxy], gc);
+            if (m[v] == 0) id = __builtin_amdgcn_rcpf(d);
+            if constexpr (XG) xv = xb[v];
+        }
+        WX[v] = wx;
+        WY[v] = wy;
+        WZ[v] = wz;
+        ID[v] = id;
+        if constexpr (XG) X[v] = xv;
+    }
+    for (int v = (int)threadIdx.x - nxy; v < span + nxy; v += NT) P[v] = 0.0f;
+
+    float x[XR], r[VPT], q[VPT];
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v0 = threadIdx.x + k * NT;
+        const int v = v0 < nv ? v0 : nv - 1;
+        const bool u = v0 < nv && m[v] == 0;
+        const float rv = rb[v];
+        r[k] = u ? rv : 0.0f;
+        if constexpr (!XG) {
+            const float xv = xb[v];
+            x[k] = u ? xv : 0.0f;
+        }
+    }
+    // the weights written above are read by other threads of the workgroup
+    __syncthreads();
+    // 0x00020000: raw 32-bit buffer (third descriptor word for this chip family)
+    const SegBuf sb{__builtin_amdgcn_make_buffer_rsrc(seg, 0, (int)(4 * (5 * T)), 0x00020000)};
+    // byte offsets of the arrays (from voxel 0 of WX) and of the backward neighbours
+    const int sWX = 4 * nxy, sWY = sWX + 4 * T, sWZ = sWY + 4 * T, sID = sWZ + 4 * T, sX = sID + 4 * T;
+    const int sWXm = sWX - 4, sWYm = sWY - 4 * nx, sWZm = sWZ - 4 * nxy;
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) q[k] = r[k] * sb.ld(4u * (unsigned)(threadIdx.x + k * NT), sID);  // start z
+
+    double rz = st.rz[0], rr = st.rr[0];
+    const double bb = st.bb[0];
+    const double tol = corr ? a.inner_tol : a.tol;
+    const double tol2 = tol * tol;
+    double betac = 0.0;
+    float wr[2][G][6];  // weights of two groups of voxels
+    float ir[2][G][2];  // 1/d and (XG) x of two groups
+    int it = 0, flags = 0;
+    for (;;) {
+        if (rr <= tol2 * bb) break;
+        if (it >= a.max_iter) {
+            flags = 2;
+            break;
+        }
+        // opaque copies: per-voxel addresses stay inside the loop
+        int tb = threadIdx.x, oy = nx, oz = nxy;
+        asm volatile("" : "+v"(tb));
+        asm volatile("" : "+v"(oy));
+        asm volatile("" : "+v"(oz));
+        const unsigned o0 = 4u * (unsigned)tb;
+        auto load_w = [&](int gi, float (&w)[G][6]) {
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int k = gi * G + j;
+                if (k < VPT) {
+                    const unsigned o = o0 + 4u * (unsigned)(k * NT);
+                    w[j][0] = sb.ld(o, sWX);
+                    w[j][1] = sb.ld(o, sWXm);
+                    w[j][2] = sb.ld(o, sWY);
+                    w[j][3] = sb.ld(o, sWYm);
+                    w[j][4] = sb.ld(o, sWZ);
+                    w[j][5] = sb.ld(o, sWZm);
+                }
+            }
+        };
+        auto load_i = [&](int gi, float (&w)[G][2]) {
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int k = gi * G + j;
+                if (k < VPT) {
+                    const unsigned o = o0 + 4u * (unsigned)(k * NT);
+                    w[j][0] = sb.ld(o, sID);
+                    if constexpr (XG) w[j][1] = sb.ld(o, sX);
+                }
+            }
+        };
+        load_w(0, wr[0]);
+        const float be = it == 0 ? 0.0f : (float)betac;
+        float* const Pt = P + tb;
+        // p = z + beta p (z = 0 and p = 0 on seeded and unused slots), in
+        // groups of 8 so that the compiler does not read all p first
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            Pt[k * NT] = q[k] + be * Pt[k * NT];
+            if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+        res_lds_barrier();
+        const float* const Pxm = Pt - 1;
+        const float* const Pym = Pt - oy;
+        const float* const Pyp = Pt + oy;
+        const float* const Pzm = Pt - oz;
+        const float* const Pzp = Pt + oz;
+        double sig = 0.0;
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            if (gi + 1 < NG) load_w(gi + 1, wr[(gi + 1) & 1]);
+            else load_i(0, ir[0]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int k = gi * G + j;
+                if (k < VPT) {
+                    const float(&w)[6] = wr[gi & 1][j];
+                    const float d = ((w[0] + w[1]) + (w[2] + w[3])) + (w[4] + w[5]);
+                    const float pv = Pt[k * NT];
+                    const float acc = w[0] * Pxm[k * NT + 2] + w[1] * Pxm[k * NT] + w[2] * Pyp[k * NT] +
+                                      w[3] * Pym[k * NT] + w[4] * Pzp[k * NT] + w[5] * Pzm[k * NT];
+                    q[k] = d * pv - acc;  // masked in the update below
+                    sig += (double)pv * (double)q[k];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        double s1[1] = {sig};
+        res_block_sum_lds<NT, 1>(s1, red);
+        sig = s1[0];
+        const double alpha = rz / sig;
+        if (!res_finite(alpha) || !(sig > 0.0)) {
+            flags = 1;
+            break;
+        }
+        const float al = (float)alpha;
+        double acc2[2] = {0.0, 0.0};
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            if (gi + 1 < NG) load_i(gi + 1, ir[(gi + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int k = gi * G + j;
+                if (k < VPT) {
+                    const float id = ir[gi & 1][j][0];
+                    const float pv = Pt[k * NT];
+                    // p = 0 on seeded and unused slots; r stays 0 there (1/d = 0)
+                    if constexpr (XG) {
+                        sb.st(o0 + 4u * (unsigned)(k * NT), sX, ir[gi & 1][j][1] + al * pv);
+                    } else {
+                        x[k] += al * pv;
+                    }
+                    const float rn = r[k] - al * q[k];
+                    r[k] = id != 0.0f ? rn : 0.0f;
+                    const float z = r[k] * id;
+                    q[k] = z;
+                    acc2[0] += (double)r[k] * (double)z;
+                    acc2[1] += (double)r[k] * (double)r[k];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        res_block_sum_lds<NT, 2>(acc2, red);
+        ++it;
+        if (!res_finite(acc2[0]) || !res_finite(acc2[1])) {
+            flags = 1;
+            break;
+        }
+        betac = acc2[0] / rz;
+        rz = acc2[0];
+        rr = acc2[1];
+    }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v = threadIdx.x + k * NT;
+        if (v < nv && m[v] == 0) {
+            if constexpr (XG) xb[v] = X[v];  // written by this thread
+            else xb[v] = x[k];
+        }
+    }
+    if (threadIdx.x == 0) {
+        st.rz[0] = rz;
+        st.rr[0] = rr;
+        if (corr) {
+            st.refine_iters += it;
+        } else {
+            st.iters = it;
+            st.rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            if (flags & 2) st.status = RW_ST_MAX_ITER;
+        }
+        if (flags & 1) st.status = RW_ST_NONFINITE;
+        st.pending = corr && !(flags & 1) ? 1 : 0;
+    }
+}
+
 // Dynamic LDS of a launch, in elements: the largest box, nx*ny pad elements
 // before it and nx*ny + 1 after it (the unused voxel slots of a thread map
 // to the element just past the box, whose +z neighbour is the last one).
@@ -416,23 +710,55 @@ bool resident_w_fits(const BrickDev& b, size_t lds_limit) {
            (size_t)resident_lds_elems(nv, nxy) * sizeof(float4) + 1024 <= lds_limit;
 }
 
+// Voxel slots (threads x voxels per thread) of a streamed-weights launch
+// whose largest box has max_voxels voxels (0: too large).
+int64_t resident_g_span(int64_t max_voxels) {
+    if (max_voxels <= (int64_t)kResThreadsG * kResVptG0) return (int64_t)kResThreadsG * kResVptG0;
+    if (max_voxels <= (int64_t)kResThreadsG * kResMaxVptG) return (int64_t)kResThreadsG * kResMaxVptG;
+    return 0;
+}
+
+static size_t resident_g_lds(int64_t span, int64_t plane) { return (size_t)(span + 2 * plane) * sizeof(float); }
+
+bool resident_g_fits(const BrickDev& b, size_t lds_limit) {
+    const int64_t nxy = (int64_t)b.nx * b.ny, nv = nxy * b.nz;
+    const int64_t span = resident_g_span(nv);
+    return span > 0 && resident_g_lds(span, nxy) + 1024 <= lds_limit;
+}
+
+int64_t resident_g_elems(const BrickDev& b, int64_t span) {
+    const int64_t nxy = (int64_t)b.nx * b.ny;
+    return (5 * (nxy + span) + 63) & ~int64_t(63);  // five arrays, whole 256-byte lines
+}
+
 // Boxes [b0, b1) of the launch list, all eligible for the kernel `kind`
-// (0: g and p in LDS, 1: weights and p in LDS), largest first.
+// (0: g and p in LDS, 1: weights and p in LDS, 2: p in LDS and weights in a
+// global buffer), largest first.
 hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_voxels, int64_t max_plane,
                            int kind, float* xt, int corr, hipStream_t s) {
     if (b1 <= b0) return hipSuccess;
-    const size_t lds = kind == 1 ? (size_t)resident_lds_elems(max_voxels, max_plane) * sizeof(float4)
-                                 : resident_lds_bytes(max_voxels, max_plane);
+    const size_t lds = kind == 2 ? resident_g_lds(resident_g_span(max_voxels), max_plane)
+                                 : (size_t)resident_lds_elems(max_voxels, max_plane) *
+                                       (kind == 1 ? sizeof(float4) : sizeof(float2));
     const dim3 grid((unsigned)(b1 - b0));
+    const int nt = kind == 2 ? kResThreadsG : kResThreads;
     auto go = [&](auto kern) -> hipError_t {
         if (lds > 48 * 1024) {
             hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(kern, grid, dim3(kResThreads), lds, s, a, xt, corr, (int)b0);
+        hipLaunchKernelGGL(kern, grid, dim3(nt), lds, s, a, xt, corr, (int)b0);
         return hipGetLastError();
     };
-    const int64_t vpt = (max_voxels + kResThreads - 1) / kResThreads;
+    if (kind == 2) {
+        // the plan sized each box's weight segment for this launch's span
+        if (!a.wts) return hipErrorInvalidValue;
+        const int64_t span = resident_g_span(max_voxels);
+        if (span == (int64_t)kResThreadsG * kResVptG0) return go(k_pcg_resg<kResThreadsG, kResVptG0, false, 8>);
+        if (span == (int64_t)kResThreadsG * kResMaxVptG) return go(k_pcg_resg<kResThreadsG, kResMaxVptG, true, 3>);
+        return hipErrorInvalidValue;
+    }
+    const int64_t vpt = (max_voxels + nt - 1) / nt;
     if (kind == 1) {
         if (vpt <= 10) return go(k_pcg_resw<kResThreads, 10>);
         if (vpt <= kResMaxVptW) return go(k_pcg_resw<kResThreads, kResMaxVptW>);

@@ -268,10 +268,11 @@ def test_domain_solver_multi_rhs_and_cap(env):
 
 
 def test_resident_kernel_matches_oracle_and_streaming(env):
-    """Boxes that fit one CU run an on-chip PCG (schedule 0): g and p in LDS
-    (two workgroup shapes), or p in LDS for boxes up to 32^3; schedule 1
-    forces the streaming kernels.  Both against the oracle, on ragged sizes
-    of every variant."""
+    """Boxes that fit one CU run an on-chip PCG (schedule 0): g and p, or p
+    and the edge weights, in LDS, and p in LDS with the weights streamed
+    from cache for boxes up to 32^3 (schedule 4: for every box that fits);
+    schedule 1 forces the streaming kernels.  All against the oracle, on
+    ragged sizes of every variant (slots past a box's end included)."""
     rng = np.random.default_rng(31)
     shapes = [(7, 13, 11), (31, 17, 33), (20, 20, 12), (3, 3, 3), (1, 1, 5), (32, 9, 32), (5, 32, 32),
               (16, 16, 16), (32, 32, 17), (9, 1, 40), (32, 32, 32), (30, 31, 33), (26, 29, 27)]
@@ -280,12 +281,30 @@ def test_resident_kernel_matches_oracle_and_streaming(env):
     refs = [_ref(b) for b in boxes]
     xr, _, sr = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1, schedule=0)
     xs, _, ss = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1, schedule=1)
+    xg, _, sg = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1, schedule=4)
     _, x64, s64 = _run(env, d, x64=True, beta=BETA, eps=EPS, tol=1e-6, precision=2, refine_max=6,
                        refine_tol=1e-13, inner_tol=1e-4, schedule=0)
+    _, x64g, s64g = _run(env, d, x64=True, beta=BETA, eps=EPS, tol=1e-6, precision=2, refine_max=6,
+                         refine_tol=1e-13, inner_tol=1e-4, schedule=4)
+    _, rwg, _ = env
+    bricks = rwg.bricks_array(d["shapes"], d["offsets"])
+    plan0 = rwg.context().solve_plan(rwg.solve_params(schedule=0), bricks, d["g"].size)
+    plan4 = rwg.context().solve_plan(rwg.solve_params(schedule=4), bricks, d["g"].size)
+    nv = np.prod(np.asarray(shapes), axis=1)
+    # 32^3 and the other boxes above 17408 voxels take the streamed-weights
+    # kernel by default; with schedule 4 every box up to 32768 voxels does
+    assert np.all(plan0[nv > 17408] == rwg.PATH_RESIDENT_STREAMED), plan0
+    assert np.all(plan0[nv <= 17408] == rwg.PATH_RESIDENT), plan0
+    assert np.all(plan4 == rwg.PATH_RESIDENT_STREAMED), plan4
     for i, ref in enumerate(refs):
         o, n = int(d["offsets"][i]), ref.size
         assert np.max(np.abs(xr[o:o + n] - ref)) <= 1e-4, (shapes[i], sr[i])
+        assert np.max(np.abs(xg[o:o + n] - ref)) <= 1e-4, (shapes[i], sg[i])
         assert np.max(np.abs(xr[o:o + n] - xs[o:o + n])) <= 2e-5, (shapes[i], sr[i], ss[i])
+        assert np.max(np.abs(xg[o:o + n] - xs[o:o + n])) <= 2e-5, (shapes[i], sg[i], ss[i])
         assert np.max(np.abs(x64[o:o + n] - ref)) <= 1e-9, (shapes[i], s64[i])
+        assert np.max(np.abs(x64g[o:o + n] - ref)) <= 1e-9, (shapes[i], s64g[i])
         assert abs(int(sr["iters"][i]) - int(ss["iters"][i])) <= max(3, ss["iters"][i] // 20), (sr[i], ss[i])
+        assert abs(int(sg["iters"][i]) - int(ss["iters"][i])) <= max(3, ss["iters"][i] // 20), (sg[i], ss[i])
+    assert np.all(np.isin(sg["status"], (0, 2))) and np.all(np.isin(s64g["status"], (0, 2)))
     assert np.all(np.isin(sr["status"], (0, 2))) and np.all(s64["status"] == 2) | np.all(np.isin(s64["status"], (0, 2)))
