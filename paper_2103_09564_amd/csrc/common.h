@@ -140,7 +140,7 @@ struct PlanePlan {
         int64_t max_voxels;   // largest box of the range
         int64_t max_plane;    // widest nx*ny of the range
         int kind;             // 0: (g, p) kernel, 1: weights kernel, 2: streamed-weights kernel
-    } rl[4];
+    } rl[5];
     int64_t wts_elems;        // floats of weight segments the kind-2 boxes need (BrickDev::woff)
     // when set, the streaming and resident groups run on these two streams
     // (forked from and joined back into the caller's stream)
@@ -156,9 +156,8 @@ constexpr int kResThreads = 512;
 constexpr int kResMaxVpt = 34;    // voxels per thread: boxes up to 17408 voxels (32 x 32 x 17)
 constexpr int kResMaxVptW = 20;   // weights kernel: boxes up to 10240 voxels
 constexpr int kResSmallVox = 5120;  // the small weights group: at most 10 voxels per thread
-constexpr int kResThreadsG = 512;   // streamed-weights kernel
-constexpr int kResVptG0 = 34;       // its launches for boxes up to 17408 voxels (32 x 32 x 17)
-constexpr int kResMaxVptG = 64;     // and up to 32768 voxels (32^3)
+constexpr int kResSpanG0 = 17408;   // streamed-weights kernel: voxel slots of its launches for
+constexpr int kResSpanG1 = 32768;   // boxes up to 32 x 32 x 17 and up to 32^3
 bool resident_fits(const BrickDev& b, size_t lds_limit);      // (g, p) kernel
 bool resident_w_fits(const BrickDev& b, size_t lds_limit);    // weights kernel
 bool resident_g_fits(const BrickDev& b, size_t lds_limit);    // streamed-weights kernel

@@ -246,16 +246,17 @@ __global__ __launch_bounds__(NT) void k_pcg_res(SolveArgs a, float* xt, int corr
     }
 }
 
-// Variant for smaller boxes: LDS holds (p, w+x, w+y, w+z) per voxel, the
-// weights of the edges to the +x, +y and +z neighbours (0 where that
-// neighbour is not in the box), computed once per solve; the pads (as in the
-// (g, p) kernel) are all 0.
-// A voxel's other three weights are its -x, -y, -z neighbours' forward
-// weights, so the stencil is six multiply-adds with no exponential and no
-// mask.  16 bytes of LDS per voxel instead of 8.
+// Variant for smaller boxes: LDS holds four arrays, p and the weights w+x,
+// w+y, w+z of the edges to the +x, +y and +z neighbours (0 where that
+// neighbour is not in the box), computed once per solve; each array has the
+// pads of the (g, p) kernel, all 0.  A voxel's other three weights are its
+// -x, -y, -z neighbours' forward weights, so the stencil is six
+// multiply-adds with no exponential and no mask.  16 bytes of LDS per voxel
+// instead of 8; separate arrays keep every LDS access of a wave on
+// consecutive words (no bank conflicts).
 template <int NT, int VPT>
 __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int corr, int base) {
-    extern __shared__ __align__(16) float4 wp_lds[];
+    extern __shared__ __align__(16) float w_lds[];
     __shared__ double red[(NT / 64) * 2];
     constexpr int NC = (VPT + 31) / 32;  // unknown-voxel bits
     const int ib = base + blockIdx.x;
@@ -263,7 +264,11 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
     if (!st.active) return;
     const BrickDev bd = a.bricks[ib];
     const int nx = bd.nx, ny = bd.ny, nz = bd.nz, nxy = nx * ny, nv = nxy * nz;
-    float4* wp = wp_lds + nxy;
+    const int L = nv + 2 * nxy + 1;  // array stride (the pads of the (g, p) kernel)
+    float* const P = w_lds + nxy;
+    float* const WX = P + L;
+    float* const WY = WX + L;
+    float* const WZ = WY + L;
     const float* g = a.g + bd.off;
     const uint8_t* m = a.mask + bd.off;
     float* xb = xt + bd.off;
@@ -272,15 +277,18 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
 
     // forward weights from g (global loads of the voxel and its +x, +y, +z neighbours)
     for (int v = (int)threadIdx.x - nxy; v <= nv + nxy; v += NT) {
-        float4 e = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float wx = 0.0f, wy = 0.0f, wz = 0.0f;
         if (v >= 0 && v < nv) {
             const int kz = v / nxy, rem = v - kz * nxy, j = rem / nx, i = rem - j * nx;
             const float gc = g[v];
-            if (i + 1 < nx) e.y = W(gc, g[v + 1]);
-            if (j + 1 < ny) e.z = W(gc, g[v + nx]);
-            if (kz + 1 < nz) e.w = W(gc, g[v + nxy]);
+            if (i + 1 < nx) wx = W(gc, g[v + 1]);
+            if (j + 1 < ny) wy = W(gc, g[v + nx]);
+            if (kz + 1 < nz) wz = W(gc, g[v + nxy]);
         }
-        wp[v] = e;
+        P[v] = 0.0f;
+        WX[v] = wx;
+        WY[v] = wy;
+        WZ[v] = wz;
     }
     float x[VPT], r[VPT], id[VPT], d[VPT], q[VPT];
     unsigned unk[NC];
@@ -298,15 +306,14 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
     }
     auto isu = [&](int k) { return (unk[k >> 5] >> (k & 31)) & 1u; };
     auto slot = [&](int tb, int k) { const int v0 = tb + k * NT; return v0 < nv ? v0 : nv; };
-    int off_x = 1, off_y = nx, off_z = nxy;
+    int off_y = nx, off_z = nxy;
     __syncthreads();
     // d = the six weights of the voxel (its own forward ones and its
     // neighbours' forward ones toward it); static
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
         const int v = slot(threadIdx.x, k);
-        const float4 self = wp[v];
-        const float dd = self.y + self.z + self.w + wp[v - off_x].y + wp[v - off_y].z + wp[v - off_z].w;
+        const float dd = WX[v] + WY[v] + WZ[v] + WX[v - 1] + WY[v - off_y] + WZ[v - off_z];
         d[k] = isu(k) ? dd : 0.0f;
         id[k] = isu(k) ? __builtin_amdgcn_rcpf(dd) : 0.0f;
     }
@@ -332,22 +339,19 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
             const int v = slot(tb, k);
-            const float pn = r[k] * id[k] + be * wp[v].x;
-            wp[v].x = isu(k) ? pn : 0.0f;
+            const float pn = r[k] * id[k] + be * P[v];
+            P[v] = isu(k) ? pn : 0.0f;
         }
         __syncthreads();
         double sig = 0.0;
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
             const int v = slot(tb, k);
-            const float4 self = wp[v];
-            const float2 mx = *reinterpret_cast<const float2*>(&wp[v - off_x]);  // p, w+x of v - 1
-            const float4 my = wp[v - off_y];
-            const float4 mz = wp[v - off_z];
-            const float acc = self.y * wp[v + off_x].x + self.z * wp[v + off_y].x + self.w * wp[v + off_z].x +
-                              mx.y * mx.x + my.z * my.x + mz.w * mz.x;
-            q[k] = isu(k) ? d[k] * self.x - acc : 0.0f;
-            sig += (double)self.x * (double)q[k];
+            const float pv = P[v];
+            const float acc = WX[v] * P[v + 1] + WX[v - 1] * P[v - 1] + WY[v] * P[v + off_y] +
+                              WY[v - off_y] * P[v - off_y] + WZ[v] * P[v + off_z] + WZ[v - off_z] * P[v - off_z];
+            q[k] = isu(k) ? d[k] * pv - acc : 0.0f;
+            sig += (double)pv * (double)q[k];
         }
         double s1[1] = {sig};
         res_block_sum<NT, 1>(s1, red);
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
         for (int k = 0; k < VPT; ++k) {
             const int v = slot(tb, k);
             // p, q, r and 1/d are 0 on seeded and unused slots, so these stay 0
-            x[k] += al * wp[v].x;
+            x[k] += al * P[v];
             r[k] -= al * q[k];
             const float z = r[k] * id[k];
             acc2[0] += (double)r[k] * (double)z;
@@ -398,6 +402,17 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
         st.pending = corr && !(flags & 1) ? 1 : 0;
     }
 }
+
+// Launch shapes of the streamed-weights kernel per span: threads and group size.
+#ifndef RW_G0_NT
+#define RW_G0_NT 512
+#define RW_G0_G 8
+#endif
+#ifndef RW_G1_NT
+#define RW_G1_NT 512
+#define RW_G1_G 3
+#define RW_G1_XG true
+#endif
 
 // Variant for boxes whose search direction alone fits in one CU's LDS (up
 // to 32768 voxels, e.g. 32^3): LDS holds p only (4 B per voxel, pads as
@@ -559,13 +574,20 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
         asm volatile("" : "+v"(tb));
         asm volatile("" : "+v"(oy));
         asm volatile("" : "+v"(oz));
+        // byte offsets of a group's slots, from an opaque per-group base (so
+        // that the compiler keeps no per-slot offset beyond its group)
         const unsigned o0 = 4u * (unsigned)tb;
+        auto group_base = [&](int gi, unsigned ob) {
+            unsigned og = ob + 4u * (unsigned)(gi * G * NT);
+            asm volatile("" : "+v"(og));
+            return og;
+        };
         auto load_w = [&](int gi, float (&w)[G][6]) {
+            const unsigned og = group_base(gi, o0);
 #pragma unroll
             for (int j = 0; j < G; ++j) {
-                const int k = gi * G + j;
-                if (k < VPT) {
-                    const unsigned o = o0 + 4u * (unsigned)(k * NT);
+                if (gi * G + j < VPT) {
+                    const unsigned o = og + 4u * (unsigned)(j * NT);
                     w[j][0] = sb.ld(o, sWX);
                     w[j][1] = sb.ld(o, sWXm);
                     w[j][2] = sb.ld(o, sWY);
@@ -575,12 +597,12 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
                 }
             }
         };
-        auto load_i = [&](int gi, float (&w)[G][2]) {
+        auto load_i = [&](int gi, float (&w)[G][2], unsigned ob) {
+            const unsigned og = group_base(gi, ob);
 #pragma unroll
             for (int j = 0; j < G; ++j) {
-                const int k = gi * G + j;
-                if (k < VPT) {
-                    const unsigned o = o0 + 4u * (unsigned)(k * NT);
+                if (gi * G + j < VPT) {
+                    const unsigned o = og + 4u * (unsigned)(j * NT);
                     w[j][0] = sb.ld(o, sID);
                     if constexpr (XG) w[j][1] = sb.ld(o, sX);
                 }
@@ -606,7 +628,7 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
             if (gi + 1 < NG) load_w(gi + 1, wr[(gi + 1) & 1]);
-            else load_i(0, ir[0]);
+            else load_i(0, ir[0], o0);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < G; ++j) {
@@ -633,19 +655,24 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
         }
         const float al = (float)alpha;
         double acc2[2] = {0.0, 0.0};
+        // fresh opaque copy: no per-voxel address lives across the reduction
+        int t3 = threadIdx.x;
+        asm volatile("" : "+v"(t3));
+        const unsigned o3 = 4u * (unsigned)t3;
+        const float* const P3 = P + t3;
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
-            if (gi + 1 < NG) load_i(gi + 1, ir[(gi + 1) & 1]);
+            if (gi + 1 < NG) load_i(gi + 1, ir[(gi + 1) & 1], o3);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 const int k = gi * G + j;
                 if (k < VPT) {
                     const float id = ir[gi & 1][j][0];
-                    const float pv = Pt[k * NT];
+                    const float pv = P3[k * NT];
                     // p = 0 on seeded and unused slots; r stays 0 there (1/d = 0)
                     if constexpr (XG) {
-                        sb.st(o0 + 4u * (unsigned)(k * NT), sX, ir[gi & 1][j][1] + al * pv);
+                        sb.st(o3 + 4u * (unsigned)(k * NT), sX, ir[gi & 1][j][1] + al * pv);
                     } else {
                         x[k] += al * pv;
                     }
@@ -713,8 +740,8 @@ bool resident_w_fits(const BrickDev& b, size_t lds_limit) {
 // Voxel slots (threads x voxels per thread) of a streamed-weights launch
 // whose largest box has max_voxels voxels (0: too large).
 int64_t resident_g_span(int64_t max_voxels) {
-    if (max_voxels <= (int64_t)kResThreadsG * kResVptG0) return (int64_t)kResThreadsG * kResVptG0;
-    if (max_voxels <= (int64_t)kResThreadsG * kResMaxVptG) return (int64_t)kResThreadsG * kResMaxVptG;
+    if (max_voxels <= kResSpanG0) return kResSpanG0;
+    if (max_voxels <= kResSpanG1) return kResSpanG1;
     return 0;
 }
 
@@ -741,8 +768,7 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
                                  : (size_t)resident_lds_elems(max_voxels, max_plane) *
                                        (kind == 1 ? sizeof(float4) : sizeof(float2));
     const dim3 grid((unsigned)(b1 - b0));
-    const int nt = kind == 2 ? kResThreadsG : kResThreads;
-    auto go = [&](auto kern) -> hipError_t {
+    auto go = [&](auto kern, int nt) -> hipError_t {
         if (lds > 48 * 1024) {
             hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
@@ -754,20 +780,21 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
         // the plan sized each box's weight segment for this launch's span
         if (!a.wts) return hipErrorInvalidValue;
         const int64_t span = resident_g_span(max_voxels);
-        if (span == (int64_t)kResThreadsG * kResVptG0) return go(k_pcg_resg<kResThreadsG, kResVptG0, false, 8>);
-        if (span == (int64_t)kResThreadsG * kResMaxVptG) return go(k_pcg_resg<kResThreadsG, kResMaxVptG, true, 3>);
+        if (span == kResSpanG0) return go(k_pcg_resg<RW_G0_NT, kResSpanG0 / RW_G0_NT, false, RW_G0_G>, RW_G0_NT);
+        if (span == kResSpanG1) return go(k_pcg_resg<RW_G1_NT, kResSpanG1 / RW_G1_NT, RW_G1_XG, RW_G1_G>, RW_G1_NT);
         return hipErrorInvalidValue;
     }
+    const int nt = kResThreads;
     const int64_t vpt = (max_voxels + nt - 1) / nt;
     if (kind == 1) {
-        if (vpt <= 10) return go(k_pcg_resw<kResThreads, 10>);
-        if (vpt <= kResMaxVptW) return go(k_pcg_resw<kResThreads, kResMaxVptW>);
+        if (vpt <= 10) return go(k_pcg_resw<kResThreads, 10>, nt);
+        if (vpt <= kResMaxVptW) return go(k_pcg_resw<kResThreads, kResMaxVptW>, nt);
         return hipErrorInvalidValue;
     }
-    if (vpt <= 4) return go(k_pcg_res<kResThreads, 4>);
-    if (vpt <= 10) return go(k_pcg_res<kResThreads, 10>);
-    if (vpt <= 20) return go(k_pcg_res<kResThreads, 20>);
-    if (vpt <= kResMaxVpt) return go(k_pcg_res<kResThreads, kResMaxVpt>);
+    if (vpt <= 4) return go(k_pcg_res<kResThreads, 4>, nt);
+    if (vpt <= 10) return go(k_pcg_res<kResThreads, 10>, nt);
+    if (vpt <= 20) return go(k_pcg_res<kResThreads, 20>, nt);
+    if (vpt <= kResMaxVpt) return go(k_pcg_res<kResThreads, kResMaxVpt>, nt);
     return hipErrorInvalidValue;
 }
 

@@ -291,10 +291,11 @@ def test_resident_kernel_matches_oracle_and_streaming(env):
     plan0 = rwg.context().solve_plan(rwg.solve_params(schedule=0), bricks, d["g"].size)
     plan4 = rwg.context().solve_plan(rwg.solve_params(schedule=4), bricks, d["g"].size)
     nv = np.prod(np.asarray(shapes), axis=1)
-    # 32^3 and the other boxes above 17408 voxels take the streamed-weights
-    # kernel by default; with schedule 4 every box up to 32768 voxels does
-    assert np.all(plan0[nv > 17408] == rwg.PATH_RESIDENT_STREAMED), plan0
-    assert np.all(plan0[nv <= 17408] == rwg.PATH_RESIDENT), plan0
+    # boxes above 10240 voxels (up to 32^3) take the streamed-weights kernel
+    # by default, smaller ones keep the weights in LDS; with schedule 4
+    # every box up to 32768 voxels streams its weights
+    assert np.all(plan0[nv > 10240] == rwg.PATH_RESIDENT_STREAMED), plan0
+    assert np.all(plan0[nv <= 10240] == rwg.PATH_RESIDENT), plan0
     assert np.all(plan4 == rwg.PATH_RESIDENT_STREAMED), plan4
     for i, ref in enumerate(refs):
         o, n = int(d["offsets"][i]), ref.size
