@@ -36,17 +36,20 @@ EXTRAS = ("plain_sphere_64", "tubes_512_hierarchy", "blobs_512x32_adjoint", "she
 
 
 def source_hash():
+    """Hash of every HIP source and header of the library."""
     h = hashlib.sha256()
-    for f in ("pcg.hip", "capi.hip", "common.h"):
-        with open(os.path.join(ROOT, "paper_2103_09564_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2103_09564_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_ms_unused=None):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "k_pcg_w1_stress8192.md")
+def traffic_from_profile():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "k_pcg_resg_stress8192.md")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -295,7 +298,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--schedule", type=int, default=0, help="CG schedule: 0 library choice, 1 two-sweep, 2 one-sweep")
+    ap.add_argument("--schedule", type=int, default=0, help="CG schedule (rw_solve_params.schedule): 0 library choice, 1 two-sweep streaming, 2 one-sweep streaming, 3 as 0 with 2, 4 streamed-weights resident wherever it fits")
     ap.add_argument("--no-extras", action="store_true", help="skip the further workloads (sphere, tubes, blobs, shells)")
     ap.add_argument("--shells-dims", default="256,256,128", help="nested-shell volume dims nx,ny,nz")
     ap.add_argument("--only", choices=EXTRAS, default=None,
@@ -363,22 +366,32 @@ def main():
         vox_it = int(np.sum(sizes * iters))
         main = sizes * s["iters"].astype(np.int64)
         path = ctx.solve_plan(p, bricks, g.numel())
-        streaming = (path == rwg.PATH_STREAM) | (path == rwg.PATH_STREAM_GLOBAL)
+        hbm = (path == rwg.PATH_STREAM) | (path == rwg.PATH_STREAM_GLOBAL)
+        sw = path == rwg.PATH_RESIDENT_STREAMED
+        lds = path == rwg.PATH_RESIDENT
+        # the library runs two kernel groups concurrently: HBM-streaming and
+        # streamed-weights boxes on one stream (stream_ms), LDS-resident boxes
+        # on the other (resident_ms)
         return dict(wall=wall, kern=mean["pcg_ms"], t=mean, vox_it=vox_it, vox_it_main=int(main.sum()),
-                    vox_it_stream=int(main[streaming].sum()), vox_it_res=int(main[path == rwg.PATH_RESIDENT].sum()),
-                    n_stream=int(streaming.sum()), n_res=int((path == rwg.PATH_RESIDENT).sum()), stats=s,
-                    x=x.cpu().numpy())
+                    vox_it_a=int(main[hbm | sw].sum()), vox_it_sw=int(main[sw].sum()), vox_it_hbm=int(main[hbm].sum()),
+                    vox_it_res=int(main[lds].sum()), n_hbm=int(hbm.sum()), n_sw=int(sw.sum()), n_res=int(lds.sum()),
+                    stats=s, x=x.cpu().numpy())
 
     mixed = run(rwg.PREC_MIXED, args.steps, args.warmup)
     fp64 = None if args.no_fp64 else run(rwg.PREC_FP64, max(1, args.steps // 2), 1)
 
     value = mixed["vox_it"] / mixed["wall"]
-    # dominant kernel: the streaming PCG kernel of the main solve (boxes too
-    # large for the LDS-resident kernel, which runs concurrently); algorithmic
-    # bytes of one launch = 28 B x the voxel-iterations it executes, over its
-    # duration from the library's HIP events on its stream
+    # Dominant kernel: the streamed-weights resident PCG (k_pcg_resg, the 32^3
+    # and 32x32x17 boxes; two launches per call), with any HBM-streaming boxes
+    # on the same stream.  Algorithmic bytes = 28 B (the streaming
+    # formulation's floor: read x, r, p, g, write x, r, p) x the
+    # voxel-iterations of its launches, over their duration from the
+    # library's HIP events on that stream.  The kernel itself keeps x (32x32x17),
+    # r and p on chip and re-reads 16-24 B per voxel-iteration of precomputed
+    # weights that stay in the Infinity Cache, so it can beat that floor;
+    # traffic gives the measured DRAM bytes.
     t = mixed["t"]
-    achieved = BYTES_PER_VOXEL_ITER * mixed["vox_it_stream"] / t["stream_ms"] / 1e9 if t["stream_ms"] > 0 else 0.0
+    achieved = BYTES_PER_VOXEL_ITER * mixed["vox_it_a"] / t["stream_ms"] / 1e9 if t["stream_ms"] > 0 else 0.0
     traffic = traffic_from_profile()
     s = mixed["stats"]
     out = {
@@ -400,18 +413,23 @@ def main():
                    "tol": TOL, "precision": "mixed (FP32 vectors, FP64 reductions + FP64 true-residual check)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "kernel": "k_pcg_resg (streamed-weights resident PCG), main-solve launches",
+                     "note": "achieved counts the 28 B/voxel-iteration of the HBM-streaming formulation; the kernel "
+                             "keeps the CG vectors on chip and re-reads cached weights, so frac can exceed 1; "
+                             "traffic is its measured DRAM bytes per launch"},
         "solve": {"pcg_phase_ms": mixed["kern"] * 1e3, "voxel_iters": mixed["vox_it"],
                   "pcg_voxel_iters": mixed["vox_it_main"],
                   "pcg_phase_voxel_iters_per_s": mixed["vox_it_main"] / mixed["kern"],
-                  "streaming": {"boxes": mixed["n_stream"], "voxel_iters": mixed["vox_it_stream"],
-                                "ms": t["stream_ms"] * 1e3,
-                                "voxel_iters_per_s": mixed["vox_it_stream"] / t["stream_ms"] if t["stream_ms"] else None},
+                  "pcg_phase_algorithmic_GBps": BYTES_PER_VOXEL_ITER * mixed["vox_it_main"] / mixed["kern"] / 1e9,
+                  "stream_group": {"boxes_streamed_weights": mixed["n_sw"], "boxes_hbm_streaming": mixed["n_hbm"],
+                                   "voxel_iters": mixed["vox_it_a"], "ms": t["stream_ms"] * 1e3,
+                                   "voxel_iters_per_s": mixed["vox_it_a"] / t["stream_ms"] if t["stream_ms"] else None},
                   "lds_resident": {"boxes": mixed["n_res"], "voxel_iters": mixed["vox_it_res"],
                                    "ms": t["resident_ms"] * 1e3,
                                    "voxel_iters_per_s": mixed["vox_it_res"] / t["resident_ms"] if t["resident_ms"] else None,
-                                   "note": "on-chip: vectors stay in LDS and registers during the iteration; "
-                                           "HBM is read once per solve, so no HBM roofline applies"},
+                                   "note": "on-chip: p and the edge weights in LDS, x and r in registers; HBM is "
+                                           "read once per solve, so no HBM roofline applies"},
                   "mean_iters": float(s["iters"].mean()), "max_iters": int(s["iters"].max()),
                   "refined_boxes": int((s["refine_steps"] > 0).sum()),
                   "status_counts": {rwg.STATUS_NAMES[k]: int((s["status"] == k).sum()) for k in np.unique(s["status"])},
