@@ -74,6 +74,7 @@ struct BoxState {
     int32_t iters, status, refine_steps, refine_iters;
     int32_t active;               // next k_pcg runs on this machine
     int32_t pending;              // a correction was solved and is to be applied
+    int32_t checked, check_ok;    // true_rel is current for x (no correction applied since), and its verdict
 };
 
 struct SolveArgs {

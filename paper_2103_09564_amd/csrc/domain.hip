@@ -293,6 +293,7 @@ __global__ __launch_bounds__(kDomThreads) void k_dinit(SolveArgs a, int ib) {
         st.status = nM == 0.0 ? RW_ST_NO_DIRICHLET : RW_ST_CONVERGED;
         st.active = (nM > 0.0 && nU > 0.0 && !allzero) ? 1 : 0;
         st.pending = 0;
+        st.checked = 0;
     }
 }
 

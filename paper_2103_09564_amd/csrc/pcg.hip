@@ -1121,6 +1121,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SolveArgs a, int base) {
         st.status = nM == 0.0 ? RW_ST_NO_DIRICHLET : RW_ST_CONVERGED;
         st.active = (nM > 0.0 && nU > 0.0 && !allzero) ? 1 : 0;
         st.pending = 0;
+        st.checked = 0;
     }
 }
 
@@ -1208,6 +1209,19 @@ __global__ __launch_bounds__(kThreads) void k_check(SolveArgs a, int may_refine,
         if (threadIdx.x == 0) st.active = 0;
         return;
     }
+    // x unchanged since this box's last check (no correction applied): its
+    // true residual and verdict stand; only a retried correction needs the pass
+    if (st.checked) {
+        const bool ok = st.check_ok != 0;
+        if (!(may_refine && !ok && st.refine_steps < a.refine_max)) {
+            if (threadIdx.x == 0) {
+                st.active = 0;
+                if (!may_refine && st.refine_steps > 0 && st.status == RW_ST_CONVERGED)
+                    st.status = ok ? RW_ST_REFINED : RW_ST_STALLED;
+            }
+            return;
+        }
+    }
     const BrickDev bd = a.bricks[ib];
     const Box b = box_of(bd);
     Vecs<float, R> V = vecs<float, R>(a);
@@ -1256,6 +1270,8 @@ __global__ __launch_bounds__(kThreads) void k_check(SolveArgs a, int may_refine,
     }
     if (threadIdx.x == 0) {
         st.true_rel = tr;
+        st.checked = 1;
+        st.check_ok = ok ? 1 : 0;
         st.active = refine ? 1 : 0;
         if (!may_refine && st.refine_steps > 0 && st.status == RW_ST_CONVERGED)
             st.status = ok ? RW_ST_REFINED : RW_ST_STALLED;
@@ -1281,6 +1297,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(SolveArgs a, int base) {
     if (threadIdx.x == 0) {
         st.refine_steps += 1;
         st.pending = 0;
+        st.checked = 0;
     }
 }
 
@@ -1383,6 +1400,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_init(AdjointArgs a, SolveArgs 
         st.status = cnt[0] == 0.0 ? RW_ST_NO_DIRICHLET : RW_ST_CONVERGED;
         st.active = (cnt[0] > 0.0 && e[1] > 0.0) ? 1 : 0;
         st.pending = 0;
+        st.checked = 0;
     }
 }
 
