@@ -191,10 +191,12 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
         L.kind = gi <= 4 ? 2 : gi == 5 ? 0 : 1;
         L.max_voxels = 0;
         L.max_plane = 0;
+        L.px = 32;
         for (int64_t i = L.b0; i < L.b1; ++i) {
             const auto& b = (*list)[(size_t)i];
             L.max_voxels = std::max<int64_t>(L.max_voxels, (int64_t)b.nx * b.ny * b.nz);
             L.max_plane = std::max<int64_t>(L.max_plane, (int64_t)b.nx * b.ny);
+            if (b.nx != 32 || b.ny != 32) L.px = 0;
         }
         if (L.kind == 2) {
             const int64_t span = rwk::resident_g_span(L.max_voxels);

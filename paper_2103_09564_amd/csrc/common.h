@@ -141,6 +141,7 @@ struct PlanePlan {
         int64_t max_voxels;   // largest box of the range
         int64_t max_plane;    // widest nx*ny of the range
         int kind;             // 0: (g, p) kernel, 1: weights kernel, 2: streamed-weights kernel
+        int px;               // 32 when every box of the range has 32 x 32 planes, else 0
     } rl[5];
     int64_t wts_elems;        // floats of weight segments the kind-2 boxes need (BrickDev::woff)
     // when set, the streaming and resident groups run on these two streams
@@ -165,7 +166,7 @@ bool resident_g_fits(const BrickDev& b, size_t lds_limit);    // streamed-weight
 int64_t resident_g_span(int64_t max_voxels);                  // its voxel slots per workgroup
 int64_t resident_g_elems(const BrickDev& b, int64_t span);    // a box's weight segment, in floats
 hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_voxels, int64_t max_plane,
-                           int kind, float* xt, int corr, hipStream_t s);
+                           int kind, int px, float* xt, int corr, hipStream_t s);
 
 size_t plane_lds_bytes(int nrhs, bool fp64, int cols);
 

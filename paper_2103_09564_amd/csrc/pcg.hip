@@ -1512,8 +1512,8 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
     if constexpr (kRes) {
         for (int i = 0; i < pp.n_rl; ++i)
             if (pp.rl[i].kind == 2)
-                RW_TRY(launch_resident(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_voxels, pp.rl[i].max_plane, 2, xt,
-                                       corr, s_str));
+                RW_TRY(launch_resident(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_voxels, pp.rl[i].max_plane, 2,
+                                       pp.rl[i].px, xt, corr, s_str));
     }
     if (tev && on_a) RW_TRY(hipEventRecord(tev[1], s_str));
     if constexpr (kRes) {
@@ -1521,7 +1521,7 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
         for (int i = 0; i < pp.n_rl; ++i)
             if (pp.rl[i].kind != 2)
                 RW_TRY(launch_resident(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_voxels, pp.rl[i].max_plane,
-                                       pp.rl[i].kind, xt, corr, s_res));
+                                       pp.rl[i].kind, pp.rl[i].px, xt, corr, s_res));
         if (tev && any_lds) RW_TRY(hipEventRecord(tev[3], s_res));
     }
     if (fork) {

@@ -403,16 +403,6 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
     }
 }
 
-// Launch shapes of the streamed-weights kernel per span: threads and group size.
-#ifndef RW_G0_NT
-#define RW_G0_NT 512
-#define RW_G0_G 8
-#endif
-#ifndef RW_G1_NT
-#define RW_G1_NT 512
-#define RW_G1_G 3
-#define RW_G1_XG true
-#endif
 
 // Variant for boxes whose search direction alone fits in one CU's LDS (up
 // to 32768 voxels, e.g. 32^3): LDS holds p only (4 B per voxel, pads as
@@ -420,16 +410,15 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
 // launch into the box's segment of a global buffer and read back in every
 // iteration; a box's segment stays in the last-level cache while its
 // workgroup iterates, so an iteration reads about 16 B per voxel from there
-// and computes no exponential.  r and q (q holds z between iterations) stay
-// in registers, and x too unless XG (then x is updated in place in global
-// memory, 8 B per voxel and iteration, to leave registers for the loads).
+// and computes no exponential.  x, r and q (q holds z between iterations)
+// stay in registers.
 //
-// Segment of a box (floats): arrays WX, WY, WZ, ID (and X when XG) of
-// stride T = nx*ny + NT*VPT, each nx*ny zeros, the box, then zeros up to
-// NT*VPT.  Thread t owns the slots t + k*NT, k < VPT, of which those >= nv
-// are unused: they read LDS pads and segment zeros (p = 0, 1/d = 0) and
-// write only their own X element, so no address is clamped.  1/d = 0 also
-// marks seeded voxels, whose r is kept at 0.
+// Segment of a box (floats): arrays WX, WY, WZ, ID of stride
+// T = nx*ny + NT*VPT, each nx*ny zeros, the box, then zeros up to NT*VPT.
+// Thread t owns the slots t + k*NT, k < VPT, of which those >= nv are
+// unused: they read LDS pads and segment zeros (p = 0, 1/d = 0), so no
+// address is clamped.  1/d = 0 also marks seeded voxels, whose r is kept
+// at 0.
 //
 // The loads of each phase are issued G voxels ahead of their use (a
 // two-group register ring, pinned with scheduling barriers), so a wave has
@@ -442,9 +431,6 @@ struct SegBuf {
     __amdgpu_buffer_rsrc_t rsrc;
     __device__ __forceinline__ float ld(unsigned vo, int so) const {
         return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)vo, so, 0));
-    }
-    __device__ __forceinline__ void st(unsigned vo, int so, float v) const {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rsrc, (int)vo, so, 0);
     }
 };
 
@@ -481,17 +467,18 @@ __device__ __forceinline__ void res_block_sum_lds(double (&v)[N], double* red) {
     res_lds_barrier();
 }
 
-template <int NT, int VPT, bool XG, int G>
+// PX > 0: every box of the launch has nx = ny = PX, so the neighbour offsets
+// are compile-time and the LDS reads use immediate offsets from a few bases.
+template <int NT, int VPT, int G, int PX>
 __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int corr, int base) {
     extern __shared__ __align__(16) float p_lds[];
     __shared__ double red[(NT / 64) * 2];
     constexpr int NG = (VPT + G - 1) / G;
-    constexpr int XR = XG ? 1 : VPT;  // register copy of x
     const int ib = base + blockIdx.x;
     BoxState& st = a.state[ib];
     if (!st.active) return;
     const BrickDev bd = a.bricks[ib];
-    const int nx = bd.nx, ny = bd.ny, nz = bd.nz, nxy = nx * ny, nv = nxy * nz;
+    const int nx = PX ? PX : bd.nx, ny = PX ? PX : bd.ny, nz = bd.nz, nxy = nx * ny, nv = nxy * nz;
     constexpr int span = NT * VPT;
     const int T = nxy + span;  // stride of the segment arrays
     float* P = p_lds + nxy;
@@ -504,13 +491,12 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
     float* const WY = WX + T;
     float* const WZ = WY + T;
     float* const ID = WZ + T;
-    float* const X = ID + T;  // XG only
     const ResWeight W{(float)(-a.beta * 1.4426950408889634), (float)a.eps};
 
     // weights (0 toward neighbours outside the box) and 1/d (0 on seeded
     // voxels); pads and unused slots are 0
     for (int v = (int)threadIdx.x - nxy; v < span; v += NT) {
-        float wx = 0.0f, wy = 0.0f, wz = 0.0f, id = 0.0f, xv = 0.0f;
+        float wx = 0.0f, wy = 0.0f, wz = 0.0f, id = 0.0f;
         if (v >= 0 && v < nv) {
             const int kz = v / nxy, rem = v - kz * nxy, j = rem / nx, i = rem - j * nx;
             const float gc = g[v];
@@ -522,35 +508,30 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
             if (j > 0) d += W(g[v - nx], gc);
             if (kz > 0) d += W(g[v - nxy], gc);
             if (m[v] == 0) id = __builtin_amdgcn_rcpf(d);
-            if constexpr (XG) xv = xb[v];
         }
         WX[v] = wx;
         WY[v] = wy;
         WZ[v] = wz;
         ID[v] = id;
-        if constexpr (XG) X[v] = xv;
     }
     for (int v = (int)threadIdx.x - nxy; v < span + nxy; v += NT) P[v] = 0.0f;
 
-    float x[XR], r[VPT], q[VPT];
+    float x[VPT], r[VPT], q[VPT];
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
         const int v0 = threadIdx.x + k * NT;
         const int v = v0 < nv ? v0 : nv - 1;
         const bool u = v0 < nv && m[v] == 0;
-        const float rv = rb[v];
+        const float rv = rb[v], xv = xb[v];
         r[k] = u ? rv : 0.0f;
-        if constexpr (!XG) {
-            const float xv = xb[v];
-            x[k] = u ? xv : 0.0f;
-        }
+        x[k] = u ? xv : 0.0f;
     }
     // the weights written above are read by other threads of the workgroup
     __syncthreads();
     // 0x00020000: raw 32-bit buffer (third descriptor word for this chip family)
-    const SegBuf sb{__builtin_amdgcn_make_buffer_rsrc(seg, 0, (int)(4 * (5 * T)), 0x00020000)};
+    const SegBuf sb{__builtin_amdgcn_make_buffer_rsrc(seg, 0, (int)(4 * (4 * T)), 0x00020000)};
     // byte offsets of the arrays (from voxel 0 of WX) and of the backward neighbours
-    const int sWX = 4 * nxy, sWY = sWX + 4 * T, sWZ = sWY + 4 * T, sID = sWZ + 4 * T, sX = sID + 4 * T;
+    const int sWX = 4 * nxy, sWY = sWX + 4 * T, sWZ = sWY + 4 * T, sID = sWZ + 4 * T;
     const int sWXm = sWX - 4, sWYm = sWY - 4 * nx, sWZm = sWZ - 4 * nxy;
 #pragma unroll
     for (int k = 0; k < VPT; ++k) q[k] = r[k] * sb.ld(4u * (unsigned)(threadIdx.x + k * NT), sID);  // start z
@@ -561,7 +542,7 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
     const double tol2 = tol * tol;
     double betac = 0.0;
     float wr[2][G][6];  // weights of two groups of voxels
-    float ir[2][G][2];  // 1/d and (XG) x of two groups
+    float ir[2][G];     // 1/d of two groups
     int it = 0, flags = 0;
     for (;;) {
         if (rr <= tol2 * bb) break;
@@ -572,8 +553,10 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
         // opaque copies: per-voxel addresses stay inside the loop
         int tb = threadIdx.x, oy = nx, oz = nxy;
         asm volatile("" : "+v"(tb));
-        asm volatile("" : "+v"(oy));
-        asm volatile("" : "+v"(oz));
+        if constexpr (PX == 0) {
+            asm volatile("" : "+v"(oy));
+            asm volatile("" : "+v"(oz));
+        }
         // byte offsets of a group's slots, from an opaque per-group base (so
         // that the compiler keeps no per-slot offset beyond its group)
         const unsigned o0 = 4u * (unsigned)tb;
@@ -597,16 +580,11 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
                 }
             }
         };
-        auto load_i = [&](int gi, float (&w)[G][2], unsigned ob) {
+        auto load_i = [&](int gi, float (&w)[G], unsigned ob) {
             const unsigned og = group_base(gi, ob);
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                if (gi * G + j < VPT) {
-                    const unsigned o = og + 4u * (unsigned)(j * NT);
-                    w[j][0] = sb.ld(o, sID);
-                    if constexpr (XG) w[j][1] = sb.ld(o, sX);
-                }
-            }
+            for (int j = 0; j < G; ++j)
+                if (gi * G + j < VPT) w[j] = sb.ld(og + 4u * (unsigned)(j * NT), sID);
         };
         load_w(0, wr[0]);
         const float be = it == 0 ? 0.0f : (float)betac;
@@ -668,14 +646,13 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
             for (int j = 0; j < G; ++j) {
                 const int k = gi * G + j;
                 if (k < VPT) {
-                    const float id = ir[gi & 1][j][0];
+                    const float id = ir[gi & 1][j];
                     const float pv = P3[k * NT];
                     // p = 0 on seeded and unused slots; r stays 0 there (1/d = 0)
-                    if constexpr (XG) {
-                        sb.st(o3 + 4u * (unsigned)(k * NT), sX, ir[gi & 1][j][1] + al * pv);
-                    } else {
-                        x[k] += al * pv;
-                    }
+                    x[k] += al * pv;
+                    // pin the update here: sunk below the reduction it would
+                    // keep every p value of the pass live
+                    asm volatile("" : "+v"(x[k]));
                     const float rn = r[k] - al * q[k];
                     r[k] = id != 0.0f ? rn : 0.0f;
                     const float z = r[k] * id;
@@ -699,10 +676,7 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
         const int v = threadIdx.x + k * NT;
-        if (v < nv && m[v] == 0) {
-            if constexpr (XG) xb[v] = X[v];  // written by this thread
-            else xb[v] = x[k];
-        }
+        if (v < nv && m[v] == 0) xb[v] = x[k];
     }
     if (threadIdx.x == 0) {
         st.rz[0] = rz;
@@ -755,14 +729,14 @@ bool resident_g_fits(const BrickDev& b, size_t lds_limit) {
 
 int64_t resident_g_elems(const BrickDev& b, int64_t span) {
     const int64_t nxy = (int64_t)b.nx * b.ny;
-    return (5 * (nxy + span) + 63) & ~int64_t(63);  // five arrays, whole 256-byte lines
+    return (4 * (nxy + span) + 63) & ~int64_t(63);  // four arrays, whole 256-byte lines
 }
 
 // Boxes [b0, b1) of the launch list, all eligible for the kernel `kind`
 // (0: g and p in LDS, 1: weights and p in LDS, 2: p in LDS and weights in a
-// global buffer), largest first.
+// global buffer), largest first; px = 32 when every box has 32 x 32 planes.
 hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_voxels, int64_t max_plane,
-                           int kind, float* xt, int corr, hipStream_t s) {
+                           int kind, int px, float* xt, int corr, hipStream_t s) {
     if (b1 <= b0) return hipSuccess;
     const size_t lds = kind == 2 ? resident_g_lds(resident_g_span(max_voxels), max_plane)
                                  : (size_t)resident_lds_elems(max_voxels, max_plane) *
@@ -780,8 +754,15 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
         // the plan sized each box's weight segment for this launch's span
         if (!a.wts) return hipErrorInvalidValue;
         const int64_t span = resident_g_span(max_voxels);
-        if (span == kResSpanG0) return go(k_pcg_resg<RW_G0_NT, kResSpanG0 / RW_G0_NT, false, RW_G0_G>, RW_G0_NT);
-        if (span == kResSpanG1) return go(k_pcg_resg<RW_G1_NT, kResSpanG1 / RW_G1_NT, RW_G1_XG, RW_G1_G>, RW_G1_NT);
+        // 512 threads; loads issued 8 voxels ahead (34 per thread) or 2 (64
+        // per thread, where three register arrays leave room for no more)
+        constexpr int nt = kResThreads;
+        if (span == kResSpanG0)
+            return px == 32 ? go(k_pcg_resg<nt, kResSpanG0 / nt, 8, 32>, nt)
+                            : go(k_pcg_resg<nt, kResSpanG0 / nt, 8, 0>, nt);
+        if (span == kResSpanG1)
+            return px == 32 ? go(k_pcg_resg<nt, kResSpanG1 / nt, 2, 32>, nt)
+                            : go(k_pcg_resg<nt, kResSpanG1 / nt, 2, 0>, nt);
         return hipErrorInvalidValue;
     }
     const int nt = kResThreads;
