@@ -386,10 +386,10 @@ def main():
     # on the same stream.  Algorithmic bytes = 28 B (the streaming
     # formulation's floor: read x, r, p, g, write x, r, p) x the
     # voxel-iterations of its launches, over their duration from the
-    # library's HIP events on that stream.  The kernel itself keeps x (32x32x17),
-    # r and p on chip and re-reads 16-24 B per voxel-iteration of precomputed
-    # weights that stay in the Infinity Cache, so it can beat that floor;
-    # traffic gives the measured DRAM bytes.
+    # library's HIP events on that stream.  The kernel itself keeps x, r and p
+    # on chip and re-reads 16 B per voxel-iteration of precomputed weights and
+    # 1/d that stay in the Infinity Cache, so it can beat that floor; traffic
+    # gives the measured DRAM bytes.
     t = mixed["t"]
     achieved = BYTES_PER_VOXEL_ITER * mixed["vox_it_a"] / t["stream_ms"] / 1e9 if t["stream_ms"] > 0 else 0.0
     traffic = traffic_from_profile()
