@@ -420,9 +420,13 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
 // address is clamped.  1/d = 0 also marks seeded voxels, whose r is kept
 // at 0.
 //
-// The loads of each phase are issued G voxels ahead of their use (a
-// two-group register ring, pinned with scheduling barriers), so a wave has
-// about 6G loads in flight instead of waiting on each voxel's weights.
+// The forward weights (and 1/d) are loaded G voxels ahead of their use (a
+// two-group register ring, pinned with scheduling barriers), so a wave keeps
+// 3G loads to the Infinity Cache in flight instead of waiting on each
+// voxel's weights.  The backward weights are lines the same or a
+// neighbouring lane or wave has just brought into L1; they are loaded when
+// their group is computed, before the next group's forward loads, so that
+// waiting for them (loads complete in order) leaves those in flight.
 // Segment accesses are buffer instructions on one resource for the
 // segment: a per-voxel byte offset in a VGPR and the array (and neighbour)
 // offset in an SGPR, so no 64-bit address is formed or kept per voxel.
@@ -541,7 +545,11 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
     const double tol = corr ? a.inner_tol : a.tol;
     const double tol2 = tol * tol;
     double betac = 0.0;
-    float wr[2][G][6];  // weights of two groups of voxels
+    // The z-backward weight of slot k is the z-forward weight of slot k - 2
+    // when the plane is 1024 voxels and the workgroup 512 threads: taken
+    // from registers, not loaded.
+    constexpr bool kZc = PX == 32 && NT == 512;
+    float wr[2][G][3];  // forward weights of two groups of voxels
     float ir[2][G];     // 1/d of two groups
     int it = 0, flags = 0;
     for (;;) {
@@ -565,18 +573,30 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
             asm volatile("" : "+v"(og));
             return og;
         };
-        auto load_w = [&](int gi, float (&w)[G][6]) {
+        // forward weights (from the Infinity Cache: issued a group ahead)
+        auto load_w = [&](int gi, float (&w)[G][3]) {
             const unsigned og = group_base(gi, o0);
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 if (gi * G + j < VPT) {
                     const unsigned o = og + 4u * (unsigned)(j * NT);
                     w[j][0] = sb.ld(o, sWX);
-                    w[j][1] = sb.ld(o, sWXm);
-                    w[j][2] = sb.ld(o, sWY);
-                    w[j][3] = sb.ld(o, sWYm);
-                    w[j][4] = sb.ld(o, sWZ);
-                    w[j][5] = sb.ld(o, sWZm);
+                    w[j][1] = sb.ld(o, sWY);
+                    w[j][2] = sb.ld(o, sWZ);
+                }
+            }
+        };
+        // backward weights: lines the forward loads of this or a neighbouring
+        // lane or wave just brought into L1, loaded when the group is computed
+        auto load_b = [&](int gi, float (&w)[G][3]) {
+            const unsigned og = group_base(gi, o0);
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if (gi * G + j < VPT) {
+                    const unsigned o = og + 4u * (unsigned)(j * NT);
+                    w[j][0] = sb.ld(o, sWXm);
+                    w[j][1] = sb.ld(o, sWYm);
+                    if constexpr (!kZc) w[j][2] = sb.ld(o, sWZm);
                 }
             }
         };
@@ -603,8 +623,14 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
         const float* const Pzm = Pt - oz;
         const float* const Pzp = Pt + oz;
         double sig = 0.0;
+        float wz2 = 0.0f, wz1 = 0.0f;  // z-forward weights of slots k - 2, k - 1 (kZc; pads before slot 0)
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
+            // this group's backward loads go first: waiting for them must not
+            // wait for the next group's forward loads (loads complete in order)
+            float wb[G][3];
+            load_b(gi, wb);
+            __builtin_amdgcn_sched_barrier(0);
             if (gi + 1 < NG) load_w(gi + 1, wr[(gi + 1) & 1]);
             else load_i(0, ir[0], o0);
             __builtin_amdgcn_sched_barrier(0);
@@ -612,11 +638,20 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
             for (int j = 0; j < G; ++j) {
                 const int k = gi * G + j;
                 if (k < VPT) {
-                    const float(&w)[6] = wr[gi & 1][j];
-                    const float d = ((w[0] + w[1]) + (w[2] + w[3])) + (w[4] + w[5]);
+                    const float wxp = wr[gi & 1][j][0], wyp = wr[gi & 1][j][1], wzp = wr[gi & 1][j][2];
+                    const float wxm = wb[j][0], wym = wb[j][1];
+                    float wzm;
+                    if constexpr (kZc) {
+                        wzm = wz2;
+                        wz2 = wz1;
+                        wz1 = wzp;
+                    } else {
+                        wzm = wb[j][2];
+                    }
+                    const float d = ((wxp + wxm) + (wyp + wym)) + (wzp + wzm);
                     const float pv = Pt[k * NT];
-                    const float acc = w[0] * Pxm[k * NT + 2] + w[1] * Pxm[k * NT] + w[2] * Pyp[k * NT] +
-                                      w[3] * Pym[k * NT] + w[4] * Pzp[k * NT] + w[5] * Pzm[k * NT];
+                    const float acc = wxp * Pxm[k * NT + 2] + wxm * Pxm[k * NT] + wyp * Pyp[k * NT] +
+                                      wym * Pym[k * NT] + wzp * Pzp[k * NT] + wzm * Pzm[k * NT];
                     q[k] = d * pv - acc;  // masked in the update below
                     sig += (double)pv * (double)q[k];
                 }
@@ -754,15 +789,16 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
         // the plan sized each box's weight segment for this launch's span
         if (!a.wts) return hipErrorInvalidValue;
         const int64_t span = resident_g_span(max_voxels);
-        // 512 threads; loads issued 8 voxels ahead (34 per thread) or 2 (64
-        // per thread, where three register arrays leave room for no more)
+        // 512 threads; forward weights issued 8 voxels ahead (34 per thread)
+        // or 5 (64 per thread, where three register arrays leave room for
+        // no more)
         constexpr int nt = kResThreads;
         if (span == kResSpanG0)
             return px == 32 ? go(k_pcg_resg<nt, kResSpanG0 / nt, 8, 32>, nt)
                             : go(k_pcg_resg<nt, kResSpanG0 / nt, 8, 0>, nt);
         if (span == kResSpanG1)
-            return px == 32 ? go(k_pcg_resg<nt, kResSpanG1 / nt, 2, 32>, nt)
-                            : go(k_pcg_resg<nt, kResSpanG1 / nt, 2, 0>, nt);
+            return px == 32 ? go(k_pcg_resg<nt, kResSpanG1 / nt, 5, 32>, nt)
+                            : go(k_pcg_resg<nt, kResSpanG1 / nt, 5, 0>, nt);
         return hipErrorInvalidValue;
     }
     const int nt = kResThreads;
