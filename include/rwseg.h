@@ -94,8 +94,9 @@ typedef struct rw_solve_params {
     double stall_ratio;      /* MIXED: a box counts as stalled, and gets a correction solve, when
                                 its FP64 true relative residual exceeds stall_ratio * tol (>= 1) */
     int32_t schedule;        /* CG iteration schedule: 0 library choice (MIXED with nrhs 1: boxes
-                                that fit one CU's LDS run entirely in LDS and registers, the
-                                others stream as in 1), 1 streaming, two sweeps and two
+                                up to 32^3 whose search direction fits one CU's LDS run resident,
+                                RW_PATH_RESIDENT or RW_PATH_RESIDENT_STREAMED; the others stream
+                                as in 1), 1 streaming, two sweeps and two
                                 reductions per iteration (Hestenes-Stiefel), 2 streaming, one
                                 sweep and one reduction (Chronopoulos-Gear; weights computed once
                                 per iteration), 3 as 0 with the streaming boxes as in 2, 4 as 0
@@ -177,8 +178,8 @@ int rw_last_timing(rw_ctx* ctx, rw_timing* out);
 enum rw_path {
     RW_PATH_STREAM = 0,          /* one workgroup per box, vectors streamed from HBM, LDS window march */
     RW_PATH_STREAM_GLOBAL = 1,   /* the same without the LDS window (planes wider than it holds) */
-    RW_PATH_RESIDENT = 2,        /* one workgroup per box, g and p (or p and the edge weights) in
-                                    LDS, x and r in registers */
+    RW_PATH_RESIDENT = 2,        /* one workgroup per box, p and the edge weights in LDS (boxes up
+                                    to 10240 voxels), x and r in registers */
     RW_PATH_DOMAIN = 3,          /* large single box: many workgroups, host-driven iteration */
     RW_PATH_RESIDENT_STREAMED = 4 /* one workgroup per box, p in LDS, r in registers; the edge
                                     weights and 1/d are computed once into a per-box buffer and

@@ -140,8 +140,8 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     const int lim = use ? rwk::plane_max(cols) : 0;
     // group 0: domain solver, 1: global march, 2: plane march, 3 and 4:
     // resident (p in LDS, weights streamed) above and up to kResSpanG0
-    // voxels, 5: resident (g, p), 6: resident (weights), 7: resident
-    // (weights) small boxes; the list is largest-first
+    // voxels, 5: resident (weights in LDS), 6: the same for small boxes;
+    // the list is largest-first
     std::vector<uint8_t> grp(list->size());
     int n_dom = 0;
     for (size_t i = 0; i < list->size(); ++i) {
@@ -156,11 +156,9 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
         } else if (res_ok && prefer_g && rwk::resident_g_fits(b, ctx->lds_limit)) {
             grp[i] = vox > rwk::kResSpanG0 ? 3 : 4;
         } else if (res_ok && rwk::resident_w_fits(b, ctx->lds_limit)) {
-            grp[i] = vox <= res_small ? 7 : 6;
+            grp[i] = vox <= res_small ? 6 : 5;
         } else if (res_ok && rwk::resident_g_fits(b, ctx->lds_limit)) {
             grp[i] = vox > rwk::kResSpanG0 ? 3 : 4;
-        } else if (res_ok && rwk::resident_fits(b, ctx->lds_limit)) {
-            grp[i] = 5;
         } else {
             grp[i] = wide ? 1 : 2;
         }
@@ -169,7 +167,7 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     std::iota(idx.begin(), idx.end(), size_t(0));
     std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return grp[a] < grp[b]; });
     std::vector<rwk::BrickDev> sorted(list->size());
-    int64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t cnt[7] = {0, 0, 0, 0, 0, 0, 0};
     for (size_t i = 0; i < idx.size(); ++i) {
         sorted[i] = (*list)[idx[i]];
         cnt[grp[idx[i]]] += 1;
@@ -183,12 +181,12 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     pp.n_rl = 0;
     int64_t b0 = pp.n_res;
     pp.wts_elems = 0;
-    for (int gi = 3; gi <= 7; ++gi) {
+    for (int gi = 3; gi <= 6; ++gi) {
         if (cnt[gi] == 0) continue;
         rwk::PlanePlan::ResLaunch& L = pp.rl[pp.n_rl++];
         L.b0 = b0;
         L.b1 = b0 + cnt[gi];
-        L.kind = gi <= 4 ? 2 : gi == 5 ? 0 : 1;
+        L.kind = gi <= 4 ? 2 : 1;
         L.max_voxels = 0;
         L.max_plane = 0;
         L.px = 32;

@@ -129,20 +129,21 @@ struct PlanePlan {
     int64_t n_big;
     int64_t n_dom;
     const BrickDev* host;
-    // LDS-resident PCG (one rhs, FP32): boxes [n_res, n), in up to three
-    // launches (largest box first within each): (g, p) in LDS, then
-    // precomputed weights and p in LDS for larger and for small boxes
-    // (launched apart so that their LDS size lets several workgroups share
-    // a CU).  Without resident boxes n_res = n.
+    // Resident PCG (one rhs, FP32): boxes [n_res, n), in up to four launches
+    // (largest box first within each): p in LDS with the weights streamed
+    // from a per-box segment (boxes above and up to 17408 voxels), then p and
+    // the weights in LDS for larger and for small boxes (launched apart so
+    // that their LDS size lets several workgroups share a CU).  Without
+    // resident boxes n_res = n.
     int64_t n_res;
     int n_rl;
     struct ResLaunch {
         int64_t b0, b1;       // launch-list range
         int64_t max_voxels;   // largest box of the range
         int64_t max_plane;    // widest nx*ny of the range
-        int kind;             // 0: (g, p) kernel, 1: weights kernel, 2: streamed-weights kernel
+        int kind;             // 1: weights-in-LDS kernel, 2: streamed-weights kernel
         int px;               // 32 when every box of the range has 32 x 32 planes, else 0
-    } rl[5];
+    } rl[4];
     int64_t wts_elems;        // floats of weight segments the kind-2 boxes need (BrickDev::woff)
     // when set, the streaming and resident groups run on these two streams
     // (forked from and joined back into the caller's stream)
@@ -153,15 +154,13 @@ struct PlanePlan {
     hipEvent_t* gev;
 };
 
-// LDS-resident PCG (resident.hip).
+// Resident PCG (resident.hip).
 constexpr int kResThreads = 512;
-constexpr int kResMaxVpt = 34;    // voxels per thread: boxes up to 17408 voxels (32 x 32 x 17)
-constexpr int kResMaxVptW = 20;   // weights kernel: boxes up to 10240 voxels
+constexpr int kResMaxVptW = 20;   // weights-in-LDS kernel: boxes up to 10240 voxels
 constexpr int kResSmallVox = 5120;  // the small weights group: at most 10 voxels per thread
 constexpr int kResSpanG0 = 17408;   // streamed-weights kernel: voxel slots of its launches for
 constexpr int kResSpanG1 = 32768;   // boxes up to 32 x 32 x 17 and up to 32^3
-bool resident_fits(const BrickDev& b, size_t lds_limit);      // (g, p) kernel
-bool resident_w_fits(const BrickDev& b, size_t lds_limit);    // weights kernel
+bool resident_w_fits(const BrickDev& b, size_t lds_limit);    // weights-in-LDS kernel
 bool resident_g_fits(const BrickDev& b, size_t lds_limit);    // streamed-weights kernel
 int64_t resident_g_span(int64_t max_voxels);                  // its voxel slots per workgroup
 int64_t resident_g_elems(const BrickDev& b, int64_t span);    // a box's weight segment, in floats

@@ -309,3 +309,54 @@ def test_resident_kernel_matches_oracle_and_streaming(env):
         assert abs(int(sg["iters"][i]) - int(ss["iters"][i])) <= max(3, ss["iters"][i] // 20), (sg[i], ss[i])
     assert np.all(np.isin(sg["status"], (0, 2))) and np.all(np.isin(s64g["status"], (0, 2)))
     assert np.all(np.isin(sr["status"], (0, 2))) and np.all(s64["status"] == 2) | np.all(np.isin(s64["status"], (0, 2)))
+
+
+def test_streamed_weights_edge_cases(env):
+    """The streamed-weights resident kernel on its special boxes: a non-finite
+    g, the iteration cap, no seed, zero Dirichlet data, a single unknown
+    voxel, a 32x32-plane box next to other plane shapes (compile-time and
+    run-time neighbour offsets give the same bits), and slots past the end
+    of a box."""
+    rng = np.random.default_rng(77)
+    a = synth.random_box(rng, (32, 32, 20), dirichlet_frac=0.02)     # span 32768, 32x32 planes
+    b = synth.random_box(rng, (32, 32, 12), dirichlet_frac=0.02)     # span 17408, 32x32 planes
+    gb = a[0].copy()
+    gb[5, 6, 7] = np.nan
+    bad = (gb, a[1], a[2])
+    nodir = (b[0], np.zeros_like(b[1]), b[2])
+    zero = (b[0], b[1], np.where(b[1] != 0, 0.0, b[2]).astype(np.float32))
+    one_m = np.ones_like(b[1])
+    one_m[7, 3, 9] = 0
+    one = (b[0], one_m, b[2])
+    # iteration cap and non-finite
+    d = synth.from_boxes([a, bad])
+    x, _, st = _run(env, d, beta=BETA, eps=EPS, tol=1e-12, max_iter=3, precision=1, refine_max=0)
+    assert st["status"][0] == 1 and st["iters"][0] == 3, st
+    assert st["status"][1] == 4, st
+    # no seed, zero data, one unknown voxel, against the oracle
+    boxes = [nodir, zero, one, b]
+    d = synth.from_boxes(boxes)
+    _, rwg, _ = env
+    plan = rwg.context().solve_plan(rwg.solve_params(), rwg.bricks_array(d["shapes"], d["offsets"]), d["g"].size)
+    assert np.all(plan == rwg.PATH_RESIDENT_STREAMED), plan
+    x, _, st = _run(env, d, beta=BETA, eps=EPS, tol=1e-7, precision=1)
+    off = d["offsets"]
+    assert st["status"][0] == 5 and np.array_equal(x[off[0]:off[0] + b[0].size], nodir[2].ravel())
+    assert st["status"][1] == 0 and np.all(x[off[1]:off[1] + b[0].size][b[1].ravel() == 0] == 0.0)
+    for i in (2, 3):
+        ref = _ref(boxes[i])
+        assert np.max(np.abs(x[off[i]:off[i] + ref.size] - ref)) <= 1e-4, (i, st[i])
+    # 32x32-plane boxes alone (offsets compiled in) and beside a 31x33 box
+    # (run-time offsets): identical arithmetic, identical bits
+    c = synth.random_box(rng, (31, 33, 16), dirichlet_frac=0.02)
+    d1 = synth.from_boxes([a, b])
+    d2 = synth.from_boxes([a, b, c])
+    p1 = rwg.context().solve_plan(rwg.solve_params(), rwg.bricks_array(d1["shapes"], d1["offsets"]), d1["g"].size)
+    assert np.all(p1 == rwg.PATH_RESIDENT_STREAMED)
+    x1, _, s1 = _run(env, d1, beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    x2, _, s2 = _run(env, d2, beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    n = a[0].size + b[0].size
+    assert np.array_equal(x1[:n], x2[:n])
+    assert np.array_equal(s1["iters"], s2["iters"][:2])
+    ref_c = _ref(c)
+    assert np.max(np.abs(x2[n:n + ref_c.size] - ref_c)) <= 1e-4, s2[2]
