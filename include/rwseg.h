@@ -246,6 +246,18 @@ typedef struct rw_result rw_result;
  */
 int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels,
                      rw_pyramid** out, void* stream);
+
+/*
+ * The pyramid for the Poisson-noise weight of Section IV-C, where the edge
+ * weight between voxels of counts n_p and n_q is exp(-(sqrt n_p - sqrt n_q)^2 / 2).
+ * Level 0 holds the counts (uint16 as is; float clipped below at 0), level
+ * l+1 the 2x2x2 mean of level l's counts (as in rw_pyramid_build), and then
+ * every level is replaced by its square root.  With rw_params.beta = 0.5 the
+ * library's weight exp(-beta dg^2) + eps is that weight (plus the eps floor).
+ * Arguments, ownership and errors as for rw_pyramid_build.
+ */
+int rw_pyramid_build_counts(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels,
+                            rw_pyramid** out, void* stream);
 void rw_pyramid_free(rw_pyramid* p);
 /* Level accessor: dims = {nx, ny, nz} of the level, *data = dev float [nz][ny][nx]. */
 int rw_pyramid_level(const rw_pyramid* p, int level, int64_t dims[3], const float** data);

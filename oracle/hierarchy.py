@@ -5,7 +5,9 @@ Paper: arXiv 2103.09564.  Plain Python loops over bricks, float64.
 * Section III-A: the pyramid.  Level 0 is the input volume; level l+1 is the
   2x2x2 mean of level l (partial blocks at odd edges average the voxels they
   have).  Intensities are normalised once on level 0 (uint16: global min-max
-  to [0, 1]; float: clipped to [0, 1]).
+  to [0, 1]; float: clipped to [0, 1]).  For the Poisson-noise weight of
+  Section IV-C the levels hold the mean counts instead, each replaced by its
+  square root (``pyramid_counts``); solved with beta = 1/2.
 * Section IV-A, eq. (1): the coarsest level is solved with the user seeds only.
   Here the coarsest level is solved as one domain (the whole level).
 * Section IV-A, eq. (2) and Section IV-B, eq. (3): every finer brick (s^3
@@ -104,6 +106,20 @@ def pyramid(volume, levels):
     for _ in range(levels - 1):
         g.append(downsample2x(g[-1]))
     return g
+
+
+def pyramid_counts(volume, levels):
+    """Pyramid for the Poisson-noise weight (Section IV-C): the levels of
+    the counts n (uint16 as is, float clipped below at 0; level l+1 the 2x2x2
+    mean of level l), each replaced by sqrt(n).  The paper's weight
+    exp(-(sqrt n_p - sqrt n_q)^2 / 2) is then the Gaussian weight of these
+    values with beta = 1/2 (eps as in every solve here)."""
+    n = np.asarray(volume)
+    n = n.astype(np.float64) if n.dtype == np.uint16 else np.maximum(n.astype(np.float64), 0.0)
+    c = [n]
+    for _ in range(levels - 1):
+        c.append(downsample2x(c[-1]))
+    return [np.sqrt(a) for a in c]
 
 
 def _axis_taps(n_child, n_parent):

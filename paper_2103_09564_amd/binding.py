@@ -271,6 +271,8 @@ lib.rw_params_default.argtypes = [ctypes.POINTER(Params)]
 lib.rw_params_default.restype = None
 lib.rw_pyramid_build.argtypes = [_vp, _vp, ctypes.c_int, _dims3, ctypes.c_int, ctypes.POINTER(_vp), _vp]
 lib.rw_pyramid_build.restype = ctypes.c_int
+lib.rw_pyramid_build_counts.argtypes = lib.rw_pyramid_build.argtypes
+lib.rw_pyramid_build_counts.restype = ctypes.c_int
 lib.rw_pyramid_free.argtypes = [_vp]
 lib.rw_pyramid_free.restype = None
 lib.rw_pyramid_level.argtypes = [_vp, ctypes.c_int, _dims3, ctypes.POINTER(_vp)]
@@ -313,7 +315,11 @@ def seeds_array(seeds):
 
 
 class Pyramid:
-    def __init__(self, ctx, volume, levels, stream=None):
+    """LOD pyramid on the device.  counts=False: normalised intensities
+    (rw_pyramid_build); counts=True: square roots of the mean counts, for the
+    Poisson weight with beta 0.5 (rw_pyramid_build_counts)."""
+
+    def __init__(self, ctx, volume, levels, stream=None, counts=False):
         import torch
         self.ctx = ctx
         dt = {torch.uint16: RW_U16, torch.float32: RW_F32}.get(volume.dtype)
@@ -321,8 +327,9 @@ class Pyramid:
             raise TypeError("volume must be uint16 or float32")
         nz, ny, nx = volume.shape
         h = _vp()
-        ctx._check(lib.rw_pyramid_build(ctx.handle, _ptr(volume), dt, _dims3(nx, ny, nz), int(levels),
-                                        ctypes.byref(h), _stream(stream)))
+        build = lib.rw_pyramid_build_counts if counts else lib.rw_pyramid_build
+        ctx._check(build(ctx.handle, _ptr(volume), dt, _dims3(nx, ny, nz), int(levels), ctypes.byref(h),
+                         _stream(stream)))
         self.handle = h
         self.levels = levels
         self.device = volume.device

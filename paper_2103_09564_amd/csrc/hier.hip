@@ -128,6 +128,24 @@ __global__ void k_clip_f32(const float* __restrict__ v, int64_t n, float* __rest
         g[i] = fminf(fmaxf(v[i], 0.0f), 1.0f);
 }
 
+// Counts pyramid (Poisson weight): level 0 = the counts as float (uint16 as
+// is, float clipped below at 0); after the mean downsampling every level is
+// replaced by its square root.
+__global__ void k_counts_u16(const uint16_t* __restrict__ v, int64_t n, float* __restrict__ g) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        g[i] = (float)v[i];
+}
+
+__global__ void k_counts_f32(const float* __restrict__ v, int64_t n, float* __restrict__ g) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        g[i] = fmaxf(v[i], 0.0f);
+}
+
+__global__ void k_sqrt_inplace(float* __restrict__ g, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        g[i] = sqrtf(g[i]);
+}
+
 // Parent voxel = mean of the child voxels its 2x2x2 block holds.
 __global__ void k_downsample(const float* __restrict__ c, int64_t cx, int64_t cy, int64_t cz, float* __restrict__ p,
                              int64_t px, int64_t py, int64_t pz) {
@@ -825,8 +843,10 @@ void rw_params_default(rw_params* p) {
     p->refine_max = 1;
 }
 
-int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels, rw_pyramid** out,
-                     void* stream) {
+// counts = 0: normalised intensities (rw_pyramid_build); 1: square roots of
+// the mean counts (rw_pyramid_build_counts).
+static int pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels, int counts,
+                         rw_pyramid** out, void* stream) {
     if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
     ctx->err.clear();
     if (!out) return fail(ctx, RW_E_INVAL, "out is NULL");
@@ -854,7 +874,13 @@ int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims
     }
     const int64_t n0 = dims[0] * dims[1] * dims[2];
     const int T = 256;
-    if (dtype == RW_U16) {
+    if (counts) {
+        if (dtype == RW_U16)
+            hipLaunchKernelGGL(k_counts_u16, dim3(grid_for(n0, T)), dim3(T), 0, s, (const uint16_t*)vol, n0,
+                               p->data[0]);
+        else
+            hipLaunchKernelGGL(k_counts_f32, dim3(grid_for(n0, T)), dim3(T), 0, s, (const float*)vol, n0, p->data[0]);
+    } else if (dtype == RW_U16) {
         unsigned init[2] = {0xffffu, 0u};
         unsigned* mm = nullptr;
         hipError_t e = hipMalloc((void**)&mm, sizeof(init));
@@ -881,6 +907,11 @@ int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims
         hipLaunchKernelGGL(k_downsample, dim3(grid_for(n, T)), dim3(T), 0, s, p->data[l - 1], p->dims[l - 1][0],
                            p->dims[l - 1][1], p->dims[l - 1][2], p->data[l], p->dims[l][0], p->dims[l][1], p->dims[l][2]);
     }
+    if (counts)
+        for (int l = 0; l < levels; ++l) {
+            const int64_t n = p->dims[l][0] * p->dims[l][1] * p->dims[l][2];
+            hipLaunchKernelGGL(k_sqrt_inplace, dim3(grid_for(n, T)), dim3(T), 0, s, p->data[l], n);
+        }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         rw_pyramid_free(p);
@@ -888,6 +919,16 @@ int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims
     }
     *out = p;
     return RW_OK;
+}
+
+int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels, rw_pyramid** out,
+                     void* stream) {
+    return pyramid_build(ctx, vol, dtype, dims, levels, 0, out, stream);
+}
+
+int rw_pyramid_build_counts(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels,
+                            rw_pyramid** out, void* stream) {
+    return pyramid_build(ctx, vol, dtype, dims, levels, 1, out, stream);
 }
 
 void rw_pyramid_free(rw_pyramid* p) {
