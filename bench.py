@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 BYTES_PER_VOXEL_ITER = 28      # read x, r, p, g; write x, r, p (FP32, one rhs)
 BETA, EPS, TOL = 128.0, 1e-6, 1e-6
 N_BOXES, SEED = 8192, 3
-EXTRAS = ("plain_sphere_64", "tubes_512_hierarchy", "blobs_512x32_adjoint", "shells_hierarchy_incremental")
+EXTRAS = ("plain_sphere_64", "tubes_512_hierarchy", "blobs_512x32_adjoint", "shells_hierarchy_incremental",
+          "cells_256_ablation")
 
 
 def source_hash():
@@ -291,6 +292,36 @@ def bench_shells(torch, rwg, ctx, dims=(256, 256, 128), levels=3):
             "label_accuracy_vs_truth": acc, "generate_s": gen_s}
 
 
+def bench_cells_ablation(torch, rwg, ctx, n=256, levels=4):
+    """Ablations on the cells scenario (spheres covering 1 % of the volume,
+    0.7 on 0.3 plus noise 0.1): brick size s in {16, 32, 64} (boxes 20^3,
+    40^3, 80^3) with hom and dt pruning, and s = 32 with pruning off; time,
+    bricks reached and solved per level, and Dice against the truth."""
+    import numpy as np
+    import synth
+    t0 = time.time()
+    v, seeds, truth = synth.cells_volume(n=n, seed=11)
+    gen_s = time.time() - t0
+    vd = torch.from_numpy(v).to("cuda:0")
+    pyr = rwg.Pyramid(ctx, vd, levels)
+    gt = truth.astype(bool)
+    out = {"workload": f"cells {n}^3 float32, {int((seeds[:, 3] == 1).sum())} spheres (diameter 0.05-0.1 n, 1 % "
+                       f"of the volume), 0.7 on 0.3, noise 0.1, {levels} levels, e=1.25, beta 128, t_hom 0.3, "
+                       "t_bin 0.01, mixed tol 1e-5", "generate_s": gen_s}
+    runs = [("s16_pruned", 16, 1), ("s32_pruned", 32, 1), ("s64_pruned", 64, 1), ("s32_unpruned", 32, 0)]
+    for name, s, prune in runs:
+        kw = dict(brick=s, expand=1.25, beta=BETA, eps=EPS, tol=1e-5, precision=1, n_classes=2, prune_hom=prune,
+                  prune_dt=prune, t_hom=0.3, t_bin=0.01)
+        ms, res = _best_ms(torch, lambda: rwg.segment(pyr, seeds, **kw), 2)
+        st = res.stats()
+        _, lab = res.materialize(0, 1, prob=False, labels=True)
+        lb = lab.cpu().numpy().astype(bool)
+        out[name] = {"segment_ms": ms, "voxel_iters": int(sum(st["voxel_iters"])),
+                     "per_level": {k: st[k] for k in ("bricks", "computed", "solved", "prunable")},
+                     "dice_vs_truth": float(2 * (lb & gt).sum() / (lb.sum() + gt.sum()))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,7 +330,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--schedule", type=int, default=0, help="CG schedule (rw_solve_params.schedule): 0 library choice, 1 two-sweep streaming, 2 one-sweep streaming, 3 as 0 with 2, 4 streamed-weights resident wherever it fits")
-    ap.add_argument("--no-extras", action="store_true", help="skip the further workloads (sphere, tubes, blobs, shells)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the further workloads (sphere, tubes, blobs, shells, cells)")
     ap.add_argument("--shells-dims", default="256,256,128", help="nested-shell volume dims nx,ny,nz")
     ap.add_argument("--only", choices=EXTRAS, default=None,
                     help="run one further workload alone and print its JSON (for profiling; no headline line)")
@@ -324,6 +355,8 @@ def main():
             return bench_tubes(torch, rwg, ctx)
         if name == "blobs_512x32_adjoint":
             return bench_blobs_adjoint(torch, rwg, dev, cpu_leg=not args.no_cpu_baseline)
+        if name == "cells_256_ablation":
+            return bench_cells_ablation(torch, rwg, ctx)
         return bench_shells(torch, rwg, ctx, dims=shell_dims)
 
     if args.only:

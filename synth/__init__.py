@@ -23,6 +23,12 @@ Workloads (all numpy ``default_rng(seed)``):
   amplitudes 0.6 and 0.4) plus noise sigma 0.03; foreground seeds a 3^3 block
   at blob 1, background seeds a 3^3 block at blob 2 and all six faces; the
   ground-truth mask is blob 1 above half its maximum.
+* ``cells_volume``   -- the paper's synthetic "cells" scenario (Section VI-B):
+  spheres of diameter in [S/2, S] (S = structure size x volume side) placed
+  at random until they cover the requested fraction of the volume, no centre
+  inside another sphere; 0.7 inside on 0.3 plus iid Gaussian noise; a
+  foreground seed at each centre and two background seeds per sphere at
+  twice its radius from the centre, outside every sphere.
 """
 
 import numpy as np
@@ -417,3 +423,51 @@ def stroke(labels, geo, cls=2, length=2000, seed=6):
             p = np.array(path, np.float64) + 0.5
             return np.concatenate([p, np.full((length, 1), float(cls))], axis=1)
     raise RuntimeError("no self-avoiding walk of the requested length found")
+
+
+def cells_volume(n=256, seed=11, structure=0.1, coverage=0.01, noise=0.1, max_spheres=10000):
+    """Cells scenario: float32 volume [z, y, x] in [0, 1], seeds (x, y, z,
+    label) in voxel units (voxel k covers [k, k+1)), and the ground truth
+    (uint8, 1 inside a sphere).  Sphere diameters are U[S/2, S] with
+    S = structure * n; spheres are added until at least ``coverage`` of the
+    voxels is inside one (a centre may not fall inside an earlier sphere)."""
+    rng = np.random.default_rng(seed)
+    S = structure * n
+    truth = np.zeros((n, n, n), dtype=np.uint8)
+    centres, radii = [], []
+    target = coverage * n ** 3
+    count = 0
+    tries = 0
+    while count < target and len(centres) < max_spheres and tries < 50 * max_spheres:
+        tries += 1
+        r = rng.uniform(S / 4.0, S / 2.0)
+        c = rng.uniform(r, n - r, 3)
+        if any(np.sum((c - q) ** 2) < rq * rq for q, rq in zip(centres, radii)):
+            continue
+        lo = np.maximum(np.floor(c - r).astype(np.int64), 0)
+        hi = np.minimum(np.ceil(c + r).astype(np.int64) + 1, n)
+        zz, yy, xx = np.meshgrid(*(np.arange(lo[a], hi[a]) + 0.5 for a in (2, 1, 0)), indexing="ij")
+        inside = (xx - c[0]) ** 2 + (yy - c[1]) ** 2 + (zz - c[2]) ** 2 <= r * r
+        sub = truth[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        count += int(np.sum(inside & (sub == 0)))
+        sub[inside] = 1
+        centres.append(c)
+        radii.append(r)
+    vol = 0.3 + 0.4 * truth.astype(np.float32) + rng.standard_normal((n, n, n), dtype=np.float32) * noise
+    vol = np.clip(vol, 0.0, 1.0).astype(np.float32)
+    seeds = []
+    for c, r in zip(centres, radii):
+        seeds.append([c[0], c[1], c[2], 1])
+        placed = 0
+        for _ in range(100):
+            if placed == 2:
+                break
+            d = rng.standard_normal(3)
+            q = c + 2.0 * r * d / np.linalg.norm(d)
+            if np.any(q < 0.0) or np.any(q >= n):
+                continue
+            if any(np.sum((q - c2) ** 2) <= r2 * r2 for c2, r2 in zip(centres, radii)):
+                continue
+            seeds.append([q[0], q[1], q[2], 0])
+            placed += 1
+    return vol, np.array(seeds, dtype=np.float64), truth
