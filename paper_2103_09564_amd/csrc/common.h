@@ -97,6 +97,7 @@ struct SolveArgs {
     void* dom;             // multi-workgroup domain solver: scalar state and ticket
     double* dom_part;      // its per-workgroup partial sums
     float* wts;            // streamed-weights resident kernel: per-box weight segments
+    int32_t fused_init;    // main solve: the resident kernels compute their boxes' start state
 };
 
 struct AdjointArgs {

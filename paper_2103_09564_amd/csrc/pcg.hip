@@ -1549,10 +1549,15 @@ static hipError_t launch_mixed(const SolveArgs& a, int64_t n, const PlanePlan& p
     const dim3 grid((unsigned)(n - nd)), blk(kThreads);
     const bool rest = n > nd;
     const bool r64 = a.precision == RW_PREC_MIXED_REFINE;
-    if (rest) hipLaunchKernelGGL((k_init<float, R>), grid, blk, 0, s, a, nd);
+    // the resident kernels [n_res, n) compute their boxes' start state in the
+    // main solve themselves; the init phase covers the others
+    const int64_t n_init = R == 1 ? std::max<int64_t>(pp.n_res, nd) : n;
+    if (n_init > nd) hipLaunchKernelGGL((k_init<float, R>), dim3((unsigned)(n_init - nd)), blk, 0, s, a, nd);
     for (int i = 0; i < nd; ++i) RW_TRY((domain_init<float, R>(a, i, pp.host[i], s)));
     if (ev) RW_TRY(hipEventRecord(ev[0], s));
-    RW_TRY(launch_pcg_c<float, R, float>(a, n, a.x, 0, pp, s));
+    SolveArgs am = a;
+    am.fused_init = 1;
+    RW_TRY(launch_pcg_c<float, R, float>(am, n, a.x, 0, pp, s));
     if (ev) RW_TRY(hipEventRecord(ev[1], s));
     if (r64) {
         if (rest) hipLaunchKernelGGL((k_copy64<R>), grid, blk, 0, s, a, 1, nd);

@@ -64,6 +64,161 @@ struct ResWeight {
 
 }  // namespace
 
+// Start state of a main solve computed by a resident kernel itself (the
+// init phase computes it for the other boxes, with the same rules): on
+// unknown voxels r0 = sum_nb w x_nb - d x (every in-box neighbour; x on
+// unknown voxels is the caller's guess), written to the r workspace, and
+// b = the seeded neighbours' part of that sum; rho = r0.z0, ||r0||^2,
+// ||b||^2 and the unknown / seeded counts are reduced over the workgroup.
+//
+// res_start_finish takes each thread's partial sums {r.z, r.r, b.b,
+// unknown, seeded}, reduces them (red holds at least 5 * NT / 64 doubles),
+// resets P[0, nv) to 0 once every thread's reads of it are done and writes
+// the box's BoxState.  With no seed, no unknown or b = 0 (then x_U = 0 and
+// r = 0, written here) there is nothing to iterate and it returns false.
+template <int NT>
+__device__ bool res_start_finish(double (&sum)[5], int nv, const uint8_t* m, float* xb, float* rw, float* P,
+                                 double* red, BoxState& st, double& rz, double& rr, double& bb) {
+    res_block_sum<NT, 5>(sum, red);  // its barriers order every read of P before the reset below
+    for (int v = threadIdx.x; v < nv; v += NT) P[v] = 0.0f;
+    const double nU = sum[3], nM = sum[4];
+    const bool allzero = sum[2] == 0.0;
+    const bool act = nM > 0.0 && nU > 0.0 && !allzero;
+    const bool zero_sol = nM > 0.0 && nU > 0.0 && allzero;  // ||b|| = 0: x_U = 0, no iterations
+    rz = zero_sol ? 0.0 : sum[0];
+    rr = zero_sol ? 0.0 : sum[1];
+    bb = sum[2];
+    if (zero_sol)
+        for (int v = threadIdx.x; v < nv; v += NT)
+            if (m[v] == 0) xb[v] = rw[v] = 0.0f;
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) st.rz[c] = st.rr[c] = st.bb[c] = 0.0;
+        st.rz[0] = rz;
+        st.rr[0] = rr;
+        st.bb[0] = bb;
+        st.nU = nU;
+        st.nM = nM;
+        st.rel = 0.0;
+        st.true_rel = 0.0;
+        st.iters = st.refine_steps = st.refine_iters = 0;
+        st.status = nM == 0.0 ? RW_ST_NO_DIRICHLET : RW_ST_CONVERGED;
+        st.active = act ? 1 : 0;
+        st.pending = 0;
+        st.checked = 0;
+    }
+    __syncthreads();  // P reset and r written before any thread reads them
+    // every lane holds the same sums; said so, the caller's exit on it stays
+    // uniform and the segment offsets after it stay scalar
+    return __builtin_amdgcn_readfirstlane(act ? 1 : 0) != 0;
+}
+
+// P[v] for v in [lo, hi): x[v] on the box when with_x, 0 elsewhere.  U
+// slots per thread at a time, their loads (clamped into the box) issued
+// before any is used.
+template <int NT, int U>
+__device__ __forceinline__ void res_fill_p(float* P, const float* xb, int lo, int hi, int nv, bool with_x) {
+    for (int v0 = lo + (int)threadIdx.x; v0 < hi; v0 += U * NT) {
+        float xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * NT;
+            xv[u] = xb[min(max(v, 0), nv - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * NT;
+            if (v < hi) P[v] = with_x && v >= 0 && v < nv ? xv[u] : 0.0f;
+        }
+    }
+}
+
+// A box's weights pass over the slots v in [lo, hi) (thread t: lo + t +
+// k * NT), U slots at a time: every global load of the U (g and the mask at
+// the voxel and its six neighbours, indices clamped into the box) is issued
+// before any is used, so a thread keeps them in flight together.  Per
+// slot: the forward weights w+x, w+y, w+z (0 toward neighbours outside the
+// box and on slots outside it) and, when need_d or start, the diagonal d
+// (all six edge weights); out(v, wx, wy, wz, d, unknown) stores them.  On
+// a main solve (start set; P holds x, with zero pads) also the start-state
+// terms of each voxel: on an unknown one r0 = sum_nb w x_nb - d x -> rw[v]
+// and its parts of the sums {r.z, r.r, b.b, unknown, seeded}, with z0 =
+// r0 / d and b the seeded neighbours' part of the sum; on a seeded one
+// r = 0.
+template <int NT, int U, typename Out>
+__device__ __forceinline__ void res_weights_pass(int lo, int hi, int nx, int ny, int nz, const float* g,
+                                                 const uint8_t* m, const ResWeight& W, bool need_d, bool start,
+                                                 const float* P, float* rw, double (&sum)[5], Out out) {
+    const int nxy = nx * ny, nv = nxy * nz;
+    for (int v0 = lo + (int)threadIdx.x; v0 < hi; v0 += U * NT) {
+        int c[U];
+        bool in[U][6];
+        float gc[U], gn[U][6];
+        uint8_t mc[U], mn[U][6];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * NT;
+            c[u] = v >= 0 && v < nv ? v : 0;
+            const int kz = c[u] / nxy, rem = c[u] - kz * nxy, j = rem / nx, i = rem - j * nx;
+            const int no[6] = {1, -1, nx, -nx, nxy, -nxy};
+            in[u][0] = i + 1 < nx;
+            in[u][1] = i > 0;
+            in[u][2] = j + 1 < ny;
+            in[u][3] = j > 0;
+            in[u][4] = kz + 1 < nz;
+            in[u][5] = kz > 0;
+            gc[u] = g[c[u]];
+            mc[u] = m[c[u]];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                const int nb = in[u][e] ? c[u] + no[e] : c[u];
+                gn[u][e] = g[nb];
+                mn[u][e] = m[nb];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * NT;
+            const bool inb = v >= 0 && v < nv;
+            float w[6];  // +x, -x, +y, -y, +z, -z
+#pragma unroll
+            for (int e = 0; e < 6; ++e) w[e] = 0.0f;
+            if (inb) {
+                if (in[u][0]) w[0] = W(gc[u], gn[u][0]);
+                if (in[u][2]) w[2] = W(gc[u], gn[u][2]);
+                if (in[u][4]) w[4] = W(gc[u], gn[u][4]);
+                if (need_d || start) {
+                    if (in[u][1]) w[1] = W(gn[u][1], gc[u]);
+                    if (in[u][3]) w[3] = W(gn[u][3], gc[u]);
+                    if (in[u][5]) w[5] = W(gn[u][5], gc[u]);
+                }
+            }
+            const float d = ((w[0] + w[2]) + w[4]) + w[1] + w[3] + w[5];
+            const bool unk = inb && mc[u] == 0;
+            if (v < hi) out(v, w[0], w[2], w[4], d, unk);
+            if (start && inb) {
+                const int no[6] = {1, -1, nx, -nx, nxy, -nxy};
+                float acc = 0.0f, bs = 0.0f;  // sum_nb w x_nb, and over the seeded neighbours only
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    const float xr = P[v + no[e]];  // inside P's pads for every slot of the box
+                    const float xn = in[u][e] ? xr : 0.0f;
+                    acc += w[e] * xn;
+                    if (mn[u][e] != 0) bs += w[e] * xn;
+                }
+                const float r0 = unk ? acc - d * P[v] : 0.0f;
+                rw[v] = r0;
+                if (unk) {
+                    sum[0] += (double)r0 * (double)(r0 * __builtin_amdgcn_rcpf(d));
+                    sum[1] += (double)r0 * (double)r0;
+                    sum[2] += (double)bs * (double)bs;
+                }
+                sum[3] += unk ? 1.0 : 0.0;  // both counts updated: no run-time index into sum
+                sum[4] += unk ? 0.0 : 1.0;
+            }
+        }
+    }
+}
+
 // Boxes up to 10240 voxels: one workgroup of NT threads per box (VPT = most
 // voxels a thread owns; thread t owns voxels t + k * NT, so every LDS access
 // of a wave is to consecutive words).  LDS holds four arrays, p and the
@@ -79,11 +234,12 @@ struct ResWeight {
 template <int NT, int VPT>
 __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int corr, int base) {
     extern __shared__ __align__(16) float w_lds[];
-    __shared__ double red[(NT / 64) * 2];
+    __shared__ double red[(NT / 64) * 5];  // block sums of up to 5 values (the start state)
     constexpr int NC = (VPT + 31) / 32;  // unknown-voxel bits
     const int ib = base + blockIdx.x;
     BoxState& st = a.state[ib];
-    if (!st.active) return;
+    const bool fused = a.fused_init && !corr;  // this kernel computes the start state
+    if (!fused && !st.active) return;
     const BrickDev bd = a.bricks[ib];
     const int nx = bd.nx, ny = bd.ny, nz = bd.nz, nxy = nx * ny, nv = nxy * nz;
     const int L = nv + 2 * nxy + 1;  // array stride (box and pads)
@@ -97,20 +253,27 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
     const float* rb = (const float*)a.r + bd.off;
     const ResWeight W{(float)(-a.beta * 1.4426950408889634), (float)a.eps};
 
-    // forward weights from g (global loads of the voxel and its +x, +y, +z neighbours)
-    for (int v = (int)threadIdx.x - nxy; v <= nv + nxy; v += NT) {
-        float wx = 0.0f, wy = 0.0f, wz = 0.0f;
-        if (v >= 0 && v < nv) {
-            const int kz = v / nxy, rem = v - kz * nxy, j = rem / nx, i = rem - j * nx;
-            const float gc = g[v];
-            if (i + 1 < nx) wx = W(gc, g[v + 1]);
-            if (j + 1 < ny) wy = W(gc, g[v + nx]);
-            if (kz + 1 < nz) wz = W(gc, g[v + nxy]);
-        }
-        P[v] = 0.0f;
-        WX[v] = wx;
-        WY[v] = wy;
-        WZ[v] = wz;
+    // Main solve: P holds x (pads 0) while the weights are computed, and
+    // the start state is computed in the same pass.  Otherwise P starts at 0.
+    res_fill_p<NT, 4>(P, xb, -nxy, nv + nxy + 1, nv, fused);
+    if (fused) __syncthreads();
+    float* const rw = (float*)a.r + bd.off;
+    double sum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // r.z, r.r, b.b, unknown, seeded
+    // forward weights from g (global loads of the voxel and its neighbours)
+    res_weights_pass<NT, 4>(-nxy, nv + nxy + 1, nx, ny, nz, g, m, W, false, fused, P, rw, sum,
+                            [&](int v, float wx, float wy, float wz, float, bool) {
+                                WX[v] = wx;
+                                WY[v] = wy;
+                                WZ[v] = wz;
+                            });
+    double rz, rr, bb;
+    if (fused) {
+        if (!res_start_finish<NT>(sum, nv, m, xb, rw, P, red, st, rz, rr, bb))
+            return;  // nothing to iterate (state and x written)
+    } else {
+        rz = st.rz[0];
+        rr = st.rr[0];
+        bb = st.bb[0];
     }
     float x[VPT], r[VPT], id[VPT], d[VPT], q[VPT];
     unsigned unk[NC];
@@ -140,8 +303,6 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
         id[k] = isu(k) ? __builtin_amdgcn_rcpf(dd) : 0.0f;
     }
 
-    double rz = st.rz[0], rr = st.rr[0];
-    const double bb = st.bb[0];
     const double tol = corr ? a.inner_tol : a.tol;
     const double tol2 = tol * tol;
     double betac = 0.0;
@@ -298,11 +459,12 @@ __device__ __forceinline__ void res_block_sum_lds(double (&v)[N], double* red) {
 template <int NT, int VPT, int G, int PX>
 __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int corr, int base) {
     extern __shared__ __align__(16) float p_lds[];
-    __shared__ double red[(NT / 64) * 2];
+    __shared__ double red[(NT / 64) * 5];  // block sums of up to 5 values (the start state)
     constexpr int NG = (VPT + G - 1) / G;
     const int ib = base + blockIdx.x;
     BoxState& st = a.state[ib];
-    if (!st.active) return;
+    const bool fused = a.fused_init && !corr;  // this kernel computes the start state
+    if (!fused && !st.active) return;
     const BrickDev bd = a.bricks[ib];
     const int nx = PX ? PX : bd.nx, ny = PX ? PX : bd.ny, nz = bd.nz, nxy = nx * ny, nv = nxy * nz;
     constexpr int span = NT * VPT;
@@ -319,51 +481,61 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
     float* const ID = WZ + T;
     const ResWeight W{(float)(-a.beta * 1.4426950408889634), (float)a.eps};
 
+    // Main solve: P holds x (pads 0) while the weights are computed, and
+    // the start state is computed in the same pass from the weights in
+    // registers.  Otherwise P starts at 0.
+    res_fill_p<NT, 4>(P, xb, -nxy, span + nxy, nv, fused);
+    if (fused) __syncthreads();
+    float* const rw = (float*)a.r + bd.off;
+    double sum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // r.z, r.r, b.b, unknown, seeded
     // weights (0 toward neighbours outside the box) and 1/d (0 on seeded
     // voxels); pads and unused slots are 0
-    for (int v = (int)threadIdx.x - nxy; v < span; v += NT) {
-        float wx = 0.0f, wy = 0.0f, wz = 0.0f, id = 0.0f;
-        if (v >= 0 && v < nv) {
-            const int kz = v / nxy, rem = v - kz * nxy, j = rem / nx, i = rem - j * nx;
-            const float gc = g[v];
-            if (i + 1 < nx) wx = W(gc, g[v + 1]);
-            if (j + 1 < ny) wy = W(gc, g[v + nx]);
-            if (kz + 1 < nz) wz = W(gc, g[v + nxy]);
-            float d = wx + wy + wz;
-            if (i > 0) d += W(g[v - 1], gc);
-            if (j > 0) d += W(g[v - nx], gc);
-            if (kz > 0) d += W(g[v - nxy], gc);
-            if (m[v] == 0) id = __builtin_amdgcn_rcpf(d);
-        }
-        WX[v] = wx;
-        WY[v] = wy;
-        WZ[v] = wz;
-        ID[v] = id;
-    }
-    for (int v = (int)threadIdx.x - nxy; v < span + nxy; v += NT) P[v] = 0.0f;
-
-    float x[VPT], r[VPT], q[VPT];
-#pragma unroll
-    for (int k = 0; k < VPT; ++k) {
-        const int v0 = threadIdx.x + k * NT;
-        const int v = v0 < nv ? v0 : nv - 1;
-        const bool u = v0 < nv && m[v] == 0;
-        const float rv = rb[v], xv = xb[v];
-        r[k] = u ? rv : 0.0f;
-        x[k] = u ? xv : 0.0f;
-    }
-    // the weights written above are read by other threads of the workgroup
-    __syncthreads();
+    res_weights_pass<NT, 4>(-nxy, span, nx, ny, nz, g, m, W, true, fused, P, rw, sum,
+                            [&](int v, float wx, float wy, float wz, float d, bool unk) {
+                                WX[v] = wx;
+                                WY[v] = wy;
+                                WZ[v] = wz;
+                                ID[v] = unk ? __builtin_amdgcn_rcpf(d) : 0.0f;
+                            });
     // 0x00020000: raw 32-bit buffer (third descriptor word for this chip family)
     const SegBuf sb{__builtin_amdgcn_make_buffer_rsrc(seg, 0, (int)(4 * (4 * T)), 0x00020000)};
-    // byte offsets of the arrays (from voxel 0 of WX) and of the backward neighbours
-    const int sWX = 4 * nxy, sWY = sWX + 4 * T, sWZ = sWY + 4 * T, sID = sWZ + 4 * T;
-    const int sWXm = sWX - 4, sWYm = sWY - 4 * nx, sWZm = sWZ - 4 * nxy;
+    // byte offsets of the arrays (from voxel 0 of WX) and of the backward
+    // neighbours: uniform (stated, so that no copy of them computed in the
+    // weights loop above, whose trip count differs per lane, is taken as
+    // per-lane)
+    const int sWX = __builtin_amdgcn_readfirstlane(4 * nxy), sWY = __builtin_amdgcn_readfirstlane(sWX + 4 * T),
+              sWZ = __builtin_amdgcn_readfirstlane(sWY + 4 * T), sID = __builtin_amdgcn_readfirstlane(sWZ + 4 * T);
+    const int sWXm = sWX - 4, sWYm = __builtin_amdgcn_readfirstlane(sWY - 4 * nx),
+              sWZm = __builtin_amdgcn_readfirstlane(sWZ - 4 * nxy);
+
+    float x[VPT], r[VPT], q[VPT];
+    double rz, rr, bb;
+    if (fused) {
+        // its barriers also make the weights written above visible to the workgroup
+        if (!res_start_finish<NT>(sum, nv, m, xb, rw, P, red, st, rz, rr, bb))
+            return;  // nothing to iterate (state and x written)
+    }
+    {
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            const int v0 = threadIdx.x + k * NT;
+            const int v = v0 < nv ? v0 : nv - 1;
+            const bool u = v0 < nv && m[v] == 0;
+            const float rv = rb[v], xv = xb[v];
+            r[k] = u ? rv : 0.0f;
+            x[k] = u ? xv : 0.0f;
+        }
+        if (!fused) {
+            // the weights written above are read by other threads of the workgroup
+            __syncthreads();
+            rz = st.rz[0];
+            rr = st.rr[0];
+            bb = st.bb[0];
+        }
+    }
 #pragma unroll
     for (int k = 0; k < VPT; ++k) q[k] = r[k] * sb.ld(4u * (unsigned)(threadIdx.x + k * NT), sID);  // start z
 
-    double rz = st.rz[0], rr = st.rr[0];
-    const double bb = st.bb[0];
     const double tol = corr ? a.inner_tol : a.tol;
     const double tol2 = tol * tol;
     double betac = 0.0;
