@@ -508,6 +508,84 @@ __device__ void true_residual(const Box& b, const float* __restrict__ g, const u
     march<double, 2 * R>(b, g, m, W, load, vu, vm);
 }
 
+// The same true residual as a flat pass over the box's voxels (the check
+// phase): thread t takes voxels t + k * kThreads, U at a time, and issues
+// every load of the U (g, the seed mask and x at the voxel and its six
+// neighbours, indices clamped into the box) before using any, so a thread
+// keeps them in flight together instead of waiting plane by plane.  Each
+// voxel computes its six weights itself.
+template <int R, typename XS, typename RT>
+__device__ void true_residual_flat(const Box& b, const float* __restrict__ g, const uint8_t* __restrict__ m,
+                                   const XS* __restrict__ xs, RT* __restrict__ rout, double beta, double eps,
+                                   double (&rr)[R], double (&bb)[R]) {
+    constexpr int U = R == 1 ? 3 : 2;  // within 128 VGPRs: two workgroups per CU
+    const Weight<double> W = make_weight<double>(beta, eps);
+    const int nx = b.nx, ny = b.ny, nz = b.nz, nxy = b.nxy;
+    const int64_t nv = (int64_t)nxy * nz;
+    const float* __restrict__ gb = g + b.off;
+    const uint8_t* __restrict__ mb = m + b.off;
+    const XS* __restrict__ xb = xs + b.off * R;
+    for (int64_t v0 = threadIdx.x; v0 < nv; v0 += (int64_t)U * kThreads) {
+        bool in[U][6];
+        float gc[U], gn[U][6];
+        uint8_t mc[U], mn[U][6];
+        XS xc[U][R], xn[U][6][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t v = v0 + (int64_t)u * kThreads;
+            const int64_t c = v < nv ? v : 0;
+            const int64_t kz = c / nxy;
+            const int rem = (int)(c - kz * nxy), j = rem / nx, i = rem - j * nx;
+            const int64_t no[6] = {1, -1, nx, -nx, nxy, -nxy};
+            in[u][0] = i + 1 < nx;
+            in[u][1] = i > 0;
+            in[u][2] = j + 1 < ny;
+            in[u][3] = j > 0;
+            in[u][4] = kz + 1 < nz;
+            in[u][5] = kz > 0;
+            gc[u] = gb[c];
+            mc[u] = mb[c];
+#pragma unroll
+            for (int k = 0; k < R; ++k) xc[u][k] = xb[c * R + k];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                const int64_t nb = in[u][e] ? c + no[e] : c;
+                gn[u][e] = gb[nb];
+                mn[u][e] = mb[nb];
+#pragma unroll
+                for (int k = 0; k < R; ++k) xn[u][e][k] = xb[nb * R + k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t v = v0 + (int64_t)u * kThreads;
+            if (v >= nv || mc[u] != 0) continue;
+            double d = 0.0, acc[R], acm[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] = acm[k] = 0.0;
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                if (!in[u][e]) continue;
+                const double w = W((double)gc[u], (double)gn[u][e]);
+                d += w;
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const double xv = (double)xn[u][e][k];
+                    acc[k] += w * xv;
+                    if (mn[u][e] != 0) acm[k] += w * xv;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const double rv = acc[k] - d * (double)xc[u][k];
+                rr[k] += rv * rv;
+                bb[k] += acm[k] * acm[k];
+                if (rout) rout[(b.off + v) * R + k] = (RT)rv;
+            }
+        }
+    }
+}
+
 // Sweep A: p_new = z + beta p_old, sigma = p_new . L_UU p_new.
 template <typename T, int R, int C, bool kAligned>
 __device__ void sweep_pq(const Box& b, const float* __restrict__ g, const uint8_t* __restrict__ m,
@@ -1229,9 +1307,9 @@ __global__ __launch_bounds__(kThreads) void k_check(SolveArgs a, int may_refine,
 #pragma unroll
     for (int k = 0; k < R; ++k) r2[k] = b2[k] = 0.0;
     if (kRefine64)
-        true_residual<R, double, float>(b, a.g, a.mask, a.x64, V.r, a.beta, a.eps, r2, b2);
+        true_residual_flat<R, double, float>(b, a.g, a.mask, a.x64, V.r, a.beta, a.eps, r2, b2);
     else
-        true_residual<R, float, float>(b, a.g, a.mask, a.x, V.r, a.beta, a.eps, r2, b2);
+        true_residual_flat<R, float, float>(b, a.g, a.mask, a.x, V.r, a.beta, a.eps, r2, b2);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         q[k] = r2[k];

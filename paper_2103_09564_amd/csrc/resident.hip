@@ -484,13 +484,13 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
     // Main solve: P holds x (pads 0) while the weights are computed, and
     // the start state is computed in the same pass from the weights in
     // registers.  Otherwise P starts at 0.
-    res_fill_p<NT, 4>(P, xb, -nxy, span + nxy, nv, fused);
+    res_fill_p<NT, 8>(P, xb, -nxy, span + nxy, nv, fused);
     if (fused) __syncthreads();
     float* const rw = (float*)a.r + bd.off;
     double sum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // r.z, r.r, b.b, unknown, seeded
     // weights (0 toward neighbours outside the box) and 1/d (0 on seeded
     // voxels); pads and unused slots are 0
-    res_weights_pass<NT, 4>(-nxy, span, nx, ny, nz, g, m, W, true, fused, P, rw, sum,
+    res_weights_pass<NT, 8>(-nxy, span, nx, ny, nz, g, m, W, true, fused, P, rw, sum,
                             [&](int v, float wx, float wy, float wz, float d, bool unk) {
                                 WX[v] = wx;
                                 WY[v] = wy;
