@@ -161,10 +161,12 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
  * that phase two groups of kernels run concurrently on two streams (see
  * rw_solve_plan): the streaming boxes followed by the streamed-weights
  * resident boxes, and the boxes resident in LDS; stream_ms and resident_ms
- * are the durations of the two groups (0 for an empty group).
+ * are the durations of the two groups (0 for an empty group).  In a one-rhs
+ * MIXED or MIXED_REFINE solve the resident kernels compute their boxes'
+ * start state themselves, inside pcg_ms; init_ms covers the other boxes.
  */
 typedef struct rw_timing {
-    float init_ms;           /* Dirichlet init (r = -(L x)_U, z, p) */
+    float init_ms;           /* Dirichlet init (r = -(L x)_U, z, p) of the non-resident boxes */
     float pcg_ms;            /* main PCG phase */
     float finish_ms;         /* FP64 true residual, refinement, stats */
     float total_ms;
