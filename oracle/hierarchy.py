@@ -38,7 +38,21 @@ Paper: arXiv 2103.09564.  Plain Python loops over bricks, float64.
   parent level map changed by at least t_inc (max abs difference) over the
   parent voxels the box samples; otherwise its previous core values and
   prunable flag are reused.  The coarsest level is recomputed iff any label
-  was added.
+  was added.  This is the default ("dirty" rule).
+* Incremental labelling, the paper's own node rule (inc_rule = "node",
+  Section IV-E): every brick the new run reaches under a parent that was not
+  taken over from the previous result is solved; if its new core is within
+  t_inc of its previous core (max abs difference over the core voxels and
+  classes) and no voxel of its box has a seed conflict involving a newly
+  added label, the new node is discarded: the brick takes its previous core
+  values and prunable flag, and every descendant it had in the previous
+  result is taken over too (copied, not solved).  The coarsest level is
+  always solved; each of its bricks is such a node.
+* Warm start from the previous result (inc_warm, Section IV-E, after Grady):
+  a brick solved in an incremental run starts its unseeded voxels from the
+  previous result's map of the same level instead of the parent sample (the
+  border values still come from the parent); the solution does not depend
+  on the start.
 """
 
 from dataclasses import dataclass, field
@@ -60,6 +74,8 @@ class Params:
     t_inc: float = 0.01      # Section IV-E
     prune_hom: bool = True
     prune_dt: bool = True
+    inc_rule: str = "dirty"  # "dirty" or "node" (Section IV-E)
+    inc_warm: bool = False   # incremental runs start solved boxes from the previous map
     method: str = "direct"   # per-box oracle solve
     tol: float = 1e-13       # used when method == "pcg"
 
@@ -74,6 +90,7 @@ class Result:
     cfl: list                       # per level bool (nbz, nby, nbx)
     recomputed: list = field(default_factory=list)   # per level bool (incremental)
     seeds: np.ndarray = None
+    reused: list = field(default_factory=list)       # per level bool (node rule: taken over from prev)
 
 
 def normalize(volume):
@@ -209,15 +226,18 @@ def _prunable(core_maps, cfl, p):
     return ((p.prune_hom and hom) or (p.prune_dt and dt)) and not cfl
 
 
-def _solve(g_box, lab_box, border, up_box, p):
+def _solve(g_box, lab_box, border, up_box, p, start_box=None):
     """One box: Dirichlet from user seeds (win) and border samples, warm start
-    from the parent sample; returns (K-1, *box)."""
+    from the parent sample (or from start_box on the unseeded voxels);
+    returns (K-1, *box)."""
     K = p.n_classes
     seeded = lab_box >= 0
     mask = seeded | border
     out = np.zeros((K - 1,) + g_box.shape)
     for k in range(1, K):
         x = up_box[k - 1].copy() if up_box is not None else np.zeros(g_box.shape)
+        if start_box is not None:
+            x[~mask] = start_box[k - 1][~mask]
         x[seeded] = (lab_box[seeded] == k).astype(np.float64)
         out[k - 1] = solve_box(g_box, mask, x, p.beta, p.eps, method=p.method, tol=p.tol)
     return out
@@ -232,6 +252,10 @@ def segment(volume, seeds, p, prev=None, g=None):
     """
     if g is None:
         g = pyramid(volume, p.levels)
+    if prev is not None and p.inc_rule == "node":
+        return _segment_node_rule(g, seeds, p, prev)
+    if p.inc_rule not in ("dirty", "node"):
+        raise ValueError("inc_rule must be 'dirty' or 'node'")
     K = p.n_classes
     top = p.levels - 1
     dims = [gl.shape for gl in g]
@@ -311,14 +335,115 @@ def segment(volume, seeds, p, prev=None, g=None):
                 if hi < dl:
                     idx[ax] = -1
                     border[tuple(idx)] = True
+            start = prev.maps[lvl][(slice(None),) + _sl(box)] if prev is not None and p.inc_warm else None
             xb = _solve(g[lvl][_sl(box)], lab[_sl(box)], border,
-                        up[(slice(None),) + _sl(box)], p)
+                        up[(slice(None),) + _sl(box)], p, start)
             rel = tuple(slice(c0 - b0, c1 - b0) for (c0, c1), (b0, _) in zip(core, box))
             maps[lvl][(slice(None),) + _sl(core)] = xb[(slice(None),) + rel]
             prunable[lvl][b] = _prunable(maps[lvl][(slice(None),) + _sl(core)], cfl[lvl][b], p)
 
     return Result(params=p, dims=dims, maps=maps, computed=computed, prunable=prunable,
                   cfl=cfl, recomputed=recomputed, seeds=seeds.copy())
+
+
+def _border_layer(box, d):
+    """Outermost voxel layer of a box on faces interior to the level."""
+    border = np.zeros(tuple(hi - lo for lo, hi in box), dtype=bool)
+    for ax, ((lo, hi), dl) in enumerate(zip(box, d)):
+        idx = [slice(None)] * 3
+        if lo > 0:
+            idx[ax] = 0
+            border[tuple(idx)] = True
+        if hi < dl:
+            idx[ax] = -1
+            border[tuple(idx)] = True
+    return border
+
+
+def _segment_node_rule(g, seeds, p, prev):
+    """Incremental run with the paper's node rule (Section IV-E): solve a
+    reached node, then keep the previous node and its subtree instead when
+    the two cores are within t_inc and no conflict involves a new label."""
+    K = p.n_classes
+    top = p.levels - 1
+    dims = [gl.shape for gl in g]
+    seeds = np.zeros((0, 4)) if seeds is None else np.asarray(seeds, dtype=np.float64)
+    old = {tuple(r) for r in np.asarray(prev.seeds).tolist()}
+    new_seeds = np.array([r for r in seeds.tolist() if tuple(r) not in old]).reshape(-1, 4)
+    L = p.levels
+    maps, computed, prunable, cfl, recomputed, reused = ([None] * L for _ in range(6))
+
+    def grids(lvl):
+        d = dims[lvl]
+        lab = rasterize(seeds, lvl, d)
+        lab_new = rasterize(new_seeds, lvl, d)
+        nb = brick_counts(d, p.brick)
+        c = np.zeros(nb, dtype=bool)
+        c_new = np.zeros(nb, dtype=bool)   # a conflict that involves a new label
+        conf = lab == -2
+        conf_new = conf & (lab_new != -1)
+        for b in np.ndindex(nb):
+            _, box = brick_box(b, d, p.brick, p.expand)
+            c[b] = bool(conf[_sl(box)].any())
+            c_new[b] = bool(conf_new[_sl(box)].any())
+        return lab, nb, c, c_new
+
+    def close(lvl, core):
+        cs = (slice(None),) + _sl(core)
+        return float(np.abs(maps[lvl][cs] - prev.maps[lvl][cs]).max()) < p.t_inc
+
+    def take_over(lvl, b, core):
+        cs = (slice(None),) + _sl(core)
+        maps[lvl][cs] = prev.maps[lvl][cs]
+        prunable[lvl][b] = prev.prunable[lvl][b]
+        reused[lvl][b] = True
+
+    # coarsest level: one domain (eq. 1); each brick is a node
+    lab, nb, cfl[top], c_new = grids(top)
+    start = prev.maps[top] if p.inc_warm else None
+    maps[top] = _solve(g[top], lab, np.zeros(dims[top], dtype=bool), None, p, start)
+    computed[top] = np.ones(nb, dtype=bool)
+    recomputed[top] = np.ones(nb, dtype=bool)
+    prunable[top] = np.zeros(nb, dtype=bool)
+    reused[top] = np.zeros(nb, dtype=bool)
+    for b in np.ndindex(nb):
+        core, _ = brick_box(b, dims[top], p.brick, p.expand)
+        if close(top, core) and not c_new[b]:
+            take_over(top, b, core)
+        else:
+            prunable[top][b] = _prunable(maps[top][(slice(None),) + _sl(core)], cfl[top][b], p)
+
+    for lvl in range(top - 1, -1, -1):
+        d = dims[lvl]
+        up = upsample(maps[lvl + 1], d)
+        maps[lvl] = up.copy()
+        lab, nb, cfl[lvl], c_new = grids(lvl)
+        computed[lvl] = np.zeros(nb, dtype=bool)
+        prunable[lvl] = np.zeros(nb, dtype=bool)
+        recomputed[lvl] = np.zeros(nb, dtype=bool)
+        reused[lvl] = np.zeros(nb, dtype=bool)
+        for b in np.ndindex(nb):
+            pb = tuple(i // 2 for i in b)
+            if not computed[lvl + 1][pb] or prunable[lvl + 1][pb]:
+                continue
+            core, box = brick_box(b, d, p.brick, p.expand)
+            computed[lvl][b] = True
+            if reused[lvl + 1][pb] and prev.computed[lvl][b]:
+                take_over(lvl, b, core)          # a descendant of a node taken over
+                continue
+            recomputed[lvl][b] = True
+            start = prev.maps[lvl][(slice(None),) + _sl(box)] if p.inc_warm else None
+            xb = _solve(g[lvl][_sl(box)], lab[_sl(box)], _border_layer(box, d),
+                        up[(slice(None),) + _sl(box)], p, start)
+            rel = tuple(slice(c0 - b0, c1 - b0) for (c0, c1), (b0, _) in zip(core, box))
+            maps[lvl][(slice(None),) + _sl(core)] = xb[(slice(None),) + rel]
+            if prev.computed[lvl][b] and close(lvl, core) and not c_new[b]:
+                take_over(lvl, b, core)
+            else:
+                prunable[lvl][b] = _prunable(maps[lvl][(slice(None),) + _sl(core)], cfl[lvl][b], p)
+
+    return Result(params=p, dims=dims, maps=maps, computed=computed, prunable=prunable,
+                  cfl=cfl, recomputed=recomputed, seeds=seeds.copy(), reused=reused)
 
 
 def probabilities(res, level=0):
