@@ -284,12 +284,31 @@ def bench_shells(torch, rwg, ctx, dims=(256, 256, 128), levels=3):
     st, si = res.stats(), rinc.stats()
     _, lab = rinc.materialize(0, 0, prob=False, labels=True)
     acc = float((lab.cpu().numpy() == labels).mean())
+    # incremental rules against a full run with every seed: the dirty-brick
+    # rule (above), the node rule of Section IV-E, each with and without the
+    # warm start from the previous result
+    _, rfull = _best_ms(torch, lambda: rwg.segment(pyr, more, **kw), 1)
+    lab_full = rfull.materialize(0, 0, prob=False, labels=True)[1].cpu().numpy()
+    maps_full = [rfull.level_map(l) for l in range(levels)]
+    rules = {}
+    for name, mode in (("dirty", 0), ("dirty_warm", rwg.INC_WARM), ("node", rwg.INC_NODE),
+                       ("node_warm", rwg.INC_NODE | rwg.INC_WARM)):
+        ms, r = (inc_ms, rinc) if mode == 0 else _best_ms(
+            torch, lambda: rwg.segment(pyr, more, prev=res, incremental=mode, **kw), 2)
+        sr = r.stats()
+        lb = r.materialize(0, 0, prob=False, labels=True)[1].cpu().numpy()
+        rules[name] = {"incremental_ms": ms, "solved": sr["solved"], "voxel_iters": int(sum(sr["voxel_iters"])),
+                       "kept": [int(((r.flags(l) & rwg.F_KEPT) != 0).sum().item()) for l in range(levels)],
+                       "max_abs_diff_vs_full_run": max(float((r.level_map(l) - maps_full[l]).abs().max().item())
+                                                       for l in range(levels)),
+                       "label_agreement_vs_full_run": float((lb == lab_full).mean()),
+                       "label_accuracy_vs_truth": float((lb == labels).mean())}
     return {"workload": f"nested shells {dims[0]}x{dims[1]}x{dims[2]} uint16, 4 classes (3 rhs), {levels} levels, "
                         "s=32, e=1.25, hom pruning t_hom 0.3, mixed tol 1e-5; then a 2000-voxel stroke (class 2)",
             "pyramid_ms": pyr_ms, "full_ms": full_ms, "incremental_ms": inc_ms,
             "full_voxel_iters_per_s": float(sum(st["voxel_iters"]) / (full_ms / 1e3)),
             "full_solved": st["solved"], "incremental_solved": si["solved"], "bricks": st["bricks"],
-            "label_accuracy_vs_truth": acc, "generate_s": gen_s}
+            "label_accuracy_vs_truth": acc, "incremental_rules": rules, "generate_s": gen_s}
 
 
 def bench_cells_ablation(torch, rwg, ctx, n=256, levels=4):
@@ -319,6 +338,26 @@ def bench_cells_ablation(torch, rwg, ctx, n=256, levels=4):
         out[name] = {"segment_ms": ms, "voxel_iters": int(sum(st["voxel_iters"])),
                      "per_level": {k: st[k] for k in ("bricks", "computed", "solved", "prunable")},
                      "dice_vs_truth": float(2 * (lb & gt).sum() / (lb.sum() + gt.sum()))}
+    # incremental (Section IV-E): a first run misses one cell's seed, the
+    # second adds it; the dirty-brick rule and the node rule, with and without
+    # the warm start from the previous result, against the full s = 16 run
+    kw = dict(brick=16, expand=1.25, beta=BETA, eps=EPS, tol=1e-5, precision=1, n_classes=2, prune_hom=1,
+              prune_dt=1, t_hom=0.3, t_bin=0.01)
+    first = np.delete(seeds, np.flatnonzero(seeds[:, 3] == 1)[0], axis=0)
+    _, r0 = _best_ms(torch, lambda: rwg.segment(pyr, first, **kw), 1)
+    _, rfull = _best_ms(torch, lambda: rwg.segment(pyr, seeds, **kw), 1)
+    lab_full = rfull.materialize(0, 1, prob=False, labels=True)[1].cpu().numpy()
+    inc = {"brick": 16, "full_run_ms": out["s16_pruned"]["segment_ms"], "full_run_solved": rfull.stats()["solved"]}
+    for name, mode in (("dirty", 0), ("dirty_warm", rwg.INC_WARM), ("node", rwg.INC_NODE),
+                       ("node_warm", rwg.INC_NODE | rwg.INC_WARM)):
+        ms, r = _best_ms(torch, lambda: rwg.segment(pyr, seeds, prev=r0, incremental=mode, **kw), 2)
+        st = r.stats()
+        lb = r.materialize(0, 1, prob=False, labels=True)[1].cpu().numpy()
+        inc[name] = {"incremental_ms": ms, "solved": st["solved"], "voxel_iters": int(sum(st["voxel_iters"])),
+                     "kept": [int(((r.flags(l) & rwg.F_KEPT) != 0).sum().item()) for l in range(levels)],
+                     "label_agreement_vs_full_run": float((lb == lab_full).mean()),
+                     "dice_vs_truth": float(2 * (lb.astype(bool) & gt).sum() / (lb.astype(bool).sum() + gt.sum()))}
+    out["incremental_add_one_cell_seed"] = inc
     return out
 
 

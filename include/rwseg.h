@@ -286,7 +286,8 @@ typedef struct rw_params {
     int32_t n_classes;       /* K in [2, 4]; K - 1 right-hand sides are solved */
     int32_t prune_hom, prune_dt;  /* enable the hom / dt tests (dt only for K = 2) */
     int32_t refine_max;
-    int32_t reserved;        /* must be 0 */
+    int32_t incremental;     /* runs with prev: bit 0 the node rule (else the dirty-brick rule),
+                                bit 1 warm start from prev (Section IV-E); 0 by default */
 } rw_params;
 
 void rw_params_default(rw_params* p);
@@ -318,10 +319,21 @@ typedef struct rw_run_stats {
  *    sample (Section IV-D2); the solution's s^3 core is kept;
  *  - prunable = (hom or dt) and not cfl (a conflict voxel in the box);
  *  - regions not reached keep the upsampled parent map (ancestor fallback);
- *  - incremental: a reached brick is solved again only if a new label lands
- *    in its box, it was not reached in `prev`, or the parent level map moved by
- *    >= t_inc over the parent voxels its box samples; otherwise its previous
- *    core values and prunable flag are reused.
+ *  - incremental, dirty-brick rule (default): a reached brick is solved
+ *    again only if a new label lands in its box, it was not reached in
+ *    `prev`, or the parent level map moved by >= t_inc over the parent voxels
+ *    its box samples; otherwise its previous core values and prunable flag
+ *    are reused;
+ *  - incremental, node rule (params->incremental bit 0; the rule of Section
+ *    IV-E): the coarsest level and every brick reached under a parent that
+ *    was not kept are solved; a solved brick that `prev` also reached is
+ *    kept (flag bit 4) when its new core is within t_inc of the previous one
+ *    (max abs difference) and no seed conflict in its box involves a newly
+ *    added label: it takes its previous core and prunable flag, and its
+ *    reached descendants in `prev` are copied, not solved;
+ *  - warm start (params->incremental bit 1): solved boxes start their
+ *    unseeded voxels from prev's map of the same level (the border still
+ *    samples the parent).
  * `seeds` is a host array.  The run is queued on `stream` but the call
  * synchronises with it once per level (it reads back brick flags and
  * solver statistics to plan the next level).  *out owns its device memory.
@@ -335,7 +347,8 @@ int rw_result_stats(const rw_result* r, rw_run_stats* out);
 int rw_result_level(const rw_result* r, int level, int64_t dims[3], int* nrhs, const float** map);
 /* Brick flags of a level: nb = bricks per axis {x, y, z}, *flags = dev uint8
  * [nbz][nby][nbx]; bit 0 reached, bit 1 prunable, bit 2 seed conflict in the
- * box, bit 3 solved in this run. */
+ * box, bit 3 solved in this run, bit 4 kept from prev by the node rule (with
+ * its subtree). */
 int rw_result_flags(const rw_result* r, int level, int64_t nb[3], const uint8_t** flags);
 /* Copies of the data behind the accessors above into caller device buffers,
  * queued on `stream`: a level map (float [voxel][K-1]), a level's brick flags

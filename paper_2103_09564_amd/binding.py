@@ -237,7 +237,7 @@ def solve_bricks_adjoint(g, mask, x, dl_dx, shapes, offsets, lam=None, stream=No
 
 RW_U16, RW_F32 = 0, 1
 MAX_LEVELS = 16
-F_REACHED, F_PRUNABLE, F_CFL, F_SOLVED = 1, 2, 4, 8
+F_REACHED, F_PRUNABLE, F_CFL, F_SOLVED, F_KEPT = 1, 2, 4, 8, 16
 
 
 class Params(ctypes.Structure):
@@ -245,7 +245,7 @@ class Params(ctypes.Structure):
                 ("expand", ctypes.c_double), ("t_hom", ctypes.c_double), ("t_bin", ctypes.c_double),
                 ("t_inc", ctypes.c_double), ("brick", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("n_classes", ctypes.c_int32), ("prune_hom", ctypes.c_int32),
-                ("prune_dt", ctypes.c_int32), ("refine_max", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("prune_dt", ctypes.c_int32), ("refine_max", ctypes.c_int32), ("incremental", ctypes.c_int32)]
 
 
 class Seed(ctypes.Structure):
@@ -292,6 +292,11 @@ lib.rw_result_materialize.restype = ctypes.c_int
 for _f in ("rw_result_copy_level", "rw_result_copy_flags", "rw_pyramid_copy_level"):
     getattr(lib, _f).argtypes = [_vp, _vp, ctypes.c_int, _vp, _vp]
     getattr(lib, _f).restype = ctypes.c_int
+
+
+# rw_params.incremental bits (runs with a previous result)
+INC_NODE = 1   # the node rule of Section IV-E (else the dirty-brick rule)
+INC_WARM = 2   # warm start of the solved boxes from the previous result
 
 
 def params(**kw):

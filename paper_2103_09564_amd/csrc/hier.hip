@@ -49,7 +49,7 @@ struct rw_result {
 namespace rwk {
 
 constexpr int kHThreads = 256;
-enum : uint8_t { F_REACHED = 1, F_PRUNABLE = 2, F_CFL = 4, F_SOLVED = 8 };
+enum : uint8_t { F_REACHED = 1, F_PRUNABLE = 2, F_CFL = 4, F_SOLVED = 8, F_KEPT = 16 };
 
 // Geometry of one packed box of a level (level voxel coordinates).
 struct BoxGeo {
@@ -233,8 +233,9 @@ __device__ __forceinline__ float sample_parent(const float* __restrict__ pm, int
 // another box's border.
 template <int R>
 __global__ void k_setup(const BoxGeo* __restrict__ geo, const float* __restrict__ glev, int64_t Dx, int64_t Dy,
-                        const float* __restrict__ pm, int64_t px, int64_t py, int64_t pz, float* __restrict__ gb,
-                        uint8_t* __restrict__ mb, float* __restrict__ xb) {
+                        const float* __restrict__ pm, int64_t px, int64_t py, int64_t pz,
+                        const float* __restrict__ warm, float* __restrict__ gb, uint8_t* __restrict__ mb,
+                        float* __restrict__ xb) {
     const BoxGeo b = geo[blockIdx.x];
     const int64_t n = (int64_t)b.nx * b.ny * b.nz;
     for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
@@ -247,8 +248,12 @@ __global__ void k_setup(const BoxGeo* __restrict__ geo, const float* __restrict_
                             ((b.faces & 4) && j == 0) || ((b.faces & 8) && j == b.ny - 1) ||
                             ((b.faces & 16) && k == 0) || ((b.faces & 32) && k == b.nz - 1);
         mb[v] = border ? 1 : 0;
+        // the border takes the parent sample; with a warm map (a previous
+        // result of this level) the unseeded voxels start from it instead
 #pragma unroll
-        for (int c = 0; c < R; ++c) xb[v * R + c] = pm ? sample_parent<R>(pm, px, py, pz, X, Y, Z, c) : 0.0f;
+        for (int c = 0; c < R; ++c)
+            xb[v * R + c] = warm && !border ? warm[L * R + c]
+                                            : pm ? sample_parent<R>(pm, px, py, pz, X, Y, Z, c) : 0.0f;
     }
 }
 
@@ -360,6 +365,26 @@ __global__ void k_prune(const BoxGeo* __restrict__ geo, const float* __restrict_
 
 // Incremental: max |new - old| of the parent level map over the parent voxels
 // a box samples, [(lo-1)/2, hi/2] per axis, clamped.  One workgroup per box.
+// Max abs difference of two maps of one level over each box's core (all
+// classes): the similarity test of the node rule.
+template <int R>
+__global__ void k_core_change(const BoxGeo* __restrict__ geo, const float* __restrict__ a, const float* __restrict__ b_,
+                              int64_t Dx, int64_t Dy, float* __restrict__ out) {
+    __shared__ float red[2 * 16];
+    const BoxGeo b = geo[blockIdx.x];
+    const int64_t n = (int64_t)b.cnx * b.cny * b.cnz;
+    float m = 0.0f, dummy = 0.0f;
+    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
+        const int i = (int)(t % b.cnx), j = (int)((t / b.cnx) % b.cny), k = (int)(t / ((int64_t)b.cnx * b.cny));
+        const int64_t L = (b.cx0 + i) + Dx * ((b.cy0 + j) + Dy * (int64_t)(b.cz0 + k));
+#pragma unroll
+        for (int c = 0; c < R; ++c) m = fmaxf(m, fabsf(a[L * R + c] - b_[L * R + c]));
+    }
+    float lo = -m;
+    block_minmax(lo, dummy, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = -lo;
+}
+
 template <int R>
 __global__ void k_parent_change(const BoxGeo* __restrict__ geo, const float* __restrict__ pn, const float* __restrict__ po,
                                 int64_t Px, int64_t Py, int64_t Pz, float* __restrict__ out) {
@@ -514,17 +539,19 @@ static int upload(rw_ctx* ctx, void* dst, const std::vector<T>& v, hipStream_t s
 
 template <int R>
 static void launch_setup(const BoxGeo* geo, int64_t n, const float* glev, int64_t Dx, int64_t Dy, const float* pm,
-                         const int64_t* PD, float* gb, uint8_t* mb, float* xb, hipStream_t s) {
+                         const int64_t* PD, const float* warm, float* gb, uint8_t* mb, float* xb, hipStream_t s) {
     hipLaunchKernelGGL(k_setup<R>, dim3((unsigned)n), dim3(kHThreads), 0, s, geo, glev, Dx, Dy, pm, PD ? PD[0] : 0,
-                       PD ? PD[1] : 0, PD ? PD[2] : 0, gb, mb, xb);
+                       PD ? PD[1] : 0, PD ? PD[2] : 0, warm, gb, mb, xb);
 }
 
 // Solve the listed boxes of a level and scatter their cores into lmap.
-// `geos` are the boxes (host); `entries` the seed overrides per packed voxel.
+// `geos` are the boxes (host); `entries` the seed overrides per packed voxel;
+// `warm` (or null): a previous map of this level to start the unseeded
+// voxels from.
 template <int R>
 static int solve_boxes(rw_ctx* ctx, hipStream_t s, const rw_params& P, const LevelGeo& L, const float* glev,
                        float* lmap, const float* pmap, const int64_t* PD, std::vector<BoxGeo>& geos,
-                       const std::map<int64_t, int>& lab, rw_run_stats* st, int level) {
+                       const std::map<int64_t, int>& lab, rw_run_stats* st, int level, const float* warm) {
     const int top = pmap == nullptr;
     const int64_t maxv_batch = (int64_t)1 << 28;   // voxels per batch
     size_t i0 = 0;
@@ -577,7 +604,7 @@ static int solve_boxes(rw_ctx* ctx, hipStream_t s, const rw_params& P, const Lev
         std::vector<BoxGeo> part(geos.begin() + i0, geos.begin() + i1);
         H_TRY(upload(ctx, dgeo, part, s));
         H_TRY(upload(ctx, dent, ent, s));
-        launch_setup<R>(dgeo, nb, glev, L.D[0], L.D[1], pmap, PD, gb, mb, xb, s);
+        launch_setup<R>(dgeo, nb, glev, L.D[0], L.D[1], pmap, PD, warm, gb, mb, xb, s);
         if (!ent.empty())
             hipLaunchKernelGGL(k_seeds<R>, dim3(grid_for((int64_t)ent.size(), kHThreads)), dim3(kHThreads), 0, s, dent,
                                (int64_t)ent.size(), mb, xb);
@@ -681,6 +708,66 @@ static int segment_impl(rw_ctx* ctx, const rw_pyramid* pyr, const std::vector<rw
             bricks_containing(L, P.brick, P.expand, X, Y, Z, [&](int32_t b) { hflags[(size_t)b] |= F_CFL; });
         }
     };
+    // Node rule (Section IV-E): conflicts that involve a newly added label
+    const bool node = prev && (P.incremental & 1);
+    const float* no_warm = nullptr;
+    auto warm_of = [&](int l) { return prev && (P.incremental & 2) ? (const float*)prev->lv[l].map : no_warm; };
+    auto cfl_new = [&](int l, const std::map<int64_t, int>& lab) {
+        const LevelGeo& L = LG[(size_t)l];
+        std::vector<uint8_t> c((size_t)(L.nb[0] * L.nb[1] * L.nb[2]), 0);
+        for (const auto& kv : rasterize(newseeds, l, L)) {
+            auto it = lab.find(kv.first);
+            if (it == lab.end() || it->second != -2) continue;
+            const int64_t v = kv.first;
+            const int64_t X = v % L.D[0], Y = (v / L.D[0]) % L.D[1], Z = v / (L.D[0] * L.D[1]);
+            bricks_containing(L, P.brick, P.expand, X, Y, Z, [&](int32_t b) { c[(size_t)b] = 1; });
+        }
+        return c;
+    };
+    // After a node-rule level is solved and prune-tested: every solved brick
+    // that the previous result also reached is compared with its previous
+    // core; within t_inc and no conflict with a new label, the previous core
+    // and prunable flag replace the new ones and the brick is marked kept
+    // (its previous subtree is taken over level by level below).
+    auto take_over = [&](int l, const std::vector<BoxGeo>& solved, const std::vector<uint8_t>& prevflags,
+                         const std::vector<uint8_t>& cnew) -> int {
+        const LevelGeo& L = LG[(size_t)l];
+        rwk::LevelRes& lr = res->lv[l];
+        const int64_t nbr = L.nb[0] * L.nb[1] * L.nb[2];
+        std::vector<BoxGeo> cand;
+        for (const BoxGeo& g : solved)
+            if (prevflags[(size_t)g.brick] & F_REACHED) cand.push_back(g);
+        if (cand.empty()) return RW_OK;
+        const size_t gg = (cand.size() * sizeof(BoxGeo) + 255) & ~size_t(255);
+        H_HIP(grow(ctx, &ctx->hgeo, &ctx->hgeo_bytes, gg + cand.size() * sizeof(float), s), "allocating box geometry");
+        H_TRY(upload(ctx, ctx->hgeo, cand, s));
+        float* dch = (float*)((char*)ctx->hgeo + gg);
+        hipLaunchKernelGGL(k_core_change<R>, dim3((unsigned)cand.size()), dim3(kHThreads), 0, s,
+                           (const BoxGeo*)ctx->hgeo, lr.map, prev->lv[l].map, L.D[0], L.D[1], dch);
+        H_HIP(hipGetLastError(), "launching core change test");
+        std::vector<float> ch(cand.size());
+        std::vector<uint8_t> f((size_t)nbr);
+        H_HIP(hipMemcpyAsync(ch.data(), dch, ch.size() * sizeof(float), hipMemcpyDeviceToHost, s), "reading change test");
+        H_HIP(hipMemcpyAsync(f.data(), lr.flags, (size_t)nbr, hipMemcpyDeviceToHost, s), "reading flags");
+        H_HIP(hipStreamSynchronize(s), "synchronising change test");
+        std::vector<BoxGeo> keep;
+        for (size_t i = 0; i < cand.size(); ++i) {
+            const size_t b = (size_t)cand[i].brick;
+            if ((double)ch[i] < P.t_inc && !cnew[b]) {
+                keep.push_back(cand[i]);
+                f[b] = (uint8_t)((f[b] & ~F_PRUNABLE) | (prevflags[b] & F_PRUNABLE) | F_KEPT);
+            }
+        }
+        if (keep.empty()) return RW_OK;
+        H_HIP(grow(ctx, &ctx->hgeo, &ctx->hgeo_bytes, keep.size() * sizeof(BoxGeo), s), "allocating box geometry");
+        H_TRY(upload(ctx, ctx->hgeo, keep, s));
+        hipLaunchKernelGGL(k_copy_core<R>, dim3((unsigned)keep.size()), dim3(kHThreads), 0, s,
+                           (const BoxGeo*)ctx->hgeo, prev->lv[l].map, L.D[0], L.D[1], lr.map);
+        H_HIP(hipGetLastError(), "launching take-over copy");
+        H_HIP(hipMemcpyAsync(lr.flags, f.data(), (size_t)nbr, hipMemcpyHostToDevice, s), "uploading flags");
+        H_HIP(hipStreamSynchronize(s), "synchronising take-over");   // f is host memory of this scope
+        return RW_OK;
+    };
 
     // ---- coarsest level: one domain, user seeds only (eq. 1)
     {
@@ -690,7 +777,7 @@ static int segment_impl(rw_ctx* ctx, const rw_pyramid* pyr, const std::vector<rw
         auto lab = rasterize(seeds, top, L);
         std::vector<uint8_t> hflags((size_t)nbr, F_REACHED);
         cfl_bricks(top, lab, hflags);
-        const bool reuse = prev && newseeds.empty();
+        const bool reuse = prev && !node && newseeds.empty();
         if (reuse) {
             H_HIP(hipMemcpyAsync(lr.map, prev->lv[top].map, (size_t)(L.D[0] * L.D[1] * L.D[2]) * R * sizeof(float),
                                  hipMemcpyDeviceToDevice, s),
@@ -706,10 +793,18 @@ static int segment_impl(rw_ctx* ctx, const rw_pyramid* pyr, const std::vector<rw
             g.cnz = g.nz;
             g.brick = 0;
             std::vector<BoxGeo> one{g};
-            H_TRY(solve_boxes<R>(ctx, s, P, L, pyr->data[top], lr.map, nullptr, nullptr, one, lab, &st, top));
+            H_TRY(solve_boxes<R>(ctx, s, P, L, pyr->data[top], lr.map, nullptr, nullptr, one, lab, &st, top,
+                                 warm_of(top)));
         }
         H_HIP(hipMemcpyAsync(lr.flags, hflags.data(), (size_t)nbr, hipMemcpyHostToDevice, s), "uploading flags");
         H_TRY(run_prune<R>(ctx, s, P, L, lr.map, all_bricks(top), lr.flags));
+        if (node) {
+            std::vector<uint8_t> pf((size_t)nbr);
+            H_HIP(hipMemcpyAsync(pf.data(), prev->lv[top].flags, (size_t)nbr, hipMemcpyDeviceToHost, s),
+                  "reading previous flags");
+            H_HIP(hipStreamSynchronize(s), "synchronising flags");
+            H_TRY(take_over(top, all_bricks(top), pf, cfl_new(top, lab)));
+        }
         st.computed[top] = nbr;
     }
 
@@ -747,6 +842,14 @@ static int segment_impl(rw_ctx* ctx, const rw_pyramid* pyr, const std::vector<rw
         std::vector<BoxGeo> solve, reuse;
         if (!prev) {
             solve = reached;
+        } else if (node) {
+            // descendants of kept nodes are taken over; every other reached brick is solved
+            for (const BoxGeo& g : reached) {
+                const int64_t bx = g.brick % L.nb[0], by = (g.brick / L.nb[0]) % L.nb[1], bz = g.brick / (L.nb[0] * L.nb[1]);
+                const int64_t pb = bx / 2 + PL.nb[0] * (by / 2 + PL.nb[1] * (bz / 2));
+                if ((pflags[(size_t)pb] & F_KEPT) && (prevflags[(size_t)g.brick] & F_REACHED)) reuse.push_back(g);
+                else solve.push_back(g);
+            }
         } else {
             std::vector<uint8_t> newin((size_t)nbr, 0);
             auto nl = rasterize(newseeds, l, L);
@@ -781,7 +884,8 @@ static int segment_impl(rw_ctx* ctx, const rw_pyramid* pyr, const std::vector<rw
         }
         for (const BoxGeo& g : reached) hflags[(size_t)g.brick] |= F_REACHED;
         for (const BoxGeo& g : solve) hflags[(size_t)g.brick] |= F_SOLVED;
-        for (const BoxGeo& g : reuse) hflags[(size_t)g.brick] |= (uint8_t)(prevflags[(size_t)g.brick] & F_PRUNABLE);
+        for (const BoxGeo& g : reuse)
+            hflags[(size_t)g.brick] |= (uint8_t)((prevflags[(size_t)g.brick] & F_PRUNABLE) | (node ? F_KEPT : 0));
         H_HIP(hipMemcpyAsync(lr.flags, hflags.data(), (size_t)nbr, hipMemcpyHostToDevice, s), "uploading flags");
         H_HIP(hipStreamSynchronize(s), "synchronising flags");   // hflags is host memory of this scope
         if (!reuse.empty()) {
@@ -794,8 +898,9 @@ static int segment_impl(rw_ctx* ctx, const rw_pyramid* pyr, const std::vector<rw
         }
         if (!solve.empty()) {
             // largest boxes first is done by the solver; keep brick order here
-            H_TRY(solve_boxes<R>(ctx, s, P, L, pyr->data[l], lr.map, pr.map, PL.D, solve, lab, &st, l));
+            H_TRY(solve_boxes<R>(ctx, s, P, L, pyr->data[l], lr.map, pr.map, PL.D, solve, lab, &st, l, warm_of(l)));
             H_TRY(run_prune<R>(ctx, s, P, L, lr.map, solve, lr.flags));
+            if (node) H_TRY(take_over(l, solve, prevflags, cfl_new(l, lab)));
         }
         st.computed[l] = (int64_t)reached.size();
     }
@@ -961,7 +1066,7 @@ int rw_segment(rw_ctx* ctx, const rw_pyramid* pyr, const rw_seed* seeds, int64_t
     if (P.brick < 2 || P.brick > 1024) return fail(ctx, RW_E_INVAL, "brick must be in [2, 1024]");
     if (!(P.expand >= 1.0) || P.expand > 4.0) return fail(ctx, RW_E_INVAL, "expand must be in [1, 4]");
     if (!(P.t_hom >= 0) || !(P.t_bin >= 0) || !(P.t_inc >= 0)) return fail(ctx, RW_E_INVAL, "thresholds must be >= 0");
-    if (P.reserved != 0) return fail(ctx, RW_E_INVAL, "reserved must be 0");
+    if (P.incremental < 0 || P.incremental > 3) return fail(ctx, RW_E_INVAL, "incremental must be in 0..3");
     for (int64_t i = 0; i < n_seeds; ++i) {
         const rw_seed& q = seeds[i];
         if (!std::isfinite(q.x) || !std::isfinite(q.y) || !std::isfinite(q.z))

@@ -192,6 +192,38 @@ def test_incremental_matches_oracle(env, binary_case, extra):
         assert np.array_equal(gm2[l], gmaps[l])
 
 
+@pytest.mark.parametrize("warm", [False, True])
+@pytest.mark.parametrize("extra", [[[3.0, 3.0, 60.0, 0]], [[50.5, 12.25, 40.0, 1], [10.0, 52.0, 20.5, 0]]])
+def test_incremental_node_rule_matches_oracle(env, binary_case, extra, warm):
+    """The node rule of Section IV-E (solve, then keep the previous node and
+    subtree when within t_inc) and the warm start from the previous result."""
+    torch, rwg, ctx = env
+    vol, seeds, p, ores = binary_case
+    kw = dict(brick=8, beta=64.0, t_bin=0.01, t_hom=0.3, precision=0, tol=1e-12)
+    pyr, res, _, _ = _gpu_run(env, vol, seeds, p.levels, **kw)
+    more = np.concatenate([seeds, extra])
+    oinc = H.segment(vol, more, H.Params(**{**p.__dict__, "inc_rule": "node", "inc_warm": warm}), prev=ores)
+    mode = rwg.INC_NODE | (rwg.INC_WARM if warm else 0)
+    _, rinc, gmaps, gflags = _gpu_run(env, vol, more, p.levels, prev=res, pyr=pyr, incremental=mode, **kw)
+    _compare(oinc.maps, oinc, gmaps, gflags, 1e-6, exact_flags=True)
+    kept = solved = 0
+    for l in range(p.levels):
+        assert np.array_equal((gflags[l] & rwg.F_SOLVED) != 0, oinc.recomputed[l]), f"level {l}: solved bricks differ"
+        assert np.array_equal((gflags[l] & rwg.F_KEPT) != 0, oinc.reused[l]), f"level {l}: kept bricks differ"
+        kept += int(oinc.reused[l].sum())
+        solved += int(oinc.recomputed[l].sum())
+    assert solved > 0
+    if len(extra) == 1:
+        assert kept > 0   # one background seed near a corner leaves nodes within t_inc
+    if warm:
+        # the same run started from the parent samples: the same result (the
+        # start changes the iteration count only, either way)
+        _, rcold, cmaps, _ = _gpu_run(env, vol, more, p.levels, prev=res, pyr=pyr, incremental=rwg.INC_NODE, **kw)
+        for l in range(p.levels):
+            assert np.max(np.abs(cmaps[l] - gmaps[l])) <= 2e-6
+        assert rinc.stats()["voxel_iters"] != rcold.stats()["voxel_iters"]   # the warm start took effect
+
+
 def test_single_level_is_plain_solve(env):
     torch, rwg, ctx = env
     vol = _sphere_volume(24, "f32", seed=7)
@@ -212,6 +244,8 @@ def test_segment_argument_errors(env):
         rwg.segment(pyr, [[1, 1, 1, 1]], n_classes=9)
     with pytest.raises(rwg.RWError):
         rwg.segment(pyr, [[1, 1, 1, 1]], brick=1)
+    with pytest.raises(rwg.RWError):
+        rwg.segment(pyr, [[1, 1, 1, 1]], incremental=4)
 
 
 def test_conflicting_labels_match_oracle(env):
