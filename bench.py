@@ -33,7 +33,7 @@ BYTES_PER_VOXEL_ITER = 28      # read x, r, p, g; write x, r, p (FP32, one rhs)
 BETA, EPS, TOL = 128.0, 1e-6, 1e-6
 N_BOXES, SEED = 8192, 3
 EXTRAS = ("plain_sphere_64", "tubes_512_hierarchy", "blobs_512x32_adjoint", "shells_hierarchy_incremental",
-          "cells_256_ablation")
+          "cells_256_ablation", "cells_brick_growth")
 
 
 # The sources that define, plan and launch the kernels of the headline
@@ -367,6 +367,40 @@ def bench_cells_ablation(torch, rwg, ctx, n=256, levels=4):
     return out
 
 
+def bench_cells_growth(torch, rwg, ctx, sizes=(64, 128, 256, 512)):
+    """Active-brick growth (Section IV-D1): the same cells geometry scaled to
+    n^3 voxels (structure and coverage relative to n, so the spheres' surface
+    grows as n^2 = v^(2/3)), s = 16 with hom and dt pruning, levels chosen so
+    that the coarsest level is 32^3.  Per size: level-0 bricks in all and
+    reached, bricks solved, time; and the growth exponent of the reached
+    level-0 bricks in v between successive sizes (2/3 for a surface)."""
+    import numpy as np
+    import synth
+    rows = []
+    for n in sizes:
+        v, seeds, truth = synth.cells_volume(n=n, seed=11)
+        levels = int(round(np.log2(n / 32))) + 1
+        vd = torch.from_numpy(v).to("cuda:0")
+        pyr = rwg.Pyramid(ctx, vd, levels)
+        kw = dict(brick=16, expand=1.25, beta=BETA, eps=EPS, tol=1e-5, precision=1, n_classes=2, prune_hom=1,
+                  prune_dt=1, t_hom=0.3, t_bin=0.01)
+        ms, res = _best_ms(torch, lambda: rwg.segment(pyr, seeds, **kw), 2)
+        st = res.stats()
+        lb = res.materialize(0, 1, prob=False, labels=True)[1].cpu().numpy().astype(bool)
+        gt = truth.astype(bool)
+        rows.append({"n": n, "voxels": n ** 3, "levels": levels, "spheres": int((seeds[:, 3] == 1).sum()),
+                     "level0_bricks": st["bricks"][0], "level0_reached": st["computed"][0],
+                     "solved": st["solved"], "segment_ms": ms, "voxel_iters": int(sum(st["voxel_iters"])),
+                     "dice_vs_truth": float(2 * (lb & gt).sum() / (lb.sum() + gt.sum()))})
+        del vd, pyr, res
+    for a, b in zip(rows, rows[1:]):
+        dv = np.log(b["voxels"] / a["voxels"])
+        b["reached_exponent_in_v"] = float(np.log(b["level0_reached"] / a["level0_reached"]) / dv)
+        b["time_exponent_in_v"] = float(np.log(b["segment_ms"] / a["segment_ms"]) / dv)
+    return {"workload": "cells geometry scaled to n^3, n in " + ", ".join(str(n) for n in sizes) +
+                        "; s=16, e=1.25, hom and dt pruning, coarsest level 32^3, mixed tol 1e-5", "runs": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,6 +436,8 @@ def main():
             return bench_blobs_adjoint(torch, rwg, dev, cpu_leg=not args.no_cpu_baseline)
         if name == "cells_256_ablation":
             return bench_cells_ablation(torch, rwg, ctx)
+        if name == "cells_brick_growth":
+            return bench_cells_growth(torch, rwg, ctx)
         return bench_shells(torch, rwg, ctx, dims=shell_dims)
 
     if args.only:
