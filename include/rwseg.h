@@ -154,6 +154,33 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
                     void* stream);
 
 /*
+ * The same solve for boxes held in host memory, streamed through the GPU
+ * (out-of-core brick queues; the paper's volumes reach hundreds of GB, more
+ * than one GPU holds).  g, mask, x and stats have rw_solve_bricks' layout but
+ * are HOST arrays; page-locked memory (hipHostMalloc) lets the copies run
+ * asynchronously and overlap the solves, pageable memory works but copies
+ * synchronously.  The boxes must be listed in increasing offset order without
+ * overlap; runs of consecutive boxes whose voxel span is at most
+ * chunk_voxels (0: 2^25; a larger box forms a chunk alone) are copied into
+ * one of two device staging sets on a copy stream while the previous chunk
+ * is solved on `stream`, and x (and stats) are copied back on a second copy
+ * stream behind each solve.  Per box the result is that of rw_solve_bricks
+ * (the same kernels).  No x64 output.  The call returns once everything is
+ * queued: x and stats are complete when `stream` has completed (the copy
+ * streams are joined to it).  On an error part-way the queued copies finish
+ * before the call returns.  The staging sets (about 2 x (9 + 4 (nrhs - 1))
+ * bytes per voxel of the largest chunk) and page-locked copies of the box
+ * lists stay allocated on the context.  Chunks are solved one after
+ * another, each ending with its slowest box: chunks much smaller than the
+ * default leave the GPU idle in those tails.
+ * Returns RW_E_INVAL on bad descriptors (as rw_solve_bricks, plus the order).
+ */
+int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks,
+                             const rw_brick* bricks, int64_t n_voxels, const float* g,
+                             const uint8_t* mask, float* x, rw_brick_stats* stats,
+                             int64_t chunk_voxels, void* stream);
+
+/*
  * Phase timing of rw_solve_bricks (tracing).  With timing enabled the next
  * solves record HIP events on their stream around each phase; rw_last_timing
  * waits for those events and returns the phase durations of the last solve

@@ -53,6 +53,9 @@ lib.rw_last_error.argtypes = [_vp]
 lib.rw_last_error.restype = ctypes.c_char_p
 lib.rw_solve_bricks.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
 lib.rw_solve_bricks.restype = ctypes.c_int
+lib.rw_solve_bricks_streamed.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp,
+                                         _i64, _vp]
+lib.rw_solve_bricks_streamed.restype = ctypes.c_int
 lib.rw_solve_bricks_adjoint.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp,
                                         _vp, _vp, _vp, _vp, _vp]
 lib.rw_solve_bricks_adjoint.restype = ctypes.c_int
@@ -166,6 +169,18 @@ class Context:
                                         bricks.ctypes.data_as(_vp), n_vox, _ptr(g), _ptr(mask), _ptr(x),
                                         _ptr(x64), _ptr(stats), _stream(stream)))
 
+    def rw_solve_bricks_streamed(self, params, bricks, g, mask, x, stats=None, chunk_voxels=0, stream=None):
+        """Queue rw_solve_bricks_streamed.  g, mask, x (and stats) are HOST
+        tensors (page-locked for overlapped copies); bricks a host
+        BRICK_DTYPE array in increasing offset order."""
+        for t in (g, mask, x) + ((stats,) if stats is not None else ()):
+            if t.is_cuda or not t.is_contiguous():
+                raise ValueError("streamed solve: g, mask, x and stats must be contiguous host tensors")
+        bricks = np.ascontiguousarray(bricks, dtype=BRICK_DTYPE)
+        self._check(lib.rw_solve_bricks_streamed(self.handle, ctypes.byref(params), len(bricks),
+                                                 bricks.ctypes.data_as(_vp), g.numel(), _ptr(g), _ptr(mask),
+                                                 _ptr(x), _ptr(stats), int(chunk_voxels), _stream(stream)))
+
     def set_timing(self, enable=True):
         self._check(lib.rw_set_timing(self.handle, 1 if enable else 0))
 
@@ -215,6 +230,22 @@ def solve_bricks(g, mask, x, shapes, offsets, x64=None, stream=None, ctx=None, *
     b = bricks_array(shapes, offsets)
     st = torch.empty((len(b), STATS_DTYPE.itemsize), dtype=torch.uint8, device=g.device)
     ctx.rw_solve_bricks(solve_params(**params), b, g, mask, x, x64=x64, stats=st, stream=stream)
+    return st
+
+
+def solve_bricks_streamed(g, mask, x, shapes, offsets, chunk_voxels=0, stream=None, ctx=None, device=0, **params):
+    """Solve boxes held in host memory (x updated in place once the stream
+    completes; this call synchronises it).  Returns the host stats tensor."""
+    import torch
+    ctx = ctx or context(device)
+    b = bricks_array(shapes, offsets)
+    st = torch.empty((len(b), STATS_DTYPE.itemsize), dtype=torch.uint8, pin_memory=g.is_pinned())
+    ctx.rw_solve_bricks_streamed(solve_params(**params), b, g, mask, x, stats=st, chunk_voxels=chunk_voxels,
+                                 stream=stream)
+    if stream is None:
+        torch.cuda.current_stream(device).synchronize()
+    else:
+        stream.synchronize()
     return st
 
 

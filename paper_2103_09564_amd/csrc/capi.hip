@@ -249,7 +249,14 @@ int upload_list(rw_ctx* ctx, const std::vector<rwk::BrickDev>& list, hipStream_t
     hipError_t e = grow(ctx, &ctx->bricks, &ctx->bricks_bytes, bytes, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating brick list");
     if (!list.empty()) {
-        e = hipMemcpyAsync(ctx->bricks, list.data(), list.size() * sizeof(rwk::BrickDev), hipMemcpyHostToDevice, s);
+        // from a page-locked slot when the caller set one (the copy then
+        // does not wait for the stream), else from the vector itself
+        const void* src = list.data();
+        if (ctx->list_stage) {
+            std::memcpy(ctx->list_stage, list.data(), list.size() * sizeof(rwk::BrickDev));
+            src = ctx->list_stage;
+        }
+        e = hipMemcpyAsync(ctx->bricks, src, list.size() * sizeof(rwk::BrickDev), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(ctx, e, "uploading brick list");
     }
     return RW_OK;
@@ -304,6 +311,13 @@ void rw_ctx_destroy(rw_ctx* ctx) {
     if (ctx->hws) (void)hipFree(ctx->hws);
     if (ctx->hgeo) (void)hipFree(ctx->hgeo);
     if (ctx->wts) (void)hipFree(ctx->wts);
+    if (ctx->ooc) (void)hipFree(ctx->ooc);
+    if (ctx->pin) (void)hipHostFree(ctx->pin);
+    if (ctx->pin_ev) (void)hipEventDestroy(ctx->pin_ev);
+    for (hipStream_t& c : ctx->cs)
+        if (c) (void)hipStreamDestroy(c);
+    for (hipEvent_t& e : ctx->cev)
+        if (e) (void)hipEventDestroy(e);
     for (int i = 0; i < 4; ++i) {
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
         if (ctx->gev[i]) (void)hipEventDestroy(ctx->gev[i]);
@@ -477,6 +491,152 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
         if (e != hipSuccess) return hip_fail(ctx, e, "recording timing event");
         ctx->ev_valid = 1;
     }
+    return RW_OK;
+}
+
+int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                             int64_t n_voxels, const float* g, const uint8_t* mask, float* x,
+                             rw_brick_stats* stats, int64_t chunk_voxels, void* stream) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    if (n_bricks < 0 || n_voxels < 0) return fail(ctx, RW_E_INVAL, "n_bricks and n_voxels must be >= 0");
+    if (n_bricks == 0) return RW_OK;
+    if (!bricks || !g || !mask || !x) return fail(ctx, RW_E_INVAL, "bricks, g, mask and x must be non-NULL");
+    const int R = params->nrhs;
+    // default: 2^25 voxels, large enough that a chunk fills the GPU with
+    // several waves of boxes (each chunk's solve ends with its slowest box)
+    if (chunk_voxels <= 0) chunk_voxels = (int64_t)1 << 25;
+    // chunks: runs of consecutive boxes (in increasing offset order) whose
+    // voxel span stays within chunk_voxels; a larger box is a chunk alone
+    auto vox = [&](int64_t i) { return (int64_t)bricks[i].nx * bricks[i].ny * bricks[i].nz; };
+    std::vector<int64_t> cut{0};
+    int64_t span_max = 0, boxes_max = 0;
+    for (int64_t i = 0; i < n_bricks; ++i) {
+        if (bricks[i].nx < 1 || bricks[i].ny < 1 || bricks[i].nz < 1 || bricks[i].offset < 0 ||
+            bricks[i].offset + vox(i) > n_voxels)
+            return fail(ctx, RW_E_INVAL, "brick %lld does not fit the %lld voxels", (long long)i, (long long)n_voxels);
+        if (i > 0 && bricks[i].offset < bricks[i - 1].offset + vox(i - 1))
+            return fail(ctx, RW_E_INVAL, "streamed boxes must be in increasing offset order without overlap (brick %lld)",
+                        (long long)i);
+        const int64_t c0 = cut.back();
+        if (i > c0 && bricks[i].offset + vox(i) - bricks[c0].offset > chunk_voxels) cut.push_back(i);
+    }
+    cut.push_back(n_bricks);
+    const int64_t nc = (int64_t)cut.size() - 1;
+    for (int64_t c = 0; c < nc; ++c) {
+        const int64_t b0 = cut[c], b1 = cut[c + 1];
+        span_max = std::max(span_max, bricks[b1 - 1].offset + vox(b1 - 1) - bricks[b0].offset);
+        boxes_max = std::max(boxes_max, b1 - b0);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    DevGuard dg(ctx->device);
+    if (!ctx->cs[0]) {
+        for (int i = 0; i < 2; ++i) {
+            hipError_t e = hipStreamCreateWithFlags(&ctx->cs[i], hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(ctx, e, "creating copy streams");
+        }
+        for (hipEvent_t& ev : ctx->cev) {
+            hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(ctx, e, "creating copy events");
+        }
+        hipError_t e = hipEventCreateWithFlags(&ctx->pin_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(ctx, e, "creating copy events");
+    }
+    // page-locked box-list slots, one per chunk (a slot per BrickDev list,
+    // 256-byte aligned); an earlier call's uploads from them are waited for
+    {
+        hipError_t e = hipEventSynchronize(ctx->pin_ev);
+        const size_t want = (size_t)n_bricks * sizeof(rwk::BrickDev) + (size_t)nc * 256 + 256;
+        if (e == hipSuccess && ctx->pin_bytes < want) {
+            if (ctx->pin) e = hipHostFree(ctx->pin);
+            ctx->pin = nullptr;
+            ctx->pin_bytes = 0;
+            if (e == hipSuccess) e = hipHostMalloc(&ctx->pin, want, hipHostMallocDefault);
+            if (e == hipSuccess) ctx->pin_bytes = want;
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "allocating page-locked box lists");
+    }
+    // staging set k: g float [span], x float [span * R], stats [boxes], mask uint8 [span]
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t bg = up((size_t)span_max * 4), bx = up((size_t)span_max * R * 4),
+                 bs = up((size_t)boxes_max * sizeof(rw_brick_stats)), bm = up((size_t)span_max);
+    const size_t set = bg + bx + bs + bm;
+    // nothing of an earlier call may still use the staging sets
+    hipError_t e = hipStreamSynchronize(ctx->cs[0]);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->cs[1]);
+    if (e == hipSuccess) e = grow(ctx, &ctx->ooc, &ctx->ooc_bytes, 2 * set, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "allocating staging buffers");
+    char* base = (char*)ctx->ooc;
+    auto G = [&](int k) { return (float*)(base + k * set); };
+    auto X = [&](int k) { return (float*)(base + k * set + bg); };
+    auto S = [&](int k) { return (rw_brick_stats*)(base + k * set + bg + bx); };
+    auto M = [&](int k) { return (uint8_t*)(base + k * set + bg + bx + bs); };
+    hipEvent_t* h2d = &ctx->cev[0];     // [2] staging set k filled
+    hipEvent_t* done = &ctx->cev[2];    // [2] staging set k solved
+    hipEvent_t* d2h = &ctx->cev[4];     // [2] staging set k copied back
+    hipEvent_t start = ctx->cev[6];
+    // on a failure part-way, the copies already queued finish before returning
+    auto drain = [&](int code) {
+        (void)hipStreamSynchronize(ctx->cs[0]);
+        (void)hipStreamSynchronize(ctx->cs[1]);
+        (void)hipEventRecord(ctx->pin_ev, s);
+        return code;
+    };
+    auto span_of = [&](int64_t c, int64_t* off) {
+        *off = bricks[cut[c]].offset;
+        return bricks[cut[c + 1] - 1].offset + vox(cut[c + 1] - 1) - *off;
+    };
+    auto fill = [&](int64_t c, int k) -> hipError_t {
+        int64_t off;
+        const int64_t n = span_of(c, &off);
+        hipError_t r = hipMemcpyAsync(G(k), g + off, (size_t)n * 4, hipMemcpyHostToDevice, ctx->cs[0]);
+        if (r == hipSuccess) r = hipMemcpyAsync(M(k), mask + off, (size_t)n, hipMemcpyHostToDevice, ctx->cs[0]);
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(X(k), x + off * R, (size_t)n * R * 4, hipMemcpyHostToDevice, ctx->cs[0]);
+        if (r == hipSuccess) r = hipEventRecord(h2d[k], ctx->cs[0]);
+        return r;
+    };
+    e = hipEventRecord(start, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->cs[0], start, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->cs[1], start, 0);
+    for (int64_t c = 0; c < std::min<int64_t>(nc, 2) && e == hipSuccess; ++c) e = fill(c, (int)c);
+    if (e != hipSuccess) return drain(hip_fail(ctx, e, "queuing host-to-device copies"));
+    std::vector<rw_brick> rb;
+    char* slot = (char*)ctx->pin;
+    for (int64_t c = 0; c < nc; ++c) {
+        const int k = (int)(c & 1);
+        int64_t off;
+        const int64_t n = span_of(c, &off);
+        rb.assign(bricks + cut[c], bricks + cut[c + 1]);
+        for (rw_brick& b : rb) b.offset -= off;
+        e = hipStreamWaitEvent(s, h2d[k], 0);
+        if (e != hipSuccess) return drain(hip_fail(ctx, e, "ordering the solve after its copies"));
+        ctx->list_stage = slot;
+        rc = rw_solve_bricks(ctx, params, (int64_t)rb.size(), rb.data(), n, G(k), M(k), X(k), nullptr,
+                             stats ? S(k) : nullptr, s);
+        ctx->list_stage = nullptr;
+        slot += ((rb.size() * sizeof(rwk::BrickDev) + 255) & ~size_t(255));
+        if (rc) return drain(rc);
+        e = hipEventRecord(done[k], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ctx->cs[1], done[k], 0);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(x + off * R, X(k), (size_t)n * R * 4, hipMemcpyDeviceToHost, ctx->cs[1]);
+        if (e == hipSuccess && stats)
+            e = hipMemcpyAsync(stats + cut[c], S(k), rb.size() * sizeof(rw_brick_stats), hipMemcpyDeviceToHost,
+                               ctx->cs[1]);
+        if (e == hipSuccess) e = hipEventRecord(d2h[k], ctx->cs[1]);
+        // the set is refilled once its results are out
+        if (e == hipSuccess && c + 2 < nc) {
+            e = hipStreamWaitEvent(ctx->cs[0], d2h[k], 0);
+            if (e == hipSuccess) e = fill(c + 2, k);
+        }
+        if (e != hipSuccess) return drain(hip_fail(ctx, e, "queuing copies"));
+    }
+    e = hipStreamWaitEvent(s, d2h[(nc - 1) & 1], 0);
+    if (e == hipSuccess) e = hipEventRecord(ctx->pin_ev, s);
+    if (e != hipSuccess) return drain(hip_fail(ctx, e, "joining the copy stream"));
     return RW_OK;
 }
 

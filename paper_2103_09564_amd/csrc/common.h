@@ -36,6 +36,20 @@ struct rw_ctx {
     // start/end, resident start/end; gev_used bit 0 / bit 1 when recorded
     hipEvent_t gev[4] = {nullptr, nullptr, nullptr, nullptr};
     int gev_used = 0;
+    // solves of boxes held in host memory: two device staging sets, a
+    // host-to-device and a device-to-host copy stream (default priority)
+    // and their events
+    void* ooc = nullptr;
+    size_t ooc_bytes = 0;
+    hipStream_t cs[2] = {nullptr, nullptr};
+    hipEvent_t cev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // page-locked staging of the per-chunk box lists (so that their upload
+    // does not block the host), the slot of the current chunk, and an event
+    // after the last upload that read it
+    void* pin = nullptr;
+    size_t pin_bytes = 0;
+    void* list_stage = nullptr;
+    hipEvent_t pin_ev = nullptr;
 };
 
 namespace rwk {
