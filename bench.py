@@ -403,7 +403,7 @@ def bench_cells_growth(torch, rwg, ctx, sizes=(64, 128, 256, 512)):
 
 def bench_streamed(torch, rwg, ctx, steps=3):
     """The 8192 stress boxes held in page-locked host memory and streamed
-    through the GPU (rw_solve_bricks_streamed, default 2^25-voxel chunks), against
+    through the GPU (rw_solve_bricks_streamed, default 2^24-voxel chunks, two lanes), against
     the same solve with the boxes resident in HBM.  The PCIe-inclusive rate."""
     import numpy as np
     import synth
@@ -443,7 +443,7 @@ def bench_streamed(torch, rwg, ctx, steps=3):
     stn = rwg.stats_to_numpy(st)
     vox_it = int(np.sum(sizes * (stn["iters"].astype(np.int64) + stn["refine_iters"].astype(np.int64))))
     moved = int(sizes.sum()) * (4 + 1 + 4 + 4)   # g, mask, x in; x out
-    return {"workload": "stress boxes (8192, 113.5M voxels) in page-locked host memory, 2^25-voxel chunks, "
+    return {"workload": "stress boxes (8192, 113.5M voxels) in page-locked host memory, 2^24-voxel chunks, two lanes, "
                         "mixed precision, tol 1e-6",
             "streamed_ms_per_call": ms, "device_resident_ms_per_call": ms_dev,
             "streamed_voxel_iters_per_s": vox_it / (ms / 1e3),

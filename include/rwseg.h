@@ -161,17 +161,19 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
  * asynchronously and overlap the solves, pageable memory works but copies
  * synchronously.  The boxes must be listed in increasing offset order without
  * overlap; runs of consecutive boxes whose voxel span is at most
- * chunk_voxels (0: 2^25; a larger box forms a chunk alone) are copied into
- * one of two device staging sets on a copy stream while the previous chunk
- * is solved on `stream`, and x (and stats) are copied back on a second copy
- * stream behind each solve.  Per box the result is that of rw_solve_bricks
- * (the same kernels).  No x64 output.  The call returns once everything is
- * queued: x and stats are complete when `stream` has completed (the copy
- * streams are joined to it).  On an error part-way the queued copies finish
- * before the call returns.  The staging sets (about 2 x (9 + 4 (nrhs - 1))
- * bytes per voxel of the largest chunk) and page-locked copies of the box
- * lists stay allocated on the context.  Chunks are solved one after
- * another, each ending with its slowest box: chunks much smaller than the
+ * chunk_voxels (0: 2^24; a larger box forms a chunk alone) go round two
+ * lanes: chunk c is copied into lane c % 2's device staging set on a copy
+ * stream, solved by that lane (lane 0: ctx on `stream`; lane 1: an internal
+ * context with its own workspaces and stream), and its x
+ * (and stats) copied back on a second copy stream, so copies in, solves of
+ * consecutive chunks and copies out overlap.  Per box the result is that of
+ * rw_solve_bricks (the same kernels).  No x64 output.  The call returns
+ * once everything is queued: x and stats are complete when `stream` has
+ * completed (every other stream is joined to it).  On an error part-way the
+ * queued work finishes before the call returns.  The staging sets (about
+ * 2 x (9 + 4 (nrhs - 1)) bytes per voxel of the largest chunk), page-locked
+ * copies of the box lists and the lane context stay allocated on ctx.
+ * Each chunk's solve ends with its slowest box: chunks much smaller than the
  * default leave the GPU idle in those tails.
  * Returns RW_E_INVAL on bad descriptors (as rw_solve_bricks, plus the order).
  */

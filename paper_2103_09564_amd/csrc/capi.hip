@@ -314,6 +314,10 @@ void rw_ctx_destroy(rw_ctx* ctx) {
     if (ctx->ooc) (void)hipFree(ctx->ooc);
     if (ctx->pin) (void)hipHostFree(ctx->pin);
     if (ctx->pin_ev) (void)hipEventDestroy(ctx->pin_ev);
+    for (int i = 0; i < 2; ++i) {
+        if (ctx->tstream[i]) (void)hipStreamDestroy(ctx->tstream[i]);
+        rw_ctx_destroy(ctx->twin[i]);
+    }
     for (hipStream_t& c : ctx->cs)
         if (c) (void)hipStreamDestroy(c);
     for (hipEvent_t& e : ctx->cev)
@@ -494,6 +498,11 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
     return RW_OK;
 }
 
+// lanes of the streamed solve: context, compute stream and staging set
+// (three lanes measured slower than two: each solve forks onto two side
+// streams, and a process has four hardware queues)
+static constexpr int kLanes = 2;
+
 int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
                              int64_t n_voxels, const float* g, const uint8_t* mask, float* x,
                              rw_brick_stats* stats, int64_t chunk_voxels, void* stream) {
@@ -505,9 +514,9 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
     if (n_bricks == 0) return RW_OK;
     if (!bricks || !g || !mask || !x) return fail(ctx, RW_E_INVAL, "bricks, g, mask and x must be non-NULL");
     const int R = params->nrhs;
-    // default: 2^25 voxels, large enough that a chunk fills the GPU with
+    // default: 2^24 voxels, large enough that a chunk fills the GPU with
     // several waves of boxes (each chunk's solve ends with its slowest box)
-    if (chunk_voxels <= 0) chunk_voxels = (int64_t)1 << 25;
+    if (chunk_voxels <= 0) chunk_voxels = (int64_t)1 << 24;
     // chunks: runs of consecutive boxes (in increasing offset order) whose
     // voxel span stays within chunk_voxels; a larger box is a chunk alone
     auto vox = [&](int64_t i) { return (int64_t)bricks[i].nx * bricks[i].ny * bricks[i].nz; };
@@ -542,8 +551,15 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
             if (e != hipSuccess) return hip_fail(ctx, e, "creating copy events");
         }
         hipError_t e = hipEventCreateWithFlags(&ctx->pin_ev, hipEventDisableTiming);
+        for (int i = 0; i < kLanes - 1 && e == hipSuccess; ++i)
+            e = hipStreamCreateWithFlags(&ctx->tstream[i], hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(ctx, e, "creating copy events");
     }
+    for (int i = 0; i < kLanes - 1; ++i)
+        if (!ctx->twin[i]) {
+            rc = rw_ctx_create(ctx->device, &ctx->twin[i]);
+            if (rc) return fail(ctx, rc, "creating a lane's solve context: %s", rw_last_error(nullptr));
+        }
     // page-locked box-list slots, one per chunk (a slot per BrickDev list,
     // 256-byte aligned); an earlier call's uploads from them are waited for
     {
@@ -566,21 +582,23 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
     // nothing of an earlier call may still use the staging sets
     hipError_t e = hipStreamSynchronize(ctx->cs[0]);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->cs[1]);
-    if (e == hipSuccess) e = grow(ctx, &ctx->ooc, &ctx->ooc_bytes, 2 * set, s);
+    if (e == hipSuccess) e = grow(ctx, &ctx->ooc, &ctx->ooc_bytes, kLanes * set, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating staging buffers");
     char* base = (char*)ctx->ooc;
     auto G = [&](int k) { return (float*)(base + k * set); };
     auto X = [&](int k) { return (float*)(base + k * set + bg); };
     auto S = [&](int k) { return (rw_brick_stats*)(base + k * set + bg + bx); };
     auto M = [&](int k) { return (uint8_t*)(base + k * set + bg + bx + bs); };
-    hipEvent_t* h2d = &ctx->cev[0];     // [2] staging set k filled
-    hipEvent_t* done = &ctx->cev[2];    // [2] staging set k solved
-    hipEvent_t* d2h = &ctx->cev[4];     // [2] staging set k copied back
-    hipEvent_t start = ctx->cev[6];
+    hipEvent_t* h2d = &ctx->cev[0];     // [kLanes] staging set k filled
+    hipEvent_t* done = &ctx->cev[3];    // [kLanes] staging set k solved
+    hipEvent_t* d2h = &ctx->cev[6];     // [kLanes] staging set k copied back
+    hipEvent_t start = ctx->cev[9];
     // on a failure part-way, the copies already queued finish before returning
     auto drain = [&](int code) {
         (void)hipStreamSynchronize(ctx->cs[0]);
         (void)hipStreamSynchronize(ctx->cs[1]);
+        for (hipStream_t t : ctx->tstream)
+            if (t) (void)hipStreamSynchronize(t);
         (void)hipEventRecord(ctx->pin_ev, s);
         return code;
     };
@@ -598,28 +616,40 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
         if (r == hipSuccess) r = hipEventRecord(h2d[k], ctx->cs[0]);
         return r;
     };
+    // chunk c is solved by lane c % kLanes: its context, its stream (lane
+    // 0: the caller's context and stream) and its staging set
+    rw_ctx* C[kLanes] = {ctx};
+    hipStream_t SS[kLanes] = {s};
+    for (int i = 1; i < kLanes; ++i) {
+        C[i] = ctx->twin[i - 1];
+        SS[i] = ctx->tstream[i - 1];
+    }
     e = hipEventRecord(start, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->cs[0], start, 0);
-    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->cs[1], start, 0);
-    for (int64_t c = 0; c < std::min<int64_t>(nc, 2) && e == hipSuccess; ++c) e = fill(c, (int)c);
+    for (hipStream_t t : {ctx->cs[0], ctx->cs[1]})
+        if (e == hipSuccess) e = hipStreamWaitEvent(t, start, 0);
+    for (int i = 1; i < kLanes && e == hipSuccess; ++i) e = hipStreamWaitEvent(SS[i], start, 0);
+    for (int64_t c = 0; c < std::min<int64_t>(nc, kLanes) && e == hipSuccess; ++c) e = fill(c, (int)c);
     if (e != hipSuccess) return drain(hip_fail(ctx, e, "queuing host-to-device copies"));
     std::vector<rw_brick> rb;
     char* slot = (char*)ctx->pin;
     for (int64_t c = 0; c < nc; ++c) {
-        const int k = (int)(c & 1);
+        const int k = (int)(c % kLanes);
         int64_t off;
         const int64_t n = span_of(c, &off);
         rb.assign(bricks + cut[c], bricks + cut[c + 1]);
         for (rw_brick& b : rb) b.offset -= off;
-        e = hipStreamWaitEvent(s, h2d[k], 0);
+        e = hipStreamWaitEvent(SS[k], h2d[k], 0);
         if (e != hipSuccess) return drain(hip_fail(ctx, e, "ordering the solve after its copies"));
-        ctx->list_stage = slot;
-        rc = rw_solve_bricks(ctx, params, (int64_t)rb.size(), rb.data(), n, G(k), M(k), X(k), nullptr,
-                             stats ? S(k) : nullptr, s);
-        ctx->list_stage = nullptr;
+        C[k]->list_stage = slot;
+        rc = rw_solve_bricks(C[k], params, (int64_t)rb.size(), rb.data(), n, G(k), M(k), X(k), nullptr,
+                             stats ? S(k) : nullptr, SS[k]);
+        C[k]->list_stage = nullptr;
         slot += ((rb.size() * sizeof(rwk::BrickDev) + 255) & ~size_t(255));
-        if (rc) return drain(rc);
-        e = hipEventRecord(done[k], s);
+        if (rc) {
+            if (k) ctx->err = C[k]->err;
+            return drain(rc);
+        }
+        e = hipEventRecord(done[k], SS[k]);
         if (e == hipSuccess) e = hipStreamWaitEvent(ctx->cs[1], done[k], 0);
         if (e == hipSuccess)
             e = hipMemcpyAsync(x + off * R, X(k), (size_t)n * R * 4, hipMemcpyDeviceToHost, ctx->cs[1]);
@@ -628,13 +658,13 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
                                ctx->cs[1]);
         if (e == hipSuccess) e = hipEventRecord(d2h[k], ctx->cs[1]);
         // the set is refilled once its results are out
-        if (e == hipSuccess && c + 2 < nc) {
+        if (e == hipSuccess && c + kLanes < nc) {
             e = hipStreamWaitEvent(ctx->cs[0], d2h[k], 0);
-            if (e == hipSuccess) e = fill(c + 2, k);
+            if (e == hipSuccess) e = fill(c + kLanes, k);
         }
         if (e != hipSuccess) return drain(hip_fail(ctx, e, "queuing copies"));
     }
-    e = hipStreamWaitEvent(s, d2h[(nc - 1) & 1], 0);
+    e = hipStreamWaitEvent(s, d2h[(nc - 1) % kLanes], 0);
     if (e == hipSuccess) e = hipEventRecord(ctx->pin_ev, s);
     if (e != hipSuccess) return drain(hip_fail(ctx, e, "joining the copy stream"));
     return RW_OK;

@@ -42,7 +42,7 @@ struct rw_ctx {
     void* ooc = nullptr;
     size_t ooc_bytes = 0;
     hipStream_t cs[2] = {nullptr, nullptr};
-    hipEvent_t cev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t cev[10] = {};   // per lane: filled, solved, copied back (3 x 3); start
     // page-locked staging of the per-chunk box lists (so that their upload
     // does not block the host), the slot of the current chunk, and an event
     // after the last upload that read it
@@ -50,6 +50,11 @@ struct rw_ctx {
     size_t pin_bytes = 0;
     void* list_stage = nullptr;
     hipEvent_t pin_ev = nullptr;
+    // contexts with their own workspaces and compute streams (default
+    // priority) for the streamed solve's lanes beyond the first, so that
+    // consecutive chunks overlap on the GPU (up to three lanes)
+    rw_ctx* twin[2] = {nullptr, nullptr};
+    hipStream_t tstream[2] = {nullptr, nullptr};
 };
 
 namespace rwk {
