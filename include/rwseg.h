@@ -166,8 +166,11 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
  * stream, solved by that lane (lane 0: ctx on `stream`; lane 1: an internal
  * context with its own workspaces and stream), and its x
  * (and stats) copied back on a second copy stream, so copies in, solves of
- * consecutive chunks and copies out overlap.  Per box the result is that of
- * rw_solve_bricks (the same kernels).  No x64 output.  The call returns
+ * consecutive chunks and copies out overlap.  Every chunk takes the kernel
+ * variants the whole list would get, so per box the result is bit-identical
+ * to rw_solve_bricks on the whole list, except where that call would leave
+ * single-domain boxes beyond its cap of 16 to the window kernels (a chunk may
+ * then run them on the domain solver: equal up to rounding).  No x64 output.  The call returns
  * once everything is queued: x and stats are complete when `stream` has
  * completed (every other stream is joined to it).  On an error part-way the
  * queued work finishes before the call returns.  The staging sets (about

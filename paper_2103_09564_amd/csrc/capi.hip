@@ -122,46 +122,63 @@ int build_list(rw_ctx* ctx, int64_t n, const rw_brick* bricks, int64_t n_voxels,
 // The few largest boxes (single domains) go to the multi-workgroup solver in
 // front of the list; boxes that fit in one CU's LDS (one rhs, FP32, streaming
 // schedule not forced) go to the resident kernel at the end.
+// Window columns of a batch: from its widest plane that the window holds.
+int plan_cols_of(const rw_ctx* ctx, const rw_brick* b, int64_t n, int nrhs, bool fp64) {
+    int widest = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (b[i].nx * b[i].ny <= rwk::plane_max(4)) widest = std::max(widest, b[i].nx * b[i].ny);
+    int cols = rwk::plane_cols(widest);
+    if (rwk::plane_lds_bytes(nrhs, fp64, cols) > ctx->lds_limit) cols = 2;
+    return cols;
+}
+
+// Kernel group of one box (the domain cap aside): 0 domain solver, 1 global
+// march, 2 plane march, 3 and 4 resident (p in LDS, weights streamed) above
+// and up to kResSpanG0 voxels, 5 resident (weights in LDS), 6 the same for
+// small boxes.
+int group_of(const rw_ctx* ctx, int nx, int ny, int nz, int lim, bool res_ok, bool prefer_g, bool dom_left) {
+    rwk::BrickDev b{};
+    b.nx = nx;
+    b.ny = ny;
+    b.nz = nz;
+    const int64_t nxy = (int64_t)nx * ny, vox = nxy * nz;
+    const bool wide = nxy > lim;
+    // (the domain kernels index voxels with 32-bit integers)
+    const bool dom = vox < (int64_t(1) << 31) && (vox >= rwk::kDomBigVox || (wide && vox >= rwk::kDomMinVox));
+    if (dom && dom_left) return 0;
+    if (res_ok && prefer_g && rwk::resident_g_fits(b, ctx->lds_limit)) return vox > rwk::kResSpanG0 ? 3 : 4;
+    if (res_ok && rwk::resident_w_fits(b, ctx->lds_limit)) return vox <= rwk::kResSmallVox ? 6 : 5;
+    if (res_ok && rwk::resident_g_fits(b, ctx->lds_limit)) return vox > rwk::kResSpanG0 ? 3 : 4;
+    return wide ? 1 : 2;
+}
+
+bool resident_ok(int nrhs, bool fp64, int schedule) {
+    return nrhs == 1 && !fp64 && (schedule == 0 || schedule == 3 || schedule == 4);
+}
+
 rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, int nrhs, bool fp64,
                            int schedule) {
     const int64_t n = (int64_t)list->size();
     rwk::PlanePlan pp{};
     pp.cols = 2;
     pp.n_big = pp.n_res = n;
-    const bool res_ok = nrhs == 1 && !fp64 && (schedule == 0 || schedule == 3 || schedule == 4);
+    const bool res_ok = resident_ok(nrhs, fp64, schedule);
     const bool prefer_g = schedule == 4;
-    const int64_t res_small = rwk::kResSmallVox;
-    int widest = 0;
-    for (const auto& b : *list)
-        if (b.nx * b.ny <= rwk::plane_max(4)) widest = std::max(widest, b.nx * b.ny);
-    int cols = rwk::plane_cols(widest);
-    if (rwk::plane_lds_bytes(nrhs, fp64, cols) > ctx->lds_limit) cols = 2;
+    int cols = ctx->plan_cols;
+    if (cols == 0) {
+        std::vector<rw_brick> hb(list->size());
+        for (size_t i = 0; i < list->size(); ++i) hb[i] = rw_brick{(*list)[i].nx, (*list)[i].ny, (*list)[i].nz, 0, 0};
+        cols = plan_cols_of(ctx, hb.data(), n, nrhs, fp64);
+    }
     const bool use = rwk::plane_lds_bytes(nrhs, fp64, cols) <= ctx->lds_limit;
     const int lim = use ? rwk::plane_max(cols) : 0;
-    // group 0: domain solver, 1: global march, 2: plane march, 3 and 4:
-    // resident (p in LDS, weights streamed) above and up to kResSpanG0
-    // voxels, 5: resident (weights in LDS), 6: the same for small boxes;
     // the list is largest-first
     std::vector<uint8_t> grp(list->size());
     int n_dom = 0;
     for (size_t i = 0; i < list->size(); ++i) {
         const rwk::BrickDev& b = (*list)[i];
-        const int64_t nxy = (int64_t)b.nx * b.ny, vox = nxy * b.nz;
-        const bool wide = nxy > lim;
-        // (the domain kernels index voxels with 32-bit integers)
-        const bool dom = vox < (int64_t(1) << 31) && (vox >= rwk::kDomBigVox || (wide && vox >= rwk::kDomMinVox));
-        if (dom && n_dom < rwk::kDomMaxBoxes) {
-            grp[i] = 0;
-            ++n_dom;
-        } else if (res_ok && prefer_g && rwk::resident_g_fits(b, ctx->lds_limit)) {
-            grp[i] = vox > rwk::kResSpanG0 ? 3 : 4;
-        } else if (res_ok && rwk::resident_w_fits(b, ctx->lds_limit)) {
-            grp[i] = vox <= res_small ? 6 : 5;
-        } else if (res_ok && rwk::resident_g_fits(b, ctx->lds_limit)) {
-            grp[i] = vox > rwk::kResSpanG0 ? 3 : 4;
-        } else {
-            grp[i] = wide ? 1 : 2;
-        }
+        grp[i] = (uint8_t)group_of(ctx, b.nx, b.ny, b.nz, lim, res_ok, prefer_g, n_dom < rwk::kDomMaxBoxes);
+        if (grp[i] == 0) ++n_dom;
     }
     std::vector<size_t> idx(list->size());
     std::iota(idx.begin(), idx.end(), size_t(0));
@@ -206,7 +223,7 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
         }
         b0 = L.b1;
     }
-    pp.plane_aligned = 1;
+    pp.plane_aligned = ctx->plan_unaligned ? 0 : 1;
     for (int64_t i = pp.n_big; i < pp.n_res; ++i) {
         const auto& b = (*list)[(size_t)i];
         if ((int64_t)rwk::plane_max(cols) % ((int64_t)b.nx * b.ny) != 0) pp.plane_aligned = 0;
@@ -595,6 +612,8 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
     hipEvent_t start = ctx->cev[9];
     // on a failure part-way, the copies already queued finish before returning
     auto drain = [&](int code) {
+        for (rw_ctx* c : {ctx, ctx->twin[0], ctx->twin[1]})
+            if (c) c->plan_cols = c->plan_unaligned = 0;
         (void)hipStreamSynchronize(ctx->cs[0]);
         (void)hipStreamSynchronize(ctx->cs[1]);
         for (hipStream_t t : ctx->tstream)
@@ -624,6 +643,26 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
         C[i] = ctx->twin[i - 1];
         SS[i] = ctx->tstream[i - 1];
     }
+    // every chunk takes the window columns and plane-march variant of the
+    // whole list, so that each box runs the kernel it runs in one call
+    {
+        const bool fp64 = params->precision == RW_PREC_FP64;
+        const int cols = plan_cols_of(ctx, bricks, n_bricks, R, fp64);
+        const int lim = rwk::plane_lds_bytes(R, fp64, cols) <= ctx->lds_limit ? rwk::plane_max(cols) : 0;
+        const bool res_ok = resident_ok(R, fp64, params->schedule);
+        int unaligned = 0;
+        for (int64_t i = 0; i < n_bricks; ++i)
+            if (group_of(ctx, bricks[i].nx, bricks[i].ny, bricks[i].nz, lim, res_ok, params->schedule == 4, false) == 2 &&
+                (int64_t)rwk::plane_max(cols) % ((int64_t)bricks[i].nx * bricks[i].ny) != 0)
+                unaligned = 1;
+        for (rw_ctx* c : C) {
+            c->plan_cols = cols;
+            c->plan_unaligned = unaligned;
+        }
+    }
+    auto unplan = [&] {
+        for (rw_ctx* c : C) c->plan_cols = c->plan_unaligned = 0;
+    };
     e = hipEventRecord(start, s);
     for (hipStream_t t : {ctx->cs[0], ctx->cs[1]})
         if (e == hipSuccess) e = hipStreamWaitEvent(t, start, 0);
@@ -664,6 +703,7 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
         }
         if (e != hipSuccess) return drain(hip_fail(ctx, e, "queuing copies"));
     }
+    unplan();
     e = hipStreamWaitEvent(s, d2h[(nc - 1) % kLanes], 0);
     if (e == hipSuccess) e = hipEventRecord(ctx->pin_ev, s);
     if (e != hipSuccess) return drain(hip_fail(ctx, e, "joining the copy stream"));

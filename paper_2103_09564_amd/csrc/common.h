@@ -55,6 +55,11 @@ struct rw_ctx {
     // consecutive chunks overlap on the GPU (up to three lanes)
     rw_ctx* twin[2] = {nullptr, nullptr};
     hipStream_t tstream[2] = {nullptr, nullptr};
+    // plan choices fixed by the streamed solve for every chunk, as the whole
+    // box list would make them: window columns (0: from the batch) and the
+    // unaligned plane-march variant
+    int plan_cols = 0;
+    int plan_unaligned = 0;
 };
 
 namespace rwk {

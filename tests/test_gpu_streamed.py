@@ -74,3 +74,26 @@ def test_streamed_argument_errors(env):
         rwg.solve_bricks_streamed(g[:10], m[:10], x[:10], shapes, d["offsets"][:2], **KW)
     # no boxes: nothing happens
     rwg.solve_bricks_streamed(g, m, x, shapes[:0], d["offsets"][:0], **KW)
+
+
+def test_streamed_three_rhs_and_fp64(env):
+    """x interleaved [voxel][3] (the copies scale with nrhs) and the plain FP64
+    path: still bit-identical to the device-resident solve."""
+    torch, rwg, _, _, _ = env
+    rng = np.random.default_rng(31)
+    boxes = [synth.random_box(rng, s, dirichlet_frac=0.05) for s in [(9, 8, 7), (16, 5, 3), (20, 20, 20), (12, 30, 6)]]
+    d = synth.from_boxes(boxes)
+    R = 3
+    xs = [np.where(d["mask"] != 0, rng.random(d["x"].size), 0.0).astype(np.float32) for _ in range(R)]
+    x3 = np.stack(xs, axis=1).ravel()
+    for kw in (dict(precision=rwg.PREC_MIXED, nrhs=R), dict(precision=rwg.PREC_FP64, nrhs=R)):
+        print(f"streamed solve, 4 random boxes, {kw}", flush=True)
+        xd = torch.from_numpy(x3.copy()).cuda()
+        rwg.solve_bricks(torch.from_numpy(d["g"]).cuda(), torch.from_numpy(d["mask"]).cuda(), xd,
+                         d["shapes"], d["offsets"], beta=128.0, eps=1e-6, tol=1e-7, **kw)
+        torch.cuda.synchronize()
+        xh = torch.from_numpy(x3.copy()).pin_memory()
+        rwg.solve_bricks_streamed(torch.from_numpy(d["g"]).pin_memory(), torch.from_numpy(d["mask"]).pin_memory(),
+                                  xh, d["shapes"], d["offsets"], chunk_voxels=3000, beta=128.0, eps=1e-6,
+                                  tol=1e-7, **kw)
+        assert torch.equal(xh, xd.cpu())
