@@ -224,6 +224,27 @@ def test_incremental_node_rule_matches_oracle(env, binary_case, extra, warm):
         assert rinc.stats()["voxel_iters"] != rcold.stats()["voxel_iters"]   # the warm start took effect
 
 
+def test_incremental_node_rule_multiclass(env):
+    """The node rule with three classes (two right-hand sides): the
+    similarity test takes the max over both classes' maps."""
+    torch, rwg, ctx = env
+    n, levels, K = 32, 2, 3
+    vol = _sphere_volume(n, "f32", seed=5)
+    seeds = _seeds(n, np.random.default_rng(6), n_classes=K)
+    kw = dict(brick=8, beta=64.0, n_classes=K, prune_dt=0, t_hom=0.3, precision=0, tol=1e-12)
+    p = _oracle_params(levels=levels, brick=8, beta=64.0, n_classes=K, prune_dt=False, t_hom=0.3)
+    ores = H.segment(vol, seeds, p)
+    pyr, res, _, _ = _gpu_run(env, vol, seeds, levels, **kw)
+    more = np.concatenate([seeds, [[30.0, 30.0, 30.0, 0]]])   # keeps 39 + 2 nodes, solves 48 + 8
+    oinc = H.segment(vol, more, H.Params(**{**p.__dict__, "inc_rule": "node"}), prev=ores)
+    assert oinc.reused[0].any() and oinc.reused[1].any()
+    _, _, gmaps, gflags = _gpu_run(env, vol, more, levels, prev=res, pyr=pyr, incremental=rwg.INC_NODE, **kw)
+    _compare(oinc.maps, oinc, gmaps, gflags, 1e-6, exact_flags=True)
+    for l in range(levels):
+        assert np.array_equal((gflags[l] & rwg.F_SOLVED) != 0, oinc.recomputed[l]), f"level {l}: solved bricks differ"
+        assert np.array_equal((gflags[l] & rwg.F_KEPT) != 0, oinc.reused[l]), f"level {l}: kept bricks differ"
+
+
 def test_single_level_is_plain_solve(env):
     torch, rwg, ctx = env
     vol = _sphere_volume(24, "f32", seed=7)
