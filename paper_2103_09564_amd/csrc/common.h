@@ -122,6 +122,8 @@ struct SolveArgs {
     double* dom_part;      // its per-workgroup partial sums
     float* wts;            // streamed-weights resident kernel: per-box weight segments
     int32_t fused_init;    // main solve: the resident kernels compute their boxes' start state
+    int32_t early_check;   // main solve: 1 + may_refine: each kernel group's boxes get their first
+                           // true-residual check on the group's stream as soon as the group ends
 };
 
 struct AdjointArgs {

@@ -1594,6 +1594,19 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
                                        pp.rl[i].px, xt, corr, s_str));
     }
     if (tev && on_a) RW_TRY(hipEventRecord(tev[1], s_str));
+    // first true-residual check of a group's boxes, on its stream, while the
+    // other group may still run (the check phase skips them afterwards)
+    const bool early = kRes && corr == 0 && a.early_check > 0;
+    auto check_range = [&](int64_t b0, int64_t b1, hipStream_t st) {
+        if (b1 > b0)
+            hipLaunchKernelGGL((k_check<1, false>), dim3((unsigned)(b1 - b0)), dim3(kThreads), 0, st, a,
+                               a.early_check - 1, (int)b0);
+    };
+    if (early) {
+        check_range(pp.n_dom, n_stream_end, s_str);
+        for (int i = 0; i < pp.n_rl; ++i)
+            if (pp.rl[i].kind == 2) check_range(pp.rl[i].b0, pp.rl[i].b1, s_str);
+    }
     if constexpr (kRes) {
         if (tev && any_lds) RW_TRY(hipEventRecord(tev[2], s_res));
         for (int i = 0; i < pp.n_rl; ++i)
@@ -1601,6 +1614,9 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
                 RW_TRY(launch_resident(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_voxels, pp.rl[i].max_plane,
                                        pp.rl[i].kind, pp.rl[i].px, xt, corr, s_res));
         if (tev && any_lds) RW_TRY(hipEventRecord(tev[3], s_res));
+        if (early)
+            for (int i = 0; i < pp.n_rl; ++i)
+                if (pp.rl[i].kind != 2) check_range(pp.rl[i].b0, pp.rl[i].b1, s_res);
     }
     if (fork) {
         RW_TRY(hipEventRecord(pp.join[0], s_str));
@@ -1635,6 +1651,9 @@ static hipError_t launch_mixed(const SolveArgs& a, int64_t n, const PlanePlan& p
     if (ev) RW_TRY(hipEventRecord(ev[0], s));
     SolveArgs am = a;
     am.fused_init = 1;
+    // one rhs, FP32 x checked: each kernel group's boxes are checked as soon
+    // as the group ends (the check below then skips them)
+    am.early_check = R == 1 && !r64 ? 1 + (a.refine_max > 0 ? 1 : 0) : 0;
     RW_TRY(launch_pcg_c<float, R, float>(am, n, a.x, 0, pp, s));
     if (ev) RW_TRY(hipEventRecord(ev[1], s));
     if (r64) {
