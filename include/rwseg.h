@@ -195,12 +195,15 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
  * resident boxes, and the boxes resident in LDS; stream_ms and resident_ms
  * are the durations of the two groups (0 for an empty group).  In a one-rhs
  * MIXED or MIXED_REFINE solve the resident kernels compute their boxes'
- * start state themselves, inside pcg_ms; init_ms covers the other boxes.
+ * start state themselves, inside pcg_ms; init_ms covers the other boxes.  In
+ * a one-rhs MIXED solve each group's first FP64 check runs on its stream
+ * right after the group, so it falls in pcg_ms (not in stream_ms or
+ * resident_ms) and finish_ms keeps the rest of the check phase.
  */
 typedef struct rw_timing {
     float init_ms;           /* Dirichlet init (r = -(L x)_U, z, p) of the non-resident boxes */
     float pcg_ms;            /* main PCG phase */
-    float finish_ms;         /* FP64 true residual, refinement, stats */
+    float finish_ms;         /* FP64 true residual (when not done in pcg_ms), refinement, stats */
     float total_ms;
     float stream_ms;         /* main PCG: RW_PATH_STREAM* then RW_PATH_RESIDENT_STREAMED boxes */
     float resident_ms;       /* main PCG: RW_PATH_RESIDENT boxes */
