@@ -193,7 +193,10 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
  * that phase two groups of kernels run concurrently on two streams (see
  * rw_solve_plan): the streaming boxes followed by the streamed-weights
  * resident boxes, and the boxes resident in LDS; stream_ms and resident_ms
- * are the durations of the two groups (0 for an empty group).  In a one-rhs
+ * are the durations of the two groups (0 for an empty group).  When the
+ * streamed-weights boxes form two launches beside LDS-resident ones (and no
+ * box streams), the second launch runs on a third stream, concurrently with
+ * the first: stream_ms then times the first launch and stream2_ms the second.  In a one-rhs
  * MIXED or MIXED_REFINE solve the resident kernels compute their boxes'
  * start state themselves, inside pcg_ms; init_ms covers the other boxes.  In
  * a one-rhs MIXED solve each group's first FP64 check runs on its stream
@@ -205,8 +208,11 @@ typedef struct rw_timing {
     float pcg_ms;            /* main PCG phase */
     float finish_ms;         /* FP64 true residual (when not done in pcg_ms), refinement, stats */
     float total_ms;
-    float stream_ms;         /* main PCG: RW_PATH_STREAM* then RW_PATH_RESIDENT_STREAMED boxes */
+    float stream_ms;         /* main PCG: RW_PATH_STREAM* then RW_PATH_RESIDENT_STREAMED boxes
+                                (only the first of two streamed-weights launches when stream2_ms > 0) */
     float resident_ms;       /* main PCG: RW_PATH_RESIDENT boxes */
+    float stream2_ms;        /* main PCG: the second streamed-weights launch (boxes up to 17408 voxels)
+                                when it runs on a stream of its own beside the first, else 0 */
 } rw_timing;
 int rw_set_timing(rw_ctx* ctx, int enable);
 int rw_last_timing(rw_ctx* ctx, rw_timing* out);

@@ -65,7 +65,8 @@ lib.rw_validate_solve.restype = ctypes.c_int
 
 class Timing(ctypes.Structure):
     _fields_ = [("init_ms", ctypes.c_float), ("pcg_ms", ctypes.c_float), ("finish_ms", ctypes.c_float),
-                ("total_ms", ctypes.c_float), ("stream_ms", ctypes.c_float), ("resident_ms", ctypes.c_float)]
+                ("total_ms", ctypes.c_float), ("stream_ms", ctypes.c_float), ("resident_ms", ctypes.c_float),
+                ("stream2_ms", ctypes.c_float)]
 
 
 lib.rw_set_timing.argtypes = [_vp, ctypes.c_int]

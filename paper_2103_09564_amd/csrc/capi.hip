@@ -235,7 +235,7 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
 // Side streams and events for concurrent kernel groups (created once).
 int attach_side_streams(rw_ctx* ctx, rwk::PlanePlan* pp) {
     if (!ctx->side[0]) {
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < 3; ++i) {
             hipError_t e = hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join[i], hipEventDisableTiming);
             if (e != hipSuccess) return hip_fail(ctx, e, "creating side streams");
@@ -245,9 +245,14 @@ int attach_side_streams(rw_ctx* ctx, rwk::PlanePlan* pp) {
     }
     pp->side[0] = ctx->side[0];
     pp->side[1] = ctx->side[1];
+    pp->side[2] = ctx->side[2];
+    int n_g = 0, n_w = 0;
+    for (int i = 0; i < pp->n_rl; ++i) (pp->rl[i].kind == 2 ? n_g : n_w) += 1;
+    pp->third = n_g == 2 && n_w > 0 && pp->n_res == pp->n_dom ? 1 : 0;
     pp->fork = ctx->fork;
     pp->join[0] = ctx->join[0];
     pp->join[1] = ctx->join[1];
+    pp->join[2] = ctx->join[2];
     return RW_OK;
 }
 
@@ -339,11 +344,11 @@ void rw_ctx_destroy(rw_ctx* ctx) {
         if (c) (void)hipStreamDestroy(c);
     for (hipEvent_t& e : ctx->cev)
         if (e) (void)hipEventDestroy(e);
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 4; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    for (int i = 0; i < 6; ++i)
         if (ctx->gev[i]) (void)hipEventDestroy(ctx->gev[i]);
-    }
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 3; ++i) {
         if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
         if (ctx->join[i]) (void)hipEventDestroy(ctx->join[i]);
     }
@@ -372,11 +377,10 @@ int rw_last_timing(rw_ctx* ctx, rw_timing* out) {
     out->pcg_ms = t[1];
     out->finish_ms = t[2];
     out->total_ms = t[0] + t[1] + t[2];
-    out->stream_ms = out->resident_ms = 0.0f;
-    for (int gidx = 0; gidx < 2 && e == hipSuccess; ++gidx)
-        if (ctx->gev_used & (1 << gidx))
-            e = hipEventElapsedTime(gidx ? &out->resident_ms : &out->stream_ms, ctx->gev[2 * gidx],
-                                    ctx->gev[2 * gidx + 1]);
+    out->stream_ms = out->resident_ms = out->stream2_ms = 0.0f;
+    float* dst[3] = {&out->stream_ms, &out->resident_ms, &out->stream2_ms};
+    for (int gidx = 0; gidx < 3 && e == hipSuccess; ++gidx)
+        if (ctx->gev_used & (1 << gidx)) e = hipEventElapsedTime(dst[gidx], ctx->gev[2 * gidx], ctx->gev[2 * gidx + 1]);
     if (e != hipSuccess) return hip_fail(ctx, e, "reading timing events");
     return RW_OK;
 }
@@ -489,7 +493,7 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
                 e = hipEventCreate(&ctx->ev[i]);
                 if (e != hipSuccess) return hip_fail(ctx, e, "creating timing events");
             }
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 6; ++i)
             if (!ctx->gev[i]) {
                 e = hipEventCreate(&ctx->gev[i]);
                 if (e != hipSuccess) return hip_fail(ctx, e, "creating timing events");
@@ -503,7 +507,8 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
         bool any_g = false, any_lds = false;
         for (int i = 0; i < pp.n_rl; ++i) (pp.rl[i].kind == 2 ? any_g : any_lds) = true;
         const bool res_path = R == 1 && !fp64;
-        ctx->gev_used = (pp.n_res > pp.n_dom || (res_path && any_g) ? 1 : 0) | (res_path && any_lds ? 2 : 0);
+        ctx->gev_used = (pp.n_res > pp.n_dom || (res_path && any_g) ? 1 : 0) | (res_path && any_lds ? 2 : 0) |
+                        (res_path && pp.third ? 4 : 0);
     }
     e = rwk::launch_solve(a, n_bricks, R, fp64, pp, s, ev);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching solve kernel");

@@ -29,12 +29,12 @@ struct rw_ctx {
     int ev_valid = 0;
     // two side streams (default priority) that run the streaming and the
     // LDS-resident PCG kernels of one call concurrently, and their events
-    hipStream_t side[2] = {nullptr, nullptr};
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr;
-    hipEvent_t join[2] = {nullptr, nullptr};
+    hipEvent_t join[3] = {nullptr, nullptr, nullptr};
     // timing of the two kernel groups of the main PCG phase: streaming
     // start/end, resident start/end; gev_used bit 0 / bit 1 when recorded
-    hipEvent_t gev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t gev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int gev_used = 0;
     // solves of boxes held in host memory: two device staging sets, a
     // host-to-device and a device-to-host copy stream (default priority)
@@ -174,10 +174,13 @@ struct PlanePlan {
     int64_t wts_elems;        // floats of weight segments the kind-2 boxes need (BrickDev::woff)
     // when set, the streaming and resident groups run on these two streams
     // (forked from and joined back into the caller's stream)
-    hipStream_t side[2];
-    hipEvent_t fork, join[2];
+    hipStream_t side[3];
+    hipEvent_t fork, join[3];
+    // the second streamed-weights launch runs on side[2] (two such launches,
+    // weights-in-LDS launches beside them, no streaming boxes)
+    int third;
     // main-solve group timing events (start/end streaming, start/end
-    // resident) or null
+    // resident, start/end of the launch on side[2]) or null
     hipEvent_t* gev;
 };
 

@@ -1566,12 +1566,21 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
     const bool on_a = any_str || any_g;
     const bool fork = on_a && any_lds && pp.side[0] != nullptr;
     hipStream_t s_str = s, s_res = s;
+    // a second streamed-weights launch (the boxes up to 17408 voxels) runs on
+    // a third stream, so that it need not wait for the first one's tail
+    const bool third = kRes && fork && pp.third && pp.side[2] != nullptr;
+    hipStream_t s_g2 = s;
     if (fork) {
         RW_TRY(hipEventRecord(pp.fork, s));
         RW_TRY(hipStreamWaitEvent(pp.side[0], pp.fork, 0));
         RW_TRY(hipStreamWaitEvent(pp.side[1], pp.fork, 0));
         s_str = pp.side[0];
         s_res = pp.side[1];
+        s_g2 = s_str;
+        if (third) {
+            RW_TRY(hipStreamWaitEvent(pp.side[2], pp.fork, 0));
+            s_g2 = pp.side[2];
+        }
     }
     hipEvent_t* tev = corr == 0 ? pp.gev : nullptr;
     if (tev && on_a) RW_TRY(hipEventRecord(tev[0], s_str));
@@ -1588,12 +1597,22 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
                            (int)n_big);
     }
     if constexpr (kRes) {
+        int k = 0;
         for (int i = 0; i < pp.n_rl; ++i)
-            if (pp.rl[i].kind == 2)
+            if (pp.rl[i].kind == 2) {
+                const bool second = third && k++ == 1;   // on the third stream, timed on its own
+                if (second && tev) RW_TRY(hipEventRecord(tev[4], s_g2));
                 RW_TRY(launch_resident(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_voxels, pp.rl[i].max_plane, 2,
-                                       pp.rl[i].px, xt, corr, s_str));
+                                       pp.rl[i].px, xt, corr, second ? s_g2 : s_str));
+                if (second && tev) RW_TRY(hipEventRecord(tev[5], s_g2));
+            }
     }
     if (tev && on_a) RW_TRY(hipEventRecord(tev[1], s_str));
+    if (third) {
+        // the stream group ends when both launches have
+        RW_TRY(hipEventRecord(pp.join[2], s_g2));
+        RW_TRY(hipStreamWaitEvent(s_str, pp.join[2], 0));
+    }
     // first true-residual check of a group's boxes, on its stream, while the
     // other group may still run (the check phase skips them afterwards)
     const bool early = kRes && corr == 0 && a.early_check > 0;
