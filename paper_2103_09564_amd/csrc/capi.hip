@@ -248,7 +248,7 @@ int attach_side_streams(rw_ctx* ctx, rwk::PlanePlan* pp) {
     pp->side[2] = ctx->side[2];
     int n_g = 0, n_w = 0;
     for (int i = 0; i < pp->n_rl; ++i) (pp->rl[i].kind == 2 ? n_g : n_w) += 1;
-    pp->third = n_g == 2 && n_w > 0 && pp->n_res == pp->n_dom ? 1 : 0;
+    pp->third = n_g == 2 && n_w > 0 && pp->n_res == pp->n_dom && !ctx->plan_no_third ? 1 : 0;
     pp->fork = ctx->fork;
     pp->join[0] = ctx->join[0];
     pp->join[1] = ctx->join[1];
@@ -618,7 +618,7 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
     // on a failure part-way, the copies already queued finish before returning
     auto drain = [&](int code) {
         for (rw_ctx* c : {ctx, ctx->twin[0], ctx->twin[1]})
-            if (c) c->plan_cols = c->plan_unaligned = 0;
+            if (c) c->plan_cols = c->plan_unaligned = c->plan_no_third = 0;
         (void)hipStreamSynchronize(ctx->cs[0]);
         (void)hipStreamSynchronize(ctx->cs[1]);
         for (hipStream_t t : ctx->tstream)
@@ -663,10 +663,11 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
         for (rw_ctx* c : C) {
             c->plan_cols = cols;
             c->plan_unaligned = unaligned;
+            c->plan_no_third = 1;
         }
     }
     auto unplan = [&] {
-        for (rw_ctx* c : C) c->plan_cols = c->plan_unaligned = 0;
+        for (rw_ctx* c : C) c->plan_cols = c->plan_unaligned = c->plan_no_third = 0;
     };
     e = hipEventRecord(start, s);
     for (hipStream_t t : {ctx->cs[0], ctx->cs[1]})

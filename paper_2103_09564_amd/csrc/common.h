@@ -60,6 +60,9 @@ struct rw_ctx {
     // unaligned plane-march variant
     int plan_cols = 0;
     int plan_unaligned = 0;
+    // keep both streamed-weights launches on one stream (the streamed solve's
+    // lanes already run two solves at once)
+    int plan_no_third = 0;
 };
 
 namespace rwk {
