@@ -226,20 +226,38 @@ def _prunable(core_maps, cfl, p):
     return ((p.prune_hom and hom) or (p.prune_dt and dt)) and not cfl
 
 
-def _solve(g_box, lab_box, border, up_box, p, start_box=None):
-    """One box: Dirichlet from user seeds (win) and border samples, warm start
-    from the parent sample (or from start_box on the unseeded voxels);
-    returns (K-1, *box)."""
-    K = p.n_classes
+def box_dirichlet(lab_box, border, up_box, n_classes, start_box=None):
+    """Dirichlet data and start values of one box (Section IV-A eq. (2),
+    Section IV-B eq. (3), Section IV-D2).
+
+    lab_box: rasterised labels over the box (-1 none, -2 conflict, k class);
+    border: the box's outer layer on faces interior to the level; up_box:
+    the parent map sampled at the box voxels, (K-1, *box), or None (coarsest
+    level).  A voxel is seeded when it carries a user label or lies on the
+    border; a user label overrides the border sample (value 1 for its own
+    class, 0 otherwise); a conflicting voxel carries no label, so on the
+    border it keeps the parent sample.  Unseeded voxels start from the parent
+    sample, or from ``start_box`` when given (warm start from a previous
+    result).  Returns (mask, x) with x of shape (K-1, *box)."""
     seeded = lab_box >= 0
     mask = seeded | border
-    out = np.zeros((K - 1,) + g_box.shape)
-    for k in range(1, K):
-        x = up_box[k - 1].copy() if up_box is not None else np.zeros(g_box.shape)
+    x = np.zeros((n_classes - 1,) + lab_box.shape)
+    for k in range(1, n_classes):
+        xk = up_box[k - 1].copy() if up_box is not None else np.zeros(lab_box.shape)
         if start_box is not None:
-            x[~mask] = start_box[k - 1][~mask]
-        x[seeded] = (lab_box[seeded] == k).astype(np.float64)
-        out[k - 1] = solve_box(g_box, mask, x, p.beta, p.eps, method=p.method, tol=p.tol)
+            xk[~mask] = start_box[k - 1][~mask]
+        xk[seeded] = (lab_box[seeded] == k).astype(np.float64)
+        x[k - 1] = xk
+    return mask, x
+
+
+def _solve(g_box, lab_box, border, up_box, p, start_box=None):
+    """One box: the Dirichlet problem of ``box_dirichlet`` solved per class;
+    returns (K-1, *box)."""
+    mask, x = box_dirichlet(lab_box, border, up_box, p.n_classes, start_box)
+    out = np.zeros_like(x)
+    for k in range(p.n_classes - 1):
+        out[k] = solve_box(g_box, mask, x[k], p.beta, p.eps, method=p.method, tol=p.tol)
     return out
 
 
@@ -326,17 +344,8 @@ def segment(volume, seeds, p, prev=None, g=None):
                     prunable[lvl][b] = prev.prunable[lvl][b]
                     continue
             recomputed[lvl][b] = True
-            border = np.zeros(tuple(hi - lo for lo, hi in box), dtype=bool)
-            for ax, ((lo, hi), dl) in enumerate(zip(box, d)):
-                idx = [slice(None)] * 3
-                if lo > 0:
-                    idx[ax] = 0
-                    border[tuple(idx)] = True
-                if hi < dl:
-                    idx[ax] = -1
-                    border[tuple(idx)] = True
             start = prev.maps[lvl][(slice(None),) + _sl(box)] if prev is not None and p.inc_warm else None
-            xb = _solve(g[lvl][_sl(box)], lab[_sl(box)], border,
+            xb = _solve(g[lvl][_sl(box)], lab[_sl(box)], border_layer(box, d),
                         up[(slice(None),) + _sl(box)], p, start)
             rel = tuple(slice(c0 - b0, c1 - b0) for (c0, c1), (b0, _) in zip(core, box))
             maps[lvl][(slice(None),) + _sl(core)] = xb[(slice(None),) + rel]
@@ -346,8 +355,9 @@ def segment(volume, seeds, p, prev=None, g=None):
                   cfl=cfl, recomputed=recomputed, seeds=seeds.copy())
 
 
-def _border_layer(box, d):
-    """Outermost voxel layer of a box on faces interior to the level."""
+def border_layer(box, d):
+    """Outermost voxel layer of a box on faces interior to the level
+    (Section IV-A eq. (2)); box: (lo, hi) per axis (z, y, x), d: level dims."""
     border = np.zeros(tuple(hi - lo for lo, hi in box), dtype=bool)
     for ax, ((lo, hi), dl) in enumerate(zip(box, d)):
         idx = [slice(None)] * 3
@@ -433,7 +443,7 @@ def _segment_node_rule(g, seeds, p, prev):
                 continue
             recomputed[lvl][b] = True
             start = prev.maps[lvl][(slice(None),) + _sl(box)] if p.inc_warm else None
-            xb = _solve(g[lvl][_sl(box)], lab[_sl(box)], _border_layer(box, d),
+            xb = _solve(g[lvl][_sl(box)], lab[_sl(box)], border_layer(box, d),
                         up[(slice(None),) + _sl(box)], p, start)
             rel = tuple(slice(c0 - b0, c1 - b0) for (c0, c1), (b0, _) in zip(core, box))
             maps[lvl][(slice(None),) + _sl(core)] = xb[(slice(None),) + rel]

@@ -146,13 +146,6 @@ def solve_box(g, mask, x, beta, eps, method="direct", tol=1e-13, max_iter=100000
     return flat.reshape(g.shape)
 
 
-def residual_norms(g, mask, x, beta, eps):
-    """(||b - A x_U||_2, ||b||_2) of a candidate full-box x (float64)."""
-    A, b, U, M = dirichlet_system(g, mask, x, beta, eps)
-    xu = np.asarray(x, dtype=np.float64).ravel()[U]
-    return float(np.linalg.norm(b - A @ xu)), float(np.linalg.norm(b))
-
-
 def dirichlet_energy(g, x, beta, eps):
     """D(x) = 1/2 sum over edges w_pq (x_p - x_q)^2 (Section III-B)."""
     i, j, w = edge_list(np.asarray(g).shape, edge_weights(g, beta, eps))
