@@ -27,6 +27,7 @@
 #ifndef RWSEG_H
 #define RWSEG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -152,6 +153,32 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
                     const rw_brick* bricks, int64_t n_voxels, const float* g,
                     const uint8_t* mask, float* x, double* x64, rw_brick_stats* stats,
                     void* stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as rw_solve_bricks, with the same arguments, kernels and results,
+ * that allocates nothing.  Its workspace (CG vectors, per-box state, the
+ * device box list and the weight segments of the streamed-weights boxes) is
+ * carved from a fixed device array of rw_noalloc_scratch_bytes() bytes
+ * (64 MiB) that the library holds on each device from its first
+ * rw_ctx_create there until the process ends; all kernels run on `stream`
+ * (no side streams, no events, no phase timing).  A batch whose workspace
+ * exceeds the array is rejected with RW_E_INVAL before anything is queued
+ * (about 20 bytes per voxel and right-hand side for MIXED, 40 for FP64 or
+ * when x64 is not given on MIXED_REFINE, plus 17 bytes per voxel of boxes on
+ * the streamed-weights path and about 200 bytes per box: some fifty 32^3
+ * boxes).  Every call on a device shares that device's array and leaves its
+ * last contents there: calls that overlap on one device (on different
+ * streams, or from different host threads) race and corrupt each other's
+ * results; order them on one stream.  The box list is copied from host
+ * memory on `stream`.  Host-side planning still uses the C++ heap.
+ */
+int rw_solve_bricks_noalloc(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks,
+                            const rw_brick* bricks, int64_t n_voxels, const float* g,
+                            const uint8_t* mask, float* x, double* x64, rw_brick_stats* stats,
+                            void* stream);
+size_t rw_noalloc_scratch_bytes(void);
 
 /*
  * The same solve for boxes held in host memory, streamed through the GPU

@@ -53,6 +53,11 @@ lib.rw_last_error.argtypes = [_vp]
 lib.rw_last_error.restype = ctypes.c_char_p
 lib.rw_solve_bricks.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]
 lib.rw_solve_bricks.restype = ctypes.c_int
+lib.rw_solve_bricks_noalloc.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp,
+                                        _vp]
+lib.rw_solve_bricks_noalloc.restype = ctypes.c_int
+lib.rw_noalloc_scratch_bytes.argtypes = []
+lib.rw_noalloc_scratch_bytes.restype = ctypes.c_size_t
 lib.rw_solve_bricks_streamed.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp,
                                          _i64, _vp]
 lib.rw_solve_bricks_streamed.restype = ctypes.c_int
@@ -87,6 +92,11 @@ class RWError(RuntimeError):
 
 def version():
     return lib.rw_version()
+
+
+def noalloc_scratch_bytes():
+    """Size of the fixed device scratch of rw_solve_bricks_noalloc."""
+    return int(lib.rw_noalloc_scratch_bytes())
 
 
 def validate_solve(params, bricks, n_voxels):
@@ -169,6 +179,15 @@ class Context:
         self._check(lib.rw_solve_bricks(self.handle, ctypes.byref(params), len(bricks),
                                         bricks.ctypes.data_as(_vp), n_vox, _ptr(g), _ptr(mask), _ptr(x),
                                         _ptr(x64), _ptr(stats), _stream(stream)))
+
+    def rw_solve_bricks_noalloc(self, params, bricks, g, mask, x, x64=None, stats=None, stream=None):
+        """Queue rw_solve_bricks_noalloc (same arguments as rw_solve_bricks;
+        the workspace comes from the library's fixed device scratch)."""
+        bricks = np.ascontiguousarray(bricks, dtype=BRICK_DTYPE)
+        n_vox = g.numel()
+        self._check(lib.rw_solve_bricks_noalloc(self.handle, ctypes.byref(params), len(bricks),
+                                                bricks.ctypes.data_as(_vp), n_vox, _ptr(g), _ptr(mask), _ptr(x),
+                                                _ptr(x64), _ptr(stats), _stream(stream)))
 
     def rw_solve_bricks_streamed(self, params, bricks, g, mask, x, stats=None, chunk_voxels=0, stream=None):
         """Queue rw_solve_bricks_streamed.  g, mask, x (and stats) are HOST

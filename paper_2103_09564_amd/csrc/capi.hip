@@ -8,14 +8,30 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
 #include <vector>
 
+// Device scratch of rw_solve_bricks_noalloc: a fixed array in the code
+// object, so that call allocates nothing.  Each device holds its own copy
+// (until the process ends) at its own address, which rw_ctx_create looks up
+// once per device; in host code `scratch` is only a stand-in for that
+// address and is never passed to a kernel or copy.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_create_err;
+
+// Address of `scratch` on each device, looked up by the first context
+// created on that device.
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
 
 }  // namespace
 
@@ -61,6 +77,7 @@ namespace {
 using rwk::DevGuard;
 using rwk::fail;
 using rwk::grow;
+using rwk::guarded;
 using rwk::hip_fail;
 
 int check_params(rw_ctx* ctx, const rw_solve_params* p) {
@@ -284,6 +301,169 @@ int upload_list(rw_ctx* ctx, const std::vector<rwk::BrickDev>& list, hipStream_t
     return RW_OK;
 }
 
+// Workspace of one rw_solve_bricks call: the CG vectors (r, z, p0, p1 of
+// the compute type, the FP32 correction buffer, an FP64 solution buffer when
+// the caller gave none), the per-box state and domain-solver scratch, the
+// device box list and the weight segments of the streamed-weights boxes.
+// Offsets are from the start of each buffer; every part is 256-byte aligned.
+struct SolveLayout {
+    size_t nv, es, off_dcorr, off_x64, ws_bytes;   // vector workspace
+    size_t state_bytes, aux_bytes;                 // BoxState [n] + domain scratch
+    size_t list_bytes, wts_bytes;                  // BrickDev [n], weight segments
+};
+
+size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
+
+SolveLayout solve_layout(const rw_solve_params& p, int64_t n_bricks, int64_t n_voxels, const double* x64,
+                         const rwk::PlanePlan& pp) {
+    SolveLayout L{};
+    const bool fp64 = p.precision == RW_PREC_FP64;
+    const bool need_x64 = fp64 || p.precision == RW_PREC_MIXED_REFINE;
+    L.nv = (size_t)n_voxels * (size_t)p.nrhs;
+    L.es = fp64 ? sizeof(double) : sizeof(float);
+    size_t bytes = 4 * L.nv * L.es;
+    L.off_dcorr = bytes;
+    if (!fp64) bytes += L.nv * sizeof(float);
+    L.off_x64 = up256(bytes);
+    if (need_x64 && !x64) bytes = L.off_x64 + L.nv * sizeof(double);
+    L.ws_bytes = up256(std::max<size_t>(bytes, 256));
+    L.state_bytes = up256((size_t)n_bricks * sizeof(rwk::BoxState));
+    L.aux_bytes = up256(L.state_bytes + rwk::domain_scratch_bytes());
+    L.list_bytes = up256(std::max<size_t>((size_t)n_bricks * sizeof(rwk::BrickDev), 64));
+    L.wts_bytes = up256((size_t)pp.wts_elems * sizeof(float));
+    return L;
+}
+
+// rw_solve_bricks and rw_solve_bricks_noalloc.  noalloc: every buffer is
+// carved from the device's static scratch array (no allocation, no side
+// stream or event; all kernels on `stream`), else from the context's
+// buffers, grown on demand.
+int solve_bricks_impl(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                      int64_t n_voxels, const float* g, const uint8_t* mask, float* x, double* x64,
+                      rw_brick_stats* stats, void* stream, bool noalloc) {
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    std::vector<rwk::BrickDev> list;
+    rc = build_list(ctx, n_bricks, bricks, n_voxels, &list);
+    if (rc) return rc;
+    if (n_bricks == 0) return RW_OK;
+    if (!g || !mask || !x) return fail(ctx, RW_E_INVAL, "g, mask and x must be non-NULL");
+    const rw_solve_params& p = *params;
+    const int R = p.nrhs;
+    const bool fp64 = p.precision == RW_PREC_FP64;
+    const bool need_x64 = fp64 || p.precision == RW_PREC_MIXED_REFINE;
+    hipStream_t s = (hipStream_t)stream;
+    DevGuard dg(ctx->device);
+
+    rwk::PlanePlan pp = plan_planes(ctx, &list, R, fp64, p.schedule);
+    const SolveLayout L = solve_layout(p, n_bricks, n_voxels, x64, pp);
+    char *w, *aux, *blist;
+    float* wts = nullptr;
+    if (noalloc) {
+        const size_t total = L.ws_bytes + L.aux_bytes + L.list_bytes + L.wts_bytes;
+        if (total > kScratchBytes)
+            return fail(ctx, RW_E_INVAL,
+                        "rw_solve_bricks_noalloc: these boxes need %zu bytes of workspace, more than the "
+                        "%zu-byte static scratch",
+                        total, (size_t)kScratchBytes);
+        if (!ctx->scratch) return fail(ctx, RW_E_HIP, "no static scratch address for device %d", ctx->device);
+        char* base = (char*)ctx->scratch;
+        w = base;
+        aux = w + L.ws_bytes;
+        blist = aux + L.aux_bytes;
+        if (pp.wts_elems) wts = (float*)(blist + L.list_bytes);
+        pp.side[0] = pp.side[1] = pp.side[2] = nullptr;  // one stream: the caller's
+        pp.third = 0;
+        pp.gev = nullptr;
+        if (!list.empty()) {
+            hipError_t e = hipMemcpyAsync(blist, list.data(), list.size() * sizeof(rwk::BrickDev),
+                                          hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return hip_fail(ctx, e, "uploading brick list");
+        }
+    } else {
+        hipError_t e = grow(ctx, &ctx->ws, &ctx->ws_bytes, L.ws_bytes, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "allocating solver workspace");
+        e = grow(ctx, &ctx->aux, &ctx->aux_bytes, L.aux_bytes, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "allocating per-box state");
+        rc = attach_side_streams(ctx, &pp);
+        if (rc) return rc;
+        rc = upload_list(ctx, list, s);
+        if (rc) return rc;
+        if (pp.wts_elems) {
+            e = grow(ctx, &ctx->wts, &ctx->wts_bytes, L.wts_bytes, s);
+            if (e != hipSuccess) return hip_fail(ctx, e, "allocating weight segments");
+            wts = (float*)ctx->wts;
+        }
+        w = (char*)ctx->ws;
+        aux = (char*)ctx->aux;
+        blist = (char*)ctx->bricks;
+    }
+
+    const size_t nv = L.nv, es = L.es;
+    rwk::SolveArgs a{};
+    a.bricks = (const rwk::BrickDev*)blist;
+    a.g = g;
+    a.mask = mask;
+    a.x = x;
+    a.r = w;
+    a.z = w + nv * es;
+    a.p0 = w + 2 * nv * es;
+    a.p1 = w + 3 * nv * es;
+    a.dcorr = fp64 ? nullptr : (float*)(w + L.off_dcorr);
+    double* x64buf = x64 ? x64 : (need_x64 ? (double*)(w + L.off_x64) : nullptr);
+    a.x64 = x64buf;
+    a.xt = x64buf;
+    a.want_x64 = x64 ? 1 : 0;
+    a.stats = stats;
+    a.state = (rwk::BoxState*)aux;
+    a.beta = p.beta;
+    a.eps = p.eps;
+    a.tol = p.tol;
+    a.refine_tol = p.refine_tol;
+    a.inner_tol = p.inner_tol;
+    a.max_iter = p.max_iter;
+    a.precision = p.precision;
+    a.refine_max = p.refine_max;
+    a.stall_ratio = p.stall_ratio;
+    a.schedule = stream_schedule(p.schedule);
+    rwk::domain_bind(a, aux + L.state_bytes);
+    a.wts = wts;
+    hipError_t e;
+    hipEvent_t* ev = nullptr;
+    const bool timed = ctx->timing && !noalloc;
+    if (timed) {
+        for (int i = 0; i < 4; ++i)
+            if (!ctx->ev[i]) {
+                e = hipEventCreate(&ctx->ev[i]);
+                if (e != hipSuccess) return hip_fail(ctx, e, "creating timing events");
+            }
+        for (int i = 0; i < 6; ++i)
+            if (!ctx->gev[i]) {
+                e = hipEventCreate(&ctx->gev[i]);
+                if (e != hipSuccess) return hip_fail(ctx, e, "creating timing events");
+            }
+        e = hipEventRecord(ctx->ev[0], s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "recording timing event");
+        ev = &ctx->ev[1];
+        pp.gev = ctx->gev;
+        // bit 0: streaming kernels or streamed-weights resident launches
+        // (one stream), bit 1: the other resident launches
+        bool any_g = false, any_lds = false;
+        for (int i = 0; i < pp.n_rl; ++i) (pp.rl[i].kind == 2 ? any_g : any_lds) = true;
+        const bool res_path = R == 1 && !fp64;
+        ctx->gev_used = (pp.n_res > pp.n_dom || (res_path && any_g) ? 1 : 0) | (res_path && any_lds ? 2 : 0) |
+                        (res_path && pp.third ? 4 : 0);
+    }
+    e = rwk::launch_solve(a, n_bricks, R, fp64, pp, s, ev);
+    if (e != hipSuccess) return hip_fail(ctx, e, "launching solve kernel");
+    if (timed) {
+        e = hipEventRecord(ctx->ev[3], s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "recording timing event");
+        ctx->ev_valid = 1;
+    }
+    return RW_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -319,6 +499,22 @@ int rw_ctx_create(int hip_device, rw_ctx** out) {
     int lds = 0;
     e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device);
     c->lds_limit = e == hipSuccess && lds > 0 ? (size_t)lds : 64 * 1024;
+    // the device's copy of the no-allocation scratch, looked up once per
+    // device with that device current
+    if (hip_device < kMaxDevices) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[hip_device]) {
+            DevGuard dg(hip_device);
+            void* ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr) {
+                delete c;
+                return fail(nullptr, RW_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            }
+            g_scratch_ptr[hip_device] = ptr;
+        }
+        c->scratch = g_scratch_ptr[hip_device];
+    }
     *out = c;
     return RW_OK;
 }
@@ -387,15 +583,18 @@ int rw_last_timing(rw_ctx* ctx, rw_timing* out) {
 
 int rw_validate_solve(const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
                       int64_t n_voxels) {
+    return guarded(nullptr, [&]() -> int {
     g_create_err.clear();
     int rc = check_params(nullptr, params);
     if (rc) return rc;
     std::vector<rwk::BrickDev> list;
     return build_list(nullptr, n_bricks, bricks, n_voxels, &list);
+    });
 }
 
 int rw_solve_plan(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
                   int64_t n_voxels, int32_t* path) {
+    return guarded(ctx, [&]() -> int {
     if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
     ctx->err.clear();
     int rc = check_params(ctx, params);
@@ -416,6 +615,7 @@ int rw_solve_plan(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, 
             if (pp.rl[k].kind == 2 && i >= pp.rl[k].b0 && i < pp.rl[k].b1) path[slot] = RW_PATH_RESIDENT_STREAMED;
     }
     return RW_OK;
+    });
 }
 
 int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
@@ -423,102 +623,22 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
                     rw_brick_stats* stats, void* stream) {
     if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
     ctx->err.clear();
-    int rc = check_params(ctx, params);
-    if (rc) return rc;
-    std::vector<rwk::BrickDev> list;
-    rc = build_list(ctx, n_bricks, bricks, n_voxels, &list);
-    if (rc) return rc;
-    if (n_bricks == 0) return RW_OK;
-    if (!g || !mask || !x) return fail(ctx, RW_E_INVAL, "g, mask and x must be non-NULL");
-    const rw_solve_params& p = *params;
-    const int R = p.nrhs;
-    const bool fp64 = p.precision == RW_PREC_FP64;
-    const bool need_x64 = fp64 || p.precision == RW_PREC_MIXED_REFINE;
-    hipStream_t s = (hipStream_t)stream;
-    DevGuard dg(ctx->device);
-
-    const size_t nv = (size_t)n_voxels * (size_t)R;
-    const size_t es = fp64 ? sizeof(double) : sizeof(float);
-    // r, z, p0, p1, then FP32 correction buffer, then FP64 solution buffer if the caller gave none
-    size_t bytes = 4 * nv * es;
-    const size_t off_dcorr = bytes;
-    if (!fp64) bytes += nv * sizeof(float);
-    const size_t off_x64 = (bytes + 255) & ~size_t(255);
-    if (need_x64 && !x64) bytes = off_x64 + nv * sizeof(double);
-    hipError_t e = grow(ctx, &ctx->ws, &ctx->ws_bytes, std::max<size_t>(bytes, 256), s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "allocating solver workspace");
-    const size_t state_bytes = ((size_t)n_bricks * sizeof(rwk::BoxState) + 255) & ~size_t(255);
-    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, state_bytes + rwk::domain_scratch_bytes(), s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "allocating per-box state");
-    rwk::PlanePlan pp = plan_planes(ctx, &list, R, fp64, p.schedule);
-    rc = attach_side_streams(ctx, &pp);
-    if (rc) return rc;
-    rc = upload_list(ctx, list, s);
-    if (rc) return rc;
-
-    char* w = (char*)ctx->ws;
-    rwk::SolveArgs a{};
-    a.bricks = (const rwk::BrickDev*)ctx->bricks;
-    a.g = g;
-    a.mask = mask;
-    a.x = x;
-    a.r = w;
-    a.z = w + nv * es;
-    a.p0 = w + 2 * nv * es;
-    a.p1 = w + 3 * nv * es;
-    a.dcorr = fp64 ? nullptr : (float*)(w + off_dcorr);
-    double* x64buf = x64 ? x64 : (need_x64 ? (double*)(w + off_x64) : nullptr);
-    a.x64 = x64buf;
-    a.xt = x64buf;
-    a.want_x64 = x64 ? 1 : 0;
-    a.stats = stats;
-    a.state = (rwk::BoxState*)ctx->aux;
-    a.beta = p.beta;
-    a.eps = p.eps;
-    a.tol = p.tol;
-    a.refine_tol = p.refine_tol;
-    a.inner_tol = p.inner_tol;
-    a.max_iter = p.max_iter;
-    a.precision = p.precision;
-    a.refine_max = p.refine_max;
-    a.stall_ratio = p.stall_ratio;
-    a.schedule = stream_schedule(p.schedule);
-    rwk::domain_bind(a, (char*)ctx->aux + state_bytes);
-    rc = bind_weights(ctx, pp, &a, s);
-    if (rc) return rc;
-    hipEvent_t* ev = nullptr;
-    if (ctx->timing) {
-        for (int i = 0; i < 4; ++i)
-            if (!ctx->ev[i]) {
-                e = hipEventCreate(&ctx->ev[i]);
-                if (e != hipSuccess) return hip_fail(ctx, e, "creating timing events");
-            }
-        for (int i = 0; i < 6; ++i)
-            if (!ctx->gev[i]) {
-                e = hipEventCreate(&ctx->gev[i]);
-                if (e != hipSuccess) return hip_fail(ctx, e, "creating timing events");
-            }
-        e = hipEventRecord(ctx->ev[0], s);
-        if (e != hipSuccess) return hip_fail(ctx, e, "recording timing event");
-        ev = &ctx->ev[1];
-        pp.gev = ctx->gev;
-        // bit 0: streaming kernels or streamed-weights resident launches
-        // (one stream), bit 1: the other resident launches
-        bool any_g = false, any_lds = false;
-        for (int i = 0; i < pp.n_rl; ++i) (pp.rl[i].kind == 2 ? any_g : any_lds) = true;
-        const bool res_path = R == 1 && !fp64;
-        ctx->gev_used = (pp.n_res > pp.n_dom || (res_path && any_g) ? 1 : 0) | (res_path && any_lds ? 2 : 0) |
-                        (res_path && pp.third ? 4 : 0);
-    }
-    e = rwk::launch_solve(a, n_bricks, R, fp64, pp, s, ev);
-    if (e != hipSuccess) return hip_fail(ctx, e, "launching solve kernel");
-    if (ctx->timing) {
-        e = hipEventRecord(ctx->ev[3], s);
-        if (e != hipSuccess) return hip_fail(ctx, e, "recording timing event");
-        ctx->ev_valid = 1;
-    }
-    return RW_OK;
+    return guarded(ctx, [&] {
+        return solve_bricks_impl(ctx, params, n_bricks, bricks, n_voxels, g, mask, x, x64, stats, stream, false);
+    });
 }
+
+int rw_solve_bricks_noalloc(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                            int64_t n_voxels, const float* g, const uint8_t* mask, float* x, double* x64,
+                            rw_brick_stats* stats, void* stream) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    return guarded(ctx, [&] {
+        return solve_bricks_impl(ctx, params, n_bricks, bricks, n_voxels, g, mask, x, x64, stats, stream, true);
+    });
+}
+
+size_t rw_noalloc_scratch_bytes(void) { return (size_t)kScratchBytes; }
 
 // lanes of the streamed solve: context, compute stream and staging set
 // (three lanes measured slower than two: each solve forks onto two side
@@ -528,6 +648,7 @@ static constexpr int kLanes = 2;
 int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
                              int64_t n_voxels, const float* g, const uint8_t* mask, float* x,
                              rw_brick_stats* stats, int64_t chunk_voxels, void* stream) {
+    return guarded(ctx, [&]() -> int {
     if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
     ctx->err.clear();
     int rc = check_params(ctx, params);
@@ -714,12 +835,14 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
     if (e == hipSuccess) e = hipEventRecord(ctx->pin_ev, s);
     if (e != hipSuccess) return drain(hip_fail(ctx, e, "joining the copy stream"));
     return RW_OK;
+    });
 }
 
 int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks,
                             const rw_brick* bricks, int64_t n_voxels, const float* g, const uint8_t* mask,
                             const float* x, const float* dl_dx, float* dl_dg, double* dl_dbeta,
                             float* lambda, rw_brick_stats* stats, void* stream) {
+    return guarded(ctx, [&]() -> int {
     if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
     ctx->err.clear();
     int rc = check_params(ctx, params);
@@ -789,6 +912,7 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     e = rwk::launch_adjoint(a, sa, n_bricks, dl_dbeta, pp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "launching adjoint kernels");
     return RW_OK;
+    });
 }
 
 }  // extern "C"

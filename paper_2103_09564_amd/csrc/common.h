@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <exception>
+#include <new>
 #include <string>
 
 #include "rwseg.h"
@@ -63,6 +65,8 @@ struct rw_ctx {
     // keep both streamed-weights launches on one stream (the streamed solve's
     // lanes already run two solves at once)
     int plan_no_third = 0;
+    // this device's copy of the static scratch of rw_solve_bricks_noalloc
+    void* scratch = nullptr;
 };
 
 namespace rwk {
@@ -73,6 +77,21 @@ int fail(rw_ctx* ctx, int code, const char* fmt, ...) __attribute__((format(prin
 int hip_fail(rw_ctx* ctx, hipError_t e, const char* what);
 // Grow a device buffer to at least `bytes` (contents are not kept; syncs `s` first).
 hipError_t grow(rw_ctx* ctx, void** buf, size_t* have, size_t bytes, hipStream_t s);
+
+// No C++ exception crosses the ABI: host allocation failures map to
+// RW_E_NOMEM, anything else thrown to RW_E_INVAL.
+template <typename F>
+inline int guarded(rw_ctx* ctx, F&& f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, RW_E_NOMEM, "host allocation failed");
+    } catch (const std::exception& ex) {
+        return fail(ctx, RW_E_INVAL, "%s", ex.what());
+    } catch (...) {
+        return fail(ctx, RW_E_INVAL, "unexpected exception");
+    }
+}
 
 struct DevGuard {
     int prev = -1;

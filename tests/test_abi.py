@@ -63,3 +63,8 @@ def test_params_defaults():
     assert p.precision == rwg.PREC_MIXED
     with pytest.raises(TypeError):
         rwg.solve_params(bogus=1)
+
+
+def test_noalloc_scratch_size_is_stated():
+    import paper_2103_09564_amd as rwg
+    assert rwg.noalloc_scratch_bytes() == 64 << 20
