@@ -952,6 +952,7 @@ void rw_params_default(rw_params* p) {
 // the mean counts (rw_pyramid_build_counts).
 static int pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels, int counts,
                          rw_pyramid** out, void* stream) {
+    return rwk::guarded(ctx, [&]() -> int {
     if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
     ctx->err.clear();
     if (!out) return fail(ctx, RW_E_INVAL, "out is NULL");
@@ -1024,6 +1025,7 @@ static int pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t 
     }
     *out = p;
     return RW_OK;
+    });
 }
 
 int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels, rw_pyramid** out,
@@ -1055,6 +1057,7 @@ int rw_pyramid_level(const rw_pyramid* p, int level, int64_t dims[3], const floa
 
 int rw_segment(rw_ctx* ctx, const rw_pyramid* pyr, const rw_seed* seeds, int64_t n_seeds, const rw_params* params,
                const rw_result* prev, rw_result** out, void* stream) {
+    return rwk::guarded(ctx, [&]() -> int {
     if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
     ctx->err.clear();
     if (!out) return fail(ctx, RW_E_INVAL, "out is NULL");
@@ -1088,15 +1091,22 @@ int rw_segment(rw_ctx* ctx, const rw_pyramid* pyr, const rw_seed* seeds, int64_t
     r->params = P;
     r->levels = pyr->levels;
     r->R = P.n_classes - 1;
-    r->seeds.assign(seeds, seeds + n_seeds);
+    try {
+        r->seeds.assign(seeds, seeds + n_seeds);
+    } catch (...) {
+        delete r;
+        throw;
+    }
     hipStream_t s = (hipStream_t)stream;
     DevGuard dg(ctx->device);
-    int rc = RW_OK;
-    switch (r->R) {
-        case 1: rc = segment_impl<1>(ctx, pyr, r->seeds, P, prev, r, s); break;
-        case 2: rc = segment_impl<2>(ctx, pyr, r->seeds, P, prev, r, s); break;
-        case 3: rc = segment_impl<3>(ctx, pyr, r->seeds, P, prev, r, s); break;
-    }
+    const int rc = rwk::guarded(ctx, [&]() -> int {
+        switch (r->R) {
+            case 1: return segment_impl<1>(ctx, pyr, r->seeds, P, prev, r, s);
+            case 2: return segment_impl<2>(ctx, pyr, r->seeds, P, prev, r, s);
+            case 3: return segment_impl<3>(ctx, pyr, r->seeds, P, prev, r, s);
+        }
+        return RW_OK;
+    });
     if (rc != RW_OK) {
         (void)hipStreamSynchronize(s);
         free_result_mem(r);
@@ -1105,6 +1115,7 @@ int rw_segment(rw_ctx* ctx, const rw_pyramid* pyr, const rw_seed* seeds, int64_t
     }
     *out = r;
     return RW_OK;
+    });
 }
 
 void rw_result_free(rw_result* r) {
