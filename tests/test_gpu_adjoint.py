@@ -3,8 +3,14 @@ adjoint and against central finite differences of the GPU forward solve.
 
 Workload: boxes of the two-blob recipe (32^3, beta 64 learnable, g learnable),
 loss = mean over unseeded voxels of BCE(clamp(x, 1e-6, 1-1e-6), y) with y the
-blob-1 half-maximum mask.  Bar: gradients within 1e-3 relative (norm-wise for
-dl/dg, scalar for dl/dbeta).
+blob-1 half-maximum mask.  Bar: gradients within 1e-3 relative: dl/dbeta as a
+scalar; dl/dg per box in norm and per voxel, where each voxel must satisfy
+|gpu - oracle| <= 1e-3 |oracle| + FLOOR * max_box |oracle| (FLOOR below: the
+gradient is formed in FP32 from an FP32 adjoint solved to relative residual
+1e-7, so voxels whose gradient cancels to near zero carry an absolute error of
+that order of the box's largest gradient); and each of the 64 finite-difference
+voxels on its own within 1e-3 relative plus the finite difference's own
+truncation error, estimated from a second difference at h/2.
 """
 
 import numpy as np
@@ -17,6 +23,16 @@ from oracle import rw as orw
 pytestmark = pytest.mark.gpu
 
 BETA, EPS = 64.0, 1e-6
+FLOOR = 1e-4
+
+
+def _elementwise(dg, og, tag):
+    """Per-voxel check; returns the worst ratio of error to allowance."""
+    allow = 1e-3 * np.abs(og) + FLOOR * np.max(np.abs(og))
+    ratio = np.abs(dg - og) / allow
+    worst = float(ratio.max())
+    assert worst <= 1.0, (tag, worst, int(np.argmax(ratio)))
+    return worst
 
 
 @pytest.fixture(scope="module")
@@ -70,6 +86,8 @@ def test_adjoint_matches_oracle(env, blobs):
         tot_db += odb
         rel = np.linalg.norm(dg[o:o + gb.size] - og.ravel()) / np.linalg.norm(og)
         assert rel <= 1e-3, (i, rel)
+        worst = _elementwise(dg[o:o + gb.size], og.ravel(), i)
+        print(f"blob box {i}: norm rel {rel:.2e}, worst per-voxel error/allowance {worst:.3f}", flush=True)
     assert abs(db - tot_db) <= 1e-3 * abs(tot_db), (db, tot_db)
     assert np.all(rwg.stats_to_numpy(st)["status"] == 0)
 
@@ -108,14 +126,23 @@ def test_rwsolve_autograd_and_finite_differences(env, blobs):
     unk = np.flatnonzero(d["mask"] == 0)
     picks = rng.choice(unk, 64, replace=False)
     num = den = 0.0
+    worst = 0.0
     for v in picks:
-        gp = g0.clone()
-        gm = g0.clone()
-        gp[v] += h
-        gm[v] -= h
-        fd = (loss64(gp, BETA) - loss64(gm, BETA)) / (2 * h)
-        num += (ag[v] - fd) ** 2
-        den += fd ** 2
+        def fd(step):
+            gp = g0.clone()
+            gm = g0.clone()
+            gp[v] += step
+            gm[v] -= step
+            return (loss64(gp, BETA) - loss64(gm, BETA)) / (2 * step)
+        f1, f2 = fd(h), fd(h / 2)
+        trunc = 4.0 / 3.0 * abs(f1 - f2)     # error estimate of the h-difference (O(h^2))
+        err = abs(ag[v] - f1)
+        allow = 1e-3 * abs(f1) + trunc + 1e-12
+        worst = max(worst, err / allow)
+        assert err <= allow, (int(v), ag[v], f1, f2)
+        num += (ag[v] - f1) ** 2
+        den += f1 ** 2
+    print(f"64 FD voxels: worst error/allowance {worst:.3f}, pooled RMS rel {np.sqrt(num / den):.2e}", flush=True)
     assert np.sqrt(num / den) <= 1e-3, np.sqrt(num / den)
 
 
@@ -148,5 +175,7 @@ def test_adjoint_on_resident_and_ragged_boxes(env):
         tot += odb
         rel = np.linalg.norm(dg[o:o + gb.size] - og.ravel()) / np.linalg.norm(og)
         assert rel <= 1e-3, (shapes[i], rel)
+        worst = _elementwise(dg[o:o + gb.size], og.ravel(), shapes[i])
+        print(f"box {shapes[i]}: norm rel {rel:.2e}, worst per-voxel error/allowance {worst:.3f}", flush=True)
     assert abs(float(dl_db.cpu()[0]) - tot) <= 1e-3 * abs(tot)
     assert np.all(rwg.stats_to_numpy(st)["status"] == 0)
