@@ -294,6 +294,24 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
                             float* dl_dg, double* dl_dbeta, float* lambda,
                             rw_brick_stats* stats, void* stream);
 
+/*
+ * Memory-system probes (measurement, not a step of the method): the
+ * ceilings the solve kernels are measured against on the device at hand.
+ * rw_probe_read queues one kernel of rw_probe_blocks() workgroups that reads
+ * the `bytes` at `src` (dev, 16-byte aligned, bytes a positive multiple of
+ * 16) `passes` times with 16-byte loads, `unroll` (4, 8 or 16) of them in
+ * flight per thread, and writes one float per workgroup to
+ * `part` (dev float [rw_probe_blocks()]); a buffer well beyond the 256 MB
+ * last-level cache measures HBM, a smaller one read many times that cache.
+ * rw_probe_copy queues a plain copy of `bytes` from src to dst (dev, 16-byte
+ * aligned, not overlapping).  Time them with events on `stream`.
+ * Errors: RW_E_INVAL on a bad size, alignment or overlap.
+ */
+int rw_probe_blocks(void);
+int rw_probe_read(rw_ctx* ctx, const void* src, int64_t bytes, int passes, int unroll, float* part,
+                  void* stream);
+int rw_probe_copy(rw_ctx* ctx, void* dst, const void* src, int64_t bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Hierarchical random walker over the LOD pyramid (Sections III-A and IV).
  * ------------------------------------------------------------------------ */

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librwseg.so")
 
-SOURCES = ["capi.hip", "pcg.hip", "domain.hip", "resident.hip", "hier.hip"]
+SOURCES = ["capi.hip", "pcg.hip", "domain.hip", "resident.hip", "hier.hip", "probe.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

@@ -78,6 +78,12 @@ lib.rw_set_timing.argtypes = [_vp, ctypes.c_int]
 lib.rw_set_timing.restype = ctypes.c_int
 lib.rw_last_timing.argtypes = [_vp, ctypes.POINTER(Timing)]
 lib.rw_last_timing.restype = ctypes.c_int
+lib.rw_probe_blocks.argtypes = []
+lib.rw_probe_blocks.restype = ctypes.c_int
+lib.rw_probe_read.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, _vp, _vp]
+lib.rw_probe_read.restype = ctypes.c_int
+lib.rw_probe_copy.argtypes = [_vp, _vp, _vp, _i64, _vp]
+lib.rw_probe_copy.restype = ctypes.c_int
 lib.rw_solve_plan.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp]
 lib.rw_solve_plan.restype = ctypes.c_int
 
@@ -92,6 +98,11 @@ class RWError(RuntimeError):
 
 def version():
     return lib.rw_version()
+
+
+def probe_blocks():
+    """Workgroups of the memory probes (floats of their ``part`` output)."""
+    return int(lib.rw_probe_blocks())
 
 
 def noalloc_scratch_bytes():
@@ -217,6 +228,20 @@ class Context:
         self._check(lib.rw_solve_plan(self.handle, ctypes.byref(params), len(bricks), bricks.ctypes.data_as(_vp),
                                       int(n_voxels), out.ctypes.data_as(_vp)))
         return out
+
+    def probe_read(self, src, passes, part, unroll=8, stream=None):
+        """Queue the read probe over tensor ``src`` (``passes`` times, ``unroll``
+        loads in flight per thread); ``part`` a float32 device tensor of
+        rw_probe_blocks() elements."""
+        self._check(lib.rw_probe_read(self.handle, _ptr(src), src.numel() * src.element_size(), int(passes),
+                                      int(unroll), _ptr(part), _stream(stream)))
+
+    def probe_copy(self, dst, src, stream=None):
+        """Queue a plain copy of tensor ``src`` into ``dst`` (same byte size)."""
+        n = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() != n:
+            raise ValueError("probe_copy: dst and src differ in size")
+        self._check(lib.rw_probe_copy(self.handle, _ptr(dst), _ptr(src), n, _stream(stream)))
 
     def rw_solve_bricks_adjoint(self, params, bricks, g, mask, x, dl_dx, dl_dg, dl_dbeta, lam=None,
                                 stats=None, stream=None):

@@ -915,4 +915,32 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     });
 }
 
+int rw_probe_blocks(void) { return rwk::kProbeBlocks; }
+
+int rw_probe_read(rw_ctx* ctx, const void* src, int64_t bytes, int passes, int unroll, float* part, void* stream) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!src || !part) return fail(ctx, RW_E_INVAL, "src and part must be non-NULL");
+    if (bytes <= 0 || bytes % 16 != 0 || ((uintptr_t)src & 15) != 0)
+        return fail(ctx, RW_E_INVAL, "bytes must be a positive multiple of 16 and src 16-byte aligned");
+    if (passes < 1) return fail(ctx, RW_E_INVAL, "passes must be >= 1");
+    if (unroll != 4 && unroll != 8 && unroll != 16) return fail(ctx, RW_E_INVAL, "unroll must be 4, 8 or 16");
+    DevGuard dg(ctx->device);
+    hipError_t e = rwk::launch_probe_read(src, bytes, passes, unroll, part, (hipStream_t)stream);
+    return e == hipSuccess ? RW_OK : hip_fail(ctx, e, "launching the read probe");
+}
+
+int rw_probe_copy(rw_ctx* ctx, void* dst, const void* src, int64_t bytes, void* stream) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!src || !dst) return fail(ctx, RW_E_INVAL, "src and dst must be non-NULL");
+    if (bytes <= 0 || bytes % 16 != 0 || ((uintptr_t)src & 15) != 0 || ((uintptr_t)dst & 15) != 0)
+        return fail(ctx, RW_E_INVAL, "bytes must be a positive multiple of 16 and both buffers 16-byte aligned");
+    const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+    if (a < b + (uintptr_t)bytes && b < a + (uintptr_t)bytes) return fail(ctx, RW_E_INVAL, "src and dst overlap");
+    DevGuard dg(ctx->device);
+    hipError_t e = rwk::launch_probe_copy(dst, src, bytes, (hipStream_t)stream);
+    return e == hipSuccess ? RW_OK : hip_fail(ctx, e, "launching the copy probe");
+}
+
 }  // extern "C"

@@ -248,6 +248,14 @@ hipError_t domain_finish64(const SolveArgs& a, int ib, const BrickDev& bd, hipSt
 int plane_cols(int max_plane);
 int plane_max(int cols);
 
+// Memory-system probes (probe.hip): kProbeBlocks workgroups of 256 threads
+// (eight per CU on 256 CUs) stream float4 loads over a buffer `passes` times
+// (one float per workgroup to part), `unroll` (4, 8 or 16) loads in flight
+// per thread, or copy it.
+constexpr int kProbeBlocks = 2048;
+hipError_t launch_probe_read(const void* src, int64_t bytes, int passes, int unroll, float* part, hipStream_t s);
+hipError_t launch_probe_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);
+
 // Launchers (pcg.hip).  Return a hipError_t.
 // ev: optional events {after init, after main PCG} recorded on s (may be null).
 hipError_t launch_solve(const SolveArgs& a, int64_t n_bricks, int nrhs, bool fp64, const PlanePlan& pp,

@@ -471,3 +471,98 @@ def cells_volume(n=256, seed=11, structure=0.1, coverage=0.01, noise=0.1, max_sp
             seeds.append([q[0], q[1], q[2], 0])
             placed += 1
     return vol, np.array(seeds, dtype=np.float64), truth
+
+
+def _segment_mask(shape, a, b, r):
+    """Voxels (centres at index + 0.5) within distance r of segment a-b:
+    (lo, hi, mask) over the segment's bounding box, coordinates (x, y, z)."""
+    n = np.array(shape[::-1])
+    lo = np.maximum(np.floor(np.minimum(a, b) - r).astype(np.int64), 0)
+    hi = np.minimum(np.ceil(np.maximum(a, b) + r).astype(np.int64) + 1, n)
+    if np.any(hi <= lo):
+        return lo, hi, None
+    zz, yy, xx = np.meshgrid(*(np.arange(lo[k], hi[k]) + 0.5 for k in (2, 1, 0)), indexing="ij")
+    p = np.stack([xx, yy, zz], -1)
+    ab = b - a
+    t = np.clip(((p - a) @ ab) / max(float(ab @ ab), 1e-12), 0.0, 1.0)
+    d2 = np.sum((p - (a + t[..., None] * ab)) ** 2, axis=-1)
+    return lo, hi, d2 <= r * r
+
+
+def vessels_volume(n=256, seed=12, structure=0.1, coverage=0.01, noise=0.1, max_trees=200, min_radius=1.0):
+    """Vessels scenario: trees of cylindrical segments with spheres at the
+    branch points.  A tree starts at a random point of the volume border,
+    heading inwards, with a diameter in [S/2, S] (S = structure * n); a
+    segment is 5 radii long and then branches into two segments whose radii
+    keep the cross-section area (r / sqrt 2), turned 35 degrees either side
+    about a random axis normal to the parent; branches stop below
+    `min_radius` or outside the volume.  Trees are added until `coverage` of
+    the voxels is inside a vessel.  Labels: per segment two points on its
+    centreline (foreground) and, for each, a point two radii away normal to
+    the segment (background, dropped if it lands inside a vessel or outside
+    the volume).  Intensities 0.7 in vessels, 0.3 elsewhere, plus Gaussian
+    noise, clipped to [0, 1].  Returns (vol float32 [z, y, x], seeds float64
+    (x, y, z, label), truth uint8)."""
+    rng = np.random.default_rng(seed)
+    S = structure * n
+    truth = np.zeros((n, n, n), dtype=np.uint8)
+    segs = []
+    target = coverage * n ** 3
+    count = 0
+
+    def paint(a, b, r):
+        nonlocal count
+        lo, hi, m = _segment_mask(truth.shape, a, b, r)
+        if m is None:
+            return
+        sub = truth[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        count += int(np.sum(m & (sub == 0)))
+        sub[m] = 1
+
+    def normal_to(d):
+        v = rng.standard_normal(3)
+        v -= (v @ d) * d
+        return v / np.linalg.norm(v)
+
+    trees = 0
+    while count < target and trees < max_trees:
+        trees += 1
+        r0 = rng.uniform(S / 4.0, S / 2.0)
+        face = rng.integers(0, 6)
+        axis, side = face // 2, face % 2
+        p = rng.uniform(0.0, n, 3)
+        p[axis] = 0.0 if side == 0 else float(n)
+        d = np.zeros(3)
+        d[axis] = 1.0 if side == 0 else -1.0
+        d = d + 0.3 * normal_to(d)
+        d /= np.linalg.norm(d)
+        stack = [(p, d, r0)]
+        while stack and count < target:
+            a, d, r = stack.pop()
+            if r < min_radius:
+                continue
+            b = a + 5.0 * r * d
+            paint(a, b, r)
+            paint(b, b, r)                       # sphere at the branch point
+            segs.append((a, b, r))
+            if np.all(b >= 0) and np.all(b < n):
+                ax = normal_to(d)
+                c, s = np.cos(np.radians(35.0)), np.sin(np.radians(35.0))
+                for sign in (1.0, -1.0):
+                    dn = c * d + sign * s * ax
+                    stack.append((b, dn / np.linalg.norm(dn), r / np.sqrt(2.0)))
+    vol = 0.3 + 0.4 * truth.astype(np.float32) + rng.standard_normal((n, n, n), dtype=np.float32) * noise
+    vol = np.clip(vol, 0.0, 1.0).astype(np.float32)
+    seeds = []
+    for a, b, r in segs:
+        nrm = normal_to((b - a) / np.linalg.norm(b - a))
+        for t in (0.25, 0.75):
+            q = a + t * (b - a)
+            if np.any(q < 0) or np.any(q >= n):
+                continue
+            seeds.append([q[0], q[1], q[2], 1])
+            o = q + 2.0 * r * nrm
+            oi = np.floor(o).astype(np.int64)
+            if np.all(o >= 0) and np.all(o < n) and truth[oi[2], oi[1], oi[0]] == 0:
+                seeds.append([o[0], o[1], o[2], 0])
+    return vol, np.array(seeds, dtype=np.float64), truth
