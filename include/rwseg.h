@@ -102,12 +102,18 @@ typedef struct rw_solve_params {
                                 sweep and one reduction (Chronopoulos-Gear; weights computed once
                                 per iteration), 3 as 0 with the streaming boxes as in 2, 4 as 0
                                 with every box that fits it on the streamed-weights resident
-                                kernel (RW_PATH_RESIDENT_STREAMED).  Every
+                                kernel (RW_PATH_RESIDENT_STREAMED), RW_SCHED_TUNED (5) the
+                                schedule rw_autotune measured fastest for the batch.  Every
                                 schedule is the same Jacobi-PCG iteration in exact arithmetic;
                                 results differ by rounding (the one-sweep recurrence is the less
                                 stable one on very ill-conditioned boxes). */
     int32_t reserved;        /* must be 0 */
 } rw_solve_params;
+
+/* rw_solve_params.schedule value: the schedule rw_autotune measured fastest
+ * for this batch (its box shapes, nrhs and precision) on this context, or
+ * schedule 0 when the batch was not tuned. */
+#define RW_SCHED_TUNED 5
 
 /* Fill *p with the defaults: beta 128, eps 1e-6, tol 1e-6, max_iter 5000,
  * MIXED, nrhs 1, refine_max 1, refine_tol 1e-13, inner_tol 1e-4, stall_ratio 10. */
@@ -243,6 +249,59 @@ typedef struct rw_timing {
 } rw_timing;
 int rw_set_timing(rw_ctx* ctx, int enable);
 int rw_last_timing(rw_ctx* ctx, rw_timing* out);
+
+/*
+ * Autotuner (a batching pattern, not a step of the method).  Times candidate
+ * schedules of rw_solve_bricks on this batch and records the fastest on ctx
+ * for RW_SCHED_TUNED: for MIXED or MIXED_REFINE with one rhs schedule 0 with
+ * and without the second streamed-weights launch on a stream of its own,
+ * schedule 4, schedule 3 and schedule 1; otherwise schedules 1 and 2.  Each
+ * candidate runs 1 + reps solves of the batch from x0 (dev, copied into
+ * x_work before every run; both [n_voxels * nrhs]); the median of the reps
+ * timed runs (HIP events on `stream`) ranks it.  params->schedule must be
+ * 0..4 (ignored otherwise: every candidate sets it).  The call synchronises
+ * `stream`.  out (host, may be NULL) receives the table.  A later tuning of
+ * the same batch signature replaces the entry.  Results of every candidate
+ * are equal up to rounding (they are the same Jacobi-PCG).
+ */
+typedef struct rw_tune_report {
+    int32_t n_candidates;
+    int32_t best;             /* index of the fastest candidate */
+    int32_t schedule[8];      /* rw_solve_params.schedule of each candidate */
+    int32_t third_stream[8];  /* 1: the second streamed-weights launch may take a stream of its own */
+    float ms[8];              /* median milliseconds per solve */
+    uint64_t key;             /* signature of the batch */
+} rw_tune_report;
+int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                int64_t n_voxels, const float* g, const uint8_t* mask, const float* x0, float* x_work, int reps,
+                rw_tune_report* out, void* stream);
+/* Host-only: the schedule a RW_SCHED_TUNED call would run for this batch
+ * (*tuned = 1 when ctx holds a measured entry for it, else 0 and the
+ * default). */
+int rw_tuned_schedule(const rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                      int32_t* schedule, int32_t* third_stream, int32_t* tuned);
+
+/*
+ * Captured graph of one batched solve (a batching pattern, not a step of the
+ * method): the whole launch sequence of rw_solve_bricks for these boxes,
+ * buffers and params, recorded once with stream capture on `stream` (not
+ * the null stream) and replayed by rw_graph_launch with no host planning and
+ * no allocation.  Nothing runs at creation; each launch solves the boxes
+ * from whatever g, mask and x (and x64, stats) hold then, exactly as
+ * rw_solve_bricks would.  The graph owns its device workspace (allocated at
+ * creation, like rw_solve_bricks' workspace) and the box list, so it does not
+ * depend on ctx afterwards; the caller keeps the buffers alive while the
+ * graph exists.  Replays of one graph must not overlap (they share its
+ * workspace).  Errors: as rw_solve_bricks, plus RW_E_UNSUPPORTED for a batch
+ * with single-domain boxes (that solver polls the host) and RW_E_HIP when
+ * capture fails.  No phase timing inside a graph.
+ */
+typedef struct rw_graph rw_graph;
+int rw_graph_create(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                    int64_t n_voxels, const float* g, const uint8_t* mask, float* x, double* x64,
+                    rw_brick_stats* stats, void* stream, rw_graph** out);
+int rw_graph_launch(rw_graph* graph, void* stream);
+void rw_graph_free(rw_graph* graph);
 
 /* Kernel path of a box in rw_solve_bricks. */
 enum rw_path {

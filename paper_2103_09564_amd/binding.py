@@ -84,6 +84,25 @@ lib.rw_probe_read.argtypes = [_vp, _vp, _i64, ctypes.c_int, ctypes.c_int, _vp, _
 lib.rw_probe_read.restype = ctypes.c_int
 lib.rw_probe_copy.argtypes = [_vp, _vp, _vp, _i64, _vp]
 lib.rw_probe_copy.restype = ctypes.c_int
+class TuneReport(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int32), ("best", ctypes.c_int32), ("schedule", ctypes.c_int32 * 8),
+                ("third_stream", ctypes.c_int32 * 8), ("ms", ctypes.c_float * 8), ("key", ctypes.c_uint64)]
+
+
+SCHED_TUNED = 5
+lib.rw_autotune.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_int,
+                            ctypes.POINTER(TuneReport), _vp]
+lib.rw_autotune.restype = ctypes.c_int
+lib.rw_tuned_schedule.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+lib.rw_tuned_schedule.restype = ctypes.c_int
+lib.rw_graph_create.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
+                                ctypes.POINTER(_vp)]
+lib.rw_graph_create.restype = ctypes.c_int
+lib.rw_graph_launch.argtypes = [_vp, _vp]
+lib.rw_graph_launch.restype = ctypes.c_int
+lib.rw_graph_free.argtypes = [_vp]
+lib.rw_graph_free.restype = None
 lib.rw_solve_plan.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp]
 lib.rw_solve_plan.restype = ctypes.c_int
 
@@ -229,6 +248,28 @@ class Context:
                                       int(n_voxels), out.ctypes.data_as(_vp)))
         return out
 
+    def autotune(self, params, bricks, g, mask, x0, x_work, reps=3, stream=None):
+        """Time the candidate schedules on this batch (rw_autotune; synchronises
+        the stream) and record the fastest for SCHED_TUNED.  Returns the table
+        as a dict."""
+        bricks = np.ascontiguousarray(bricks, dtype=BRICK_DTYPE)
+        rep = TuneReport()
+        self._check(lib.rw_autotune(self.handle, ctypes.byref(params), len(bricks), bricks.ctypes.data_as(_vp),
+                                    g.numel(), _ptr(g), _ptr(mask), _ptr(x0), _ptr(x_work), int(reps),
+                                    ctypes.byref(rep), _stream(stream)))
+        n = rep.n_candidates
+        return {"best": rep.best, "key": int(rep.key),
+                "candidates": [{"schedule": rep.schedule[i], "third_stream": rep.third_stream[i], "ms": rep.ms[i]}
+                               for i in range(n)]}
+
+    def tuned_schedule(self, params, bricks):
+        """(schedule, third_stream, tuned) a SCHED_TUNED call would use."""
+        bricks = np.ascontiguousarray(bricks, dtype=BRICK_DTYPE)
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib.rw_tuned_schedule(self.handle, ctypes.byref(params), len(bricks), bricks.ctypes.data_as(_vp),
+                                          ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, bool(c.value)
+
     def probe_read(self, src, passes, part, unroll=8, stream=None):
         """Queue the read probe over tensor ``src`` (``passes`` times, ``unroll``
         loads in flight per thread); ``part`` a float32 device tensor of
@@ -250,6 +291,38 @@ class Context:
                                                 bricks.ctypes.data_as(_vp), g.numel(), _ptr(g), _ptr(mask),
                                                 _ptr(x), _ptr(dl_dx), _ptr(dl_dg), _ptr(dl_dbeta), _ptr(lam),
                                                 _ptr(stats), _stream(stream)))
+
+
+class Graph:
+    """A captured rw_solve_bricks launch sequence (rw_graph_create); replay it
+    with ``launch``.  ``stream`` must not be the null stream."""
+
+    def __init__(self, ctx, params, bricks, g, mask, x, x64=None, stats=None, stream=None):
+        bricks = np.ascontiguousarray(bricks, dtype=BRICK_DTYPE)
+        h = _vp()
+        rc = lib.rw_graph_create(ctx.handle, ctypes.byref(params), len(bricks), bricks.ctypes.data_as(_vp),
+                                 g.numel(), _ptr(g), _ptr(mask), _ptr(x), _ptr(x64), _ptr(stats), _stream(stream),
+                                 ctypes.byref(h))
+        if rc != RW_OK:
+            raise RWError(rc, lib.rw_last_error(ctx.handle).decode())
+        self.handle = h
+        self._keep = (g, mask, x, x64, stats)    # the graph reads and writes these buffers
+
+    def launch(self, stream=None):
+        rc = lib.rw_graph_launch(self.handle, _stream(stream))
+        if rc != RW_OK:
+            raise RWError(rc, lib.rw_last_error(None).decode())
+
+    def close(self):
+        if self.handle:
+            lib.rw_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def stats_to_numpy(stats_tensor):

@@ -4,6 +4,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -93,13 +94,65 @@ int check_params(rw_ctx* ctx, const rw_solve_params* p) {
     if (!std::isfinite(p->refine_tol) || p->refine_tol < 0) return fail(ctx, RW_E_INVAL, "refine_tol must be >= 0");
     if (!std::isfinite(p->inner_tol) || p->inner_tol < 0) return fail(ctx, RW_E_INVAL, "inner_tol must be >= 0");
     if (!std::isfinite(p->stall_ratio) || p->stall_ratio < 1) return fail(ctx, RW_E_INVAL, "stall_ratio must be >= 1");
-    if (p->schedule < 0 || p->schedule > 4) return fail(ctx, RW_E_INVAL, "schedule must be 0, 1, 2, 3 or 4");
+    if (p->schedule < 0 || p->schedule > RW_SCHED_TUNED)
+        return fail(ctx, RW_E_INVAL, "schedule must be 0, 1, 2, 3, 4 or RW_SCHED_TUNED (5)");
     return RW_OK;
 }
 
 // Schedule of the streaming kernels for a requested schedule (0, 1 and 4:
 // two sweeps, 2 and 3: one sweep; 0, 3 and 4 also use the resident kernels).
 int stream_schedule(int requested) { return requested == 2 || requested == 3 ? 2 : 1; }
+
+// Signature of a batch for the tuned-schedule table: FNV-1a over the sorted
+// (nx, ny, nz, count) histogram of its box shapes, nrhs and precision.
+uint64_t batch_key(const rw_solve_params& p, int64_t n, const rw_brick* b) {
+    std::vector<std::array<int32_t, 3>> sh((size_t)n);
+    for (int64_t i = 0; i < n; ++i) sh[(size_t)i] = {b[i].nx, b[i].ny, b[i].nz};
+    std::sort(sh.begin(), sh.end());
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    };
+    for (size_t i = 0; i < sh.size();) {
+        size_t j = i;
+        while (j < sh.size() && sh[j] == sh[i]) ++j;
+        mix((uint64_t)(uint32_t)sh[i][0] | ((uint64_t)(uint32_t)sh[i][1] << 32));
+        mix((uint64_t)(uint32_t)sh[i][2] | ((uint64_t)(j - i) << 32));
+        i = j;
+    }
+    mix((uint64_t)p.nrhs | ((uint64_t)p.precision << 8));
+    return h;
+}
+
+// The schedule a call runs: a tuned request takes the ctx's measured winner
+// for its batch (the library's default, 0, when the batch was not tuned);
+// *no_third is that winner's stream choice.
+rw_solve_params resolve_schedule(const rw_ctx* ctx, const rw_solve_params& p, int64_t n, const rw_brick* b,
+                                 int* no_third) {
+    rw_solve_params q = p;
+    *no_third = ctx->plan_no_third;
+    if (p.schedule != RW_SCHED_TUNED) return q;
+    q.schedule = 0;
+    if (ctx->tuned.empty() || n == 0) return q;
+    const uint64_t key = batch_key(p, n, b);
+    for (const rw_ctx::Tuned& t : ctx->tuned)
+        if (t.key == key) {
+            q.schedule = t.schedule;
+            *no_third = *no_third || t.no_third;
+        }
+    return q;
+}
+
+// Sets ctx->plan_no_third for the duration of a call.
+struct NoThirdScope {
+    rw_ctx* ctx;
+    int saved;
+    NoThirdScope(rw_ctx* c, int v) : ctx(c), saved(c->plan_no_third) { c->plan_no_third = v; }
+    ~NoThirdScope() { ctx->plan_no_third = saved; }
+};
 
 // Validate host descriptors and build the launch list (largest box first).
 int build_list(rw_ctx* ctx, int64_t n, const rw_brick* bricks, int64_t n_voxels,
@@ -334,13 +387,24 @@ SolveLayout solve_layout(const rw_solve_params& p, int64_t n_bricks, int64_t n_v
     return L;
 }
 
-// rw_solve_bricks and rw_solve_bricks_noalloc.  noalloc: every buffer is
-// carved from the device's static scratch array (no allocation, no side
-// stream or event; all kernels on `stream`), else from the context's
-// buffers, grown on demand.
+// Where a solve's workspace comes from.  Default: the context's buffers,
+// grown on demand.  noalloc: the device's static scratch array (no
+// allocation, no side stream or event; all kernels on `stream`).  ext: a
+// buffer laid out by solve_layout that already holds the box list (a
+// captured graph's own workspace); nothing is allocated or copied.
+struct SolveMode {
+    bool noalloc = false;
+    char* ext = nullptr;
+    size_t ext_bytes = 0;
+};
+
+size_t layout_total(const SolveLayout& L) { return L.ws_bytes + L.aux_bytes + L.list_bytes + L.wts_bytes; }
+
+// rw_solve_bricks, rw_solve_bricks_noalloc and the captured graph's solve.
 int solve_bricks_impl(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
                       int64_t n_voxels, const float* g, const uint8_t* mask, float* x, double* x64,
-                      rw_brick_stats* stats, void* stream, bool noalloc) {
+                      rw_brick_stats* stats, void* stream, const SolveMode& mode) {
+    const bool noalloc = mode.noalloc;
     int rc = check_params(ctx, params);
     if (rc) return rc;
     std::vector<rwk::BrickDev> list;
@@ -348,7 +412,9 @@ int solve_bricks_impl(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bric
     if (rc) return rc;
     if (n_bricks == 0) return RW_OK;
     if (!g || !mask || !x) return fail(ctx, RW_E_INVAL, "g, mask and x must be non-NULL");
-    const rw_solve_params& p = *params;
+    int no_third = 0;
+    const rw_solve_params p = resolve_schedule(ctx, *params, n_bricks, bricks, &no_third);
+    NoThirdScope nts(ctx, no_third);
     const int R = p.nrhs;
     const bool fp64 = p.precision == RW_PREC_FP64;
     const bool need_x64 = fp64 || p.precision == RW_PREC_MIXED_REFINE;
@@ -359,7 +425,15 @@ int solve_bricks_impl(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bric
     const SolveLayout L = solve_layout(p, n_bricks, n_voxels, x64, pp);
     char *w, *aux, *blist;
     float* wts = nullptr;
-    if (noalloc) {
+    if (mode.ext) {
+        if (layout_total(L) > mode.ext_bytes) return fail(ctx, RW_E_INVAL, "workspace smaller than the batch's layout");
+        w = mode.ext;
+        aux = w + L.ws_bytes;
+        blist = aux + L.aux_bytes;
+        if (pp.wts_elems) wts = (float*)(blist + L.list_bytes);
+        rc = attach_side_streams(ctx, &pp);
+        if (rc) return rc;
+    } else if (noalloc) {
         const size_t total = L.ws_bytes + L.aux_bytes + L.list_bytes + L.wts_bytes;
         if (total > kScratchBytes)
             return fail(ctx, RW_E_INVAL,
@@ -430,7 +504,7 @@ int solve_bricks_impl(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bric
     a.wts = wts;
     hipError_t e;
     hipEvent_t* ev = nullptr;
-    const bool timed = ctx->timing && !noalloc;
+    const bool timed = ctx->timing && !noalloc && !mode.ext;
     if (timed) {
         for (int i = 0; i < 4; ++i)
             if (!ctx->ev[i]) {
@@ -603,8 +677,9 @@ int rw_solve_plan(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, 
     rc = build_list(ctx, n_bricks, bricks, n_voxels, &list);
     if (rc) return rc;
     if (n_bricks > 0 && !path) return fail(ctx, RW_E_INVAL, "path is NULL");
-    const rwk::PlanePlan pp =
-        plan_planes(ctx, &list, params->nrhs, params->precision == RW_PREC_FP64, params->schedule);
+    int no_third = 0;
+    const rw_solve_params pe = resolve_schedule(ctx, *params, n_bricks, bricks, &no_third);
+    const rwk::PlanePlan pp = plan_planes(ctx, &list, pe.nrhs, pe.precision == RW_PREC_FP64, pe.schedule);
     for (int64_t i = 0; i < n_bricks; ++i) {
         const int32_t slot = list[(size_t)i].slot;
         path[slot] = i < pp.n_dom ? RW_PATH_DOMAIN
@@ -624,7 +699,7 @@ int rw_solve_bricks(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
     if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
     ctx->err.clear();
     return guarded(ctx, [&] {
-        return solve_bricks_impl(ctx, params, n_bricks, bricks, n_voxels, g, mask, x, x64, stats, stream, false);
+        return solve_bricks_impl(ctx, params, n_bricks, bricks, n_voxels, g, mask, x, x64, stats, stream, SolveMode{});
     });
 }
 
@@ -634,7 +709,9 @@ int rw_solve_bricks_noalloc(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
     ctx->err.clear();
     return guarded(ctx, [&] {
-        return solve_bricks_impl(ctx, params, n_bricks, bricks, n_voxels, g, mask, x, x64, stats, stream, true);
+        SolveMode mode;
+        mode.noalloc = true;
+        return solve_bricks_impl(ctx, params, n_bricks, bricks, n_voxels, g, mask, x, x64, stats, stream, mode);
     });
 }
 
@@ -656,6 +733,10 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
     if (n_bricks < 0 || n_voxels < 0) return fail(ctx, RW_E_INVAL, "n_bricks and n_voxels must be >= 0");
     if (n_bricks == 0) return RW_OK;
     if (!bricks || !g || !mask || !x) return fail(ctx, RW_E_INVAL, "bricks, g, mask and x must be non-NULL");
+    // a tuned request takes the whole list's tuned schedule for every chunk
+    int no_third_unused = 0;
+    const rw_solve_params presolved = resolve_schedule(ctx, *params, n_bricks, bricks, &no_third_unused);
+    params = &presolved;
     const int R = params->nrhs;
     // default: 2^24 voxels, large enough that a chunk fills the GPU with
     // several waves of boxes (each chunk's solve ends with its slowest box)
@@ -866,7 +947,10 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     const size_t part_bytes = ((size_t)n_bricks * sizeof(double) + 255) & ~size_t(255);
     e = grow(ctx, &ctx->aux, &ctx->aux_bytes, state_bytes + part_bytes + rwk::domain_scratch_bytes(), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint partials");
-    rwk::PlanePlan pp = plan_planes(ctx, &list, 1, false, params->schedule);
+    int no_third = 0;
+    const rw_solve_params pe = resolve_schedule(ctx, *params, n_bricks, bricks, &no_third);
+    NoThirdScope nts(ctx, no_third);
+    rwk::PlanePlan pp = plan_planes(ctx, &list, 1, false, pe.schedule);
     rc = attach_side_streams(ctx, &pp);
     if (rc) return rc;
     rc = upload_list(ctx, list, s);
@@ -905,7 +989,7 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     sa.inner_tol = a.tol;
     sa.max_iter = a.max_iter;
     sa.precision = RW_PREC_MIXED;
-    sa.schedule = stream_schedule(params->schedule);
+    sa.schedule = stream_schedule(pe.schedule);
     rwk::domain_bind(sa, (char*)ctx->aux + state_bytes + part_bytes);
     rc = bind_weights(ctx, pp, &sa, s);
     if (rc) return rc;
@@ -941,6 +1025,228 @@ int rw_probe_copy(rw_ctx* ctx, void* dst, const void* src, int64_t bytes, void* 
     DevGuard dg(ctx->device);
     hipError_t e = rwk::launch_probe_copy(dst, src, bytes, (hipStream_t)stream);
     return e == hipSuccess ? RW_OK : hip_fail(ctx, e, "launching the copy probe");
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times candidate schedules of one batch and keeps the fastest.
+// ---------------------------------------------------------------------------
+
+int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                int64_t n_voxels, const float* g, const uint8_t* mask, const float* x0, float* x_work, int reps,
+                rw_tune_report* out, void* stream) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    return guarded(ctx, [&]() -> int {
+        int rc = check_params(ctx, params);
+        if (rc) return rc;
+        if (params->schedule == RW_SCHED_TUNED) return fail(ctx, RW_E_INVAL, "tune a concrete schedule (0..4)");
+        if (n_bricks < 1 || !x0 || !x_work || reps < 1 || reps > 64)
+            return fail(ctx, RW_E_INVAL, "need n_bricks >= 1, x0, x_work and 1 <= reps <= 64");
+        if (x0 == x_work) return fail(ctx, RW_E_INVAL, "x0 and x_work must differ");
+        std::vector<rwk::BrickDev> list;
+        rc = build_list(ctx, n_bricks, bricks, n_voxels, &list);
+        if (rc) return rc;
+        // candidates: the resident plans (MIXED, one rhs) with and without
+        // the third stream, every fitting box on the streamed-weights kernel,
+        // and the streaming schedules (two sweeps; one sweep)
+        struct Cand {
+            int schedule, no_third;
+        };
+        std::vector<Cand> cands;
+        if (params->nrhs == 1 && params->precision != RW_PREC_FP64)
+            cands = {{0, 0}, {0, 1}, {4, 0}, {3, 0}, {1, 0}};
+        else
+            cands = {{1, 0}, {2, 0}};
+        hipStream_t s = (hipStream_t)stream;
+        DevGuard dg(ctx->device);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            return hip_fail(ctx, e, "creating tuning events");
+        }
+        const size_t xbytes = (size_t)n_voxels * params->nrhs * sizeof(float);
+        const int saved_timing = ctx->timing;
+        ctx->timing = 0;
+        std::vector<float> med(cands.size(), 0.0f);
+        rc = RW_OK;
+        for (size_t c = 0; c < cands.size() && rc == RW_OK; ++c) {
+            rw_solve_params q = *params;
+            q.schedule = cands[c].schedule;
+            NoThirdScope nts(ctx, cands[c].no_third);
+            std::vector<float> t;
+            for (int r = 0; r <= reps && rc == RW_OK; ++r) {   // run 0 warms up
+                e = hipMemcpyAsync(x_work, x0, xbytes, hipMemcpyDeviceToDevice, s);
+                if (e == hipSuccess) e = hipEventRecord(e0, s);
+                if (e != hipSuccess) {
+                    rc = hip_fail(ctx, e, "resetting x for a tuning run");
+                    break;
+                }
+                rc = solve_bricks_impl(ctx, &q, n_bricks, bricks, n_voxels, g, mask, x_work, nullptr, nullptr, stream,
+                                       SolveMode{});
+                if (rc) break;
+                float ms = 0.0f;
+                e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) rc = hip_fail(ctx, e, "timing a tuning run");
+                if (r > 0) t.push_back(ms);
+            }
+            if (rc == RW_OK) {
+                std::sort(t.begin(), t.end());
+                med[c] = t[t.size() / 2];
+            }
+        }
+        ctx->timing = saved_timing;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return rc;
+        size_t best = 0;
+        for (size_t c = 1; c < cands.size(); ++c)
+            if (med[c] < med[best]) best = c;
+        const uint64_t key = batch_key(*params, n_bricks, bricks);
+        bool found = false;
+        for (rw_ctx::Tuned& t : ctx->tuned)
+            if (t.key == key) {
+                t = rw_ctx::Tuned{key, cands[best].schedule, cands[best].no_third, med[best]};
+                found = true;
+            }
+        if (!found) ctx->tuned.push_back(rw_ctx::Tuned{key, cands[best].schedule, cands[best].no_third, med[best]});
+        if (out) {
+            std::memset(out, 0, sizeof(*out));
+            out->n_candidates = (int32_t)cands.size();
+            out->best = (int32_t)best;
+            out->key = key;
+            for (size_t c = 0; c < cands.size(); ++c) {
+                out->schedule[c] = cands[c].schedule;
+                out->third_stream[c] = cands[c].no_third ? 0 : 1;
+                out->ms[c] = med[c];
+            }
+        }
+        return RW_OK;
+    });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Captured graphs of one batched solve.
+// ---------------------------------------------------------------------------
+
+struct rw_graph {
+    int device = 0;
+    void* ws = nullptr;          // the graph's own workspace (box list included)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static void graph_release(rw_graph* gr) {
+    if (!gr) return;
+    DevGuard dg(gr->device);
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    if (gr->ws) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(gr->ws);
+    }
+    delete gr;
+}
+
+extern "C" {
+
+int rw_graph_create(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                    int64_t n_voxels, const float* g, const uint8_t* mask, float* x, double* x64,
+                    rw_brick_stats* stats, void* stream, rw_graph** out) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    ctx->err.clear();
+    if (!out) return fail(ctx, RW_E_INVAL, "out is NULL");
+    *out = nullptr;
+    return guarded(ctx, [&]() -> int {
+        int rc = check_params(ctx, params);
+        if (rc) return rc;
+        std::vector<rwk::BrickDev> list;
+        rc = build_list(ctx, n_bricks, bricks, n_voxels, &list);
+        if (rc) return rc;
+        if (n_bricks == 0) return fail(ctx, RW_E_INVAL, "a graph needs at least one box");
+        if (!g || !mask || !x) return fail(ctx, RW_E_INVAL, "g, mask and x must be non-NULL");
+        int no_third = 0;
+        const rw_solve_params p = resolve_schedule(ctx, *params, n_bricks, bricks, &no_third);
+        NoThirdScope nts(ctx, no_third);
+        const bool fp64 = p.precision == RW_PREC_FP64;
+        rwk::PlanePlan pp = plan_planes(ctx, &list, p.nrhs, fp64, p.schedule);
+        if (pp.n_dom > 0)
+            return fail(ctx, RW_E_UNSUPPORTED,
+                        "a batch with single-domain boxes (the domain solver polls the host) cannot be captured");
+        const SolveLayout L = solve_layout(p, n_bricks, n_voxels, x64, pp);
+        hipStream_t s = (hipStream_t)stream;
+        DevGuard dg(ctx->device);
+        rw_graph* gr = new rw_graph();
+        gr->device = ctx->device;
+        hipError_t e = hipMalloc(&gr->ws, layout_total(L));
+        if (e != hipSuccess) {
+            graph_release(gr);
+            return hip_fail(ctx, e, "allocating the graph's workspace");
+        }
+        // the box list goes into the workspace once, before the capture
+        char* blist = (char*)gr->ws + L.ws_bytes + L.aux_bytes;
+        e = hipMemcpy(blist, list.data(), list.size() * sizeof(rwk::BrickDev), hipMemcpyHostToDevice);
+        rc = e == hipSuccess ? attach_side_streams(ctx, &pp) : hip_fail(ctx, e, "uploading the box list");
+        if (rc) {
+            graph_release(gr);
+            return rc;
+        }
+        const int saved_timing = ctx->timing;
+        ctx->timing = 0;
+        e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) {
+            ctx->timing = saved_timing;
+            graph_release(gr);
+            return hip_fail(ctx, e, "beginning stream capture (the stream must not be the null stream)");
+        }
+        SolveMode mode;
+        mode.ext = (char*)gr->ws;
+        mode.ext_bytes = layout_total(L);
+        rc = solve_bricks_impl(ctx, &p, n_bricks, bricks, n_voxels, g, mask, x, x64, stats, stream, mode);
+        e = hipStreamEndCapture(s, &gr->graph);
+        ctx->timing = saved_timing;
+        if (rc == RW_OK && e != hipSuccess) rc = hip_fail(ctx, e, "ending stream capture");
+        if (rc == RW_OK) {
+            e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) rc = hip_fail(ctx, e, "instantiating the graph");
+        }
+        if (rc) {
+            graph_release(gr);
+            return rc;
+        }
+        *out = gr;
+        return RW_OK;
+    });
+}
+
+int rw_graph_launch(rw_graph* gr, void* stream) {
+    if (!gr || !gr->exec) return fail(nullptr, RW_E_INVAL, "graph is NULL");
+    DevGuard dg(gr->device);
+    hipError_t e = hipGraphLaunch(gr->exec, (hipStream_t)stream);
+    return e == hipSuccess ? RW_OK : fail(nullptr, RW_E_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+}
+
+void rw_graph_free(rw_graph* gr) { graph_release(gr); }
+
+int rw_tuned_schedule(const rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
+                      int32_t* schedule, int32_t* third_stream, int32_t* tuned) {
+    if (!ctx || !params || !schedule || !third_stream || !tuned || n_bricks < 0 || (n_bricks > 0 && !bricks))
+        return fail(nullptr, RW_E_INVAL, "bad arguments");
+    rw_solve_params q = *params;
+    q.schedule = RW_SCHED_TUNED;
+    int no_third = 0;
+    const rw_solve_params r = resolve_schedule(ctx, q, n_bricks, bricks, &no_third);
+    *schedule = r.schedule;
+    *third_stream = no_third ? 0 : 1;
+    *tuned = 0;
+    for (const rw_ctx::Tuned& t : ctx->tuned)
+        if (n_bricks > 0 && t.key == batch_key(*params, n_bricks, bricks)) *tuned = 1;
+    return RW_OK;
 }
 
 }  // extern "C"

@@ -6,6 +6,7 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "rwseg.h"
 
@@ -67,6 +68,14 @@ struct rw_ctx {
     int plan_no_third = 0;
     // this device's copy of the static scratch of rw_solve_bricks_noalloc
     void* scratch = nullptr;
+    // autotuned schedules: per batch signature (box shapes, nrhs,
+    // precision) the fastest candidate rw_autotune measured
+    struct Tuned {
+        uint64_t key;
+        int32_t schedule, no_third;
+        float ms;
+    };
+    std::vector<Tuned> tuned;
 };
 
 namespace rwk {
