@@ -540,7 +540,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--schedule", type=int, default=0, help="CG schedule (rw_solve_params.schedule): 0 library choice, 1 two-sweep streaming, 2 one-sweep streaming, 3 as 0 with 2, 4 streamed-weights resident wherever it fits")
+    ap.add_argument("--schedule", type=int, default=-1, help="CG schedule (rw_solve_params.schedule): -1 autotune the batch (rw_autotune) and run the tuned schedule (default), 0 library choice, 1 two-sweep streaming, 2 one-sweep streaming, 3 as 0 with 2, 4 streamed-weights resident wherever it fits")
     ap.add_argument("--no-extras", action="store_true", help="skip the further workloads (sphere, tubes, blobs, shells, cells)")
     ap.add_argument("--shells-dims", default="256,256,128", help="nested-shell volume dims nx,ny,nz")
     ap.add_argument("--only", choices=EXTRAS, default=None,
@@ -591,9 +591,24 @@ def main():
     st = torch.empty((N_BOXES, 32), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
+    # the library's autotuner times its candidate schedules on this batch
+    # (outside the timed region) and the timed steps run its winner
+    tune = None
+    sched = args.schedule
+    if sched < 0:
+        xw = torch.empty_like(x0)
+        tune = {}
+        for prec, name in ((rwg.PREC_MIXED, "mixed"), (rwg.PREC_FP64, "fp64")):
+            if prec == rwg.PREC_FP64 and args.no_fp64:
+                continue
+            pt = rwg.solve_params(beta=BETA, eps=EPS, tol=TOL, precision=prec, refine_max=1, inner_tol=1e-4)
+            tune[name] = ctx.autotune(pt, bricks, g, m, x0, xw, reps=2, stream=stream)
+        del xw
+        sched = rwg.SCHED_TUNED
+
     def run(prec, steps, warmup):
         p = rwg.solve_params(beta=BETA, eps=EPS, tol=TOL, precision=prec, refine_max=1, inner_tol=1e-4,
-                             schedule=args.schedule)
+                             schedule=sched)
         for _ in range(warmup):
             x.copy_(x0)
             ctx.rw_solve_bricks(p, bricks, g, m, x, stats=st, stream=stream)
@@ -616,6 +631,25 @@ def main():
         vox_it = int(np.sum(sizes * iters))
         main = sizes * s["iters"].astype(np.int64)
         path = ctx.solve_plan(p, bricks, g.numel())
+        # eager launches queued back to back against a captured graph of
+        # the same solve (the x reset stays outside the graph)
+        gs = torch.cuda.Stream()
+        xg = x0.clone()
+        with torch.cuda.stream(gs):
+            graph = rwg.Graph(ctx, p, bricks, g, m, xg, stream=gs)
+            for _ in range(warmup):
+                xg.copy_(x0)
+                graph.launch(stream=gs)
+        gs.synchronize()
+        tg0 = time.perf_counter()
+        with torch.cuda.stream(gs):
+            for _ in range(steps):
+                xg.copy_(x0)
+                graph.launch(stream=gs)
+        gs.synchronize()
+        graph_wall = (time.perf_counter() - tg0) / steps
+        graph_same = bool(torch.equal(xg, x))
+        graph.close()
         hbm = (path == rwg.PATH_STREAM) | (path == rwg.PATH_STREAM_GLOBAL)
         sw = path == rwg.PATH_RESIDENT_STREAMED
         lds = path == rwg.PATH_RESIDENT
@@ -623,6 +657,8 @@ def main():
         # streamed-weights boxes on one stream (stream_ms), LDS-resident boxes
         # on the other (resident_ms)
         return dict(wall=wall, kern=mean["pcg_ms"], t=mean, vox_it=vox_it, vox_it_main=int(main.sum()),
+                    graph_wall=graph_wall, graph_same=graph_same, schedule=ctx.tuned_schedule(p, bricks),
+                    res_vox=int(sizes[lds].sum()),
                     vox_it_a=int(main[hbm | sw].sum()), vox_it_sw=int(main[sw].sum()), vox_it_hbm=int(main[hbm].sum()),
                     vox_it_sw1=int(main[sw & (sizes > 17408)].sum()), vox_it_sw2=int(main[sw & (sizes <= 17408)].sum()),
                     vox_it_res=int(main[lds].sum()), n_hbm=int(hbm.sum()), n_sw=int(sw.sum()), n_res=int(lds.sum()),
@@ -651,7 +687,7 @@ def main():
     ceilings = measure_ceilings(torch, rwg, ctx)
     # memory bytes of the whole PCG phase, each box at its kernel's own
     # algorithmic bytes (a cross-check that must stay below the HBM peak)
-    n_res_vox = int(sizes[ctx.solve_plan(rwg.solve_params(), bricks, g.numel()) == rwg.PATH_RESIDENT].sum())
+    n_res_vox = mixed["res_vox"]
     phase_bytes = (SEGMENT_BYTES_PER_VOXEL_ITER * mixed["vox_it_sw"] + BYTES_PER_VOXEL_ITER * mixed["vox_it_hbm"]
                    + RESIDENT_BYTES_PER_VOXEL * n_res_vox)
     traffic = traffic_from_profile()
@@ -708,6 +744,12 @@ def main():
                                    "voxel_iters_per_s": mixed["vox_it_res"] / t["resident_ms"] if t["resident_ms"] else None,
                                    "note": "on-chip: p and the edge weights in LDS, x and r in registers; HBM is "
                                            "read once per solve, so no HBM roofline applies"},
+                  "schedule": {"requested": "tuned" if args.schedule < 0 else args.schedule,
+                               "ran": mixed["schedule"][0], "third_stream": mixed["schedule"][1],
+                               "autotune": tune},
+                  "graph_replay": {"ms_per_step": mixed["graph_wall"] * 1e3,
+                                   "x_equal_to_eager": mixed["graph_same"],
+                                   "note": "the same solve captured once (rw_graph_create) and replayed K times"},
                   "mean_iters": float(s["iters"].mean()), "max_iters": int(s["iters"].max()),
                   "refined_boxes": int((s["refine_steps"] > 0).sum()),
                   "status_counts": {rwg.STATUS_NAMES[k]: int((s["status"] == k).sum()) for k in np.unique(s["status"])},
