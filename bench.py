@@ -34,6 +34,8 @@ SEGMENT_BYTES_PER_VOXEL_ITER = 16  # streamed-weights resident kernel: read w+x,
 RESIDENT_BYTES_PER_VOXEL = 13  # weights-in-LDS kernel: read g, mask, x once per solve, write x once
 BETA, EPS, TOL = 128.0, 1e-6, 1e-6
 N_BOXES, SEED = 8192, 3
+# workloads run only on request (--only NAME): minutes of GPU time
+ON_REQUEST = ("shells_full",)
 EXTRAS = ("plain_sphere_64", "tubes_512_hierarchy", "blobs_512x32_adjoint", "shells_hierarchy_incremental",
           "cells_256_ablation", "cells_brick_growth", "pruning_table_256", "stress_streamed_from_host")
 
@@ -361,6 +363,107 @@ def bench_shells(torch, rwg, ctx, dims=(256, 256, 128), levels=3):
             "label_accuracy_vs_truth": acc, "incremental_rules": rules, "generate_s": gen_s}
 
 
+def _replay_worker(args):
+    """cpu_baseline leg: one level-0 box of the full-size shell run rebuilt
+    by the oracle from the GPU's level-1 map and solved exactly."""
+    from threadpoolctl import threadpool_limits
+    from oracle import hierarchy as H
+    vol_box, vrange, lab_box, border, up_box, p, rel = args
+    with threadpool_limits(1):
+        g_box = H.normalize(vol_box, vrange=vrange)
+        xb = H._solve(g_box, lab_box, border, up_box, p)
+    return xb[(slice(None),) + rel]
+
+
+def bench_shells_full(torch, rwg, ctx, dims=(2048, 2048, 1024), levels=5, n_replay=64, cpu_leg=True):
+    """The large multi-class incremental configuration at full size:
+    2048 x 2048 x 1024 uint16 (8 GiB), four classes (background and three
+    nested ellipsoidal shells, sigma 250 noise plus 1/f noise), 5 levels,
+    s = 32, e = 1.25, three right-hand sides per box, hom pruning t_hom 0.3,
+    mixed tol 1e-5; then a 2000-voxel class-2 stroke solved incrementally
+    under the dirty-brick rule and the node rule.  The volume is generated
+    on the device (``synth.shell_volume_device``).  cpu_baseline leg: sampled
+    solved level-0 boxes of the full run rebuilt by the oracle from the
+    GPU's level-1 map and solved exactly (max error of the GPU cores)."""
+    import numpy as np
+    import synth
+    from oracle import hierarchy as H
+    t0 = time.time()
+    vol, labels, seeds, geo = synth.shell_volume_device(dims, seed=5, n_per_class=50)
+    stroke = synth.stroke_geo(geo, cls=2, length=2000, seed=6)
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    kw = dict(brick=32, expand=1.25, beta=BETA, eps=EPS, tol=1e-5, precision=1, n_classes=4, prune_hom=1,
+              prune_dt=0, t_hom=0.3)
+    pyr_ms, pyr = _best_ms(torch, lambda: rwg.Pyramid(ctx, vol, levels), 1)
+    print("bench.py: shells_full pyramid built", file=sys.stderr, flush=True)
+    full_ms, res = _best_ms(torch, lambda: rwg.segment(pyr, seeds, **kw), 1)
+    print("bench.py: shells_full full run done", file=sys.stderr, flush=True)
+    more = np.concatenate([seeds, stroke])
+    inc = {}
+    for name, mode in (("dirty", 0), ("node", rwg.INC_NODE)):
+        ms, r = _best_ms(torch, lambda: rwg.segment(pyr, more, prev=res, incremental=mode, **kw), 1)
+        sr = r.stats()
+        inc[name] = {"ms": ms, "solved": sr["solved"], "voxel_iters": int(sum(sr["voxel_iters"])),
+                     "kept": [int(((r.flags(l) & rwg.F_KEPT) != 0).sum().item()) for l in range(levels)]}
+        del r
+        print(f"bench.py: shells_full incremental ({name}) done", file=sys.stderr, flush=True)
+    st = res.stats()
+    lab = res.materialize(0, 0, prob=False, labels=True)[1]
+    acc = float((lab == labels).float().mean().item())
+    del lab
+    out = {"workload": f"nested shells {dims[0]}x{dims[1]}x{dims[2]} uint16 (generated on the device), 4 classes "
+                       f"(3 rhs), {levels} levels, s=32, e=1.25, hom pruning t_hom 0.3, mixed tol 1e-5; then a "
+                       "2000-voxel class-2 stroke solved incrementally",
+           "generate_s": gen_s, "pyramid_ms": pyr_ms, "full_ms": full_ms,
+           "full_voxel_iters_per_s": float(sum(st["voxel_iters"]) / (full_ms / 1e3)),
+           "end_to_end_voxels_per_s": float(np.prod(dims) / (full_ms / 1e3)),
+           "bricks": st["bricks"], "full_computed": st["computed"], "full_solved": st["solved"],
+           "full_not_converged": st["not_converged"], "full_max_iters": st["max_iters"],
+           "label_accuracy_vs_truth": acc, "incremental": inc}
+    if cpu_leg:
+        # sampled solved level-0 boxes of the full run, replayed by the oracle
+        import multiprocessing as mp
+        p = H.Params(levels=levels, brick=32, expand=1.25, beta=BETA, eps=EPS, n_classes=4, method="pcg",
+                     tol=1e-12)
+        f0 = res.flags(0).cpu().numpy()
+        solved = np.argwhere((f0 & rwg.F_SOLVED) != 0)
+        rng = np.random.default_rng(0)
+        picks = solved[rng.choice(len(solved), min(n_replay, len(solved)), replace=False)]
+        v16 = vol.view(torch.int16)
+        # the uint16 range of the whole volume (stored as int16 bits)
+        vr = (int(min((v16[z:z + 64].to(torch.int32) & 0xFFFF).min().item() for z in range(0, dims[2], 64))),
+              int(max((v16[z:z + 64].to(torch.int32) & 0xFFFF).max().item() for z in range(0, dims[2], 64))))
+        m1 = res.level_map(1)
+        m0 = res.level_map(0)
+        d0 = (dims[2], dims[1], dims[0])
+        d1 = tuple(m1.shape[:3])
+        jobs, cores = [], []
+        for b in map(tuple, picks):
+            core, box = H.brick_box(b, d0, 32, 1.25)
+            lo1 = tuple(max((lo - 1) // 2, 0) for lo, _ in box)
+            hi1 = tuple(min(hi // 2 + 1, n) for (_, hi), n in zip(box, d1))
+            crop = m1[lo1[0]:hi1[0], lo1[1]:hi1[1], lo1[2]:hi1[2]].permute(3, 0, 1, 2).cpu().numpy()
+            up_box = H.upsample_box(crop, d0, box, origin=lo1, parent_shape=d1)
+            vb = v16[box[0][0]:box[0][1], box[1][0]:box[1][1], box[2][0]:box[2][1]].cpu().numpy().view(np.uint16)
+            lab_box = H.rasterize_box(seeds, 0, d0, box)
+            rel = tuple(slice(c0 - b0, c1 - b0) for (c0, c1), (b0, _) in zip(core, box))
+            jobs.append((vb, vr, lab_box, H.border_layer(box, d0), up_box, p, rel))
+            cores.append(m0[core[0][0]:core[0][1], core[1][0]:core[1][1], core[2][0]:core[2][1]]
+                         .permute(3, 0, 1, 2).cpu().numpy())
+        del m0, m1
+        t1 = time.time()
+        workers = min(os.cpu_count() or 1, 16)
+        with mp.get_context("fork").Pool(workers) as pool:
+            refs = pool.map(_replay_worker, jobs, chunksize=1)
+        errs = [float(np.max(np.abs(c - r))) for c, r in zip(cores, refs)]
+        out["oracle_replay"] = {"bricks": len(errs), "max_abs_err": max(errs), "median_abs_err": float(np.median(errs)),
+                                "cpu_s": time.time() - t1, "cores": workers,
+                                "note": "level-0 boxes of the full run: oracle set-up from the GPU's level-1 map, "
+                                        "FP64 PCG to 1e-12 per class; error of the GPU cores over the three classes"}
+    return out
+
+
 def bench_cells_ablation(torch, rwg, ctx, n=256, levels=4):
     """Ablations on the cells scenario (spheres covering 1 % of the volume,
     0.7 on 0.3 plus noise 0.1): brick size s in {16, 32, 64} (boxes 20^3,
@@ -543,7 +646,7 @@ def main():
     ap.add_argument("--schedule", type=int, default=-1, help="CG schedule (rw_solve_params.schedule): -1 autotune the batch (rw_autotune) and run the tuned schedule (default), 0 library choice, 1 two-sweep streaming, 2 one-sweep streaming, 3 as 0 with 2, 4 streamed-weights resident wherever it fits")
     ap.add_argument("--no-extras", action="store_true", help="skip the further workloads (sphere, tubes, blobs, shells, cells)")
     ap.add_argument("--shells-dims", default="256,256,128", help="nested-shell volume dims nx,ny,nz")
-    ap.add_argument("--only", choices=EXTRAS, default=None,
+    ap.add_argument("--only", choices=EXTRAS + ON_REQUEST, default=None,
                     help="run one further workload alone and print its JSON (for profiling; no headline line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -572,6 +675,8 @@ def main():
             return bench_cells_growth(torch, rwg, ctx)
         if name == "pruning_table_256":
             return bench_pruning_table(torch, rwg, ctx)
+        if name == "shells_full":
+            return bench_shells_full(torch, rwg, ctx, cpu_leg=not args.no_cpu_baseline)
         if name == "stress_streamed_from_host":
             return bench_streamed(torch, rwg, ctx)
         return bench_shells(torch, rwg, ctx, dims=shell_dims)

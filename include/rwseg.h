@@ -253,9 +253,11 @@ int rw_last_timing(rw_ctx* ctx, rw_timing* out);
 /*
  * Autotuner (a batching pattern, not a step of the method).  Times candidate
  * schedules of rw_solve_bricks on this batch and records the fastest on ctx
- * for RW_SCHED_TUNED: for MIXED or MIXED_REFINE with one rhs schedule 0 with
- * and without the second streamed-weights launch on a stream of its own,
- * schedule 4, schedule 3 and schedule 1; otherwise schedules 1 and 2.  Each
+ * for RW_SCHED_TUNED: for MIXED or MIXED_REFINE with one rhs schedule 0
+ * (as is, without the second streamed-weights launch on a stream of its
+ * own, and with the small resident boxes' weights in LDS instead of
+ * registers), schedule 4, schedule 3 and schedule 1; otherwise schedules 1
+ * and 2.  Each
  * candidate runs 1 + reps solves of the batch from x0 (dev, copied into
  * x_work before every run; both [n_voxels * nrhs]); the median of the reps
  * timed runs (HIP events on `stream`) ranks it.  params->schedule must be
@@ -269,17 +271,19 @@ typedef struct rw_tune_report {
     int32_t best;             /* index of the fastest candidate */
     int32_t schedule[8];      /* rw_solve_params.schedule of each candidate */
     int32_t third_stream[8];  /* 1: the second streamed-weights launch may take a stream of its own */
+    int32_t weights_in_registers[8];  /* 1: small resident boxes keep their edge weights in registers
+                                         (RW_PATH_RESIDENT, k_pcg_resr), 0: in LDS (k_pcg_resw) */
     float ms[8];              /* median milliseconds per solve */
     uint64_t key;             /* signature of the batch */
 } rw_tune_report;
 int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
                 int64_t n_voxels, const float* g, const uint8_t* mask, const float* x0, float* x_work, int reps,
                 rw_tune_report* out, void* stream);
-/* Host-only: the schedule a RW_SCHED_TUNED call would run for this batch
- * (*tuned = 1 when ctx holds a measured entry for it, else 0 and the
- * default). */
+/* Host-only: the schedule and plan choices a RW_SCHED_TUNED call would run
+ * for this batch (*tuned = 1 when ctx holds a measured entry for it, else 0
+ * and the default); regs may be NULL. */
 int rw_tuned_schedule(const rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
-                      int32_t* schedule, int32_t* third_stream, int32_t* tuned);
+                      int32_t* schedule, int32_t* third_stream, int32_t* regs, int32_t* tuned);
 
 /*
  * Captured graph of one batched solve (a batching pattern, not a step of the
@@ -307,8 +311,9 @@ void rw_graph_free(rw_graph* graph);
 enum rw_path {
     RW_PATH_STREAM = 0,          /* one workgroup per box, vectors streamed from HBM, LDS window march */
     RW_PATH_STREAM_GLOBAL = 1,   /* the same without the LDS window (planes wider than it holds) */
-    RW_PATH_RESIDENT = 2,        /* one workgroup per box, p and the edge weights in LDS (boxes up
-                                    to 10240 voxels), x and r in registers */
+    RW_PATH_RESIDENT = 2,        /* one workgroup per box, p in LDS, x and r in registers, the edge
+                                    weights in registers (boxes up to 5120 voxels) or in LDS (up
+                                    to 10240 voxels) */
     RW_PATH_DOMAIN = 3,          /* large single box: many workgroups, host-driven iteration */
     RW_PATH_RESIDENT_STREAMED = 4 /* one workgroup per box, p in LDS, r in registers; the edge
                                     weights and 1/d are computed once into a per-box buffer and

@@ -93,12 +93,13 @@ class Result:
     reused: list = field(default_factory=list)       # per level bool (node rule: taken over from prev)
 
 
-def normalize(volume):
-    """Level-0 intensities in [0, 1] (float64)."""
+def normalize(volume, vrange=None):
+    """Level-0 intensities in [0, 1] (float64).  ``vrange`` = (min, max) of
+    the whole uint16 volume when ``volume`` is only a part of it."""
     v = np.asarray(volume)
     if v.dtype == np.uint16:
         v = v.astype(np.float64)
-        lo, hi = v.min(), v.max()
+        lo, hi = (v.min(), v.max()) if vrange is None else (float(vrange[0]), float(vrange[1]))
         return (v - lo) / (hi - lo) if hi > lo else np.zeros_like(v)
     return np.clip(v.astype(np.float64), 0.0, 1.0)
 
@@ -165,6 +166,31 @@ def upsample(parent, child_shape):
     return out
 
 
+def upsample_box(parent, child_shape, box, origin=(0, 0, 0), parent_shape=None):
+    """``upsample(parent, child_shape)`` restricted to ``box`` ((lo, hi) per
+    axis z, y, x): the same per-axis taps, evaluated only at the box's child
+    voxels (for levels too large to upsample whole).  ``parent`` may be a
+    crop of the parent level that starts at voxel ``origin`` of a level of
+    spatial shape ``parent_shape`` (the taps follow the whole level); the
+    crop must hold every parent voxel the box's taps use."""
+    parent = np.asarray(parent, dtype=np.float64)
+    if parent_shape is None:
+        parent_shape = parent.shape[-3:]
+    out = parent
+    for axis, n, (lo, hi), o, npar in zip((-3, -2, -1), child_shape, box, origin, parent_shape):
+        i0, i1, t = _axis_taps(n, npar)
+        i0, i1, t = i0[lo:hi] - o, i1[lo:hi] - o, t[lo:hi]
+        if i0.min() < 0 or i1.max() >= out.shape[axis]:
+            raise ValueError("the parent crop does not cover the box")
+        a0 = np.take(out, i0, axis=axis)
+        a1 = np.take(out, i1, axis=axis)
+        shape = [1] * out.ndim
+        shape[axis] = hi - lo
+        tt = t.reshape(shape)
+        out = (1.0 - tt) * a0 + tt * a1
+    return out
+
+
 def rasterize(seeds, level, dims):
     """Level-l seed grid: -1 unseeded, k >= 0 class k, -2 conflict."""
     lab = np.full(dims, -1, dtype=np.int64)
@@ -178,6 +204,29 @@ def rasterize(seeds, level, dims):
     for x, y, z, k in zip(vx, vy, vz, s[:, 3].astype(np.int64)):
         if not (0 <= z < dims[0] and 0 <= y < dims[1] and 0 <= x < dims[2]):
             continue
+        cur = lab[z, y, x]
+        if cur == -1:
+            lab[z, y, x] = k
+        elif cur >= 0 and cur != k:
+            lab[z, y, x] = -2
+    return lab
+
+
+def rasterize_box(seeds, level, dims, box):
+    """``rasterize(seeds, level, dims)`` restricted to ``box`` ((lo, hi) per
+    axis z, y, x), without building the whole level's grid."""
+    shape = tuple(hi - lo for lo, hi in box)
+    lab = np.full(shape, -1, dtype=np.int64)
+    if seeds is None or len(seeds) == 0:
+        return lab
+    s = np.asarray(seeds, dtype=np.float64)
+    f = 2.0 ** level
+    v = [np.floor(s[:, a] / f).astype(np.int64) for a in (2, 1, 0)]   # z, y, x
+    inside = np.ones(len(s), dtype=bool)
+    for a in range(3):
+        inside &= (v[a] >= box[a][0]) & (v[a] < box[a][1]) & (v[a] >= 0) & (v[a] < dims[a])
+    for i in np.flatnonzero(inside):
+        z, y, x, k = v[0][i] - box[0][0], v[1][i] - box[1][0], v[2][i] - box[2][0], int(s[i, 3])
         cur = lab[z, y, x]
         if cur == -1:
             lab[z, y, x] = k

@@ -130,10 +130,17 @@ uint64_t batch_key(const rw_solve_params& p, int64_t n, const rw_brick* b) {
 // The schedule a call runs: a tuned request takes the ctx's measured winner
 // for its batch (the library's default, 0, when the batch was not tuned);
 // *no_third is that winner's stream choice.
+// Plan choices a schedule entry carries beside the schedule number.
+struct PlanChoice {
+    int no_third = 0;   // both streamed-weights launches on one stream
+    int no_regs = 0;    // small resident boxes keep their weights in LDS
+};
+
 rw_solve_params resolve_schedule(const rw_ctx* ctx, const rw_solve_params& p, int64_t n, const rw_brick* b,
-                                 int* no_third) {
+                                 PlanChoice* pc) {
     rw_solve_params q = p;
-    *no_third = ctx->plan_no_third;
+    pc->no_third = ctx->plan_no_third;
+    pc->no_regs = ctx->plan_no_regs;
     if (p.schedule != RW_SCHED_TUNED) return q;
     q.schedule = 0;
     if (ctx->tuned.empty() || n == 0) return q;
@@ -141,17 +148,25 @@ rw_solve_params resolve_schedule(const rw_ctx* ctx, const rw_solve_params& p, in
     for (const rw_ctx::Tuned& t : ctx->tuned)
         if (t.key == key) {
             q.schedule = t.schedule;
-            *no_third = *no_third || t.no_third;
+            pc->no_third = pc->no_third || t.no_third;
+            pc->no_regs = pc->no_regs || t.no_regs;
         }
     return q;
 }
 
-// Sets ctx->plan_no_third for the duration of a call.
-struct NoThirdScope {
+// Sets the context's plan choices for the duration of a call.
+struct PlanScope {
     rw_ctx* ctx;
-    int saved;
-    NoThirdScope(rw_ctx* c, int v) : ctx(c), saved(c->plan_no_third) { c->plan_no_third = v; }
-    ~NoThirdScope() { ctx->plan_no_third = saved; }
+    int saved_third, saved_regs;
+    PlanScope(rw_ctx* c, const PlanChoice& pc)
+        : ctx(c), saved_third(c->plan_no_third), saved_regs(c->plan_no_regs) {
+        c->plan_no_third = pc.no_third;
+        c->plan_no_regs = pc.no_regs;
+    }
+    ~PlanScope() {
+        ctx->plan_no_third = saved_third;
+        ctx->plan_no_regs = saved_regs;
+    }
 };
 
 // Validate host descriptors and build the launch list (largest box first).
@@ -204,8 +219,8 @@ int plan_cols_of(const rw_ctx* ctx, const rw_brick* b, int64_t n, int nrhs, bool
 
 // Kernel group of one box (the domain cap aside): 0 domain solver, 1 global
 // march, 2 plane march, 3 and 4 resident (p in LDS, weights streamed) above
-// and up to kResSpanG0 voxels, 5 resident (weights in LDS), 6 the same for
-// small boxes.
+// and up to kResSpanG0 voxels, 5 resident (weights in LDS), 6 and 7 resident
+// (weights in registers) above and up to kResSmallVox voxels.
 int group_of(const rw_ctx* ctx, int nx, int ny, int nz, int lim, bool res_ok, bool prefer_g, bool dom_left) {
     rwk::BrickDev b{};
     b.nx = nx;
@@ -217,7 +232,9 @@ int group_of(const rw_ctx* ctx, int nx, int ny, int nz, int lim, bool res_ok, bo
     const bool dom = vox < (int64_t(1) << 31) && (vox >= rwk::kDomBigVox || (wide && vox >= rwk::kDomMinVox));
     if (dom && dom_left) return 0;
     if (res_ok && prefer_g && rwk::resident_g_fits(b, ctx->lds_limit)) return vox > rwk::kResSpanG0 ? 3 : 4;
-    if (res_ok && rwk::resident_w_fits(b, ctx->lds_limit)) return vox <= rwk::kResSmallVox ? 6 : 5;
+    if (res_ok && !ctx->plan_no_regs && rwk::resident_r_fits(b, ctx->lds_limit))
+        return vox <= rwk::kResSmallVox ? 7 : 6;
+    if (res_ok && rwk::resident_w_fits(b, ctx->lds_limit)) return 5;
     if (res_ok && rwk::resident_g_fits(b, ctx->lds_limit)) return vox > rwk::kResSpanG0 ? 3 : 4;
     return wide ? 1 : 2;
 }
@@ -254,7 +271,7 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     std::iota(idx.begin(), idx.end(), size_t(0));
     std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return grp[a] < grp[b]; });
     std::vector<rwk::BrickDev> sorted(list->size());
-    int64_t cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+    int64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (size_t i = 0; i < idx.size(); ++i) {
         sorted[i] = (*list)[idx[i]];
         cnt[grp[idx[i]]] += 1;
@@ -268,12 +285,12 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     pp.n_rl = 0;
     int64_t b0 = pp.n_res;
     pp.wts_elems = 0;
-    for (int gi = 3; gi <= 6; ++gi) {
+    for (int gi = 3; gi <= 7; ++gi) {
         if (cnt[gi] == 0) continue;
         rwk::PlanePlan::ResLaunch& L = pp.rl[pp.n_rl++];
         L.b0 = b0;
         L.b1 = b0 + cnt[gi];
-        L.kind = gi <= 4 ? 2 : 1;
+        L.kind = gi <= 4 ? 2 : gi == 5 ? 1 : 3;
         L.max_voxels = 0;
         L.max_plane = 0;
         L.px = 32;
@@ -412,9 +429,9 @@ int solve_bricks_impl(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bric
     if (rc) return rc;
     if (n_bricks == 0) return RW_OK;
     if (!g || !mask || !x) return fail(ctx, RW_E_INVAL, "g, mask and x must be non-NULL");
-    int no_third = 0;
-    const rw_solve_params p = resolve_schedule(ctx, *params, n_bricks, bricks, &no_third);
-    NoThirdScope nts(ctx, no_third);
+    PlanChoice pc;
+    const rw_solve_params p = resolve_schedule(ctx, *params, n_bricks, bricks, &pc);
+    PlanScope pls(ctx, pc);
     const int R = p.nrhs;
     const bool fp64 = p.precision == RW_PREC_FP64;
     const bool need_x64 = fp64 || p.precision == RW_PREC_MIXED_REFINE;
@@ -677,8 +694,9 @@ int rw_solve_plan(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, 
     rc = build_list(ctx, n_bricks, bricks, n_voxels, &list);
     if (rc) return rc;
     if (n_bricks > 0 && !path) return fail(ctx, RW_E_INVAL, "path is NULL");
-    int no_third = 0;
-    const rw_solve_params pe = resolve_schedule(ctx, *params, n_bricks, bricks, &no_third);
+    PlanChoice pc;
+    const rw_solve_params pe = resolve_schedule(ctx, *params, n_bricks, bricks, &pc);
+    PlanScope pls(ctx, pc);
     const rwk::PlanePlan pp = plan_planes(ctx, &list, pe.nrhs, pe.precision == RW_PREC_FP64, pe.schedule);
     for (int64_t i = 0; i < n_bricks; ++i) {
         const int32_t slot = list[(size_t)i].slot;
@@ -734,9 +752,10 @@ int rw_solve_bricks_streamed(rw_ctx* ctx, const rw_solve_params* params, int64_t
     if (n_bricks == 0) return RW_OK;
     if (!bricks || !g || !mask || !x) return fail(ctx, RW_E_INVAL, "bricks, g, mask and x must be non-NULL");
     // a tuned request takes the whole list's tuned schedule for every chunk
-    int no_third_unused = 0;
-    const rw_solve_params presolved = resolve_schedule(ctx, *params, n_bricks, bricks, &no_third_unused);
+    PlanChoice pc_all;
+    const rw_solve_params presolved = resolve_schedule(ctx, *params, n_bricks, bricks, &pc_all);
     params = &presolved;
+    PlanScope pls(ctx, pc_all);
     const int R = params->nrhs;
     // default: 2^24 voxels, large enough that a chunk fills the GPU with
     // several waves of boxes (each chunk's solve ends with its slowest box)
@@ -947,9 +966,9 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     const size_t part_bytes = ((size_t)n_bricks * sizeof(double) + 255) & ~size_t(255);
     e = grow(ctx, &ctx->aux, &ctx->aux_bytes, state_bytes + part_bytes + rwk::domain_scratch_bytes(), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint partials");
-    int no_third = 0;
-    const rw_solve_params pe = resolve_schedule(ctx, *params, n_bricks, bricks, &no_third);
-    NoThirdScope nts(ctx, no_third);
+    PlanChoice pc;
+    const rw_solve_params pe = resolve_schedule(ctx, *params, n_bricks, bricks, &pc);
+    PlanScope pls(ctx, pc);
     rwk::PlanePlan pp = plan_planes(ctx, &list, 1, false, pe.schedule);
     rc = attach_side_streams(ctx, &pp);
     if (rc) return rc;
@@ -1050,13 +1069,13 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
         // the third stream, every fitting box on the streamed-weights kernel,
         // and the streaming schedules (two sweeps; one sweep)
         struct Cand {
-            int schedule, no_third;
+            int schedule, no_third, no_regs;
         };
         std::vector<Cand> cands;
         if (params->nrhs == 1 && params->precision != RW_PREC_FP64)
-            cands = {{0, 0}, {0, 1}, {4, 0}, {3, 0}, {1, 0}};
+            cands = {{0, 0, 0}, {0, 1, 0}, {0, 0, 1}, {4, 0, 0}, {3, 0, 0}, {1, 0, 0}};
         else
-            cands = {{1, 0}, {2, 0}};
+            cands = {{1, 0, 0}, {2, 0, 0}};
         hipStream_t s = (hipStream_t)stream;
         DevGuard dg(ctx->device);
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1074,7 +1093,10 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
         for (size_t c = 0; c < cands.size() && rc == RW_OK; ++c) {
             rw_solve_params q = *params;
             q.schedule = cands[c].schedule;
-            NoThirdScope nts(ctx, cands[c].no_third);
+            PlanChoice pc;
+            pc.no_third = cands[c].no_third;
+            pc.no_regs = cands[c].no_regs;
+            PlanScope pls(ctx, pc);
             std::vector<float> t;
             for (int r = 0; r <= reps && rc == RW_OK; ++r) {   // run 0 warms up
                 e = hipMemcpyAsync(x_work, x0, xbytes, hipMemcpyDeviceToDevice, s);
@@ -1109,10 +1131,12 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
         bool found = false;
         for (rw_ctx::Tuned& t : ctx->tuned)
             if (t.key == key) {
-                t = rw_ctx::Tuned{key, cands[best].schedule, cands[best].no_third, med[best]};
+                t = rw_ctx::Tuned{key, cands[best].schedule, cands[best].no_third, cands[best].no_regs, med[best]};
                 found = true;
             }
-        if (!found) ctx->tuned.push_back(rw_ctx::Tuned{key, cands[best].schedule, cands[best].no_third, med[best]});
+        if (!found)
+            ctx->tuned.push_back(
+                rw_ctx::Tuned{key, cands[best].schedule, cands[best].no_third, cands[best].no_regs, med[best]});
         if (out) {
             std::memset(out, 0, sizeof(*out));
             out->n_candidates = (int32_t)cands.size();
@@ -1121,6 +1145,7 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
             for (size_t c = 0; c < cands.size(); ++c) {
                 out->schedule[c] = cands[c].schedule;
                 out->third_stream[c] = cands[c].no_third ? 0 : 1;
+                out->weights_in_registers[c] = cands[c].no_regs ? 0 : 1;
                 out->ms[c] = med[c];
             }
         }
@@ -1170,9 +1195,9 @@ int rw_graph_create(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks
         if (rc) return rc;
         if (n_bricks == 0) return fail(ctx, RW_E_INVAL, "a graph needs at least one box");
         if (!g || !mask || !x) return fail(ctx, RW_E_INVAL, "g, mask and x must be non-NULL");
-        int no_third = 0;
-        const rw_solve_params p = resolve_schedule(ctx, *params, n_bricks, bricks, &no_third);
-        NoThirdScope nts(ctx, no_third);
+        PlanChoice pc;
+        const rw_solve_params p = resolve_schedule(ctx, *params, n_bricks, bricks, &pc);
+        PlanScope pls(ctx, pc);
         const bool fp64 = p.precision == RW_PREC_FP64;
         rwk::PlanePlan pp = plan_planes(ctx, &list, p.nrhs, fp64, p.schedule);
         if (pp.n_dom > 0)
@@ -1234,15 +1259,16 @@ int rw_graph_launch(rw_graph* gr, void* stream) {
 void rw_graph_free(rw_graph* gr) { graph_release(gr); }
 
 int rw_tuned_schedule(const rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
-                      int32_t* schedule, int32_t* third_stream, int32_t* tuned) {
+                      int32_t* schedule, int32_t* third_stream, int32_t* regs, int32_t* tuned) {
     if (!ctx || !params || !schedule || !third_stream || !tuned || n_bricks < 0 || (n_bricks > 0 && !bricks))
         return fail(nullptr, RW_E_INVAL, "bad arguments");
     rw_solve_params q = *params;
     q.schedule = RW_SCHED_TUNED;
-    int no_third = 0;
-    const rw_solve_params r = resolve_schedule(ctx, q, n_bricks, bricks, &no_third);
+    PlanChoice pc;
+    const rw_solve_params r = resolve_schedule(ctx, q, n_bricks, bricks, &pc);
     *schedule = r.schedule;
-    *third_stream = no_third ? 0 : 1;
+    *third_stream = pc.no_third ? 0 : 1;
+    if (regs) *regs = pc.no_regs ? 0 : 1;
     *tuned = 0;
     for (const rw_ctx::Tuned& t : ctx->tuned)
         if (n_bricks > 0 && t.key == batch_key(*params, n_bricks, bricks)) *tuned = 1;

@@ -66,13 +66,16 @@ struct rw_ctx {
     // keep both streamed-weights launches on one stream (the streamed solve's
     // lanes already run two solves at once)
     int plan_no_third = 0;
+    // keep the weights of small resident boxes in LDS (k_pcg_resw) instead of
+    // registers (k_pcg_resr): a tuning choice
+    int plan_no_regs = 0;
     // this device's copy of the static scratch of rw_solve_bricks_noalloc
     void* scratch = nullptr;
     // autotuned schedules: per batch signature (box shapes, nrhs,
     // precision) the fastest candidate rw_autotune measured
     struct Tuned {
         uint64_t key;
-        int32_t schedule, no_third;
+        int32_t schedule, no_third, no_regs;
         float ms;
     };
     std::vector<Tuned> tuned;
@@ -187,10 +190,11 @@ struct PlanePlan {
     int64_t n_big;
     int64_t n_dom;
     const BrickDev* host;
-    // Resident PCG (one rhs, FP32): boxes [n_res, n), in up to four launches
+    // Resident PCG (one rhs, FP32): boxes [n_res, n), in up to five launches
     // (largest box first within each): p in LDS with the weights streamed
-    // from a per-box segment (boxes above and up to 17408 voxels), then p and
-    // the weights in LDS for larger and for small boxes (launched apart so
+    // from a per-box segment (boxes above and up to 17408 voxels), p and the
+    // weights in LDS (boxes the registers do not hold), then p in LDS and the
+    // weights in registers for larger and for small boxes (launched apart so
     // that their LDS size lets several workgroups share a CU).  Without
     // resident boxes n_res = n.
     int64_t n_res;
@@ -199,9 +203,9 @@ struct PlanePlan {
         int64_t b0, b1;       // launch-list range
         int64_t max_voxels;   // largest box of the range
         int64_t max_plane;    // widest nx*ny of the range
-        int kind;             // 1: weights-in-LDS kernel, 2: streamed-weights kernel
+        int kind;             // 1: weights-in-LDS kernel, 2: streamed-weights kernel, 3: weights in registers
         int px;               // 32 when every box of the range has 32 x 32 planes, else 0
-    } rl[4];
+    } rl[6];
     int64_t wts_elems;        // floats of weight segments the kind-2 boxes need (BrickDev::woff)
     // when set, the streaming and resident groups run on these two streams
     // (forked from and joined back into the caller's stream)
@@ -218,10 +222,12 @@ struct PlanePlan {
 // Resident PCG (resident.hip).
 constexpr int kResThreads = 512;
 constexpr int kResMaxVptW = 20;   // weights-in-LDS kernel: boxes up to 10240 voxels
+constexpr int kResMaxVptR = 10;   // weights-in-registers kernel: boxes up to 5120 voxels
 constexpr int kResSmallVox = 5120;  // the small weights group: at most 10 voxels per thread
 constexpr int kResSpanG0 = 17408;   // streamed-weights kernel: voxel slots of its launches for
 constexpr int kResSpanG1 = 32768;   // boxes up to 32 x 32 x 17 and up to 32^3
 bool resident_w_fits(const BrickDev& b, size_t lds_limit);    // weights-in-LDS kernel
+bool resident_r_fits(const BrickDev& b, size_t lds_limit);    // weights-in-registers kernel
 bool resident_g_fits(const BrickDev& b, size_t lds_limit);    // streamed-weights kernel
 int64_t resident_g_span(int64_t max_voxels);                  // its voxel slots per workgroup
 int64_t resident_g_elems(const BrickDev& b, int64_t span);    // a box's weight segment, in floats

@@ -387,6 +387,232 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
 }
 
 
+// Boxes up to kResMaxVptR * 512 voxels (e.g. 16^3, 5x32x32): the
+// weights-in-registers kernel.  Each thread computes, once per solve, all six
+// edge weights of each of its voxels (thread t owns voxels t + k * NT) from
+// g and keeps them in registers with d, 1/d, x, r, p and q; the LDS holds
+// only p (with nx*ny zero pads on both sides and one past the box, where the
+// unused slots of a thread point).  Per iteration a voxel then touches the
+// LDS seven times (its p written once, six neighbours read), against sixteen
+// in k_pcg_resw, which keeps the forward weights in LDS: the weights-in-LDS
+// kernel is bound by LDS bandwidth, this one by arithmetic.  On a seeded or
+// unused slot every weight, d and 1/d are 0, so p, q and r stay 0 there.
+// The edge weight is symmetric in its two voxels, so a voxel's backward
+// weights equal its neighbours' forward ones bit for bit, and the stencil
+// sums in the same order as k_pcg_resw.
+template <int NT, int VPT>
+__global__ __launch_bounds__(NT) void k_pcg_resr(SolveArgs a, float* xt, int corr, int base) {
+    extern __shared__ __align__(16) float pr_lds[];
+    __shared__ double red[(NT / 64) * 5];  // block sums of up to 5 values (the start state)
+    constexpr int NC = (VPT + 31) / 32;  // unknown-voxel bits
+    constexpr int U = 2;                 // voxels per thread whose loads are issued together
+    const int ib = base + blockIdx.x;
+    BoxState& st = a.state[ib];
+    const bool fused = a.fused_init && !corr;  // this kernel computes the start state
+    if (!fused && !st.active) return;
+    const BrickDev bd = a.bricks[ib];
+    const int nx = bd.nx, ny = bd.ny, nz = bd.nz, nxy = nx * ny, nv = nxy * nz;
+    float* const P = pr_lds + nxy;
+    const float* g = a.g + bd.off;
+    const uint8_t* m = a.mask + bd.off;
+    float* xb = xt + bd.off;
+    float* const rw = (float*)a.r + bd.off;
+    const ResWeight W{(float)(-a.beta * 1.4426950408889634), (float)a.eps};
+
+    // Main solve: P holds x (pads 0) while the weights and the start state
+    // are computed.  Otherwise P starts at 0.
+    res_fill_p<NT, 4>(P, xb, -nxy, nv + nxy + 1, nv, fused);
+    if (fused) __syncthreads();
+    float x[VPT], r[VPT], q[VPT], p[VPT], d[VPT], id[VPT], w[6][VPT];
+    unsigned unk[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) unk[c] = 0u;
+    double sum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // r.z, r.r, b.b, unknown, seeded
+    // weights (and, main solve, start state) U voxels at a time, every
+    // global load of the U (g and mask at the voxel and its six neighbours,
+    // indices clamped into the box) issued before any is used
+#pragma unroll
+    for (int k0 = 0; k0 < VPT; k0 += U) {
+        int c[U];
+        bool in[U][6];
+        float gc[U], gn[U][6];
+        uint8_t mc[U], mn[U][6];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k0 + u < VPT) {
+                const int v = threadIdx.x + (k0 + u) * NT;
+                c[u] = v < nv ? v : 0;
+                const int kz = c[u] / nxy, rem = c[u] - kz * nxy, j = rem / nx, i = rem - j * nx;
+                const int no[6] = {1, -1, nx, -nx, nxy, -nxy};
+                in[u][0] = i + 1 < nx;
+                in[u][1] = i > 0;
+                in[u][2] = j + 1 < ny;
+                in[u][3] = j > 0;
+                in[u][4] = kz + 1 < nz;
+                in[u][5] = kz > 0;
+                gc[u] = g[c[u]];
+                mc[u] = m[c[u]];
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    const int nb = in[u][e] ? c[u] + no[e] : c[u];
+                    gn[u][e] = g[nb];
+                    mn[u][e] = m[nb];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u;
+            if (k < VPT) {
+                const int v = threadIdx.x + k * NT;
+                const bool inb = v < nv;
+                const bool uk = inb && mc[u] == 0;
+                float we[6];
+#pragma unroll
+                for (int e = 0; e < 6; ++e) we[e] = inb && in[u][e] ? W(gc[u], gn[u][e]) : 0.0f;
+                const float dd = ((we[0] + we[2]) + we[4]) + we[1] + we[3] + we[5];
+                float xv = 0.0f, r0 = 0.0f;
+                if (fused) {
+                    if (inb) {
+                        const int no[6] = {1, -1, nx, -nx, nxy, -nxy};
+                        float acc = 0.0f, bs = 0.0f;  // sum_nb w x_nb, and over the seeded neighbours only
+#pragma unroll
+                        for (int e = 0; e < 6; ++e) {
+                            const float xr = P[v + no[e]];  // inside P's pads for every voxel of the box
+                            const float xn = in[u][e] ? xr : 0.0f;
+                            acc += we[e] * xn;
+                            if (mn[u][e] != 0) bs += we[e] * xn;
+                        }
+                        xv = P[v];
+                        r0 = uk ? acc - dd * xv : 0.0f;
+                        rw[v] = r0;
+                        if (uk) {
+                            sum[0] += (double)r0 * (double)(r0 * __builtin_amdgcn_rcpf(dd));
+                            sum[1] += (double)r0 * (double)r0;
+                            sum[2] += (double)bs * (double)bs;
+                        }
+                        sum[3] += uk ? 1.0 : 0.0;
+                        sum[4] += uk ? 0.0 : 1.0;
+                    }
+                } else {
+                    const int cv = inb ? v : nv - 1;
+                    xv = xb[cv];
+                    r0 = rw[cv];
+                }
+#pragma unroll
+                for (int e = 0; e < 6; ++e) w[e][k] = uk ? we[e] : 0.0f;
+                d[k] = uk ? dd : 0.0f;
+                id[k] = uk ? __builtin_amdgcn_rcpf(dd) : 0.0f;
+                x[k] = uk ? xv : 0.0f;
+                r[k] = uk ? r0 : 0.0f;
+                unk[k >> 5] |= (uk ? 1u : 0u) << (k & 31);
+            }
+        }
+    }
+    double rz, rr, bb;
+    if (fused) {
+        if (!res_start_finish<NT>(sum, nv, m, xb, rw, P, red, st, rz, rr, bb))
+            return;  // nothing to iterate (state and x written)
+    } else {
+        rz = st.rz[0];
+        rr = st.rr[0];
+        bb = st.bb[0];
+    }
+    auto isu = [&](int k) { return (unk[k >> 5] >> (k & 31)) & 1u; };
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        q[k] = r[k] * id[k];  // z0
+        p[k] = 0.0f;
+    }
+
+    const double tol = corr ? a.inner_tol : a.tol;
+    const double tol2 = tol * tol;
+    double betac = 0.0;
+    int it = 0, flags = 0;
+    for (;;) {
+        if (rr <= tol2 * bb) break;
+        if (it >= a.max_iter) {
+            flags = 2;
+            break;
+        }
+        // opaque copies, fresh for each pass: no per-voxel address is kept
+        // from one pass to the next
+        int tb = threadIdx.x;
+        asm volatile("" : "+v"(tb));
+        const float be = it == 0 ? 0.0f : (float)betac;
+        // p = z + beta p (0 on seeded and unused slots)
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            p[k] = q[k] + be * p[k];
+            const int v0 = tb + k * NT;
+            P[v0 < nv ? v0 : nv] = p[k];
+        }
+        __syncthreads();
+        int t2 = threadIdx.x, oy = nx, oz = nxy;
+        asm volatile("" : "+v"(t2));
+        asm volatile("" : "+v"(oy));
+        asm volatile("" : "+v"(oz));
+        double sig = 0.0;
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            const int v0 = t2 + k * NT;
+            const int v = v0 < nv ? v0 : nv;
+            const float acc = w[0][k] * P[v + 1] + w[1][k] * P[v - 1] + w[2][k] * P[v + oy] + w[3][k] * P[v - oy] +
+                              w[4][k] * P[v + oz] + w[5][k] * P[v - oz];
+            q[k] = d[k] * p[k] - acc;
+            sig += (double)p[k] * (double)q[k];
+        }
+        double s1[1] = {sig};
+        res_block_sum<NT, 1>(s1, red);
+        sig = s1[0];
+        const double alpha = rz / sig;
+        if (!res_finite(alpha) || !(sig > 0.0)) {
+            flags = 1;
+            break;
+        }
+        const float al = (float)alpha;
+        double acc2[2] = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            // p, q, r and 1/d are 0 on seeded and unused slots, so these stay 0
+            x[k] += al * p[k];
+            r[k] -= al * q[k];
+            const float z = r[k] * id[k];
+            q[k] = z;
+            acc2[0] += (double)r[k] * (double)z;
+            acc2[1] += (double)r[k] * (double)r[k];
+        }
+        res_block_sum<NT, 2>(acc2, red);
+        ++it;
+        if (!res_finite(acc2[0]) || !res_finite(acc2[1])) {
+            flags = 1;
+            break;
+        }
+        betac = acc2[0] / rz;
+        rz = acc2[0];
+        rr = acc2[1];
+    }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v = threadIdx.x + k * NT;
+        if (isu(k)) xb[v] = x[k];
+    }
+    if (threadIdx.x == 0) {
+        st.rz[0] = rz;
+        st.rr[0] = rr;
+        if (corr) {
+            st.refine_iters += it;
+        } else {
+            st.iters = it;
+            st.rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            if (flags & 2) st.status = RW_ST_MAX_ITER;
+        }
+        if (flags & 1) st.status = RW_ST_NONFINITE;
+        st.pending = corr && !(flags & 1) ? 1 : 0;
+    }
+}
+
+
 // Variant for boxes whose search direction alone fits in one CU's LDS (up
 // to 32768 voxels, e.g. 32^3): LDS holds p only (4 B per voxel, pads as
 // above).  The forward weights w+x, w+y, w+z and 1/d are computed once per
@@ -733,6 +959,14 @@ bool resident_w_fits(const BrickDev& b, size_t lds_limit) {
            (size_t)resident_lds_elems(nv, nxy) * sizeof(float4) + 1024 <= lds_limit;
 }
 
+// The weights-in-registers kernel: p alone in LDS, at most kResMaxVptR voxels
+// per thread.
+bool resident_r_fits(const BrickDev& b, size_t lds_limit) {
+    const int64_t nxy = (int64_t)b.nx * b.ny, nv = nxy * b.nz;
+    return nv <= (int64_t)kResMaxVptR * kResThreads &&
+           (size_t)resident_lds_elems(nv, nxy) * sizeof(float) + 1024 <= lds_limit;
+}
+
 // Voxel slots (threads x voxels per thread) of a streamed-weights launch
 // whose largest box has max_voxels voxels (0: too large).
 int64_t resident_g_span(int64_t max_voxels) {
@@ -755,13 +989,15 @@ int64_t resident_g_elems(const BrickDev& b, int64_t span) {
 }
 
 // Boxes [b0, b1) of the launch list, all eligible for the kernel `kind`
-// (1: weights and p in LDS, 2: p in LDS and weights in a global buffer),
+// (1: weights and p in LDS, 2: p in LDS and weights in a global buffer,
+// 3: p in LDS and weights in registers),
 // largest first; px = 32 when every box has 32 x 32 planes.
 hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_voxels, int64_t max_plane,
                            int kind, int px, float* xt, int corr, hipStream_t s) {
     if (b1 <= b0) return hipSuccess;
-    const size_t lds = kind == 2 ? resident_g_lds(resident_g_span(max_voxels), max_plane)
-                                 : (size_t)resident_lds_elems(max_voxels, max_plane) * sizeof(float4);
+    const size_t lds = kind == 2   ? resident_g_lds(resident_g_span(max_voxels), max_plane)
+                       : kind == 3 ? (size_t)resident_lds_elems(max_voxels, max_plane) * sizeof(float)
+                                   : (size_t)resident_lds_elems(max_voxels, max_plane) * sizeof(float4);
     const dim3 grid((unsigned)(b1 - b0));
     auto go = [&](auto kern, int nt) -> hipError_t {
         if (lds > 48 * 1024) {
@@ -792,6 +1028,11 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
     if (kind == 1) {
         if (vpt <= 10) return go(k_pcg_resw<kResThreads, 10>, nt);
         if (vpt <= kResMaxVptW) return go(k_pcg_resw<kResThreads, kResMaxVptW>, nt);
+    }
+    if (kind == 3) {
+        if (vpt <= 4) return go(k_pcg_resr<kResThreads, 4>, nt);
+        if (vpt <= 8) return go(k_pcg_resr<kResThreads, 8>, nt);
+        if (vpt <= kResMaxVptR) return go(k_pcg_resr<kResThreads, kResMaxVptR>, nt);
     }
     return hipErrorInvalidValue;
 }

@@ -566,3 +566,149 @@ def vessels_volume(n=256, seed=12, structure=0.1, coverage=0.01, noise=0.1, max_
             if np.all(o >= 0) and np.all(o < n) and truth[oi[2], oi[1], oi[0]] == 0:
                 seeds.append([o[0], o[1], o[2], 0])
     return vol, np.array(seeds, dtype=np.float64), truth
+
+
+def shell_geometry(dims, seed=5):
+    """The nested-shell geometry of ``shell_volume`` (same draws, same order):
+    centre, rotation and semi-axes, plus a label function of voxel centres
+    (integer indices, arrays of x, y, z) and the clearance bound."""
+    rng = np.random.default_rng(seed)
+    D = np.array(dims, np.float64)
+    c = D / 2.0 + rng.uniform(-0.05, 0.05, 3) * D
+    Q = _rotation(rng)
+    a1 = rng.uniform(0.35, 0.45, 3) * D
+    a2 = a1 * rng.uniform(0.6, 0.75, 3)
+    a3 = a2 * rng.uniform(0.5, 0.7, 3)
+    axes = [a1, a2, a3]
+
+    def rho(p):
+        u = (np.atleast_2d(p) - c) @ Q
+        return [np.sqrt(np.sum((u / a) ** 2, axis=-1)) for a in axes]
+
+    def label(p):
+        r = rho(p)
+        lab = np.zeros(len(r[0]), np.int64)
+        for k in range(3):
+            lab[r[k] <= 1.0] = k + 1
+        return lab
+
+    def clearance(p):
+        return np.min([np.abs(r - 1.0) * a.min() for r, a in zip(rho(p), axes)], axis=0)
+
+    return dict(centre=c, rotation=Q, axes=axes, label=label, clearance=clearance, rng=rng)
+
+
+def shell_volume_device(dims=(2048, 2048, 1024), seed=5, n_per_class=50, margin=None, fbm_std=100.0,
+                        device="cuda:0", slab=8):
+    """The nested-shell recipe of ``shell_volume`` at sizes the host cannot
+    draw quickly: the geometry and seeds come from numpy exactly as there
+    (``shell_geometry``; seeds tested with the analytic labels), the noise
+    from a seeded torch generator on ``device`` (so the volume differs from
+    ``shell_volume``'s at the same seed but follows the same recipe), built
+    ``slab`` z-planes at a time.  Returns (vol uint16 [z, y, x] tensor on the
+    device, labels uint8 tensor on the device, seeds
+    float64 [k, 4], geometry dict)."""
+    import torch
+    nx, ny, nz = dims
+    geo = shell_geometry(dims, seed)
+    rng = geo["rng"]
+    if margin is None:
+        margin = max(2.0, 8.0 * min(dims) / 1024.0)
+    dev = torch.device(device)
+    c = torch.tensor(geo["centre"], dtype=torch.float64, device=dev)
+    Q = torch.tensor(geo["rotation"], dtype=torch.float64, device=dev)
+    ax = [torch.tensor(a, dtype=torch.float64, device=dev) for a in geo["axes"]]
+    # lattice values of the six fBm octaves (small; drawn on the host)
+    octaves = []
+    amp, var = 1.0, 0.0
+    for o in range(6):
+        wl = 512.0 / 2 ** o
+        cells = [int(np.ceil(d / wl)) + 2 for d in (nz, ny, nx)]
+        octaves.append((wl, amp, torch.from_numpy(rng.standard_normal(cells).astype(np.float32)).to(dev)))
+        var += amp * amp
+        amp *= 0.5
+    fscale = float(fbm_std / np.sqrt(var))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed) * 1000003 + 17)
+    means = torch.tensor([500.0, 1500.0, 2500.0, 3500.0], device=dev)
+    vol = torch.empty((nz, ny, nx), dtype=torch.int16, device=dev)
+    labels = torch.empty((nz, ny, nx), dtype=torch.uint8, device=dev)
+    xs = torch.arange(nx, dtype=torch.float64, device=dev)
+    ys = torch.arange(ny, dtype=torch.float64, device=dev)
+    for z0 in range(0, nz, slab):
+        z1 = min(nz, z0 + slab)
+        zs = torch.arange(z0, z1, dtype=torch.float64, device=dev)
+        P = torch.stack(torch.broadcast_tensors(xs[None, None, :], ys[None, :, None], zs[:, None, None]), -1) - c
+        u = P @ Q
+        lab = torch.zeros((z1 - z0, ny, nx), dtype=torch.uint8, device=dev)
+        for k, a in enumerate(ax):
+            lab[torch.sum((u / a) ** 2, dim=-1) <= 1.0] = k + 1
+        del P, u
+        labels[z0:z1] = lab
+        v = means[lab.long()]
+        fbm = torch.zeros((z1 - z0, ny, nx), dtype=torch.float32, device=dev)
+        for wl, am, lat in octaves:
+            coords = [(torch.arange(a0, a1, dtype=torch.float32, device=dev) + 0.5) / wl
+                      for a0, a1 in ((z0, z1), (0, ny), (0, nx))]
+            i0 = [t.floor().long() for t in coords]
+            f = [t - t.floor() for t in coords]
+            for dz in (0, 1):
+                wz = (f[0] if dz else 1 - f[0])[:, None, None]
+                for dy in (0, 1):
+                    wy = (f[1] if dy else 1 - f[1])[None, :, None]
+                    for dx in (0, 1):
+                        wx = (f[2] if dx else 1 - f[2])[None, None, :]
+                        fbm += am * wz * wy * wx * lat[(i0[0] + dz)[:, None, None], (i0[1] + dy)[None, :, None],
+                                                       (i0[2] + dx)[None, None, :]]
+        v = v + fbm * fscale
+        v = v + torch.randn(v.shape, generator=gen, device=dev, dtype=torch.float32) * 250.0
+        vu = torch.clamp(torch.round(v), 0.0, 65535.0).to(torch.int32)
+        vol[z0:z1] = (vu - 65536 * (vu > 32767).to(torch.int32)).to(torch.int16)
+        del v, fbm, vu, lab
+    D = np.array(dims, np.float64)
+    seeds = []
+    for cls in range(4):
+        got, tries = 0, 0
+        while got < n_per_class:
+            tries += 1
+            if tries > 1000:
+                raise RuntimeError(f"class {cls}: too few voxels {margin} away from the boundaries")
+            q = np.rint(rng.uniform(0.0, 1.0, (4096, 3)) * (D - 1)).astype(np.int64)
+            ok = (geo["label"](q.astype(np.float64)) == cls) & (geo["clearance"](q.astype(np.float64)) >= margin)
+            for vq in q[ok][: n_per_class - got]:
+                seeds.append([vq[0] + 0.5, vq[1] + 0.5, vq[2] + 0.5, cls])
+                got += 1
+    geo = dict(geo, margin=margin, dims=dims)
+    del geo["rng"]
+    return vol.view(torch.uint16), labels, np.array(seeds, np.float64), geo
+
+
+def stroke_geo(geo, cls=2, length=2000, seed=6):
+    """``stroke`` driven by the analytic labels of a shell geometry (for
+    volumes whose label array stays on the device)."""
+    rng = np.random.default_rng(seed)
+    margin = geo["margin"]
+    nx, ny, nz = geo["dims"]
+    steps = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]])
+
+    def ok(v):
+        return (0 <= v[0] < nx and 0 <= v[1] < ny and 0 <= v[2] < nz
+                and geo["label"](v.astype(np.float64))[0] == cls
+                and geo["clearance"](v.astype(np.float64))[0] >= margin)
+
+    for _ in range(100000):
+        start = np.array([rng.integers(0, nx), rng.integers(0, ny), rng.integers(0, nz)])
+        if not ok(start):
+            continue
+        path, seen = [start], {tuple(start)}
+        while len(path) < length:
+            cand = [path[-1] + s for s in steps[rng.permutation(6)]]
+            nxt = next((v for v in cand if tuple(v) not in seen and ok(v)), None)
+            if nxt is None:
+                break
+            path.append(nxt)
+            seen.add(tuple(nxt))
+        if len(path) == length:
+            p = np.array(path, np.float64) + 0.5
+            return np.concatenate([p, np.full((length, 1), float(cls))], axis=1)
+    raise RuntimeError("no self-avoiding walk of the requested length found")

@@ -292,8 +292,9 @@ def test_resident_kernel_matches_oracle_and_streaming(env):
     plan4 = rwg.context().solve_plan(rwg.solve_params(schedule=4), bricks, d["g"].size)
     nv = np.prod(np.asarray(shapes), axis=1)
     # boxes above 10240 voxels (up to 32^3) take the streamed-weights kernel
-    # by default, smaller ones keep the weights in LDS; with schedule 4
-    # every box up to 32768 voxels streams its weights
+    # by default, smaller ones keep the weights on chip (in registers up to
+    # 5120 voxels, else in LDS); with schedule 4 every box up to 32768
+    # voxels streams its weights
     assert np.all(plan0[nv > 10240] == rwg.PATH_RESIDENT_STREAMED), plan0
     assert np.all(plan0[nv <= 10240] == rwg.PATH_RESIDENT), plan0
     assert np.all(plan4 == rwg.PATH_RESIDENT_STREAMED), plan4
@@ -301,8 +302,10 @@ def test_resident_kernel_matches_oracle_and_streaming(env):
         o, n = int(d["offsets"][i]), ref.size
         assert np.max(np.abs(xr[o:o + n] - ref)) <= 1e-4, (shapes[i], sr[i])
         assert np.max(np.abs(xg[o:o + n] - ref)) <= 1e-4, (shapes[i], sg[i])
-        assert np.max(np.abs(xr[o:o + n] - xs[o:o + n])) <= 2e-5, (shapes[i], sr[i], ss[i])
-        assert np.max(np.abs(xg[o:o + n] - xs[o:o + n])) <= 2e-5, (shapes[i], sg[i], ss[i])
+        # two stops at relative residual 1e-6 (each up to about 2e-5 from the
+        # solution on the weak-link chain boxes) agree to the sum of the two
+        assert np.max(np.abs(xr[o:o + n] - xs[o:o + n])) <= 4e-5, (shapes[i], sr[i], ss[i])
+        assert np.max(np.abs(xg[o:o + n] - xs[o:o + n])) <= 4e-5, (shapes[i], sg[i], ss[i])
         assert np.max(np.abs(x64[o:o + n] - ref)) <= 1e-9, (shapes[i], s64[i])
         assert np.max(np.abs(x64g[o:o + n] - ref)) <= 1e-9, (shapes[i], s64g[i])
         assert abs(int(sr["iters"][i]) - int(ss["iters"][i])) <= max(3, ss["iters"][i] // 20), (sr[i], ss[i])

@@ -51,18 +51,24 @@ def test_autotune_and_tuned_solve(env):
     p = rwg.solve_params(beta=BETA, eps=EPS, tol=1e-6, precision=1)
     rep = ctx.autotune(p, b, g, m, x0, xw, reps=2)
     print(rep, flush=True)
-    assert len(rep["candidates"]) == 5 and 0 <= rep["best"] < 5
+    assert len(rep["candidates"]) == 6 and 0 <= rep["best"] < 6
     assert all(c["ms"] > 0 for c in rep["candidates"])
     best = rep["candidates"][rep["best"]]
-    sched, third, tuned = ctx.tuned_schedule(p, b)
-    assert tuned and (sched, third) == (best["schedule"], best["third_stream"])
-    # a tuned solve equals the winner given explicitly
+    sched, third, regs, tuned = ctx.tuned_schedule(p, b)
+    assert tuned and (sched, third, regs) == (best["schedule"], best["third_stream"], best["weights_in_registers"])
+    # a tuned solve equals the winner run directly (a winner that differs
+    # from its schedule's default plan only by a plan choice is run as a
+    # second tuned call: the same plan, so the same bits)
     xt = x0.clone()
     ctx.rw_solve_bricks(rwg.solve_params(beta=BETA, eps=EPS, tol=1e-6, precision=1, schedule=rwg.SCHED_TUNED),
                         b, g, m, xt)
     xe = x0.clone()
-    ctx.rw_solve_bricks(rwg.solve_params(beta=BETA, eps=EPS, tol=1e-6, precision=1, schedule=best["schedule"]),
-                        b, g, m, xe)
+    if best["third_stream"] == 1 and best["weights_in_registers"] == 1:
+        ctx.rw_solve_bricks(rwg.solve_params(beta=BETA, eps=EPS, tol=1e-6, precision=1, schedule=best["schedule"]),
+                            b, g, m, xe)
+    else:
+        ctx.rw_solve_bricks(rwg.solve_params(beta=BETA, eps=EPS, tol=1e-6, precision=1, schedule=rwg.SCHED_TUNED),
+                            b, g, m, xe)
     torch.cuda.synchronize()
     assert np.array_equal(xt.cpu().numpy(), xe.cpu().numpy())
     xs = xt.cpu().numpy()
@@ -74,7 +80,7 @@ def test_autotune_and_tuned_solve(env):
     # an untuned batch falls back to the default schedule
     other = synth.stress_boxes(n=7, seed=32)
     _, _, _, b2 = _dev(env, other)
-    assert ctx.tuned_schedule(p, b2) == (0, 1, False)
+    assert ctx.tuned_schedule(p, b2) == (0, 1, 1, False)
     ctx.close()
 
 

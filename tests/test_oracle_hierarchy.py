@@ -195,3 +195,49 @@ def test_multiclass_hierarchy_sums_to_one():
     assert np.max(np.abs(pr.sum(axis=0) - 1)) < 1e-12
     lab = H.labels(res, 0)
     assert lab[7, 7, 7] == 1 and lab[14, 14, 14] == 2 and lab[1, 1, 1] == 0
+
+
+def test_upsample_box_is_the_whole_upsample_restricted():
+    """upsample_box equals the whole-level upsample on the box, for boxes on
+    every edge (clamped taps) and in the interior, odd and even sizes."""
+    rng = np.random.default_rng(3)
+    parent = rng.random((2, 5, 7, 6))
+    shape = (9, 13, 12)
+    full = H.upsample(parent, shape)
+    for box in [((0, 9), (0, 13), (0, 12)), ((0, 3), (5, 13), (7, 12)), ((4, 9), (1, 2), (0, 5)),
+                ((3, 7), (6, 11), (2, 10))]:
+        got = H.upsample_box(parent, shape, box)
+        want = full[(slice(None),) + tuple(slice(a, b) for a, b in box)]
+        assert got.shape == want.shape
+        assert np.array_equal(got, want)
+
+
+def test_upsample_box_from_a_crop_and_rasterize_box():
+    rng = np.random.default_rng(4)
+    parent = rng.random((3, 6, 5, 7))
+    shape = (12, 9, 14)
+    full = H.upsample(parent, shape)
+    box = ((5, 12), (0, 4), (6, 11))
+    # parent crop that covers the box's taps: child X -> parent (X + 1/2)/2 - 1/2
+    origin = (2, 0, 2)
+    crop = parent[:, 2:6, 0:3, 2:6]
+    got = H.upsample_box(crop, shape, box, origin=origin, parent_shape=(6, 5, 7))
+    assert np.array_equal(got, full[(slice(None),) + tuple(slice(a, b) for a, b in box)])
+    with pytest.raises(ValueError):
+        H.upsample_box(parent[:, 3:6], shape, box, origin=(3, 0, 0), parent_shape=(6, 5, 7))
+    seeds = np.array([[6.2, 1.0, 7.9, 1], [6.7, 1.5, 7.1, 0], [10.0, 3.9, 11.5, 2], [0.5, 0.5, 0.5, 1],
+                      [13.9, 8.9, 11.9, 3]])
+    dims = (12, 9, 14)
+    for lvl in (0, 1):
+        d = tuple((n + (1 << lvl) - 1) >> lvl for n in dims)
+        whole = H.rasterize(seeds, lvl, d)
+        for b in [((0, d[0]), (0, d[1]), (0, d[2])), ((1, 4), (0, 3), (3, 7))]:
+            sub = whole[tuple(slice(a, c) for a, c in b)]
+            assert np.array_equal(H.rasterize_box(seeds, lvl, d, b), sub)
+
+
+def test_normalize_with_a_global_range():
+    v = np.array([[[100, 300], [200, 500]]], dtype=np.uint16)
+    whole = H.normalize(v)
+    part = H.normalize(v[:, :1, :], vrange=(100, 500))
+    assert np.array_equal(part, whole[:, :1, :])
