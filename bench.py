@@ -35,7 +35,7 @@ RESIDENT_BYTES_PER_VOXEL = 13  # weights-in-LDS kernel: read g, mask, x once per
 BETA, EPS, TOL = 128.0, 1e-6, 1e-6
 N_BOXES, SEED = 8192, 3
 # workloads run only on request (--only NAME): minutes of GPU time
-ON_REQUEST = ("shells_full",)
+ON_REQUEST = ("shells_full", "memory_ceilings")
 EXTRAS = ("plain_sphere_64", "tubes_512_hierarchy", "blobs_512x32_adjoint", "shells_hierarchy_incremental",
           "cells_256_ablation", "cells_brick_growth", "pruning_table_256", "stress_streamed_from_host")
 
@@ -259,14 +259,23 @@ def bench_tubes(torch, rwg, ctx, n=512, n_tubes=40, levels=4):
     lb = lab.cpu().numpy().astype(bool)
     gt = (tube > 0) & (tube <= 20)
     vi = int(sum(st["voxel_iters"]))
+    # the level solves under the other CG schedules of the 40^3 window
+    # boxes: one sweep and one reduction per iteration (3), two sweeps (1)
+    sched = {}
+    for sc in (1, 3):
+        ms, r = _best_ms(torch, lambda: rwg.segment(pyr, seeds, schedule=sc, **kw), 2)
+        sched[str(sc)] = {"segment_ms": ms, "voxel_iters": int(sum(r.stats()["voxel_iters"])),
+                          "max_abs_diff_vs_schedule_0": max(float((r.level_map(l) - res.level_map(l)).abs().max().item())
+                                                            for l in range(levels))}
     return {"workload": f"tubes {n}^3 uint16, {n_tubes} tubes, 20 fg + 200 bg seeds, {levels} levels, s=32, e=1.25, "
                         "beta 128, dt pruning t_bin 0.49, mixed tol 1e-5",
             "pyramid_ms": pyr_ms, "segment_ms": seg_ms,
             "end_to_end_voxels_per_s": float(v.size / (seg_ms / 1e3)),
             "voxel_iters": vi, "voxel_iters_per_s": float(vi / (seg_ms / 1e3)),
-            "per_level": {k: st[k] for k in ("bricks", "computed", "solved", "prunable", "max_iters", "not_converged")},
+            "per_level": {k: st[k] for k in ("bricks", "computed", "solved", "prunable", "voxel_iters", "max_iters",
+                                             "not_converged")},
             "dice_vs_seeded_tubes": float(2 * (lb & gt).sum() / (lb.sum() + gt.sum())),
-            "generate_s": gen_s}
+            "level_solve_schedules": sched, "generate_s": gen_s}
 
 
 def bench_blobs_adjoint(torch, rwg, dev, n=512, cpu_leg=False):
@@ -677,6 +686,8 @@ def main():
             return bench_pruning_table(torch, rwg, ctx)
         if name == "shells_full":
             return bench_shells_full(torch, rwg, ctx, cpu_leg=not args.no_cpu_baseline)
+        if name == "memory_ceilings":
+            return measure_ceilings(torch, rwg, ctx)
         if name == "stress_streamed_from_host":
             return bench_streamed(torch, rwg, ctx)
         return bench_shells(torch, rwg, ctx, dims=shell_dims)

@@ -438,6 +438,8 @@ typedef struct rw_params {
     int32_t refine_max;
     int32_t incremental;     /* runs with prev: bit 0 the node rule (else the dirty-brick rule),
                                 bit 1 warm start from prev (Section IV-E); 0 by default */
+    int32_t schedule;        /* rw_solve_params.schedule of the level solves (0 by default) */
+    int32_t reserved;        /* must be 0 */
 } rw_params;
 
 void rw_params_default(rw_params* p);

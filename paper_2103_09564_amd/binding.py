@@ -398,7 +398,8 @@ class Params(ctypes.Structure):
                 ("expand", ctypes.c_double), ("t_hom", ctypes.c_double), ("t_bin", ctypes.c_double),
                 ("t_inc", ctypes.c_double), ("brick", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("n_classes", ctypes.c_int32), ("prune_hom", ctypes.c_int32),
-                ("prune_dt", ctypes.c_int32), ("refine_max", ctypes.c_int32), ("incremental", ctypes.c_int32)]
+                ("prune_dt", ctypes.c_int32), ("refine_max", ctypes.c_int32), ("incremental", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Seed(ctypes.Structure):

@@ -622,6 +622,7 @@ static int solve_boxes(rw_ctx* ctx, hipStream_t s, const rw_params& P, const Lev
         sp.precision = P.precision;
         sp.nrhs = R;
         sp.refine_max = P.refine_max;
+        sp.schedule = P.schedule;
         H_TRY(rw_solve_bricks(ctx, &sp, nb, br.data(), nv, gb, mb, xb, nullptr, dst, s));
         hipLaunchKernelGGL(k_contract<R>, dim3((unsigned)nb), dim3(kHThreads), 0, s, dgeo, xb, L.D[0], L.D[1], lmap);
         H_HIP(hipGetLastError(), "launching contraction");
@@ -1070,6 +1071,8 @@ int rw_segment(rw_ctx* ctx, const rw_pyramid* pyr, const rw_seed* seeds, int64_t
     if (!(P.expand >= 1.0) || P.expand > 4.0) return fail(ctx, RW_E_INVAL, "expand must be in [1, 4]");
     if (!(P.t_hom >= 0) || !(P.t_bin >= 0) || !(P.t_inc >= 0)) return fail(ctx, RW_E_INVAL, "thresholds must be >= 0");
     if (P.incremental < 0 || P.incremental > 3) return fail(ctx, RW_E_INVAL, "incremental must be in 0..3");
+    if (P.schedule < 0 || P.schedule > RW_SCHED_TUNED) return fail(ctx, RW_E_INVAL, "schedule must be in 0..5");
+    if (P.reserved != 0) return fail(ctx, RW_E_INVAL, "reserved must be 0");
     for (int64_t i = 0; i < n_seeds; ++i) {
         const rw_seed& q = seeds[i];
         if (!std::isfinite(q.x) || !std::isfinite(q.y) || !std::isfinite(q.z))
