@@ -312,7 +312,7 @@ enum rw_path {
     RW_PATH_STREAM = 0,          /* one workgroup per box, vectors streamed from HBM, LDS window march */
     RW_PATH_STREAM_GLOBAL = 1,   /* the same without the LDS window (planes wider than it holds) */
     RW_PATH_RESIDENT = 2,        /* one workgroup per box, p in LDS, x and r in registers, the edge
-                                    weights in registers (boxes up to 5120 voxels) or in LDS (up
+                                    weights in registers (boxes up to 9216 voxels) or in LDS (up
                                     to 10240 voxels) */
     RW_PATH_DOMAIN = 3,          /* large single box: many workgroups, host-driven iteration */
     RW_PATH_RESIDENT_STREAMED = 4 /* one workgroup per box, p in LDS, r in registers; the edge

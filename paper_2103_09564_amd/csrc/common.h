@@ -222,7 +222,7 @@ struct PlanePlan {
 // Resident PCG (resident.hip).
 constexpr int kResThreads = 512;
 constexpr int kResMaxVptW = 20;   // weights-in-LDS kernel: boxes up to 10240 voxels
-constexpr int kResMaxVptR = 10;   // weights-in-registers kernel: boxes up to 5120 voxels
+constexpr int kResMaxVptR = 18;   // weights-in-registers kernel: boxes up to 9216 voxels
 constexpr int kResSmallVox = 5120;  // the small weights group: at most 10 voxels per thread
 constexpr int kResSpanG0 = 17408;   // streamed-weights kernel: voxel slots of its launches for
 constexpr int kResSpanG1 = 32768;   // boxes up to 32 x 32 x 17 and up to 32^3

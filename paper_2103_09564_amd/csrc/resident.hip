@@ -405,7 +405,7 @@ __global__ __launch_bounds__(NT) void k_pcg_resr(SolveArgs a, float* xt, int cor
     extern __shared__ __align__(16) float pr_lds[];
     __shared__ double red[(NT / 64) * 5];  // block sums of up to 5 values (the start state)
     constexpr int NC = (VPT + 31) / 32;  // unknown-voxel bits
-    constexpr int U = 2;                 // voxels per thread whose loads are issued together
+    constexpr int U = VPT > 10 ? 1 : 2;  // voxels per thread whose loads are issued together
     const int ib = base + blockIdx.x;
     BoxState& st = a.state[ib];
     const bool fused = a.fused_init && !corr;  // this kernel computes the start state
@@ -421,9 +421,14 @@ __global__ __launch_bounds__(NT) void k_pcg_resr(SolveArgs a, float* xt, int cor
 
     // Main solve: P holds x (pads 0) while the weights and the start state
     // are computed.  Otherwise P starts at 0.
-    res_fill_p<NT, 4>(P, xb, -nxy, nv + nxy + 1, nv, fused);
+    constexpr int span = NT * VPT;  // voxel slots: a thread's unused ones (v >= nv) are LDS slots of their own
+    res_fill_p<NT, 4>(P, xb, -nxy, span + nxy, nv, fused);
     if (fused) __syncthreads();
-    float x[VPT], r[VPT], q[VPT], p[VPT], d[VPT], id[VPT], w[6][VPT];
+    // above 10 voxels per thread d is not kept but summed from the six
+    // weights in every pass (the same sum in the same order, so the same
+    // value): one register per voxel less, which 18 voxels per thread need
+    constexpr bool kKeepD = VPT <= 10;
+    float x[VPT], r[VPT], q[VPT], p[VPT], d[kKeepD ? VPT : 1], id[VPT], w[6][VPT];
     unsigned unk[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) unk[c] = 0u;
@@ -501,7 +506,7 @@ __global__ __launch_bounds__(NT) void k_pcg_resr(SolveArgs a, float* xt, int cor
                 }
 #pragma unroll
                 for (int e = 0; e < 6; ++e) w[e][k] = uk ? we[e] : 0.0f;
-                d[k] = uk ? dd : 0.0f;
+                if constexpr (kKeepD) d[k] = uk ? dd : 0.0f;
                 id[k] = uk ? __builtin_amdgcn_rcpf(dd) : 0.0f;
                 x[k] = uk ? xv : 0.0f;
                 r[k] = uk ? r0 : 0.0f;
@@ -535,31 +540,38 @@ __global__ __launch_bounds__(NT) void k_pcg_resr(SolveArgs a, float* xt, int cor
             flags = 2;
             break;
         }
-        // opaque copies, fresh for each pass: no per-voxel address is kept
-        // from one pass to the next
+        // one base per neighbour direction, fresh for each pass (opaque
+        // copies); slot k is base + k * NT, an immediate offset, so no
+        // per-voxel address is kept
         int tb = threadIdx.x;
         asm volatile("" : "+v"(tb));
+        float* const Pt = P + tb;
         const float be = it == 0 ? 0.0f : (float)betac;
         // p = z + beta p (0 on seeded and unused slots)
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
             p[k] = q[k] + be * p[k];
-            const int v0 = tb + k * NT;
-            P[v0 < nv ? v0 : nv] = p[k];
+            Pt[k * NT] = p[k];
         }
         __syncthreads();
         int t2 = threadIdx.x, oy = nx, oz = nxy;
         asm volatile("" : "+v"(t2));
         asm volatile("" : "+v"(oy));
         asm volatile("" : "+v"(oz));
+        const float* const Q0 = P + t2;
+        const float* const Qyp = Q0 + oy;
+        const float* const Qym = Q0 - oy;
+        const float* const Qzp = Q0 + oz;
+        const float* const Qzm = Q0 - oz;
         double sig = 0.0;
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
-            const int v0 = t2 + k * NT;
-            const int v = v0 < nv ? v0 : nv;
-            const float acc = w[0][k] * P[v + 1] + w[1][k] * P[v - 1] + w[2][k] * P[v + oy] + w[3][k] * P[v - oy] +
-                              w[4][k] * P[v + oz] + w[5][k] * P[v - oz];
-            q[k] = d[k] * p[k] - acc;
+            const float acc = w[0][k] * Q0[k * NT + 1] + w[1][k] * Q0[k * NT - 1] + w[2][k] * Qyp[k * NT] +
+                              w[3][k] * Qym[k * NT] + w[4][k] * Qzp[k * NT] + w[5][k] * Qzm[k * NT];
+            float dk;
+            if constexpr (kKeepD) dk = d[k];
+            else dk = ((w[0][k] + w[2][k]) + w[4][k]) + w[1][k] + w[3][k] + w[5][k];
+            q[k] = dk * p[k] - acc;
             sig += (double)p[k] * (double)q[k];
         }
         double s1[1] = {sig};
@@ -960,11 +972,20 @@ bool resident_w_fits(const BrickDev& b, size_t lds_limit) {
 }
 
 // The weights-in-registers kernel: p alone in LDS, at most kResMaxVptR voxels
-// per thread.
+// per thread; its LDS array holds every voxel slot of the launch (threads x
+// voxels per thread, as launch_resident picks them) and nx*ny pads on both
+// sides.
+static int64_t resident_r_vpt(int64_t max_voxels) {
+    const int64_t v = (max_voxels + kResThreads - 1) / kResThreads;
+    return v <= 4 ? 4 : v <= 8 ? 8 : v <= 10 ? 10 : kResMaxVptR;
+}
+static int64_t resident_r_lds_elems(int64_t max_voxels, int64_t plane) {
+    return resident_r_vpt(max_voxels) * kResThreads + 2 * plane;
+}
 bool resident_r_fits(const BrickDev& b, size_t lds_limit) {
     const int64_t nxy = (int64_t)b.nx * b.ny, nv = nxy * b.nz;
     return nv <= (int64_t)kResMaxVptR * kResThreads &&
-           (size_t)resident_lds_elems(nv, nxy) * sizeof(float) + 1024 <= lds_limit;
+           (size_t)resident_r_lds_elems(nv, nxy) * sizeof(float) + 1024 <= lds_limit;
 }
 
 // Voxel slots (threads x voxels per thread) of a streamed-weights launch
@@ -996,7 +1017,7 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
                            int kind, int px, float* xt, int corr, hipStream_t s) {
     if (b1 <= b0) return hipSuccess;
     const size_t lds = kind == 2   ? resident_g_lds(resident_g_span(max_voxels), max_plane)
-                       : kind == 3 ? (size_t)resident_lds_elems(max_voxels, max_plane) * sizeof(float)
+                       : kind == 3 ? (size_t)resident_r_lds_elems(max_voxels, max_plane) * sizeof(float)
                                    : (size_t)resident_lds_elems(max_voxels, max_plane) * sizeof(float4);
     const dim3 grid((unsigned)(b1 - b0));
     auto go = [&](auto kern, int nt) -> hipError_t {
@@ -1032,6 +1053,7 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
     if (kind == 3) {
         if (vpt <= 4) return go(k_pcg_resr<kResThreads, 4>, nt);
         if (vpt <= 8) return go(k_pcg_resr<kResThreads, 8>, nt);
+        if (vpt <= 10) return go(k_pcg_resr<kResThreads, 10>, nt);
         if (vpt <= kResMaxVptR) return go(k_pcg_resr<kResThreads, kResMaxVptR>, nt);
     }
     return hipErrorInvalidValue;
