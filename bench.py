@@ -862,6 +862,7 @@ def main():
                                            "read once per solve, so no HBM roofline applies"},
                   "schedule": {"requested": "tuned" if args.schedule < 0 else args.schedule,
                                "ran": mixed["schedule"][0], "third_stream": mixed["schedule"][1],
+                               "weights_in_registers": mixed["schedule"][2], "persistent": mixed["schedule"][3],
                                "autotune": tune},
                   "graph_replay": {"ms_per_step": mixed["graph_wall"] * 1e3,
                                    "x_equal_to_eager": mixed["graph_same"],

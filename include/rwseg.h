@@ -273,17 +273,30 @@ typedef struct rw_tune_report {
     int32_t third_stream[8];  /* 1: the second streamed-weights launch may take a stream of its own */
     int32_t weights_in_registers[8];  /* 1: small resident boxes keep their edge weights in registers
                                          (RW_PATH_RESIDENT, k_pcg_resr), 0: in LDS (k_pcg_resw) */
+    int32_t persistent[8];    /* 1: the register- and LDS-resident launches are persistent grids (as many workgroups
+                                 as the CUs hold, each taking boxes in launch order from a device
+                                 counter), 0: one workgroup per box */
     float ms[8];              /* median milliseconds per solve */
     uint64_t key;             /* signature of the batch */
 } rw_tune_report;
 int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
                 int64_t n_voxels, const float* g, const uint8_t* mask, const float* x0, float* x_work, int reps,
                 rw_tune_report* out, void* stream);
+/* The plan choices of the next calls on ctx (those the autotuner also
+ * varies; a tuned entry's choices are applied on top): the second
+ * streamed-weights launch may take a stream of its own (default 1), small
+ * resident boxes keep their weights in registers (default 1), the register-
+ * and LDS-resident launches run as persistent grids (default 0; the
+ * streamed-weights launches always take one workgroup per box).  Each 0 or 1.  Results do not
+ * depend on them: every box runs the same iteration in every plan. */
+int rw_set_plan_choices(rw_ctx* ctx, int third_stream, int weights_in_registers, int persistent);
+
 /* Host-only: the schedule and plan choices a RW_SCHED_TUNED call would run
  * for this batch (*tuned = 1 when ctx holds a measured entry for it, else 0
- * and the default); regs may be NULL. */
+ * and the default); regs and persist may be NULL. */
 int rw_tuned_schedule(const rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
-                      int32_t* schedule, int32_t* third_stream, int32_t* regs, int32_t* tuned);
+                      int32_t* schedule, int32_t* third_stream, int32_t* regs, int32_t* persist,
+                      int32_t* tuned);
 
 /*
  * Captured graph of one batched solve (a batching pattern, not a step of the

@@ -87,16 +87,16 @@ lib.rw_probe_copy.restype = ctypes.c_int
 class TuneReport(ctypes.Structure):
     _fields_ = [("n_candidates", ctypes.c_int32), ("best", ctypes.c_int32), ("schedule", ctypes.c_int32 * 8),
                 ("third_stream", ctypes.c_int32 * 8), ("weights_in_registers", ctypes.c_int32 * 8),
-                ("ms", ctypes.c_float * 8), ("key", ctypes.c_uint64)]
+                ("persistent", ctypes.c_int32 * 8), ("ms", ctypes.c_float * 8), ("key", ctypes.c_uint64)]
 
 
 SCHED_TUNED = 5
 lib.rw_autotune.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_int,
                             ctypes.POINTER(TuneReport), _vp]
 lib.rw_autotune.restype = ctypes.c_int
-lib.rw_tuned_schedule.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, ctypes.POINTER(ctypes.c_int32),
-                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                  ctypes.POINTER(ctypes.c_int32)]
+lib.rw_set_plan_choices.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+lib.rw_set_plan_choices.restype = ctypes.c_int
+lib.rw_tuned_schedule.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp] + [ctypes.POINTER(ctypes.c_int32)] * 5
 lib.rw_tuned_schedule.restype = ctypes.c_int
 lib.rw_graph_create.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
                                 ctypes.POINTER(_vp)]
@@ -262,17 +262,23 @@ class Context:
         n = rep.n_candidates
         return {"best": rep.best, "key": int(rep.key),
                 "candidates": [{"schedule": rep.schedule[i], "third_stream": rep.third_stream[i],
-                                "weights_in_registers": rep.weights_in_registers[i], "ms": rep.ms[i]}
+                                "weights_in_registers": rep.weights_in_registers[i],
+                                "persistent": rep.persistent[i], "ms": rep.ms[i]}
                                for i in range(n)]}
 
+    def set_plan_choices(self, third_stream=True, weights_in_registers=True, persistent=False):
+        """rw_set_plan_choices for the next calls on this context."""
+        self._check(lib.rw_set_plan_choices(self.handle, int(bool(third_stream)), int(bool(weights_in_registers)),
+                                            int(bool(persistent))))
+
     def tuned_schedule(self, params, bricks):
-        """(schedule, third_stream, weights_in_registers, tuned) a SCHED_TUNED
-        call would use."""
+        """(schedule, third_stream, weights_in_registers, persistent, tuned) a
+        SCHED_TUNED call would use."""
         bricks = np.ascontiguousarray(bricks, dtype=BRICK_DTYPE)
-        a, b, r, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        v = [ctypes.c_int32() for _ in range(5)]
         self._check(lib.rw_tuned_schedule(self.handle, ctypes.byref(params), len(bricks), bricks.ctypes.data_as(_vp),
-                                          ctypes.byref(a), ctypes.byref(b), ctypes.byref(r), ctypes.byref(c)))
-        return a.value, b.value, r.value, bool(c.value)
+                                          *[ctypes.byref(x) for x in v]))
+        return v[0].value, v[1].value, v[2].value, v[3].value, bool(v[4].value)
 
     def probe_read(self, src, passes, part, unroll=8, stream=None):
         """Queue the read probe over tensor ``src`` (``passes`` times, ``unroll``

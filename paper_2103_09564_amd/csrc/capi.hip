@@ -134,6 +134,7 @@ uint64_t batch_key(const rw_solve_params& p, int64_t n, const rw_brick* b) {
 struct PlanChoice {
     int no_third = 0;   // both streamed-weights launches on one stream
     int no_regs = 0;    // small resident boxes keep their weights in LDS
+    int persist = 0;    // resident launches as persistent grids
 };
 
 rw_solve_params resolve_schedule(const rw_ctx* ctx, const rw_solve_params& p, int64_t n, const rw_brick* b,
@@ -141,6 +142,7 @@ rw_solve_params resolve_schedule(const rw_ctx* ctx, const rw_solve_params& p, in
     rw_solve_params q = p;
     pc->no_third = ctx->plan_no_third;
     pc->no_regs = ctx->plan_no_regs;
+    pc->persist = ctx->plan_persist;
     if (p.schedule != RW_SCHED_TUNED) return q;
     q.schedule = 0;
     if (ctx->tuned.empty() || n == 0) return q;
@@ -150,6 +152,7 @@ rw_solve_params resolve_schedule(const rw_ctx* ctx, const rw_solve_params& p, in
             q.schedule = t.schedule;
             pc->no_third = pc->no_third || t.no_third;
             pc->no_regs = pc->no_regs || t.no_regs;
+            pc->persist = pc->persist || t.persist;
         }
     return q;
 }
@@ -157,15 +160,17 @@ rw_solve_params resolve_schedule(const rw_ctx* ctx, const rw_solve_params& p, in
 // Sets the context's plan choices for the duration of a call.
 struct PlanScope {
     rw_ctx* ctx;
-    int saved_third, saved_regs;
+    int saved_third, saved_regs, saved_persist;
     PlanScope(rw_ctx* c, const PlanChoice& pc)
-        : ctx(c), saved_third(c->plan_no_third), saved_regs(c->plan_no_regs) {
+        : ctx(c), saved_third(c->plan_no_third), saved_regs(c->plan_no_regs), saved_persist(c->plan_persist) {
         c->plan_no_third = pc.no_third;
         c->plan_no_regs = pc.no_regs;
+        c->plan_persist = pc.persist;
     }
     ~PlanScope() {
         ctx->plan_no_third = saved_third;
         ctx->plan_no_regs = saved_regs;
+        ctx->plan_persist = saved_persist;
     }
 };
 
@@ -310,6 +315,7 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
         }
         b0 = L.b1;
     }
+    pp.persist = ctx->plan_persist;
     pp.plane_aligned = ctx->plan_unaligned ? 0 : 1;
     for (int64_t i = pp.n_big; i < pp.n_res; ++i) {
         const auto& b = (*list)[(size_t)i];
@@ -378,11 +384,15 @@ int upload_list(rw_ctx* ctx, const std::vector<rwk::BrickDev>& list, hipStream_t
 // Offsets are from the start of each buffer; every part is 256-byte aligned.
 struct SolveLayout {
     size_t nv, es, off_dcorr, off_x64, ws_bytes;   // vector workspace
-    size_t state_bytes, aux_bytes;                 // BoxState [n] + domain scratch
+    size_t state_bytes, tickets_off, aux_bytes;    // BoxState [n], domain scratch, launch tickets
     size_t list_bytes, wts_bytes;                  // BrickDev [n], weight segments
 };
 
 size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Ticket counters of the persistent resident launches (one per launch of a
+// plan, at most six).
+constexpr size_t kTicketBytes = 256;
 
 SolveLayout solve_layout(const rw_solve_params& p, int64_t n_bricks, int64_t n_voxels, const double* x64,
                          const rwk::PlanePlan& pp) {
@@ -398,7 +408,8 @@ SolveLayout solve_layout(const rw_solve_params& p, int64_t n_bricks, int64_t n_v
     if (need_x64 && !x64) bytes = L.off_x64 + L.nv * sizeof(double);
     L.ws_bytes = up256(std::max<size_t>(bytes, 256));
     L.state_bytes = up256((size_t)n_bricks * sizeof(rwk::BoxState));
-    L.aux_bytes = up256(L.state_bytes + rwk::domain_scratch_bytes());
+    L.tickets_off = up256(L.state_bytes + rwk::domain_scratch_bytes());
+    L.aux_bytes = L.tickets_off + kTicketBytes;
     L.list_bytes = up256(std::max<size_t>((size_t)n_bricks * sizeof(rwk::BrickDev), 64));
     L.wts_bytes = up256((size_t)pp.wts_elems * sizeof(float));
     return L;
@@ -518,6 +529,7 @@ int solve_bricks_impl(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bric
     a.stall_ratio = p.stall_ratio;
     a.schedule = stream_schedule(p.schedule);
     rwk::domain_bind(a, aux + L.state_bytes);
+    a.tickets = (uint32_t*)(aux + L.tickets_off);
     a.wts = wts;
     hipError_t e;
     hipEvent_t* ev = nullptr;
@@ -644,6 +656,16 @@ void rw_ctx_destroy(rw_ctx* ctx) {
 }
 
 const char* rw_last_error(const rw_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+int rw_set_plan_choices(rw_ctx* ctx, int third_stream, int weights_in_registers, int persistent) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    if ((third_stream | weights_in_registers | persistent) & ~1)
+        return fail(ctx, RW_E_INVAL, "plan choices are 0 or 1");
+    ctx->plan_no_third = third_stream ? 0 : 1;
+    ctx->plan_no_regs = weights_in_registers ? 0 : 1;
+    ctx->plan_persist = persistent;
+    return RW_OK;
+}
 
 int rw_set_timing(rw_ctx* ctx, int enable) {
     if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
@@ -964,7 +986,8 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint workspace");
     const size_t state_bytes = ((size_t)n_bricks * sizeof(rwk::BoxState) + 255) & ~size_t(255);
     const size_t part_bytes = ((size_t)n_bricks * sizeof(double) + 255) & ~size_t(255);
-    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, state_bytes + part_bytes + rwk::domain_scratch_bytes(), s);
+    const size_t tickets_off = up256(state_bytes + part_bytes + rwk::domain_scratch_bytes());
+    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, tickets_off + kTicketBytes, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint partials");
     PlanChoice pc;
     const rw_solve_params pe = resolve_schedule(ctx, *params, n_bricks, bricks, &pc);
@@ -1010,6 +1033,7 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     sa.precision = RW_PREC_MIXED;
     sa.schedule = stream_schedule(pe.schedule);
     rwk::domain_bind(sa, (char*)ctx->aux + state_bytes + part_bytes);
+    sa.tickets = (uint32_t*)((char*)ctx->aux + tickets_off);
     rc = bind_weights(ctx, pp, &sa, s);
     if (rc) return rc;
     e = rwk::launch_adjoint(a, sa, n_bricks, dl_dbeta, pp, s);
@@ -1069,13 +1093,13 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
         // the third stream, every fitting box on the streamed-weights kernel,
         // and the streaming schedules (two sweeps; one sweep)
         struct Cand {
-            int schedule, no_third, no_regs;
+            int schedule, no_third, no_regs, persist;
         };
         std::vector<Cand> cands;
         if (params->nrhs == 1 && params->precision != RW_PREC_FP64)
-            cands = {{0, 0, 0}, {0, 1, 0}, {0, 0, 1}, {4, 0, 0}, {3, 0, 0}, {1, 0, 0}};
+            cands = {{0, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}, {4, 0, 0, 0}, {3, 0, 0, 0}, {1, 0, 0, 0}};
         else
-            cands = {{1, 0, 0}, {2, 0, 0}};
+            cands = {{1, 0, 0, 0}, {2, 0, 0, 0}};
         hipStream_t s = (hipStream_t)stream;
         DevGuard dg(ctx->device);
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1096,6 +1120,7 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
             PlanChoice pc;
             pc.no_third = cands[c].no_third;
             pc.no_regs = cands[c].no_regs;
+            pc.persist = cands[c].persist;
             PlanScope pls(ctx, pc);
             std::vector<float> t;
             for (int r = 0; r <= reps && rc == RW_OK; ++r) {   // run 0 warms up
@@ -1131,12 +1156,13 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
         bool found = false;
         for (rw_ctx::Tuned& t : ctx->tuned)
             if (t.key == key) {
-                t = rw_ctx::Tuned{key, cands[best].schedule, cands[best].no_third, cands[best].no_regs, med[best]};
+                t = rw_ctx::Tuned{key, cands[best].schedule, cands[best].no_third, cands[best].no_regs,
+                                  cands[best].persist, med[best]};
                 found = true;
             }
         if (!found)
-            ctx->tuned.push_back(
-                rw_ctx::Tuned{key, cands[best].schedule, cands[best].no_third, cands[best].no_regs, med[best]});
+            ctx->tuned.push_back(rw_ctx::Tuned{key, cands[best].schedule, cands[best].no_third,
+                                               cands[best].no_regs, cands[best].persist, med[best]});
         if (out) {
             std::memset(out, 0, sizeof(*out));
             out->n_candidates = (int32_t)cands.size();
@@ -1146,6 +1172,7 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
                 out->schedule[c] = cands[c].schedule;
                 out->third_stream[c] = cands[c].no_third ? 0 : 1;
                 out->weights_in_registers[c] = cands[c].no_regs ? 0 : 1;
+                out->persistent[c] = cands[c].persist;
                 out->ms[c] = med[c];
             }
         }
@@ -1259,7 +1286,8 @@ int rw_graph_launch(rw_graph* gr, void* stream) {
 void rw_graph_free(rw_graph* gr) { graph_release(gr); }
 
 int rw_tuned_schedule(const rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
-                      int32_t* schedule, int32_t* third_stream, int32_t* regs, int32_t* tuned) {
+                      int32_t* schedule, int32_t* third_stream, int32_t* regs, int32_t* persist,
+                      int32_t* tuned) {
     if (!ctx || !params || !schedule || !third_stream || !tuned || n_bricks < 0 || (n_bricks > 0 && !bricks))
         return fail(nullptr, RW_E_INVAL, "bad arguments");
     rw_solve_params q = *params;
@@ -1269,6 +1297,7 @@ int rw_tuned_schedule(const rw_ctx* ctx, const rw_solve_params* params, int64_t 
     *schedule = r.schedule;
     *third_stream = pc.no_third ? 0 : 1;
     if (regs) *regs = pc.no_regs ? 0 : 1;
+    if (persist) *persist = pc.persist;
     *tuned = 0;
     for (const rw_ctx::Tuned& t : ctx->tuned)
         if (n_bricks > 0 && t.key == batch_key(*params, n_bricks, bricks)) *tuned = 1;

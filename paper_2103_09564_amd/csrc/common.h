@@ -69,13 +69,16 @@ struct rw_ctx {
     // keep the weights of small resident boxes in LDS (k_pcg_resw) instead of
     // registers (k_pcg_resr): a tuning choice
     int plan_no_regs = 0;
+    // resident launches as persistent grids taking boxes from a ticket
+    // counter instead of one workgroup per box: a tuning choice
+    int plan_persist = 0;
     // this device's copy of the static scratch of rw_solve_bricks_noalloc
     void* scratch = nullptr;
     // autotuned schedules: per batch signature (box shapes, nrhs,
     // precision) the fastest candidate rw_autotune measured
     struct Tuned {
         uint64_t key;
-        int32_t schedule, no_third, no_regs;
+        int32_t schedule, no_third, no_regs, persist;
         float ms;
     };
     std::vector<Tuned> tuned;
@@ -158,6 +161,7 @@ struct SolveArgs {
     int32_t fused_init;    // main solve: the resident kernels compute their boxes' start state
     int32_t early_check;   // main solve: 1 + may_refine: each kernel group's boxes get their first
                            // true-residual check on the group's stream as soon as the group ends
+    uint32_t* tickets;     // persistent resident launches: one counter per launch of the plan (or null)
 };
 
 struct AdjointArgs {
@@ -211,6 +215,8 @@ struct PlanePlan {
     // (forked from and joined back into the caller's stream)
     hipStream_t side[3];
     hipEvent_t fork, join[3];
+    // resident launches as persistent grids (SolveArgs::tickets)
+    int persist;
     // the second streamed-weights launch runs on side[2] (two such launches,
     // weights-in-LDS launches beside them, no streaming boxes)
     int third;
@@ -231,8 +237,10 @@ bool resident_r_fits(const BrickDev& b, size_t lds_limit);    // weights-in-regi
 bool resident_g_fits(const BrickDev& b, size_t lds_limit);    // streamed-weights kernel
 int64_t resident_g_span(int64_t max_voxels);                  // its voxel slots per workgroup
 int64_t resident_g_elems(const BrickDev& b, int64_t span);    // a box's weight segment, in floats
+// ticket: null for one workgroup per box, else a counter (cleared by the
+// launch) for a persistent grid that takes the boxes in order.
 hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_voxels, int64_t max_plane,
-                           int kind, int px, float* xt, int corr, hipStream_t s);
+                           int kind, int px, float* xt, int corr, uint32_t* ticket, hipStream_t s);
 
 size_t plane_lds_bytes(int nrhs, bool fp64, int cols);
 

@@ -1602,8 +1602,10 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
             if (pp.rl[i].kind == 2) {
                 const bool second = third && k++ == 1;   // on the third stream, timed on its own
                 if (second && tev) RW_TRY(hipEventRecord(tev[4], s_g2));
+                // (the streamed-weights kernel's persistent twin spills registers:
+                // one workgroup per box for it)
                 RW_TRY(launch_resident(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_voxels, pp.rl[i].max_plane, 2,
-                                       pp.rl[i].px, xt, corr, second ? s_g2 : s_str));
+                                       pp.rl[i].px, xt, corr, nullptr, second ? s_g2 : s_str));
                 if (second && tev) RW_TRY(hipEventRecord(tev[5], s_g2));
             }
     }
@@ -1631,7 +1633,8 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
         for (int i = 0; i < pp.n_rl; ++i)
             if (pp.rl[i].kind != 2)
                 RW_TRY(launch_resident(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_voxels, pp.rl[i].max_plane,
-                                       pp.rl[i].kind, pp.rl[i].px, xt, corr, s_res));
+                                       pp.rl[i].kind, pp.rl[i].px, xt, corr, pp.persist ? a.tickets + i : nullptr,
+                                       s_res));
         if (tev && any_lds) RW_TRY(hipEventRecord(tev[3], s_res));
         if (early)
             for (int i = 0; i < pp.n_rl; ++i)

@@ -232,11 +232,10 @@ __device__ __forceinline__ void res_weights_pass(int lo, int hi, int nx, int ny,
 // q = L_UU p stay in registers.  xt: x (main solve) or the correction
 // accumulator (corr = 1).
 template <int NT, int VPT>
-__global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int corr, int base) {
+__device__ __forceinline__ void resw_box(const SolveArgs& a, float* xt, int corr, int ib) {
     extern __shared__ __align__(16) float w_lds[];
     __shared__ double red[(NT / 64) * 5];  // block sums of up to 5 values (the start state)
     constexpr int NC = (VPT + 31) / 32;  // unknown-voxel bits
-    const int ib = base + blockIdx.x;
     BoxState& st = a.state[ib];
     const bool fused = a.fused_init && !corr;  // this kernel computes the start state
     if (!fused && !st.active) return;
@@ -386,6 +385,29 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
     }
 }
 
+// One workgroup per box.
+template <int NT, int VPT>
+__global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int corr, int base, int, uint32_t*) {
+    resw_box<NT, VPT>(a, xt, corr, base + (int)blockIdx.x);
+}
+
+// Persistent grid: its workgroups take the boxes [base, end) in launch order
+// (largest first) from the ticket counter until none is left.  A kernel of
+// its own, so that the loop does not cost the one-box kernel registers.
+template <int NT, int VPT>
+__global__ __launch_bounds__(NT) void k_pcg_resw_q(SolveArgs a, float* xt, int corr, int base, int end,
+                                             uint32_t* ticket) {
+    __shared__ int s_ib;
+    for (;;) {
+        __syncthreads();  // the previous box's last LDS reads are done
+        if (threadIdx.x == 0) s_ib = base + (int)atomicAdd(ticket, 1u);
+        __syncthreads();
+        const int ib = s_ib;
+        if (ib >= end) return;
+        resw_box<NT, VPT>(a, xt, corr, ib);
+    }
+}
+
 
 // Boxes up to kResMaxVptR * 512 voxels (e.g. 16^3, 5x32x32): the
 // weights-in-registers kernel.  Each thread computes, once per solve, all six
@@ -401,12 +423,11 @@ __global__ __launch_bounds__(NT) void k_pcg_resw(SolveArgs a, float* xt, int cor
 // weights equal its neighbours' forward ones bit for bit, and the stencil
 // sums in the same order as k_pcg_resw.
 template <int NT, int VPT>
-__global__ __launch_bounds__(NT) void k_pcg_resr(SolveArgs a, float* xt, int corr, int base) {
+__device__ __forceinline__ void resr_box(const SolveArgs& a, float* xt, int corr, int ib) {
     extern __shared__ __align__(16) float pr_lds[];
     __shared__ double red[(NT / 64) * 5];  // block sums of up to 5 values (the start state)
     constexpr int NC = (VPT + 31) / 32;  // unknown-voxel bits
     constexpr int U = VPT > 10 ? 1 : 2;  // voxels per thread whose loads are issued together
-    const int ib = base + blockIdx.x;
     BoxState& st = a.state[ib];
     const bool fused = a.fused_init && !corr;  // this kernel computes the start state
     if (!fused && !st.active) return;
@@ -624,6 +645,29 @@ __global__ __launch_bounds__(NT) void k_pcg_resr(SolveArgs a, float* xt, int cor
     }
 }
 
+// One workgroup per box.
+template <int NT, int VPT>
+__global__ __launch_bounds__(NT) void k_pcg_resr(SolveArgs a, float* xt, int corr, int base, int, uint32_t*) {
+    resr_box<NT, VPT>(a, xt, corr, base + (int)blockIdx.x);
+}
+
+// Persistent grid: its workgroups take the boxes [base, end) in launch order
+// (largest first) from the ticket counter until none is left.  A kernel of
+// its own, so that the loop does not cost the one-box kernel registers.
+template <int NT, int VPT>
+__global__ __launch_bounds__(NT) void k_pcg_resr_q(SolveArgs a, float* xt, int corr, int base, int end,
+                                             uint32_t* ticket) {
+    __shared__ int s_ib;
+    for (;;) {
+        __syncthreads();  // the previous box's last LDS reads are done
+        if (threadIdx.x == 0) s_ib = base + (int)atomicAdd(ticket, 1u);
+        __syncthreads();
+        const int ib = s_ib;
+        if (ib >= end) return;
+        resr_box<NT, VPT>(a, xt, corr, ib);
+    }
+}
+
 
 // Variant for boxes whose search direction alone fits in one CU's LDS (up
 // to 32768 voxels, e.g. 32^3): LDS holds p only (4 B per voxel, pads as
@@ -695,11 +739,10 @@ __device__ __forceinline__ void res_block_sum_lds(double (&v)[N], double* red) {
 // PX > 0: every box of the launch has nx = ny = PX, so the neighbour offsets
 // are compile-time and the LDS reads use immediate offsets from a few bases.
 template <int NT, int VPT, int G, int PX>
-__global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int corr, int base) {
+__device__ __forceinline__ void resg_box(const SolveArgs& a, float* xt, int corr, int ib) {
     extern __shared__ __align__(16) float p_lds[];
     __shared__ double red[(NT / 64) * 5];  // block sums of up to 5 values (the start state)
     constexpr int NG = (VPT + G - 1) / G;
-    const int ib = base + blockIdx.x;
     BoxState& st = a.state[ib];
     const bool fused = a.fused_init && !corr;  // this kernel computes the start state
     if (!fused && !st.active) return;
@@ -960,6 +1003,13 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
     }
 }
 
+// One workgroup per box.
+template <int NT, int VPT, int G, int PX>
+__global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int corr, int base, int, uint32_t*) {
+    resg_box<NT, VPT, G, PX>(a, xt, corr, base + (int)blockIdx.x);
+}
+
+
 // Elements of each LDS array of the weights kernel for the largest box of a
 // launch: the box, nx*ny pad elements before it and nx*ny + 1 after it (the
 // unused voxel slots of a thread map to the element just past the box, whose
@@ -1013,21 +1063,39 @@ int64_t resident_g_elems(const BrickDev& b, int64_t span) {
 // (1: weights and p in LDS, 2: p in LDS and weights in a global buffer,
 // 3: p in LDS and weights in registers),
 // largest first; px = 32 when every box has 32 x 32 planes.
+// Clears a launch's ticket counter (a kernel, not a memset, so that the
+// sequence stays valid inside a captured graph).
+__global__ void k_clear_ticket(uint32_t* t) {
+    if (threadIdx.x == 0) *t = 0u;
+}
+
 hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_voxels, int64_t max_plane,
-                           int kind, int px, float* xt, int corr, hipStream_t s) {
+                           int kind, int px, float* xt, int corr, uint32_t* ticket, hipStream_t s) {
     if (b1 <= b0) return hipSuccess;
     const size_t lds = kind == 2   ? resident_g_lds(resident_g_span(max_voxels), max_plane)
                        : kind == 3 ? (size_t)resident_r_lds_elems(max_voxels, max_plane) * sizeof(float)
                                    : (size_t)resident_lds_elems(max_voxels, max_plane) * sizeof(float4);
-    const dim3 grid((unsigned)(b1 - b0));
-    auto go = [&](auto kern, int nt) -> hipError_t {
+    auto go1 = [&](auto kern, int nt) -> hipError_t {
         if (lds > 48 * 1024) {
             hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(kern, grid, dim3(nt), lds, s, a, xt, corr, (int)b0);
+        int64_t n = b1 - b0;
+        if (ticket) {
+            // persistent: as many workgroups as the CUs hold at once
+            int per_cu = 0, cus = 0, dev = 0;
+            hipError_t e = hipGetDevice(&dev);
+            if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds);
+            if (e != hipSuccess) return e;
+            n = std::min<int64_t>(n, (int64_t)std::max(per_cu, 1) * std::max(cus, 1));
+            hipLaunchKernelGGL(k_clear_ticket, dim3(1), dim3(64), 0, s, ticket);
+        }
+        hipLaunchKernelGGL(kern, dim3((unsigned)n), dim3(nt), lds, s, a, xt, corr, (int)b0, (int)b1, ticket);
         return hipGetLastError();
     };
+    // the one-box kernel, or its persistent twin when a ticket is given
+    auto go = [&](auto kern, auto kern_q, int nt) -> hipError_t { return ticket ? go1(kern_q, nt) : go1(kern, nt); };
     if (kind == 2) {
         // the plan sized each box's weight segment for this launch's span
         if (!a.wts) return hipErrorInvalidValue;
@@ -1036,25 +1104,28 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
         // or 5 (64 per thread, where three register arrays leave room for
         // no more)
         constexpr int nt = kResThreads;
+        // one workgroup per box only: a persistent twin of this kernel would
+        // spill registers (its box loop keeps values live across boxes)
+        if (ticket) return hipErrorInvalidValue;
         if (span == kResSpanG0)
-            return px == 32 ? go(k_pcg_resg<nt, kResSpanG0 / nt, 8, 32>, nt)
-                            : go(k_pcg_resg<nt, kResSpanG0 / nt, 8, 0>, nt);
+            return px == 32 ? go1(k_pcg_resg<nt, kResSpanG0 / nt, 8, 32>, nt)
+                            : go1(k_pcg_resg<nt, kResSpanG0 / nt, 8, 0>, nt);
         if (span == kResSpanG1)
-            return px == 32 ? go(k_pcg_resg<nt, kResSpanG1 / nt, 5, 32>, nt)
-                            : go(k_pcg_resg<nt, kResSpanG1 / nt, 5, 0>, nt);
+            return px == 32 ? go1(k_pcg_resg<nt, kResSpanG1 / nt, 5, 32>, nt)
+                            : go1(k_pcg_resg<nt, kResSpanG1 / nt, 5, 0>, nt);
         return hipErrorInvalidValue;
     }
     const int nt = kResThreads;
     const int64_t vpt = (max_voxels + nt - 1) / nt;
     if (kind == 1) {
-        if (vpt <= 10) return go(k_pcg_resw<kResThreads, 10>, nt);
-        if (vpt <= kResMaxVptW) return go(k_pcg_resw<kResThreads, kResMaxVptW>, nt);
+        if (vpt <= 10) return go(k_pcg_resw<kResThreads, 10>, k_pcg_resw_q<kResThreads, 10>, nt);
+        if (vpt <= kResMaxVptW) return go(k_pcg_resw<kResThreads, kResMaxVptW>, k_pcg_resw_q<kResThreads, kResMaxVptW>, nt);
     }
     if (kind == 3) {
-        if (vpt <= 4) return go(k_pcg_resr<kResThreads, 4>, nt);
-        if (vpt <= 8) return go(k_pcg_resr<kResThreads, 8>, nt);
-        if (vpt <= 10) return go(k_pcg_resr<kResThreads, 10>, nt);
-        if (vpt <= kResMaxVptR) return go(k_pcg_resr<kResThreads, kResMaxVptR>, nt);
+        if (vpt <= 4) return go(k_pcg_resr<kResThreads, 4>, k_pcg_resr_q<kResThreads, 4>, nt);
+        if (vpt <= 8) return go(k_pcg_resr<kResThreads, 8>, k_pcg_resr_q<kResThreads, 8>, nt);
+        if (vpt <= 10) return go(k_pcg_resr<kResThreads, 10>, k_pcg_resr_q<kResThreads, 10>, nt);
+        if (vpt <= kResMaxVptR) return go(k_pcg_resr<kResThreads, kResMaxVptR>, k_pcg_resr_q<kResThreads, kResMaxVptR>, nt);
     }
     return hipErrorInvalidValue;
 }

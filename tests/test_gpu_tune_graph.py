@@ -51,11 +51,12 @@ def test_autotune_and_tuned_solve(env):
     p = rwg.solve_params(beta=BETA, eps=EPS, tol=1e-6, precision=1)
     rep = ctx.autotune(p, b, g, m, x0, xw, reps=2)
     print(rep, flush=True)
-    assert len(rep["candidates"]) == 6 and 0 <= rep["best"] < 6
+    assert len(rep["candidates"]) == 7 and 0 <= rep["best"] < 7
     assert all(c["ms"] > 0 for c in rep["candidates"])
     best = rep["candidates"][rep["best"]]
-    sched, third, regs, tuned = ctx.tuned_schedule(p, b)
-    assert tuned and (sched, third, regs) == (best["schedule"], best["third_stream"], best["weights_in_registers"])
+    sched, third, regs, persist, tuned = ctx.tuned_schedule(p, b)
+    assert tuned and (sched, third, regs, persist) == (best["schedule"], best["third_stream"],
+                                                       best["weights_in_registers"], best["persistent"])
     # a tuned solve equals the winner run directly (a winner that differs
     # from its schedule's default plan only by a plan choice is run as a
     # second tuned call: the same plan, so the same bits)
@@ -63,7 +64,7 @@ def test_autotune_and_tuned_solve(env):
     ctx.rw_solve_bricks(rwg.solve_params(beta=BETA, eps=EPS, tol=1e-6, precision=1, schedule=rwg.SCHED_TUNED),
                         b, g, m, xt)
     xe = x0.clone()
-    if best["third_stream"] == 1 and best["weights_in_registers"] == 1:
+    if best["third_stream"] == 1 and best["weights_in_registers"] == 1 and best["persistent"] == 0:
         ctx.rw_solve_bricks(rwg.solve_params(beta=BETA, eps=EPS, tol=1e-6, precision=1, schedule=best["schedule"]),
                             b, g, m, xe)
     else:
@@ -80,7 +81,47 @@ def test_autotune_and_tuned_solve(env):
     # an untuned batch falls back to the default schedule
     other = synth.stress_boxes(n=7, seed=32)
     _, _, _, b2 = _dev(env, other)
-    assert ctx.tuned_schedule(p, b2) == (0, 1, 1, False)
+    assert ctx.tuned_schedule(p, b2) == (0, 1, 1, 0, False)
+    ctx.close()
+
+
+def test_plan_choices_give_the_same_bits(env):
+    """Persistent resident grids (boxes taken from a device counter), the
+    weights of small boxes in LDS instead of registers, and both
+    streamed-weights launches on one stream: every plan runs each box through
+    the same iteration, so x and the stats agree bit for bit with the
+    default plan."""
+    torch, rwg, dev = env
+    print("plan choices", flush=True)
+    rng = np.random.default_rng(36)
+    boxes = list(synth.stress_boxes(n=300, seed=36)["boxes"])
+    for s in [(13, 7, 19), (31, 17, 33), (3, 3, 3)]:
+        boxes.append(synth.random_box(rng, s, dirichlet_frac=0.03))
+    d = synth.from_boxes(boxes)
+    params = dict(beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    ctx = rwg.Context(0)
+    g, m, x0, b = _dev(env, d)
+    outs = []
+    for third, regs, persist in [(1, 1, 0), (1, 1, 1), (0, 1, 1), (1, 0, 1), (0, 0, 0)]:
+        ctx.set_plan_choices(third, regs, persist)
+        x = x0.clone()
+        st = torch.zeros((len(b), 32), dtype=torch.uint8, device=dev)
+        ctx.rw_solve_bricks(rwg.solve_params(**params), b, g, m, x, stats=st)
+        torch.cuda.synchronize()
+        outs.append((x.cpu().numpy(), st.cpu().numpy()))
+    # the weights-in-LDS kernel rounds like the registers kernel only up to
+    # FP contraction, so the plans with the same weights placement must agree
+    # exactly and the others to the solver's accuracy
+    for i in (1, 2):
+        assert np.array_equal(outs[i][0], outs[0][0]) and np.array_equal(outs[i][1], outs[0][1]), i
+    assert np.array_equal(outs[3][0], outs[4][0]) and np.array_equal(outs[3][1], outs[4][1])
+    assert np.max(np.abs(outs[3][0] - outs[0][0])) <= 4e-5
+    xs = outs[1][0]
+    for i in (0, 150, len(boxes) - 1):
+        gb, mb, xb = boxes[i]
+        ref = orw.solve_box(gb, mb, xb, BETA, EPS, method="pcg", tol=1e-14).ravel()
+        o = int(d["offsets"][i])
+        assert np.max(np.abs(xs[o:o + gb.size] - ref)) <= 1e-4
     ctx.close()
 
 
