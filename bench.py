@@ -868,6 +868,10 @@ def main():
                                    "x_equal_to_eager": mixed["graph_same"],
                                    "note": "the same solve captured once (rw_graph_create) and replayed K times"},
                   "mean_iters": float(s["iters"].mean()), "max_iters": int(s["iters"].max()),
+                  "iters_by_shape": {f"{a}x{b}x{c}": {"boxes": int(sel.sum()), "mean_iters": float(s["iters"][sel].mean()),
+                                                      "max_iters": int(s["iters"][sel].max())}
+                                     for a, b, c in sorted({tuple(int(v) for v in r) for r in shapes})
+                                     for sel in [(shapes[:, 0] == a) & (shapes[:, 1] == b) & (shapes[:, 2] == c)]},
                   "refined_boxes": int((s["refine_steps"] > 0).sum()),
                   "status_counts": {rwg.STATUS_NAMES[k]: int((s["status"] == k).sum()) for k in np.unique(s["status"])},
                   "max_true_rel_resid": float(s["true_rel_resid"].max()),
