@@ -114,6 +114,35 @@ def measure_ceilings(torch, rwg, ctx, reps=5):
                     "bytes), 32 re-reads of 128 MiB (last-level cache); best of 5 launches"}
 
 
+def probe_read_sweep(torch, rwg, ctx, reps=4):
+    """Read bandwidth against buffer size: each buffer re-read in one probe
+    launch (up to 64 passes, about 4 GiB in all), best of `reps` launches for
+    4, 8 and 16 loads in flight per thread, GB/s.  Buffers up to 32 MiB stay
+    in the XCDs' L2, those up to the 256 MB last-level cache in that cache."""
+    dev = torch.device("cuda:0")
+    part = torch.empty(rwg.probe_blocks(), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for mib in (8, 16, 32, 64, 96, 128, 192, 256, 384, 512, 1024, 4096):
+        buf = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+        passes = max(1, min(64, 4096 // mib))
+        row = {"MiB": mib, "passes": passes}
+        for u in (4, 8, 16):
+            ms = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                ctx.probe_read(buf, passes, part, unroll=u, stream=stream)
+                b.record(stream)
+                b.synchronize()
+                ms.append(a.elapsed_time(b))
+            row[f"GBps_unroll{u}"] = passes * (mib << 20) / (min(ms) * 1e-3) / 1e9
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+        del buf
+    return rows
+
+
 def _oracle_worker(args):
     import numpy as np
     from threadpoolctl import threadpool_limits
@@ -687,7 +716,7 @@ def main():
         if name == "shells_full":
             return bench_shells_full(torch, rwg, ctx, cpu_leg=not args.no_cpu_baseline)
         if name == "memory_ceilings":
-            return measure_ceilings(torch, rwg, ctx)
+            return {"ceilings": measure_ceilings(torch, rwg, ctx), "read_sweep": probe_read_sweep(torch, rwg, ctx)}
         if name == "stress_streamed_from_host":
             return bench_streamed(torch, rwg, ctx)
         return bench_shells(torch, rwg, ctx, dims=shell_dims)
