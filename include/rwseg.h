@@ -60,7 +60,10 @@ enum rw_status {
     RW_ST_REFINED = 2,       /* FP32 solve stalled in FP64; refinement brought it within target */
     RW_ST_STALLED = 3,       /* refinement steps exhausted without meeting the target */
     RW_ST_NONFINITE = 4,     /* NaN/Inf met (input g or breakdown); x left as the last finite iterate */
-    RW_ST_NO_DIRICHLET = 5   /* box has no seeded voxel: problem has no unique solution, x untouched */
+    RW_ST_NO_DIRICHLET = 5,  /* box has no seeded voxel: problem has no unique solution, x untouched */
+    RW_ST_SYNC_LOST = 6      /* the two workgroups of a split box (RW_PATH_RESIDENT_SPLIT) stopped
+                                hearing from each other within a few seconds (a scheduling failure,
+                                not a numerical one); x left as the last iterate */
 };
 
 /* One box (solve domain).  nx, ny, nz >= 1. */
@@ -255,9 +258,10 @@ int rw_last_timing(rw_ctx* ctx, rw_timing* out);
  * schedules of rw_solve_bricks on this batch and records the fastest on ctx
  * for RW_SCHED_TUNED: for MIXED or MIXED_REFINE with one rhs schedule 0
  * (as is, without the second streamed-weights launch on a stream of its
- * own, and with the small resident boxes' weights in LDS instead of
- * registers), schedule 4, schedule 3 and schedule 1; otherwise schedules 1
- * and 2.  Each
+ * own, with the small resident boxes' weights in LDS instead of registers,
+ * with persistent resident grids, and, when the batch has boxes that split,
+ * with those boxes streaming), schedule 4, schedule 3 and schedule 1;
+ * otherwise schedules 1 and 2.  Each
  * candidate runs 1 + reps solves of the batch from x0 (dev, copied into
  * x_work before every run; both [n_voxels * nrhs]); the median of the reps
  * timed runs (HIP events on `stream`) ranks it.  params->schedule must be
@@ -278,6 +282,8 @@ typedef struct rw_tune_report {
                                  counter), 0: one workgroup per box */
     float ms[8];              /* median milliseconds per solve */
     uint64_t key;             /* signature of the batch */
+    int32_t split_boxes[8];   /* 1: boxes above 32768 voxels that fit run split over two
+                                 workgroups (RW_PATH_RESIDENT_SPLIT), 0: they stream */
 } rw_tune_report;
 int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, const rw_brick* bricks,
                 int64_t n_voxels, const float* g, const uint8_t* mask, const float* x0, float* x_work, int reps,
@@ -290,6 +296,11 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
  * streamed-weights launches always take one workgroup per box).  Each 0 or 1.  Results do not
  * depend on them: every box runs the same iteration in every plan. */
 int rw_set_plan_choices(rw_ctx* ctx, int third_stream, int weights_in_registers, int persistent);
+/* Whether boxes above 32768 voxels whose halves fit (RW_PATH_RESIDENT_SPLIT)
+ * run split over two workgroups (enable = 1, the default) or on the
+ * streaming kernels (0), for the next calls on ctx that carry no tuned plan.
+ * Host-only.  RW_E_INVAL unless enable is 0 or 1. */
+int rw_set_split_boxes(rw_ctx* ctx, int enable);
 
 /* Host-only: the schedule and plan choices a RW_SCHED_TUNED call would run
  * for this batch (*tuned = 1 when ctx holds a measured entry for it, else 0
@@ -328,9 +339,14 @@ enum rw_path {
                                     weights in registers (boxes up to 9216 voxels) or in LDS (up
                                     to 10240 voxels) */
     RW_PATH_DOMAIN = 3,          /* large single box: many workgroups, host-driven iteration */
-    RW_PATH_RESIDENT_STREAMED = 4 /* one workgroup per box, p in LDS, r in registers; the edge
+    RW_PATH_RESIDENT_STREAMED = 4, /* one workgroup per box, p in LDS, r in registers; the edge
                                     weights and 1/d are computed once into a per-box buffer and
                                     re-read from cache each iteration (boxes up to 32768 voxels) */
+    RW_PATH_RESIDENT_SPLIT = 5   /* two workgroups per box, one per half along z, each as
+                                    RW_PATH_RESIDENT_STREAMED on its half; the halves exchange
+                                    their partial sums and one plane of z per iteration through
+                                    global memory (boxes above 32768 voxels whose halves hold at
+                                    most 32768 and whose planes at most 2048) */
 };
 
 /*

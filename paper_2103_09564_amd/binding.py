@@ -25,7 +25,7 @@ lib = ctypes.CDLL(LIB_PATH)
 RW_OK, RW_E_INVAL, RW_E_HIP, RW_E_NOMEM, RW_E_UNSUPPORTED = 0, -1, -2, -3, -4
 PREC_FP64, PREC_MIXED, PREC_MIXED_REFINE = 0, 1, 2
 ST_CONVERGED, ST_MAX_ITER, ST_REFINED, ST_STALLED, ST_NONFINITE, ST_NO_DIRICHLET = range(6)
-STATUS_NAMES = ["CONVERGED", "MAX_ITER", "REFINED", "STALLED", "NONFINITE", "NO_DIRICHLET"]
+STATUS_NAMES = ["CONVERGED", "MAX_ITER", "REFINED", "STALLED", "NONFINITE", "NO_DIRICHLET", "SYNC_LOST"]
 
 BRICK_DTYPE = np.dtype([("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"), ("reserved", "<i4"), ("offset", "<i8")])
 STATS_DTYPE = np.dtype([("iters", "<i4"), ("status", "<i4"), ("refine_steps", "<i4"), ("refine_iters", "<i4"),
@@ -87,7 +87,8 @@ lib.rw_probe_copy.restype = ctypes.c_int
 class TuneReport(ctypes.Structure):
     _fields_ = [("n_candidates", ctypes.c_int32), ("best", ctypes.c_int32), ("schedule", ctypes.c_int32 * 8),
                 ("third_stream", ctypes.c_int32 * 8), ("weights_in_registers", ctypes.c_int32 * 8),
-                ("persistent", ctypes.c_int32 * 8), ("ms", ctypes.c_float * 8), ("key", ctypes.c_uint64)]
+                ("persistent", ctypes.c_int32 * 8), ("ms", ctypes.c_float * 8), ("key", ctypes.c_uint64),
+                ("split_boxes", ctypes.c_int32 * 8)]
 
 
 SCHED_TUNED = 5
@@ -96,6 +97,8 @@ lib.rw_autotune.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _
 lib.rw_autotune.restype = ctypes.c_int
 lib.rw_set_plan_choices.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
 lib.rw_set_plan_choices.restype = ctypes.c_int
+lib.rw_set_split_boxes.argtypes = [_vp, ctypes.c_int]
+lib.rw_set_split_boxes.restype = ctypes.c_int
 lib.rw_tuned_schedule.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp] + [ctypes.POINTER(ctypes.c_int32)] * 5
 lib.rw_tuned_schedule.restype = ctypes.c_int
 lib.rw_graph_create.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -108,7 +111,8 @@ lib.rw_graph_free.restype = None
 lib.rw_solve_plan.argtypes = [_vp, ctypes.POINTER(SolveParams), _i64, _vp, _i64, _vp]
 lib.rw_solve_plan.restype = ctypes.c_int
 
-PATH_STREAM, PATH_STREAM_GLOBAL, PATH_RESIDENT, PATH_DOMAIN, PATH_RESIDENT_STREAMED = 0, 1, 2, 3, 4
+PATH_STREAM, PATH_STREAM_GLOBAL, PATH_RESIDENT, PATH_DOMAIN, PATH_RESIDENT_STREAMED, PATH_RESIDENT_SPLIT = \
+    0, 1, 2, 3, 4, 5
 
 
 class RWError(RuntimeError):
@@ -263,13 +267,18 @@ class Context:
         return {"best": rep.best, "key": int(rep.key),
                 "candidates": [{"schedule": rep.schedule[i], "third_stream": rep.third_stream[i],
                                 "weights_in_registers": rep.weights_in_registers[i],
-                                "persistent": rep.persistent[i], "ms": rep.ms[i]}
+                                "persistent": rep.persistent[i], "split_boxes": rep.split_boxes[i],
+                                "ms": rep.ms[i]}
                                for i in range(n)]}
 
     def set_plan_choices(self, third_stream=True, weights_in_registers=True, persistent=False):
         """rw_set_plan_choices for the next calls on this context."""
         self._check(lib.rw_set_plan_choices(self.handle, int(bool(third_stream)), int(bool(weights_in_registers)),
                                             int(bool(persistent))))
+
+    def set_split_boxes(self, enable=True):
+        """rw_set_split_boxes for the next calls on this context."""
+        self._check(lib.rw_set_split_boxes(self.handle, int(bool(enable))))
 
     def tuned_schedule(self, params, bricks):
         """(schedule, third_stream, weights_in_registers, persistent, tuned) a

@@ -135,6 +135,7 @@ struct PlanChoice {
     int no_third = 0;   // both streamed-weights launches on one stream
     int no_regs = 0;    // small resident boxes keep their weights in LDS
     int persist = 0;    // resident launches as persistent grids
+    int no_split = 0;   // boxes above 32768 voxels stream instead of splitting
 };
 
 rw_solve_params resolve_schedule(const rw_ctx* ctx, const rw_solve_params& p, int64_t n, const rw_brick* b,
@@ -143,6 +144,7 @@ rw_solve_params resolve_schedule(const rw_ctx* ctx, const rw_solve_params& p, in
     pc->no_third = ctx->plan_no_third;
     pc->no_regs = ctx->plan_no_regs;
     pc->persist = ctx->plan_persist;
+    pc->no_split = ctx->plan_no_split;
     if (p.schedule != RW_SCHED_TUNED) return q;
     q.schedule = 0;
     if (ctx->tuned.empty() || n == 0) return q;
@@ -153,6 +155,7 @@ rw_solve_params resolve_schedule(const rw_ctx* ctx, const rw_solve_params& p, in
             pc->no_third = pc->no_third || t.no_third;
             pc->no_regs = pc->no_regs || t.no_regs;
             pc->persist = pc->persist || t.persist;
+            pc->no_split = pc->no_split || t.no_split;
         }
     return q;
 }
@@ -160,17 +163,20 @@ rw_solve_params resolve_schedule(const rw_ctx* ctx, const rw_solve_params& p, in
 // Sets the context's plan choices for the duration of a call.
 struct PlanScope {
     rw_ctx* ctx;
-    int saved_third, saved_regs, saved_persist;
+    int saved_third, saved_regs, saved_persist, saved_split;
     PlanScope(rw_ctx* c, const PlanChoice& pc)
-        : ctx(c), saved_third(c->plan_no_third), saved_regs(c->plan_no_regs), saved_persist(c->plan_persist) {
+        : ctx(c), saved_third(c->plan_no_third), saved_regs(c->plan_no_regs), saved_persist(c->plan_persist),
+          saved_split(c->plan_no_split) {
         c->plan_no_third = pc.no_third;
         c->plan_no_regs = pc.no_regs;
         c->plan_persist = pc.persist;
+        c->plan_no_split = pc.no_split;
     }
     ~PlanScope() {
         ctx->plan_no_third = saved_third;
         ctx->plan_no_regs = saved_regs;
         ctx->plan_persist = saved_persist;
+        ctx->plan_no_split = saved_split;
     }
 };
 
@@ -225,7 +231,8 @@ int plan_cols_of(const rw_ctx* ctx, const rw_brick* b, int64_t n, int nrhs, bool
 // Kernel group of one box (the domain cap aside): 0 domain solver, 1 global
 // march, 2 plane march, 3 and 4 resident (p in LDS, weights streamed) above
 // and up to kResSpanG0 voxels, 5 resident (weights in LDS), 6 and 7 resident
-// (weights in registers) above and up to kResSmallVox voxels.
+// (weights in registers) above and up to kResSmallVox voxels, 8 split
+// (two workgroups per box).
 int group_of(const rw_ctx* ctx, int nx, int ny, int nz, int lim, bool res_ok, bool prefer_g, bool dom_left) {
     rwk::BrickDev b{};
     b.nx = nx;
@@ -241,6 +248,7 @@ int group_of(const rw_ctx* ctx, int nx, int ny, int nz, int lim, bool res_ok, bo
         return vox <= rwk::kResSmallVox ? 7 : 6;
     if (res_ok && rwk::resident_w_fits(b, ctx->lds_limit)) return 5;
     if (res_ok && rwk::resident_g_fits(b, ctx->lds_limit)) return vox > rwk::kResSpanG0 ? 3 : 4;
+    if (res_ok && !ctx->plan_no_split && rwk::resident_split_fits(b, ctx->lds_limit)) return 8;
     return wide ? 1 : 2;
 }
 
@@ -276,7 +284,7 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     std::iota(idx.begin(), idx.end(), size_t(0));
     std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return grp[a] < grp[b]; });
     std::vector<rwk::BrickDev> sorted(list->size());
-    int64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t cnt[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (size_t i = 0; i < idx.size(); ++i) {
         sorted[i] = (*list)[idx[i]];
         cnt[grp[idx[i]]] += 1;
@@ -290,12 +298,14 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
     pp.n_rl = 0;
     int64_t b0 = pp.n_res;
     pp.wts_elems = 0;
-    for (int gi = 3; gi <= 7; ++gi) {
+    // (the split boxes sort last; their launch comes first, with the other
+    // streamed-weights launches)
+    for (int gi = 3; gi <= 8; ++gi) {
         if (cnt[gi] == 0) continue;
         rwk::PlanePlan::ResLaunch& L = pp.rl[pp.n_rl++];
         L.b0 = b0;
         L.b1 = b0 + cnt[gi];
-        L.kind = gi <= 4 ? 2 : gi == 5 ? 1 : 3;
+        L.kind = gi <= 4 ? 2 : gi == 5 ? 1 : gi == 8 ? 4 : 3;
         L.max_voxels = 0;
         L.max_plane = 0;
         L.px = 32;
@@ -311,6 +321,13 @@ rwk::PlanePlan plan_planes(const rw_ctx* ctx, std::vector<rwk::BrickDev>* list, 
                 auto& b = (*list)[(size_t)i];
                 b.woff = pp.wts_elems;
                 pp.wts_elems += rwk::resident_g_elems(b, span);
+            }
+        }
+        if (L.kind == 4) {
+            for (int64_t i = L.b0; i < L.b1; ++i) {
+                auto& b = (*list)[(size_t)i];
+                b.woff = pp.wts_elems;
+                pp.wts_elems += rwk::resident_split_elems(b);
             }
         }
         b0 = L.b1;
@@ -339,9 +356,9 @@ int attach_side_streams(rw_ctx* ctx, rwk::PlanePlan* pp) {
     pp->side[0] = ctx->side[0];
     pp->side[1] = ctx->side[1];
     pp->side[2] = ctx->side[2];
-    int n_g = 0, n_w = 0;
-    for (int i = 0; i < pp->n_rl; ++i) (pp->rl[i].kind == 2 ? n_g : n_w) += 1;
-    pp->third = n_g == 2 && n_w > 0 && pp->n_res == pp->n_dom && !ctx->plan_no_third ? 1 : 0;
+    int n_g = 0, n_w = 0, n_s = 0;
+    for (int i = 0; i < pp->n_rl; ++i) (pp->rl[i].kind == 2 ? n_g : pp->rl[i].kind == 4 ? n_s : n_w) += 1;
+    pp->third = n_g == 2 && n_s == 0 && n_w > 0 && pp->n_res == pp->n_dom && !ctx->plan_no_third ? 1 : 0;
     pp->fork = ctx->fork;
     pp->join[0] = ctx->join[0];
     pp->join[1] = ctx->join[1];
@@ -552,7 +569,7 @@ int solve_bricks_impl(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bric
         // bit 0: streaming kernels or streamed-weights resident launches
         // (one stream), bit 1: the other resident launches
         bool any_g = false, any_lds = false;
-        for (int i = 0; i < pp.n_rl; ++i) (pp.rl[i].kind == 2 ? any_g : any_lds) = true;
+        for (int i = 0; i < pp.n_rl; ++i) (pp.rl[i].kind == 2 || pp.rl[i].kind == 4 ? any_g : any_lds) = true;
         const bool res_path = R == 1 && !fp64;
         ctx->gev_used = (pp.n_res > pp.n_dom || (res_path && any_g) ? 1 : 0) | (res_path && any_lds ? 2 : 0) |
                         (res_path && pp.third ? 4 : 0);
@@ -667,6 +684,13 @@ int rw_set_plan_choices(rw_ctx* ctx, int third_stream, int weights_in_registers,
     return RW_OK;
 }
 
+int rw_set_split_boxes(rw_ctx* ctx, int enable) {
+    if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
+    if (enable & ~1) return fail(ctx, RW_E_INVAL, "enable is 0 or 1");
+    ctx->plan_no_split = enable ? 0 : 1;
+    return RW_OK;
+}
+
 int rw_set_timing(rw_ctx* ctx, int enable) {
     if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
     ctx->timing = enable ? 1 : 0;
@@ -727,7 +751,8 @@ int rw_solve_plan(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, 
                      : i < pp.n_res ? RW_PATH_STREAM
                                       : RW_PATH_RESIDENT;
         for (int k = 0; k < pp.n_rl; ++k)
-            if (pp.rl[k].kind == 2 && i >= pp.rl[k].b0 && i < pp.rl[k].b1) path[slot] = RW_PATH_RESIDENT_STREAMED;
+            if (i >= pp.rl[k].b0 && i < pp.rl[k].b1 && (pp.rl[k].kind == 2 || pp.rl[k].kind == 4))
+                path[slot] = pp.rl[k].kind == 2 ? RW_PATH_RESIDENT_STREAMED : RW_PATH_RESIDENT_SPLIT;
     }
     return RW_OK;
     });
@@ -1093,13 +1118,19 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
         // the third stream, every fitting box on the streamed-weights kernel,
         // and the streaming schedules (two sweeps; one sweep)
         struct Cand {
-            int schedule, no_third, no_regs, persist;
+            int schedule, no_third, no_regs, persist, no_split;
         };
         std::vector<Cand> cands;
-        if (params->nrhs == 1 && params->precision != RW_PREC_FP64)
-            cands = {{0, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}, {4, 0, 0, 0}, {3, 0, 0, 0}, {1, 0, 0, 0}};
-        else
-            cands = {{1, 0, 0, 0}, {2, 0, 0, 0}};
+        if (params->nrhs == 1 && params->precision != RW_PREC_FP64) {
+            cands = {{0, 0, 0, 0, 0}, {0, 1, 0, 0, 0}, {0, 0, 1, 0, 0}, {0, 0, 0, 1, 0},
+                     {4, 0, 0, 0, 0}, {3, 0, 0, 0, 0}, {1, 0, 0, 0, 0}};
+            // with split boxes in the batch: the default plan with them streaming
+            bool any_split = false;
+            for (const auto& b : list) any_split = any_split || rwk::resident_split_fits(b, ctx->lds_limit);
+            if (any_split) cands.push_back({0, 0, 0, 0, 1});
+        } else {
+            cands = {{1, 0, 0, 0, 0}, {2, 0, 0, 0, 0}};
+        }
         hipStream_t s = (hipStream_t)stream;
         DevGuard dg(ctx->device);
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1121,6 +1152,7 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
             pc.no_third = cands[c].no_third;
             pc.no_regs = cands[c].no_regs;
             pc.persist = cands[c].persist;
+            pc.no_split = cands[c].no_split;
             PlanScope pls(ctx, pc);
             std::vector<float> t;
             for (int r = 0; r <= reps && rc == RW_OK; ++r) {   // run 0 warms up
@@ -1157,12 +1189,13 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
         for (rw_ctx::Tuned& t : ctx->tuned)
             if (t.key == key) {
                 t = rw_ctx::Tuned{key, cands[best].schedule, cands[best].no_third, cands[best].no_regs,
-                                  cands[best].persist, med[best]};
+                                  cands[best].persist, cands[best].no_split, med[best]};
                 found = true;
             }
         if (!found)
             ctx->tuned.push_back(rw_ctx::Tuned{key, cands[best].schedule, cands[best].no_third,
-                                               cands[best].no_regs, cands[best].persist, med[best]});
+                                               cands[best].no_regs, cands[best].persist, cands[best].no_split,
+                                               med[best]});
         if (out) {
             std::memset(out, 0, sizeof(*out));
             out->n_candidates = (int32_t)cands.size();
@@ -1173,6 +1206,7 @@ int rw_autotune(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bricks, co
                 out->third_stream[c] = cands[c].no_third ? 0 : 1;
                 out->weights_in_registers[c] = cands[c].no_regs ? 0 : 1;
                 out->persistent[c] = cands[c].persist;
+                out->split_boxes[c] = cands[c].no_split ? 0 : 1;
                 out->ms[c] = med[c];
             }
         }

@@ -72,13 +72,16 @@ struct rw_ctx {
     // resident launches as persistent grids taking boxes from a ticket
     // counter instead of one workgroup per box: a tuning choice
     int plan_persist = 0;
+    // solve boxes above 32768 voxels on the streaming kernels instead of
+    // splitting them over two workgroups: a tuning choice
+    int plan_no_split = 0;
     // this device's copy of the static scratch of rw_solve_bricks_noalloc
     void* scratch = nullptr;
     // autotuned schedules: per batch signature (box shapes, nrhs,
     // precision) the fastest candidate rw_autotune measured
     struct Tuned {
         uint64_t key;
-        int32_t schedule, no_third, no_regs, persist;
+        int32_t schedule, no_third, no_regs, persist, no_split;
         float ms;
     };
     std::vector<Tuned> tuned;
@@ -241,6 +244,16 @@ int64_t resident_g_elems(const BrickDev& b, int64_t span);    // a box's weight 
 // launch) for a persistent grid that takes the boxes in order.
 hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_voxels, int64_t max_plane,
                            int kind, int px, float* xt, int corr, uint32_t* ticket, hipStream_t s);
+// Split boxes (two workgroups per box, one per half along z): boxes above
+// kResSpanG1 voxels whose halves hold at most kResSpanG1 and whose planes at
+// most kPairMaxPlane.  Their weight area (BrickDev::woff) holds the two
+// halves' segments and a mailbox of kPairMailboxElems floats.
+constexpr int kPairMaxPlane = 2048;
+constexpr int64_t kPairMailboxElems = (512 + 8 * (kPairMaxPlane + kResThreads)) / 4;
+bool resident_split_fits(const BrickDev& b, size_t lds_limit);
+int64_t resident_split_elems(const BrickDev& b);
+hipError_t launch_split(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_plane, float* xt, int corr,
+                        hipStream_t s);
 
 size_t plane_lds_bytes(int nrhs, bool fp64, int cols);
 

@@ -637,7 +637,8 @@ static int solve_boxes(rw_ctx* ctx, hipStream_t s, const rw_params& P, const Lev
             st->voxel_iters[level] += v * (int64_t)(q.iters + q.refine_iters);
             st->box_voxels[level] += v;
             st->max_iters[level] = std::max(st->max_iters[level], q.iters);
-            if (q.status == RW_ST_MAX_ITER || q.status == RW_ST_STALLED || q.status == RW_ST_NONFINITE)
+            if (q.status == RW_ST_MAX_ITER || q.status == RW_ST_STALLED || q.status == RW_ST_NONFINITE ||
+                q.status == RW_ST_SYNC_LOST)
                 st->not_converged[level] += 1;
         }
         st->solved[level] += nb;

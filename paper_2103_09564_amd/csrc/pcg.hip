@@ -1561,7 +1561,7 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
     // the other resident launches run on a second stream, concurrently
     bool any_g = false, any_lds = false;
     if (kRes && n > pp.n_res)
-        for (int i = 0; i < pp.n_rl; ++i) (pp.rl[i].kind == 2 ? any_g : any_lds) = true;
+        for (int i = 0; i < pp.n_rl; ++i) (pp.rl[i].kind == 2 || pp.rl[i].kind == 4 ? any_g : any_lds) = true;
     const bool any_str = n_stream_end > pp.n_dom;
     const bool on_a = any_str || any_g;
     const bool fork = on_a && any_lds && pp.side[0] != nullptr;
@@ -1597,6 +1597,10 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
                            (int)n_big);
     }
     if constexpr (kRes) {
+        // split boxes first: the largest, two workgroups each
+        for (int i = 0; i < pp.n_rl; ++i)
+            if (pp.rl[i].kind == 4)
+                RW_TRY(launch_split(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_plane, xt, corr, s_str));
         int k = 0;
         for (int i = 0; i < pp.n_rl; ++i)
             if (pp.rl[i].kind == 2) {
@@ -1626,19 +1630,19 @@ static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big,
     if (early) {
         check_range(pp.n_dom, n_stream_end, s_str);
         for (int i = 0; i < pp.n_rl; ++i)
-            if (pp.rl[i].kind == 2) check_range(pp.rl[i].b0, pp.rl[i].b1, s_str);
+            if (pp.rl[i].kind == 2 || pp.rl[i].kind == 4) check_range(pp.rl[i].b0, pp.rl[i].b1, s_str);
     }
     if constexpr (kRes) {
         if (tev && any_lds) RW_TRY(hipEventRecord(tev[2], s_res));
         for (int i = 0; i < pp.n_rl; ++i)
-            if (pp.rl[i].kind != 2)
+            if (pp.rl[i].kind != 2 && pp.rl[i].kind != 4)
                 RW_TRY(launch_resident(a, pp.rl[i].b0, pp.rl[i].b1, pp.rl[i].max_voxels, pp.rl[i].max_plane,
                                        pp.rl[i].kind, pp.rl[i].px, xt, corr, pp.persist ? a.tickets + i : nullptr,
                                        s_res));
         if (tev && any_lds) RW_TRY(hipEventRecord(tev[3], s_res));
         if (early)
             for (int i = 0; i < pp.n_rl; ++i)
-                if (pp.rl[i].kind != 2) check_range(pp.rl[i].b0, pp.rl[i].b1, s_res);
+                if (pp.rl[i].kind != 2 && pp.rl[i].kind != 4) check_range(pp.rl[i].b0, pp.rl[i].b1, s_res);
     }
     if (fork) {
         RW_TRY(hipEventRecord(pp.join[0], s_str));

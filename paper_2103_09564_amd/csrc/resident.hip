@@ -1009,6 +1009,529 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
     resg_box<NT, VPT, G, PX>(a, xt, corr, base + (int)blockIdx.x);
 }
 
+// ---------------------------------------------------------------------------
+// Split boxes: two workgroups per box (k_pcg_res2).
+//
+// A 40^3 box (a brick of 32^3 expanded by 1.25, Section IV-B) needs 250 KB
+// for p alone, more than one CU's LDS.  Cut along z, each half (up to 32768
+// voxels) fits the streamed-weights layout above: p of the half in LDS, x, r
+// and q in registers, the half's edge weights and 1/d in a segment of its
+// own.  The upper half's voxels take slots 0.., the lower half's end at the
+// last slot, so that the other half's plane at the cut falls in the LDS pad
+// below (upper) or above (lower) the slots, and every stencil access is as
+// in k_pcg_resg.  Per CG iteration the halves exchange two messages through
+// a per-box mailbox in global memory: their parts of p.q (giving alpha), then
+// their parts of r.z and ||r||^2 with z on their plane at the cut (giving
+// beta; each half then forms the other's new p at the cut itself, with the
+// same fused multiply-add, so the halo needs no message of its own).  Both
+// halves add the two parts in the same order and so take the same decisions
+// (convergence, breakdown, iteration cap) and leave together.
+//
+// Mailbox words are written and read with device-scope atomic accesses; a
+// message's stores are complete (s_waitcnt) before its flag is written, and
+// its words are read after the flag is seen, so no cache is flushed.  A
+// message n >= 1 sits in buffer n & 1: the start message (odd) and each
+// iteration's p.q (even) and r.z message (odd) with the plane; a buffer is
+// written again only after the other half has answered the message in
+// between, by which time it has read the first.
+
+struct PairBox {
+    char* base;
+    __device__ uint32_t* flag(int h) const { return (uint32_t*)(base + 128 * h); }
+    __device__ uint64_t* part(int h, int b) const { return (uint64_t*)(base + 256 + 64 * (2 * h + b)); }
+    // z at the cut, then one spare word per thread
+    __device__ uint32_t* plane(int h) const { return (uint32_t*)(base + 512 + 4 * (kPairMaxPlane + kResThreads) * h); }
+};
+static_assert(512 + 8 * (kPairMaxPlane + kResThreads) <= kPairMailboxElems * 4, "mailbox size");
+
+__device__ __forceinline__ void dev_st(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t dev_ld(uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void dev_st64(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t dev_ld64(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Polls of the other half's flag before a half gives up (a few seconds).
+constexpr uint32_t kPairSpin = 1u << 22;
+
+// Message n of half h: the NV sums v (equal on every thread) go out and the
+// other half's come back in o (equal on every thread); the plane stores of
+// this message were issued before the call.  false (on every thread): the
+// other half did not answer within kPairSpin polls.
+template <int NV>
+__device__ __forceinline__ bool pair_exchange(const PairBox& mb, int h, uint32_t n, const double (&v)[NV],
+                                              double (&o)[NV], double* s_part, int* s_ok) {
+    const int b = (int)(n & 1u);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NV; ++k) dev_st64(mb.part(h, b) + k, (uint64_t)__double_as_longlong(v[k]));
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's mailbox stores have completed
+    __syncthreads();                // and every thread's
+    if (threadIdx.x == 0) {
+        dev_st(mb.flag(h), n);
+        int ok = 1;
+        for (uint32_t spins = 0; dev_ld(mb.flag(h ^ 1)) < n;) {
+            if (++spins > kPairSpin) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (ok)
+            for (int k = 0; k < NV; ++k) s_part[k] = __longlong_as_double((long long)dev_ld64(mb.part(h ^ 1, b) + k));
+        *s_ok = ok;
+    }
+    __syncthreads();
+    const bool ok = __builtin_amdgcn_readfirstlane(*s_ok) != 0;  // the same on every lane
+    if (ok)
+        for (int k = 0; k < NV; ++k) o[k] = s_part[k];
+    __syncthreads();  // s_part and s_ok are rewritten by the next message
+    return ok;
+}
+
+// Floats of one half's segment (four arrays of nxy + span) and of a split
+// box's weight area (two halves and the mailbox).
+__host__ __device__ inline int64_t split_half_elems(int64_t nxy) {
+    return (4 * (nxy + kResSpanG1) + 63) & ~int64_t(63);
+}
+
+template <int NT, int VPT, int G>
+__device__ __forceinline__ void res2_half(const SolveArgs& a, float* xt, int corr, int ib, int h) {
+    extern __shared__ __align__(16) float p_lds[];
+    __shared__ double red[(NT / 64) * 5];
+    __shared__ double s_part[8];
+    __shared__ int s_ok;
+    constexpr int NG = (VPT + G - 1) / G;
+    constexpr int span = NT * VPT;
+    constexpr int U = 8;  // slots per thread at a time in the weights pass
+    constexpr int kPlaneSlots = (kPairMaxPlane + NT - 1) / NT;  // a thread's slots on a plane at the cut
+    static_assert(span == kResSpanG1, "split halves use the 32768-slot layout");
+    BoxState& st = a.state[ib];
+    const bool fused = a.fused_init && !corr;
+    if (!fused && !st.active) return;  // both halves read the same flag
+    const BrickDev bd = a.bricks[ib];
+    const int nx = bd.nx, ny = bd.ny, nz = bd.nz, nxy = nx * ny;
+    const int z0 = (nz + 1) >> 1;           // planes of the lower half
+    const int zh = h ? nz - z0 : z0;        // planes of this half
+    const int nv = nxy * zh;                // its voxels
+    const int S = h ? 0 : span - nv;        // slot of its first voxel
+    const int goff = h ? z0 * nxy : 0;      // box voxel of its first voxel
+    const int hb = h ? -nxy : span;         // slots of the other half's plane at the cut (the halo)
+    const int bs = h ? 0 : span - nxy;      // slots of this half's plane at the cut
+    const int T = nxy + span;
+    float* P = p_lds + nxy;
+    // the half's voxel v (slot v + S) is box voxel goff + v
+    const float* g = a.g + bd.off + goff;
+    const uint8_t* m = a.mask + bd.off + goff;
+    float* const xb = xt + bd.off + goff;
+    float* const rw = (float*)a.r + bd.off + goff;
+    const int64_t he = split_half_elems(nxy);
+    float* const seg = a.wts + bd.woff + h * he;
+    float* const WX = seg + nxy;
+    float* const WY = WX + T;
+    float* const WZ = WY + T;
+    float* const ID = WZ + T;
+    const PairBox mb{(char*)(a.wts + bd.woff + 2 * he)};
+    const ResWeight W{(float)(-a.beta * 1.4426950408889634), (float)a.eps};
+    // local voxels with x in P for the start state: the half and the halo
+    const int vlo = h ? -nxy : 0, vhi = h ? nv : nv + nxy;
+
+    // P over [-nxy, span + nxy): x of the half's voxels and of the halo for
+    // a main solve's start state, 0 elsewhere
+    for (int s = -nxy + (int)threadIdx.x; s < span + nxy; s += NT) {
+        const int v = s - S;
+        float xv = 0.0f;
+        if (fused && v >= vlo && v < vhi) xv = xb[v];
+        P[s] = xv;
+    }
+    if (fused) __syncthreads();
+    double sum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // r.z, r.r, b.b, unknown, seeded
+    // Weights pass over the slots [-nxy, span) (thread t: -nxy + t + k * NT),
+    // U at a time with all their loads issued first: the forward weights
+    // w+x, w+y, w+z (0 toward neighbours outside the box and on slots
+    // outside the half) and 1/d (0 on seeded voxels and outside the half);
+    // in the upper half's pad plane, the weight of the edge across the cut.
+    // A main solve also forms the start state (r0 = sum_nb w x_nb - d x, the
+    // sums) as res_weights_pass does; neighbours across the cut are in box.
+    for (int s0 = -nxy + (int)threadIdx.x; s0 < span; s0 += U * NT) {
+        int c[U];
+        bool in[U][6];
+        float gc[U], gn[U][6];
+        uint8_t mc[U], mn[U][6];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int s = s0 + u * NT;
+            const int v = s - S;
+            // a voxel of the half, the upper half's pad plane, or (unused
+            // slots) voxel 0
+            c[u] = v >= 0 && v < nv ? v : (h && s < 0 ? v : 0);
+            const int kz = c[u] >= 0 ? c[u] / nxy : -1, rem = c[u] - kz * nxy, j = rem / nx, i = rem - j * nx;
+            const int no[6] = {1, -1, nx, -nx, nxy, -nxy};
+            in[u][0] = i + 1 < nx;
+            in[u][1] = i > 0;
+            in[u][2] = j + 1 < ny;
+            in[u][3] = j > 0;
+            in[u][4] = kz + 1 < zh || !h;  // (the lower half's top plane faces the upper half)
+            in[u][5] = kz > 0 || (h && kz == 0);  // (the upper half's first plane faces the lower half)
+            gc[u] = g[c[u]];
+            mc[u] = m[c[u]];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                const int nb = in[u][e] ? c[u] + no[e] : c[u];
+                gn[u][e] = g[nb];
+                mn[u][e] = m[nb];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int s = s0 + u * NT;
+            const int v = s - S;
+            const bool inb = v >= 0 && v < nv;
+            float w[6];  // +x, -x, +y, -y, +z, -z
+#pragma unroll
+            for (int e = 0; e < 6; ++e) w[e] = 0.0f;
+            if (inb) {
+#pragma unroll
+                for (int e = 0; e < 6; e += 2)
+                    if (in[u][e]) w[e] = W(gc[u], gn[u][e]);
+#pragma unroll
+                for (int e = 1; e < 6; e += 2)
+                    if (in[u][e]) w[e] = W(gn[u][e], gc[u]);
+            } else if (h && s < 0) {
+                w[4] = W(gc[u], gn[u][4]);  // the edge across the cut
+            }
+            const float d = ((w[0] + w[2]) + w[4]) + w[1] + w[3] + w[5];
+            const bool unk = inb && mc[u] == 0;
+            if (s < span) {
+                WX[s] = w[0];
+                WY[s] = w[2];
+                WZ[s] = w[4];
+                ID[s] = unk ? __builtin_amdgcn_rcpf(d) : 0.0f;
+            }
+            if (fused && inb) {
+                const int no[6] = {1, -1, nx, -nx, nxy, -nxy};
+                float acc = 0.0f, bs2 = 0.0f;  // sum_nb w x_nb, and over the seeded neighbours only
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    const float xr = P[s + no[e]];
+                    const float xn = in[u][e] ? xr : 0.0f;
+                    acc += w[e] * xn;
+                    if (mn[u][e] != 0) bs2 += w[e] * xn;
+                }
+                const float r0 = unk ? acc - d * P[s] : 0.0f;
+                rw[v] = r0;
+                if (unk) {
+                    sum[0] += (double)r0 * (double)(r0 * __builtin_amdgcn_rcpf(d));
+                    sum[1] += (double)r0 * (double)r0;
+                    sum[2] += (double)bs2 * (double)bs2;
+                }
+                sum[3] += unk ? 1.0 : 0.0;
+                sum[4] += unk ? 0.0 : 1.0;
+            }
+        }
+    }
+    res_block_sum<NT, 5>(sum, red);  // its barriers also publish rw and the segment to the workgroup
+
+    // a correction solve starts from the box's state (read before the start
+    // message: the lower half rewrites it when it ends)
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+    if (!fused) {
+        rz = st.rz[0];
+        rr = st.rr[0];
+        bb = st.bb[0];
+    }
+    // x, r and the start z on this half's slots; z on its plane at the cut
+    // goes to the other half with the start sums
+    float x[VPT], r[VPT], q[VPT];
+    uint32_t* const pl_out = mb.plane(h);
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int s = threadIdx.x + k * NT;
+        const int v0 = s - S;
+        const int v = v0 < 0 ? 0 : v0 < nv ? v0 : nv - 1;
+        const uint8_t mv = m[v];
+        const float rv = rw[v], xv = xb[v];
+        const bool u = v0 >= 0 && v0 < nv && mv == 0;
+        r[k] = u ? rv : 0.0f;
+        x[k] = u ? xv : 0.0f;
+    }
+    // 0x00020000: raw 32-bit buffer (third descriptor word for this chip family)
+    const SegBuf sb{__builtin_amdgcn_make_buffer_rsrc(seg, 0, (int)(4 * (4 * T)), 0x00020000)};
+    const int sWX = __builtin_amdgcn_readfirstlane(4 * nxy), sWY = __builtin_amdgcn_readfirstlane(sWX + 4 * T),
+              sWZ = __builtin_amdgcn_readfirstlane(sWY + 4 * T), sID = __builtin_amdgcn_readfirstlane(sWZ + 4 * T);
+    const int sWXm = sWX - 4, sWYm = __builtin_amdgcn_readfirstlane(sWY - 4 * nx),
+              sWZm = __builtin_amdgcn_readfirstlane(sWZ - 4 * nxy);
+    // start z (the 1/d of unused and seeded slots is 0)
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) q[k] = r[k] * sb.ld(4u * (unsigned)(threadIdx.x + k * NT), sID);
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        if (k < kPlaneSlots || k >= VPT - kPlaneSlots) {
+            const unsigned o = (unsigned)((int)threadIdx.x + k * NT - bs);
+            dev_st(pl_out + (o < (unsigned)nxy ? o : (unsigned)(kPairMaxPlane + threadIdx.x)), __float_as_uint(q[k]));
+        }
+    }
+    double tot[5];
+    {
+        double o[5];
+        if (!pair_exchange<5>(mb, h, 1u, sum, o, s_part, &s_ok)) {
+            if (threadIdx.x == 0 && h == 0) {
+                st.status = RW_ST_SYNC_LOST;
+                st.active = 0;
+                st.pending = 0;
+            }
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) tot[k] = h == 0 ? sum[k] + o[k] : o[k] + sum[k];
+    }
+    if (fused) {
+        // reset P (the halo held the other half's x) and settle the box's
+        // state as res_start_finish does, on the two halves' sums
+        for (int s = -nxy + (int)threadIdx.x; s < span + nxy; s += NT) P[s] = 0.0f;
+        const double nU = tot[3], nM = tot[4];
+        const bool allzero = tot[2] == 0.0;
+        const bool act = nM > 0.0 && nU > 0.0 && !allzero;
+        const bool zero_sol = nM > 0.0 && nU > 0.0 && allzero;
+        rz = zero_sol ? 0.0 : tot[0];
+        rr = zero_sol ? 0.0 : tot[1];
+        bb = tot[2];
+        if (zero_sol)
+            for (int v = threadIdx.x; v < nv; v += NT)
+                if (m[v] == 0) xb[v] = rw[v] = 0.0f;
+        if (threadIdx.x == 0 && h == 0) {
+            for (int cc = 0; cc < 3; ++cc) st.rz[cc] = st.rr[cc] = st.bb[cc] = 0.0;
+            st.rz[0] = rz;
+            st.rr[0] = rr;
+            st.bb[0] = bb;
+            st.nU = nU;
+            st.nM = nM;
+            st.rel = 0.0;
+            st.true_rel = 0.0;
+            st.iters = st.refine_steps = st.refine_iters = 0;
+            st.status = nM == 0.0 ? RW_ST_NO_DIRICHLET : RW_ST_CONVERGED;
+            st.active = act ? 1 : 0;
+            st.pending = 0;
+            st.checked = 0;
+        }
+        __syncthreads();
+        if (!__builtin_amdgcn_readfirstlane(act ? 1 : 0)) return;
+    }
+
+    uint32_t* const pl_in = mb.plane(h ^ 1);
+
+    const double tol = corr ? a.inner_tol : a.tol;
+    const double tol2 = tol * tol;
+    double betac = 0.0;
+    float wr[2][G][3];
+    float ir[2][G];
+    int it = 0, flags = 0;
+    uint32_t msg = 1;
+    for (;;) {
+        if (rr <= tol2 * bb) break;
+        if (it >= a.max_iter) {
+            flags = 2;
+            break;
+        }
+        int tb = threadIdx.x, oy = nx, oz = nxy;
+        asm volatile("" : "+v"(tb));
+        asm volatile("" : "+v"(oy));
+        asm volatile("" : "+v"(oz));
+        const unsigned o0 = 4u * (unsigned)tb;
+        auto group_base = [&](int gi, unsigned ob) {
+            unsigned og = ob + 4u * (unsigned)(gi * G * NT);
+            asm volatile("" : "+v"(og));
+            return og;
+        };
+        auto load_w = [&](int gi, float (&w)[G][3]) {
+            const unsigned og = group_base(gi, o0);
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if (gi * G + j < VPT) {
+                    const unsigned o = og + 4u * (unsigned)(j * NT);
+                    w[j][0] = sb.ld(o, sWX);
+                    w[j][1] = sb.ld(o, sWY);
+                    w[j][2] = sb.ld(o, sWZ);
+                }
+            }
+        };
+        auto load_b = [&](int gi, float (&w)[G][3]) {
+            const unsigned og = group_base(gi, o0);
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if (gi * G + j < VPT) {
+                    const unsigned o = og + 4u * (unsigned)(j * NT);
+                    w[j][0] = sb.ld(o, sWXm);
+                    w[j][1] = sb.ld(o, sWYm);
+                    w[j][2] = sb.ld(o, sWZm);
+                }
+            }
+        };
+        auto load_i = [&](int gi, float (&w)[G], unsigned ob) {
+            const unsigned og = group_base(gi, ob);
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (gi * G + j < VPT) w[j] = sb.ld(og + 4u * (unsigned)(j * NT), sID);
+        };
+        load_w(0, wr[0]);
+        const float be = it == 0 ? 0.0f : (float)betac;
+        float* const Pt = P + tb;
+        // p = z + beta p on this half's slots and, from the other half's z,
+        // on its plane at the cut (the halo), with the multiply-add that half
+        // uses there
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            Pt[k * NT] = __builtin_fmaf(be, Pt[k * NT], q[k]);
+            if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int i = tb; i < nxy; i += NT)
+            P[hb + i] = __builtin_fmaf(be, P[hb + i], __uint_as_float(dev_ld(pl_in + i)));
+        res_lds_barrier();
+        const float* const Pxm = Pt - 1;
+        const float* const Pym = Pt - oy;
+        const float* const Pyp = Pt + oy;
+        const float* const Pzm = Pt - oz;
+        const float* const Pzp = Pt + oz;
+        double sig = 0.0;
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            float wb[G][3];
+            load_b(gi, wb);
+            __builtin_amdgcn_sched_barrier(0);
+            if (gi + 1 < NG) load_w(gi + 1, wr[(gi + 1) & 1]);
+            else load_i(0, ir[0], o0);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int k = gi * G + j;
+                if (k < VPT) {
+                    const float wxp = wr[gi & 1][j][0], wyp = wr[gi & 1][j][1], wzp = wr[gi & 1][j][2];
+                    const float wxm = wb[j][0], wym = wb[j][1], wzm = wb[j][2];
+                    const float d = ((wxp + wxm) + (wyp + wym)) + (wzp + wzm);
+                    const float pv = Pt[k * NT];
+                    const float acc = wxp * Pxm[k * NT + 2] + wxm * Pxm[k * NT] + wyp * Pyp[k * NT] +
+                                      wym * Pym[k * NT] + wzp * Pzp[k * NT] + wzm * Pzm[k * NT];
+                    q[k] = d * pv - acc;  // masked in the update below
+                    sig += (double)pv * (double)q[k];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        double s1[1] = {sig};
+        res_block_sum_lds<NT, 1>(s1, red);
+        {
+            double o1[1];
+            if (!pair_exchange<1>(mb, h, ++msg, s1, o1, s_part, &s_ok)) {
+                flags = 4;
+                break;
+            }
+            sig = h == 0 ? s1[0] + o1[0] : o1[0] + s1[0];
+        }
+        const double alpha = rz / sig;
+        if (!res_finite(alpha) || !(sig > 0.0)) {
+            flags = 1;
+            break;
+        }
+        const float al = (float)alpha;
+        double acc2[2] = {0.0, 0.0};
+        int t3 = threadIdx.x;
+        asm volatile("" : "+v"(t3));
+        const unsigned o3 = 4u * (unsigned)t3;
+        const float* const P3 = P + t3;
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            if (gi + 1 < NG) load_i(gi + 1, ir[(gi + 1) & 1], o3);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int k = gi * G + j;
+                if (k < VPT) {
+                    const float id = ir[gi & 1][j];
+                    const float pv = P3[k * NT];
+                    x[k] += al * pv;
+                    asm volatile("" : "+v"(x[k]));
+                    const float rn = r[k] - al * q[k];
+                    r[k] = id != 0.0f ? rn : 0.0f;
+                    const float z = r[k] * id;
+                    q[k] = z;
+                    acc2[0] += (double)r[k] * (double)z;
+                    acc2[1] += (double)r[k] * (double)r[k];
+                    // z on this half's plane at the cut, for the other
+                    // half's p there (only the first and last slots of a
+                    // thread can be on it)
+                    if (k < kPlaneSlots || k >= VPT - kPlaneSlots) {
+                        // (slots off the plane write the thread's spare word: no branch)
+                        const unsigned o = (unsigned)(t3 + k * NT - bs);
+                        dev_st(pl_out + (o < (unsigned)nxy ? o : (unsigned)(kPairMaxPlane + t3)), __float_as_uint(z));
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        res_block_sum_lds<NT, 2>(acc2, red);
+        ++it;
+        {
+            double o2[2];
+            if (!pair_exchange<2>(mb, h, ++msg, acc2, o2, s_part, &s_ok)) {
+                flags = 4;
+                break;
+            }
+            for (int k = 0; k < 2; ++k) acc2[k] = h == 0 ? acc2[k] + o2[k] : o2[k] + acc2[k];
+        }
+        if (!res_finite(acc2[0]) || !res_finite(acc2[1])) {
+            flags = 1;
+            break;
+        }
+        betac = acc2[0] / rz;
+        rz = acc2[0];
+        rr = acc2[1];
+    }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v = (int)threadIdx.x + k * NT - S;
+        if (v >= 0 && v < nv && m[v] == 0) xb[v] = x[k];
+    }
+    if (threadIdx.x == 0 && h == 0) {
+        st.rz[0] = rz;
+        st.rr[0] = rr;
+        if (corr) {
+            st.refine_iters += it;
+        } else {
+            st.iters = it;
+            st.rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            if (flags & 2) st.status = RW_ST_MAX_ITER;
+        }
+        if (flags & 1) st.status = RW_ST_NONFINITE;
+        if (flags & 4) st.status = RW_ST_SYNC_LOST;
+        st.pending = corr && !(flags & 5) ? 1 : 0;
+    }
+}
+
+// Workgroups b and b + 8 of each group of 16 are the lower and upper half of
+// one box (consecutive workgroups go to different XCDs, these two to the
+// same one).
+template <int NT, int VPT, int G>
+__global__ __launch_bounds__(NT) void k_pcg_res2(SolveArgs a, float* xt, int corr, int base, int n) {
+    const int b = (int)blockIdx.x;
+    const int i = (b >> 4) * 8 + (b & 7);
+    if (i >= n) return;
+    res2_half<NT, VPT, G>(a, xt, corr, base + i, (b >> 3) & 1);
+}
+
+// Clears the mailbox flags of boxes [base, base + gridDim.x) (a kernel, so
+// that the sequence is valid inside a captured graph).
+__global__ void k_pair_clear(SolveArgs a, int base) {
+    const BrickDev bd = a.bricks[base + (int)blockIdx.x];
+    const int64_t he = split_half_elems((int64_t)bd.nx * bd.ny);
+    const PairBox mb{(char*)(a.wts + bd.woff + 2 * he)};
+    if (threadIdx.x < 2) dev_st(mb.flag((int)threadIdx.x), 0u);
+}
+
 
 // Elements of each LDS array of the weights kernel for the largest box of a
 // launch: the box, nx*ny pad elements before it and nx*ny + 1 after it (the
@@ -1128,6 +1651,33 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
         if (vpt <= kResMaxVptR) return go(k_pcg_resr<kResThreads, kResMaxVptR>, k_pcg_resr_q<kResThreads, kResMaxVptR>, nt);
     }
     return hipErrorInvalidValue;
+}
+
+bool resident_split_fits(const BrickDev& b, size_t lds_limit) {
+    const int64_t nxy = (int64_t)b.nx * b.ny, nv = nxy * b.nz;
+    const int64_t z0 = (b.nz + 1) / 2;
+    return nv > kResSpanG1 && b.nz >= 2 && nxy >= kResThreads && nxy <= kPairMaxPlane && nxy * z0 <= kResSpanG1 &&
+           (size_t)(kResSpanG1 + 2 * nxy) * sizeof(float) + 1024 <= lds_limit;
+}
+
+int64_t resident_split_elems(const BrickDev& b) {
+    return 2 * split_half_elems((int64_t)b.nx * b.ny) + ((kPairMailboxElems + 63) & ~int64_t(63));
+}
+
+hipError_t launch_split(const SolveArgs& a, int64_t b0, int64_t b1, int64_t max_plane, float* xt, int corr,
+                        hipStream_t s) {
+    if (b1 <= b0) return hipSuccess;
+    if (!a.wts || max_plane > kPairMaxPlane) return hipErrorInvalidValue;
+    const int64_t n = b1 - b0;
+    hipLaunchKernelGGL(k_pair_clear, dim3((unsigned)n), dim3(64), 0, s, a, (int)b0);
+    constexpr int nt = kResThreads;
+    auto k = k_pcg_res2<nt, kResSpanG1 / nt, 4>;
+    const size_t lds = (size_t)(kResSpanG1 + 2 * max_plane) * sizeof(float);
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    // 16 workgroups for each group of 8 boxes (a box's halves are b and b + 8)
+    hipLaunchKernelGGL(k, dim3((unsigned)(16 * ((n + 7) / 8))), dim3(nt), lds, s, a, xt, corr, (int)b0, (int)n);
+    return hipGetLastError();
 }
 
 }  // namespace rwk
