@@ -296,6 +296,17 @@ def bench_tubes(torch, rwg, ctx, n=512, n_tubes=40, levels=4):
         sched[str(sc)] = {"segment_ms": ms, "voxel_iters": int(sum(r.stats()["voxel_iters"])),
                           "max_abs_diff_vs_schedule_0": max(float((r.level_map(l) - res.level_map(l)).abs().max().item())
                                                             for l in range(levels))}
+    # schedule 0 with the 40^3 boxes on the streaming window march instead of
+    # split over two workgroups
+    ctx.set_split_boxes(False)
+    try:
+        ms, r = _best_ms(torch, lambda: rwg.segment(pyr, seeds, **kw), 2)
+    finally:
+        ctx.set_split_boxes(True)
+    sched["0_boxes_streaming"] = {
+        "segment_ms": ms, "voxel_iters": int(sum(r.stats()["voxel_iters"])),
+        "max_abs_diff_vs_schedule_0": max(float((r.level_map(l) - res.level_map(l)).abs().max().item())
+                                          for l in range(levels))}
     return {"workload": f"tubes {n}^3 uint16, {n_tubes} tubes, 20 fg + 200 bg seeds, {levels} levels, s=32, e=1.25, "
                         "beta 128, dt pruning t_bin 0.49, mixed tol 1e-5",
             "pyramid_ms": pyr_ms, "segment_ms": seg_ms,

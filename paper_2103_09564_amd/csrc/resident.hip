@@ -1062,36 +1062,34 @@ constexpr uint32_t kPairSpin = 1u << 22;
 
 // Message n of half h: the NV sums v (equal on every thread) go out and the
 // other half's come back in o (equal on every thread); the plane stores of
-// this message were issued before the call.  false (on every thread): the
-// other half did not answer within kPairSpin polls.
+// this message were issued before the call.  Every wave polls the other
+// half's flag itself (a uniform loop); false on every thread when some wave
+// saw no answer within kPairSpin polls.
 template <int NV>
 __device__ __forceinline__ bool pair_exchange(const PairBox& mb, int h, uint32_t n, const double (&v)[NV],
-                                              double (&o)[NV], double* s_part, int* s_ok) {
+                                              double (&o)[NV]) {
     const int b = (int)(n & 1u);
     if (threadIdx.x == 0)
         for (int k = 0; k < NV; ++k) dev_st64(mb.part(h, b) + k, (uint64_t)__double_as_longlong(v[k]));
     __builtin_amdgcn_s_waitcnt(0);  // this thread's mailbox stores have completed
     __syncthreads();                // and every thread's
-    if (threadIdx.x == 0) {
-        dev_st(mb.flag(h), n);
-        int ok = 1;
-        for (uint32_t spins = 0; dev_ld(mb.flag(h ^ 1)) < n;) {
-            if (++spins > kPairSpin) {
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
+    if (threadIdx.x == 0) dev_st(mb.flag(h), n);
+    int late = 0;
+    for (uint32_t spins = 0; __builtin_amdgcn_readfirstlane(dev_ld(mb.flag(h ^ 1))) < n;) {
+        if (++spins > kPairSpin) {
+            late = 1;
+            break;
         }
-        if (ok)
-            for (int k = 0; k < NV; ++k) s_part[k] = __longlong_as_double((long long)dev_ld64(mb.part(h ^ 1, b) + k));
-        *s_ok = ok;
+        __builtin_amdgcn_s_sleep(1);
     }
-    __syncthreads();
-    const bool ok = __builtin_amdgcn_readfirstlane(*s_ok) != 0;  // the same on every lane
-    if (ok)
-        for (int k = 0; k < NV; ++k) o[k] = s_part[k];
-    __syncthreads();  // s_part and s_ok are rewritten by the next message
-    return ok;
+    // (no early return: a branch out of the caller's iteration here costs
+    // that loop registers; the caller stops at its next convergence test)
+    const bool lost = __syncthreads_or(late) != 0;
+    for (int k = 0; k < NV; ++k) {
+        const double w = __longlong_as_double((long long)dev_ld64(mb.part(h ^ 1, b) + k));
+        o[k] = lost ? 0.0 : w;
+    }
+    return !lost;
 }
 
 // Floats of one half's segment (four arrays of nxy + span) and of a split
@@ -1104,8 +1102,6 @@ template <int NT, int VPT, int G>
 __device__ __forceinline__ void res2_half(const SolveArgs& a, float* xt, int corr, int ib, int h) {
     extern __shared__ __align__(16) float p_lds[];
     __shared__ double red[(NT / 64) * 5];
-    __shared__ double s_part[8];
-    __shared__ int s_ok;
     constexpr int NG = (VPT + G - 1) / G;
     constexpr int span = NT * VPT;
     constexpr int U = 8;  // slots per thread at a time in the weights pass
@@ -1279,7 +1275,7 @@ __device__ __forceinline__ void res2_half(const SolveArgs& a, float* xt, int cor
     double tot[5];
     {
         double o[5];
-        if (!pair_exchange<5>(mb, h, 1u, sum, o, s_part, &s_ok)) {
+        if (!pair_exchange<5>(mb, h, 1u, sum, o)) {
             if (threadIdx.x == 0 && h == 0) {
                 st.status = RW_ST_SYNC_LOST;
                 st.active = 0;
@@ -1333,6 +1329,7 @@ __device__ __forceinline__ void res2_half(const SolveArgs& a, float* xt, int cor
     int it = 0, flags = 0;
     uint32_t msg = 1;
     for (;;) {
+        if (flags & 4) break;  // the other half stopped answering
         if (rr <= tol2 * bb) break;
         if (it >= a.max_iter) {
             flags = 2;
@@ -1426,15 +1423,12 @@ __device__ __forceinline__ void res2_half(const SolveArgs& a, float* xt, int cor
         res_block_sum_lds<NT, 1>(s1, red);
         {
             double o1[1];
-            if (!pair_exchange<1>(mb, h, ++msg, s1, o1, s_part, &s_ok)) {
-                flags = 4;
-                break;
-            }
+            flags |= pair_exchange<1>(mb, h, ++msg, s1, o1) ? 0 : 4;
             sig = h == 0 ? s1[0] + o1[0] : o1[0] + s1[0];
         }
         const double alpha = rz / sig;
         if (!res_finite(alpha) || !(sig > 0.0)) {
-            flags = 1;
+            flags |= 1;
             break;
         }
         const float al = (float)alpha;
@@ -1477,23 +1471,24 @@ __device__ __forceinline__ void res2_half(const SolveArgs& a, float* xt, int cor
         ++it;
         {
             double o2[2];
-            if (!pair_exchange<2>(mb, h, ++msg, acc2, o2, s_part, &s_ok)) {
-                flags = 4;
-                break;
-            }
+            flags |= pair_exchange<2>(mb, h, ++msg, acc2, o2) ? 0 : 4;
             for (int k = 0; k < 2; ++k) acc2[k] = h == 0 ? acc2[k] + o2[k] : o2[k] + acc2[k];
         }
         if (!res_finite(acc2[0]) || !res_finite(acc2[1])) {
-            flags = 1;
+            flags |= 1;
             break;
         }
         betac = acc2[0] / rz;
         rz = acc2[0];
         rr = acc2[1];
     }
+    // (an opaque index: addresses and mask bytes of the start are not kept
+    // across the iteration for these stores)
+    int te = (int)threadIdx.x - S;
+    asm volatile("" : "+v"(te));
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
-        const int v = (int)threadIdx.x + k * NT - S;
+        const int v = te + k * NT;
         if (v >= 0 && v < nv && m[v] == 0) xb[v] = x[k];
     }
     if (threadIdx.x == 0 && h == 0) {
