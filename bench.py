@@ -898,8 +898,8 @@ def main():
                   "lds_resident": {"boxes": mixed["n_res"], "voxel_iters": mixed["vox_it_res"],
                                    "ms": t["resident_ms"] * 1e3,
                                    "voxel_iters_per_s": mixed["vox_it_res"] / t["resident_ms"] if t["resident_ms"] else None,
-                                   "note": "on-chip: p and the edge weights in LDS, x and r in registers; HBM is "
-                                           "read once per solve, so no HBM roofline applies"},
+                                   "note": "on-chip: p in LDS, the edge weights in registers (or LDS), x and r in "
+                                           "registers; HBM is read once per solve, so no HBM roofline applies"},
                   "schedule": {"requested": "tuned" if args.schedule < 0 else args.schedule,
                                "ran": mixed["schedule"][0], "third_stream": mixed["schedule"][1],
                                "weights_in_registers": mixed["schedule"][2], "persistent": mixed["schedule"][3],
