@@ -404,9 +404,14 @@ def bench_shells(torch, rwg, ctx, dims=(256, 256, 128), levels=3):
                                                        for l in range(levels)),
                        "label_agreement_vs_full_run": float((lb == lab_full).mean()),
                        "label_accuracy_vs_truth": float((lb == labels).mean())}
+    # the three classes solved together in each box (weights shared, streaming kernels)
+    joint_ms, rj = _best_ms(torch, lambda: rwg.segment(pyr, seeds, joint_classes=1, **kw), 2)
+    joint = {"full_ms": joint_ms, "voxel_iters": int(sum(rj.stats()["voxel_iters"])),
+             "max_abs_diff_vs_per_class": max(float((rj.level_map(l) - res.level_map(l)).abs().max().item())
+                                              for l in range(levels))}
     return {"workload": f"nested shells {dims[0]}x{dims[1]}x{dims[2]} uint16, 4 classes (3 rhs), {levels} levels, "
                         "s=32, e=1.25, hom pruning t_hom 0.3, mixed tol 1e-5; then a 2000-voxel stroke (class 2)",
-            "pyramid_ms": pyr_ms, "full_ms": full_ms, "incremental_ms": inc_ms,
+            "pyramid_ms": pyr_ms, "full_ms": full_ms, "incremental_ms": inc_ms, "joint_classes": joint,
             "full_voxel_iters_per_s": float(sum(st["voxel_iters"]) / (full_ms / 1e3)),
             "full_solved": st["solved"], "incremental_solved": si["solved"], "bricks": st["bricks"],
             "label_accuracy_vs_truth": acc, "incremental_rules": rules, "generate_s": gen_s}
@@ -457,6 +462,15 @@ def bench_shells_full(torch, rwg, ctx, dims=(2048, 2048, 1024), levels=5, n_repl
                      "kept": [int(((r.flags(l) & rwg.F_KEPT) != 0).sum().item()) for l in range(levels)]}
         del r
         print(f"bench.py: shells_full incremental ({name}) done", file=sys.stderr, flush=True)
+    # the three classes solved together in each box (weights shared, streaming kernels)
+    jt_ms, rj = _best_ms(torch, lambda: rwg.segment(pyr, seeds, joint_classes=1, **kw), 1)
+
+    # (levels 1.. only: a copy of level 0 is 51.5 GB; the 256x256x128 twin compares every level)
+    joint = {"full_ms": jt_ms, "voxel_iters": int(sum(rj.stats()["voxel_iters"])),
+             "max_abs_diff_vs_per_class_levels_1_up": max(
+                 float((rj.level_map(l) - res.level_map(l)).abs().max().item()) for l in range(1, levels))}
+    del rj
+    print("bench.py: shells_full joint classes done", file=sys.stderr, flush=True)
     st = res.stats()
     lab = res.materialize(0, 0, prob=False, labels=True)[1]
     acc = float((lab == labels).float().mean().item())
@@ -469,7 +483,7 @@ def bench_shells_full(torch, rwg, ctx, dims=(2048, 2048, 1024), levels=5, n_repl
            "end_to_end_voxels_per_s": float(np.prod(dims) / (full_ms / 1e3)),
            "bricks": st["bricks"], "full_computed": st["computed"], "full_solved": st["solved"],
            "full_not_converged": st["not_converged"], "full_max_iters": st["max_iters"],
-           "label_accuracy_vs_truth": acc, "incremental": inc}
+           "label_accuracy_vs_truth": acc, "incremental": inc, "joint_classes": joint}
     if cpu_leg:
         # sampled solved level-0 boxes of the full run, replayed by the oracle
         import multiprocessing as mp

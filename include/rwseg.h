@@ -468,7 +468,12 @@ typedef struct rw_params {
     int32_t incremental;     /* runs with prev: bit 0 the node rule (else the dirty-brick rule),
                                 bit 1 warm start from prev (Section IV-E); 0 by default */
     int32_t schedule;        /* rw_solve_params.schedule of the level solves (0 by default) */
-    int32_t reserved;        /* must be 0 */
+    int32_t joint_classes;   /* K > 2 with MIXED or MIXED_REFINE: 0 (default) solves each of the
+                                K - 1 right-hand sides of a box below the coarsest level as a box
+                                of its own (one right-hand side, so the resident and split
+                                kernels take it; the results are the same solves); 1 solves
+                                them together (the weights shared, streaming kernels).  The
+                                coarsest level's domain always solves them together. */
 } rw_params;
 
 void rw_params_default(rw_params* p);
@@ -481,7 +486,8 @@ typedef struct rw_run_stats {
     int64_t computed[RW_MAX_LEVELS];    /* bricks reached (solved or reused) */
     int64_t solved[RW_MAX_LEVELS];      /* boxes solved in this run */
     int64_t prunable[RW_MAX_LEVELS];    /* reached bricks whose children were pruned */
-    int64_t voxel_iters[RW_MAX_LEVELS]; /* sum over solved boxes of box voxels x PCG iterations */
+    int64_t voxel_iters[RW_MAX_LEVELS]; /* sum over solved boxes of box voxels x PCG iterations (a box with
+                                           several right-hand sides: the most any of them took) */
     int64_t box_voxels[RW_MAX_LEVELS];  /* sum of solved box voxels */
     int32_t max_iters[RW_MAX_LEVELS];
     int32_t not_converged[RW_MAX_LEVELS];  /* solved boxes with status MAX_ITER / STALLED / NONFINITE */

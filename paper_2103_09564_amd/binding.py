@@ -414,7 +414,7 @@ class Params(ctypes.Structure):
                 ("t_inc", ctypes.c_double), ("brick", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("n_classes", ctypes.c_int32), ("prune_hom", ctypes.c_int32),
                 ("prune_dt", ctypes.c_int32), ("refine_max", ctypes.c_int32), ("incremental", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("joint_classes", ctypes.c_int32)]
 
 
 class Seed(ctypes.Structure):

@@ -231,11 +231,16 @@ __device__ __forceinline__ float sample_parent(const float* __restrict__ pm, int
 // start), or 0 on the coarsest level (pm == nullptr).  The parent map is read
 // directly, so cores already written into this level's map never leak into
 // another box's border.
+//
+// ps = 0: one packed box per box, x interleaved [voxel][class].  ps > 0 (the
+// per-class layout): the packed boxes repeat once per class at strides of ps
+// voxels, g and the mask copied into each, x of class c in copy c, so that
+// each class solves as a box of its own.
 template <int R>
 __global__ void k_setup(const BoxGeo* __restrict__ geo, const float* __restrict__ glev, int64_t Dx, int64_t Dy,
                         const float* __restrict__ pm, int64_t px, int64_t py, int64_t pz,
                         const float* __restrict__ warm, float* __restrict__ gb, uint8_t* __restrict__ mb,
-                        float* __restrict__ xb) {
+                        float* __restrict__ xb, int64_t ps) {
     const BoxGeo b = geo[blockIdx.x];
     const int64_t n = (int64_t)b.nx * b.ny * b.nz;
     for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
@@ -243,35 +248,52 @@ __global__ void k_setup(const BoxGeo* __restrict__ geo, const float* __restrict_
         const int64_t X = b.x0 + i, Y = b.y0 + j, Z = b.z0 + k;
         const int64_t L = X + Dx * (Y + Dy * Z);
         const int64_t v = b.off + t;
-        gb[v] = glev[L];
+        const float gv = glev[L];
         const bool border = ((b.faces & 1) && i == 0) || ((b.faces & 2) && i == b.nx - 1) ||
                             ((b.faces & 4) && j == 0) || ((b.faces & 8) && j == b.ny - 1) ||
                             ((b.faces & 16) && k == 0) || ((b.faces & 32) && k == b.nz - 1);
-        mb[v] = border ? 1 : 0;
         // the border takes the parent sample; with a warm map (a previous
         // result of this level) the unseeded voxels start from it instead
 #pragma unroll
-        for (int c = 0; c < R; ++c)
-            xb[v * R + c] = warm && !border ? warm[L * R + c]
-                                            : pm ? sample_parent<R>(pm, px, py, pz, X, Y, Z, c) : 0.0f;
+        for (int c = 0; c < R; ++c) {
+            const float xv = warm && !border ? warm[L * R + c]
+                                             : pm ? sample_parent<R>(pm, px, py, pz, X, Y, Z, c) : 0.0f;
+            if (ps) {
+                gb[c * ps + v] = gv;
+                mb[c * ps + v] = border ? 1 : 0;
+                xb[c * ps + v] = xv;
+            } else {
+                xb[v * R + c] = xv;
+            }
+        }
+        if (!ps) {
+            gb[v] = gv;
+            mb[v] = border ? 1 : 0;
+        }
     }
 }
 
 // User seeds override: x = [label == class] for classes 1..K-1.
+// (ps as in k_setup)
 template <int R>
-__global__ void k_seeds(const SeedEntry* __restrict__ e, int64_t n, uint8_t* __restrict__ mb, float* __restrict__ xb) {
+__global__ void k_seeds(const SeedEntry* __restrict__ e, int64_t n, uint8_t* __restrict__ mb, float* __restrict__ xb,
+                        int64_t ps) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const SeedEntry s = e[i];
-    mb[s.v] = 1;
 #pragma unroll
-    for (int c = 0; c < R; ++c) xb[s.v * R + c] = s.label == c + 1 ? 1.0f : 0.0f;
+    for (int c = 0; c < R; ++c) {
+        if (ps) mb[c * ps + s.v] = 1;
+        xb[ps ? c * ps + s.v : s.v * R + c] = s.label == c + 1 ? 1.0f : 0.0f;
+    }
+    if (!ps) mb[s.v] = 1;
 }
 
 // Keep the box solution's core (eq. 3, contraction).
+// (ps as in k_setup)
 template <int R>
 __global__ void k_contract(const BoxGeo* __restrict__ geo, const float* __restrict__ xb, int64_t Dx, int64_t Dy,
-                           float* __restrict__ lmap) {
+                           float* __restrict__ lmap, int64_t ps) {
     const BoxGeo b = geo[blockIdx.x];
     const int64_t n = (int64_t)b.cnx * b.cny * b.cnz;
     for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
@@ -280,7 +302,7 @@ __global__ void k_contract(const BoxGeo* __restrict__ geo, const float* __restri
         const int64_t L = X + Dx * (Y + Dy * (int64_t)Z);
         const int64_t v = b.off + (X - b.x0) + (int64_t)b.nx * ((Y - b.y0) + (int64_t)b.ny * (Z - b.z0));
 #pragma unroll
-        for (int c = 0; c < R; ++c) lmap[L * R + c] = xb[v * R + c];
+        for (int c = 0; c < R; ++c) lmap[L * R + c] = xb[ps ? c * ps + v : v * R + c];
     }
 }
 
@@ -539,9 +561,10 @@ static int upload(rw_ctx* ctx, void* dst, const std::vector<T>& v, hipStream_t s
 
 template <int R>
 static void launch_setup(const BoxGeo* geo, int64_t n, const float* glev, int64_t Dx, int64_t Dy, const float* pm,
-                         const int64_t* PD, const float* warm, float* gb, uint8_t* mb, float* xb, hipStream_t s) {
+                         const int64_t* PD, const float* warm, float* gb, uint8_t* mb, float* xb, int64_t ps,
+                         hipStream_t s) {
     hipLaunchKernelGGL(k_setup<R>, dim3((unsigned)n), dim3(kHThreads), 0, s, geo, glev, Dx, Dy, pm, PD ? PD[0] : 0,
-                       PD ? PD[1] : 0, PD ? PD[2] : 0, warm, gb, mb, xb);
+                       PD ? PD[1] : 0, PD ? PD[2] : 0, warm, gb, mb, xb, ps);
 }
 
 // Solve the listed boxes of a level and scatter their cores into lmap.
@@ -553,7 +576,9 @@ static int solve_boxes(rw_ctx* ctx, hipStream_t s, const rw_params& P, const Lev
                        float* lmap, const float* pmap, const int64_t* PD, std::vector<BoxGeo>& geos,
                        const std::map<int64_t, int>& lab, rw_run_stats* st, int level, const float* warm) {
     const int top = pmap == nullptr;
-    const int64_t maxv_batch = (int64_t)1 << 28;   // voxels per batch
+    // each class a box of its own below the coarsest level (rw_params.joint_classes)
+    const bool per_class = R > 1 && P.precision != RW_PREC_FP64 && !top && P.joint_classes == 0;
+    const int64_t maxv_batch = ((int64_t)1 << 28) / (per_class ? R : 1);   // voxels per batch
     size_t i0 = 0;
     while (i0 < geos.size()) {
         // batch [i0, i1)
@@ -586,9 +611,12 @@ static int solve_boxes(rw_ctx* ctx, hipStream_t s, const rw_params& P, const Lev
             else bricks_containing(L, P.brick, P.expand, X, Y, Z, add);
         }
         // workspace: g f32, x f32 * R, mask u8 | geo, seed entries, stats
+        // (per class: g and the mask once per class too, copy c at c * nv)
+        const int64_t ps = per_class ? nv : 0;
+        const int64_t ncopy = per_class ? R : 1;
         const size_t bx = ((size_t)nv * R * 4 + 255) & ~size_t(255);
-        const size_t bg = ((size_t)nv * 4 + 255) & ~size_t(255);
-        const size_t bm = ((size_t)nv + 255) & ~size_t(255);
+        const size_t bg = ((size_t)nv * ncopy * 4 + 255) & ~size_t(255);
+        const size_t bm = ((size_t)nv * ncopy + 255) & ~size_t(255);
         H_HIP(grow(ctx, &ctx->hws, &ctx->hws_bytes, bx + bg + bm, s), "allocating packed boxes");
         char* w = (char*)ctx->hws;
         float* xb = (float*)w;
@@ -596,7 +624,7 @@ static int solve_boxes(rw_ctx* ctx, hipStream_t s, const rw_params& P, const Lev
         uint8_t* mb = (uint8_t*)(w + bx + bg);
         const size_t gg = ((size_t)nb * sizeof(BoxGeo) + 255) & ~size_t(255);
         const size_t ge = ((ent.size() + 1) * sizeof(SeedEntry) + 255) & ~size_t(255);
-        const size_t gs = (size_t)nb * sizeof(rw_brick_stats);
+        const size_t gs = (size_t)nb * ncopy * sizeof(rw_brick_stats);
         H_HIP(grow(ctx, &ctx->hgeo, &ctx->hgeo_bytes, gg + ge + gs, s), "allocating box geometry");
         BoxGeo* dgeo = (BoxGeo*)ctx->hgeo;
         SeedEntry* dent = (SeedEntry*)((char*)ctx->hgeo + gg);
@@ -604,15 +632,17 @@ static int solve_boxes(rw_ctx* ctx, hipStream_t s, const rw_params& P, const Lev
         std::vector<BoxGeo> part(geos.begin() + i0, geos.begin() + i1);
         H_TRY(upload(ctx, dgeo, part, s));
         H_TRY(upload(ctx, dent, ent, s));
-        launch_setup<R>(dgeo, nb, glev, L.D[0], L.D[1], pmap, PD, warm, gb, mb, xb, s);
+        launch_setup<R>(dgeo, nb, glev, L.D[0], L.D[1], pmap, PD, warm, gb, mb, xb, ps, s);
         if (!ent.empty())
             hipLaunchKernelGGL(k_seeds<R>, dim3(grid_for((int64_t)ent.size(), kHThreads)), dim3(kHThreads), 0, s, dent,
-                               (int64_t)ent.size(), mb, xb);
+                               (int64_t)ent.size(), mb, xb, ps);
         H_HIP(hipGetLastError(), "launching box setup");
-        // batched box solve
-        std::vector<rw_brick> br((size_t)nb);
-        for (int64_t i = 0; i < nb; ++i)
-            br[(size_t)i] = rw_brick{part[(size_t)i].nx, part[(size_t)i].ny, part[(size_t)i].nz, 0, part[(size_t)i].off};
+        // batched box solve (per class: class c of box i is box c * nb + i)
+        std::vector<rw_brick> br((size_t)(nb * ncopy));
+        for (int64_t c = 0; c < ncopy; ++c)
+            for (int64_t i = 0; i < nb; ++i)
+                br[(size_t)(c * nb + i)] = rw_brick{part[(size_t)i].nx, part[(size_t)i].ny, part[(size_t)i].nz, 0,
+                                                     c * ps + part[(size_t)i].off};
         rw_solve_params sp;
         rw_solve_params_default(&sp);
         sp.beta = P.beta;
@@ -620,26 +650,34 @@ static int solve_boxes(rw_ctx* ctx, hipStream_t s, const rw_params& P, const Lev
         sp.tol = P.tol;
         sp.max_iter = P.max_iter;
         sp.precision = P.precision;
-        sp.nrhs = R;
+        sp.nrhs = per_class ? 1 : R;
         sp.refine_max = P.refine_max;
         sp.schedule = P.schedule;
-        H_TRY(rw_solve_bricks(ctx, &sp, nb, br.data(), nv, gb, mb, xb, nullptr, dst, s));
-        hipLaunchKernelGGL(k_contract<R>, dim3((unsigned)nb), dim3(kHThreads), 0, s, dgeo, xb, L.D[0], L.D[1], lmap);
+        H_TRY(rw_solve_bricks(ctx, &sp, nb * ncopy, br.data(), nv * ncopy, gb, mb, xb, nullptr, dst, s));
+        hipLaunchKernelGGL(k_contract<R>, dim3((unsigned)nb), dim3(kHThreads), 0, s, dgeo, xb, L.D[0], L.D[1], lmap,
+                           ps);
         H_HIP(hipGetLastError(), "launching contraction");
         // stats (the workspaces are reused by the next batch: sync)
-        std::vector<rw_brick_stats> hs((size_t)nb);
-        H_HIP(hipMemcpyAsync(hs.data(), dst, (size_t)nb * sizeof(rw_brick_stats), hipMemcpyDeviceToHost, s),
+        std::vector<rw_brick_stats> hs((size_t)(nb * ncopy));
+        H_HIP(hipMemcpyAsync(hs.data(), dst, hs.size() * sizeof(rw_brick_stats), hipMemcpyDeviceToHost, s),
               "reading solver stats");
         H_HIP(hipStreamSynchronize(s), "synchronising level");
         for (int64_t i = 0; i < nb; ++i) {
-            const rw_brick_stats& q = hs[(size_t)i];
+            // a box's sweeps and status over its classes, as a joint solve reports them
+            int32_t it = 0, rit = 0;
+            bool bad = false;
+            for (int64_t c = 0; c < ncopy; ++c) {
+                const rw_brick_stats& q = hs[(size_t)(c * nb + i)];
+                it = std::max(it, q.iters);
+                rit = std::max(rit, q.refine_iters);
+                bad = bad || q.status == RW_ST_MAX_ITER || q.status == RW_ST_STALLED || q.status == RW_ST_NONFINITE ||
+                      q.status == RW_ST_SYNC_LOST;
+            }
             const int64_t v = (int64_t)part[(size_t)i].nx * part[(size_t)i].ny * part[(size_t)i].nz;
-            st->voxel_iters[level] += v * (int64_t)(q.iters + q.refine_iters);
+            st->voxel_iters[level] += v * (int64_t)(it + rit);
             st->box_voxels[level] += v;
-            st->max_iters[level] = std::max(st->max_iters[level], q.iters);
-            if (q.status == RW_ST_MAX_ITER || q.status == RW_ST_STALLED || q.status == RW_ST_NONFINITE ||
-                q.status == RW_ST_SYNC_LOST)
-                st->not_converged[level] += 1;
+            st->max_iters[level] = std::max(st->max_iters[level], it);
+            if (bad) st->not_converged[level] += 1;
         }
         st->solved[level] += nb;
         i0 = i1;
@@ -1073,7 +1111,7 @@ int rw_segment(rw_ctx* ctx, const rw_pyramid* pyr, const rw_seed* seeds, int64_t
     if (!(P.t_hom >= 0) || !(P.t_bin >= 0) || !(P.t_inc >= 0)) return fail(ctx, RW_E_INVAL, "thresholds must be >= 0");
     if (P.incremental < 0 || P.incremental > 3) return fail(ctx, RW_E_INVAL, "incremental must be in 0..3");
     if (P.schedule < 0 || P.schedule > RW_SCHED_TUNED) return fail(ctx, RW_E_INVAL, "schedule must be in 0..5");
-    if (P.reserved != 0) return fail(ctx, RW_E_INVAL, "reserved must be 0");
+    if (P.joint_classes != 0 && P.joint_classes != 1) return fail(ctx, RW_E_INVAL, "joint_classes must be 0 or 1");
     for (int64_t i = 0; i < n_seeds; ++i) {
         const rw_seed& q = seeds[i];
         if (!std::isfinite(q.x) || !std::isfinite(q.y) || !std::isfinite(q.z))
