@@ -114,6 +114,40 @@ def measure_ceilings(torch, rwg, ctx, reps=5):
                     "bytes), 32 re-reads of 128 MiB (last-level cache); best of 5 launches"}
 
 
+def roofline_alone(torch, rwg, ctx, d, g, m, x, x0, stream, reps=3):
+    """The dominant launch without the others beside it: the 32^3 boxes of
+    the workload solved by themselves (same parameters, outside the timed
+    steps; their offsets index the same arrays), the launch timed by the
+    library's HIP events on its stream.  The kernel's own rate; in the timed
+    step it shares the chip with the other launches."""
+    import numpy as np
+    sizes = d["shapes"].prod(axis=1)
+    sel = np.where(sizes == 32 ** 3)[0]
+    if len(sel) == 0:
+        return None
+    b = rwg.bricks_array(d["shapes"][sel], d["offsets"][sel])
+    p = rwg.solve_params(beta=BETA, eps=EPS, tol=TOL, precision=rwg.PREC_MIXED, refine_max=1, inner_tol=1e-4)
+    st = torch.empty((len(sel), 32), dtype=torch.uint8, device=g.device)
+    x.copy_(x0)
+    ctx.rw_solve_bricks(p, b, g, m, x, stats=st, stream=stream)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ms = []
+    for _ in range(reps):
+        x.copy_(x0)
+        ctx.rw_solve_bricks(p, b, g, m, x, stats=st, stream=stream)
+        ms.append(ctx.last_timing()["stream_ms"])
+    ctx.set_timing(False)
+    torch.cuda.synchronize()
+    s = rwg.stats_to_numpy(st)
+    vi = int(np.sum(sizes[sel] * s["iters"].astype(np.int64)))
+    t = float(np.median(ms)) / 1e3
+    ach = SEGMENT_BYTES_PER_VOXEL_ITER * vi / t / 1e9
+    return {"boxes": int(len(sel)), "voxel_iters": vi, "ms": t * 1e3, "achieved": ach, "frac": ach / HBM_PEAK_GBS,
+            "note": "the 32^3 boxes solved alone (median of 3 calls, outside the timed steps): the launch's own "
+                    "rate at 16 B per voxel-iteration; in the timed step it shares the chip with the other launches"}
+
+
 def probe_read_sweep(torch, rwg, ctx, reps=4):
     """Read bandwidth against buffer size: each buffer re-read in one probe
     launch (up to 64 passes, about 4 GiB in all), best of `reps` launches for
@@ -855,6 +889,7 @@ def main():
     achieved = SEGMENT_BYTES_PER_VOXEL_ITER * vox_roof / t["stream_ms"] / 1e9 if t["stream_ms"] > 0 else 0.0
     stream_equiv = BYTES_PER_VOXEL_ITER * vox_roof / t["stream_ms"] / 1e9 if t["stream_ms"] > 0 else 0.0
     ceilings = measure_ceilings(torch, rwg, ctx)
+    alone = roofline_alone(torch, rwg, ctx, d, g, m, x, x0, stream) if split else None
     # memory bytes of the whole PCG phase, each box at its kernel's own
     # algorithmic bytes (a cross-check that must stay below the HBM peak)
     n_res_vox = mixed["res_vox"]
@@ -886,6 +921,7 @@ def main():
                                 "launch" if split else "k_pcg_resg (streamed-weights resident PCG), main-solve launches"),
                      "bytes_per_voxel_iter": SEGMENT_BYTES_PER_VOXEL_ITER,
                      "measured_ceilings": ceilings,
+                     "alone": alone,
                      "frac_of_measured_hbm_read": achieved / ceilings["hbm_read_GBps"],
                      "frac_of_measured_llc_reread": achieved / ceilings["llc_reread_GBps"],
                      "streaming_equivalent": {"bytes_per_voxel_iter": BYTES_PER_VOXEL_ITER, "GBps": stream_equiv,

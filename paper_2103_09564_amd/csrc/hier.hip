@@ -182,48 +182,37 @@ __device__ __forceinline__ void taps(int64_t X, int64_t n, int64_t& i0, int64_t&
     t = P - (float)a;
 }
 
+// One workgroup per row (Y, Z) of the child map (grid cy x cz): the y and z
+// taps and the four parent rows they select are the workgroup's, so a voxel
+// only takes its x taps; threads walk the row at a stride of the workgroup.
 template <int R>
 __global__ void k_upsample(const float* __restrict__ pm, int64_t px, int64_t py, int64_t pz, float* __restrict__ cm,
                            int64_t cx, int64_t cy, int64_t cz) {
-    const int64_t n = cx * cy * cz;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t X = i % cx, Y = (i / cx) % cy, Z = i / (cx * cy);
-        int64_t x0, x1, y0, y1, z0, z1;
-        float tx, ty, tz;
-        taps(X, px, x0, x1, tx);
-        taps(Y, py, y0, y1, ty);
-        taps(Z, pz, z0, z1, tz);
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            auto P = [&](int64_t a, int64_t b, int64_t c) { return pm[(a + px * (b + py * c)) * R + k]; };
-            const float c00 = (1.0f - tx) * P(x0, y0, z0) + tx * P(x1, y0, z0);
-            const float c10 = (1.0f - tx) * P(x0, y1, z0) + tx * P(x1, y1, z0);
-            const float c01 = (1.0f - tx) * P(x0, y0, z1) + tx * P(x1, y0, z1);
-            const float c11 = (1.0f - tx) * P(x0, y1, z1) + tx * P(x1, y1, z1);
-            const float c0 = (1.0f - ty) * c00 + ty * c10;
-            const float c1 = (1.0f - ty) * c01 + ty * c11;
-            cm[i * R + k] = (1.0f - tz) * c0 + tz * c1;
-        }
-    }
-}
-
-// Trilinear sample of a parent level map at child voxel (X, Y, Z), class c.
-template <int R>
-__device__ __forceinline__ float sample_parent(const float* __restrict__ pm, int64_t px, int64_t py, int64_t pz,
-                                               int64_t X, int64_t Y, int64_t Z, int c) {
-    int64_t x0, x1, y0, y1, z0, z1;
-    float tx, ty, tz;
-    taps(X, px, x0, x1, tx);
+    const int64_t Y = blockIdx.x, Z = blockIdx.y;
+    int64_t y0, y1, z0, z1;
+    float ty, tz;
     taps(Y, py, y0, y1, ty);
     taps(Z, pz, z0, z1, tz);
-    auto P = [&](int64_t a, int64_t b, int64_t cc) { return pm[(a + px * (b + py * cc)) * R + c]; };
-    const float c00 = (1.0f - tx) * P(x0, y0, z0) + tx * P(x1, y0, z0);
-    const float c10 = (1.0f - tx) * P(x0, y1, z0) + tx * P(x1, y1, z0);
-    const float c01 = (1.0f - tx) * P(x0, y0, z1) + tx * P(x1, y0, z1);
-    const float c11 = (1.0f - tx) * P(x0, y1, z1) + tx * P(x1, y1, z1);
-    const float c0 = (1.0f - ty) * c00 + ty * c10;
-    const float c1 = (1.0f - ty) * c01 + ty * c11;
-    return (1.0f - tz) * c0 + tz * c1;
+    const float* r00 = pm + px * (y0 + py * z0) * R;
+    const float* r10 = pm + px * (y1 + py * z0) * R;
+    const float* r01 = pm + px * (y0 + py * z1) * R;
+    const float* r11 = pm + px * (y1 + py * z1) * R;
+    float* out = cm + cx * (Y + cy * Z) * R;
+    for (int64_t X = threadIdx.x; X < cx; X += blockDim.x) {
+        int64_t x0, x1;
+        float tx;
+        taps(X, px, x0, x1, tx);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const float c00 = (1.0f - tx) * r00[x0 * R + k] + tx * r00[x1 * R + k];
+            const float c10 = (1.0f - tx) * r10[x0 * R + k] + tx * r10[x1 * R + k];
+            const float c01 = (1.0f - tx) * r01[x0 * R + k] + tx * r01[x1 * R + k];
+            const float c11 = (1.0f - tx) * r11[x0 * R + k] + tx * r11[x1 * R + k];
+            const float c0 = (1.0f - ty) * c00 + ty * c10;
+            const float c1 = (1.0f - ty) * c01 + ty * c11;
+            out[X * R + k] = (1.0f - tz) * c0 + tz * c1;
+        }
+    }
 }
 
 // One workgroup per box: gather g, set the Dirichlet layer on border faces,
@@ -242,9 +231,9 @@ __global__ void k_setup(const BoxGeo* __restrict__ geo, const float* __restrict_
                         const float* __restrict__ warm, float* __restrict__ gb, uint8_t* __restrict__ mb,
                         float* __restrict__ xb, int64_t ps) {
     const BoxGeo b = geo[blockIdx.x];
-    const int64_t n = (int64_t)b.nx * b.ny * b.nz;
-    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
-        const int i = (int)(t % b.nx), j = (int)((t / b.nx) % b.ny), k = (int)(t / ((int64_t)b.nx * b.ny));
+    const int nxy = b.nx * b.ny, n = nxy * b.nz;  // (box voxels fit 32 bits)
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int k = t / nxy, rem = t - k * nxy, j = rem / b.nx, i = rem - j * b.nx;
         const int64_t X = b.x0 + i, Y = b.y0 + j, Z = b.z0 + k;
         const int64_t L = X + Dx * (Y + Dy * Z);
         const int64_t v = b.off + t;
@@ -254,10 +243,29 @@ __global__ void k_setup(const BoxGeo* __restrict__ geo, const float* __restrict_
                             ((b.faces & 16) && k == 0) || ((b.faces & 32) && k == b.nz - 1);
         // the border takes the parent sample; with a warm map (a previous
         // result of this level) the unseeded voxels start from it instead
+        const bool from_warm = warm && !border;
+        int64_t x0 = 0, x1 = 0, y0 = 0, y1 = 0, z0 = 0, z1 = 0;
+        float tx = 0.0f, ty = 0.0f, tz = 0.0f;
+        if (pm && !from_warm) {
+            taps(X, px, x0, x1, tx);
+            taps(Y, py, y0, y1, ty);
+            taps(Z, pz, z0, z1, tz);
+        }
 #pragma unroll
         for (int c = 0; c < R; ++c) {
-            const float xv = warm && !border ? warm[L * R + c]
-                                             : pm ? sample_parent<R>(pm, px, py, pz, X, Y, Z, c) : 0.0f;
+            float xv = 0.0f;
+            if (from_warm) {
+                xv = warm[L * R + c];
+            } else if (pm) {
+                auto P = [&](int64_t a, int64_t bb, int64_t cc) { return pm[(a + px * (bb + py * cc)) * R + c]; };
+                const float c00 = (1.0f - tx) * P(x0, y0, z0) + tx * P(x1, y0, z0);
+                const float c10 = (1.0f - tx) * P(x0, y1, z0) + tx * P(x1, y1, z0);
+                const float c01 = (1.0f - tx) * P(x0, y0, z1) + tx * P(x1, y0, z1);
+                const float c11 = (1.0f - tx) * P(x0, y1, z1) + tx * P(x1, y1, z1);
+                const float c0 = (1.0f - ty) * c00 + ty * c10;
+                const float c1 = (1.0f - ty) * c01 + ty * c11;
+                xv = (1.0f - tz) * c0 + tz * c1;
+            }
             if (ps) {
                 gb[c * ps + v] = gv;
                 mb[c * ps + v] = border ? 1 : 0;
@@ -854,10 +862,10 @@ static int segment_impl(rw_ctx* ctx, const rw_pyramid* pyr, const std::vector<rw
         const LevelGeo& PL = LG[(size_t)l + 1];
         rwk::LevelRes& lr = res->lv[l];
         const rwk::LevelRes& pr = res->lv[l + 1];
-        const int64_t nvox = L.D[0] * L.D[1] * L.D[2];
         const int64_t nbr = L.nb[0] * L.nb[1] * L.nb[2];
-        hipLaunchKernelGGL(k_upsample<R>, dim3(grid_for(nvox, kHThreads)), dim3(kHThreads), 0, s, pr.map, PL.D[0],
-                           PL.D[1], PL.D[2], lr.map, L.D[0], L.D[1], L.D[2]);
+        if (L.D[2] > 65535) return fail(ctx, RW_E_UNSUPPORTED, "levels deeper than 65535 planes are not supported");
+        hipLaunchKernelGGL(k_upsample<R>, dim3((unsigned)L.D[1], (unsigned)L.D[2]), dim3(kHThreads), 0, s, pr.map,
+                           PL.D[0], PL.D[1], PL.D[2], lr.map, L.D[0], L.D[1], L.D[2]);
         H_HIP(hipGetLastError(), "launching upsample");
         std::vector<uint8_t> pflags((size_t)(PL.nb[0] * PL.nb[1] * PL.nb[2]));
         H_HIP(hipMemcpyAsync(pflags.data(), pr.flags, pflags.size(), hipMemcpyDeviceToHost, s), "reading parent flags");

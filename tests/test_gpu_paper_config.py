@@ -145,6 +145,25 @@ def test_shell_twin_k4_mixed_labels(env, shell_twin):
           f"with margin > 1e-3; accuracy vs truth GPU {acc_g:.4f} oracle {acc_o:.4f}", flush=True)
 
 
+def test_shell_twin_k4_joint_and_per_class(env, shell_twin):
+    """Below the coarsest level each class of a box is solved as a box of its
+    own (one right-hand side) by default; rw_params.joint_classes = 1 solves
+    the three together.  The same independent solves: the same decisions,
+    level maps within 4e-5 of each other (two stops at relative residual
+    1e-6) and both within 1e-4 of the oracle."""
+    vol, lab, seeds, kw, ores = shell_twin
+    rp, mp, fp = _gpu(env, vol, seeds, 3, precision=1, tol=1e-6, **kw)
+    rj, mj, fj = _gpu(env, vol, seeds, 3, precision=1, tol=1e-6, joint_classes=1, **kw)
+    for l in range(3):
+        assert np.array_equal(fp[l], fj[l]), l
+    diff = max(float(np.max(np.abs(mp[l] - mj[l]))) for l in range(3))
+    print(f"shell twin K=4: per-class vs joint max diff {diff:.3e}", flush=True)
+    assert diff <= 4e-5
+    assert max(_max_err(mp, ores, 3)) <= 1e-4 and max(_max_err(mj, ores, 3)) <= 1e-4
+    # a box's iterations are the most any of its classes took in both
+    assert rp.stats()["solved"] == rj.stats()["solved"]
+
+
 def test_tube_512_per_brick_replay(env):
     """Sampled level-0 bricks of the full-size tube pipeline, rebuilt by the
     oracle from the GPU's level-1 map and solved exactly.
