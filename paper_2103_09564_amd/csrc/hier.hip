@@ -182,12 +182,17 @@ __device__ __forceinline__ void taps(int64_t X, int64_t n, int64_t& i0, int64_t&
     t = P - (float)a;
 }
 
-// One workgroup per row (Y, Z) of the child map (grid cy x cz): the y and z
-// taps and the four parent rows they select are the workgroup's, so a voxel
-// only takes its x taps; threads walk the row at a stride of the workgroup.
+// One workgroup per row (Y, Z) of the child map (grid cy x cz).  The
+// workgroup first blends, for every parent x of the row, the four parent
+// rows its y and z taps select (in LDS, up to kUpRow parent voxels at a
+// time), then each child voxel takes the two x taps from LDS: every parent
+// value is loaded once per row instead of eight times per voxel.
+constexpr int kUpRow = 1024;  // parent voxels of a row blended at a time
+
 template <int R>
 __global__ void k_upsample(const float* __restrict__ pm, int64_t px, int64_t py, int64_t pz, float* __restrict__ cm,
                            int64_t cx, int64_t cy, int64_t cz) {
+    __shared__ float yz[kUpRow * R];
     const int64_t Y = blockIdx.x, Z = blockIdx.y;
     int64_t y0, y1, z0, z1;
     float ty, tz;
@@ -198,19 +203,31 @@ __global__ void k_upsample(const float* __restrict__ pm, int64_t px, int64_t py,
     const float* r01 = pm + px * (y0 + py * z1) * R;
     const float* r11 = pm + px * (y1 + py * z1) * R;
     float* out = cm + cx * (Y + cy * Z) * R;
-    for (int64_t X = threadIdx.x; X < cx; X += blockDim.x) {
-        int64_t x0, x1;
-        float tx;
-        taps(X, px, x0, x1, tx);
+    // windows of W children: a child X takes parent x floor(X/2 - 1/4) and
+    // the next, so the window [X0, X0 + W) needs at most (W - 1)/2 + 3 <=
+    // kUpRow parent voxels from the first child's first tap on
+    constexpr int64_t W = 2 * (kUpRow - 4);
+    for (int64_t X0 = 0; X0 < cx; X0 += W) {
+        int64_t a0, a1;
+        float t0;
+        taps(X0, px, a0, a1, t0);
+        const int64_t na = std::min<int64_t>(kUpRow, px - a0);
+        const int64_t X1 = std::min<int64_t>(cx, X0 + W);
+        __syncthreads();  // the previous window's readers are done
+        for (int64_t q = threadIdx.x; q < na * R; q += blockDim.x) {
+            const int64_t e = a0 * R + q;
+            const float c0 = (1.0f - ty) * r00[e] + ty * r10[e];
+            const float c1 = (1.0f - ty) * r01[e] + ty * r11[e];
+            yz[q] = (1.0f - tz) * c0 + tz * c1;
+        }
+        __syncthreads();
+        for (int64_t X = X0 + threadIdx.x; X < X1; X += blockDim.x) {
+            int64_t x0, x1;
+            float tx;
+            taps(X, px, x0, x1, tx);
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const float c00 = (1.0f - tx) * r00[x0 * R + k] + tx * r00[x1 * R + k];
-            const float c10 = (1.0f - tx) * r10[x0 * R + k] + tx * r10[x1 * R + k];
-            const float c01 = (1.0f - tx) * r01[x0 * R + k] + tx * r01[x1 * R + k];
-            const float c11 = (1.0f - tx) * r11[x0 * R + k] + tx * r11[x1 * R + k];
-            const float c0 = (1.0f - ty) * c00 + ty * c10;
-            const float c1 = (1.0f - ty) * c01 + ty * c11;
-            out[X * R + k] = (1.0f - tz) * c0 + tz * c1;
+            for (int k = 0; k < R; ++k)
+                out[X * R + k] = (1.0f - tx) * yz[(x0 - a0) * R + k] + tx * yz[(x1 - a0) * R + k];
         }
     }
 }
