@@ -463,7 +463,7 @@ def _replay_worker(args):
     return xb[(slice(None),) + rel]
 
 
-def bench_shells_full(torch, rwg, ctx, dims=(2048, 2048, 1024), levels=5, n_replay=64, cpu_leg=True):
+def bench_shells_full(torch, rwg, ctx, dims=(2048, 2048, 1024), levels=5, n_replay=256, cpu_leg=True):
     """The large multi-class incremental configuration at full size:
     2048 x 2048 x 1024 uint16 (8 GiB), four classes (background and three
     nested ellipsoidal shells, sigma 250 noise plus 1/f noise), 5 levels,

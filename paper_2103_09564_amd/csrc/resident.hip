@@ -726,12 +726,19 @@ __device__ __forceinline__ void res_block_sum_lds(double (&v)[N], double* red) {
         for (int k = 0; k < N; ++k) red[w * N + k] = v[k];
     }
     res_lds_barrier();
+    // lane k < N adds value k over the waves (wave order); every lane then
+    // reads the N totals from those lanes (uniform: no VGPR holds them)
+    double s = 0.0;
+    if (lane < N) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) s += red[i * N + lane];
+    }
+    const unsigned long long sb = (unsigned long long)__double_as_longlong(s);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < W; ++i) s += red[i * N + k];
-        v[k] = s;
+        const unsigned lo = __builtin_amdgcn_readlane((unsigned)sb, k);
+        const unsigned hi = __builtin_amdgcn_readlane((unsigned)(sb >> 32), k);
+        v[k] = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
     }
     res_lds_barrier();
 }
