@@ -240,6 +240,7 @@ def _best_ms(torch, fn, reps):
     best = float("inf")
     out = None
     for _ in range(reps):
+        out = None  # (the previous repetition's result is released outside the timed call)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = fn()

@@ -127,7 +127,8 @@ typedef struct rw_ctx rw_ctx;
 int rw_version(void);
 
 /* Create a context on HIP device `hip_device`.  The context owns a device
- * workspace that grows on demand and is freed by rw_ctx_destroy. */
+ * workspace that grows on demand and is freed by rw_ctx_destroy, which also
+ * frees the device's cached hierarchy buffers (see rw_result_free). */
 int rw_ctx_create(int hip_device, rw_ctx** out);
 void rw_ctx_destroy(rw_ctx* ctx);
 
@@ -439,6 +440,10 @@ int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims
  */
 int rw_pyramid_build_counts(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels,
                             rw_pyramid** out, void* stream);
+/* Waits for the device, then hands the levels' buffers to a per-device cache
+ * that the next pyramid or rw_segment of the same sizes takes them from (at
+ * most 8 GiB per device are kept, the rest is freed; an allocation that
+ * fails empties the cache first; rw_ctx_destroy empties it). */
 void rw_pyramid_free(rw_pyramid* p);
 /* Level accessor: dims = {nx, ny, nz} of the level, *data = dev float [nz][ny][nx]. */
 int rw_pyramid_level(const rw_pyramid* p, int level, int64_t dims[3], const float** data);
@@ -527,6 +532,8 @@ typedef struct rw_run_stats {
  */
 int rw_segment(rw_ctx* ctx, const rw_pyramid* pyr, const rw_seed* seeds, int64_t n_seeds,
                const rw_params* params, const rw_result* prev, rw_result** out, void* stream);
+/* Waits for the device, then hands the result's level maps and flag arrays
+ * to the per-device cache described at rw_pyramid_free. */
 void rw_result_free(rw_result* r);
 int rw_result_stats(const rw_result* r, rw_run_stats* out);
 /* Level map: dims = {nx, ny, nz}, nrhs = K - 1, *map = dev float [voxel][nrhs]

@@ -643,6 +643,7 @@ void rw_ctx_destroy(rw_ctx* ctx) {
     if (!ctx) return;
     DevGuard g(ctx->device);
     (void)hipDeviceSynchronize();
+    rwk::pool_trim(ctx->device);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->bricks) (void)hipFree(ctx->bricks);
     if (ctx->aux) (void)hipFree(ctx->aux);

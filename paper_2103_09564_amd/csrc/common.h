@@ -265,6 +265,9 @@ constexpr int64_t kDomBigVox = int64_t(1) << 20;
 constexpr int kDomMaxBoxes = 16;
 size_t domain_scratch_bytes();
 void domain_bind(SolveArgs& a, void* scratch);
+// Frees the hierarchy's cached level buffers of device `dev` (hier.hip; the
+// current device must be dev).
+void pool_trim(int dev);
 // The phases of the per-box solve for box ib of the launch list (bd: its host
 // descriptor), each over many workgroups.  domain_pcg runs PCG from the state
 // the init or check left, into xt (corr = 0: main solve, 1: correction

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <set>
 #include <tuple>
@@ -33,6 +34,7 @@ struct LevelRes {
     int64_t nb[3] = {0, 0, 0};
     float* map = nullptr;
     uint8_t* flags = nullptr;
+    size_t map_bytes = 0, flags_bytes = 0;
 };
 }  // namespace rwk
 
@@ -482,6 +484,72 @@ static unsigned grid_for(int64_t n, int threads) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
 }
 
+// The buffers of freed results and pyramids (level maps, brick flags,
+// pyramid levels) are kept per device for the next allocation of the same
+// size, since hipFree synchronises the device and a run allocates two buffers
+// per level: at most kPoolBytes per device are kept, the rest is freed.  An
+// allocation that fails empties the device's cache and is tried once more;
+// rw_ctx_destroy empties it too.  The cache is never destroyed (no hipFree
+// at process exit).
+constexpr size_t kPoolBytes = size_t(8) << 30;
+struct BufPool {
+    std::mutex mu;
+    std::multimap<std::pair<int, size_t>, void*> idle;  // (device, bytes) -> buffer
+    std::map<int, size_t> held;                         // idle bytes per device
+};
+static BufPool& buf_pool() {
+    static BufPool* p = new BufPool();
+    return *p;
+}
+// Frees the idle buffers of `dev` (the current device).
+void pool_trim(int dev) {
+    BufPool& P = buf_pool();
+    std::lock_guard<std::mutex> g(P.mu);
+    for (auto it = P.idle.begin(); it != P.idle.end();) {
+        if (it->first.first == dev) {
+            (void)hipFree(it->second);
+            it = P.idle.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    P.held[dev] = 0;
+}
+// A buffer of `bytes` on `dev` (the current device): a cached one of that
+// size, else hipMalloc.
+static hipError_t pool_alloc(int dev, void** out, size_t bytes) {
+    BufPool& P = buf_pool();
+    {
+        std::lock_guard<std::mutex> g(P.mu);
+        auto it = P.idle.find({dev, bytes});
+        if (it != P.idle.end()) {
+            *out = it->second;
+            P.held[dev] -= bytes;
+            P.idle.erase(it);
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        pool_trim(dev);
+        e = hipMalloc(out, bytes);
+    }
+    return e;
+}
+// Returns a buffer no queued work uses any more (the caller has synchronised).
+static void pool_release(int dev, void* p, size_t bytes) {
+    if (!p) return;
+    BufPool& P = buf_pool();
+    std::lock_guard<std::mutex> g(P.mu);
+    if (P.held[dev] + bytes > kPoolBytes) {
+        (void)hipFree(p);
+        return;
+    }
+    P.idle.insert({{dev, bytes}, p});
+    P.held[dev] += bytes;
+}
+
 // ---- host planning ------------------------------------------------------------
 
 struct LevelGeo {
@@ -752,8 +820,10 @@ static int segment_impl(rw_ctx* ctx, const rw_pyramid* pyr, const std::vector<rw
         const int64_t nvox = lr.dims[0] * lr.dims[1] * lr.dims[2];
         const int64_t nbr = lr.nb[0] * lr.nb[1] * lr.nb[2];
         st.bricks[l] = nbr;
-        H_HIP(hipMalloc((void**)&lr.map, (size_t)nvox * R * sizeof(float)), "allocating level map");
-        H_HIP(hipMalloc((void**)&lr.flags, (size_t)nbr), "allocating brick flags");
+        lr.map_bytes = (size_t)nvox * R * sizeof(float);
+        lr.flags_bytes = (size_t)nbr;
+        H_HIP(pool_alloc(res->device, (void**)&lr.map, lr.map_bytes), "allocating level map");
+        H_HIP(pool_alloc(res->device, (void**)&lr.flags, lr.flags_bytes), "allocating brick flags");
         H_HIP(hipMemsetAsync(lr.flags, 0, (size_t)nbr, s), "clearing brick flags");
     }
     auto all_bricks = [&](int l) {
@@ -985,8 +1055,8 @@ using namespace rwk;
 
 static void free_result_mem(rw_result* r) {
     for (int l = 0; l < RW_MAX_LEVELS; ++l) {
-        if (r->lv[l].map) (void)hipFree(r->lv[l].map);
-        if (r->lv[l].flags) (void)hipFree(r->lv[l].flags);
+        pool_release(r->device, r->lv[l].map, r->lv[l].map_bytes);
+        pool_release(r->device, r->lv[l].flags, r->lv[l].flags_bytes);
         r->lv[l].map = nullptr;
         r->lv[l].flags = nullptr;
     }
@@ -1037,7 +1107,7 @@ static int pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t 
         for (int a = 0; a < 3; ++a) p->dims[l][a] = l == 0 ? dims[a] : (p->dims[l - 1][a] + 1) / 2;
     for (int l = 0; l < levels; ++l) {
         const int64_t n = p->dims[l][0] * p->dims[l][1] * p->dims[l][2];
-        hipError_t e = hipMalloc((void**)&p->data[l], (size_t)n * sizeof(float));
+        hipError_t e = pool_alloc(p->device, (void**)&p->data[l], (size_t)n * sizeof(float));
         if (e != hipSuccess) {
             rw_pyramid_free(p);
             return hip_fail(ctx, e, "allocating pyramid level");
@@ -1054,7 +1124,7 @@ static int pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t 
     } else if (dtype == RW_U16) {
         unsigned init[2] = {0xffffu, 0u};
         unsigned* mm = nullptr;
-        hipError_t e = hipMalloc((void**)&mm, sizeof(init));
+        hipError_t e = pool_alloc(p->device, (void**)&mm, sizeof(init));
         if (e == hipSuccess) e = hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) {
             const unsigned gmm = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kMinMaxBlocks, (n0 / 8 + 255) / 256));
@@ -1065,7 +1135,8 @@ static int pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t 
             e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (mm) (void)hipFree(mm);
+        if (e == hipSuccess) pool_release(p->device, mm, sizeof(init));
+        else if (mm) (void)hipFree(mm);
         if (e != hipSuccess) {
             rw_pyramid_free(p);
             return hip_fail(ctx, e, "normalising volume");
@@ -1107,8 +1178,8 @@ void rw_pyramid_free(rw_pyramid* p) {
     if (!p) return;
     DevGuard dg(p->device);
     (void)hipDeviceSynchronize();
-    for (int l = 0; l < RW_MAX_LEVELS; ++l)
-        if (p->data[l]) (void)hipFree(p->data[l]);
+    for (int l = 0; l < p->levels; ++l)
+        pool_release(p->device, p->data[l], (size_t)(p->dims[l][0] * p->dims[l][1] * p->dims[l][2]) * sizeof(float));
     delete p;
 }
 
