@@ -16,11 +16,13 @@
 //   B(n): x += alpha p, r -= alpha L_UU p, z = r / d, partial r.z, ||r||^2;
 //         last workgroup: convergence test, beta_{n+1}, state n+1
 // The scalar state of iteration n lives in slot n & 1; the host reads the
-// done flag every few iterations and stops launching.
+// done flag every few iterations (one read behind the queued launches) and
+// stops launching.
 
 #include "common.h"
 
 #include <algorithm>
+#include <map>
 
 namespace rwk {
 
@@ -812,6 +814,33 @@ hipError_t domain_init(const SolveArgs& a, int ib, const BrickDev& bd, hipStream
     return hipGetLastError();
 }
 
+// Page-locked slots and events for the done-flag reads of domain_pcg, per
+// host thread and device, created on first use and kept for the thread's
+// lifetime; null when they cannot be had.
+struct DomPoll {
+    int32_t* flag = nullptr;  // [2], page-locked
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool tried = false;
+};
+static DomPoll* dom_poll() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    thread_local std::map<int, DomPoll> polls;
+    DomPoll& p = polls[dev];
+    if (!p.tried) {
+        p.tried = true;
+        void* h = nullptr;
+        bool ok = hipHostMalloc(&h, 64, hipHostMallocDefault) == hipSuccess;
+        if (ok) p.flag = (int32_t*)h;
+        for (int i = 0; i < 2 && ok; ++i) ok = hipEventCreateWithFlags(&p.ev[i], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            p.flag = nullptr;
+        }
+    }
+    return p.flag ? &p : nullptr;
+}
+
 template <typename T, int R, typename XT>
 hipError_t domain_pcg(const SolveArgs& a, int ib, const BrickDev& bd, XT* xt, int corr, hipStream_t s) {
     const int64_t nv = (int64_t)bd.nx * bd.ny * bd.nz;
@@ -823,6 +852,13 @@ hipError_t domain_pcg(const SolveArgs& a, int ib, const BrickDev& bd, XT* xt, in
     T* p1 = (T*)a.p1;
     DomCtl* ctl = (DomCtl*)a.dom;
     hipLaunchKernelGGL(k_dstart<R>, dim3(1), dim3(64), 0, s, a, ib);
+    // The done flag is read after the first iteration and every `poll`
+    // iterations: copied into page-locked memory behind the launches, and
+    // waited for only after the next `poll` iterations are queued, so the
+    // device does not idle while the host reads it.  Iterations queued past
+    // the end are no-ops (A and B return at once when the state is done).
+    // Without the page-locked slots the flag is read synchronously.
+    DomPoll* pl = dom_poll();
     auto finished = [&](int slot, bool* out) -> hipError_t {
         int32_t f = 0;
         hipError_t e = hipMemcpyAsync(&f, &ctl->s[slot].all_done, sizeof(f), hipMemcpyDeviceToHost, s);
@@ -831,7 +867,7 @@ hipError_t domain_pcg(const SolveArgs& a, int ib, const BrickDev& bd, XT* xt, in
         return e;
     };
     const int poll = 16;
-    int it = 0;
+    int it = 0, checks = 0, pending = -1;
     for (;; ++it) {
         T* pold = (it & 1) ? p1 : p0;
         T* pnew = (it & 1) ? p0 : p1;
@@ -841,8 +877,23 @@ hipError_t domain_pcg(const SolveArgs& a, int ib, const BrickDev& bd, XT* xt, in
         hipLaunchKernelGGL((k_dB<T, R, XT>), dim3(G), dim3(kDomThreads), 0, s, a, ib, it, xt, (const T*)pnew);
         if (it == 0 || (it + 1) % poll == 0) {
             bool done = false;
-            hipError_t e = finished(it & 1, &done);
-            if (e != hipSuccess) return e;
+            if (!pl) {
+                hipError_t e = finished(it & 1, &done);
+                if (e != hipSuccess) return e;
+            } else {
+                // check `checks` goes to slot checks & 1, whose last use (check
+                // checks - 2) was waited for at check checks - 1
+                const int slot = checks++ & 1;
+                hipError_t e = hipMemcpyAsync(&pl->flag[slot], &ctl->s[it & 1].all_done, sizeof(int32_t),
+                                              hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipEventRecord(pl->ev[slot], s);
+                if (e == hipSuccess && pending >= 0) {
+                    e = hipEventSynchronize(pl->ev[pending]);
+                    done = e == hipSuccess && pl->flag[pending] != 0;
+                }
+                if (e != hipSuccess) return e;
+                pending = slot;
+            }
             if (done) break;
         }
     }
