@@ -425,7 +425,7 @@ SolveLayout solve_layout(const rw_solve_params& p, int64_t n_bricks, int64_t n_v
     if (need_x64 && !x64) bytes = L.off_x64 + L.nv * sizeof(double);
     L.ws_bytes = up256(std::max<size_t>(bytes, 256));
     L.state_bytes = up256((size_t)n_bricks * sizeof(rwk::BoxState));
-    L.tickets_off = up256(L.state_bytes + rwk::domain_scratch_bytes());
+    L.tickets_off = up256(L.state_bytes + rwk::domain_scratch_bytes(pp.n_dom));
     L.aux_bytes = L.tickets_off + kTicketBytes;
     L.list_bytes = up256(std::max<size_t>((size_t)n_bricks * sizeof(rwk::BrickDev), 64));
     L.wts_bytes = up256((size_t)pp.wts_elems * sizeof(float));
@@ -1010,15 +1010,15 @@ int rw_solve_bricks_adjoint(rw_ctx* ctx, const rw_solve_params* params, int64_t 
     if (!lambda) bytes += nv * sizeof(float);
     hipError_t e = grow(ctx, &ctx->ws, &ctx->ws_bytes, std::max<size_t>(bytes, 256), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint workspace");
-    const size_t state_bytes = ((size_t)n_bricks * sizeof(rwk::BoxState) + 255) & ~size_t(255);
-    const size_t part_bytes = ((size_t)n_bricks * sizeof(double) + 255) & ~size_t(255);
-    const size_t tickets_off = up256(state_bytes + part_bytes + rwk::domain_scratch_bytes());
-    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, tickets_off + kTicketBytes, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint partials");
     PlanChoice pc;
     const rw_solve_params pe = resolve_schedule(ctx, *params, n_bricks, bricks, &pc);
     PlanScope pls(ctx, pc);
     rwk::PlanePlan pp = plan_planes(ctx, &list, 1, false, pe.schedule);
+    const size_t state_bytes = ((size_t)n_bricks * sizeof(rwk::BoxState) + 255) & ~size_t(255);
+    const size_t part_bytes = ((size_t)n_bricks * sizeof(double) + 255) & ~size_t(255);
+    const size_t tickets_off = up256(state_bytes + part_bytes + rwk::domain_scratch_bytes(pp.n_dom));
+    e = grow(ctx, &ctx->aux, &ctx->aux_bytes, tickets_off + kTicketBytes, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "allocating adjoint partials");
     rc = attach_side_streams(ctx, &pp);
     if (rc) return rc;
     rc = upload_list(ctx, list, s);

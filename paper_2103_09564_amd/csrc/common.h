@@ -259,31 +259,33 @@ size_t plane_lds_bytes(int nrhs, bool fp64, int cols);
 
 // Multi-workgroup domain solver (domain.hip).  A box goes there when it has at
 // least kDomMinVox voxels and a plane too wide for the LDS march, or at least
-// kDomBigVox voxels; at most kDomMaxBoxes boxes per call (the largest).
+// kDomBigVox voxels; at most kDomMaxBoxes boxes per call (the largest), all of
+// them in each launch.
 constexpr int64_t kDomMinVox = int64_t(1) << 16;
 constexpr int64_t kDomBigVox = int64_t(1) << 20;
-constexpr int kDomMaxBoxes = 16;
-size_t domain_scratch_bytes();
+constexpr int kDomMaxBoxes = 64;
+size_t domain_scratch_bytes(int64_t n_dom);  // scalar state and partials of n_dom boxes
 void domain_bind(SolveArgs& a, void* scratch);
 // Frees the hierarchy's cached level buffers of device `dev` (hier.hip; the
 // current device must be dev).
 void pool_trim(int dev);
-// The phases of the per-box solve for box ib of the launch list (bd: its host
-// descriptor), each over many workgroups.  domain_pcg runs PCG from the state
-// the init or check left, into xt (corr = 0: main solve, 1: correction
-// solve); it synchronises s every few iterations to test for convergence.
+// The phases of the per-box solve for the domain boxes [0, nd) of the launch
+// list (host: their host descriptors), each over many workgroups per box.
+// domain_pcg runs PCG from the state the init or check left, into xt
+// (corr = 0: main solve, 1: correction solve), until every box is done; it
+// reads a done flag every few iterations.
 template <typename T, int R>
-hipError_t domain_init(const SolveArgs& a, int ib, const BrickDev& bd, hipStream_t s);
+hipError_t domain_init(const SolveArgs& a, int nd, const BrickDev* host, hipStream_t s);
 template <typename T, int R, typename XT>
-hipError_t domain_pcg(const SolveArgs& a, int ib, const BrickDev& bd, XT* xt, int corr, hipStream_t s);
+hipError_t domain_pcg(const SolveArgs& a, int nd, const BrickDev* host, XT* xt, int corr, hipStream_t s);
 template <int R, bool kRefine64>
-hipError_t domain_check(const SolveArgs& a, int ib, const BrickDev& bd, int may_refine, hipStream_t s);
+hipError_t domain_check(const SolveArgs& a, int nd, const BrickDev* host, int may_refine, hipStream_t s);
 template <int R, bool kRefine64>
-hipError_t domain_apply(const SolveArgs& a, int ib, const BrickDev& bd, hipStream_t s);
+hipError_t domain_apply(const SolveArgs& a, int nd, const BrickDev* host, hipStream_t s);
 template <int R>
-hipError_t domain_copy64(const SolveArgs& a, int ib, const BrickDev& bd, int to64, hipStream_t s);
+hipError_t domain_copy64(const SolveArgs& a, int nd, const BrickDev* host, int to64, hipStream_t s);
 template <int R>
-hipError_t domain_finish64(const SolveArgs& a, int ib, const BrickDev& bd, hipStream_t s);
+hipError_t domain_finish64(const SolveArgs& a, int nd, const BrickDev* host, hipStream_t s);
 int plane_cols(int max_plane);
 int plane_max(int cols);
 

@@ -1,8 +1,11 @@
-// Multi-workgroup solve of one large box (a single domain such as the
-// coarsest pyramid level or a plain volume solve): every phase of the per-box
-// solve (Dirichlet init, Jacobi-PCG, FP64 true residual, correction set-up and
-// apply; Section III-B system, Section V solver) spread over up to kDomMaxWG
-// workgroups of kDomThreads threads (grid-stride over the box's voxels).
+// Multi-workgroup solve of large boxes (single domains such as the coarsest
+// pyramid level or a plain volume solve, and the boxes of large bricks):
+// every phase of the per-box solve (Dirichlet init, Jacobi-PCG, FP64 true
+// residual, correction set-up and apply; Section III-B system, Section V
+// solver) spread over up to kDomMaxWG workgroups of kDomThreads threads per
+// box (grid-stride over the box's voxels).  The domain boxes of a call (the
+// first nd of its list) share each launch: box j takes the next dom_wgs
+// workgroups, and has its own scalar state, ticket and partials.
 //
 // Each voxel's stencil is evaluated branch-free: out-of-box neighbours are
 // replaced by the voxel itself with weight 0, so all loads of a voxel are in
@@ -10,7 +13,7 @@
 // to finish (ticket counter) adds them in workgroup order and writes the
 // scalars, so every result is deterministic.
 //
-// One CG iteration is two launches:
+// One CG iteration is two launches (for every domain box of the call):
 //   A(n): p_new = z + beta_n p_old, partial sigma = p_new . L_UU p_new;
 //         last workgroup: alpha_n = rho_n / sigma (breakdown test)
 //   B(n): x += alpha p, r -= alpha L_UU p, z = r / d, partial r.z, ||r||^2;
@@ -43,14 +46,36 @@ struct DomCtl {
     int32_t pad[3];
 };
 
-// Scratch layout: DomCtl (padded to 512 B), partials [kDomMaxWG][kDomPart].
-size_t domain_scratch_bytes() { return 512 + (size_t)kDomMaxWG * kDomPart * sizeof(double); }
+// Scratch layout: a table (the workgroup prefix of each domain box in the two
+// launch kinds, int32 [2][kDomMaxBoxes + 1], and the every-box-done word at
+// byte 2048) in its first 4 KB, then per domain box DomCtl (padded to
+// 512 B) and partials [kDomMaxWG][kDomPart].
+constexpr size_t kDomTableBytes = 4096;
+constexpr size_t kDomDoneOff = 2048;
+constexpr size_t kDomBoxBytes = 512 + (size_t)kDomMaxWG * kDomPart * sizeof(double);
+size_t domain_scratch_bytes(int64_t n_dom) {
+    return kDomTableBytes + (size_t)std::max<int64_t>(n_dom, 1) * kDomBoxBytes;
+}
+static_assert(2 * (kDomMaxBoxes + 1) * sizeof(int32_t) <= kDomDoneOff, "domain table size");
+__host__ __device__ inline DomCtl* dom_ctl(void* dom, int j) {
+    return (DomCtl*)((char*)dom + kDomTableBytes + (size_t)j * kDomBoxBytes);
+}
 
 void domain_bind(SolveArgs& a, void* scratch) {
     static_assert(sizeof(DomCtl) <= 512, "DomCtl exceeds its scratch");
-    char* c = (char*)scratch;
-    a.dom = c;
-    a.dom_part = (double*)(c + 512);
+    a.dom = scratch;
+    a.dom_part = nullptr;  // (per box: after its DomCtl)
+}
+
+// Workgroups of a domain box in a launch: kind 0 (the phases) one voxel per
+// thread and pass, kind 1 (the PCG launches) kVpt.
+constexpr int kDomPcgWG = 1024;
+constexpr int kVpt = 2;
+__host__ __device__ inline int dom_wgs(int64_t nv, int kind) {
+    const int64_t per = kind ? (int64_t)kVpt * kDomThreads : (int64_t)kDomThreads;
+    const int64_t cap = kind ? kDomPcgWG : kDomMaxWG;
+    const int64_t g = (nv + per - 1) / per;
+    return (int)(g < 1 ? 1 : g > cap ? cap : g);
 }
 
 namespace {
@@ -121,6 +146,27 @@ __device__ __forceinline__ T stencil_weights(const float* __restrict__ g, int v,
     return d;
 }
 
+// This workgroup's share of a launch over the domain boxes [0, nd): box ib,
+// workgroup w of the box's G, the box's scalar state and partials.
+struct DomView {
+    int ib, w, G;
+    DomCtl* ctl;
+    double* part;
+};
+// Every wave reads the launch's prefix table (lane l: box l's first
+// workgroup) and takes the last box that starts at or before this workgroup.
+__device__ __forceinline__ DomView dom_view(const SolveArgs& a, int nd, int kind) {
+    const int32_t* pre = (const int32_t*)a.dom + kind * (kDomMaxBoxes + 1);
+    const int lane = threadIdx.x & 63, b = (int)blockIdx.x;
+    const int lo = lane < nd ? pre[lane] : 0x7fffffff;
+    const int hi = lane < nd ? pre[lane + 1] : 0;
+    const unsigned long long m = __ballot(lo <= b);  // bit 0 always set (pre[0] = 0)
+    const int j = 63 - __clzll(m);
+    const int l0 = __shfl(lo, j, 64), l1 = __shfl(hi, j, 64);
+    DomCtl* c = dom_ctl(a.dom, j);
+    return DomView{j, b - l0, l1 - l0, c, (double*)((char*)c + 512)};
+}
+
 template <int N>
 __device__ __forceinline__ void wg_sum(double (&v)[N], double* red) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -149,15 +195,17 @@ __device__ __forceinline__ void wg_sum(double (&v)[N], double* red) {
 // Store this workgroup's sums, take a ticket; in the last workgroup to arrive
 // return true with the sums over all workgroups (fixed order) in v.
 template <int N>
-__device__ __forceinline__ bool last_wg_sum(double (&v)[N], DomCtl* ctl, double* part, double* red) {
+__device__ __forceinline__ bool last_wg_sum(double (&v)[N], const DomView& dv, double* red) {
     __shared__ int last;
+    DomCtl* ctl = dv.ctl;
+    double* part = dv.part;
     wg_sum<N>(v, red);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < N; ++k) part[blockIdx.x * kDomPart + k] = v[k];
+        for (int k = 0; k < N; ++k) part[dv.w * kDomPart + k] = v[k];
         __threadfence();
         const uint32_t t = atomicAdd(&ctl->ticket, 1u);
-        last = t == gridDim.x - 1 ? 1 : 0;
+        last = t == (uint32_t)dv.G - 1 ? 1 : 0;
     }
     __syncthreads();
     if (!last) return false;
@@ -166,7 +214,7 @@ __device__ __forceinline__ bool last_wg_sum(double (&v)[N], DomCtl* ctl, double*
 #pragma unroll
     for (int k = 0; k < N; ++k) s[k] = 0.0;
     // thread t adds workgroups t, t + 256, ... in order; then the fixed tree of wg_sum
-    for (int w = threadIdx.x; w < (int)gridDim.x; w += kDomThreads) {
+    for (int w = threadIdx.x; w < dv.G; w += kDomThreads) {
 #pragma unroll
         for (int k = 0; k < N; ++k) s[k] += __builtin_nontemporal_load(&part[w * kDomPart + k]);
     }
@@ -178,13 +226,14 @@ __device__ __forceinline__ bool last_wg_sum(double (&v)[N], DomCtl* ctl, double*
 }
 
 // Ticket without sums: true in the last workgroup to arrive.
-__device__ __forceinline__ bool last_wg(DomCtl* ctl) {
+__device__ __forceinline__ bool last_wg(const DomView& dv) {
     __shared__ int last;
+    DomCtl* ctl = dv.ctl;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
         const uint32_t t = atomicAdd(&ctl->ticket, 1u);
-        last = t == gridDim.x - 1 ? 1 : 0;
+        last = t == (uint32_t)dv.G - 1 ? 1 : 0;
     }
     __syncthreads();
     if (!last) return false;
@@ -195,7 +244,7 @@ __device__ __forceinline__ bool last_wg(DomCtl* ctl) {
 
 __device__ __forceinline__ bool fin(double v) { return isfinite(v); }
 
-#define RW_DOM_LOOP(v, nv) for (int v = blockIdx.x * kDomThreads + threadIdx.x; v < (nv); v += gridDim.x * kDomThreads)
+#define RW_DOM_LOOP(dv, v, nv) for (int v = (dv).w * kDomThreads + threadIdx.x; v < (nv); v += (dv).G * kDomThreads)
 
 }  // namespace
 
@@ -205,8 +254,10 @@ __device__ __forceinline__ bool fin(double v) { return isfinite(v); }
 // into its FP64 solution buffer.
 // ---------------------------------------------------------------------------
 template <typename T, int R>
-__global__ __launch_bounds__(kDomThreads) void k_dinit(SolveArgs a, int ib) {
+__global__ __launch_bounds__(kDomThreads) void k_dinit(SolveArgs a, int nd) {
     __shared__ double red[kDomWaves * kDomPart];
+    const DomView dv = dom_view(a, nd, 0);
+    const int ib = dv.ib;
     const BrickDev b = a.bricks[ib];
     const int nv = b.nx * b.ny * b.nz;
     double s[3 * R + 2];
@@ -220,7 +271,7 @@ __global__ __launch_bounds__(kDomThreads) void k_dinit(SolveArgs a, int ib) {
     T* z = (T*)a.z + b.off * R;
     T* p0 = (T*)a.p0 + b.off * R;
     T* p1 = (T*)a.p1 + b.off * R;
-    RW_DOM_LOOP(v, nv) {
+    RW_DOM_LOOP(dv, v, nv) {
         if (sizeof(T) == 8) {
             double* xt = (double*)a.xt + b.off * R;
 #pragma unroll
@@ -271,8 +322,7 @@ __global__ __launch_bounds__(kDomThreads) void k_dinit(SolveArgs a, int ib) {
             s[3 * R + 1] += 1.0;
         }
     }
-    DomCtl* ctl = (DomCtl*)a.dom;
-    if (!last_wg_sum<3 * R + 2>(s, ctl, a.dom_part, red)) return;
+    if (!last_wg_sum<3 * R + 2>(s, dv, red)) return;
     if (threadIdx.x == 0) {
         BoxState& st = a.state[ib];
         const double nU = s[3 * R], nM = s[3 * R + 1];
@@ -301,7 +351,9 @@ __global__ __launch_bounds__(kDomThreads) void k_dinit(SolveArgs a, int ib) {
 
 // Right-hand sides with ||b|| = 0: x_U = r = z = 0 for them.
 template <typename T, int R>
-__global__ __launch_bounds__(kDomThreads) void k_dzero(SolveArgs a, int ib) {
+__global__ __launch_bounds__(kDomThreads) void k_dzero(SolveArgs a, int nd) {
+    const DomView dv = dom_view(a, nd, 0);
+    const int ib = dv.ib;
     const BoxState& st = a.state[ib];
     if (!(st.nM > 0.0 && st.nU > 0.0)) return;
     bool any = false;
@@ -313,7 +365,7 @@ __global__ __launch_bounds__(kDomThreads) void k_dzero(SolveArgs a, int ib) {
     T* xt = (sizeof(T) == 8 ? (T*)a.xt : (T*)a.x) + b.off * R;
     T* r = (T*)a.r + b.off * R;
     T* z = (T*)a.z + b.off * R;
-    RW_DOM_LOOP(v, nv) {
+    RW_DOM_LOOP(dv, v, nv) {
         if (a.mask[b.off + v] != 0) continue;
 #pragma unroll
         for (int k = 0; k < R; ++k)
@@ -329,9 +381,10 @@ __global__ __launch_bounds__(kDomThreads) void k_dzero(SolveArgs a, int ib) {
 // Jacobi-PCG
 // ---------------------------------------------------------------------------
 
-// Ticket counter to 0 (device memory is not cleared when allocated).
+// Ticket counters to 0 (device memory is not cleared when allocated); one
+// workgroup per domain box.
 __global__ void k_dreset(SolveArgs a) {
-    if (threadIdx.x == 0) ((DomCtl*)a.dom)->ticket = 0u;
+    if (threadIdx.x == 0) dom_ctl(a.dom, (int)blockIdx.x)->ticket = 0u;
 }
 
 // The PCG kernels spread a box over at most kDomPcgWG workgroups, kVpt voxels
@@ -339,9 +392,6 @@ __global__ void k_dreset(SolveArgs a) {
 // per-workgroup partials in workgroup order (every workgroup gets the same
 // scalars; kernel boundaries make the partials visible); workgroup 0 records
 // the scalar state.
-constexpr int kDomPcgWG = 1024;
-constexpr int kVpt = 2;
-
 // Sum of per-workgroup partials part[w * stride + k], w < G, k < N, in order.
 template <int N>
 __device__ __forceinline__ void sum_partials(const double* part, int stride, int G, double (&out)[N], double* red) {
@@ -357,16 +407,17 @@ __device__ __forceinline__ void sum_partials(const double* part, int stride, int
     for (int k = 0; k < N; ++k) out[k] = v[k];
 }
 
-// Slot layout of the PCG partials: A (sigma) [G][3], B (r.z, ||r||^2) [G][6].
-__device__ __forceinline__ double* part_a(const SolveArgs& a) { return a.dom_part; }
-__device__ __forceinline__ double* part_b(const SolveArgs& a) { return a.dom_part + kDomPcgWG * 3; }
+// Slot layout of a box's PCG partials: A (sigma) [G][3], B (r.z, ||r||^2) [G][6].
+__device__ __forceinline__ double* part_a(const DomView& dv) { return dv.part; }
+__device__ __forceinline__ double* part_b(const DomView& dv) { return dv.part + kDomPcgWG * 3; }
 
 // State for A(0) (slot 1, and slot 0) from the box state (init or check).
 template <int R>
-__global__ void k_dstart(SolveArgs a, int ib) {
+__global__ void k_dstart(SolveArgs a) {
     if (threadIdx.x != 0) return;
+    const int ib = (int)blockIdx.x;
     const BoxState& st = a.state[ib];
-    DomCtl* ctl = (DomCtl*)a.dom;
+    DomCtl* ctl = dom_ctl(a.dom, ib);
     DomState s{};
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -383,14 +434,16 @@ __global__ void k_dstart(SolveArgs a, int ib) {
 // start state), convergence test; then p_new = z + beta p_old and the
 // partials of sigma = p_new . L_UU p_new.
 template <typename T, int R>
-__global__ __launch_bounds__(kDomThreads) void k_dA(SolveArgs a, int ib, int it, double tol, int max_iter,
+__global__ __launch_bounds__(kDomThreads) void k_dA(SolveArgs a, int nd, int it, double tol, int max_iter,
                                                     const T* __restrict__ z, const T* __restrict__ pold,
                                                     T* __restrict__ pnew) {
     __shared__ double red[kDomWaves * kDomPart];
-    DomCtl* ctl = (DomCtl*)a.dom;
+    const DomView dv = dom_view(a, nd, 1);
+    const int ib = dv.ib;
+    DomCtl* ctl = dv.ctl;
     const volatile DomState* prev = &ctl->s[(it + 1) & 1];
     DomState* out = &ctl->s[it & 1];
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool lead = dv.w == 0 && threadIdx.x == 0;
     if (prev->all_done) {
         if (lead) *out = *(const DomState*)prev;
         return;
@@ -404,7 +457,7 @@ __global__ __launch_bounds__(kDomThreads) void k_dA(SolveArgs a, int ib, int it,
         }
     } else {
         double s2[2 * R];
-        sum_partials<2 * R>(part_b(a), 6, gridDim.x, s2, red);
+        sum_partials<2 * R>(part_b(dv), 6, dv.G, s2, red);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             rz[k] = s2[k];
@@ -454,8 +507,8 @@ __global__ __launch_bounds__(kDomThreads) void k_dA(SolveArgs a, int ib, int it,
     double sig[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) sig[k] = 0.0;
-    const int stride = gridDim.x * kDomThreads;
-    for (int v0 = blockIdx.x * kDomThreads + threadIdx.x; v0 < nv; v0 += kVpt * stride) {
+    const int stride = dv.G * kDomThreads;
+    for (int v0 = dv.w * kDomThreads + threadIdx.x; v0 < nv; v0 += kVpt * stride) {
         // all loads of the kVpt voxels first (clamped in-box indices), then compute
         int vv[kVpt];
         bool use[kVpt];
@@ -493,20 +546,22 @@ __global__ __launch_bounds__(kDomThreads) void k_dA(SolveArgs a, int ib, int it,
     wg_sum<R>(sig, red);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < R; ++k) part_a(a)[blockIdx.x * 3 + k] = sig[k];
+        for (int k = 0; k < R; ++k) part_a(dv)[dv.w * 3 + k] = sig[k];
     }
 }
 
 // B(it): alpha from A(it)'s partials (breakdown test); x += alpha p,
 // r -= alpha L_UU p, z = r / d and the partials of r.z, ||r||^2.
 template <typename T, int R, typename XT>
-__global__ __launch_bounds__(kDomThreads) void k_dB(SolveArgs a, int ib, int it, XT* xt, const T* __restrict__ p) {
+__global__ __launch_bounds__(kDomThreads) void k_dB(SolveArgs a, int nd, int it, XT* xt, const T* __restrict__ p) {
     __shared__ double red[kDomWaves * kDomPart];
-    DomCtl* ctl = (DomCtl*)a.dom;
+    const DomView dv = dom_view(a, nd, 1);
+    const int ib = dv.ib;
+    DomCtl* ctl = dv.ctl;
     const volatile DomState* cur = &ctl->s[it & 1];
     if (cur->all_done) return;
     double sig[R];
-    sum_partials<R>(part_a(a), 3, gridDim.x, sig, red);
+    sum_partials<R>(part_a(dv), 3, dv.G, sig, red);
     T al[R];
     bool bad = false;
 #pragma unroll
@@ -518,7 +573,7 @@ __global__ __launch_bounds__(kDomThreads) void k_dB(SolveArgs a, int ib, int it,
     }
     if (bad) {
         // breakdown: stop with the current iterate
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (dv.w == 0 && threadIdx.x == 0) {
             DomState s = *(const DomState*)cur;
             s.flags |= 1;
             s.all_done = 1;
@@ -539,8 +594,8 @@ __global__ __launch_bounds__(kDomThreads) void k_dB(SolveArgs a, int ib, int it,
     double arz[R], arr[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) arz[k] = arr[k] = 0.0;
-    const int stride = gridDim.x * kDomThreads;
-    for (int v0 = blockIdx.x * kDomThreads + threadIdx.x; v0 < nv; v0 += kVpt * stride) {
+    const int stride = dv.G * kDomThreads;
+    for (int v0 = dv.w * kDomThreads + threadIdx.x; v0 < nv; v0 += kVpt * stride) {
         int vv[kVpt];
         bool use[kVpt];
         Nb n[kVpt];
@@ -592,15 +647,16 @@ __global__ __launch_bounds__(kDomThreads) void k_dB(SolveArgs a, int ib, int it,
     wg_sum<2 * R>(s2, red);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < 2 * R; ++k) part_b(a)[blockIdx.x * 6 + k] = s2[k];
+        for (int k = 0; k < 2 * R; ++k) part_b(dv)[dv.w * 6 + k] = s2[k];
     }
 }
 
 // Final scalars into the box state (as the per-box PCG kernel leaves it).
 template <int R>
-__global__ void k_dend(SolveArgs a, int ib, int slot, int corr) {
+__global__ void k_dend(SolveArgs a, int slot, int corr) {
     if (threadIdx.x != 0) return;
-    const DomState s = ((DomCtl*)a.dom)->s[slot];
+    const int ib = (int)blockIdx.x;
+    const DomState s = dom_ctl(a.dom, ib)->s[slot];
     BoxState& st = a.state[ib];
     if (!st.active) return;
 #pragma unroll
@@ -630,9 +686,11 @@ __global__ void k_dend(SolveArgs a, int ib, int slot, int corr) {
 // last workgroup stores the true relative residual.
 // ---------------------------------------------------------------------------
 template <int R, typename XS, int kMode>
-__global__ __launch_bounds__(kDomThreads) void k_dresid(SolveArgs a, int ib, const XS* __restrict__ xs,
+__global__ __launch_bounds__(kDomThreads) void k_dresid(SolveArgs a, int nd, const XS* __restrict__ xs,
                                                         int may_refine, int refine64) {
     __shared__ double red[kDomWaves * kDomPart];
+    const DomView dv = dom_view(a, nd, 0);
+    const int ib = dv.ib;
     const BoxState& st0 = a.state[ib];
     const bool solved = st0.nM > 0.0 && st0.nU > 0.0 && st0.status != RW_ST_NONFINITE;
     const BrickDev b = a.bricks[ib];
@@ -640,21 +698,21 @@ __global__ __launch_bounds__(kDomThreads) void k_dresid(SolveArgs a, int ib, con
     const uint8_t* m = a.mask + b.off;
     const XS* x = xs + b.off * R;
     if (kMode == 1) {
-        RW_DOM_LOOP(v, nv) {
+        RW_DOM_LOOP(dv, v, nv) {
             if (m[v] != 0) continue;
 #pragma unroll
             for (int k = 0; k < R; ++k) a.x[(b.off + v) * R + k] = (float)x[v * R + k];
         }
     }
     if (!solved) {
-        if (kMode == 0 && blockIdx.x == 0 && threadIdx.x == 0) a.state[ib].active = 0;
+        if (kMode == 0 && dv.w == 0 && threadIdx.x == 0) a.state[ib].active = 0;
         return;
     }
     double q[2 * R];
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) q[k] = 0.0;
     const DWeight<double> W(a.beta, a.eps);
-    RW_DOM_LOOP(v, nv) {
+    RW_DOM_LOOP(dv, v, nv) {
         if (m[v] != 0) continue;
         const Nb n = neighbours(v, b.nx, b.ny, b.nz);
         bool sm[6];
@@ -683,7 +741,7 @@ __global__ __launch_bounds__(kDomThreads) void k_dresid(SolveArgs a, int ib, con
             if (kMode == 0) ((float*)a.r)[(b.off + v) * R + k] = (float)rv;
         }
     }
-    if (!last_wg_sum<2 * R>(q, (DomCtl*)a.dom, a.dom_part, red)) return;
+    if (!last_wg_sum<2 * R>(q, dv, red)) return;
     if (threadIdx.x != 0) return;
     BoxState& st = a.state[ib];
     double tr = 0.0;
@@ -706,8 +764,10 @@ __global__ __launch_bounds__(kDomThreads) void k_dresid(SolveArgs a, int ib, con
 // Correction system L_UU d = r64 (r holds r64 in FP32): z = r/d, p = 0, d = 0;
 // seeded voxels all 0; ||b||^2 = ||r||^2.  Only when the check set `active`.
 template <int R>
-__global__ __launch_bounds__(kDomThreads) void k_dexplicit(SolveArgs a, int ib) {
+__global__ __launch_bounds__(kDomThreads) void k_dexplicit(SolveArgs a, int nd) {
     __shared__ double red[kDomWaves * kDomPart];
+    const DomView dv = dom_view(a, nd, 0);
+    const int ib = dv.ib;
     if (!a.state[ib].active) return;
     const BrickDev b = a.bricks[ib];
     const int nv = b.nx * b.ny * b.nz;
@@ -720,7 +780,7 @@ __global__ __launch_bounds__(kDomThreads) void k_dexplicit(SolveArgs a, int ib) 
     float* p0 = (float*)a.p0 + b.off * R;
     float* p1 = (float*)a.p1 + b.off * R;
     float* dc = a.dcorr + b.off * R;
-    RW_DOM_LOOP(v, nv) {
+    RW_DOM_LOOP(dv, v, nv) {
         if (a.mask[b.off + v] == 0) {
             const Nb n = neighbours(v, b.nx, b.ny, b.nz);
             float w[6];
@@ -747,7 +807,7 @@ __global__ __launch_bounds__(kDomThreads) void k_dexplicit(SolveArgs a, int ib) 
             }
         }
     }
-    if (!last_wg_sum<2 * R>(e, (DomCtl*)a.dom, a.dom_part, red)) return;
+    if (!last_wg_sum<2 * R>(e, dv, red)) return;
     if (threadIdx.x == 0) {
         BoxState& st = a.state[ib];
 #pragma unroll
@@ -760,11 +820,13 @@ __global__ __launch_bounds__(kDomThreads) void k_dexplicit(SolveArgs a, int ib) 
 
 // x (MIXED) or x64 (MIXED_REFINE) += d on U when a correction is pending.
 template <int R, bool kRefine64>
-__global__ __launch_bounds__(kDomThreads) void k_dapply(SolveArgs a, int ib) {
+__global__ __launch_bounds__(kDomThreads) void k_dapply(SolveArgs a, int nd) {
+    const DomView dv = dom_view(a, nd, 0);
+    const int ib = dv.ib;
     if (!a.state[ib].pending) return;
     const BrickDev b = a.bricks[ib];
     const int nv = b.nx * b.ny * b.nz;
-    RW_DOM_LOOP(v, nv) {
+    RW_DOM_LOOP(dv, v, nv) {
         if (a.mask[b.off + v] != 0) continue;
         const int64_t o = (b.off + v) * R;
 #pragma unroll
@@ -773,7 +835,7 @@ __global__ __launch_bounds__(kDomThreads) void k_dapply(SolveArgs a, int ib) {
             else a.x[o + k] += a.dcorr[o + k];
         }
     }
-    if (!last_wg((DomCtl*)a.dom)) return;
+    if (!last_wg(dv)) return;
     if (threadIdx.x == 0) {
         BoxState& st = a.state[ib];
         st.refine_steps += 1;
@@ -783,10 +845,11 @@ __global__ __launch_bounds__(kDomThreads) void k_dapply(SolveArgs a, int ib) {
 
 // to64: x64 = x on every voxel; else x = (float)x64 on U.
 template <int R>
-__global__ __launch_bounds__(kDomThreads) void k_dcopy64(SolveArgs a, int ib, int to64) {
-    const BrickDev b = a.bricks[ib];
+__global__ __launch_bounds__(kDomThreads) void k_dcopy64(SolveArgs a, int nd, int to64) {
+    const DomView dv = dom_view(a, nd, 0);
+    const BrickDev b = a.bricks[dv.ib];
     const int nv = b.nx * b.ny * b.nz;
-    RW_DOM_LOOP(v, nv) {
+    RW_DOM_LOOP(dv, v, nv) {
         const int64_t o = (b.off + v) * R;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -800,17 +863,45 @@ __global__ __launch_bounds__(kDomThreads) void k_dcopy64(SolveArgs a, int ib, in
 // Host side
 // ---------------------------------------------------------------------------
 
-static unsigned dom_grid(const BrickDev& bd) {
-    const int64_t nv = (int64_t)bd.nx * bd.ny * bd.nz;
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kDomMaxWG, (nv + kDomThreads - 1) / kDomThreads));
+// Workgroups of a launch over the domain boxes [0, nd) (host copies in host).
+static unsigned dom_total(const BrickDev* host, int nd, int kind) {
+    int64_t g = 0;
+    for (int j = 0; j < nd; ++j) g += dom_wgs((int64_t)host[j].nx * host[j].ny * host[j].nz, kind);
+    return (unsigned)std::max<int64_t>(g, 1);
+}
+
+// The every-box-done word: 1 when every domain box's state in `slot` is done.
+__global__ void k_dall(SolveArgs a, int nd, int slot) {
+    int all = 1;
+    for (int j = threadIdx.x; j < nd; j += blockDim.x) all &= dom_ctl(a.dom, j)->s[slot].all_done != 0 ? 1 : 0;
+    all = __syncthreads_and(all);
+    if (threadIdx.x == 0) *(int32_t*)((char*)a.dom + kDomDoneOff) = all;
+}
+
+// The prefix table of the domain boxes [0, nd) for both launch kinds (one
+// thread), as the host sums them in dom_total.
+__global__ void k_dtable(SolveArgs a, int nd) {
+    if (threadIdx.x != 0) return;
+    int32_t* pre = (int32_t*)a.dom;
+    for (int kind = 0; kind < 2; ++kind) {
+        int32_t acc = 0;
+        pre[kind * (kDomMaxBoxes + 1)] = 0;
+        for (int j = 0; j < nd; ++j) {
+            const BrickDev b = a.bricks[j];
+            acc += dom_wgs((int64_t)b.nx * b.ny * b.nz, kind);
+            pre[kind * (kDomMaxBoxes + 1) + j + 1] = acc;
+        }
+    }
 }
 
 template <typename T, int R>
-hipError_t domain_init(const SolveArgs& a, int ib, const BrickDev& bd, hipStream_t s) {
-    const unsigned G = dom_grid(bd);
-    hipLaunchKernelGGL(k_dreset, dim3(1), dim3(64), 0, s, a);
-    hipLaunchKernelGGL((k_dinit<T, R>), dim3(G), dim3(kDomThreads), 0, s, a, ib);
-    hipLaunchKernelGGL((k_dzero<T, R>), dim3(G), dim3(kDomThreads), 0, s, a, ib);
+hipError_t domain_init(const SolveArgs& a, int nd, const BrickDev* host, hipStream_t s) {
+    if (nd <= 0) return hipSuccess;
+    const unsigned G = dom_total(host, nd, 0);
+    hipLaunchKernelGGL(k_dtable, dim3(1), dim3(64), 0, s, a, nd);
+    hipLaunchKernelGGL(k_dreset, dim3((unsigned)nd), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_dinit<T, R>), dim3(G), dim3(kDomThreads), 0, s, a, nd);
+    hipLaunchKernelGGL((k_dzero<T, R>), dim3(G), dim3(kDomThreads), 0, s, a, nd);
     return hipGetLastError();
 }
 
@@ -842,26 +933,28 @@ static DomPoll* dom_poll() {
 }
 
 template <typename T, int R, typename XT>
-hipError_t domain_pcg(const SolveArgs& a, int ib, const BrickDev& bd, XT* xt, int corr, hipStream_t s) {
-    const int64_t nv = (int64_t)bd.nx * bd.ny * bd.nz;
-    const unsigned G = (unsigned)std::max<int64_t>(
-        1, std::min<int64_t>(kDomPcgWG, (nv + kVpt * kDomThreads - 1) / (kVpt * kDomThreads)));
+hipError_t domain_pcg(const SolveArgs& a, int nd, const BrickDev* host, XT* xt, int corr, hipStream_t s) {
+    if (nd <= 0) return hipSuccess;
+    const unsigned G = dom_total(host, nd, 1);
     const double tol = corr ? a.inner_tol : a.tol;
     T* z = (T*)a.z;
     T* p0 = (T*)a.p0;
     T* p1 = (T*)a.p1;
-    DomCtl* ctl = (DomCtl*)a.dom;
-    hipLaunchKernelGGL(k_dstart<R>, dim3(1), dim3(64), 0, s, a, ib);
-    // The done flag is read after the first iteration and every `poll`
-    // iterations: copied into page-locked memory behind the launches, and
-    // waited for only after the next `poll` iterations are queued, so the
-    // device does not idle while the host reads it.  Iterations queued past
-    // the end are no-ops (A and B return at once when the state is done).
-    // Without the page-locked slots the flag is read synchronously.
+    int32_t* done_word = (int32_t*)((char*)a.dom + kDomDoneOff);
+    // (the table again: the adjoint's solve reaches this without the init)
+    hipLaunchKernelGGL(k_dtable, dim3(1), dim3(64), 0, s, a, nd);
+    hipLaunchKernelGGL(k_dstart<R>, dim3((unsigned)nd), dim3(64), 0, s, a);
+    // The done flag (every box done) is read after the first iteration and
+    // every `poll` iterations: copied into page-locked memory behind the
+    // launches, and waited for only after the next `poll` iterations are
+    // queued, so the device does not idle while the host reads it.
+    // Iterations queued past the end are no-ops (A and B return at once for a
+    // box whose state is done).  Without the page-locked slots the flag is
+    // read synchronously.
     DomPoll* pl = dom_poll();
-    auto finished = [&](int slot, bool* out) -> hipError_t {
+    auto finished = [&](bool* out) -> hipError_t {
         int32_t f = 0;
-        hipError_t e = hipMemcpyAsync(&f, &ctl->s[slot].all_done, sizeof(f), hipMemcpyDeviceToHost, s);
+        hipError_t e = hipMemcpyAsync(&f, done_word, sizeof(f), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         *out = f != 0;
         return e;
@@ -871,21 +964,22 @@ hipError_t domain_pcg(const SolveArgs& a, int ib, const BrickDev& bd, XT* xt, in
     for (;; ++it) {
         T* pold = (it & 1) ? p1 : p0;
         T* pnew = (it & 1) ? p0 : p1;
-        hipLaunchKernelGGL((k_dA<T, R>), dim3(G), dim3(kDomThreads), 0, s, a, ib, it, tol, a.max_iter, z, pold,
+        hipLaunchKernelGGL((k_dA<T, R>), dim3(G), dim3(kDomThreads), 0, s, a, nd, it, tol, a.max_iter, z, pold,
                            pnew);
         if (it >= a.max_iter) break;  // A(max_iter) records the final state
-        hipLaunchKernelGGL((k_dB<T, R, XT>), dim3(G), dim3(kDomThreads), 0, s, a, ib, it, xt, (const T*)pnew);
+        hipLaunchKernelGGL((k_dB<T, R, XT>), dim3(G), dim3(kDomThreads), 0, s, a, nd, it, xt, (const T*)pnew);
         if (it == 0 || (it + 1) % poll == 0) {
+            hipLaunchKernelGGL(k_dall, dim3(1), dim3(64), 0, s, a, nd, it & 1);
             bool done = false;
             if (!pl) {
-                hipError_t e = finished(it & 1, &done);
+                hipError_t e = finished(&done);
                 if (e != hipSuccess) return e;
             } else {
                 // check `checks` goes to slot checks & 1, whose last use (check
                 // checks - 2) was waited for at check checks - 1
                 const int slot = checks++ & 1;
-                hipError_t e = hipMemcpyAsync(&pl->flag[slot], &ctl->s[it & 1].all_done, sizeof(int32_t),
-                                              hipMemcpyDeviceToHost, s);
+                hipError_t e =
+                    hipMemcpyAsync(&pl->flag[slot], done_word, sizeof(int32_t), hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipEventRecord(pl->ev[slot], s);
                 if (e == hipSuccess && pending >= 0) {
                     e = hipEventSynchronize(pl->ev[pending]);
@@ -897,56 +991,60 @@ hipError_t domain_pcg(const SolveArgs& a, int ib, const BrickDev& bd, XT* xt, in
             if (done) break;
         }
     }
-    // slot it & 1 holds the final scalars (written by A(it), or carried there)
-    hipLaunchKernelGGL(k_dend<R>, dim3(1), dim3(64), 0, s, a, ib, it & 1, corr);
+    // slot it & 1 holds each box's final scalars (written by A(it), or carried there)
+    hipLaunchKernelGGL(k_dend<R>, dim3((unsigned)nd), dim3(64), 0, s, a, it & 1, corr);
     return hipGetLastError();
 }
 
 template <int R, bool kRefine64>
-hipError_t domain_check(const SolveArgs& a, int ib, const BrickDev& bd, int may_refine, hipStream_t s) {
-    const unsigned G = dom_grid(bd);
+hipError_t domain_check(const SolveArgs& a, int nd, const BrickDev* host, int may_refine, hipStream_t s) {
+    if (nd <= 0) return hipSuccess;
+    const unsigned G = dom_total(host, nd, 0);
     if (kRefine64)
-        hipLaunchKernelGGL((k_dresid<R, double, 0>), dim3(G), dim3(kDomThreads), 0, s, a, ib,
+        hipLaunchKernelGGL((k_dresid<R, double, 0>), dim3(G), dim3(kDomThreads), 0, s, a, nd,
                            (const double*)a.x64, may_refine, 1);
     else
-        hipLaunchKernelGGL((k_dresid<R, float, 0>), dim3(G), dim3(kDomThreads), 0, s, a, ib, (const float*)a.x,
+        hipLaunchKernelGGL((k_dresid<R, float, 0>), dim3(G), dim3(kDomThreads), 0, s, a, nd, (const float*)a.x,
                            may_refine, 0);
-    if (may_refine) hipLaunchKernelGGL((k_dexplicit<R>), dim3(G), dim3(kDomThreads), 0, s, a, ib);
+    if (may_refine) hipLaunchKernelGGL((k_dexplicit<R>), dim3(G), dim3(kDomThreads), 0, s, a, nd);
     return hipGetLastError();
 }
 
 template <int R, bool kRefine64>
-hipError_t domain_apply(const SolveArgs& a, int ib, const BrickDev& bd, hipStream_t s) {
-    hipLaunchKernelGGL((k_dapply<R, kRefine64>), dim3(dom_grid(bd)), dim3(kDomThreads), 0, s, a, ib);
+hipError_t domain_apply(const SolveArgs& a, int nd, const BrickDev* host, hipStream_t s) {
+    if (nd <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_dapply<R, kRefine64>), dim3(dom_total(host, nd, 0)), dim3(kDomThreads), 0, s, a, nd);
     return hipGetLastError();
 }
 
 template <int R>
-hipError_t domain_copy64(const SolveArgs& a, int ib, const BrickDev& bd, int to64, hipStream_t s) {
-    hipLaunchKernelGGL((k_dcopy64<R>), dim3(dom_grid(bd)), dim3(kDomThreads), 0, s, a, ib, to64);
+hipError_t domain_copy64(const SolveArgs& a, int nd, const BrickDev* host, int to64, hipStream_t s) {
+    if (nd <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_dcopy64<R>), dim3(dom_total(host, nd, 0)), dim3(kDomThreads), 0, s, a, nd, to64);
     return hipGetLastError();
 }
 
 template <int R>
-hipError_t domain_finish64(const SolveArgs& a, int ib, const BrickDev& bd, hipStream_t s) {
-    hipLaunchKernelGGL((k_dresid<R, double, 1>), dim3(dom_grid(bd)), dim3(kDomThreads), 0, s, a, ib,
+hipError_t domain_finish64(const SolveArgs& a, int nd, const BrickDev* host, hipStream_t s) {
+    if (nd <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_dresid<R, double, 1>), dim3(dom_total(host, nd, 0)), dim3(kDomThreads), 0, s, a, nd,
                        (const double*)a.xt, 0, 0);
     return hipGetLastError();
 }
 
-#define RW_DOM_INST_R(R)                                                                                    \
-    template hipError_t domain_init<float, R>(const SolveArgs&, int, const BrickDev&, hipStream_t);         \
-    template hipError_t domain_init<double, R>(const SolveArgs&, int, const BrickDev&, hipStream_t);        \
-    template hipError_t domain_pcg<float, R, float>(const SolveArgs&, int, const BrickDev&, float*, int,    \
-                                                    hipStream_t);                                           \
-    template hipError_t domain_pcg<double, R, double>(const SolveArgs&, int, const BrickDev&, double*, int, \
-                                                      hipStream_t);                                         \
-    template hipError_t domain_check<R, false>(const SolveArgs&, int, const BrickDev&, int, hipStream_t);   \
-    template hipError_t domain_check<R, true>(const SolveArgs&, int, const BrickDev&, int, hipStream_t);    \
-    template hipError_t domain_apply<R, false>(const SolveArgs&, int, const BrickDev&, hipStream_t);        \
-    template hipError_t domain_apply<R, true>(const SolveArgs&, int, const BrickDev&, hipStream_t);         \
-    template hipError_t domain_copy64<R>(const SolveArgs&, int, const BrickDev&, int, hipStream_t);         \
-    template hipError_t domain_finish64<R>(const SolveArgs&, int, const BrickDev&, hipStream_t);
+#define RW_DOM_INST_R(R)                                                                                     \
+    template hipError_t domain_init<float, R>(const SolveArgs&, int, const BrickDev*, hipStream_t);          \
+    template hipError_t domain_init<double, R>(const SolveArgs&, int, const BrickDev*, hipStream_t);         \
+    template hipError_t domain_pcg<float, R, float>(const SolveArgs&, int, const BrickDev*, float*, int,     \
+                                                    hipStream_t);                                            \
+    template hipError_t domain_pcg<double, R, double>(const SolveArgs&, int, const BrickDev*, double*, int,  \
+                                                      hipStream_t);                                          \
+    template hipError_t domain_check<R, false>(const SolveArgs&, int, const BrickDev*, int, hipStream_t);    \
+    template hipError_t domain_check<R, true>(const SolveArgs&, int, const BrickDev*, int, hipStream_t);     \
+    template hipError_t domain_apply<R, false>(const SolveArgs&, int, const BrickDev*, hipStream_t);         \
+    template hipError_t domain_apply<R, true>(const SolveArgs&, int, const BrickDev*, hipStream_t);          \
+    template hipError_t domain_copy64<R>(const SolveArgs&, int, const BrickDev*, int, hipStream_t);          \
+    template hipError_t domain_finish64<R>(const SolveArgs&, int, const BrickDev*, hipStream_t);
 RW_DOM_INST_R(1)
 RW_DOM_INST_R(2)
 RW_DOM_INST_R(3)

@@ -1554,7 +1554,7 @@ __global__ __launch_bounds__(kThreads) void k_sum_partials(const double* part, i
 template <typename T, int R, int C, typename XT>
 static hipError_t launch_pcg_plane(const SolveArgs& a, int64_t n, int64_t n_big, XT* xt, int corr, size_t lds,
                                    const PlanePlan& pp, hipStream_t s) {
-    for (int64_t i = 0; i < pp.n_dom; ++i) RW_TRY((domain_pcg<T, R, XT>(a, (int)i, pp.host[i], xt, corr, s)));
+    RW_TRY((domain_pcg<T, R, XT>(a, (int)pp.n_dom, pp.host, xt, corr, s)));
     const int64_t n_stream_end = std::min<int64_t>(n, pp.n_res);
     constexpr bool kRes = std::is_same<T, float>::value && std::is_same<XT, float>::value && R == 1;
     // streamed-weights resident launches share the streaming kernel's stream;
@@ -1673,7 +1673,7 @@ static hipError_t launch_mixed(const SolveArgs& a, int64_t n, const PlanePlan& p
     // main solve themselves; the init phase covers the others
     const int64_t n_init = R == 1 ? std::max<int64_t>(pp.n_res, nd) : n;
     if (n_init > nd) hipLaunchKernelGGL((k_init<float, R>), dim3((unsigned)(n_init - nd)), blk, 0, s, a, nd);
-    for (int i = 0; i < nd; ++i) RW_TRY((domain_init<float, R>(a, i, pp.host[i], s)));
+    RW_TRY((domain_init<float, R>(a, nd, pp.host, s)));
     if (ev) RW_TRY(hipEventRecord(ev[0], s));
     SolveArgs am = a;
     am.fused_init = 1;
@@ -1684,16 +1684,15 @@ static hipError_t launch_mixed(const SolveArgs& a, int64_t n, const PlanePlan& p
     if (ev) RW_TRY(hipEventRecord(ev[1], s));
     if (r64) {
         if (rest) hipLaunchKernelGGL((k_copy64<R>), grid, blk, 0, s, a, 1, nd);
-        for (int i = 0; i < nd; ++i) RW_TRY(domain_copy64<R>(a, i, pp.host[i], 1, s));
+        RW_TRY(domain_copy64<R>(a, nd, pp.host, 1, s));
     }
     auto check = [&](int may_refine) -> hipError_t {
         if (rest) {
             if (r64) hipLaunchKernelGGL((k_check<R, true>), grid, blk, 0, s, a, may_refine, nd);
             else hipLaunchKernelGGL((k_check<R, false>), grid, blk, 0, s, a, may_refine, nd);
         }
-        for (int i = 0; i < nd; ++i)
-            RW_TRY(r64 ? domain_check<R, true>(a, i, pp.host[i], may_refine, s)
-                       : domain_check<R, false>(a, i, pp.host[i], may_refine, s));
+        RW_TRY(r64 ? domain_check<R, true>(a, nd, pp.host, may_refine, s)
+                   : domain_check<R, false>(a, nd, pp.host, may_refine, s));
         return hipGetLastError();
     };
     for (int step = 0; step < a.refine_max; ++step) {
@@ -1703,17 +1702,16 @@ static hipError_t launch_mixed(const SolveArgs& a, int64_t n, const PlanePlan& p
             if (r64) hipLaunchKernelGGL((k_apply<R, true>), grid, blk, 0, s, a, nd);
             else hipLaunchKernelGGL((k_apply<R, false>), grid, blk, 0, s, a, nd);
         }
-        for (int i = 0; i < nd; ++i)
-            RW_TRY(r64 ? domain_apply<R, true>(a, i, pp.host[i], s) : domain_apply<R, false>(a, i, pp.host[i], s));
+        RW_TRY(r64 ? domain_apply<R, true>(a, nd, pp.host, s) : domain_apply<R, false>(a, nd, pp.host, s));
     }
     RW_TRY(check(0));
     if (r64) {
         if (rest) hipLaunchKernelGGL((k_copy64<R>), grid, blk, 0, s, a, 0, nd);
-        for (int i = 0; i < nd; ++i) RW_TRY(domain_copy64<R>(a, i, pp.host[i], 0, s));
+        RW_TRY(domain_copy64<R>(a, nd, pp.host, 0, s));
     }
     const int copy = (a.want_x64 && !r64) ? 1 : 0;
     if (copy)
-        for (int i = 0; i < nd; ++i) RW_TRY(domain_copy64<R>(a, i, pp.host[i], 1, s));
+        RW_TRY(domain_copy64<R>(a, nd, pp.host, 1, s));
     hipLaunchKernelGGL((k_stats<R>), dim3((unsigned)n), blk, 0, s, a, copy, nd);
     return hipGetLastError();
 }
@@ -1724,12 +1722,12 @@ static hipError_t launch_fp64(const SolveArgs& a, int64_t n, const PlanePlan& pp
     const dim3 grid((unsigned)(n - nd)), blk(kThreads);
     const bool rest = n > nd;
     if (rest) hipLaunchKernelGGL((k_init<double, R>), grid, blk, 0, s, a, nd);
-    for (int i = 0; i < nd; ++i) RW_TRY((domain_init<double, R>(a, i, pp.host[i], s)));
+    RW_TRY((domain_init<double, R>(a, nd, pp.host, s)));
     if (ev) RW_TRY(hipEventRecord(ev[0], s));
     RW_TRY(launch_pcg_c<double, R, double>(a, n, (double*)a.xt, 0, pp, s));
     if (ev) RW_TRY(hipEventRecord(ev[1], s));
     if (rest) hipLaunchKernelGGL((k_finish64<R>), grid, blk, 0, s, a, nd);
-    for (int i = 0; i < nd; ++i) RW_TRY(domain_finish64<R>(a, i, pp.host[i], s));
+    RW_TRY(domain_finish64<R>(a, nd, pp.host, s));
     hipLaunchKernelGGL((k_stats<R>), dim3((unsigned)n), blk, 0, s, a, 0, nd);
     return hipGetLastError();
 }
