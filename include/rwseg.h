@@ -206,7 +206,7 @@ size_t rw_noalloc_scratch_bytes(void);
  * consecutive chunks and copies out overlap.  Every chunk takes the kernel
  * variants the whole list would get, so per box the result is bit-identical
  * to rw_solve_bricks on the whole list, except where that call would leave
- * single-domain boxes beyond its cap of 16 to the window kernels (a chunk may
+ * single-domain boxes beyond its cap of 64 to the window kernels (a chunk may
  * then run them on the domain solver: equal up to rounding).  No x64 output.  The call returns
  * once everything is queued: x and stats are complete when `stream` has
  * completed (every other stream is joined to it).  On an error part-way the
@@ -339,7 +339,7 @@ enum rw_path {
     RW_PATH_RESIDENT = 2,        /* one workgroup per box, p in LDS, x and r in registers, the edge
                                     weights in registers (boxes up to 9216 voxels) or in LDS (up
                                     to 10240 voxels) */
-    RW_PATH_DOMAIN = 3,          /* large single box: many workgroups, host-driven iteration */
+    RW_PATH_DOMAIN = 3,          /* large box: many workgroups (every large box of the call in each launch), host-driven iteration */
     RW_PATH_RESIDENT_STREAMED = 4, /* one workgroup per box, p in LDS, r in registers; the edge
                                     weights and 1/d are computed once into a per-box buffer and
                                     re-read from cache each iteration (boxes up to 32768 voxels) */
