@@ -371,3 +371,28 @@ def test_counts_pyramid_and_poisson_weight_pipeline(env):
     c = (n - 1) / 2
     truth = (x - c) ** 2 + (y - 0.8 * c) ** 2 + (z - 1.1 * c) ** 2 <= (0.3 * n) ** 2
     assert np.mean((gmaps[0][..., 0] > 0.5) == truth) > 0.8
+
+
+def test_cached_buffers_carry_nothing_over(env):
+    """Level maps, brick flags and pyramid levels come back from the
+    per-device cache once freed: a run on another volume in between (its
+    buffers reused, holding its values) must leave the repeated run's maps and
+    flags bit for bit as before, for a binary and a three-class run."""
+    import gc
+    torch, rwg, ctx = env
+    n, levels = 64, 3
+    a = _sphere_volume(n, "u16", seed=7)
+    b = _sphere_volume(n, "u16", seed=8)[::-1].copy()
+    for n_classes in (2, 3):
+        seeds = _seeds(n, np.random.default_rng(9), n_classes=n_classes)
+        kw = dict(brick=16, beta=128.0, t_bin=0.49, prune_hom=0, precision=1, tol=1e-6, n_classes=n_classes)
+        pyr, res, maps1, flags1 = _gpu_run(env, a, seeds, levels, **kw)
+        del pyr, res
+        gc.collect()
+        pyr, res, _, _ = _gpu_run(env, b, seeds[::-1].copy(), levels, **kw)
+        del pyr, res
+        gc.collect()
+        _, _, maps2, flags2 = _gpu_run(env, a, seeds, levels, **kw)
+        for l in range(levels):
+            assert np.array_equal(maps1[l], maps2[l]), (n_classes, l)
+            assert np.array_equal(flags1[l], flags2[l]), (n_classes, l)

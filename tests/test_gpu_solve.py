@@ -220,8 +220,9 @@ def test_full_size_stress_sampled(env):
 
 def test_domain_solver_boxes(env):
     """Large single boxes (wide planes of >= 2^16 voxels, or >= 2^20 voxels)
-    take the multi-workgroup solver, at most 16 per call; the rest of such a
-    call runs the per-box kernels.  Every path against the oracle."""
+    take the multi-workgroup solver, at most 64 per call, all of them in each
+    launch; the rest of such a call runs the per-box kernels.  Every path
+    against the oracle."""
     rng = np.random.default_rng(21)
     wide = synth.random_box(rng, (48, 48, 40), dirichlet_frac=0.02)
     tall = synth.random_box(rng, (32, 32, 1024), dirichlet_frac=0.05)
@@ -240,31 +241,44 @@ def test_domain_solver_boxes(env):
 
 
 def test_domain_solver_multi_rhs_and_cap(env):
-    # 17 wide boxes of 2^16+ voxels: 16 go to the domain solver, one to the
-    # global-memory march; nrhs = 2 and 3 against per-rhs oracle solves
+    """65 wide boxes of 2^16+ voxels: the 64 largest share the domain
+    solver's launches, the smallest goes to the global-memory march; nrhs = 2
+    and 3 against per-rhs oracle solves, and boxes of the batched call against
+    the same boxes solved one per call."""
+    _, rwg, _ = env
     rng = np.random.default_rng(22)
-    boxes = [synth.random_box(rng, (46, 46, 31), dirichlet_frac=0.03) for _ in range(17)]
+    # sizes differ so that the boxes take different workgroup counts; the last is the smallest
+    boxes = [synth.random_box(rng, (46, 46, 31 + (i % 5)), dirichlet_frac=0.03) for i in range(64)]
+    boxes.append(synth.random_box(rng, (46, 46, 31), dirichlet_frac=0.03))
     d = synth.from_boxes(boxes)
+    ctx = rwg.Context(0)
+    plan = ctx.solve_plan(rwg.solve_params(beta=BETA, eps=EPS, tol=1e-7, precision=1),
+                          rwg.bricks_array(d["shapes"], d["offsets"]), d["g"].size)
+    ctx.close()
+    assert int(np.sum(plan == rwg.PATH_DOMAIN)) == 64 and plan[64] != rwg.PATH_DOMAIN, plan
     for R in (2, 3):
         xs = [np.where(d["mask"] != 0, rng.random(d["x"].size), 0.0).astype(np.float32) for _ in range(R)]
         dR = dict(d, x=np.stack(xs, axis=1).ravel())
         xR, _, st = _run(env, dR, beta=BETA, eps=EPS, tol=1e-7, precision=1, nrhs=R)
         xR = xR.reshape(-1, R)
         assert np.all(np.isin(st["status"], (0, 2))), st
-        for i in (0, 7, 15, 16):
+        for i in (0, 33, 63, 64):
             g, m, _ = boxes[i]
             o = int(d["offsets"][i])
             for k in range(R):
                 ref = orw.solve_box(g, m, xs[k][o:o + g.size].reshape(g.shape), BETA, EPS, method="pcg",
                                     tol=1e-14)
                 assert np.max(np.abs(xR[o:o + g.size, k] - ref.ravel())) <= 1e-4, (R, i, k)
-    # same boxes solved one call per box agree with the batched call
-    x1, _, _ = _run(env, d, beta=BETA, eps=EPS, tol=1e-7, precision=1)
-    for i in (3, 16):
+    # same boxes solved one call per box agree with the batched call; the
+    # iteration counts of the domain boxes are their own
+    x1, _, s1 = _run(env, d, beta=BETA, eps=EPS, tol=1e-7, precision=1)
+    for i in (3, 40, 64):
         di = synth.from_boxes([boxes[i]])
-        xi, _, _ = _run(env, di, beta=BETA, eps=EPS, tol=1e-7, precision=1)
+        xi, _, si = _run(env, di, beta=BETA, eps=EPS, tol=1e-7, precision=1)
         o = int(d["offsets"][i])
         assert np.max(np.abs(x1[o:o + boxes[i][0].size] - xi)) <= 1e-5
+        if i < 64:
+            assert s1["iters"][i] == si["iters"][0], (i, s1[i], si[0])
 
 
 def test_resident_kernel_matches_oracle_and_streaming(env):
