@@ -547,6 +547,7 @@ int solve_bricks_impl(rw_ctx* ctx, const rw_solve_params* params, int64_t n_bric
     a.schedule = stream_schedule(p.schedule);
     rwk::domain_bind(a, aux + L.state_bytes);
     a.tickets = (uint32_t*)(aux + L.tickets_off);
+    a.dom_sync_poll = noalloc ? 1 : 0;
     a.wts = wts;
     hipError_t e;
     hipEvent_t* ev = nullptr;

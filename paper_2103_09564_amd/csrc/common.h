@@ -165,6 +165,8 @@ struct SolveArgs {
     int32_t early_check;   // main solve: 1 + may_refine: each kernel group's boxes get their first
                            // true-residual check on the group's stream as soon as the group ends
     uint32_t* tickets;     // persistent resident launches: one counter per launch of the plan (or null)
+    int32_t dom_sync_poll; // domain solver: read its done flag synchronously (no page-locked slots or
+                           // events; the solve that allocates nothing)
 };
 
 struct AdjointArgs {

@@ -950,8 +950,8 @@ hipError_t domain_pcg(const SolveArgs& a, int nd, const BrickDev* host, XT* xt, 
     // queued, so the device does not idle while the host reads it.
     // Iterations queued past the end are no-ops (A and B return at once for a
     // box whose state is done).  Without the page-locked slots the flag is
-    // read synchronously.
-    DomPoll* pl = dom_poll();
+    // read synchronously, and so is it in the solve that allocates nothing.
+    DomPoll* pl = a.dom_sync_poll ? nullptr : dom_poll();
     auto finished = [&](bool* out) -> hipError_t {
         int32_t f = 0;
         hipError_t e = hipMemcpyAsync(&f, done_word, sizeof(f), hipMemcpyDeviceToHost, s);

@@ -68,8 +68,10 @@ def test_noalloc_matches_solve_two_calls(env, precision, x64):
     print(f"noalloc precision={precision}", flush=True)
     params = dict(beta=BETA, eps=EPS, tol=1e-6, precision=precision, refine_max=2 if precision == 2 else 1)
     # first call: the stress shapes (both resident paths and the window
-    # march for the odd boxes); second call: a smaller batch
-    big = _batch(21, 24, extra=[(40, 40, 40), (7, 1, 9), (33, 2, 3)])
+    # march for the odd boxes) and a wide box for the multi-workgroup domain
+    # solver (its done flag read synchronously here); second call: a smaller
+    # batch
+    big = _batch(21, 24, extra=[(40, 40, 40), (7, 1, 9), (33, 2, 3), (48, 48, 40)])
     small = _batch(22, 6, extra=[(3, 4, 5)])
     for boxes, d in (big, small):
         ref = _solve(env, d, False, x64=x64, **params)
