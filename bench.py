@@ -873,8 +873,9 @@ def main():
     fp64 = None if args.no_fp64 else run(rwg.PREC_FP64, max(1, args.steps // 2), 1)
 
     value = mixed["vox_it"] / mixed["wall"]
-    # Dominant kernel: the streamed-weights resident PCG (k_pcg_resg; the 32^3
-    # and the 32x32x17 boxes form two launches), timed by the library's HIP
+    # Dominant kernel: the streamed-weights resident PCG (k_pcg_resg4, four
+    # voxels per 16-byte load on 32 x 32 planes; the 32^3 and the 32x32x17
+    # boxes form two launches), timed by the library's HIP
     # events on the stream it runs on.  When the two launches run concurrently
     # on streams of their own (stream2_ms > 0) the roofline is that of the
     # 32^3 launch alone; otherwise of the two together (one after the other on
@@ -918,8 +919,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": ("k_pcg_resg<512, 64, 5, 32> (streamed-weights resident PCG, the 32^3 boxes), main-solve "
-                                "launch" if split else "k_pcg_resg (streamed-weights resident PCG), main-solve launches"),
+                     "kernel": ("k_pcg_resg4<512, 16> (streamed-weights resident PCG, the 32^3 boxes), main-solve "
+                                "launch" if split else "k_pcg_resg4 (streamed-weights resident PCG), main-solve launches"),
                      "bytes_per_voxel_iter": SEGMENT_BYTES_PER_VOXEL_ITER,
                      "measured_ceilings": ceilings,
                      "alone": alone,

@@ -1016,6 +1016,256 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
     resg_box<NT, VPT, G, PX>(a, xt, corr, base + (int)blockIdx.x);
 }
 
+// The 32^3 launch with 32 x 32 planes: each thread owns four consecutive
+// voxels per group, voxels 4 (t + NT j) + i (i < 4, j < NGR), so p, the
+// weights and 1/d move as 16-byte loads: per group one LDS load of p, two
+// scalar ones (the x neighbours outside the group) and four of the y and z
+// neighbour groups, three forward-weight loads, one backward x weight and two
+// backward y and z groups from the segment.  The iteration is the one of
+// resg_box, voxel for voxel in the same order of operations; only the
+// per-thread FP64 partial sums run over other voxels.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+struct SegBuf4 {
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ __forceinline__ float4 ld(unsigned vo, int so) const {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)vo, so, 0);
+        return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
+    }
+    __device__ __forceinline__ float ld1(unsigned vo, int so) const {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)vo, so, 0));
+    }
+};
+
+__device__ __forceinline__ float f4c(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+
+template <int NT, int NGR>
+__device__ __forceinline__ void resg4_box(const SolveArgs& a, float* xt, int corr, int ib) {
+    extern __shared__ __align__(16) float p_lds[];
+    __shared__ double red[(NT / 64) * 5];
+    constexpr int PX = 32, NXY = PX * PX;
+    constexpr int span = 4 * NT * NGR;
+    BoxState& st = a.state[ib];
+    const bool fused = a.fused_init && !corr;
+    if (!fused && !st.active) return;
+    const BrickDev bd = a.bricks[ib];
+    const int nz = bd.nz, nv = NXY * nz;
+    const int T = NXY + span;
+    float* const P = p_lds + NXY;
+    float4* const P4 = (float4*)P;  // group k of the box: voxels 4k .. 4k + 3
+    const float* g = a.g + bd.off;
+    const uint8_t* m = a.mask + bd.off;
+    float* const xb = xt + bd.off;
+    const float* rb = (const float*)a.r + bd.off;
+    float* const seg = a.wts + bd.woff;
+    float* const WX = seg + NXY;
+    float* const WY = WX + T;
+    float* const WZ = WY + T;
+    float* const ID = WZ + T;
+    const ResWeight W{(float)(-a.beta * 1.4426950408889634), (float)a.eps};
+
+    res_fill_p<NT, 8>(P, xb, -NXY, span + NXY, nv, fused);
+    if (fused) __syncthreads();
+    float* const rw = (float*)a.r + bd.off;
+    double sum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    res_weights_pass<NT, 8>(-NXY, span, PX, PX, nz, g, m, W, true, fused, P, rw, sum,
+                            [&](int v, float wx, float wy, float wz, float d, bool unk) {
+                                WX[v] = wx;
+                                WY[v] = wy;
+                                WZ[v] = wz;
+                                ID[v] = unk ? __builtin_amdgcn_rcpf(d) : 0.0f;
+                            });
+    // (the segment, its arrays 16-byte aligned: its offset in the weight
+    // buffer is a whole number of 256-byte lines, and nx*ny and the stride
+    // are multiples of four floats)
+    const SegBuf4 sb{__builtin_amdgcn_make_buffer_rsrc(seg, 0, (int)(4 * (4 * T)), 0x00020000)};
+    const int sWX = __builtin_amdgcn_readfirstlane(4 * NXY), sWY = __builtin_amdgcn_readfirstlane(sWX + 4 * T),
+              sWZ = __builtin_amdgcn_readfirstlane(sWY + 4 * T), sID = __builtin_amdgcn_readfirstlane(sWZ + 4 * T);
+    const int sWXm = sWX - 4, sWYm = __builtin_amdgcn_readfirstlane(sWY - 4 * PX),
+              sWZm = __builtin_amdgcn_readfirstlane(sWZ - 4 * NXY);
+
+    float4 x[NGR], r[NGR], q[NGR];
+    double rz, rr, bb;
+    if (fused) {
+        if (!res_start_finish<NT>(sum, nv, m, xb, rw, P, red, st, rz, rr, bb)) return;
+    }
+    {
+#pragma unroll
+        for (int j = 0; j < NGR; ++j) {
+            float rv4[4], xv4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int v0 = 4 * ((int)threadIdx.x + j * NT) + i;
+                const int v = v0 < nv ? v0 : nv - 1;
+                const bool u = v0 < nv && m[v] == 0;
+                const float rv = rb[v], xv = xb[v];
+                rv4[i] = u ? rv : 0.0f;
+                xv4[i] = u ? xv : 0.0f;
+            }
+            r[j] = make_float4(rv4[0], rv4[1], rv4[2], rv4[3]);
+            x[j] = make_float4(xv4[0], xv4[1], xv4[2], xv4[3]);
+            if ((j & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        if (!fused) {
+            __syncthreads();
+            rz = st.rz[0];
+            rr = st.rr[0];
+            bb = st.bb[0];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NGR; ++j) {
+        const float4 id = sb.ld(16u * (unsigned)(threadIdx.x + j * NT), sID);
+        q[j] = make_float4(r[j].x * id.x, r[j].y * id.y, r[j].z * id.z, r[j].w * id.w);  // start z
+    }
+
+    const double tol = corr ? a.inner_tol : a.tol;
+    const double tol2 = tol * tol;
+    double betac = 0.0;
+    float4 wr[2][3];  // forward weights of two groups
+    float4 ir[2];     // 1/d of two groups
+    int it = 0, flags = 0;
+    for (;;) {
+        if (rr <= tol2 * bb) break;
+        if (it >= a.max_iter) {
+            flags = 2;
+            break;
+        }
+        int tb = threadIdx.x;
+        asm volatile("" : "+v"(tb));
+        const unsigned o0 = 16u * (unsigned)tb;
+        auto group_base = [&](int j, unsigned ob) {
+            unsigned og = ob + 16u * (unsigned)(j * NT);
+            asm volatile("" : "+v"(og));
+            return og;
+        };
+        auto load_w = [&](int j, float4 (&w)[3]) {
+            const unsigned og = group_base(j, o0);
+            w[0] = sb.ld(og, sWX);
+            w[1] = sb.ld(og, sWY);
+            w[2] = sb.ld(og, sWZ);
+        };
+        load_w(0, wr[0]);
+        const float be = it == 0 ? 0.0f : (float)betac;
+        float4* const Pt = P4 + tb;
+#pragma unroll
+        for (int j = 0; j < NGR; ++j) {
+            const float4 pv = Pt[j * NT];
+            Pt[j * NT] = make_float4(q[j].x + be * pv.x, q[j].y + be * pv.y, q[j].z + be * pv.z, q[j].w + be * pv.w);
+            if ((j & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        res_lds_barrier();
+        const float* const Ps = P + 4 * tb;  // first voxel of group 0
+        double sig = 0.0;
+#pragma unroll
+        for (int j = 0; j < NGR; ++j) {
+            // this group's backward loads first, then the next group's forward ones
+            const unsigned og = group_base(j, o0);
+            const float wxm0 = sb.ld1(og, sWXm);
+            const float4 wym = sb.ld(og, sWYm);
+            const float4 wzm = sb.ld(og, sWZm);
+            __builtin_amdgcn_sched_barrier(0);
+            if (j + 1 < NGR) load_w(j + 1, wr[(j + 1) & 1]);
+            else ir[0] = sb.ld(o0, sID);
+            __builtin_amdgcn_sched_barrier(0);
+            const float4 wx = wr[j & 1][0], wy = wr[j & 1][1], wz = wr[j & 1][2];
+            const float4 pv = Pt[j * NT];
+            const float pxm = Ps[4 * j * NT - 1], pxp = Ps[4 * j * NT + 4];
+            const float4 pym = Pt[j * NT - PX / 4], pyp = Pt[j * NT + PX / 4];
+            const float4 pzm = Pt[j * NT - NXY / 4], pzp = Pt[j * NT + NXY / 4];
+            float qv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float wxp = f4c(wx, i), wyp = f4c(wy, i), wzp = f4c(wz, i);
+                const float wxmi = i == 0 ? wxm0 : f4c(wx, i - 1);
+                const float wymi = f4c(wym, i), wzmi = f4c(wzm, i);
+                const float d = ((wxp + wxmi) + (wyp + wymi)) + (wzp + wzmi);
+                const float p0 = f4c(pv, i);
+                const float pl = i == 0 ? pxm : f4c(pv, i - 1);
+                const float pr = i == 3 ? pxp : f4c(pv, i + 1);
+                const float acc = wxp * pr + wxmi * pl + wyp * f4c(pyp, i) + wymi * f4c(pym, i) + wzp * f4c(pzp, i) +
+                                  wzmi * f4c(pzm, i);
+                qv[i] = d * p0 - acc;  // masked in the update below
+                sig += (double)p0 * (double)qv[i];
+            }
+            q[j] = make_float4(qv[0], qv[1], qv[2], qv[3]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        double s1[1] = {sig};
+        res_block_sum_lds<NT, 1>(s1, red);
+        sig = s1[0];
+        const double alpha = rz / sig;
+        if (!res_finite(alpha) || !(sig > 0.0)) {
+            flags = 1;
+            break;
+        }
+        const float al = (float)alpha;
+        double acc2[2] = {0.0, 0.0};
+        int t3 = threadIdx.x;
+        asm volatile("" : "+v"(t3));
+        const unsigned o3 = 16u * (unsigned)t3;
+        const float4* const P3 = P4 + t3;
+#pragma unroll
+        for (int j = 0; j < NGR; ++j) {
+            if (j + 1 < NGR) ir[(j + 1) & 1] = sb.ld(group_base(j + 1, o3), sID);
+            __builtin_amdgcn_sched_barrier(0);
+            const float4 id = ir[j & 1];
+            const float4 pv = P3[j * NT];
+            x[j] = make_float4(x[j].x + al * pv.x, x[j].y + al * pv.y, x[j].z + al * pv.z, x[j].w + al * pv.w);
+            asm volatile("" : "+v"(x[j].x), "+v"(x[j].y), "+v"(x[j].z), "+v"(x[j].w));
+            float rn[4], zn[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float idi = f4c(id, i);
+                const float rr0 = f4c(r[j], i) - al * f4c(q[j], i);
+                rn[i] = idi != 0.0f ? rr0 : 0.0f;
+                zn[i] = rn[i] * idi;
+                acc2[0] += (double)rn[i] * (double)zn[i];
+                acc2[1] += (double)rn[i] * (double)rn[i];
+            }
+            r[j] = make_float4(rn[0], rn[1], rn[2], rn[3]);
+            q[j] = make_float4(zn[0], zn[1], zn[2], zn[3]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        res_block_sum_lds<NT, 2>(acc2, red);
+        ++it;
+        if (!res_finite(acc2[0]) || !res_finite(acc2[1])) {
+            flags = 1;
+            break;
+        }
+        betac = acc2[0] / rz;
+        rz = acc2[0];
+        rr = acc2[1];
+    }
+    int te = (int)threadIdx.x;
+    asm volatile("" : "+v"(te));
+#pragma unroll
+    for (int j = 0; j < NGR; ++j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int v = 4 * (te + j * NT) + i;
+            if (v < nv && m[v] == 0) xb[v] = f4c(x[j], i);
+        }
+    }
+    if (threadIdx.x == 0) {
+        st.rz[0] = rz;
+        st.rr[0] = rr;
+        if (corr) {
+            st.refine_iters += it;
+        } else {
+            st.iters = it;
+            st.rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            if (flags & 2) st.status = RW_ST_MAX_ITER;
+        }
+        if (flags & 1) st.status = RW_ST_NONFINITE;
+        st.pending = corr && !(flags & 1) ? 1 : 0;
+    }
+}
+
+template <int NT, int NGR>
+__global__ __launch_bounds__(NT) void k_pcg_resg4(SolveArgs a, float* xt, int corr, int base, int, uint32_t*) {
+    resg4_box<NT, NGR>(a, xt, corr, base + (int)blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Split boxes: two workgroups per box (k_pcg_res2).
 //
@@ -1625,9 +1875,10 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
         // the plan sized each box's weight segment for this launch's span
         if (!a.wts) return hipErrorInvalidValue;
         const int64_t span = resident_g_span(max_voxels);
-        // 512 threads; forward weights issued 8 voxels ahead (34 per thread)
-        // or 5 (64 per thread, where three register arrays leave room for
-        // no more)
+        // 512 threads; forward weights issued 8 voxels ahead (34 per thread);
+        // on the larger span 32 x 32 planes take four voxels per 16-byte load
+        // (64 per thread), other planes issue 5 ahead (three register arrays
+        // of 64 leave room for no more)
         constexpr int nt = kResThreads;
         // one workgroup per box only: a persistent twin of this kernel would
         // spill registers (its box loop keeps values live across boxes)
@@ -1636,7 +1887,7 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
             return px == 32 ? go1(k_pcg_resg<nt, kResSpanG0 / nt, 8, 32>, nt)
                             : go1(k_pcg_resg<nt, kResSpanG0 / nt, 8, 0>, nt);
         if (span == kResSpanG1)
-            return px == 32 ? go1(k_pcg_resg<nt, kResSpanG1 / nt, 5, 32>, nt)
+            return px == 32 ? go1(k_pcg_resg4<nt, kResSpanG1 / (4 * nt)>, nt)
                             : go1(k_pcg_resg<nt, kResSpanG1 / nt, 5, 0>, nt);
         return hipErrorInvalidValue;
     }
