@@ -57,10 +57,12 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, if it was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "k_pcg_resg_stress8192.md")
+def traffic_from_profile(split):
+    """HBM bytes of the dominant kernel from the committed counter summary, if
+    it was taken on the current kernel sources (else None): of the 32^3 launch
+    when the two streamed-weights launches run on streams of their own
+    (`split`), else of the two launches together."""
+    path = os.path.join(ROOT, "profiles", "k_pcg_resg4_stress8192.md")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -69,7 +71,7 @@ def traffic_from_profile():
             rec = json.loads(line.split(":", 1)[1])
     if rec.get("source_hash") != source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("hbm_bytes_32cube_launch" if split else "hbm_bytes_streamed_launches")
 
 
 def measure_ceilings(torch, rwg, ctx, reps=5):
@@ -891,13 +893,13 @@ def main():
     achieved = SEGMENT_BYTES_PER_VOXEL_ITER * vox_roof / t["stream_ms"] / 1e9 if t["stream_ms"] > 0 else 0.0
     stream_equiv = BYTES_PER_VOXEL_ITER * vox_roof / t["stream_ms"] / 1e9 if t["stream_ms"] > 0 else 0.0
     ceilings = measure_ceilings(torch, rwg, ctx)
-    alone = roofline_alone(torch, rwg, ctx, d, g, m, x, x0, stream) if split else None
+    alone = roofline_alone(torch, rwg, ctx, d, g, m, x, x0, stream)
     # memory bytes of the whole PCG phase, each box at its kernel's own
     # algorithmic bytes (a cross-check that must stay below the HBM peak)
     n_res_vox = mixed["res_vox"]
     phase_bytes = (SEGMENT_BYTES_PER_VOXEL_ITER * mixed["vox_it_sw"] + BYTES_PER_VOXEL_ITER * mixed["vox_it_hbm"]
                    + RESIDENT_BYTES_PER_VOXEL * n_res_vox)
-    traffic = traffic_from_profile()
+    traffic = traffic_from_profile(split)
     s = mixed["stats"]
     out = {
         "metric": "brick-PCG voxel-iters/s, %HBM peak; mixed vs plain FP64 at 1e-4 err",
@@ -920,7 +922,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "kernel": ("k_pcg_resg4<512, 16> (streamed-weights resident PCG, the 32^3 boxes), main-solve "
-                                "launch" if split else "k_pcg_resg4 (streamed-weights resident PCG), main-solve launches"),
+                                "launch" if split else "k_pcg_resg4<512, 16> and <512, 9> (streamed-weights resident PCG, the 32^3 and "
+                                "the 32x32x17 boxes one after the other on one stream), main-solve launches"),
                      "bytes_per_voxel_iter": SEGMENT_BYTES_PER_VOXEL_ITER,
                      "measured_ceilings": ceilings,
                      "alone": alone,

@@ -1016,14 +1016,16 @@ __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int cor
     resg_box<NT, VPT, G, PX>(a, xt, corr, base + (int)blockIdx.x);
 }
 
-// The 32^3 launch with 32 x 32 planes: each thread owns four consecutive
-// voxels per group, voxels 4 (t + NT j) + i (i < 4, j < NGR), so p, the
-// weights and 1/d move as 16-byte loads: per group one LDS load of p, two
-// scalar ones (the x neighbours outside the group) and four of the y and z
-// neighbour groups, three forward-weight loads, one backward x weight and two
-// backward y and z groups from the segment.  The iteration is the one of
-// resg_box, voxel for voxel in the same order of operations; only the
-// per-thread FP64 partial sums run over other voxels.
+// Launches with 32 x 32 planes: each thread owns four consecutive voxels per
+// group, voxels 4 (t + NT j) + i (i < 4, j < NGR, t + NT j < NG, the span's
+// NG groups), so p, the weights and 1/d move as 16-byte loads: per group one
+// LDS load of p, two scalar ones (the x neighbours outside the group) and
+// four of the y and z neighbour groups, three forward-weight loads, one
+// backward x weight and two backward y and z groups from the segment.  The
+// iteration is the one of resg_box, voxel for voxel in the same order of
+// operations; only the per-thread FP64 partial sums run over other voxels.
+// When NG is not a multiple of NT the last group belongs to the first
+// NG mod NT threads, a whole number of waves.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 struct SegBuf4 {
     __amdgpu_buffer_rsrc_t rsrc;
@@ -1038,12 +1040,13 @@ struct SegBuf4 {
 
 __device__ __forceinline__ float f4c(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
 
-template <int NT, int NGR>
+template <int NT, int NGR, int NG>
 __device__ __forceinline__ void resg4_box(const SolveArgs& a, float* xt, int corr, int ib) {
     extern __shared__ __align__(16) float p_lds[];
     __shared__ double red[(NT / 64) * 5];
     constexpr int PX = 32, NXY = PX * PX;
-    constexpr int span = 4 * NT * NGR;
+    static_assert(NGR == (NG + NT - 1) / NT && (NG % NT) % 64 == 0, "groups per thread, whole waves in the last");
+    constexpr int span = 4 * NG;
     BoxState& st = a.state[ib];
     const bool fused = a.fused_init && !corr;
     if (!fused && !st.active) return;
@@ -1123,6 +1126,9 @@ __device__ __forceinline__ void resg4_box(const SolveArgs& a, float* xt, int cor
     double betac = 0.0;
     float4 wr[2][3];  // forward weights of two groups
     float4 ir[2];     // 1/d of two groups
+    // this thread owns group NGR - 1 (the loads of a group it does not own
+    // stay inside the segment and go unused)
+    const bool last = NG % NT == 0 || (int)threadIdx.x < NG % NT;
     int it = 0, flags = 0;
     for (;;) {
         if (rr <= tol2 * bb) break;
@@ -1149,6 +1155,7 @@ __device__ __forceinline__ void resg4_box(const SolveArgs& a, float* xt, int cor
         float4* const Pt = P4 + tb;
 #pragma unroll
         for (int j = 0; j < NGR; ++j) {
+            if (j == NGR - 1 && !last) continue;
             const float4 pv = Pt[j * NT];
             Pt[j * NT] = make_float4(q[j].x + be * pv.x, q[j].y + be * pv.y, q[j].z + be * pv.z, q[j].w + be * pv.w);
             if ((j & 1) == 1) __builtin_amdgcn_sched_barrier(0);
@@ -1167,6 +1174,7 @@ __device__ __forceinline__ void resg4_box(const SolveArgs& a, float* xt, int cor
             if (j + 1 < NGR) load_w(j + 1, wr[(j + 1) & 1]);
             else ir[0] = sb.ld(o0, sID);
             __builtin_amdgcn_sched_barrier(0);
+            if (j == NGR - 1 && !last) continue;
             const float4 wx = wr[j & 1][0], wy = wr[j & 1][1], wz = wr[j & 1][2];
             const float4 pv = Pt[j * NT];
             const float pxm = Ps[4 * j * NT - 1], pxp = Ps[4 * j * NT + 4];
@@ -1208,6 +1216,7 @@ __device__ __forceinline__ void resg4_box(const SolveArgs& a, float* xt, int cor
         for (int j = 0; j < NGR; ++j) {
             if (j + 1 < NGR) ir[(j + 1) & 1] = sb.ld(group_base(j + 1, o3), sID);
             __builtin_amdgcn_sched_barrier(0);
+            if (j == NGR - 1 && !last) continue;
             const float4 id = ir[j & 1];
             const float4 pv = P3[j * NT];
             x[j] = make_float4(x[j].x + al * pv.x, x[j].y + al * pv.y, x[j].z + al * pv.z, x[j].w + al * pv.w);
@@ -1261,9 +1270,9 @@ __device__ __forceinline__ void resg4_box(const SolveArgs& a, float* xt, int cor
     }
 }
 
-template <int NT, int NGR>
+template <int NT, int NGR, int NG>
 __global__ __launch_bounds__(NT) void k_pcg_resg4(SolveArgs a, float* xt, int corr, int base, int, uint32_t*) {
-    resg4_box<NT, NGR>(a, xt, corr, base + (int)blockIdx.x);
+    resg4_box<NT, NGR, NG>(a, xt, corr, base + (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1883,11 +1892,12 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
         // one workgroup per box only: a persistent twin of this kernel would
         // spill registers (its box loop keeps values live across boxes)
         if (ticket) return hipErrorInvalidValue;
+        constexpr int ng0 = kResSpanG0 / 4, ng1 = kResSpanG1 / 4;
         if (span == kResSpanG0)
-            return px == 32 ? go1(k_pcg_resg<nt, kResSpanG0 / nt, 8, 32>, nt)
+            return px == 32 ? go1(k_pcg_resg4<nt, (ng0 + nt - 1) / nt, ng0>, nt)
                             : go1(k_pcg_resg<nt, kResSpanG0 / nt, 8, 0>, nt);
         if (span == kResSpanG1)
-            return px == 32 ? go1(k_pcg_resg4<nt, kResSpanG1 / (4 * nt)>, nt)
+            return px == 32 ? go1(k_pcg_resg4<nt, ng1 / nt, ng1>, nt)
                             : go1(k_pcg_resg<nt, kResSpanG1 / nt, 5, 0>, nt);
         return hipErrorInvalidValue;
     }

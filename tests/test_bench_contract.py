@@ -22,12 +22,15 @@ def test_traffic_follows_the_source_hash(tmp_path, monkeypatch):
     assert len(h) == 16
     prof = tmp_path / "profiles"
     prof.mkdir()
-    f = prof / "k_pcg_resg_stress8192.md"
+    f = prof / "k_pcg_resg4_stress8192.md"
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    f.write_text('summary\nbench-traffic: {"source_hash": "%s", "hbm_bytes_per_launch": 123}\n' % "x")
+    line = 'summary\nbench-traffic: {"source_hash": "%s", "hbm_bytes_32cube_launch": 123, ' \
+           '"hbm_bytes_streamed_launches": 456}\n'
+    f.write_text(line % "x")
     monkeypatch.setattr(bench, "source_hash", lambda: h)
-    assert bench.traffic_from_profile() is None          # profiled on other sources
-    f.write_text('summary\nbench-traffic: {"source_hash": "%s", "hbm_bytes_per_launch": 123}\n' % h)
-    assert bench.traffic_from_profile() == 123
+    assert bench.traffic_from_profile(True) is None      # profiled on other sources
+    f.write_text(line % h)
+    assert bench.traffic_from_profile(True) == 123       # the 32^3 launch on a stream of its own
+    assert bench.traffic_from_profile(False) == 456      # both streamed-weights launches on one stream
     f.unlink()
-    assert bench.traffic_from_profile() is None          # no profile
+    assert bench.traffic_from_profile(True) is None      # no profile

@@ -331,9 +331,10 @@ def test_resident_kernel_matches_oracle_and_streaming(env):
 def test_streamed_weights_edge_cases(env):
     """The streamed-weights resident kernel on its special boxes: a non-finite
     g, the iteration cap, no seed, zero Dirichlet data, a single unknown
-    voxel, a 32x32-plane box next to other plane shapes (compile-time and
-    run-time neighbour offsets give the same bits), and slots past the end
-    of a box."""
+    voxel, 32x32-plane boxes next to other plane shapes (the four-voxel
+    layout of 32 x 32 planes and the one-voxel layout with run-time
+    neighbour offsets: the same FP32 arithmetic per voxel, FP64 sums in
+    another order), and slots past the end of a box."""
     rng = np.random.default_rng(77)
     a = synth.random_box(rng, (32, 32, 20), dirichlet_frac=0.02)     # span 32768, 32x32 planes
     b = synth.random_box(rng, (32, 32, 12), dirichlet_frac=0.02)     # span 17408, 32x32 planes
@@ -363,8 +364,9 @@ def test_streamed_weights_edge_cases(env):
     for i in (2, 3):
         ref = _ref(boxes[i])
         assert np.max(np.abs(x[off[i]:off[i] + ref.size] - ref)) <= 1e-4, (i, st[i])
-    # 32x32-plane boxes alone (offsets compiled in) and beside a 31x33 box
-    # (run-time offsets): identical arithmetic, identical bits
+    # 32x32-plane boxes alone (four-voxel layout in both launches) and with a
+    # 31x33 box joining b's launch (one-voxel layout there): a's launch is the
+    # same in both runs, bit for bit; b agrees to the FP64 sums' rounding
     c = synth.random_box(rng, (31, 33, 16), dirichlet_frac=0.02)
     d1 = synth.from_boxes([a, b])
     d2 = synth.from_boxes([a, b, c])
@@ -372,8 +374,10 @@ def test_streamed_weights_edge_cases(env):
     assert np.all(p1 == rwg.PATH_RESIDENT_STREAMED)
     x1, _, s1 = _run(env, d1, beta=BETA, eps=EPS, tol=1e-6, precision=1)
     x2, _, s2 = _run(env, d2, beta=BETA, eps=EPS, tol=1e-6, precision=1)
-    n = a[0].size + b[0].size
-    assert np.array_equal(x1[:n], x2[:n])
-    assert np.array_equal(s1["iters"], s2["iters"][:2])
+    na, n = a[0].size, a[0].size + b[0].size
+    assert np.array_equal(x1[:na], x2[:na]) and s1["iters"][0] == s2["iters"][0]
+    assert np.max(np.abs(x1[na:n] - x2[na:n])) <= 1e-5 and abs(int(s1["iters"][1]) - int(s2["iters"][1])) <= 1
+    ref_b = _ref(b)
+    assert np.max(np.abs(x1[na:n] - ref_b)) <= 1e-4, s1[1]
     ref_c = _ref(c)
     assert np.max(np.abs(x2[n:n + ref_c.size] - ref_c)) <= 1e-4, s2[2]
