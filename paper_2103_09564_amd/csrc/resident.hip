@@ -743,9 +743,7 @@ __device__ __forceinline__ void res_block_sum_lds(double (&v)[N], double* red) {
     res_lds_barrier();
 }
 
-// PX > 0: every box of the launch has nx = ny = PX, so the neighbour offsets
-// are compile-time and the LDS reads use immediate offsets from a few bases.
-template <int NT, int VPT, int G, int PX>
+template <int NT, int VPT, int G>
 __device__ __forceinline__ void resg_box(const SolveArgs& a, float* xt, int corr, int ib) {
     extern __shared__ __align__(16) float p_lds[];
     __shared__ double red[(NT / 64) * 5];  // block sums of up to 5 values (the start state)
@@ -754,7 +752,7 @@ __device__ __forceinline__ void resg_box(const SolveArgs& a, float* xt, int corr
     const bool fused = a.fused_init && !corr;  // this kernel computes the start state
     if (!fused && !st.active) return;
     const BrickDev bd = a.bricks[ib];
-    const int nx = PX ? PX : bd.nx, ny = PX ? PX : bd.ny, nz = bd.nz, nxy = nx * ny, nv = nxy * nz;
+    const int nx = bd.nx, ny = bd.ny, nz = bd.nz, nxy = nx * ny, nv = nxy * nz;
     constexpr int span = NT * VPT;
     const int T = nxy + span;  // stride of the segment arrays
     float* P = p_lds + nxy;
@@ -827,10 +825,6 @@ __device__ __forceinline__ void resg_box(const SolveArgs& a, float* xt, int corr
     const double tol = corr ? a.inner_tol : a.tol;
     const double tol2 = tol * tol;
     double betac = 0.0;
-    // The z-backward weight of slot k is the z-forward weight of slot k - 2
-    // when the plane is 1024 voxels and the workgroup 512 threads: taken
-    // from registers, not loaded.
-    constexpr bool kZc = PX == 32 && NT == 512;
     float wr[2][G][3];  // forward weights of two groups of voxels
     float ir[2][G];     // 1/d of two groups
     int it = 0, flags = 0;
@@ -843,10 +837,8 @@ __device__ __forceinline__ void resg_box(const SolveArgs& a, float* xt, int corr
         // opaque copies: per-voxel addresses stay inside the loop
         int tb = threadIdx.x, oy = nx, oz = nxy;
         asm volatile("" : "+v"(tb));
-        if constexpr (PX == 0) {
-            asm volatile("" : "+v"(oy));
-            asm volatile("" : "+v"(oz));
-        }
+        asm volatile("" : "+v"(oy));
+        asm volatile("" : "+v"(oz));
         // byte offsets of a group's slots, from an opaque per-group base (so
         // that the compiler keeps no per-slot offset beyond its group)
         const unsigned o0 = 4u * (unsigned)tb;
@@ -878,7 +870,7 @@ __device__ __forceinline__ void resg_box(const SolveArgs& a, float* xt, int corr
                     const unsigned o = og + 4u * (unsigned)(j * NT);
                     w[j][0] = sb.ld(o, sWXm);
                     w[j][1] = sb.ld(o, sWYm);
-                    if constexpr (!kZc) w[j][2] = sb.ld(o, sWZm);
+                    w[j][2] = sb.ld(o, sWZm);
                 }
             }
         };
@@ -905,7 +897,6 @@ __device__ __forceinline__ void resg_box(const SolveArgs& a, float* xt, int corr
         const float* const Pzm = Pt - oz;
         const float* const Pzp = Pt + oz;
         double sig = 0.0;
-        float wz2 = 0.0f, wz1 = 0.0f;  // z-forward weights of slots k - 2, k - 1 (kZc; pads before slot 0)
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi) {
             // this group's backward loads go first: waiting for them must not
@@ -921,15 +912,7 @@ __device__ __forceinline__ void resg_box(const SolveArgs& a, float* xt, int corr
                 const int k = gi * G + j;
                 if (k < VPT) {
                     const float wxp = wr[gi & 1][j][0], wyp = wr[gi & 1][j][1], wzp = wr[gi & 1][j][2];
-                    const float wxm = wb[j][0], wym = wb[j][1];
-                    float wzm;
-                    if constexpr (kZc) {
-                        wzm = wz2;
-                        wz2 = wz1;
-                        wz1 = wzp;
-                    } else {
-                        wzm = wb[j][2];
-                    }
+                    const float wxm = wb[j][0], wym = wb[j][1], wzm = wb[j][2];
                     const float d = ((wxp + wxm) + (wyp + wym)) + (wzp + wzm);
                     const float pv = Pt[k * NT];
                     const float acc = wxp * Pxm[k * NT + 2] + wxm * Pxm[k * NT] + wyp * Pyp[k * NT] +
@@ -1011,9 +994,9 @@ __device__ __forceinline__ void resg_box(const SolveArgs& a, float* xt, int corr
 }
 
 // One workgroup per box.
-template <int NT, int VPT, int G, int PX>
+template <int NT, int VPT, int G>
 __global__ __launch_bounds__(NT) void k_pcg_resg(SolveArgs a, float* xt, int corr, int base, int, uint32_t*) {
-    resg_box<NT, VPT, G, PX>(a, xt, corr, base + (int)blockIdx.x);
+    resg_box<NT, VPT, G>(a, xt, corr, base + (int)blockIdx.x);
 }
 
 // Launches with 32 x 32 planes: each thread owns four consecutive voxels per
@@ -1884,10 +1867,10 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
         // the plan sized each box's weight segment for this launch's span
         if (!a.wts) return hipErrorInvalidValue;
         const int64_t span = resident_g_span(max_voxels);
-        // 512 threads; forward weights issued 8 voxels ahead (34 per thread);
-        // on the larger span 32 x 32 planes take four voxels per 16-byte load
-        // (64 per thread), other planes issue 5 ahead (three register arrays
-        // of 64 leave room for no more)
+        // 512 threads; 32 x 32 planes: four voxels per 16-byte load (k_pcg_resg4,
+        // 34 or 64 voxels per thread); other planes one voxel per load, the
+        // forward weights issued 8 voxels ahead (34 per thread) or 5 (64 per
+        // thread, where three register arrays leave room for no more)
         constexpr int nt = kResThreads;
         // one workgroup per box only: a persistent twin of this kernel would
         // spill registers (its box loop keeps values live across boxes)
@@ -1895,10 +1878,10 @@ hipError_t launch_resident(const SolveArgs& a, int64_t b0, int64_t b1, int64_t m
         constexpr int ng0 = kResSpanG0 / 4, ng1 = kResSpanG1 / 4;
         if (span == kResSpanG0)
             return px == 32 ? go1(k_pcg_resg4<nt, (ng0 + nt - 1) / nt, ng0>, nt)
-                            : go1(k_pcg_resg<nt, kResSpanG0 / nt, 8, 0>, nt);
+                            : go1(k_pcg_resg<nt, kResSpanG0 / nt, 8>, nt);
         if (span == kResSpanG1)
             return px == 32 ? go1(k_pcg_resg4<nt, ng1 / nt, ng1>, nt)
-                            : go1(k_pcg_resg<nt, kResSpanG1 / nt, 5, 0>, nt);
+                            : go1(k_pcg_resg<nt, kResSpanG1 / nt, 5>, nt);
         return hipErrorInvalidValue;
     }
     const int nt = kResThreads;
