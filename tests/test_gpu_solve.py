@@ -328,6 +328,32 @@ def test_resident_kernel_matches_oracle_and_streaming(env):
     assert np.all(np.isin(sr["status"], (0, 2))) and np.all(s64["status"] == 2) | np.all(np.isin(s64["status"], (0, 2)))
 
 
+def test_four_voxel_layout_over_box_depths(env):
+    """The streamed-weights kernel's four-voxel layout on 32 x 32 planes at
+    every kind of depth: the smallest box it takes (nz = 11), the 17408-slot
+    span whose last group belongs to half the threads (nz up to 17), the
+    32768-slot span (nz 18 to 32); unused slots past each box's end.  Each
+    box against the oracle, one launch per span."""
+    print("four-voxel depths", flush=True)
+    _, rwg, _ = env
+    rng = np.random.default_rng(91)
+    depths = (11, 14, 17, 18, 24, 31, 32)
+    boxes = [synth.random_box(rng, (32, 32, nz), dirichlet_frac=0.02) for nz in depths]
+    d = synth.from_boxes(boxes)
+    plan = rwg.context().solve_plan(rwg.solve_params(), rwg.bricks_array(d["shapes"], d["offsets"]), d["g"].size)
+    assert np.all(plan == rwg.PATH_RESIDENT_STREAMED), plan
+    x, _, st = _run(env, d, beta=BETA, eps=EPS, tol=1e-6, precision=1)
+    off = d["offsets"]
+    for i, b in enumerate(boxes):
+        ref = _ref(b)
+        err = np.max(np.abs(x[off[i]:off[i] + ref.size] - ref))
+        assert err <= 1e-4, (depths[i], err, st[i])
+        assert st["status"][i] in (0, 2) and st["true_rel_resid"][i] <= 1e-5 * 1.0001, (depths[i], st[i])
+        # seeded voxels keep their values
+        mk = b[1].ravel() != 0
+        assert np.array_equal(x[off[i]:off[i] + ref.size][mk], b[2].ravel()[mk]), depths[i]
+
+
 def test_streamed_weights_edge_cases(env):
     """The streamed-weights resident kernel on its special boxes: a non-finite
     g, the iteration cap, no seed, zero Dirichlet data, a single unknown
