@@ -35,7 +35,7 @@ RESIDENT_BYTES_PER_VOXEL = 13  # weights-in-LDS kernel: read g, mask, x once per
 BETA, EPS, TOL = 128.0, 1e-6, 1e-6
 N_BOXES, SEED = 8192, 3
 # workloads run only on request (--only NAME): minutes of GPU time
-ON_REQUEST = ("shells_full", "memory_ceilings")
+ON_REQUEST = ("shells_full", "memory_ceilings", "tubes_512_host_finest")
 EXTRAS = ("plain_sphere_64", "tubes_512_hierarchy", "blobs_512x32_adjoint", "shells_hierarchy_incremental",
           "cells_256_ablation", "cells_brick_growth", "pruning_table_256", "stress_streamed_from_host")
 
@@ -353,6 +353,31 @@ def bench_tubes(torch, rwg, ctx, n=512, n_tubes=40, levels=4):
                                              "not_converged")},
             "dice_vs_seeded_tubes": float(2 * (lb & gt).sum() / (lb.sum() + gt.sum())),
             "level_solve_schedules": sched, "generate_s": gen_s}
+
+
+def bench_tubes_host(torch, rwg, ctx, n=512, n_tubes=40, levels=4):
+    """The tube pipeline out of core: the volume in pinned host memory, the
+    finest level's pyramid data and level map in page-locked host memory
+    (rw_pyramid_build_host, rw_params.host_levels = 1), read and written in
+    place by the kernels; against the same pipeline in device memory.  The
+    level maps must agree bit for bit."""
+    import synth
+    v, seeds, _ = synth.tube_volume(n=n, n_tubes=n_tubes, n_fg=20, n_bg=200, seed=2)
+    vh = torch.from_numpy(v).pin_memory()
+    vd = vh.to("cuda:0")
+    kw = dict(brick=32, expand=1.25, beta=BETA, eps=EPS, tol=1e-5, precision=1, n_classes=2, prune_hom=0,
+              prune_dt=1, t_bin=0.49)
+    pd_ms, pyr_d = _best_ms(torch, lambda: rwg.Pyramid(ctx, vd, levels), 3)
+    sd_ms, res_d = _best_ms(torch, lambda: rwg.segment(pyr_d, seeds, **kw), 3)
+    ph_ms, pyr_h = _best_ms(torch, lambda: rwg.Pyramid(ctx, vh, levels, host_levels=1), 3)
+    sh_ms, res_h = _best_ms(torch, lambda: rwg.segment(pyr_h, seeds, host_levels=1, **kw), 3)
+    equal = all(bool(torch.equal(res_h.level_map(l), res_d.level_map(l))) for l in range(levels))
+    host_bytes = v.size * 4 * 2      # level 0: g and the one-rhs map
+    return {"workload": f"tubes {n}^3 uint16 in pinned host memory, level 0 (g and map) in page-locked host "
+                        f"memory, {levels} levels, s=32, e=1.25, dt pruning, mixed tol 1e-5",
+            "device": {"pyramid_ms": pd_ms, "segment_ms": sd_ms},
+            "host_level0": {"pyramid_ms": ph_ms, "segment_ms": sh_ms, "host_bytes": host_bytes},
+            "level_maps_equal": equal, "solved": res_h.stats()["solved"]}
 
 
 def bench_blobs_adjoint(torch, rwg, dev, n=512, cpu_leg=False):
@@ -781,6 +806,8 @@ def main():
             return {"ceilings": measure_ceilings(torch, rwg, ctx), "read_sweep": probe_read_sweep(torch, rwg, ctx)}
         if name == "stress_streamed_from_host":
             return bench_streamed(torch, rwg, ctx)
+        if name == "tubes_512_host_finest":
+            return bench_tubes_host(torch, rwg, ctx)
         return bench_shells(torch, rwg, ctx, dims=shell_dims)
 
     if args.only:

@@ -424,10 +424,26 @@ typedef struct rw_result rw_result;
  * they have; dims halve rounding up).  `vol` dev [nz][ny][nx] (x fastest);
  * dims = {nx, ny, nz}; 1 <= levels <= RW_MAX_LEVELS.  The pyramid owns its
  * device memory.  Work is queued on `stream`; the call returns after it is
- * queued.  Errors: RW_E_INVAL (dims, dtype, levels), RW_E_NOMEM.
+ * queued.  Errors: RW_E_INVAL (dims, dtype, levels; `vol` not device memory
+ * or page-locked host memory), RW_E_NOMEM.
  */
 int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels,
                      rw_pyramid** out, void* stream);
+
+/*
+ * Out-of-core pyramid (Section IV-A: the bricks a solve touches are small,
+ * the volume need not fit in device memory).  As rw_pyramid_build, but
+ * levels 0 .. host_levels - 1 (0 <= host_levels < levels) live in
+ * page-locked, coherent host memory that the device's kernels read and write
+ * in place over the host link; the coarser levels are in device memory.
+ * `vol` may itself be page-locked host memory (hipHostMalloc, a pinned
+ * tensor); pageable memory is rejected.  The levels equal rw_pyramid_build's
+ * bit for bit.  Pair it with rw_params.host_levels for the level maps.
+ * Errors: RW_E_INVAL (as rw_pyramid_build; host_levels), RW_E_NOMEM (host
+ * or device memory).
+ */
+int rw_pyramid_build_host(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels,
+                          int host_levels, rw_pyramid** out, void* stream);
 
 /*
  * The pyramid for the Poisson-noise weight of Section IV-C, where the edge
@@ -445,7 +461,9 @@ int rw_pyramid_build_counts(rw_ctx* ctx, const void* vol, int dtype, const int64
  * most 8 GiB per device are kept, the rest is freed; an allocation that
  * fails empties the cache first; rw_ctx_destroy empties it). */
 void rw_pyramid_free(rw_pyramid* p);
-/* Level accessor: dims = {nx, ny, nz} of the level, *data = dev float [nz][ny][nx]. */
+/* Level accessor: dims = {nx, ny, nz} of the level, *data = float [nz][ny][nx]
+ * (device memory, or page-locked host memory for the host levels of
+ * rw_pyramid_build_host). */
 int rw_pyramid_level(const rw_pyramid* p, int level, int64_t dims[3], const float** data);
 
 /* A label (Section IV-A): a point in full-resolution voxel units (voxel k
@@ -479,6 +497,10 @@ typedef struct rw_params {
                                 kernels take it; the results are the same solves); 1 solves
                                 them together (the weights shared, streaming kernels).  The
                                 coarsest level's domain always solves them together. */
+    int32_t host_levels;     /* the level maps of levels 0 .. host_levels - 1 in page-locked host
+                                memory (out of core, with rw_pyramid_build_host): the same
+                                kernels read and write them in place, and the maps equal a
+                                device-memory run's bit for bit; 0 (default) to levels - 1 */
 } rw_params;
 
 void rw_params_default(rw_params* p);
@@ -536,8 +558,9 @@ int rw_segment(rw_ctx* ctx, const rw_pyramid* pyr, const rw_seed* seeds, int64_t
  * to the per-device cache described at rw_pyramid_free. */
 void rw_result_free(rw_result* r);
 int rw_result_stats(const rw_result* r, rw_run_stats* out);
-/* Level map: dims = {nx, ny, nz}, nrhs = K - 1, *map = dev float [voxel][nrhs]
- * (probabilities of classes 1..K-1; class 0 is the complement). */
+/* Level map: dims = {nx, ny, nz}, nrhs = K - 1, *map = float [voxel][nrhs]
+ * (probabilities of classes 1..K-1; class 0 is the complement), in device
+ * memory, or page-locked host memory for levels below rw_params.host_levels. */
 int rw_result_level(const rw_result* r, int level, int64_t dims[3], int* nrhs, const float** map);
 /* Brick flags of a level: nb = bricks per axis {x, y, z}, *flags = dev uint8
  * [nbz][nby][nbx]; bit 0 reached, bit 1 prunable, bit 2 seed conflict in the

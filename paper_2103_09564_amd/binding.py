@@ -414,7 +414,7 @@ class Params(ctypes.Structure):
                 ("t_inc", ctypes.c_double), ("brick", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("n_classes", ctypes.c_int32), ("prune_hom", ctypes.c_int32),
                 ("prune_dt", ctypes.c_int32), ("refine_max", ctypes.c_int32), ("incremental", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("joint_classes", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("joint_classes", ctypes.c_int32), ("host_levels", ctypes.c_int32)]
 
 
 class Seed(ctypes.Structure):
@@ -442,6 +442,9 @@ lib.rw_pyramid_build.argtypes = [_vp, _vp, ctypes.c_int, _dims3, ctypes.c_int, c
 lib.rw_pyramid_build.restype = ctypes.c_int
 lib.rw_pyramid_build_counts.argtypes = lib.rw_pyramid_build.argtypes
 lib.rw_pyramid_build_counts.restype = ctypes.c_int
+lib.rw_pyramid_build_host.argtypes = [_vp, _vp, ctypes.c_int, _dims3, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp),
+                                      _vp]
+lib.rw_pyramid_build_host.restype = ctypes.c_int
 lib.rw_pyramid_free.argtypes = [_vp]
 lib.rw_pyramid_free.restype = None
 lib.rw_pyramid_level.argtypes = [_vp, ctypes.c_int, _dims3, ctypes.POINTER(_vp)]
@@ -491,9 +494,11 @@ def seeds_array(seeds):
 class Pyramid:
     """LOD pyramid on the device.  counts=False: normalised intensities
     (rw_pyramid_build); counts=True: square roots of the mean counts, for the
-    Poisson weight with beta 0.5 (rw_pyramid_build_counts)."""
+    Poisson weight with beta 0.5 (rw_pyramid_build_counts).  host_levels > 0:
+    the finest host_levels levels in page-locked host memory
+    (rw_pyramid_build_host; `volume` may then be a pinned CPU tensor)."""
 
-    def __init__(self, ctx, volume, levels, stream=None, counts=False):
+    def __init__(self, ctx, volume, levels, stream=None, counts=False, host_levels=0):
         import torch
         self.ctx = ctx
         dt = {torch.uint16: RW_U16, torch.float32: RW_F32}.get(volume.dtype)
@@ -501,12 +506,18 @@ class Pyramid:
             raise TypeError("volume must be uint16 or float32")
         nz, ny, nx = volume.shape
         h = _vp()
-        build = lib.rw_pyramid_build_counts if counts else lib.rw_pyramid_build
-        ctx._check(build(ctx.handle, _ptr(volume), dt, _dims3(nx, ny, nz), int(levels), ctypes.byref(h),
-                         _stream(stream)))
+        if host_levels:
+            if counts:
+                raise ValueError("host_levels is supported for the intensity pyramid only")
+            ctx._check(lib.rw_pyramid_build_host(ctx.handle, _ptr(volume), dt, _dims3(nx, ny, nz), int(levels),
+                                                 int(host_levels), ctypes.byref(h), _stream(stream)))
+        else:
+            build = lib.rw_pyramid_build_counts if counts else lib.rw_pyramid_build
+            ctx._check(build(ctx.handle, _ptr(volume), dt, _dims3(nx, ny, nz), int(levels), ctypes.byref(h),
+                             _stream(stream)))
         self.handle = h
         self.levels = levels
-        self.device = volume.device
+        self.device = volume.device if volume.is_cuda else torch.device("cuda", ctx.device)
 
     def level(self, l, stream=None):
         """Copy of pyramid level l as a (nz, ny, nx) float32 device tensor."""

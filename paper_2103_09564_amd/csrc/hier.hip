@@ -26,6 +26,7 @@ struct rw_pyramid {
     int levels = 0;
     int64_t dims[RW_MAX_LEVELS][3] = {};   // x, y, z
     float* data[RW_MAX_LEVELS] = {};
+    bool host[RW_MAX_LEVELS] = {};         // level in page-locked host memory
 };
 
 namespace rwk {
@@ -35,6 +36,7 @@ struct LevelRes {
     float* map = nullptr;
     uint8_t* flags = nullptr;
     size_t map_bytes = 0, flags_bytes = 0;
+    bool host = false;             // map in page-locked host memory
 };
 }  // namespace rwk
 
@@ -558,6 +560,26 @@ struct LevelGeo {
 };
 
 // Brick b (bx, by, bz) -> box geometry (core and expanded box, clipped).
+// Page-locked host memory that kernels read and write in place, for levels
+// larger than device memory (Section IV-A: bricks are small, the volume need
+// not be).  Coherent: every device access goes to host memory, so no XCD's
+// cache keeps a stale copy between kernels.
+static hipError_t host_alloc(void** out, size_t bytes) {
+    *out = nullptr;
+    return hipHostMalloc(out, std::max<size_t>(bytes, 4), hipHostMallocMapped | hipHostMallocCoherent);
+}
+
+// Whether kernels may read p: device memory or page-locked host memory
+// (pageable host memory would fault the device).
+static bool device_readable(const void* p) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeHost || at.type == hipMemoryTypeManaged;
+}
+
 static BoxGeo brick_box(const LevelGeo& L, int s, double e, int64_t bx, int64_t by, int64_t bz) {
     const int se = (int)std::floor(e * s);
     const int lo_pad = (se - s) / 2, hi_pad = se - s - lo_pad;
@@ -822,7 +844,9 @@ static int segment_impl(rw_ctx* ctx, const rw_pyramid* pyr, const std::vector<rw
         st.bricks[l] = nbr;
         lr.map_bytes = (size_t)nvox * R * sizeof(float);
         lr.flags_bytes = (size_t)nbr;
-        H_HIP(pool_alloc(res->device, (void**)&lr.map, lr.map_bytes), "allocating level map");
+        lr.host = l < P.host_levels;
+        if (lr.host) H_HIP(host_alloc((void**)&lr.map, lr.map_bytes), "allocating level map in host memory");
+        else H_HIP(pool_alloc(res->device, (void**)&lr.map, lr.map_bytes), "allocating level map");
         H_HIP(pool_alloc(res->device, (void**)&lr.flags, lr.flags_bytes), "allocating brick flags");
         H_HIP(hipMemsetAsync(lr.flags, 0, (size_t)nbr, s), "clearing brick flags");
     }
@@ -1055,7 +1079,8 @@ using namespace rwk;
 
 static void free_result_mem(rw_result* r) {
     for (int l = 0; l < RW_MAX_LEVELS; ++l) {
-        pool_release(r->device, r->lv[l].map, r->lv[l].map_bytes);
+        if (r->lv[l].host) (void)hipHostFree(r->lv[l].map);
+        else pool_release(r->device, r->lv[l].map, r->lv[l].map_bytes);
         pool_release(r->device, r->lv[l].flags, r->lv[l].flags_bytes);
         r->lv[l].map = nullptr;
         r->lv[l].flags = nullptr;
@@ -1086,7 +1111,7 @@ void rw_params_default(rw_params* p) {
 // counts = 0: normalised intensities (rw_pyramid_build); 1: square roots of
 // the mean counts (rw_pyramid_build_counts).
 static int pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels, int counts,
-                         rw_pyramid** out, void* stream) {
+                         int host_levels, rw_pyramid** out, void* stream) {
     return rwk::guarded(ctx, [&]() -> int {
     if (!ctx) return fail(nullptr, RW_E_INVAL, "ctx is NULL");
     ctx->err.clear();
@@ -1097,8 +1122,12 @@ static int pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t 
     if (levels < 1 || levels > RW_MAX_LEVELS) return fail(ctx, RW_E_INVAL, "levels must be in [1, %d]", RW_MAX_LEVELS);
     for (int a = 0; a < 3; ++a)
         if (dims[a] < 1 || dims[a] > (1 << 20)) return fail(ctx, RW_E_INVAL, "dims must be in [1, 2^20]");
+    if (host_levels < 0 || host_levels >= levels)
+        return fail(ctx, RW_E_INVAL, "host_levels must be in [0, levels - 1]");
     hipStream_t s = (hipStream_t)stream;
     DevGuard dg(ctx->device);
+    if (!device_readable(vol))
+        return fail(ctx, RW_E_INVAL, "vol must be device memory or page-locked host memory");
     rw_pyramid* p = new (std::nothrow) rw_pyramid();
     if (!p) return fail(ctx, RW_E_NOMEM, "host allocation failed");
     p->device = ctx->device;
@@ -1107,7 +1136,9 @@ static int pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t 
         for (int a = 0; a < 3; ++a) p->dims[l][a] = l == 0 ? dims[a] : (p->dims[l - 1][a] + 1) / 2;
     for (int l = 0; l < levels; ++l) {
         const int64_t n = p->dims[l][0] * p->dims[l][1] * p->dims[l][2];
-        hipError_t e = pool_alloc(p->device, (void**)&p->data[l], (size_t)n * sizeof(float));
+        p->host[l] = l < host_levels;
+        hipError_t e = p->host[l] ? host_alloc((void**)&p->data[l], (size_t)n * sizeof(float))
+                                  : pool_alloc(p->device, (void**)&p->data[l], (size_t)n * sizeof(float));
         if (e != hipSuccess) {
             rw_pyramid_free(p);
             return hip_fail(ctx, e, "allocating pyramid level");
@@ -1166,20 +1197,27 @@ static int pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t 
 
 int rw_pyramid_build(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels, rw_pyramid** out,
                      void* stream) {
-    return pyramid_build(ctx, vol, dtype, dims, levels, 0, out, stream);
+    return pyramid_build(ctx, vol, dtype, dims, levels, 0, 0, out, stream);
+}
+
+int rw_pyramid_build_host(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels,
+                          int host_levels, rw_pyramid** out, void* stream) {
+    return pyramid_build(ctx, vol, dtype, dims, levels, 0, host_levels, out, stream);
 }
 
 int rw_pyramid_build_counts(rw_ctx* ctx, const void* vol, int dtype, const int64_t dims[3], int levels,
                             rw_pyramid** out, void* stream) {
-    return pyramid_build(ctx, vol, dtype, dims, levels, 1, out, stream);
+    return pyramid_build(ctx, vol, dtype, dims, levels, 1, 0, out, stream);
 }
 
 void rw_pyramid_free(rw_pyramid* p) {
     if (!p) return;
     DevGuard dg(p->device);
     (void)hipDeviceSynchronize();
-    for (int l = 0; l < p->levels; ++l)
-        pool_release(p->device, p->data[l], (size_t)(p->dims[l][0] * p->dims[l][1] * p->dims[l][2]) * sizeof(float));
+    for (int l = 0; l < p->levels; ++l) {
+        if (p->host[l]) (void)hipHostFree(p->data[l]);
+        else pool_release(p->device, p->data[l], (size_t)(p->dims[l][0] * p->dims[l][1] * p->dims[l][2]) * sizeof(float));
+    }
     delete p;
 }
 
@@ -1208,6 +1246,8 @@ int rw_segment(rw_ctx* ctx, const rw_pyramid* pyr, const rw_seed* seeds, int64_t
     if (P.incremental < 0 || P.incremental > 3) return fail(ctx, RW_E_INVAL, "incremental must be in 0..3");
     if (P.schedule < 0 || P.schedule > RW_SCHED_TUNED) return fail(ctx, RW_E_INVAL, "schedule must be in 0..5");
     if (P.joint_classes != 0 && P.joint_classes != 1) return fail(ctx, RW_E_INVAL, "joint_classes must be 0 or 1");
+    if (P.host_levels < 0 || P.host_levels >= pyr->levels)
+        return fail(ctx, RW_E_INVAL, "host_levels must be in [0, levels - 1]");
     for (int64_t i = 0; i < n_seeds; ++i) {
         const rw_seed& q = seeds[i];
         if (!std::isfinite(q.x) || !std::isfinite(q.y) || !std::isfinite(q.z))
@@ -1292,7 +1332,8 @@ static int copy_out(rw_ctx* ctx, void* dst, const void* src, size_t bytes, void*
     ctx->err.clear();
     if (!dst) return fail(ctx, RW_E_INVAL, "dst is NULL");
     DevGuard dg(device);
-    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    // (the source may be a level in page-locked host memory)
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, (hipStream_t)stream);
     return e == hipSuccess ? RW_OK : hip_fail(ctx, e, "copying out");
 }
 

@@ -396,3 +396,44 @@ def test_cached_buffers_carry_nothing_over(env):
         for l in range(levels):
             assert np.array_equal(maps1[l], maps2[l]), (n_classes, l)
             assert np.array_equal(flags1[l], flags2[l]), (n_classes, l)
+
+
+def test_finest_levels_in_host_memory(env):
+    """Out-of-core placement (Section IV-A): the finest levels' pyramid data
+    and level maps in page-locked host memory (rw_pyramid_build_host,
+    rw_params.host_levels), read and written in place by the same kernels.
+    Pyramid levels, level maps, brick flags and run statistics equal the
+    device-memory run's bit for bit, for a volume on the device (one host
+    level) and one in pinned host memory (two), binary and three-class, and
+    for an incremental run on top; pageable host memory and out-of-range
+    level counts are refused."""
+    torch, rwg, ctx = env
+    print("host levels", flush=True)
+    n, levels = 64, 3
+    vol = _sphere_volume(n, "u16", seed=11)
+    dv = torch.from_numpy(vol).cuda()
+    hv = torch.from_numpy(vol).pin_memory()
+    for n_classes in (2, 3):
+        seeds = _seeds(n, np.random.default_rng(12), n_classes=n_classes)
+        kw = dict(brick=16, beta=128.0, t_bin=0.49, prune_hom=1, precision=1, tol=1e-6, n_classes=n_classes)
+        pyr_d, res_d, maps_d, flags_d = _gpu_run(env, vol, seeds, levels, **kw)
+        more = np.vstack([seeds, [[n / 2 + 3, n / 2 - 5, n / 2, 1]]])
+        _, _, mi_d, fi_d = _gpu_run(env, vol, more, levels, prev=res_d, pyr=pyr_d, **kw)
+        for src, hl in ((dv, 1), (hv, 2)):
+            pyr_h = rwg.Pyramid(ctx, src, levels, host_levels=hl)
+            for l in range(levels):
+                assert np.array_equal(pyr_h.level(l).cpu().numpy(), pyr_d.level(l).cpu().numpy()), (hl, l)
+            _, res_h, maps_h, flags_h = _gpu_run(env, vol, seeds, levels, pyr=pyr_h, host_levels=hl, **kw)
+            for l in range(levels):
+                assert np.array_equal(maps_h[l], maps_d[l]), (n_classes, hl, l)
+                assert np.array_equal(flags_h[l], flags_d[l]), (n_classes, hl, l)
+            assert res_h.stats() == res_d.stats(), (n_classes, hl)
+            _, _, mi_h, fi_h = _gpu_run(env, vol, more, levels, prev=res_h, pyr=pyr_h, host_levels=hl, **kw)
+            for l in range(levels):
+                assert np.array_equal(mi_h[l], mi_d[l]) and np.array_equal(fi_h[l], fi_d[l]), (n_classes, hl, l)
+    with pytest.raises(rwg.RWError):
+        rwg.Pyramid(ctx, torch.from_numpy(vol), levels, host_levels=1)      # pageable host memory
+    with pytest.raises(rwg.RWError):
+        rwg.Pyramid(ctx, dv, levels, host_levels=levels)                    # the coarsest level stays on the device
+    with pytest.raises(rwg.RWError):
+        rwg.segment(rwg.Pyramid(ctx, dv, levels), _seeds(n, np.random.default_rng(13)), host_levels=levels)
