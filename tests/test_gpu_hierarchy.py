@@ -402,8 +402,9 @@ def test_finest_levels_in_host_memory(env):
     """Out-of-core placement (Section IV-A): the finest levels' pyramid data
     and level maps in page-locked host memory (rw_pyramid_build_host,
     rw_params.host_levels), read and written in place by the same kernels.
-    Pyramid levels, level maps, brick flags and run statistics equal the
-    device-memory run's bit for bit, for a volume on the device (one host
+    Pyramid levels, level maps, brick flags, run statistics and the
+    materialised probabilities and labels equal the device-memory run's bit
+    for bit, for a volume on the device (one host
     level) and one in pinned host memory (two), binary and three-class, and
     for an incremental run on top; pageable host memory and out-of-range
     level counts are refused."""
@@ -428,6 +429,10 @@ def test_finest_levels_in_host_memory(env):
                 assert np.array_equal(maps_h[l], maps_d[l]), (n_classes, hl, l)
                 assert np.array_equal(flags_h[l], flags_d[l]), (n_classes, hl, l)
             assert res_h.stats() == res_d.stats(), (n_classes, hl)
+            for cls in range(1, n_classes):
+                pd_, ld_ = res_d.materialize(0, cls, prob=True, labels=True)
+                ph_, lh_ = res_h.materialize(0, cls, prob=True, labels=True)
+                assert torch.equal(pd_, ph_) and torch.equal(ld_, lh_), (n_classes, hl, cls)
             _, _, mi_h, fi_h = _gpu_run(env, vol, more, levels, prev=res_h, pyr=pyr_h, host_levels=hl, **kw)
             for l in range(levels):
                 assert np.array_equal(mi_h[l], mi_d[l]) and np.array_equal(fi_h[l], fi_d[l]), (n_classes, hl, l)
