@@ -398,14 +398,39 @@ def test_cached_buffers_carry_nothing_over(env):
             assert np.array_equal(flags1[l], flags2[l]), (n_classes, l)
 
 
+def _mem_types(pyr, res, levels):
+    """hipMemoryType (1 host, 2 device) of each pyramid level and level map,
+    asked of the HIP runtime this process has loaded."""
+    import ctypes
+    from paper_2103_09564_amd import binding as B
+    path = next(ln.split()[-1] for ln in open("/proc/self/maps") if "libamdhip64" in ln)
+    hip = ctypes.CDLL(path)
+
+    class Attr(ctypes.Structure):
+        _fields_ = [("type", ctypes.c_int), ("device", ctypes.c_int), ("devicePointer", ctypes.c_void_p),
+                    ("hostPointer", ctypes.c_void_p), ("isManaged", ctypes.c_int), ("allocationFlags", ctypes.c_uint)]
+
+    def kind(ptr):
+        a = Attr()
+        assert hip.hipPointerGetAttributes(ctypes.byref(a), ctypes.c_void_p(ptr)) == 0
+        return a.type
+    out = []
+    for l in range(levels):
+        pp, pm, d, r = ctypes.c_void_p(), ctypes.c_void_p(), B._dims3(), ctypes.c_int()
+        assert B.lib.rw_pyramid_level(pyr.handle, l, d, ctypes.byref(pp)) == 0
+        assert B.lib.rw_result_level(res.handle, l, d, ctypes.byref(r), ctypes.byref(pm)) == 0
+        out.append((kind(pp.value), kind(pm.value)))
+    return out
+
+
 def test_finest_levels_in_host_memory(env):
     """Out-of-core placement (Section IV-A): the finest levels' pyramid data
     and level maps in page-locked host memory (rw_pyramid_build_host,
     rw_params.host_levels), read and written in place by the same kernels.
     Pyramid levels, level maps, brick flags, run statistics and the
     materialised probabilities and labels equal the device-memory run's bit
-    for bit, for a volume on the device (one host
-    level) and one in pinned host memory (two), binary and three-class, and
+    for bit (and the finest levels are indeed host memory), for a volume on
+    the device (one host level) and one in pinned host memory (two), binary and three-class, and
     for an incremental run on top; pageable host memory and out-of-range
     level counts are refused."""
     torch, rwg, ctx = env
@@ -425,6 +450,8 @@ def test_finest_levels_in_host_memory(env):
             for l in range(levels):
                 assert np.array_equal(pyr_h.level(l).cpu().numpy(), pyr_d.level(l).cpu().numpy()), (hl, l)
             _, res_h, maps_h, flags_h = _gpu_run(env, vol, seeds, levels, pyr=pyr_h, host_levels=hl, **kw)
+            assert _mem_types(pyr_h, res_h, levels) == [(1, 1)] * hl + [(2, 2)] * (levels - hl), hl
+            assert _mem_types(pyr_d, res_d, levels) == [(2, 2)] * levels
             for l in range(levels):
                 assert np.array_equal(maps_h[l], maps_d[l]), (n_classes, hl, l)
                 assert np.array_equal(flags_h[l], flags_d[l]), (n_classes, hl, l)
